@@ -1,0 +1,909 @@
+/*
+ * CPU oracle for the ray-cast rendering path — TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * load this library.  The product (the HIP library) never calls it, and the two
+ * share no code: no headers, helpers, tables or constants.
+ *
+ * Everything here is the plain definition, evaluated in FP64 from the FP32
+ * inputs (which FP64 holds exactly), except where a bit-exact FP32 mirror is
+ * the definition itself (camera rays, vertex transforms, the resolve order):
+ *
+ *  - Closest hit / any hit (the acceleration structure of Sec. IV-B "Ray-traced
+ *    shadows" only speeds up an exact answer): the closest, resp. any, hit over
+ *    ALL triangles, Moller-Trumbore in FP64, ties to the smaller triangle id.
+ *    The oracle's own BVH (median split) only prunes; it is checked against
+ *    brute force.  Every query also reports whether the answer is inside the
+ *    FP32 "band": the set of rays for which some triangle's FP32 hit decision
+ *    or hit order is not certain under a running forward-error bound of the
+ *    FP32 Moller-Trumbore evaluation (times a safety factor c).
+ *  - Hard shadows (Sec. IV-B): a ray from the surface point towards the light;
+ *    any opaque hit strictly between them means the light is blocked.
+ *  - Shading (Sec. IV-B, the Cook-Torrance equation): GGX normal distribution,
+ *    Schlick Fresnel with F0 from the metallic-roughness workflow, Schlick-GGX
+ *    geometry term; plus a Lambert diffuse lobe.
+ *  - Anti-aliasing (Sec. IV-B): supersampling, i.e. every sample shaded and
+ *    the samples box-averaged in a fixed order.
+ *
+ * Readings where the paper is silent are listed in the design notes; the
+ * ones that change numbers are restated next to the code that uses them.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_API __attribute__((visibility("default")))
+#define NO_HIT 0xFFFFFFFFu
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the        */
+/* multiply-xorshift round with the published multipliers and Weyl key bumps. */
+/* ------------------------------------------------------------------------- */
+OR_API void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 24-bit uniform in [0,1): exact in FP32 and FP64. */
+static double unit24(uint32_t x) { return (double)(x >> 8) * 0x1p-24; }
+static float unit24f(uint32_t x) { return (float)(x >> 8) * 0x1p-24f; }
+
+/* ------------------------------------------------------------------------- */
+/* Camera: FP32 mirror of the ray definition (no contraction, IEEE RNE,       */
+/* correctly rounded sqrt and divide).  Right-handed, y up; pixel row 0 is   */
+/* the top row.                                                               */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    float eye[3], target[3], up[3];
+    float vfov_deg;
+    int32_t width, height, ssaa;
+    uint32_t seed, frame;
+} or_camera;
+
+typedef struct { float f[3], r[3], u[3]; float tan_half, x_scale; } cam_basis;
+
+static void f_normalize(float v[3])
+{
+    float n2 = v[0] * v[0] + v[1] * v[1];
+    n2 = n2 + v[2] * v[2];
+    float len = sqrtf(n2);
+    v[0] = v[0] / len; v[1] = v[1] / len; v[2] = v[2] / len;
+}
+
+static void f_cross(const float a[3], const float b[3], float o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void camera_basis(const or_camera* c, cam_basis* b)
+{
+    for (int k = 0; k < 3; ++k) b->f[k] = c->target[k] - c->eye[k];
+    f_normalize(b->f);
+    f_cross(b->f, c->up, b->r);
+    f_normalize(b->r);
+    f_cross(b->r, b->f, b->u);
+    /* half field of view: tan evaluated in FP64, rounded once to FP32 */
+    b->tan_half = (float)tan((double)c->vfov_deg * (3.14159265358979323846 / 360.0));
+    float aspect = (float)c->width / (float)c->height;
+    b->x_scale = b->tan_half * aspect;
+}
+
+static void sample_offset(const or_camera* c, uint32_t pixel, uint32_t k, float* ox, float* oy)
+{
+    if (c->ssaa <= 1) { *ox = 0.5f; *oy = 0.5f; return; }
+    uint32_t ctr[4] = {pixel, k, 0u, 0u}, key[2] = {c->seed, c->frame}, r[4];
+    or_philox4x32_10(ctr, key, r);
+    *ox = ((float)(k & 1u) + unit24f(r[0])) * 0.5f;
+    *oy = ((float)(k >> 1) + unit24f(r[1])) * 0.5f;
+}
+
+static void gen_ray(const or_camera* c, const cam_basis* b, int64_t s, float o[3], float d[3])
+{
+    int64_t spp = (int64_t)c->ssaa * c->ssaa;
+    uint32_t pixel = (uint32_t)(s / spp), k = (uint32_t)(s % spp);
+    uint32_t i = pixel % (uint32_t)c->width, j = pixel / (uint32_t)c->width;
+    float ox, oy;
+    sample_offset(c, pixel, k, &ox, &oy);
+    float px = (2.0f * ((float)i + ox)) / (float)c->width;
+    px = (px - 1.0f) * b->x_scale;
+    float py = (2.0f * ((float)j + oy)) / (float)c->height;
+    py = (1.0f - py) * b->tan_half;
+    for (int a = 0; a < 3; ++a) {
+        float t0 = px * b->r[a];
+        float t1 = py * b->u[a];
+        d[a] = (t0 + t1) + b->f[a];
+        o[a] = c->eye[a];
+    }
+    f_normalize(d);
+}
+
+OR_API void or_gen_rays(const or_camera* c, const int64_t* samples, int64_t n, float* o, float* d)
+{
+    cam_basis b;
+    camera_basis(c, &b);
+    for (int64_t q = 0; q < n; ++q) gen_ray(c, &b, samples[q], o + 3 * q, d + 3 * q);
+}
+
+/* ------------------------------------------------------------------------- */
+/* FP64 vectors                                                               */
+/* ------------------------------------------------------------------------- */
+typedef struct { double x, y, z; } v3;
+static v3 mk(double x, double y, double z) { v3 r = {x, y, z}; return r; }
+static v3 add(v3 a, v3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static v3 sub(v3 a, v3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static v3 scl(v3 a, double s) { return mk(a.x * s, a.y * s, a.z * s); }
+static double dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static v3 cross(v3 a, v3 b) { return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+static double len(v3 a) { return sqrt(dot(a, a)); }
+static v3 nrm(v3 a) { return scl(a, 1.0 / len(a)); }
+static double amax(v3 a) { return fmax(fabs(a.x), fmax(fabs(a.y), fabs(a.z))); }
+static double comp(v3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+static v3 from_f(const float* p) { return mk(p[0], p[1], p[2]); }
+
+/* ------------------------------------------------------------------------- */
+/* Running forward-error bounds of an FP32 evaluation.                        */
+/* ev = (value computed in FP64 ~ exact, bound on |FP32 result - value|).     */
+/* u = 2^-24 is the FP32 unit roundoff.                                       */
+/* ------------------------------------------------------------------------- */
+typedef struct { double v, e; } ev;
+static const double U32R = 0x1p-24;
+static ev ev_x(double v, double e) { ev r = {v, e}; return r; }
+static ev ev_add(ev a, ev b) { double v = a.v + b.v, e = a.e + b.e; return ev_x(v, e + U32R * (fabs(v) + e)); }
+static ev ev_sub(ev a, ev b) { double v = a.v - b.v, e = a.e + b.e; return ev_x(v, e + U32R * (fabs(v) + e)); }
+static ev ev_mul(ev a, ev b)
+{
+    double v = a.v * b.v;
+    double e = fabs(a.v) * b.e + fabs(b.v) * a.e + a.e * b.e;
+    return ev_x(v, e + U32R * (fabs(v) + e));
+}
+typedef struct { ev x, y, z; } ev3;
+static ev3 ev3_sub(ev3 a, ev3 b) { ev3 r = {ev_sub(a.x, b.x), ev_sub(a.y, b.y), ev_sub(a.z, b.z)}; return r; }
+static ev ev3_dot(ev3 a, ev3 b) { return ev_add(ev_add(ev_mul(a.x, b.x), ev_mul(a.y, b.y)), ev_mul(a.z, b.z)); }
+static ev3 ev3_cross(ev3 a, ev3 b)
+{
+    ev3 r = {ev_sub(ev_mul(a.y, b.z), ev_mul(a.z, b.y)),
+             ev_sub(ev_mul(a.z, b.x), ev_mul(a.x, b.z)),
+             ev_sub(ev_mul(a.x, b.y), ev_mul(a.y, b.x))};
+    return r;
+}
+static ev3 ev3_exact(v3 a) { ev3 r = {{a.x, 0}, {a.y, 0}, {a.z, 0}}; return r; }
+/* an FP64 vector that the FP32 side holds rounded to FP32 (<= half an ulp per component) */
+static ev3 ev3_rounded(v3 a) { ev3 r = {{a.x, U32R * fabs(a.x)}, {a.y, U32R * fabs(a.y)}, {a.z, U32R * fabs(a.z)}}; return r; }
+
+/* ------------------------------------------------------------------------- */
+/* Triangles and the exact Moller-Trumbore test with FP32 certainty.          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    const float* pos; int64_t nv;
+    const uint32_t* idx; int64_t nt;
+    const uint32_t* tri_mat;
+    const float* mats; int64_t nmat;    /* albedo rgb, roughness, metallic */
+} or_scene;
+
+static void tri_verts(const or_scene* s, uint32_t t, v3* a, v3* b, v3* c)
+{
+    const uint32_t* ix = s->idx + 3 * (int64_t)t;
+    *a = from_f(s->pos + 3 * (int64_t)ix[0]);
+    *b = from_f(s->pos + 3 * (int64_t)ix[1]);
+    *c = from_f(s->pos + 3 * (int64_t)ix[2]);
+}
+
+enum { ST_FAIL = 0, ST_PASS = 1, ST_UNC = 2 };
+
+typedef struct {
+    int exact_hit;          /* FP64 Moller-Trumbore says hit, with tmin < t < tmax */
+    int status;             /* FP32 outcome certainty: FAIL, PASS, UNC */
+    double t, u, v;         /* FP64 values */
+    double et, eu, ev;      /* bounds on the FP32 error of t, u, v (times c) */
+} tri_test;
+
+/* A ray as the FP32 side holds it: value + per-component error bound. */
+typedef struct { v3 o, d; ev3 eo, ed; } ray_ev;
+
+static int certain(double margin, double err) { return margin > err ? ST_PASS : (margin < -err ? ST_FAIL : ST_UNC); }
+
+static void mt_test(const or_scene* s, uint32_t tri, const ray_ev* r, double tmin, double tmax, double c, tri_test* out)
+{
+    v3 a, b, cc;
+    tri_verts(s, tri, &a, &b, &cc);
+    /* FP64 Moller-Trumbore (Moller & Trumbore, JGT 1997) */
+    v3 e1 = sub(b, a), e2 = sub(cc, a);
+    v3 p = cross(r->d, e2);
+    double det = dot(e1, p);
+    v3 sv = sub(r->o, a);
+    v3 q = cross(sv, e1);
+    double u = 0, v = 0, t = 0;
+    out->exact_hit = 0;
+    if (det != 0.0) {
+        u = dot(sv, p) / det;
+        v = dot(r->d, q) / det;
+        t = dot(e2, q) / det;
+        out->exact_hit = (u >= 0.0 && v >= 0.0 && u + v <= 1.0 && t > tmin && t < tmax);
+    }
+    out->t = t; out->u = u; out->v = v;
+
+    /* The same steps with FP32 error bounds: edges e1 = fl(v1 - v0), e2 = fl(v2 - v0). */
+    ev3 A = ev3_exact(a), B = ev3_exact(b), C = ev3_exact(cc);
+    ev3 E1 = ev3_sub(B, A), E2 = ev3_sub(C, A);
+    ev3 P = ev3_cross(r->ed, E2);
+    ev DET = ev3_dot(E1, P);
+    ev3 S = ev3_sub(r->eo, A);
+    ev3 Q = ev3_cross(S, E1);
+    ev SP = ev3_dot(S, P), DQ = ev3_dot(r->ed, Q), TQ = ev3_dot(E2, Q);
+    double edet = c * DET.e, esp = c * SP.e, edq = c * DQ.e, etq = c * TQ.e;
+
+    if (fabs(DET.v) > edet) {
+        /* determinant sign certain: interval quotients of the FP32 numerators over the
+         * FP32 determinant, widened by the reciprocal (<= 1 ulp) and product roundings */
+        double sg = DET.v > 0 ? 1.0 : -1.0;
+        double dlo = fabs(DET.v) - edet, dhi = fabs(DET.v) + edet;
+        double qlo[3], qhi[3];
+        const double num[3] = {sg * SP.v, sg * DQ.v, sg * TQ.v}, en[3] = {esp, edq, etq};
+        for (int k = 0; k < 3; ++k) {
+            double a = num[k] - en[k], b = num[k] + en[k];
+            double lo = fmin(a / dlo, a / dhi), hi = fmax(b / dlo, b / dhi);
+            double w = 4.0 * c * U32R;
+            qlo[k] = lo - w * fabs(lo);
+            qhi[k] = hi + w * fabs(hi);
+        }
+        /* FP32 evaluates u + v <= 1 on the rounded quotients */
+        double slo = (qlo[0] + qlo[1]), shi = (qhi[0] + qhi[1]);
+        slo -= c * U32R * fabs(slo); shi += c * U32R * fabs(shi);
+        int st[5];
+        st[0] = qlo[0] >= 0.0 ? ST_PASS : (qhi[0] < 0.0 ? ST_FAIL : ST_UNC);
+        st[1] = qlo[1] >= 0.0 ? ST_PASS : (qhi[1] < 0.0 ? ST_FAIL : ST_UNC);
+        st[2] = shi <= 1.0 ? ST_PASS : (slo > 1.0 ? ST_FAIL : ST_UNC);
+        st[3] = qlo[2] > tmin ? ST_PASS : (qhi[2] <= tmin ? ST_FAIL : ST_UNC);
+        st[4] = isinf(tmax) ? ST_PASS : (qhi[2] < tmax ? ST_PASS : (qlo[2] >= tmax ? ST_FAIL : ST_UNC));
+        int status = ST_PASS;
+        for (int k = 0; k < 5; ++k) {
+            if (st[k] == ST_FAIL) { status = ST_FAIL; break; }
+            if (st[k] == ST_UNC) status = ST_UNC;
+        }
+        out->status = status;
+        out->eu = fmax(u - qlo[0], qhi[0] - u);
+        out->ev = fmax(v - qlo[1], qhi[1] - v);
+        out->et = fmax(t - qlo[2], qhi[2] - t);
+    } else {
+        /* sign of the determinant not certain: the FP32 quotients are certainly outside
+         * [0,1] when a numerator certainly exceeds the determinant in magnitude */
+        double dmax = fabs(DET.v) + edet;
+        if (fabs(SP.v) - esp > dmax || fabs(DQ.v) - edq > dmax) out->status = ST_FAIL;
+        else out->status = ST_UNC;
+        out->et = INFINITY; out->eu = INFINITY; out->ev = INFINITY;
+    }
+    if (out->status == ST_PASS && !out->exact_hit) out->status = ST_UNC; /* cannot happen; stay safe */
+}
+
+/* ------------------------------------------------------------------------- */
+/* Oracle BVH: binary, median split on the longest centroid axis, <= 4 tris  */
+/* per leaf, FP64 boxes.  It only prunes candidate triangles.                 */
+/* ------------------------------------------------------------------------- */
+typedef struct { double lo[3], hi[3]; int32_t left, right; int32_t first, count; } bnode;
+
+typedef struct or_bvh {
+    const or_scene* scene;
+    bnode* nodes; int64_t n_nodes, cap;
+    uint32_t* tris;
+    double* cen;    /* centroids, 3 per triangle */
+    double margin;  /* absolute box padding */
+    int depth;
+} or_bvh;
+
+static void tri_bounds(const or_scene* s, uint32_t t, double lo[3], double hi[3])
+{
+    v3 a, b, c;
+    tri_verts(s, t, &a, &b, &c);
+    for (int k = 0; k < 3; ++k) {
+        double x = comp(a, k), y = comp(b, k), z = comp(c, k);
+        lo[k] = fmin(x, fmin(y, z));
+        hi[k] = fmax(x, fmax(y, z));
+    }
+}
+
+static void select_kth(uint32_t* t, const double* cen, int axis, int64_t lo, int64_t hi, int64_t k)
+{
+    /* quickselect: afterwards t[lo..k) <= t[k] <= t[k+1..hi) on the centroid axis */
+    while (hi - lo > 1) {
+        double pv = cen[3 * (int64_t)t[lo + (hi - lo) / 2] + axis];
+        int64_t i = lo, j = hi - 1;
+        while (i <= j) {
+            while (cen[3 * (int64_t)t[i] + axis] < pv) ++i;
+            while (cen[3 * (int64_t)t[j] + axis] > pv) --j;
+            if (i <= j) { uint32_t tmp = t[i]; t[i] = t[j]; t[j] = tmp; ++i; --j; }
+        }
+        if (k <= j) hi = j + 1;
+        else if (k >= i) lo = i;
+        else return;
+    }
+}
+
+static int32_t build_rec(or_bvh* B, int64_t first, int64_t count, int depth)
+{
+    if (B->n_nodes == B->cap) {
+        B->cap *= 2;
+        B->nodes = (bnode*)realloc(B->nodes, (size_t)B->cap * sizeof(bnode));
+    }
+    int32_t id = (int32_t)B->n_nodes++;
+    if (depth > B->depth) B->depth = depth;
+    bnode nd;
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k < 3; ++k) { nd.lo[k] = INFINITY; nd.hi[k] = -INFINITY; }
+    for (int64_t i = first; i < first + count; ++i) {
+        double lo[3], hi[3];
+        tri_bounds(B->scene, B->tris[i], lo, hi);
+        for (int k = 0; k < 3; ++k) {
+            nd.lo[k] = fmin(nd.lo[k], lo[k]); nd.hi[k] = fmax(nd.hi[k], hi[k]);
+            double cv = B->cen[3 * (int64_t)B->tris[i] + k];
+            clo[k] = fmin(clo[k], cv); chi[k] = fmax(chi[k], cv);
+        }
+    }
+    for (int k = 0; k < 3; ++k) { nd.lo[k] -= B->margin; nd.hi[k] += B->margin; }
+    nd.first = (int32_t)first; nd.count = (int32_t)count; nd.left = nd.right = -1;
+    if (count > 4) {
+        int axis = 0;
+        for (int k = 1; k < 3; ++k) if (chi[k] - clo[k] > chi[axis] - clo[axis]) axis = k;
+        int64_t mid = first + count / 2;
+        select_kth(B->tris, B->cen, axis, first, first + count, mid);
+        nd.count = 0;
+        B->nodes[id] = nd;
+        int32_t l = build_rec(B, first, mid - first, depth + 1);
+        int32_t r = build_rec(B, mid, first + count - mid, depth + 1);
+        B->nodes[id].left = l; B->nodes[id].right = r;
+        return id;
+    }
+    B->nodes[id] = nd;
+    return id;
+}
+
+OR_API or_bvh* or_bvh_build(const or_scene* s)
+{
+    or_bvh* B = (or_bvh*)calloc(1, sizeof(or_bvh));
+    B->scene = s;
+    B->cap = 1024;
+    B->nodes = (bnode*)malloc((size_t)B->cap * sizeof(bnode));
+    B->tris = (uint32_t*)malloc((size_t)(s->nt > 0 ? s->nt : 1) * sizeof(uint32_t));
+    B->cen = (double*)malloc((size_t)(s->nt > 0 ? s->nt : 1) * 3 * sizeof(double));
+    double scale = 1.0;
+    for (int64_t i = 0; i < 3 * s->nv; ++i) scale = fmax(scale, fabs((double)s->pos[i]));
+    /* pad boxes well beyond FP32 rounding of the GPU box test and of the hit decisions */
+    B->margin = 1e-4 * scale;
+    for (int64_t t = 0; t < s->nt; ++t) {
+        v3 a, b, c;
+        tri_verts(s, (uint32_t)t, &a, &b, &c);
+        B->tris[t] = (uint32_t)t;
+        B->cen[3 * t + 0] = (a.x + b.x + c.x) / 3.0;
+        B->cen[3 * t + 1] = (a.y + b.y + c.y) / 3.0;
+        B->cen[3 * t + 2] = (a.z + b.z + c.z) / 3.0;
+    }
+    if (s->nt > 0) build_rec(B, 0, s->nt, 0);
+    return B;
+}
+
+OR_API void or_bvh_free(or_bvh* B)
+{
+    if (!B) return;
+    free(B->nodes); free(B->tris); free(B->cen); free(B);
+}
+
+OR_API int64_t or_bvh_nodes(const or_bvh* B) { return B->n_nodes; }
+OR_API int or_bvh_depth(const or_bvh* B) { return B->depth; }
+
+/* slab test in FP64 against a padded box; returns entry distance or +inf */
+static double box_enter(const bnode* n, const ray_ev* r, double tmin, double tmax)
+{
+    double t0 = tmin, t1 = tmax;
+    for (int k = 0; k < 3; ++k) {
+        double o = comp(r->o, k), d = comp(r->d, k);
+        if (d == 0.0) {
+            if (o < n->lo[k] || o > n->hi[k]) return INFINITY;
+            continue;
+        }
+        double a = (n->lo[k] - o) / d, b = (n->hi[k] - o) / d;
+        if (a > b) { double tmp = a; a = b; b = tmp; }
+        t0 = fmax(t0, a); t1 = fmin(t1, b);
+        if (t0 > t1) return INFINITY;
+    }
+    return t0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Closest hit and any hit, with the band decision.                           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t id; double t, u, v; double et, eu, ev;
+    int band;
+    int64_t n_candidates;
+} hit_rec;
+
+typedef struct {
+    int have_best; uint32_t best_id; double best_t, best_thi; int best_status;
+    tri_test best;
+    double pass_lo1, pass_lo2; uint32_t pass_id1;
+    double unc_lo;
+    int64_t n_cand;
+} closest_acc;
+
+static void closest_consider(closest_acc* A, uint32_t tri, const tri_test* tt)
+{
+    if (tt->status == ST_FAIL && !tt->exact_hit) return;
+    A->n_cand++;
+    double tlo = tt->t - tt->et;
+    if (tt->status == ST_PASS) {
+        if (tlo < A->pass_lo1) { A->pass_lo2 = A->pass_lo1; A->pass_lo1 = tlo; A->pass_id1 = tri; }
+        else if (tlo < A->pass_lo2) A->pass_lo2 = tlo;
+    } else if (tt->status == ST_UNC) {
+        if (tlo < A->unc_lo) A->unc_lo = tlo;
+    }
+    if (tt->exact_hit) {
+        if (!A->have_best || tt->t < A->best_t || (tt->t == A->best_t && tri < A->best_id)) {
+            A->have_best = 1; A->best_id = tri; A->best_t = tt->t; A->best = *tt;
+            A->best_thi = tt->t + tt->et; A->best_status = tt->status;
+        }
+    }
+}
+
+static void closest_finish(const closest_acc* A, hit_rec* out)
+{
+    out->n_candidates = A->n_cand;
+    if (!A->have_best) {
+        out->id = NO_HIT; out->t = INFINITY; out->u = out->v = 0;
+        out->et = out->eu = out->ev = 0;
+        out->band = (A->unc_lo < INFINITY) || (A->pass_lo1 < INFINITY);
+        return;
+    }
+    out->id = A->best_id; out->t = A->best.t; out->u = A->best.u; out->v = A->best.v;
+    out->et = A->best.et; out->eu = A->best.eu; out->ev = A->best.ev;
+    /* the answer is certain when the best hit is a certain FP32 hit, no uncertain triangle could
+     * come before it, and no other certain hit overlaps its FP32 t interval */
+    double other_pass = (A->pass_id1 == A->best_id) ? A->pass_lo2 : A->pass_lo1;
+    out->band = (A->best_status != ST_PASS) || (A->unc_lo <= A->best_thi) || (other_pass <= A->best_thi);
+}
+
+static void acc_init(closest_acc* A)
+{
+    memset(A, 0, sizeof(*A));
+    A->pass_lo1 = A->pass_lo2 = A->unc_lo = INFINITY;
+    A->pass_id1 = NO_HIT;
+}
+
+static void closest_bvh(const or_bvh* B, const ray_ev* r, double tmin, double tmax, double c, hit_rec* out)
+{
+    closest_acc A;
+    acc_init(&A);
+    if (B->n_nodes > 0) {
+        int32_t stack[256];
+        int sp = 0;
+        stack[sp++] = 0;
+        while (sp > 0) {
+            const bnode* n = &B->nodes[stack[--sp]];
+            double te = box_enter(n, r, tmin - B->margin, tmax);
+            if (te == INFINITY) continue;
+            /* no triangle entering after the current best (plus padding) can change the answer
+             * or the band, except grazing triangles whose FP32 t error exceeds the padding */
+            if (A.have_best && te > A.best_thi + B->margin) continue;
+            if (n->left < 0) {
+                for (int32_t i = 0; i < n->count; ++i) {
+                    uint32_t tri = B->tris[n->first + i];
+                    tri_test tt;
+                    mt_test(B->scene, tri, r, tmin, tmax, c, &tt);
+                    closest_consider(&A, tri, &tt);
+                }
+            } else {
+                stack[sp++] = n->right;
+                stack[sp++] = n->left;
+            }
+        }
+    }
+    closest_finish(&A, out);
+}
+
+static void closest_brute(const or_scene* s, const ray_ev* r, double tmin, double tmax, double c, hit_rec* out)
+{
+    closest_acc A;
+    acc_init(&A);
+    for (int64_t t = 0; t < s->nt; ++t) {
+        tri_test tt;
+        mt_test(s, (uint32_t)t, r, tmin, tmax, c, &tt);
+        closest_consider(&A, (uint32_t)t, &tt);
+    }
+    closest_finish(&A, out);
+}
+
+/* any hit: returns occluded (exact); *band set when no certain occluder exists but an uncertain one does */
+static int any_bvh(const or_scene* s, const or_bvh* B, const ray_ev* r, double tmin, double tmax, double c, int* band, uint32_t* who)
+{
+    int occluded = 0, unc = 0;
+    *who = NO_HIT;
+    if (B == NULL) {
+        for (int64_t t = 0; t < s->nt; ++t) {
+            tri_test tt;
+            mt_test(s, (uint32_t)t, r, tmin, tmax, c, &tt);
+            if (tt.exact_hit) { occluded = 1; if (*who == NO_HIT) *who = (uint32_t)t; }
+            if (tt.status == ST_PASS) { *band = 0; return 1; }
+            if (tt.status == ST_UNC) unc = 1;
+        }
+        *band = unc;
+        return occluded;
+    }
+    if (B->n_nodes == 0) { *band = 0; return 0; }
+    int32_t stack[256];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const bnode* n = &B->nodes[stack[--sp]];
+        if (box_enter(n, r, tmin - B->margin, tmax + B->margin) == INFINITY) continue;
+        if (n->left < 0) {
+            for (int32_t i = 0; i < n->count; ++i) {
+                uint32_t tri = B->tris[n->first + i];
+                tri_test tt;
+                mt_test(s, tri, r, tmin, tmax, c, &tt);
+                if (tt.exact_hit) { occluded = 1; if (*who == NO_HIT) *who = tri; }
+                if (tt.status == ST_PASS) { *band = 0; *who = tri; return 1; }
+                if (tt.status == ST_UNC) unc = 1;
+            }
+        } else {
+            stack[sp++] = n->right;
+            stack[sp++] = n->left;
+        }
+    }
+    *band = unc;
+    return occluded;
+}
+
+static ray_ev exact_ray(v3 o, v3 d)
+{
+    ray_ev r;
+    r.o = o; r.d = d; r.eo = ev3_exact(o); r.ed = ev3_exact(d);
+    return r;
+}
+
+/* Single-ray queries with FP32-exact inputs (e.g. camera rays); bvh may be NULL (brute force). */
+OR_API void or_closest(const or_scene* s, const or_bvh* B, const float o[3], const float d[3],
+                       double tmin, double tmax, double c, uint32_t* id, double tuv[3], double err[3],
+                       int* band, int64_t* n_cand)
+{
+    ray_ev r = exact_ray(from_f(o), from_f(d));
+    hit_rec h;
+    if (B) closest_bvh(B, &r, tmin, tmax, c, &h);
+    else closest_brute(s, &r, tmin, tmax, c, &h);
+    *id = h.id; tuv[0] = h.t; tuv[1] = h.u; tuv[2] = h.v;
+    err[0] = h.et; err[1] = h.eu; err[2] = h.ev;
+    *band = h.band;
+    if (n_cand) *n_cand = h.n_candidates;
+}
+
+/* Segment query in FP64: occluded iff some triangle is hit at tmin < t < tmax. */
+OR_API int or_any(const or_scene* s, const or_bvh* B, const double o[3], const double d[3],
+                  double tmin, double tmax, double c, int* band)
+{
+    v3 O = mk(o[0], o[1], o[2]), D = mk(d[0], d[1], d[2]);
+    ray_ev r;
+    r.o = O; r.d = D; r.eo = ev3_rounded(O); r.ed = ev3_rounded(D);
+    uint32_t who;
+    return any_bvh(s, B, &r, tmin, tmax, c, band, &who);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cook-Torrance / GGX BRDF (Sec. IV-B equation) + Lambert diffuse.           */
+/* alpha = roughness^2; k = (roughness+1)^2 / 8; F0 = mix(0.04, albedo, m).   */
+/* ------------------------------------------------------------------------- */
+static const double PI = 3.14159265358979323846;
+
+/* Trowbridge-Reitz GGX normal distribution; the denominator is written as
+ * a2 (n.h)^2 + |n x h|^2, equal to 1 + (a2 - 1)(n.h)^2 for unit n and h. */
+static double ggx_D(v3 n, v3 h, double alpha)
+{
+    double a2 = alpha * alpha, ndh = dot(n, h);
+    v3 nxh = cross(n, h);
+    double den = a2 * ndh * ndh + dot(nxh, nxh);
+    return a2 / (PI * den * den);
+}
+
+/* Schlick-GGX masking for one direction: x / (x (1 - k) + k) */
+static double schlick_g1(double x, double k) { return x / (x * (1.0 - k) + k); }
+
+/* Schlick Fresnel: F0 + (1 - F0) (1 - cos)^5 */
+static double schlick_f(double f0, double cos_hv) { return f0 + (1.0 - f0) * pow(1.0 - cos_hv, 5.0); }
+
+OR_API double or_ggx_D(const double n_[3], const double h_[3], double alpha)
+{
+    return ggx_D(mk(n_[0], n_[1], n_[2]), mk(h_[0], h_[1], h_[2]), alpha);
+}
+OR_API double or_schlick_g1(double x, double k) { return schlick_g1(x, k); }
+OR_API double or_schlick_f(double f0, double c) { return schlick_f(f0, c); }
+
+/* f = (1 - F)(1 - m) albedo / pi + D F G1(n.wo) G1(n.wi) / (4 (n.wo)(n.wi)), zero unless both cosines > 0 */
+OR_API void or_brdf_k(const double n_[3], const double wo_[3], const double wi_[3], const double albedo[3],
+                      double rough, double metal, double kgeo, double out[3])
+{
+    v3 n = mk(n_[0], n_[1], n_[2]), wo = mk(wo_[0], wo_[1], wo_[2]), wi = mk(wi_[0], wi_[1], wi_[2]);
+    double ndo = dot(n, wo), ndi = dot(n, wi);
+    out[0] = out[1] = out[2] = 0.0;
+    if (!(ndo > 0.0) || !(ndi > 0.0)) return;
+    v3 h = nrm(add(wo, wi));
+    double D = ggx_D(n, h, rough * rough);
+    double G = schlick_g1(ndo, kgeo) * schlick_g1(ndi, kgeo);
+    double hdo = dot(h, wo);
+    for (int ch = 0; ch < 3; ++ch) {
+        double f0 = 0.04 * (1.0 - metal) + albedo[ch] * metal;
+        double F = schlick_f(f0, hdo);
+        double spec = D * F * G / (4.0 * ndo * ndi);
+        double diff = (1.0 - F) * (1.0 - metal) * albedo[ch] / PI;
+        out[ch] = diff + spec;
+    }
+}
+
+OR_API void or_brdf(const double n[3], const double wo[3], const double wi[3], const double albedo[3],
+                    double rough, double metal, double out[3])
+{
+    double k = (rough + 1.0) * (rough + 1.0) / 8.0;
+    or_brdf_k(n, wo, wi, albedo, rough, metal, k, out);
+}
+
+static void brdf_v(v3 n, v3 wo, v3 wi, const float* mat, double out[3])
+{
+    double nn[3] = {n.x, n.y, n.z}, o[3] = {wo.x, wo.y, wo.z}, i[3] = {wi.x, wi.y, wi.z};
+    double alb[3] = {mat[0], mat[1], mat[2]};
+    or_brdf(nn, o, i, alb, (double)mat[3], (double)mat[4], out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Surface point of a primary hit (FP64): barycentric point, two-sided       */
+/* geometric normal facing the viewer, shadow-ray origin offset.              */
+/* ------------------------------------------------------------------------- */
+typedef struct { v3 p, n, wo, os; } surface;
+
+static void make_surface(const or_scene* s, uint32_t tri, double u, double v, v3 dir, surface* S)
+{
+    v3 a, b, c;
+    tri_verts(s, tri, &a, &b, &c);
+    S->p = add(add(scl(a, 1.0 - u - v), scl(b, u)), scl(c, v));
+    v3 ng = nrm(cross(sub(b, a), sub(c, a)));
+    if (dot(ng, dir) > 0.0) ng = scl(ng, -1.0);
+    S->n = ng;
+    S->wo = nrm(scl(dir, -1.0));
+    double off = ldexp(fmax(1.0, amax(S->p)), -18);
+    S->os = add(S->p, scl(S->n, off));
+}
+
+/* Shadow segment from the surface origin to a target point; the FP32 side holds the origin
+ * rounded to FP32 and the direction as fl(target - fl(origin)), target error et per component. */
+static int shadow_test(const or_scene* s, const or_bvh* B, const surface* S, v3 target, double target_err,
+                       double c, int* cast, int* band)
+{
+    v3 d = sub(target, S->os);
+    ray_ev r;
+    r.o = S->os; r.d = d;
+    r.eo = ev3_rounded(S->os);
+    ev3 T = {{target.x, target_err}, {target.y, target_err}, {target.z, target_err}};
+    r.ed = ev3_sub(T, r.eo);
+    /* cast iff n . d > 0 (light on the front side); FP32 evaluates it from rounded n and d */
+    ev3 N = ev3_rounded(S->n);
+    ev nd = ev3_dot(N, r.ed);
+    *band = 0;
+    *cast = nd.v > 0.0;
+    if (fabs(nd.v) <= c * nd.e) *band = 1;
+    if (!*cast) return 0;
+    int b2 = 0;
+    uint32_t who;
+    int occ = any_bvh(s, B, &r, 0.0, 1.0, c, &b2, &who);
+    if (b2) *band = 1;
+    return occ;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Point-light render of a list of samples.                                   */
+/* ------------------------------------------------------------------------- */
+OR_API void or_render_point(const or_scene* s, const or_bvh* B, const or_camera* cam,
+                            const float* lights, int n_lights, double c,
+                            const int64_t* samples, int64_t n,
+                            uint32_t* hit_id, double* tuv, double* tuv_err, uint8_t* band_primary,
+                            uint32_t* mask, uint32_t* band_shadow, double* rgb)
+{
+    cam_basis cb;
+    camera_basis(cam, &cb);
+    for (int64_t q = 0; q < n; ++q) {
+        float of[3], df[3];
+        gen_ray(cam, &cb, samples[q], of, df);
+        ray_ev r = exact_ray(from_f(of), from_f(df));
+        hit_rec h;
+        if (B) closest_bvh(B, &r, 0.0, INFINITY, c, &h);
+        else closest_brute(s, &r, 0.0, INFINITY, c, &h);
+        hit_id[q] = h.id;
+        tuv[3 * q + 0] = h.t; tuv[3 * q + 1] = h.u; tuv[3 * q + 2] = h.v;
+        tuv_err[3 * q + 0] = h.et; tuv_err[3 * q + 1] = h.eu; tuv_err[3 * q + 2] = h.ev;
+        band_primary[q] = (uint8_t)h.band;
+        mask[q] = 0; band_shadow[q] = 0;
+        rgb[3 * q + 0] = rgb[3 * q + 1] = rgb[3 * q + 2] = 0.0;
+        if (h.id == NO_HIT) continue;
+        surface S;
+        make_surface(s, h.id, h.u, h.v, r.d, &S);
+        const float* mat = s->mats + 5 * (int64_t)s->tri_mat[h.id];
+        for (int l = 0; l < n_lights; ++l) {
+            const float* L = lights + 6 * l;
+            v3 lp = from_f(L);
+            int cast, band;
+            int occ = shadow_test(s, B, &S, lp, 0.0, c, &cast, &band);
+            if (band) band_shadow[q] |= 1u << l;
+            if (!cast || occ) continue;
+            mask[q] |= 1u << l;
+            v3 tl = sub(lp, S.p);
+            double d2 = dot(tl, tl);
+            v3 wi = nrm(tl);
+            double f[3];
+            brdf_v(S.n, S.wo, wi, mat, f);
+            double cosi = fmax(dot(S.n, wi), 0.0);
+            for (int ch = 0; ch < 3; ++ch) rgb[3 * q + ch] += f[ch] * (double)L[3 + ch] * cosi / d2;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Rectangular area light: visibility estimate and unshadowed radiance.      */
+/* rect = centre[3], edge_u[3], edge_v[3], radiance[3].  Light samples        */
+/* y_k = c + (xi1 - 1/2) e_u + (xi2 - 1/2) e_v, xi from Philox with counter  */
+/* (pixel, k, 1 + stream, 0).  V = mean over k of [n.d > 0, light faces the  */
+/* point, segment unoccluded].  Radiance = unshadowed centre-point radiance  */
+/* (L_e A cos_L at the centre) times V.                                       */
+/* ------------------------------------------------------------------------- */
+typedef struct { v3 C, EU, EV, nL; double area, terr; } rect_geo;
+
+static void rect_setup(const float* rect, rect_geo* R)
+{
+    R->C = from_f(rect); R->EU = from_f(rect + 3); R->EV = from_f(rect + 6);
+    v3 nl_raw = cross(R->EU, R->EV);
+    R->area = len(nl_raw);
+    R->nL = nrm(nl_raw);
+    R->terr = 3.0 * U32R * (amax(R->C) + 0.5 * amax(R->EU) + 0.5 * amax(R->EV));
+}
+
+/* N light samples at one surface point; returns the visible count, adds band samples to *band_count */
+static int rect_visibility(const or_scene* s, const or_bvh* B, const surface* S, const rect_geo* R,
+                           uint32_t pixel, int N, uint32_t stream, uint32_t seed, uint32_t frame, double c,
+                           int* band_count)
+{
+    int vis = 0;
+    for (int k = 0; k < N; ++k) {
+        uint32_t ctr[4] = {pixel, (uint32_t)k, 1u + stream, 0u}, key[2] = {seed, frame}, rr[4];
+        or_philox4x32_10(ctr, key, rr);
+        v3 y = add(add(R->C, scl(R->EU, unit24(rr[0]) - 0.5)), scl(R->EV, unit24(rr[1]) - 0.5));
+        int cast, band;
+        int occ = shadow_test(s, B, S, y, R->terr, c, &cast, &band);
+        /* the light emits on the side its normal e_u x e_v points to */
+        v3 d = sub(y, S->os);
+        double ed = 4.0 * U32R * amax(d);
+        ev3 D = {{d.x, ed}, {d.y, ed}, {d.z, ed}};
+        ev facing = ev3_dot(ev3_rounded(R->nL), D);
+        int faces = facing.v < 0.0;
+        if (fabs(facing.v) <= c * facing.e) band = 1;
+        if (band) (*band_count)++;
+        if (cast && faces && !occ) vis++;
+    }
+    return vis;
+}
+
+/* Visibility of the rect light from an explicit surface point p with unit normal n
+ * (shadow origin offset as for camera hits); Philox counter (pixel, k, 1 + stream, 0). */
+OR_API int or_rect_vis_point(const or_scene* s, const or_bvh* B, const double p[3], const double n[3],
+                             const float* rect, int N, uint32_t stream, uint32_t pixel, uint32_t seed,
+                             uint32_t frame, double c, int* band_count)
+{
+    surface S;
+    S.p = mk(p[0], p[1], p[2]);
+    S.n = nrm(mk(n[0], n[1], n[2]));
+    S.wo = S.n;
+    double off = ldexp(fmax(1.0, amax(S.p)), -18);
+    S.os = add(S.p, scl(S.n, off));
+    rect_geo R;
+    rect_setup(rect, &R);
+    *band_count = 0;
+    return rect_visibility(s, B, &S, &R, pixel, N, stream, seed, frame, c, band_count);
+}
+
+OR_API void or_render_rect(const or_scene* s, const or_bvh* B, const or_camera* cam,
+                           const float* rect, int n_light_samples, uint32_t stream, double c,
+                           const int64_t* pixels, int64_t n,
+                           uint32_t* hit_id, uint8_t* band_primary,
+                           int32_t* vis_count, int32_t* band_count, double* rgb_unshadowed)
+{
+    cam_basis cb;
+    camera_basis(cam, &cb);
+    rect_geo R;
+    rect_setup(rect, &R);
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t pix = pixels[q];
+        float of[3], df[3];
+        gen_ray(cam, &cb, pix, of, df);   /* 1 sample per pixel */
+        ray_ev r = exact_ray(from_f(of), from_f(df));
+        hit_rec h;
+        if (B) closest_bvh(B, &r, 0.0, INFINITY, c, &h);
+        else closest_brute(s, &r, 0.0, INFINITY, c, &h);
+        hit_id[q] = h.id;
+        band_primary[q] = (uint8_t)h.band;
+        vis_count[q] = 0; band_count[q] = 0;
+        rgb_unshadowed[3 * q] = rgb_unshadowed[3 * q + 1] = rgb_unshadowed[3 * q + 2] = 0.0;
+        if (h.id == NO_HIT) continue;
+        surface S;
+        make_surface(s, h.id, h.u, h.v, r.d, &S);
+        int bc = 0;
+        vis_count[q] = rect_visibility(s, B, &S, &R, (uint32_t)pix, n_light_samples, stream,
+                                       cam->seed, cam->frame, c, &bc);
+        band_count[q] = bc;
+        /* unshadowed centre-point radiance: the light seen as a point source of intensity L_e A cos_L */
+        const float* mat = s->mats + 5 * (int64_t)s->tri_mat[h.id];
+        v3 tl = sub(R.C, S.p);
+        double d2 = dot(tl, tl);
+        v3 wi = nrm(tl);
+        double cosl = fmax(-dot(R.nL, wi), 0.0);
+        double cosi = fmax(dot(S.n, wi), 0.0);
+        double f[3];
+        brdf_v(S.n, S.wo, wi, mat, f);
+        for (int ch = 0; ch < 3; ++ch)
+            rgb_unshadowed[3 * q + ch] = f[ch] * (double)rect[9 + ch] * R.area * cosl * cosi / d2;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* FP32 mirrors: supersampling resolve and rigid vertex transforms.          */
+/* ------------------------------------------------------------------------- */
+/* out[p] = ((s0 + s1) + (s2 + s3)) * 0.25 per channel; n_per = 4; or copy when n_per = 1 */
+OR_API void or_resolve_f32(const float* samples, int64_t n_pixels, int n_per, float* out)
+{
+    for (int64_t p = 0; p < n_pixels; ++p) {
+        for (int ch = 0; ch < 4; ++ch) {
+            if (n_per == 1) { out[4 * p + ch] = samples[4 * p + ch]; continue; }
+            const float* s = samples + (int64_t)16 * p + ch;
+            float a = s[0] + s[4];
+            float b = s[8] + s[12];
+            out[4 * p + ch] = (a + b) * 0.25f;
+        }
+    }
+}
+
+/* rest (nv x 3) -> out for the vertex ranges of the given bodies:
+ * x' = ((R00 x + R01 y) + R02 z) + t0, etc., with M = [R | t] row-major 3x4 */
+OR_API void or_transform_f32(const float* rest, const uint32_t* body_vrange, const uint32_t* body_ids,
+                             const float* xf, int64_t n_bodies, float* out)
+{
+    for (int64_t b = 0; b < n_bodies; ++b) {
+        const float* M = xf + 12 * b;
+        uint32_t first = body_vrange[2 * (int64_t)body_ids[b]], count = body_vrange[2 * (int64_t)body_ids[b] + 1];
+        for (uint32_t i = first; i < first + count; ++i) {
+            const float* p = rest + 3 * (int64_t)i;
+            for (int r = 0; r < 3; ++r) {
+                float a = M[4 * r + 0] * p[0];
+                float bb = M[4 * r + 1] * p[1];
+                float cc = M[4 * r + 2] * p[2];
+                out[3 * (int64_t)i + r] = ((a + bb) + cc) + M[4 * r + 3];
+            }
+        }
+    }
+}
+
+/* Per-triangle classification of an FP32-exact ray: out = {exact_hit, status, t, u, v, et, eu, ev}. */
+OR_API void or_tri_test(const or_scene* s, uint32_t tri, const float o[3], const float d[3],
+                        double tmin, double tmax, double c, double out[8])
+{
+    ray_ev r = exact_ray(from_f(o), from_f(d));
+    tri_test tt;
+    mt_test(s, tri, &r, tmin, tmax, c, &tt);
+    out[0] = tt.exact_hit; out[1] = tt.status; out[2] = tt.t; out[3] = tt.u; out[4] = tt.v;
+    out[5] = tt.et; out[6] = tt.eu; out[7] = tt.ev;
+}

@@ -1,0 +1,457 @@
+"""Pins of the CPU oracle against what mathematics and the paper fix, independent of the oracle's own code.
+
+Every check here compares the oracle with a closed form, a brute-force answer, an invariant or a
+special case that reduces to a textbook formula — never with a retyped copy of the oracle's formula.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_2410_05095_amd import scenegen as sg
+
+NO_HIT = 0xFFFFFFFF
+
+
+# ----------------------------------------------------------------------------- helpers
+def tri_scene(O, verts, tris, mats=None, tri_mat=None, bvh=True):
+    v = np.asarray(verts, np.float32).reshape(-1, 3)
+    f = np.asarray(tris, np.uint32).reshape(-1, 3)
+    m = np.asarray(mats if mats is not None else [[0.5, 0.5, 0.5, 0.5, 0.0]], np.float32)
+    tm = np.asarray(tri_mat if tri_mat is not None else np.zeros(len(f)), np.uint32)
+    return O.OracleScene(v, f, tm, m, use_bvh=bvh)
+
+
+def quad(y, half, x0=0.0, z0=0.0):
+    v = [(x0 - half, y, z0 - half), (x0 + half, y, z0 - half), (x0 + half, y, z0 + half), (x0 - half, y, z0 + half)]
+    return v, [(0, 2, 1), (0, 3, 2)]
+
+
+# ----------------------------------------------------------------------------- Philox
+def test_philox_bijective_and_uniform(oracle_mod):
+    """A fixed key makes Philox a bijection of the counter: no collisions; outputs uniform (chi-square)."""
+    O = oracle_mod
+    outs = np.array([O.philox([i, 0, 0, 0], [12345, 7]) for i in range(20000)])
+    assert len({tuple(r) for r in outs}) == len(outs)
+    top = (outs[:, 0] >> 24).astype(np.int64)
+    hist = np.bincount(top, minlength=256)
+    chi2 = ((hist - len(top) / 256) ** 2 / (len(top) / 256)).sum()
+    assert 180 < chi2 < 340  # 255 dof: mean 255, sd 22.6
+
+
+def test_philox_avalanche(oracle_mod):
+    """Flipping one counter or key bit flips about half of the 128 output bits."""
+    O = oracle_mod
+    rng = np.random.default_rng(1)
+    flips = []
+    for _ in range(200):
+        ctr = rng.integers(0, 2 ** 32, 4, dtype=np.uint64).astype(np.uint32)
+        key = rng.integers(0, 2 ** 32, 2, dtype=np.uint64).astype(np.uint32)
+        base = O.philox(ctr, key)
+        w, b = rng.integers(6), rng.integers(32)
+        c2, k2 = ctr.copy(), key.copy()
+        if w < 4:
+            c2[w] ^= np.uint32(1 << int(b))
+        else:
+            k2[w - 4] ^= np.uint32(1 << int(b))
+        diff = base ^ O.philox(c2, k2)
+        flips.append(sum(bin(int(x)).count("1") for x in diff))
+    assert 60 < np.mean(flips) < 68
+
+
+# ----------------------------------------------------------------------------- camera rays
+def test_center_ray_is_view_direction(oracle_mod):
+    O = oracle_mod
+    cam = sg.Camera(eye=(1.0, 2.0, 3.0), target=(-4.0, 0.5, 7.0), up=(0, 1, 0), vfov_deg=60.0, width=5, height=3)
+    o, d = O.gen_rays(cam, np.array([1 * 5 + 2]))
+    f = np.subtract(cam.target, cam.eye)
+    f /= np.linalg.norm(f)
+    assert np.allclose(o[0], cam.eye)
+    assert np.abs(d[0] - f).max() < 2e-7
+
+
+def test_pinhole_geometry(oracle_mod):
+    """Rays through pixel centres meet the unit image plane on a regular grid spanning the field of view."""
+    O = oracle_mod
+    W, H, fov = 64, 48, 50.0
+    cam = sg.Camera(eye=(0.0, 10.0, -28.0), target=(0.0, 5.0, 0.0), up=(0, 1, 0), vfov_deg=fov, width=W, height=H)
+    o, d = O.gen_rays(cam, np.arange(W * H))
+    d = d.astype(np.float64)
+    f = np.subtract(cam.target, cam.eye)
+    f /= np.linalg.norm(f)
+    r = np.cross(f, [0, 1, 0])
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    P = d / (d @ f)[:, None]
+    x = (P @ r).reshape(H, W)
+    y = (P @ u).reshape(H, W)
+    T = math.tan(math.radians(fov) / 2)
+    A = W / H
+    # regular spacing 2 T A / W along rows and 2 T / H down columns (rows go top to bottom)
+    assert np.allclose(np.diff(x, axis=1), 2 * T * A / W, rtol=1e-4)
+    assert np.allclose(np.diff(y, axis=0), -2 * T / H, rtol=1e-4)
+    # outermost pixel centres sit half a pixel inside the frustum edges
+    assert abs(x[0, 0] + T * A * (1 - 1 / W)) < 1e-5 and abs(x[0, -1] - T * A * (1 - 1 / W)) < 1e-5
+    assert abs(y[0, 0] - T * (1 - 1 / H)) < 1e-5 and abs(y[-1, 0] + T * (1 - 1 / H)) < 1e-5
+    assert np.abs(np.linalg.norm(d, axis=1) - 1).max() < 3e-7
+
+
+def test_ssaa_samples_in_their_strata(oracle_mod):
+    """2x2 jitter: sample k of a pixel lands in sub-pixel quadrant k (x from bit 0, y from bit 1)."""
+    O = oracle_mod
+    W, H, fov = 16, 12, 40.0
+    cam = sg.Camera(eye=(0.0, 0.0, 0.0), target=(0.0, 0.0, -1.0), up=(0, 1, 0), vfov_deg=fov, width=W, height=H,
+                    ssaa=2, seed=3)
+    o, d = O.gen_rays(cam, np.arange(W * H * 4))
+    d = d.astype(np.float64)
+    T = math.tan(math.radians(fov) / 2)
+    A = W / H
+    px = d[:, 0] / -d[:, 2]
+    py = d[:, 1] / -d[:, 2]
+    xs = (px / (T * A) + 1) * W / 2          # continuous pixel coordinate
+    ys = (1 - py / T) * H / 2
+    s = np.arange(W * H * 4)
+    pix, k = s // 4, s % 4
+    i, j = pix % W, pix // W
+    fx = xs - i - (k & 1) * 0.5
+    fy = ys - j - (k >> 1) * 0.5
+    eps = 1e-4
+    assert (fx > -eps).all() and (fx < 0.5 + eps).all()
+    assert (fy > -eps).all() and (fy < 0.5 + eps).all()
+    # the jitter is not constant: offsets spread over the stratum
+    assert fx.std() > 0.1 and fy.std() > 0.1
+
+
+# ----------------------------------------------------------------------------- ray-triangle
+def test_single_triangle_closed_form(oracle_mod):
+    O = oracle_mod
+    sc = tri_scene(O, [(0, 0, 0), (1, 0, 0), (0, 1, 0)], [(0, 1, 2)], bvh=False)
+    hid, tuv, err, band = sc.closest([0.25, 0.5, 2.0], [0, 0, -1])
+    assert hid == 0 and not band
+    assert np.allclose(tuv, [2.0, 0.25, 0.5], atol=1e-15)
+    hid, *_ = sc.closest([0.75, 0.5, 2.0], [0, 0, -1])   # outside (u + v > 1)
+    assert hid == NO_HIT
+    hid, *_ = sc.closest([0.25, 0.5, 2.0], [0, 0, 1])    # behind the origin
+    assert hid == NO_HIT
+
+
+def test_tie_to_smaller_id_and_band(oracle_mod):
+    O = oracle_mod
+    v, f = quad(0.0, 1.0)
+    verts = v + v
+    tris = f + [(a + 4, b + 4, c + 4) for a, b, c in f]
+    sc = tri_scene(O, verts, tris)
+    hid, tuv, err, band = sc.closest([0.3, 1.0, 0.1], [0, -1, 0])
+    assert hid in (0, 1) and band     # coincident copies: smallest id of the covering pair, inside the band
+    brute = sc.closest([0.3, 1.0, 0.1], [0, -1, 0], brute=True)
+    assert brute[0] == hid
+
+
+def test_shared_edge_is_band_outside_is_not(oracle_mod):
+    O = oracle_mod
+    v, f = quad(0.0, 1.0)
+    sc = tri_scene(O, v, f)
+    # diagonal edge (x = z) shared by both triangles
+    hid, _, _, band = sc.closest(np.float32([0.25, 1.0, 0.25]), [0, -1, 0])
+    assert hid in (0, 1) and band
+    hid, _, _, band = sc.closest(np.float32([0.5, 1.0, 0.1]), [0, -1, 0])
+    assert hid != NO_HIT and not band
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_bvh_equals_brute_force(oracle_mod, seed):
+    """The oracle BVH only prunes: every field equals the all-triangle answer."""
+    O = oracle_mod
+    s = sg.small_random_scene(seed, n_instances=6 + seed, width=23 + seed, height=17, ssaa=1 + seed % 2)
+    osc = O.OracleScene.from_scene(s)
+    cam = s.cameras[0]
+    smp = np.arange(cam.n_samples)
+    a = osc.render_point(cam, s.point_lights, smp)
+    b = osc.render_point(cam, s.point_lights, smp, brute=True)
+    for k in ("hit_id", "mask", "band_primary", "band_shadow"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["tuv"], b["tuv"])
+    assert np.array_equal(a["rgb"], b["rgb"])
+    assert (a["hit_id"] != NO_HIT).sum() > cam.n_samples // 3
+    assert a["band_primary"].mean() < 0.02
+
+
+def test_band_grows_with_safety_factor(oracle_mod):
+    O = oracle_mod
+    s = sg.small_random_scene(5, n_instances=10, width=40, height=30)
+    osc = O.OracleScene.from_scene(s)
+    cam = s.cameras[0]
+    smp = np.arange(cam.n_samples)
+    counts = [int(osc.render_point(cam, s.point_lights, smp, c=c)["band_primary"].sum()) for c in (1, 4, 16, 64)]
+    assert counts == sorted(counts)
+
+
+# ----------------------------------------------------------------------------- hard shadows
+def test_square_occluder_umbra(oracle_mod):
+    """Point light at height H over a square of side s at height h: ground points with
+    max(|x|,|z|) < s H / (2 (H - h)) are blocked, others are lit."""
+    O = oracle_mod
+    H, h, side = 10.0, 5.0, 2.0
+    gv, gf = quad(0.0, 20.0)
+    ov, of = quad(h, side / 2)
+    sc = tri_scene(O, gv + ov, gf + [(a + 4, b + 4, c + 4) for a, b, c in of])
+    edge = side * H / (2 * (H - h))
+    rng = np.random.default_rng(0)
+    n_checked = 0
+    for x, z in rng.uniform(-4, 4, (400, 2)):
+        o = np.array([x, 1e-4, z])
+        occ, band = sc.any_hit(o, np.array([0.0, H, 0.0]) - o)
+        dist = abs(max(abs(x), abs(z)) - edge)
+        if dist > 1e-3:
+            assert not band
+            assert occ == (max(abs(x), abs(z)) < edge)
+            n_checked += 1
+    assert n_checked > 390
+
+
+def test_tiny_box_sphere_shadow_cone(oracle_mod):
+    """In the 12+1280-triangle box, the icosphere (between its inscribed and circumscribed spheres)
+    blocks the light exactly for wall/floor points whose segment to the light passes within the
+    inscribed radius of the centre, and never when it stays outside radius 0.3."""
+    O = oracle_mod
+    s = sg.tiny_box_scene(0)
+    osc = O.OracleScene.from_scene(s)
+    cam = s.cameras[0]
+    smp = np.arange(cam.n_samples)
+    res = osc.render_point(cam, s.point_lights, smp)
+    o, d = O.gen_rays(cam, smp)
+    p = o.astype(np.float64) + res["tuv"][:, :1] * d.astype(np.float64)
+    # inscribed radius of the icosphere polyhedron: smallest distance from the centre to a face plane
+    sv = s.positions.astype(np.float64)
+    sf = s.indices[12:]
+    nrm = np.cross(sv[sf[:, 1]] - sv[sf[:, 0]], sv[sf[:, 2]] - sv[sf[:, 0]])
+    r_in = np.min(np.abs((nrm * sv[sf[:, 0]]).sum(1)) / np.linalg.norm(nrm, axis=1))
+    L = np.array([0.0, 0.45, 0.0])
+    box = res["hit_id"] < 12
+    seg = L - p
+    tt = np.clip((-(p * seg).sum(1)) / (seg * seg).sum(1), 0, 1)
+    dist = np.linalg.norm(p + tt[:, None] * seg, axis=1)
+    blocked = box & (dist < r_in - 1e-4)
+    lit = box & (dist > 0.3 + 1e-4)
+    assert blocked.sum() > 1000 and lit.sum() > 1000
+    assert (res["mask"][blocked] == 0).all()
+    assert (res["mask"][lit] == 1).all()
+    # the whole visible floor (y = -0.5) is in the umbra
+    floor = box & (np.abs(p[:, 1] + 0.5) < 1e-6)
+    assert floor.sum() > 100 and (res["mask"][floor] == 0).all()
+
+
+# ----------------------------------------------------------------------------- area light
+def test_area_light_closed_form(oracle_mod):
+    """Square light (side a, height H) over a square occluder (side s, height h): exact visibility
+    V(x) = 1 - l_x l_z / a^2; the N-sample estimate is unbiased with variance V (1 - V) / N."""
+    O = oracle_mod
+    a, H, side, h = 1.0, 21.0, 1.0, 10.0
+    gv, gf = quad(0.0, 20.0)
+    ov, of = quad(h, side / 2)
+    sc = tri_scene(O, gv + ov, gf + [(p + 4, q + 4, r + 4) for p, q, r in of])
+    rect = sg.RectLight(center=(0.0, H, 0.0), edge_u=(a, 0.0, 0.0), edge_v=(0.0, 0.0, a), radiance=(1, 1, 1))
+
+    def ell(xi):
+        lo = max(-a / 2, (-side / 2 - xi * (1 - h / H)) * H / h)
+        hi = min(a / 2, (side / 2 - xi * (1 - h / H)) * H / h)
+        return max(0.0, hi - lo)
+
+    N = 64
+    rng = np.random.default_rng(2)
+    z_sum, var_sum, n = 0.0, 0.0, 0
+    partial = 0
+    for k, (x, z) in enumerate(rng.uniform(-1.2, 1.2, (600, 2))):
+        V = 1 - ell(x) * ell(z) / a ** 2
+        vis, bands = sc.rect_vis_point([x, 0.0, z], [0, 1, 0], rect, N, stream=0, pixel=k)
+        Vn = vis / N
+        z_sum += Vn - V
+        var_sum += V * (1 - V) / N
+        n += 1
+        partial += 0 < V < 1
+        if V in (0.0, 1.0):
+            assert Vn == V
+    assert partial > 200
+    # mean error within 4 standard errors of zero
+    assert abs(z_sum) < 4 * math.sqrt(var_sum)
+
+
+def test_area_streams_independent(oracle_mod):
+    O = oracle_mod
+    gv, gf = quad(0.0, 20.0)
+    ov, of = quad(10.0, 0.25)   # partial shadow at (0.3, 0, 0.2): V = 1 - 0.695 * 0.805
+    sc = tri_scene(O, gv + ov, gf + [(p + 4, q + 4, r + 4) for p, q, r in of])
+    rect = sg.DEFAULT_RECT
+    a = [sc.rect_vis_point([0.3, 0, 0.2], [0, 1, 0], rect, 1, stream=0, pixel=k)[0] for k in range(400)]
+    b = [sc.rect_vis_point([0.3, 0, 0.2], [0, 1, 0], rect, 1, stream=1, pixel=k)[0] for k in range(400)]
+    assert 0.05 < np.mean(a) < 0.95
+    assert np.mean(np.array(a) == np.array(b)) < 0.9
+
+
+# ----------------------------------------------------------------------------- BRDF
+ROUGH = [0.05, 0.1, 0.3, 0.6, 1.0]
+
+
+@pytest.mark.parametrize("r", ROUGH)
+def test_ggx_ndf_normalised(oracle_mod, r):
+    """Projected NDF integrates to one over the hemisphere."""
+    O = oracle_mod
+    alpha = r * r
+    n = np.array([0.0, 0.0, 1.0])
+
+    def g(th):
+        return O.ggx_D(n, [math.sin(th), 0.0, math.cos(th)], alpha) * math.cos(th) * math.sin(th) * 2 * math.pi
+
+    pts = [x * alpha for x in (0.5, 1, 2, 5, 20, 100)] + [0.5, 1.0]
+    pts = sorted(p for p in pts if p < math.pi / 2)
+    val, _ = integrate.quad(g, 0, math.pi / 2, points=pts, limit=800, epsabs=1e-10, epsrel=1e-10)
+    assert abs(val - 1) < 1e-6
+
+
+@pytest.mark.parametrize("r", [0.3, 0.6, 1.0])
+@pytest.mark.parametrize("theta_o", [0.0, 30.0, 60.0, 80.0])
+def test_weak_white_furnace(oracle_mod, r, theta_o):
+    """Heitz (JCGT 2014): with the exact Smith-GGX G1, the visible normals integrate to one."""
+    O = oracle_mod
+    alpha = r * r
+    to = math.radians(theta_o)
+    wo = np.array([math.sin(to), 0.0, math.cos(to)])
+    n = np.array([0.0, 0.0, 1.0])
+    g1 = 2.0 / (1.0 + math.sqrt(1.0 + alpha ** 2 * math.tan(to) ** 2))
+    phi = np.linspace(0, 2 * math.pi, 4096, endpoint=False)
+
+    def g(th):
+        h = np.stack([np.sin(th) * np.cos(phi), np.sin(th) * np.sin(phi), np.full_like(phi, math.cos(th))], 1)
+        proj = np.maximum(h @ wo, 0).mean() * 2 * math.pi
+        return O.ggx_D(n, [math.sin(th), 0.0, math.cos(th)], alpha) * proj * math.sin(th)
+
+    val, _ = integrate.quad(g, 0, math.pi / 2, points=[alpha, 3 * alpha], limit=400, epsabs=1e-9)
+    val = g1 * val / wo[2]
+    assert abs(val - 1) < 1e-4
+
+
+def test_schlick_g1_matches_smith_at_unit_roughness(oracle_mod):
+    """With roughness 1, the remap k = (r+1)^2/8 = 1/2 makes Schlick-GGX equal exact Smith-GGX (alpha = 1)."""
+    O = oracle_mod
+    k = (1.0 + 1.0) ** 2 / 8
+    for th in np.linspace(0.01, 1.55, 40):
+        smith = 2.0 / (1.0 + math.sqrt(1.0 + math.tan(th) ** 2))
+        assert abs(O.schlick_g1(math.cos(th), k) - smith) < 1e-14
+
+
+def test_schlick_fresnel_limits(oracle_mod):
+    O = oracle_mod
+    for f0 in (0.04, 0.5, 0.95):
+        assert abs(O.schlick_f(f0, 1.0) - f0) < 1e-15
+        assert abs(O.schlick_f(f0, 0.0) - 1.0) < 1e-15
+        assert O.schlick_f(f0, 0.5) > f0
+
+
+@pytest.mark.parametrize("r", ROUGH)
+@pytest.mark.parametrize("m", [0.0, 1.0, 0.4])
+def test_brdf_normal_incidence_special_case(oracle_mod, r, m):
+    """n = wo = wi: f = (1 - F0)(1 - m) albedo / pi + F0 / (4 pi alpha^2)."""
+    O = oracle_mod
+    alb = np.array([0.3, 0.6, 0.85])
+    n = np.array([0.0, 1.0, 0.0])
+    f = O.brdf(n, n, n, alb, r, m)
+    F0 = 0.04 * (1 - m) + alb * m
+    want = (1 - F0) * (1 - m) * alb / math.pi + F0 / (4 * math.pi * r ** 4)
+    assert np.allclose(f, want, rtol=1e-13, atol=0)
+
+
+def test_brdf_reciprocity(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(4)
+    n = np.array([0.0, 0.0, 1.0])
+    for _ in range(500):
+        a, b = rng.normal(size=3), rng.normal(size=3)
+        a[2], b[2] = abs(a[2]) + 0.01, abs(b[2]) + 0.01
+        a /= np.linalg.norm(a)
+        b /= np.linalg.norm(b)
+        alb = rng.uniform(0.2, 0.9, 3)
+        r, m = rng.uniform(0.05, 1), float(rng.random() < 0.3)
+        f1 = O.brdf(n, a, b, alb, r, m)
+        f2 = O.brdf(n, b, a, alb, r, m)
+        assert np.allclose(f1, f2, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("r", ROUGH)
+def test_brdf_energy_bounded(oracle_mod, r):
+    """With F0 = 1 (white metal) the directional albedo never exceeds one."""
+    O = oracle_mod
+    alpha = r * r
+    n = np.array([0.0, 0.0, 1.0])
+    alb = np.ones(3)
+    s_nodes, s_w = np.polynomial.legendre.leggauss(160)
+    s = 0.5 * (s_nodes + 1)
+    ws = 0.5 * s_w
+    th = np.arctan(alpha * np.tan(0.5 * math.pi * s * 0.999))
+    dth = alpha * 0.5 * math.pi * 0.999 / np.cos(0.5 * math.pi * s * 0.999) ** 2 / (1 + (alpha * np.tan(0.5 * math.pi * s * 0.999)) ** 2)
+    phis = np.linspace(0, 2 * math.pi, 96, endpoint=False)
+    for theta_o in (0.0, 45.0, 75.0, 88.0):
+        to = math.radians(theta_o)
+        wo = np.array([math.sin(to), 0.0, math.cos(to)])
+        total = 0.0
+        for t, w, dt in zip(th, ws, dth):
+            for ph in phis:
+                h = np.array([math.sin(t) * math.cos(ph), math.sin(t) * math.sin(ph), math.cos(t)])
+                oh = h @ wo
+                if oh <= 0:
+                    continue
+                wi = 2 * oh * h - wo
+                if wi[2] <= 0:
+                    continue
+                f = O.brdf(n, wo, wi, alb, r, 1.0)[0]
+                total += f * wi[2] * 4 * oh * math.sin(t) * w * dt * (2 * math.pi / len(phis))
+        assert total <= 1 + 1e-3, (theta_o, total)
+        if theta_o == 0.0:
+            assert total > 0.25   # white metal at alpha = 1 reflects ~0.31 (Monte Carlo)
+
+
+def test_plane_radiance_closed_form(oracle_mod):
+    """Camera and point light on the normal of a plane: L = f(n, n, n) I / h^2 at the centre pixel."""
+    O = oracle_mod
+    v, f = quad(0.0, 5.0)
+    mats = [[0.7, 0.4, 0.2, 0.35, 0.0]]
+    sc = tri_scene(O, v, f, mats=mats)
+    hgt, inten = 3.0, 5.0
+    cam = sg.Camera(eye=(0.0, hgt, 0.0), target=(0.0, 0.0, 0.0), up=(0, 0, 1), vfov_deg=30.0, width=3, height=3)
+    lights = np.array([[0.0, hgt, 0.0, inten, inten, inten]], np.float32)
+    res = sc.render_point(cam, lights, np.array([4]))
+    assert res["hit_id"][0] != NO_HIT and res["mask"][0] == 1
+    alb = np.array(mats[0][:3], np.float32).astype(np.float64)
+    r = float(np.float32(0.35))
+    F0 = 0.04
+    fwant = (1 - F0) * alb / math.pi + F0 / (4 * math.pi * r ** 4)
+    assert np.allclose(res["rgb"][0], fwant * inten / hgt ** 2, rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------- FP32 mirrors
+def test_resolve_f32(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(0)
+    const = np.full((10, 4, 4), 0.3712, np.float32)
+    assert np.array_equal(O.resolve_f32(const, 4), np.full((10, 4), np.float32(0.3712)))
+    s = rng.uniform(0, 5, (1000, 4, 4)).astype(np.float32)
+    out = O.resolve_f32(s, 4)
+    mean64 = s.astype(np.float64).mean(axis=1)
+    assert np.abs(out - mean64).max() <= 4 * np.finfo(np.float32).eps * 5
+    assert np.array_equal(O.resolve_f32(s[:, 0, :].copy(), 1), s[:, 0, :])
+
+
+def test_transform_f32(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(0)
+    rest = rng.uniform(-5, 5, (100, 3)).astype(np.float32)
+    vr = np.array([[0, 50], [50, 50]], np.uint32)
+    ident = np.array([[1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]], np.float32)
+    out = O.transform_f32(rest, vr, np.array([1], np.uint32), ident)
+    assert np.array_equal(out, rest)
+    # 90 degrees about y: (x, y, z) -> (z, y, -x), plus an exact translation
+    rot = np.array([[0, 0, 1, 0.5, 0, 1, 0, -2.0, -1, 0, 0, 0.25]], np.float32)
+    out = O.transform_f32(rest, vr, np.array([0], np.uint32), rot)
+    want = np.stack([rest[:50, 2] + np.float32(0.5), rest[:50, 1] - np.float32(2.0), -rest[:50, 0] + np.float32(0.25)], 1)
+    assert np.array_equal(out[:50], want)
+    assert np.array_equal(out[50:], rest[50:])
