@@ -1,0 +1,216 @@
+/*
+ * raycast.h — C ABI of the MI355X ray-cast rendering library.
+ *
+ * The library renders triangle scenes by software ray casting on AMD CDNA4
+ * (gfx950): primary visibility into a G-buffer, shadow rays towards point
+ * lights (hard shadows) or a rectangular area light (soft shadows),
+ * Cook-Torrance/GGX shading and a 2x2 supersampling resolve.  These are the
+ * rendering features of the paper's Sec. IV-B (physically based rendering,
+ * anti-aliasing, ray-traced shadows), recast as compute kernels; the
+ * acceleration structure is the BVH that Sec. IV-B ("Ray-traced shadows")
+ * builds for logarithmic-time ray queries.
+ *
+ * Conventions for every entry point
+ *  - Return value: RC_OK (0) or a negative rc_status.  No C++ exception crosses
+ *    the ABI.  A failed call leaves its outputs unspecified and all handles valid.
+ *  - Pointers named d_* are device pointers (e.g. from torch); all others are host
+ *    pointers.  The caller owns every input and output buffer; the library owns the
+ *    handles it creates and every device buffer reachable only through them.
+ *  - Work is enqueued on the context's HIP stream and is asynchronous: outputs are
+ *    valid after that stream is synchronised.  Host inputs may be freed when the call
+ *    returns; device inputs must stay valid until the stream reaches the work.
+ *  - Device faults detected after a call returned are sticky: rc_get_last_error
+ *    reports (and clears) them.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef RAYCAST_H
+#define RAYCAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rc_status {
+    RC_OK = 0,
+    RC_ERR_INVALID_ARG = -1,     /* null pointer, zero or out-of-range size, unknown option */
+    RC_ERR_INVALID_VALUE = -2,   /* NaN/Inf coordinate, index out of range, bad material */
+    RC_ERR_OUT_OF_MEMORY = -3,   /* device allocation failed */
+    RC_ERR_HIP = -4,             /* HIP runtime error (no device, launch failure, fault) */
+    RC_ERR_NOT_BUILT = -5,       /* render or refit before rc_bvh_build */
+    RC_ERR_QUEUE_OVERFLOW = -6,  /* a device work queue or traversal stack exceeded its bound */
+    RC_ERR_BAD_CHECKPOINT = -7,  /* denoiser checkpoint unreadable, wrong magic/version/shape/CRC */
+    RC_ERR_UNSUPPORTED = -8      /* valid request this build does not implement */
+} rc_status;
+
+typedef struct rc_ctx rc_ctx;
+typedef struct rc_scene rc_scene;
+
+/* Static string for a status code (never NULL). */
+const char* rc_status_string(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int rc_version(void);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  Fails with RC_ERR_HIP when no usable gfx9 device exists. */
+int rc_create(rc_ctx** out, int device, void* hip_stream);
+int rc_destroy(rc_ctx* ctx);
+int rc_set_stream(rc_ctx* ctx, void* hip_stream);
+/* Report and clear the sticky device error (synchronises the stream). */
+int rc_get_last_error(rc_ctx* ctx);
+
+/* ---------------------------------------------------------------- scene ---- */
+/* Geometry and materials, all host arrays copied at creation.
+ *  positions      n_vertices x 3 float, world space, finite
+ *  indices        n_tris x 3 uint32 < n_vertices (counter-clockwise winding gives
+ *                 the geometric normal e1 x e2; shading is two-sided)
+ *  tri_material   n_tris uint32 < n_materials
+ *  materials      n_materials x 5 float: albedo rgb in [0,1] (linear), roughness r in
+ *                 [0.01,1] (GGX alpha = r^2), metallic in [0,1] (glTF metallic-roughness)
+ *  body_vertex_range  n_bodies x 2 uint32 (first vertex, count): the rigid bodies that
+ *                 rc_scene_set_transforms may move (may be NULL when n_bodies = 0).
+ * Zero-area triangles are accepted and never hit.  Errors: RC_ERR_INVALID_ARG,
+ * RC_ERR_INVALID_VALUE, RC_ERR_OUT_OF_MEMORY. */
+typedef struct rc_scene_desc {
+    const float* positions;
+    uint32_t n_vertices;
+    const uint32_t* indices;
+    uint32_t n_tris;
+    const uint32_t* tri_material;
+    const float* materials;
+    uint32_t n_materials;
+    const uint32_t* body_vertex_range;
+    uint32_t n_bodies;
+} rc_scene_desc;
+
+int rc_scene_create(rc_ctx* ctx, const rc_scene_desc* desc, rc_scene** out);
+int rc_scene_destroy(rc_ctx* ctx, rc_scene* scene);
+
+/* --------------------------------------------------------------- BVH ---- */
+/* Build the scene's BVH on the host: binned SAH (`bins` bins per axis, default 32),
+ * leaves of at most `max_leaf` triangles (1..4, default 4), collapsed to a 4-wide BVH
+ * with all four child boxes of a node in one 128-byte record.  Replaces any previous
+ * BVH.  Synchronous with respect to the host (uploads on the context stream). */
+typedef struct rc_build_opts {
+    uint32_t bins;
+    uint32_t max_leaf;
+} rc_build_opts;
+int rc_bvh_build(rc_ctx* ctx, rc_scene* scene, const rc_build_opts* opts);
+
+/* Rigid motion of bodies: for i < n, body d_body_ids[i] gets vertices
+ * x' = R x_rest + t with d_xforms[12 i ..] = row-major [R | t] (3x4 float), where
+ * x_rest are the positions given at creation.  Bodies not listed keep their current
+ * positions.  Does not touch the BVH: call rc_bvh_refit before rendering. */
+int rc_scene_set_transforms(rc_ctx* ctx, rc_scene* scene, const float* d_xforms,
+                            const uint32_t* d_body_ids, uint32_t n);
+
+/* Recompute every node box bottom-up from the current vertex positions, keeping the
+ * tree topology (exact FP32 min/max, so boxes equal a fresh computation bit for bit).
+ * RC_ERR_NOT_BUILT without a prior rc_bvh_build. */
+int rc_bvh_refit(rc_ctx* ctx, rc_scene* scene);
+
+typedef struct rc_bvh_stats {
+    uint64_t n_nodes;      /* 4-wide internal nodes */
+    uint64_t n_leaves;
+    uint64_t n_tris;
+    uint32_t depth;        /* levels of 4-wide nodes */
+    uint32_t max_stack;    /* traversal stack entries that suffice for any ray */
+    double sah_cost;       /* SAH cost (node 1, triangle 1) relative to the root box */
+    double build_ms;       /* host build time of the last rc_bvh_build */
+} rc_bvh_stats;
+int rc_bvh_get_stats(rc_ctx* ctx, const rc_scene* scene, rc_bvh_stats* out);
+
+/* Copy the BVH to host memory for inspection: n_nodes*32 floats/uint32 words per node
+ * (lo_x[4] hi_x[4] lo_y[4] hi_y[4] lo_z[4] hi_z[4] child[4] meta[4]) and the
+ * triangle order (n_tris uint32, original triangle id per leaf slot).  Either pointer
+ * may be NULL.  Child word: bit 31 set = leaf with (bits 28..30) = count - 1 and
+ * (bits 0..27) = first slot; 0xFFFFFFFF = empty; otherwise an internal node index. */
+int rc_bvh_export(rc_ctx* ctx, const rc_scene* scene, uint32_t* nodes_out, uint32_t* tri_order_out);
+
+/* ------------------------------------------------------------- render ---- */
+/* Pinhole camera: right-handed, y up, pixel row 0 at the top; forward
+ * f = normalize(target - eye), right r = normalize(f x up), up u = r x f.  Sample
+ * offsets are (0.5, 0.5) for ssaa = 1; for ssaa = 2, sample k in 0..3 of pixel p lies
+ * in sub-pixel cell (k & 1, k >> 1) with a jitter from Philox4x32-10 keyed by
+ * (seed, frame) with counter (p, k, 0, 0). */
+typedef struct rc_camera {
+    float eye[3], target[3], up[3];
+    float vfov_deg;
+    int32_t width, height;
+    int32_t ssaa;            /* 1 or 2 (2x2 samples) */
+    uint32_t seed, frame;
+} rc_camera;
+
+typedef struct rc_point_light {
+    float position[3];
+    float intensity[3];      /* radiant intensity, RGB; falloff 1/d^2 */
+} rc_point_light;
+
+/* One-sided rectangle: emits radiance `radiance` towards the side of edge_u x edge_v. */
+typedef struct rc_rect_light {
+    float center[3], edge_u[3], edge_v[3];
+    float radiance[3];
+} rc_rect_light;
+
+enum {
+    RC_FLAG_TIMING = 1u      /* record per-stage device times (rc_get_stage_times) */
+};
+
+typedef struct rc_render_opts {
+    uint32_t area_samples;   /* light samples per pixel for the rect light (>= 1 when rect != NULL) */
+    uint32_t area_stream;    /* independent Philox stream of the rect-light samples */
+    uint32_t flags;
+} rc_render_opts;
+
+/* Outputs, all caller-owned device buffers, S = ssaa^2 samples per pixel:
+ *  d_rgba         W*H*4 float: resolved linear RGBA (alpha = coverage)
+ *  d_hit          W*H*S*4 uint32 per sample: (triangle id, t, u, v) with t, u, v as
+ *                 float bits; id 0xFFFFFFFF on a miss (t = +inf)
+ *  d_shadow       W*H*S uint32 per sample: bit l set iff point light l lights it
+ *                 (required when n_lights > 0)
+ *  d_visibility   W*H float: fraction of rect-light samples that reach the point
+ *                 (required when rect != NULL; ssaa must then be 1)
+ *  d_sample_rgba  optional W*H*S*4 float: per-sample radiance before the resolve. */
+typedef struct rc_outputs {
+    float* d_rgba;
+    uint32_t* d_hit;
+    uint32_t* d_shadow;
+    float* d_visibility;
+    float* d_sample_rgba;
+} rc_outputs;
+
+/* Render one camera.  Shading (linear HDR, no ambient term) sums over point lights
+ * with bit set: f(wo, wi) I cos(n, wi) / d^2, with f = Lambert (1 - F)(1 - m) albedo / pi
+ * + Cook-Torrance D F G / (4 (n.wo)(n.wi)): D = GGX with alpha = r^2, F = Schlick with
+ * F0 = mix(0.04, albedo, m), G = Schlick-GGX with k = (r + 1)^2 / 8.  A rect light
+ * adds its unshadowed centre-point term (intensity L_e A cos_L) times the visibility.
+ * Shadow rays start at p + n 2^-18 max(1, |p|_inf) and test hits with 0 < t < 1 on
+ * the segment to the light (or light sample); they are cast only when n . d > 0.
+ * Errors: RC_ERR_INVALID_ARG, RC_ERR_NOT_BUILT, RC_ERR_UNSUPPORTED (ssaa not 1/2, or
+ * ssaa 2 with a rect light), RC_ERR_HIP. */
+int rc_render(rc_ctx* ctx, rc_scene* scene, const rc_camera* cam,
+              const rc_point_light* lights, uint32_t n_lights,
+              const rc_rect_light* rect, const rc_render_opts* opts, const rc_outputs* out);
+
+/* Camera rays of every sample, exactly as the traversal generates them: d_origins and
+ * d_dirs receive W*H*S x 3 float each (sample s = pixel * S + k).  For verification of the
+ * FP32 ray definition. */
+int rc_camera_rays(rc_ctx* ctx, const rc_camera* cam, float* d_origins, float* d_dirs);
+
+/* Device milliseconds of the stages of the last rc_render made with RC_FLAG_TIMING:
+ * ms[0] primary traversal, ms[1] shadow traversal, ms[2] shade + resolve, ms[3] whole
+ * render; rays[0] primary rays cast, rays[1] shadow rays cast (only when counted: the
+ * count adds one atomic per wave).  Synchronises the stream. */
+typedef struct rc_stage_times {
+    float ms[8];
+    uint64_t rays[2];
+} rc_stage_times;
+int rc_get_stage_times(rc_ctx* ctx, rc_stage_times* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAYCAST_H */

@@ -1,0 +1,305 @@
+"""ctypes binding of libraycast.so (the C ABI in include/raycast.h).
+
+Argument marshalling only: torch provides device memory and the current HIP stream; every
+step of the rendering path runs in the library's HIP kernels.  There is no fallback: if the
+library is not built or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libraycast.so")
+
+RC_FLAG_TIMING = 1
+NO_HIT = 0xFFFFFFFF
+
+
+class RcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+F3 = C.c_float * 3
+
+
+class RcSceneDesc(C.Structure):
+    _fields_ = [("positions", C.c_void_p), ("n_vertices", C.c_uint32), ("indices", C.c_void_p),
+                ("n_tris", C.c_uint32), ("tri_material", C.c_void_p), ("materials", C.c_void_p),
+                ("n_materials", C.c_uint32), ("body_vertex_range", C.c_void_p), ("n_bodies", C.c_uint32)]
+
+
+class RcBuildOpts(C.Structure):
+    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32)]
+
+
+class RcBvhStats(C.Structure):
+    _fields_ = [("n_nodes", C.c_uint64), ("n_leaves", C.c_uint64), ("n_tris", C.c_uint64),
+                ("depth", C.c_uint32), ("max_stack", C.c_uint32), ("sah_cost", C.c_double),
+                ("build_ms", C.c_double)]
+
+
+class RcCamera(C.Structure):
+    _fields_ = [("eye", F3), ("target", F3), ("up", F3), ("vfov_deg", C.c_float), ("width", C.c_int32),
+                ("height", C.c_int32), ("ssaa", C.c_int32), ("seed", C.c_uint32), ("frame", C.c_uint32)]
+
+
+class RcPointLight(C.Structure):
+    _fields_ = [("position", F3), ("intensity", F3)]
+
+
+class RcRectLight(C.Structure):
+    _fields_ = [("center", F3), ("edge_u", F3), ("edge_v", F3), ("radiance", F3)]
+
+
+class RcRenderOpts(C.Structure):
+    _fields_ = [("area_samples", C.c_uint32), ("area_stream", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class RcOutputs(C.Structure):
+    _fields_ = [("d_rgba", C.c_void_p), ("d_hit", C.c_void_p), ("d_shadow", C.c_void_p),
+                ("d_visibility", C.c_void_p), ("d_sample_rgba", C.c_void_p)]
+
+
+class RcStageTimes(C.Structure):
+    _fields_ = [("ms", C.c_float * 8), ("rays", C.c_uint64 * 2)]
+
+
+P = C.c_void_p
+PP = C.POINTER(C.c_void_p)
+
+# name -> (restype, argtypes); every symbol declared in include/raycast.h
+SIGNATURES = {
+    "rc_status_string": (C.c_char_p, [C.c_int]),
+    "rc_version": (C.c_int, []),
+    "rc_create": (C.c_int, [PP, C.c_int, P]),
+    "rc_destroy": (C.c_int, [P]),
+    "rc_set_stream": (C.c_int, [P, P]),
+    "rc_get_last_error": (C.c_int, [P]),
+    "rc_scene_create": (C.c_int, [P, C.POINTER(RcSceneDesc), PP]),
+    "rc_scene_destroy": (C.c_int, [P, P]),
+    "rc_bvh_build": (C.c_int, [P, P, C.POINTER(RcBuildOpts)]),
+    "rc_scene_set_transforms": (C.c_int, [P, P, P, P, C.c_uint32]),
+    "rc_bvh_refit": (C.c_int, [P, P]),
+    "rc_bvh_get_stats": (C.c_int, [P, P, C.POINTER(RcBvhStats)]),
+    "rc_bvh_export": (C.c_int, [P, P, P, P]),
+    "rc_render": (C.c_int, [P, P, C.POINTER(RcCamera), C.POINTER(RcPointLight), C.c_uint32,
+                            C.POINTER(RcRectLight), C.POINTER(RcRenderOpts), C.POINTER(RcOutputs)]),
+    "rc_get_stage_times": (C.c_int, [P, C.POINTER(RcStageTimes)]),
+    "rc_camera_rays": (C.c_int, [P, C.POINTER(RcCamera), P, P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libraycast.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first (paper_2410_05095_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().rc_status_string(int(status)).decode()
+
+
+def check(status: int, where: str):
+    if status != 0:
+        raise RcError(status, where)
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def camera_struct(cam) -> RcCamera:
+    c = RcCamera()
+    c.eye[:] = [float(x) for x in cam.eye]
+    c.target[:] = [float(x) for x in cam.target]
+    c.up[:] = [float(x) for x in cam.up]
+    c.vfov_deg = float(cam.vfov_deg)
+    c.width, c.height, c.ssaa = int(cam.width), int(cam.height), int(cam.ssaa)
+    c.seed, c.frame = int(cam.seed), int(cam.frame)
+    return c
+
+
+def rect_struct(rect) -> RcRectLight:
+    r = RcRectLight()
+    r.center[:] = [float(x) for x in rect.center]
+    r.edge_u[:] = [float(x) for x in rect.edge_u]
+    r.edge_v[:] = [float(x) for x in rect.edge_v]
+    r.radiance[:] = [float(x) for x in rect.radiance]
+    return r
+
+
+def light_array(lights) -> Optional[C.Array]:
+    L = np.asarray(lights, np.float32).reshape(-1, 6)
+    if len(L) == 0:
+        return None
+    arr = (RcPointLight * len(L))()
+    for i, row in enumerate(L):
+        arr[i].position[:] = [float(x) for x in row[:3]]
+        arr[i].intensity[:] = [float(x) for x in row[3:]]
+    return arr
+
+
+class Context:
+    """A library context bound to a device and to torch's current stream at each call."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible to torch: the HIP rendering path needs an MI355X (gfx950)")
+        self.device = device
+        torch.cuda.set_device(device)
+        h = C.c_void_p()
+        check(lib().rc_create(C.byref(h), device, C.c_void_p(torch.cuda.current_stream(device).cuda_stream)),
+              "rc_create")
+        self.h = h
+
+    def _sync_stream(self):
+        st = self.torch.cuda.current_stream(self.device).cuda_stream
+        check(lib().rc_set_stream(self.h, C.c_void_p(st)), "rc_set_stream")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> int:
+        return int(lib().rc_get_last_error(self.h))
+
+    def scene(self, positions, indices, tri_material, materials, body_vertex_range=None) -> "Scene":
+        return Scene(self, positions, indices, tri_material, materials, body_vertex_range)
+
+    def scene_from(self, sc) -> "Scene":
+        return Scene(self, sc.positions, sc.indices, sc.tri_material, sc.materials, sc.body_vertex_range)
+
+    def render(self, scene: "Scene", cam, lights=(), rect=None, area_samples: int = 0, area_stream: int = 0,
+               timing: bool = False, sample_rgba: bool = False, out: Optional[dict] = None) -> dict:
+        torch = self.torch
+        self._sync_stream()
+        W, H, S = int(cam.width), int(cam.height), int(cam.ssaa) ** 2
+        Larr = light_array(lights)
+        nl = 0 if Larr is None else len(Larr)
+        dev = torch.device("cuda", self.device)
+        if out is None:
+            out = {}
+        def get(name, shape, dtype):
+            t = out.get(name)
+            if t is None or tuple(t.shape) != shape or t.dtype != dtype:
+                t = torch.empty(shape, dtype=dtype, device=dev)
+                out[name] = t
+            return t
+        rgba = get("rgba", (H, W, 4), torch.float32)
+        hit = get("hit", (H * W * S, 4), torch.int32)
+        shadow = get("shadow", (H * W * S,), torch.int32) if nl else None
+        vis = get("visibility", (H, W), torch.float32) if rect is not None else None
+        srgba = get("sample_rgba", (H * W * S, 4), torch.float32) if sample_rgba else None
+        o = RcOutputs(_dptr(rgba), _dptr(hit), _dptr(shadow), _dptr(vis), _dptr(srgba))
+        opts = RcRenderOpts(int(area_samples), int(area_stream), RC_FLAG_TIMING if timing else 0)
+        camc = camera_struct(cam)
+        rc = rect_struct(rect) if rect is not None else None
+        check(lib().rc_render(self.h, scene.h, C.byref(camc), Larr, nl, C.byref(rc) if rc is not None else None,
+                              C.byref(opts), C.byref(o)), "rc_render")
+        return out
+
+    def camera_rays(self, cam):
+        torch = self.torch
+        self._sync_stream()
+        n = int(cam.width) * int(cam.height) * int(cam.ssaa) ** 2
+        o = torch.empty((n, 3), dtype=torch.float32, device=torch.device("cuda", self.device))
+        d = torch.empty_like(o)
+        camc = camera_struct(cam)
+        check(lib().rc_camera_rays(self.h, C.byref(camc), C.c_void_p(o.data_ptr()), C.c_void_p(d.data_ptr())),
+              "rc_camera_rays")
+        return o, d
+
+    def stage_times(self) -> dict:
+        t = RcStageTimes()
+        check(lib().rc_get_stage_times(self.h, C.byref(t)), "rc_get_stage_times")
+        return {"primary_ms": t.ms[0], "shadow_ms": t.ms[1], "shade_ms": t.ms[2], "total_ms": t.ms[3],
+                "primary_rays": int(t.rays[0]), "shadow_rays": int(t.rays[1])}
+
+
+class Scene:
+    def __init__(self, ctx: Context, positions, indices, tri_material, materials, body_vertex_range=None):
+        self.ctx = ctx
+        self.pos = np.ascontiguousarray(positions, np.float32)
+        self.idx = np.ascontiguousarray(indices, np.uint32)
+        self.tm = np.ascontiguousarray(tri_material, np.uint32)
+        self.mats = np.ascontiguousarray(materials, np.float32)
+        self.bvr = None if body_vertex_range is None else np.ascontiguousarray(body_vertex_range, np.uint32)
+        nb = 0 if self.bvr is None else self.bvr.shape[0]
+        d = RcSceneDesc(_ptr(self.pos), self.pos.shape[0], _ptr(self.idx), self.idx.shape[0], _ptr(self.tm),
+                        _ptr(self.mats), self.mats.shape[0], None if nb == 0 else _ptr(self.bvr), nb)
+        ctx._sync_stream()
+        h = C.c_void_p()
+        check(lib().rc_scene_create(ctx.h, C.byref(d), C.byref(h)), "rc_scene_create")
+        self.h = h
+        self.n_tris = self.idx.shape[0]
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            lib().rc_scene_destroy(self.ctx.h, self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, bins: int = 32, max_leaf: int = 4):
+        self.ctx._sync_stream()
+        check(lib().rc_bvh_build(self.ctx.h, self.h, C.byref(RcBuildOpts(bins, max_leaf))), "rc_bvh_build")
+        return self
+
+    def refit(self):
+        self.ctx._sync_stream()
+        check(lib().rc_bvh_refit(self.ctx.h, self.h), "rc_bvh_refit")
+
+    def set_transforms(self, d_xforms, d_body_ids):
+        """d_xforms: (n, 12) float32 device tensor, d_body_ids: (n,) int32/uint32 device tensor."""
+        assert d_xforms.is_contiguous() and d_body_ids.is_contiguous()
+        self.ctx._sync_stream()
+        check(lib().rc_scene_set_transforms(self.ctx.h, self.h, C.c_void_p(d_xforms.data_ptr()),
+                                            C.c_void_p(d_body_ids.data_ptr()), int(d_body_ids.numel())),
+              "rc_scene_set_transforms")
+
+    def stats(self) -> dict:
+        s = RcBvhStats()
+        check(lib().rc_bvh_get_stats(self.ctx.h, self.h, C.byref(s)), "rc_bvh_get_stats")
+        return {k: getattr(s, k) for k, _ in RcBvhStats._fields_}
+
+    def export(self):
+        st = self.stats()
+        nodes = np.zeros((int(st["n_nodes"]), 32), np.uint32)
+        order = np.zeros(self.n_tris, np.uint32)
+        check(lib().rc_bvh_export(self.ctx.h, self.h, _ptr(nodes), _ptr(order)), "rc_bvh_export")
+        return nodes, order

@@ -1,0 +1,208 @@
+// Shading + supersampling resolve, triangle packing, rigid-body transforms and BVH refit.
+#include "rc_device.h"
+
+namespace {
+
+// One thread per pixel: every sample is shaded in FP64 from the FP32 hit (the hit point is
+// reconstructed from the camera ray and the triangle), rounded to FP32, and the samples are
+// box-averaged in the fixed order ((s0 + s1) + (s2 + s3)) * 0.25.
+__global__ __launch_bounds__(256) void k_shade(DevScene sc, DevCamera cam, DevLights L, const uint4* gbuf,
+                                               const uint32_t* mask, const float* vis, float* rgba,
+                                               float* sample_rgba)
+{
+    const uint32_t n_pix = (uint32_t)cam.width * (uint32_t)cam.height;
+    const uint32_t pixel = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pixel >= n_pix) return;
+    const uint32_t spp = (uint32_t)(cam.ssaa * cam.ssaa);
+    float4 smp[4];
+    for (uint32_t k = 0; k < spp; ++k) {
+        size_t s = (size_t)pixel * spp + k;
+        uint4 h = gbuf[s];
+        float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (h.x != RC_NO_HIT) {
+            Surface S = rc_surface(sc, cam, pixel, k, h.x);
+            const float* mat = sc.mats + 5 * (size_t)sc.tri_mat[h.x];
+            double rgb[3] = {0.0, 0.0, 0.0};
+            uint32_t m = mask ? mask[s] : 0u;
+            for (int l = 0; l < L.n_point; ++l) {
+                if (!((m >> l) & 1u)) continue;
+                D3 lp = d3(L.point[l][0], L.point[l][1], L.point[l][2]);
+                D3 tl = d3sub(lp, S.p);
+                double d2 = d3dot(tl, tl);
+                D3 wi = d3nrm(tl);
+                double f[3];
+                rc_brdf(S.n, S.wo, wi, mat, f);
+                double cosi = fmax(d3dot(S.n, wi), 0.0);
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) rgb[ch] += f[ch] * (double)L.point[l][3 + ch] * cosi / d2;
+            }
+            if (L.has_rect) {
+                D3 C = d3(L.rect[0], L.rect[1], L.rect[2]);
+                D3 eu = d3(L.rect[3], L.rect[4], L.rect[5]), ev = d3(L.rect[6], L.rect[7], L.rect[8]);
+                D3 nraw = d3cross(eu, ev);
+                double area = sqrt(d3dot(nraw, nraw));
+                D3 nL = d3nrm(nraw);
+                D3 tl = d3sub(C, S.p);
+                double d2 = d3dot(tl, tl);
+                D3 wi = d3nrm(tl);
+                double cosl = fmax(-d3dot(nL, wi), 0.0);
+                double cosi = fmax(d3dot(S.n, wi), 0.0);
+                double f[3];
+                rc_brdf(S.n, S.wo, wi, mat, f);
+                double V = (double)vis[pixel];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch)
+                    rgb[ch] += f[ch] * (double)L.rect[9 + ch] * area * cosl * cosi / d2 * V;
+            }
+            out = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], 1.0f);
+        }
+        smp[k] = out;
+        if (sample_rgba) reinterpret_cast<float4*>(sample_rgba)[s] = out;
+    }
+    float4 r;
+    if (spp == 4) {
+        float4 a, b;
+        a.x = smp[0].x + smp[1].x; a.y = smp[0].y + smp[1].y; a.z = smp[0].z + smp[1].z; a.w = smp[0].w + smp[1].w;
+        b.x = smp[2].x + smp[3].x; b.y = smp[2].y + smp[3].y; b.z = smp[2].z + smp[3].z; b.w = smp[2].w + smp[3].w;
+        r.x = (a.x + b.x) * 0.25f; r.y = (a.y + b.y) * 0.25f; r.z = (a.z + b.z) * 0.25f; r.w = (a.w + b.w) * 0.25f;
+    } else {
+        r = smp[0];
+    }
+    reinterpret_cast<float4*>(rgba)[pixel] = r;
+}
+
+// slot i of the leaf order: (v0, id), (v1 - v0, 0), (v2 - v0, 0)
+__global__ __launch_bounds__(256) void k_pack(const float* pos, const uint32_t* idx, const uint32_t* order,
+                                              uint32_t n, float4* tris)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t t = order[i];
+    const uint32_t* ix = idx + 3 * (size_t)t;
+    const float* a = pos + 3 * (size_t)ix[0];
+    const float* b = pos + 3 * (size_t)ix[1];
+    const float* c = pos + 3 * (size_t)ix[2];
+    tris[3 * (size_t)i + 0] = make_float4(a[0], a[1], a[2], __uint_as_float(t));
+    tris[3 * (size_t)i + 1] = make_float4(b[0] - a[0], b[1] - a[1], b[2] - a[2], 0.0f);
+    tris[3 * (size_t)i + 2] = make_float4(c[0] - a[0], c[1] - a[1], c[2] - a[2], 0.0f);
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, uint32_t n)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+// x' = ((R00 x + R01 y) + R02 z) + t0 per row, from the rest positions of body body_ids[blockIdx.y]
+__global__ __launch_bounds__(256) void k_transform(const float* rest, float* pos, const uint32_t* body_vrange,
+                                                   const float* xf, const uint32_t* body_ids)
+{
+    uint32_t b = blockIdx.y;
+    uint32_t body = body_ids[b];
+    uint32_t first = body_vrange[2 * (size_t)body], count = body_vrange[2 * (size_t)body + 1];
+    const float* M = xf + 12 * (size_t)b;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const float* p = rest + 3 * (size_t)(first + i);
+        float x = p[0], y = p[1], z = p[2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            float a = M[4 * r + 0] * x;
+            float bb = M[4 * r + 1] * y;
+            float cc = M[4 * r + 2] * z;
+            pos[3 * (size_t)(first + i) + r] = ((a + bb) + cc) + M[4 * r + 3];
+        }
+    }
+}
+
+// One thread per node of one BVH level: child boxes from the triangles of leaf children and
+// from the (already refit) boxes of internal children.  Exact FP32 min/max.
+__global__ __launch_bounds__(256) void k_refit(Node4* nodes, const float* pos, const uint32_t* idx,
+                                               const uint32_t* order, uint32_t first, uint32_t count)
+{
+    uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    Node4* n = nodes + first + q;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        uint32_t w = n->child[c];
+        if (w == RC_EMPTY_CHILD) continue;
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (rc_is_leaf(w)) {
+            uint32_t f = rc_leaf_first(w), cnt = rc_leaf_count(w);
+            for (uint32_t i = 0; i < cnt; ++i) {
+                const uint32_t* ix = idx + 3 * (size_t)order[f + i];
+                for (int v = 0; v < 3; ++v) {
+                    const float* p = pos + 3 * (size_t)ix[v];
+                    for (int a = 0; a < 3; ++a) { lo[a] = fminf(lo[a], p[a]); hi[a] = fmaxf(hi[a], p[a]); }
+                }
+            }
+        } else {
+            const Node4* ch = nodes + w;
+            for (int k = 0; k < 4; ++k) {
+                lo[0] = fminf(lo[0], ch->lo_x[k]); hi[0] = fmaxf(hi[0], ch->hi_x[k]);
+                lo[1] = fminf(lo[1], ch->lo_y[k]); hi[1] = fmaxf(hi[1], ch->hi_y[k]);
+                lo[2] = fminf(lo[2], ch->lo_z[k]); hi[2] = fmaxf(hi[2], ch->hi_z[k]);
+            }
+        }
+        n->lo_x[c] = lo[0]; n->hi_x[c] = hi[0];
+        n->lo_y[c] = lo[1]; n->hi_y[c] = hi[1];
+        n->lo_z[c] = lo[2]; n->hi_z[c] = hi[2];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_camera_rays(DevCamera cam, float* o, float* d, uint32_t n)
+{
+    uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    uint32_t spp = (uint32_t)(cam.ssaa * cam.ssaa);
+    float of[3], df[3];
+    rc_camera_ray(cam, s / spp, s % spp, of, df);
+    for (int a = 0; a < 3; ++a) { o[3 * (size_t)s + a] = of[a]; d[3 * (size_t)s + a] = df[a]; }
+}
+
+inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void rc_launch_shade(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
+                     const uint32_t* mask, const float* visibility, float* rgba, float* sample_rgba,
+                     hipStream_t st)
+{
+    size_t n = (size_t)cam.width * cam.height;
+    hipLaunchKernelGGL(k_shade, dim3(blocks(n, 256)), dim3(256), 0, st, sc, cam, L, gbuf, mask, visibility, rgba,
+                       sample_rgba);
+}
+
+void rc_launch_camera_rays(const DevCamera& cam, float* o, float* d, uint32_t n, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_camera_rays, dim3(blocks(n, 256)), dim3(256), 0, st, cam, o, d, n);
+}
+
+void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris, float4* tris,
+                    hipStream_t st)
+{
+    if (n_tris == 0) return;
+    hipLaunchKernelGGL(k_pack, dim3(blocks(n_tris, 256)), dim3(256), 0, st, pos, idx, order, n_tris, tris);
+}
+
+void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks(n, 256)), dim3(256), 0, st, p, value, n);
+}
+
+void rc_launch_transform(const float* rest, float* pos, const uint32_t* body_vrange, const float* xf,
+                         const uint32_t* body_ids, uint32_t n_bodies, uint32_t max_count, hipStream_t st)
+{
+    if (n_bodies == 0 || max_count == 0) return;
+    unsigned gx = std::min(blocks(max_count, 256), 64u);
+    hipLaunchKernelGGL(k_transform, dim3(gx, n_bodies), dim3(256), 0, st, rest, pos, body_vrange, xf, body_ids);
+}
+
+void rc_launch_refit_level(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order,
+                           uint32_t first, uint32_t count, hipStream_t st)
+{
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_refit, dim3(blocks(count, 256)), dim3(256), 0, st, nodes, pos, idx, order, first, count);
+}

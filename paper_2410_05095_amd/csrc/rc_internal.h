@@ -1,0 +1,109 @@
+// Internal types shared by the host runtime and the HIP kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#define RC_NO_HIT 0xFFFFFFFFu
+#define RC_EMPTY_CHILD 0xFFFFFFFFu
+#define RC_LEAF_BIT 0x80000000u
+
+// 4-wide BVH node: the four child boxes in structure-of-arrays form followed by the
+// child words and bookkeeping, 128 bytes = one cache line of the CDNA L2.
+struct alignas(128) Node4 {
+    float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4];
+    uint32_t child[4];   // internal index | (RC_LEAF_BIT | (count-1) << 28 | first) | RC_EMPTY_CHILD
+    uint32_t parent;     // parent node index (0xFFFFFFFF for the root)
+    uint32_t level;      // depth of this node (root = 0)
+    uint32_t pad[2];
+};
+static_assert(sizeof(Node4) == 128, "node must be one 128-byte line");
+
+__host__ __device__ inline bool rc_is_leaf(uint32_t c) { return (c & RC_LEAF_BIT) != 0u && c != RC_EMPTY_CHILD; }
+__host__ __device__ inline uint32_t rc_leaf_first(uint32_t c) { return c & 0x0FFFFFFFu; }
+__host__ __device__ inline uint32_t rc_leaf_count(uint32_t c) { return ((c >> 28) & 7u) + 1u; }
+__host__ __device__ inline uint32_t rc_make_leaf(uint32_t first, uint32_t count)
+{
+    return RC_LEAF_BIT | ((count - 1u) << 28) | first;
+}
+
+// Packed triangle in leaf order: three float4 = 48 bytes,
+// (v0.xyz, original id as bits), (e1.xyz, 0), (e2.xyz, 0) with e1 = v1 - v0, e2 = v2 - v0 in FP32.
+
+struct DevScene {
+    const float* pos;         // n_vertices x 3 (current positions)
+    const uint32_t* idx;      // n_tris x 3
+    const uint32_t* tri_mat;  // n_tris
+    const float* mats;        // n_materials x 5
+    const Node4* nodes;
+    const float4* tris;       // 3 per slot
+    uint32_t n_tris, n_nodes;
+    uint32_t max_stack;
+    float scale;              // max |coordinate| of the scene (for diagnostics)
+};
+
+struct DevCamera {
+    float eye[3], f[3], r[3], u[3];
+    float tan_half, x_scale;
+    int32_t width, height, ssaa;
+    uint32_t seed, frame;
+};
+
+struct DevLights {
+    int n_point;
+    float point[16][6];       // position, intensity
+    int has_rect;
+    float rect[12];           // center, edge_u, edge_v, radiance
+    int area_samples;
+    uint32_t area_stream;
+};
+
+// Host-built BVH (binned SAH, collapsed to 4-wide, nodes in breadth-first order).
+struct HostBvh {
+    std::vector<Node4> nodes;
+    std::vector<uint32_t> tri_order;     // slot -> original triangle id
+    std::vector<uint32_t> level_start;   // node index where each level starts (size depth+1)
+    uint32_t depth = 0;
+    uint32_t max_stack = 0;
+    uint64_t n_leaves = 0;
+    double sah_cost = 0.0;
+};
+
+bool rc_build_bvh_host(const float* pos, const uint32_t* idx, uint32_t n_tris,
+                       uint32_t bins, uint32_t max_leaf, HostBvh& out);
+double rc_bvh_sah(const std::vector<Node4>& nodes);
+
+// Traversal launch geometry
+#define RC_TRACE_BLOCK 128
+#define RC_STACK_LDS 24
+
+struct TraceWork {
+    uint32_t* counters;       // device work-queue counters
+    uint32_t* overflow;       // per-lane overflow stack (lane-interleaved), entries of 2 words
+    uint32_t overflow_depth;  // entries per lane beyond the LDS part
+    uint32_t n_lanes;         // lanes of the persistent grid
+    uint32_t* error_flag;     // set on stack overflow
+    unsigned long long* ray_count; // optional ray counter (NULL = not counted)
+};
+
+// Launchers (k_trace.hip)
+void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, const TraceWork& w,
+                       int grid, hipStream_t st);
+void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
+                      uint32_t* mask, float* visibility, const TraceWork& w, int grid, hipStream_t st);
+int rc_trace_grid(int device);
+
+// Launchers (k_shade.hip)
+void rc_launch_shade(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
+                     const uint32_t* mask, const float* visibility, float* rgba, float* sample_rgba,
+                     hipStream_t st);
+void rc_launch_camera_rays(const DevCamera& cam, float* o, float* d, uint32_t n, hipStream_t st);
+void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris,
+                    float4* tris, hipStream_t st);
+void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st);
+void rc_launch_transform(const float* rest, float* pos, const uint32_t* body_vrange, const float* xf,
+                         const uint32_t* body_ids, uint32_t n_bodies, uint32_t max_count, hipStream_t st);
+void rc_launch_refit_level(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order,
+                           uint32_t first, uint32_t count, hipStream_t st);

@@ -1,0 +1,158 @@
+"""GPU parity of the rendering path (through the C ABI) against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2410_05095_amd import scenegen as sg
+from tests.parity import NO_HIT, assert_clean, compare_point, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_05095_amd import _native as N
+    c = N.Context(0)
+    yield c
+    c.close()
+
+
+def render_and_compare(ctx, O, scene, cam, rtol=1e-4, sample_idx=None, brute=False):
+    import torch
+    say(f"[render] {scene.name} {cam.width}x{cam.height} ssaa={cam.ssaa} tris={scene.n_tris}")
+    gs = ctx.scene_from(scene).build()
+    out = ctx.render(gs, cam, scene.point_lights, sample_rgba=True)
+    torch.cuda.synchronize()
+    assert ctx.last_error() == 0
+    n = cam.n_samples
+    smp = np.arange(n) if sample_idx is None else np.asarray(sample_idx)
+    osc = O.OracleScene.from_scene(scene, use_bvh=not brute)
+    orc = osc.render_point(cam, scene.point_lights, smp, brute=brute)
+    hit = to_np(out["hit"])[smp]
+    mask = to_np(out["shadow"])[smp] if len(scene.point_lights) else None
+    srgba = to_np(out["sample_rgba"])[smp]
+    st = compare_point(hit, mask, srgba, orc, len(scene.point_lights), rtol=rtol)
+    say("[parity]", st)
+    assert_clean(st)
+    # resolve: bit-exact against the fixed FP32 order applied to the GPU's own samples
+    spp = cam.ssaa ** 2
+    want = O.resolve_f32(to_np(out["sample_rgba"]).reshape(-1, spp, 4), spp)
+    got = to_np(out["rgba"]).reshape(-1, 4)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    return out, orc, st, gs
+
+
+def test_camera_rays_bit_exact(ctx, oracle_mod):
+    O = oracle_mod
+    cams = [sg.tiny_box_scene(0).cameras[0],
+            sg.Camera(eye=(0.0, 10.0, -28.0), target=(0.0, 5.0, 0.0), up=(0, 1, 0), vfov_deg=50.0,
+                      width=333, height=197, ssaa=2, seed=11, frame=3),
+            sg.Camera(eye=(1.5, -2.0, 7.25), target=(-3.0, 0.5, 1.0), up=(0.1, 1, 0.2), vfov_deg=71.5,
+                      width=64, height=1, ssaa=1)]
+    for cam in cams:
+        o, d = ctx.camera_rays(cam)
+        oo, od = O.gen_rays(cam, np.arange(cam.n_samples))
+        go, gd = to_np(o), to_np(d)
+        say(f"[rays] {cam.width}x{cam.height} ssaa={cam.ssaa}: dir mismatches "
+            f"{int((gd.view(np.uint32) != od.view(np.uint32)).any(axis=1).sum())}")
+        assert np.array_equal(go.view(np.uint32), oo.view(np.uint32))
+        assert np.array_equal(gd.view(np.uint32), od.view(np.uint32))
+
+
+def test_tiny_box_full_frame(ctx, oracle_mod):
+    scene = sg.tiny_box_scene(0)
+    out, orc, st, _ = render_and_compare(ctx, oracle_mod, scene, scene.cameras[0], brute=True)
+    assert st["clean"] > 0.95 * st["n"]
+    # the box interior: every ray hits something
+    assert (to_np(out["hit"])[:, 0].view(np.uint32) != NO_HIT).all()
+
+
+@pytest.mark.parametrize("seed,ssaa,w,h,ninst", [(0, 1, 37, 29, 8), (1, 2, 41, 23, 12), (2, 2, 67, 45, 30),
+                                                   (3, 1, 130, 71, 60)])
+def test_small_scenes_full_frame(ctx, oracle_mod, seed, ssaa, w, h, ninst):
+    scene = sg.small_random_scene(seed, n_instances=ninst, width=w, height=h, ssaa=ssaa, n_lights=1 + seed)
+    render_and_compare(ctx, oracle_mod, scene, scene.cameras[0])
+
+
+def test_city_full_size_sampled(ctx, oracle_mod):
+    """The 1.1M-triangle scene at 1920x1080 with 2x2 samples and 4 point lights: the whole frame is
+    rendered in the benchmark's configuration; 30000 samples are checked against the oracle."""
+    scene = sg.city_scene(0)
+    cam = scene.cameras[0]
+    rng = np.random.default_rng(0)
+    smp = np.sort(rng.choice(cam.n_samples, 30000, replace=False))
+    out, orc, st, gs = render_and_compare(ctx, oracle_mod, scene, cam, sample_idx=smp)
+    assert st["clean"] > 0.9 * st["n"]
+    hits = (orc["hit_id"] != NO_HIT).sum()
+    assert hits > 10000
+
+
+def test_bvh_invariants(ctx):
+    scene = sg.small_random_scene(7, n_instances=40, width=8, height=8)
+    gs = ctx.scene_from(scene).build()
+    nodes, order = gs.export()
+    st = gs.stats()
+    say("[bvh]", st)
+    assert sorted(order.tolist()) == list(range(scene.n_tris))
+    f = nodes.view(np.float32)
+    boxes = f[:, :24].reshape(-1, 6, 4)          # lo_x hi_x lo_y hi_y lo_z hi_z  x 4 children
+    child = nodes[:, 24:28]
+    pos = scene.positions
+    seen = np.zeros(scene.n_tris, int)
+    for ni in range(len(nodes)):
+        for c in range(4):
+            w = int(child[ni, c])
+            if w == 0xFFFFFFFF:
+                continue
+            lo = boxes[ni, [0, 2, 4], c]
+            hi = boxes[ni, [1, 3, 5], c]
+            if w & 0x80000000:
+                first, cnt = w & 0x0FFFFFFF, ((w >> 28) & 7) + 1
+                assert cnt <= 4
+                tris = order[first:first + cnt]
+                seen[tris] += 1
+                v = pos[scene.indices[tris].ravel()]
+                assert np.array_equal(v.min(0), lo) and np.array_equal(v.max(0), hi)
+            else:
+                cb = boxes[w]
+                valid = child[w] != 0xFFFFFFFF
+                assert np.array_equal(cb[[0, 2, 4]][:, valid].min(1), lo)
+                assert np.array_equal(cb[[1, 3, 5]][:, valid].max(1), hi)
+    assert (seen == 1).all()
+    assert st["depth"] >= 2 and st["max_stack"] == 3 * st["depth"] + 1
+
+
+def test_render_deterministic(ctx):
+    import torch
+    scene = sg.small_random_scene(4, n_instances=30, width=96, height=64, ssaa=2, n_lights=3)
+    gs = ctx.scene_from(scene).build()
+    a = ctx.render(gs, scene.cameras[0], scene.point_lights)
+    a = {k: v.clone() for k, v in a.items()}
+    b = ctx.render(gs, scene.cameras[0], scene.point_lights)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_render_error_paths(ctx):
+    from paper_2410_05095_amd import _native as N
+    scene = sg.small_random_scene(1, n_instances=3, width=8, height=8)
+    gs = ctx.scene_from(scene)
+    with pytest.raises(N.RcError) as e:
+        ctx.render(gs, scene.cameras[0], scene.point_lights)
+    assert e.value.status == -5   # not built
+    gs.build()
+    bad = sg.Camera(eye=(0, 0, 0), target=(0, 0, 1), up=(0, 1, 0), vfov_deg=50, width=8, height=8, ssaa=3)
+    with pytest.raises(N.RcError) as e:
+        ctx.render(gs, bad, scene.point_lights)
+    assert e.value.status == -8
+    with pytest.raises(N.RcError) as e:
+        ctx.scene(scene.positions * np.nan, scene.indices, scene.tri_material, scene.materials)
+    assert e.value.status == -2
+    assert ctx.last_error() == 0
