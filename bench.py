@@ -1,0 +1,166 @@
+"""Benchmark of the ray-cast rendering path on one MI355X.
+
+One step = one frame of the whole path on a synthetic scene resident in HBM: camera rays
+into the G-buffer, shadow rays, shading and resolve.  Default workload: ~7.3M triangles
+(1500 seeded procedural instances) at 1920x1080, one primary ray per pixel and 64 shadow
+rays per pixel towards a 1x1 m rectangular light (the plain soft-shadow path).
+Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload big_7M|city_1M] [--spp 64]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s + 1080p frame ms at 7.3M tris; denoised 1spp vs 64spp at equal shadow MSE"
+HBM_PEAK_GBS = 8000.0
+NODE_BYTES, TRI_BYTES = 128, 48
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene, cam, args, budget_s=12.0):
+    """The FP64 oracle as it stands, on a bounded random sample of the same frame's pixels."""
+    import numpy as np
+
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    osc = O.OracleScene.from_scene(scene)
+    build_s = time.perf_counter() - t0
+    rng = np.random.default_rng(123)
+    npix = cam.width * cam.height
+    threads = O.n_threads()
+
+    def run(n):
+        pix = np.sort(rng.choice(npix, n, replace=False))
+        t = time.perf_counter()
+        if args.workload == "big_7M":
+            r = osc.render_rect(cam, scene.rect_light, args.spp, 0, pix, threads=threads)
+            rays = n + int(r["cast_count"].sum())
+        else:
+            spp = cam.ssaa ** 2
+            smp = (pix[:, None] * spp + np.arange(spp)[None, :]).ravel()
+            r = osc.render_point(cam, scene.point_lights, smp, threads=threads)
+            rays = len(smp) + int(sum(bin(int(m)).count("1") for m in r["mask"]))  # lit shadow rays only: a lower bound
+        return rays, time.perf_counter() - t
+
+    rays, dt = run(500)
+    n = int(min(npix, max(500, 500 * budget_s / max(dt, 1e-3))))
+    rays, dt = run(n)
+    return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} random pixels of the same frame ({rays} rays, {dt:.1f} s); oracle BVH build "
+                      f"{build_s:.1f} s not included"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="big_7M", choices=["big_7M", "city_1M"])
+    ap.add_argument("--spp", type=int, default=64, help="rect-light samples per pixel (big_7M)")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="instead of rendering, copy a buffer of this many MiB 5 times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (views or tiles would be split "
+              "across GPUs with a final image gather; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_mib:
+        a = torch.ones(args.copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": a.numel() * 4, "copy_bytes_written_per_launch": b.numel() * 4,
+                          "launches": 5}), flush=True)
+        return
+
+    from paper_2410_05095_amd import _native as N
+    from paper_2410_05095_amd import scenegen as sg
+
+    t0 = time.perf_counter()
+    scene = sg.big_scene(args.seed) if args.workload == "big_7M" else sg.city_scene(args.seed)
+    cam = scene.cameras[0]
+    log(f"[bench] scene {scene.name}: {scene.n_tris} tris, generated in {time.perf_counter() - t0:.1f} s")
+    ctx = N.Context(0)
+    gs = ctx.scene_from(scene).build()
+    bst = gs.stats()
+    log(f"[bench] BVH: {bst}")
+
+    if args.workload == "big_7M":
+        kw = dict(lights=(), rect=scene.rect_light, area_samples=args.spp, area_stream=0)
+    else:
+        kw = dict(lights=scene.point_lights)
+    out = {}
+    for i in range(args.warmup):
+        ctx.render(gs, cam, out=out, timing=True, **kw)
+    torch.cuda.synchronize()
+    assert ctx.last_error() == 0
+    log(f"[bench] warmup done")
+
+    stages = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.render(gs, cam, out=out, timing=True, **kw)
+        stages.append(ctx.stage_times())   # synchronises the stream after each frame
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert ctx.last_error() == 0
+    ms_step = wall * 1000.0 / args.steps
+    st = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    rays = st["primary_rays"] + st["shadow_rays"]
+    value = rays / (ms_step / 1000.0) / 1e6
+    # roofline of the dominant kernel (shadow traversal): algorithmic bytes = BVH nodes visited x 128 B
+    # + triangles tested x 48 B + per shaded point a 16 B G-buffer read and a 4 B result write
+    npix = cam.width * cam.height * cam.ssaa ** 2
+    dom_ms = st["shadow_ms"]
+    dom_bytes = st["shadow_nodes"] * NODE_BYTES + st["shadow_tris"] * TRI_BYTES + npix * 20
+    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"{scene.name}: {scene.n_tris} FP32 triangles, {cam.width}x{cam.height}, "
+                                + (f"1 primary ray/pixel, rect light {args.spp} shadow rays/pixel"
+                                   if args.workload == "big_7M" else
+                                   f"{cam.ssaa ** 2} samples/pixel, {len(scene.point_lights)} point lights")),
+                   "tris": scene.n_tris, "width": cam.width, "height": cam.height},
+        "frame_ms": round(ms_step, 4),
+        "stages_ms": {"primary": round(st["primary_ms"], 4), "shadow": round(st["shadow_ms"], 4),
+                      "shade_resolve": round(st["shade_ms"], 4), "render_device": round(st["total_ms"], 4)},
+        "rays_per_frame": {"primary": int(st["primary_rays"]), "shadow": int(st["shadow_rays"])},
+        "mrays_per_s_kernel": {"primary": round(st["primary_rays"] / st["primary_ms"] / 1e3, 1),
+                               "shadow": round(st["shadow_rays"] / st["shadow_ms"] / 1e3, 1)},
+        "per_ray": {"primary_nodes": round(st["primary_nodes"] / max(st["primary_rays"], 1), 2),
+                    "primary_tris": round(st["primary_tris"] / max(st["primary_rays"], 1), 2),
+                    "shadow_nodes": round(st["shadow_nodes"] / max(st["shadow_rays"], 1), 2),
+                    "shadow_tris": round(st["shadow_tris"] / max(st["shadow_rays"], 1), 2)},
+        "bvh": {"build_ms": round(bst["build_ms"], 1), "nodes": int(bst["n_nodes"]), "depth": int(bst["depth"]),
+                "sah": round(bst["sah_cost"], 2)},
+        "roofline": {"kernel": "k_trace<shadow>", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host")
+        res["cpu_baseline"] = cpu_baseline(scene, cam, args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

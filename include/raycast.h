@@ -202,11 +202,13 @@ int rc_camera_rays(rc_ctx* ctx, const rc_camera* cam, float* d_origins, float* d
 
 /* Device milliseconds of the stages of the last rc_render made with RC_FLAG_TIMING:
  * ms[0] primary traversal, ms[1] shadow traversal, ms[2] shade + resolve, ms[3] whole
- * render; rays[0] primary rays cast, rays[1] shadow rays cast (only when counted: the
- * count adds one atomic per wave).  Synchronises the stream. */
+ * render.  Counts of the last rc_render (with or without timing), [0] primary and [1] shadow
+ * traversal: rays cast, 4-wide nodes visited, triangles tested.  Synchronises the stream. */
 typedef struct rc_stage_times {
     float ms[8];
     uint64_t rays[2];
+    uint64_t node_visits[2];
+    uint64_t tri_tests[2];
 } rc_stage_times;
 int rc_get_stage_times(rc_ctx* ctx, rc_stage_times* out);
 

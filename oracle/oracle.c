@@ -777,7 +777,7 @@ static void rect_setup(const float* rect, rect_geo* R)
 /* N light samples at one surface point; returns the visible count, adds band samples to *band_count */
 static int rect_visibility(const or_scene* s, const or_bvh* B, const surface* S, const rect_geo* R,
                            uint32_t pixel, int N, uint32_t stream, uint32_t seed, uint32_t frame, double c,
-                           int* band_count)
+                           int* band_count, int* cast_count)
 {
     int vis = 0;
     for (int k = 0; k < N; ++k) {
@@ -794,6 +794,7 @@ static int rect_visibility(const or_scene* s, const or_bvh* B, const surface* S,
         int faces = facing.v < 0.0;
         if (fabs(facing.v) <= c * facing.e) band = 1;
         if (band) (*band_count)++;
+        if (cast && cast_count) (*cast_count)++;
         if (cast && faces && !occ) vis++;
     }
     return vis;
@@ -814,14 +815,14 @@ OR_API int or_rect_vis_point(const or_scene* s, const or_bvh* B, const double p[
     rect_geo R;
     rect_setup(rect, &R);
     *band_count = 0;
-    return rect_visibility(s, B, &S, &R, pixel, N, stream, seed, frame, c, band_count);
+    return rect_visibility(s, B, &S, &R, pixel, N, stream, seed, frame, c, band_count, NULL);
 }
 
 OR_API void or_render_rect(const or_scene* s, const or_bvh* B, const or_camera* cam,
                            const float* rect, int n_light_samples, uint32_t stream, double c,
                            const int64_t* pixels, int64_t n,
                            uint32_t* hit_id, uint8_t* band_primary,
-                           int32_t* vis_count, int32_t* band_count, double* rgb_unshadowed)
+                           int32_t* vis_count, int32_t* band_count, int32_t* cast_count, double* rgb_unshadowed)
 {
     cam_basis cb;
     camera_basis(cam, &cb);
@@ -837,15 +838,16 @@ OR_API void or_render_rect(const or_scene* s, const or_bvh* B, const or_camera* 
         else closest_brute(s, &r, 0.0, INFINITY, c, &h);
         hit_id[q] = h.id;
         band_primary[q] = (uint8_t)h.band;
-        vis_count[q] = 0; band_count[q] = 0;
+        vis_count[q] = 0; band_count[q] = 0; cast_count[q] = 0;
         rgb_unshadowed[3 * q] = rgb_unshadowed[3 * q + 1] = rgb_unshadowed[3 * q + 2] = 0.0;
         if (h.id == NO_HIT) continue;
         surface S;
         make_surface(s, h.id, h.u, h.v, r.d, &S);
-        int bc = 0;
+        int bc = 0, cc = 0;
         vis_count[q] = rect_visibility(s, B, &S, &R, (uint32_t)pix, n_light_samples, stream,
-                                       cam->seed, cam->frame, c, &bc);
+                                       cam->seed, cam->frame, c, &bc, &cc);
         band_count[q] = bc;
+        cast_count[q] = cc;
         /* unshadowed centre-point radiance: the light seen as a point source of intensity L_e A cos_L */
         const float* mat = s->mats + 5 * (int64_t)s->tri_mat[h.id];
         v3 tl = sub(R.C, S.p);

@@ -64,7 +64,7 @@ def _declare(L):
     L.or_render_point.argtypes = [P, P, P, P, C.c_int, C.c_double, P, C.c_int64,
                                   P, P, P, P, P, P, P]
     L.or_render_rect.argtypes = [P, P, P, P, C.c_int, C.c_uint32, C.c_double, P, C.c_int64,
-                                 P, P, P, P, P]
+                                 P, P, P, P, P, P]
     L.or_resolve_f32.argtypes = [P, C.c_int64, C.c_int, P]
     L.or_transform_f32.argtypes = [P, P, P, P, C.c_int64, P]
     L.or_ggx_D.argtypes = [P, P, C.c_double]
@@ -217,7 +217,7 @@ class OracleScene:
         R = rect_array(rect)
         out = dict(hit_id=np.zeros(n, np.uint32), band_primary=np.zeros(n, np.uint8),
                    vis_count=np.zeros(n, np.int32), band_count=np.zeros(n, np.int32),
-                   rgb_unshadowed=np.zeros((n, 3)))
+                   cast_count=np.zeros(n, np.int32), rgb_unshadowed=np.zeros((n, 3)))
         cs = camera_struct(cam)
         bvh = None if brute else self.bvh
 
@@ -227,7 +227,7 @@ class OracleScene:
             lib().or_render_rect(C.byref(self.s), bvh, C.byref(cs), _p(R), int(n_light_samples), int(stream), c,
                                  _p(pixels[a:b]), b - a, _p(out["hit_id"][a:b]), _p(out["band_primary"][a:b]),
                                  _p(out["vis_count"][a:b]), _p(out["band_count"][a:b]),
-                                 _p(out["rgb_unshadowed"][a:b]))
+                                 _p(out["cast_count"][a:b]), _p(out["rgb_unshadowed"][a:b]))
 
         _parallel(run, n, threads)
         return out

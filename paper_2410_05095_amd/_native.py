@@ -67,7 +67,8 @@ class RcOutputs(C.Structure):
 
 
 class RcStageTimes(C.Structure):
-    _fields_ = [("ms", C.c_float * 8), ("rays", C.c_uint64 * 2)]
+    _fields_ = [("ms", C.c_float * 8), ("rays", C.c_uint64 * 2), ("node_visits", C.c_uint64 * 2),
+                ("tri_tests", C.c_uint64 * 2)]
 
 
 P = C.c_void_p
@@ -244,7 +245,9 @@ class Context:
         t = RcStageTimes()
         check(lib().rc_get_stage_times(self.h, C.byref(t)), "rc_get_stage_times")
         return {"primary_ms": t.ms[0], "shadow_ms": t.ms[1], "shade_ms": t.ms[2], "total_ms": t.ms[3],
-                "primary_rays": int(t.rays[0]), "shadow_rays": int(t.rays[1])}
+                "primary_rays": int(t.rays[0]), "shadow_rays": int(t.rays[1]),
+                "primary_nodes": int(t.node_visits[0]), "shadow_nodes": int(t.node_visits[1]),
+                "primary_tris": int(t.tri_tests[0]), "shadow_tris": int(t.tri_tests[1])}
 
 
 class Scene:

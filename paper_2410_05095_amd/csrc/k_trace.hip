@@ -63,7 +63,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
     uint32_t best_id = RC_NO_HIT;
     float best_t = INFINITY, best_u = 0.f, best_v = 0.f;
     bool queue_empty = false;
-    uint32_t rays_cast = 0;
+    uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
 
     auto set_dir = [&]() {
 #pragma unroll
@@ -210,6 +210,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
             if (state == 1) {
                 bool ended = false, occluded = false;
                 if (!rc_is_leaf(cur)) {
+                    ++node_visits;
                     const float4* np = reinterpret_cast<const float4*>(sc.nodes + cur);
                     float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
                     uint4 ch = reinterpret_cast<const uint4*>(np)[6];
@@ -259,6 +260,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
                 } else {
                     uint32_t first = rc_leaf_first(cur), cnt = rc_leaf_count(cur);
                     for (uint32_t i = 0; i < cnt; ++i) {
+                        ++tri_tests;
                         const float4* tp = sc.tris + 3 * (size_t)(first + i);
                         float4 A = tp[0], B = tp[1], C = tp[2];
                         // Moller-Trumbore
@@ -305,9 +307,13 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
     }
 
     if (P.w.ray_count) {
-        uint32_t total = rays_cast;
-        for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off);
-        if (lane == 0) atomicAdd(P.w.ray_count, (unsigned long long)total);
+        unsigned long long cnt[3] = {rays_cast, node_visits, tri_tests};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            unsigned long long v = cnt[q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) atomicAdd(P.w.ray_count + 2 * q, v);
+        }
     }
 }
 

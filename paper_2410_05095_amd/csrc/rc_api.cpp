@@ -186,11 +186,11 @@ int rc_create(rc_ctx** out, int device, void* hip_stream)
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->grid = rc_trace_grid(device);
     int st = dev_alloc(&c->d_counters, 16);
-    if (st == RC_OK) st = dev_alloc(&c->d_rays, 4);
+    if (st == RC_OK) st = dev_alloc(&c->d_rays, 8);
     for (int i = 0; i < 4 && st == RC_OK; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) st = RC_ERR_HIP;
     if (st == RC_OK && hipMemset(c->d_counters, 0, 16 * sizeof(uint32_t)) != hipSuccess) st = RC_ERR_HIP;
-    if (st == RC_OK && hipMemset(c->d_rays, 0, 4 * sizeof(unsigned long long)) != hipSuccess) st = RC_ERR_HIP;
+    if (st == RC_OK && hipMemset(c->d_rays, 0, 8 * sizeof(unsigned long long)) != hipSuccess) st = RC_ERR_HIP;
     if (st != RC_OK) { rc_destroy(c); return st; }
     *out = c;
     return RC_OK;
@@ -450,7 +450,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
 
     hipStream_t q = c->stream;
     rc_launch_fill_u32(c->d_counters, 0u, 8, q);
-    rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 8, q);
+    rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, q);
     uint4* gbuf = reinterpret_cast<uint4*>(out->d_hit);
     if (timing) RC_HIP(hipEventRecord(c->ev[0], q));
     w.ray_count = c->d_rays + 0;
@@ -485,17 +485,21 @@ int rc_get_stage_times(rc_ctx* c, rc_stage_times* o)
 {
     if (!c || !o) return RC_ERR_INVALID_ARG;
     memset(o, 0, sizeof(*o));
-    if (!c->timed) return RC_ERR_INVALID_ARG;
     RC_HIP(hipSetDevice(c->device));
-    RC_HIP(hipEventSynchronize(c->ev[3]));
-    RC_HIP(hipEventElapsedTime(&o->ms[0], c->ev[0], c->ev[1]));
-    RC_HIP(hipEventElapsedTime(&o->ms[1], c->ev[1], c->ev[2]));
-    RC_HIP(hipEventElapsedTime(&o->ms[2], c->ev[2], c->ev[3]));
-    RC_HIP(hipEventElapsedTime(&o->ms[3], c->ev[0], c->ev[3]));
-    unsigned long long r[2] = {0, 0};
+    RC_HIP(hipStreamSynchronize(c->stream));
+    if (c->timed) {
+        RC_HIP(hipEventElapsedTime(&o->ms[0], c->ev[0], c->ev[1]));
+        RC_HIP(hipEventElapsedTime(&o->ms[1], c->ev[1], c->ev[2]));
+        RC_HIP(hipEventElapsedTime(&o->ms[2], c->ev[2], c->ev[3]));
+        RC_HIP(hipEventElapsedTime(&o->ms[3], c->ev[0], c->ev[3]));
+    }
+    unsigned long long r[6] = {0, 0, 0, 0, 0, 0};
     RC_HIP(hipMemcpy(r, c->d_rays, sizeof(r), hipMemcpyDeviceToHost));
-    o->rays[0] = r[0];
-    o->rays[1] = r[1];
+    for (int k = 0; k < 2; ++k) {
+        o->rays[k] = r[k];
+        o->node_visits[k] = r[2 + k];
+        o->tri_tests[k] = r[4 + k];
+    }
     return RC_OK;
 }
 

@@ -85,7 +85,7 @@ struct TraceWork {
     uint32_t overflow_depth;  // entries per lane beyond the LDS part
     uint32_t n_lanes;         // lanes of the persistent grid
     uint32_t* error_flag;     // set on stack overflow
-    unsigned long long* ray_count; // optional ray counter (NULL = not counted)
+    unsigned long long* ray_count; // [0] rays cast, [2] nodes visited, [4] triangles tested (NULL = not counted)
 };
 
 // Launchers (k_trace.hip)

@@ -156,3 +156,56 @@ def test_render_error_paths(ctx):
         ctx.scene(scene.positions * np.nan, scene.indices, scene.tri_material, scene.materials)
     assert e.value.status == -2
     assert ctx.last_error() == 0
+
+
+def compare_rect(ctx, O, scene, cam, N, stream, pixels=None):
+    import torch
+    say(f"[rect] {scene.name} {cam.width}x{cam.height} N={N} tris={scene.n_tris}")
+    gs = ctx.scene_from(scene).build()
+    out = ctx.render(gs, cam, (), rect=scene.rect_light, area_samples=N, area_stream=stream, sample_rgba=True)
+    torch.cuda.synchronize()
+    assert ctx.last_error() == 0
+    npix = cam.width * cam.height
+    pix = np.arange(npix) if pixels is None else np.asarray(pixels)
+    osc = O.OracleScene.from_scene(scene)
+    orc = osc.render_rect(cam, scene.rect_light, N, stream, pix)
+    hit = to_np(out["hit"]).view(np.uint32)[pix]
+    vis = to_np(out["visibility"]).reshape(-1)[pix]
+    cnt = np.rint(vis.astype(np.float64) * N).astype(np.int64)
+    assert np.array_equal(cnt.astype(np.float32) / np.float32(N), vis)
+    bp = orc["band_primary"].astype(bool)
+    ok = ~bp
+    assert (hit[ok, 0] != orc["hit_id"][ok]).sum() == 0
+    diff = np.abs(cnt - orc["vis_count"])
+    assert (diff[ok] <= orc["band_count"][ok]).all()
+    exact = ok & (orc["band_count"] == 0)
+    assert (diff[exact] == 0).all()
+    # radiance = unshadowed centre-point term times the GPU visibility
+    want = orc["rgb_unshadowed"] * vis[:, None].astype(np.float64)
+    got = to_np(out["sample_rgba"])[pix, :3].astype(np.float64)
+    lmax = max(float(want.max()), 1e-30)
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-6 * lmax)
+    st = {"n": len(pix), "band_primary": int(bp.sum()), "band_rays": int(orc["band_count"][ok].sum()),
+          "pix_with_band_rays": int((orc["band_count"][ok] > 0).sum()), "rgb_max_rel": float(rel[ok].max()),
+          "mean_V": float(vis[ok & (orc["hit_id"] != NO_HIT)].mean())}
+    say("[rect parity]", st)
+    assert st["rgb_max_rel"] <= 1e-4
+    return out, orc, st
+
+
+@pytest.mark.parametrize("seed,w,h,N,stream", [(0, 48, 40, 16, 0), (5, 61, 33, 7, 3)])
+def test_rect_light_small(ctx, oracle_mod, seed, w, h, N, stream):
+    scene = sg.small_random_scene(seed, n_instances=40, width=w, height=h, ssaa=1)
+    out, orc, st = compare_rect(ctx, oracle_mod, scene, scene.cameras[0], N, stream)
+    assert 0.0 < st["mean_V"] < 1.0
+
+
+def test_rect_light_big_scene_sampled(ctx, oracle_mod):
+    """7.3M triangles at 1920x1080 with 64 light samples per pixel (the benchmark's plain path):
+    4000 pixels checked against the oracle."""
+    scene = sg.big_scene(0)
+    cam = scene.cameras[0]
+    rng = np.random.default_rng(1)
+    pix = np.sort(rng.choice(cam.width * cam.height, 4000, replace=False))
+    out, orc, st = compare_rect(ctx, oracle_mod, scene, cam, 64, 0, pixels=pix)
+    assert st["band_primary"] < 0.01 * st["n"]
