@@ -21,6 +21,22 @@ METRIC = "Mrays/s + 1080p frame ms at 7.3M tris; denoised 1spp vs 64spp at equal
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES = 128, 48
 
+# Bytes per launch of the dominant kernel measured with rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by
+# the copy-kernel calibration), keyed by (workload, spp, hash of the traversal kernel sources); the
+# value only applies while those sources are unchanged (summaries under profiles/).
+MEASURED_TRAFFIC = {
+    ("big_7M", 64, "debbe70d8d632e13:96fd43948bc92d3c"): 27_833_000_000,
+}
+
+
+def kernel_hash():
+    import hashlib
+    h = []
+    for f in ("k_trace.hip", "rc_device.h"):
+        with open(os.path.join(ROOT, "paper_2410_05095_amd", "csrc", f), "rb") as fh:
+            h.append(hashlib.sha256(fh.read()).hexdigest()[:16])
+    return ":".join(h)
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -154,7 +170,7 @@ def main():
                 "sah": round(bst["sah_cost"], 2)},
         "roofline": {"kernel": "k_trace<shadow>", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": MEASURED_TRAFFIC.get((args.workload, args.spp, kernel_hash()))},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
