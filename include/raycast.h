@@ -107,6 +107,9 @@ int rc_bvh_build(rc_ctx* ctx, rc_scene* scene, const rc_build_opts* opts);
 int rc_scene_set_transforms(rc_ctx* ctx, rc_scene* scene, const float* d_xforms,
                             const uint32_t* d_body_ids, uint32_t n);
 
+/* Copy the current vertex positions (n_vertices x 3 float) to host memory `out`.  Synchronous. */
+int rc_scene_get_positions(rc_ctx* ctx, const rc_scene* scene, float* out);
+
 /* Recompute every node box bottom-up from the current vertex positions, keeping the
  * tree topology (exact FP32 min/max, so boxes equal a fresh computation bit for bit).
  * RC_ERR_NOT_BUILT without a prior rc_bvh_build. */
@@ -118,7 +121,8 @@ typedef struct rc_bvh_stats {
     uint64_t n_tris;
     uint32_t depth;        /* levels of 4-wide nodes */
     uint32_t max_stack;    /* traversal stack entries that suffice for any ray */
-    double sah_cost;       /* SAH cost (node 1, triangle 1) relative to the root box */
+    double sah_cost;       /* SAH cost (node 1, triangle 1) relative to the root box, of the current
+                              (possibly refit) boxes */
     double build_ms;       /* host build time of the last rc_bvh_build */
 } rc_bvh_stats;
 int rc_bvh_get_stats(rc_ctx* ctx, const rc_scene* scene, rc_bvh_stats* out);

@@ -93,6 +93,7 @@ SIGNATURES = {
                             C.POINTER(RcRectLight), C.POINTER(RcRenderOpts), C.POINTER(RcOutputs)]),
     "rc_get_stage_times": (C.c_int, [P, C.POINTER(RcStageTimes)]),
     "rc_camera_rays": (C.c_int, [P, C.POINTER(RcCamera), P, P]),
+    "rc_scene_get_positions": (C.c_int, [P, P, P]),
 }
 
 _lib = None
@@ -294,6 +295,11 @@ class Scene:
         check(lib().rc_scene_set_transforms(self.ctx.h, self.h, C.c_void_p(d_xforms.data_ptr()),
                                             C.c_void_p(d_body_ids.data_ptr()), int(d_body_ids.numel())),
               "rc_scene_set_transforms")
+
+    def positions(self) -> np.ndarray:
+        out = np.zeros_like(self.pos)
+        check(lib().rc_scene_get_positions(self.ctx.h, self.h, _ptr(out)), "rc_scene_get_positions")
+        return out
 
     def stats(self) -> dict:
         s = RcBvhStats()

@@ -44,6 +44,7 @@ struct rc_scene {
     float4* d_tris = nullptr;
     double build_ms = 0.0;
     float scale = 1.0f;
+    bool sah_stale = false;   // boxes refit on the device since the host copy was made
 };
 
 namespace {
@@ -367,13 +368,32 @@ int rc_bvh_refit(rc_ctx* c, rc_scene* s)
     for (int lv = (int)s->hb.depth - 1; lv >= 0; --lv)
         rc_launch_refit_level(s->d_nodes, s->d_pos, s->d_idx, s->d_order, ls[lv], ls[lv + 1] - ls[lv], c->stream);
     RC_HIP(hipGetLastError());
+    s->sah_stale = true;
     return RC_OK;
 }
 
-int rc_bvh_get_stats(rc_ctx* c, const rc_scene* s, rc_bvh_stats* o)
+int rc_scene_get_positions(rc_ctx* c, const rc_scene* s, float* out)
 {
-    if (!c || !s || !o) return RC_ERR_INVALID_ARG;
-    if (!s->built) return RC_ERR_NOT_BUILT;
+    if (!c || !s || !out) return RC_ERR_INVALID_ARG;
+    RC_HIP(hipSetDevice(c->device));
+    RC_HIP(hipMemcpyAsync(out, s->d_pos, (size_t)s->nv * 12, hipMemcpyDeviceToHost, c->stream));
+    RC_HIP(hipStreamSynchronize(c->stream));
+    return RC_OK;
+}
+
+int rc_bvh_get_stats(rc_ctx* c, const rc_scene* s_, rc_bvh_stats* o)
+{
+    if (!c || !s_ || !o) return RC_ERR_INVALID_ARG;
+    if (!s_->built) return RC_ERR_NOT_BUILT;
+    rc_scene* s = const_cast<rc_scene*>(s_);
+    if (s->sah_stale) {
+        RC_HIP(hipSetDevice(c->device));
+        RC_HIP(hipMemcpyAsync(s->hb.nodes.data(), s->d_nodes, s->hb.nodes.size() * sizeof(Node4),
+                              hipMemcpyDeviceToHost, c->stream));
+        RC_HIP(hipStreamSynchronize(c->stream));
+        s->hb.sah_cost = rc_bvh_sah(s->hb.nodes);
+        s->sah_stale = false;
+    }
     o->n_nodes = s->hb.nodes.size();
     o->n_leaves = s->hb.n_leaves;
     o->n_tris = s->nt;

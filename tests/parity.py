@@ -66,3 +66,40 @@ def assert_clean(stats, max_band_frac=0.05):
               "rgb_viol", "alpha_mismatch"):
         assert stats.get(k, 0) == 0, (k, stats)
     assert stats["band_primary"] <= max_band_frac * stats["n"], stats
+
+
+def bvh_bound_errors(nodes, order, pos, idx):
+    """Vectorised check that every child box of an exported 4-wide BVH equals the exact FP32 min/max
+    of what it contains (the leaf's triangles, or the child node's boxes).  Returns the number of
+    child boxes that differ, and a histogram of leaf sizes."""
+    nodes = np.asarray(nodes, np.uint32)
+    f = nodes.view(np.float32)
+    lo = np.stack([f[:, 0:4], f[:, 8:12], f[:, 16:20]], axis=1)     # (n, 3, 4)
+    hi = np.stack([f[:, 4:8], f[:, 12:16], f[:, 20:24]], axis=1)
+    child = nodes[:, 24:28]
+    empty = child == 0xFFFFFFFF
+    leaf = ((child & 0x80000000) != 0) & ~empty
+    inner = ~leaf & ~empty
+    bad = 0
+    # leaves
+    ni, ci = np.nonzero(leaf)
+    w = child[ni, ci]
+    first = (w & 0x0FFFFFFF).astype(np.int64)
+    cnt = (((w >> 28) & 7) + 1).astype(np.int64)
+    elo = np.full((len(w), 3), np.inf, np.float32)
+    ehi = np.full((len(w), 3), -np.inf, np.float32)
+    for k in range(4):
+        m = k < cnt
+        tri = order[first[m] + k]
+        for v in range(3):
+            p = pos[idx[tri, v]]
+            elo[m] = np.minimum(elo[m], p)
+            ehi[m] = np.maximum(ehi[m], p)
+    bad += int((~((lo[ni, :, ci] == elo).all(1) & (hi[ni, :, ci] == ehi).all(1))).sum())
+    # internal children
+    ni, ci = np.nonzero(inner)
+    w = child[ni, ci].astype(np.int64)
+    clo = np.where(empty[w][:, None, :], np.inf, lo[w]).min(axis=2)
+    chi = np.where(empty[w][:, None, :], -np.inf, hi[w]).max(axis=2)
+    bad += int((~((lo[ni, :, ci] == clo).all(1) & (hi[ni, :, ci] == chi).all(1))).sum())
+    return bad, np.bincount(cnt, minlength=5)
