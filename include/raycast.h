@@ -216,6 +216,47 @@ typedef struct rc_stage_times {
 } rc_stage_times;
 int rc_get_stage_times(rc_ctx* ctx, rc_stage_times* out);
 
+/* ------------------------------------------------------------- batch ---- */
+/* One view of a batch: a camera on one of the batch's scenes, lit by a range of the batch's
+ * point lights, with its own outputs (layouts as in rc_outputs; d_shadow may be NULL when
+ * n_lights = 0). */
+typedef struct rc_view {
+    uint32_t scene;            /* index into the scenes array */
+    rc_camera camera;
+    uint32_t light_first;      /* first light in the lights array */
+    uint32_t n_lights;         /* <= 16 */
+    float* d_rgba;
+    uint32_t* d_hit;
+    uint32_t* d_shadow;
+} rc_view;
+
+/* Tuning of the persistent batched kernel.  Zero fields take defaults (8, 8, 256, 40, max). */
+typedef struct rc_tune {
+    uint32_t tile_w, tile_h;   /* work-item tile in pixels; tile_w * tile_h in 16..1024 */
+    uint32_t queue_depth;      /* pixels a wave claims per atomic on the device queue (64..4096, multiple of 64) */
+    uint32_t min_rays;         /* rays per wave kept in flight: a wave refills its idle lanes when fewer are busy (1..64) */
+    uint32_t waves_per_simd;   /* resident waves per SIMD of the persistent grid (1..occupancy limit) */
+} rc_tune;
+
+enum {
+    RC_FLAG_GRAPH = 2u         /* rc_render_batch: capture the launch as a hipGraph once per batch shape, then replay */
+};
+
+/* Render all views in one persistent kernel launch fed by a device work queue (point lights and
+ * 2x2 or 1 sample per pixel).  Every view's outputs are bit-identical to rc_render of that view
+ * alone, for any tuning.  flags: RC_FLAG_TIMING (rc_get_stage_times ms[3]), RC_FLAG_GRAPH.  All
+ * scenes must be built.  Errors: RC_ERR_INVALID_ARG, RC_ERR_NOT_BUILT, RC_ERR_UNSUPPORTED, RC_ERR_HIP. */
+int rc_render_batch(rc_ctx* ctx, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,
+                    const rc_point_light* lights, uint32_t n_lights_total, const rc_tune* tune, uint32_t flags);
+
+/* Time every candidate tuning (`reps` timed launches after one warm-up, median) on this batch and
+ * return the fastest in *best (and its median ms in *best_ms).  candidates = NULL uses a built-in grid.
+ * With cache_path != NULL, a JSON-lines file keyed by (GPU arch, CU count, batch-shape hash) is read
+ * first (a hit skips the search) and the result appended.  Overwrites the views' outputs. */
+int rc_autotune(rc_ctx* ctx, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,
+                const rc_point_light* lights, uint32_t n_lights_total, const rc_tune* candidates, uint32_t n_candidates,
+                uint32_t reps, const char* cache_path, rc_tune* best, float* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libraycast.so")
 
 RC_FLAG_TIMING = 1
+RC_FLAG_GRAPH = 2
 NO_HIT = 0xFFFFFFFF
 
 
@@ -66,6 +67,19 @@ class RcOutputs(C.Structure):
                 ("d_visibility", C.c_void_p), ("d_sample_rgba", C.c_void_p)]
 
 
+class RcView(C.Structure):
+    _fields_ = [("scene", C.c_uint32), ("camera", RcCamera), ("light_first", C.c_uint32), ("n_lights", C.c_uint32),
+                ("d_rgba", C.c_void_p), ("d_hit", C.c_void_p), ("d_shadow", C.c_void_p)]
+
+
+class RcTune(C.Structure):
+    _fields_ = [("tile_w", C.c_uint32), ("tile_h", C.c_uint32), ("queue_depth", C.c_uint32),
+                ("min_rays", C.c_uint32), ("waves_per_simd", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class RcStageTimes(C.Structure):
     _fields_ = [("ms", C.c_float * 8), ("rays", C.c_uint64 * 2), ("node_visits", C.c_uint64 * 2),
                 ("tri_tests", C.c_uint64 * 2)]
@@ -94,6 +108,11 @@ SIGNATURES = {
     "rc_get_stage_times": (C.c_int, [P, C.POINTER(RcStageTimes)]),
     "rc_camera_rays": (C.c_int, [P, C.POINTER(RcCamera), P, P]),
     "rc_scene_get_positions": (C.c_int, [P, P, P]),
+    "rc_render_batch": (C.c_int, [P, P, C.c_uint32, C.POINTER(RcView), C.c_uint32, C.POINTER(RcPointLight),
+                                  C.c_uint32, C.POINTER(RcTune), C.c_uint32]),
+    "rc_autotune": (C.c_int, [P, P, C.c_uint32, C.POINTER(RcView), C.c_uint32, C.POINTER(RcPointLight), C.c_uint32,
+                              C.POINTER(RcTune), C.c_uint32, C.c_uint32, C.c_char_p, C.POINTER(RcTune),
+                              C.POINTER(C.c_float)]),
 }
 
 _lib = None
@@ -241,6 +260,63 @@ class Context:
         check(lib().rc_camera_rays(self.h, C.byref(camc), C.c_void_p(o.data_ptr()), C.c_void_p(d.data_ptr())),
               "rc_camera_rays")
         return o, d
+
+    # -- batched rendering ----------------------------------------------------
+    def _batch_args(self, scenes, views, outs):
+        """views: list of (scene index, camera, light_first, n_lights); outs: list of dicts (allocated
+        here when empty).  Returns the ctypes arrays."""
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        sarr = (C.c_void_p * len(scenes))(*[s.h.value for s in scenes])
+        varr = (RcView * len(views))()
+        for i, (si, cam, lf, nl) in enumerate(views):
+            W, H, S = int(cam.width), int(cam.height), int(cam.ssaa) ** 2
+            o = outs[i]
+            if o.get("rgba") is None or tuple(o["rgba"].shape) != (H, W, 4):
+                o["rgba"] = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+                o["hit"] = torch.empty((H * W * S, 4), dtype=torch.int32, device=dev)
+                o["shadow"] = torch.empty((H * W * S,), dtype=torch.int32, device=dev) if nl else None
+            varr[i].scene = int(si)
+            varr[i].camera = camera_struct(cam)
+            varr[i].light_first = int(lf)
+            varr[i].n_lights = int(nl)
+            varr[i].d_rgba = o["rgba"].data_ptr()
+            varr[i].d_hit = o["hit"].data_ptr()
+            varr[i].d_shadow = o["shadow"].data_ptr() if nl else None
+        return sarr, varr
+
+    def render_batch(self, scenes, views, lights, tune: Optional[dict] = None, graph: bool = False,
+                     timing: bool = False, outs: Optional[list] = None) -> list:
+        self._sync_stream()
+        if outs is None:
+            outs = [{} for _ in views]
+        sarr, varr = self._batch_args(scenes, views, outs)
+        Larr = light_array(lights)
+        nl = 0 if Larr is None else len(Larr)
+        t = RcTune(**tune) if tune else None
+        flags = (RC_FLAG_GRAPH if graph else 0) | (RC_FLAG_TIMING if timing else 0)
+        check(lib().rc_render_batch(self.h, sarr, len(scenes), varr, len(views), Larr, nl,
+                                    C.byref(t) if t is not None else None, flags), "rc_render_batch")
+        return outs
+
+    def autotune(self, scenes, views, lights, candidates=None, reps: int = 3, cache_path: Optional[str] = None,
+                 outs: Optional[list] = None):
+        self._sync_stream()
+        if outs is None:
+            outs = [{} for _ in views]
+        sarr, varr = self._batch_args(scenes, views, outs)
+        Larr = light_array(lights)
+        nl = 0 if Larr is None else len(Larr)
+        cand = None
+        if candidates:
+            cand = (RcTune * len(candidates))(*[RcTune(**c) for c in candidates])
+        best = RcTune()
+        ms = C.c_float()
+        check(lib().rc_autotune(self.h, sarr, len(scenes), varr, len(views), Larr, nl, cand,
+                                len(candidates) if candidates else 0, int(reps),
+                                cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms)),
+              "rc_autotune")
+        return best.as_dict(), float(ms.value)
 
     def stage_times(self) -> dict:
         t = RcStageTimes()

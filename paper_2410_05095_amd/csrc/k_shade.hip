@@ -1,5 +1,5 @@
 // Shading + supersampling resolve, triangle packing, rigid-body transforms and BVH refit.
-#include "rc_device.h"
+#include "rc_trav.h"
 
 namespace {
 
@@ -19,43 +19,9 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, DevCamera cam, DevLi
         size_t s = (size_t)pixel * spp + k;
         uint4 h = gbuf[s];
         float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (h.x != RC_NO_HIT) {
-            Surface S = rc_surface(sc, cam, pixel, k, h.x);
-            const float* mat = sc.mats + 5 * (size_t)sc.tri_mat[h.x];
-            double rgb[3] = {0.0, 0.0, 0.0};
-            uint32_t m = mask ? mask[s] : 0u;
-            for (int l = 0; l < L.n_point; ++l) {
-                if (!((m >> l) & 1u)) continue;
-                D3 lp = d3(L.point[l][0], L.point[l][1], L.point[l][2]);
-                D3 tl = d3sub(lp, S.p);
-                double d2 = d3dot(tl, tl);
-                D3 wi = d3nrm(tl);
-                double f[3];
-                rc_brdf(S.n, S.wo, wi, mat, f);
-                double cosi = fmax(d3dot(S.n, wi), 0.0);
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) rgb[ch] += f[ch] * (double)L.point[l][3 + ch] * cosi / d2;
-            }
-            if (L.has_rect) {
-                D3 C = d3(L.rect[0], L.rect[1], L.rect[2]);
-                D3 eu = d3(L.rect[3], L.rect[4], L.rect[5]), ev = d3(L.rect[6], L.rect[7], L.rect[8]);
-                D3 nraw = d3cross(eu, ev);
-                double area = sqrt(d3dot(nraw, nraw));
-                D3 nL = d3nrm(nraw);
-                D3 tl = d3sub(C, S.p);
-                double d2 = d3dot(tl, tl);
-                D3 wi = d3nrm(tl);
-                double cosl = fmax(-d3dot(nL, wi), 0.0);
-                double cosi = fmax(d3dot(S.n, wi), 0.0);
-                double f[3];
-                rc_brdf(S.n, S.wo, wi, mat, f);
-                double V = (double)vis[pixel];
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch)
-                    rgb[ch] += f[ch] * (double)L.rect[9 + ch] * area * cosl * cosi / d2 * V;
-            }
-            out = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], 1.0f);
-        }
+        if (h.x != RC_NO_HIT)
+            out = rc_shade_sample(sc, cam, &L.point[0][0], L.n_point, L.has_rect ? L.rect : nullptr,
+                                  L.has_rect ? (double)vis[pixel] : 0.0, pixel, k, h.x, mask ? mask[s] : 0u);
         smp[k] = out;
         if (sample_rgba) reinterpret_cast<float4*>(sample_rgba)[s] = out;
     }

@@ -11,13 +11,12 @@
 // tests with the octant-selected near/far planes and a conservative far distance; ordered
 // descent (nearest child first) for closest hits; per-lane stack of (node, entry distance)
 // in LDS with a lane-interleaved global overflow area.  Triangles: Moller-Trumbore in FP32.
-#include "rc_device.h"
+#include "rc_trav.h"
 
 namespace {
 
 constexpr int BLOCK = RC_TRACE_BLOCK;
 constexpr int SL = RC_STACK_LDS;
-constexpr uint32_t STACK_EMPTY = 0xFFFFFFFEu;
 constexpr int REFILL_AT = 40;   // refill once a wave has at most this many busy lanes
 
 enum { MODE_PRIMARY = 0, MODE_POINT = 1, MODE_RECT = 2 };
@@ -36,9 +35,6 @@ struct KParams {
     uint32_t slot;
 };
 
-// conservative growth of the far slab distance (covers FP32 rounding of the slab tests)
-constexpr float FAR_GROW = 1.000001f;
-
 template <int MODE>
 __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
 {
@@ -51,91 +47,28 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
     const uint32_t glane = blockIdx.x * BLOCK + tid;
     const DevScene sc = P.sc;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    TravStack<SL, BLOCK, !ANY> st{s_node, s_t, tid, reinterpret_cast<uint2*>(P.w.overflow), P.w.overflow_depth,
+                                   P.w.n_lanes, glane, P.w.error_flag};
 
     int state = 0;                    // 0 idle, 1 tracing
     uint32_t px = 0, pk = 0;          // pixel and sample of the current item
     uint32_t j = 0, acc = 0;          // shadow: current light / light sample, result accumulator
     uint32_t n_rays = 0;
     float os[3] = {0, 0, 0}, nf[3] = {0, 0, 0};
-    float o[3], d[3], inv[3];
-    uint32_t cur = 0;
-    int sp = 0;
-    uint32_t best_id = RC_NO_HIT;
-    float best_t = INFINITY, best_u = 0.f, best_v = 0.f;
+    TravRay ray;
+    TravState ts;
     bool queue_empty = false;
     uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
 
-    auto set_dir = [&]() {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            float dd = fabsf(d[a]) < 1e-20f ? copysignf(1e-20f, d[a]) : d[a];
-            inv[a] = 1.0f / dd;
-        }
-        cur = 0;
-        sp = 0;
-        rays_cast++;
-    };
-
-    auto push = [&](uint32_t node, float t) {
-        if (sp < SL) {
-            s_node[sp][tid] = node;
-            if (!ANY) s_t[sp][tid] = t;
-        } else if ((uint32_t)(sp - SL) < P.w.overflow_depth) {
-            uint2* g = reinterpret_cast<uint2*>(P.w.overflow) + (size_t)(sp - SL) * P.w.n_lanes + glane;
-            *g = make_uint2(node, __float_as_uint(t));
-        } else {
-            *P.w.error_flag = 1u;   // bound exceeded: drop the entry (flagged, never expected)
-            return;
-        }
-        ++sp;
-    };
-
-    auto pop = [&]() -> uint32_t {
-        for (;;) {
-            if (sp == 0) return STACK_EMPTY;
-            --sp;
-            uint32_t node;
-            float t;
-            if (sp < SL) {
-                node = s_node[sp][tid];
-                t = ANY ? 0.0f : s_t[sp][tid];
-            } else {
-                uint2 g = reinterpret_cast<const uint2*>(P.w.overflow)[(size_t)(sp - SL) * P.w.n_lanes + glane];
-                node = g.x;
-                t = __uint_as_float(g.y);
-            }
-            if (ANY || t <= best_t) return node;
-        }
-    };
-
-    // shadow items: set up the next ray with n . d > 0 (and facing the rect light), or return false
+    // shadow items: set up the next ray that is cast, or return false
     auto next_shadow_ray = [&]() -> bool {
         while (j < n_rays) {
-            float tgt[3];
-            if (MODE == MODE_POINT) {
-                tgt[0] = P.L.point[j][0]; tgt[1] = P.L.point[j][1]; tgt[2] = P.L.point[j][2];
-            } else {
-                uint32_t r[4];
-                rc_philox(px, j, 1u + P.L.area_stream, 0u, P.cam.seed, P.cam.frame, r);
-                float x1 = rc_unit24(r[0]) - 0.5f, x2 = rc_unit24(r[1]) - 0.5f;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    float t1 = x1 * P.L.rect[3 + a];
-                    float t2 = x2 * P.L.rect[6 + a];
-                    tgt[a] = (P.L.rect[a] + t1) + t2;
-                }
+            if (rc_shadow_ray(P.L.point[MODE == MODE_POINT ? j : 0], P.L.rect, P.nL, MODE == MODE_RECT, px, j,
+                              P.L.area_stream, P.cam.seed, P.cam.frame, os, nf, ray)) {
+                trav_begin(ray, ts);
+                ++rays_cast;
+                return true;
             }
-#pragma unroll
-            for (int a = 0; a < 3; ++a) { o[a] = os[a]; d[a] = tgt[a] - os[a]; }
-            float nd = nf[0] * d[0] + nf[1] * d[1];
-            nd = nd + nf[2] * d[2];
-            bool ok = nd > 0.0f;
-            if (MODE == MODE_RECT) {
-                float ld = P.nL[0] * d[0] + P.nL[1] * d[1];
-                ld = ld + P.nL[2] * d[2];
-                ok = ok && ld < 0.0f;
-            }
-            if (ok) { set_dir(); return true; }
             ++j;
         }
         return false;
@@ -149,11 +82,9 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
     auto start_item = [&](uint32_t item) -> bool {
         if (!rc_item_to_sample(P.cam, item, px, pk)) return false;
         if (MODE == MODE_PRIMARY) {
-            rc_camera_ray(P.cam, px, pk, o, d);
-            best_id = RC_NO_HIT;
-            best_t = INFINITY;
-            best_u = best_v = 0.0f;
-            set_dir();
+            rc_camera_ray(P.cam, px, pk, ray.o, ray.d);
+            trav_begin(ray, ts);
+            ++rays_cast;
             return true;
         } else {
             size_t s = (size_t)px * (P.cam.ssaa * P.cam.ssaa) + pk;
@@ -176,7 +107,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
     auto end_ray = [&](bool occluded) -> bool {
         if (MODE == MODE_PRIMARY) {
             P.gbuf_out[(size_t)px * (P.cam.ssaa * P.cam.ssaa) + pk] =
-                make_uint4(best_id, __float_as_uint(best_t), __float_as_uint(best_u), __float_as_uint(best_v));
+                make_uint4(ts.best_id, __float_as_uint(ts.best_t), __float_as_uint(ts.best_u), __float_as_uint(ts.best_v));
             return false;
         } else {
             if (!occluded) acc += (MODE == MODE_POINT) ? (1u << j) : 1u;
@@ -208,95 +139,8 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
         // ---- traversal steps: one node or one leaf per lane and step
         for (;;) {
             if (state == 1) {
-                bool ended = false, occluded = false;
-                if (!rc_is_leaf(cur)) {
-                    ++node_visits;
-                    const float4* np = reinterpret_cast<const float4*>(sc.nodes + cur);
-                    float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-                    uint4 ch = reinterpret_cast<const uint4*>(np)[6];
-                    const float bound = ANY ? 1.0f : best_t;
-                    float lxs[4] = {lx.x, lx.y, lx.z, lx.w}, hxs[4] = {hx.x, hx.y, hx.z, hx.w};
-                    float lys[4] = {ly.x, ly.y, ly.z, ly.w}, hys[4] = {hy.x, hy.y, hy.z, hy.w};
-                    float lzs[4] = {lz.x, lz.y, lz.z, lz.w}, hzs[4] = {hz.x, hz.y, hz.z, hz.w};
-                    uint32_t cw[4] = {ch.x, ch.y, ch.z, ch.w};
-                    float tn[4];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        float nx = inv[0] >= 0.0f ? lxs[c] : hxs[c], fx = inv[0] >= 0.0f ? hxs[c] : lxs[c];
-                        float ny = inv[1] >= 0.0f ? lys[c] : hys[c], fy = inv[1] >= 0.0f ? hys[c] : lys[c];
-                        float nz = inv[2] >= 0.0f ? lzs[c] : hzs[c], fz = inv[2] >= 0.0f ? hzs[c] : lzs[c];
-                        float t0 = fmaxf(fmaxf((nx - o[0]) * inv[0], (ny - o[1]) * inv[1]),
-                                         fmaxf((nz - o[2]) * inv[2], 0.0f));
-                        float t1 = fminf(fminf((fx - o[0]) * inv[0], (fy - o[1]) * inv[1]), (fz - o[2]) * inv[2]);
-                        bool hit = t0 <= fminf(t1 * FAR_GROW, bound);
-                        tn[c] = hit ? t0 : INFINITY;
-                    }
-                    if (!ANY) {
-                        // sort (distance, child) ascending: misses (inf) sink to the end
-#define RC_CS(a, b)                                                                   \
-    {                                                                                 \
-        bool sw = tn[b] < tn[a];                                                      \
-        float ta = sw ? tn[b] : tn[a], tb = sw ? tn[a] : tn[b];                       \
-        uint32_t ca = sw ? cw[b] : cw[a], cb = sw ? cw[a] : cw[b];                    \
-        tn[a] = ta; tn[b] = tb; cw[a] = ca; cw[b] = cb;                               \
-    }
-                        RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
-#undef RC_CS
-                        if (tn[3] < INFINITY) push(cw[3], tn[3]);
-                        if (tn[2] < INFINITY) push(cw[2], tn[2]);
-                        if (tn[1] < INFINITY) push(cw[1], tn[1]);
-                        cur = tn[0] < INFINITY ? cw[0] : pop();
-                    } else {
-                        uint32_t next = STACK_EMPTY;
-#pragma unroll
-                        for (int c = 3; c >= 0; --c) {
-                            if (tn[c] < INFINITY) {
-                                if (next != STACK_EMPTY) push(next, 0.0f);
-                                next = cw[c];
-                            }
-                        }
-                        cur = next != STACK_EMPTY ? next : pop();
-                    }
-                } else {
-                    uint32_t first = rc_leaf_first(cur), cnt = rc_leaf_count(cur);
-                    for (uint32_t i = 0; i < cnt; ++i) {
-                        ++tri_tests;
-                        const float4* tp = sc.tris + 3 * (size_t)(first + i);
-                        float4 A = tp[0], B = tp[1], C = tp[2];
-                        // Moller-Trumbore
-                        float px_ = d[1] * C.z - d[2] * C.y;
-                        float py_ = d[2] * C.x - d[0] * C.z;
-                        float pz_ = d[0] * C.y - d[1] * C.x;
-                        float det = B.x * px_ + B.y * py_;
-                        det = det + B.z * pz_;
-                        float idet = __builtin_amdgcn_rcpf(det);
-                        float sx = o[0] - A.x, sy = o[1] - A.y, sz = o[2] - A.z;
-                        float su = sx * px_ + sy * py_;
-                        su = su + sz * pz_;
-                        float u = su * idet;
-                        float qx = sy * B.z - sz * B.y;
-                        float qy = sz * B.x - sx * B.z;
-                        float qz = sx * B.y - sy * B.x;
-                        float sv = d[0] * qx + d[1] * qy;
-                        sv = sv + d[2] * qz;
-                        float v = sv * idet;
-                        float st = C.x * qx + C.y * qy;
-                        st = st + C.z * qz;
-                        float t = st * idet;
-                        bool hit = u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f;
-                        if (ANY) {
-                            if (hit && t < 1.0f) { occluded = true; break; }
-                        } else {
-                            uint32_t id = __float_as_uint(A.w);
-                            if (hit && (t < best_t || (t == best_t && id < best_id))) {
-                                best_t = t; best_u = u; best_v = v; best_id = id;
-                            }
-                        }
-                    }
-                    cur = occluded ? STACK_EMPTY : pop();
-                }
-                if (cur == STACK_EMPTY) ended = true;
-                if (ended) {
+                bool occluded;
+                if (trav_step(sc, ray, ts, st, ANY, occluded, node_visits, tri_tests)) {
                     if (!end_ray(occluded)) state = 0;
                 }
             }

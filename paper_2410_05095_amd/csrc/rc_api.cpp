@@ -3,9 +3,12 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdio.h>
+
 #include <algorithm>
 #include <chrono>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/raycast.h"
@@ -21,7 +24,18 @@ struct rc_ctx {
     size_t overflow_words = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
+    bool timed_batch = false;
     int sticky = RC_OK;
+    // batched rendering: device table, pinned staging copy, captured graph
+    uint8_t* d_table = nullptr;
+    uint8_t* h_table = nullptr;
+    size_t table_cap = 0;
+    hipEvent_t ev_staging = nullptr;
+    bool staging_pending = false;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_key = 0;
 };
 
 struct rc_scene {
@@ -203,6 +217,12 @@ int rc_destroy(rc_ctx* c)
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
+    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
+    if (c->ev_staging) hipEventDestroy(c->ev_staging);
+    if (c->h_table) hipHostFree(c->h_table);
+    dev_free(c->d_table);
     dev_free(c->d_counters);
     dev_free(c->d_rays);
     dev_free(c->d_overflow);
@@ -485,6 +505,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
                     out->d_sample_rgba, q);
     if (timing) RC_HIP(hipEventRecord(c->ev[3], q));
     c->timed = timing;
+    c->timed_batch = false;
     RC_HIP(hipGetLastError());
     return RC_OK;
 }
@@ -507,18 +528,345 @@ int rc_get_stage_times(rc_ctx* c, rc_stage_times* o)
     memset(o, 0, sizeof(*o));
     RC_HIP(hipSetDevice(c->device));
     RC_HIP(hipStreamSynchronize(c->stream));
-    if (c->timed) {
+    if (c->timed && !c->timed_batch) {
         RC_HIP(hipEventElapsedTime(&o->ms[0], c->ev[0], c->ev[1]));
         RC_HIP(hipEventElapsedTime(&o->ms[1], c->ev[1], c->ev[2]));
         RC_HIP(hipEventElapsedTime(&o->ms[2], c->ev[2], c->ev[3]));
-        RC_HIP(hipEventElapsedTime(&o->ms[3], c->ev[0], c->ev[3]));
     }
+    if (c->timed) RC_HIP(hipEventElapsedTime(&o->ms[3], c->ev[0], c->ev[3]));
     unsigned long long r[6] = {0, 0, 0, 0, 0, 0};
     RC_HIP(hipMemcpy(r, c->d_rays, sizeof(r), hipMemcpyDeviceToHost));
     for (int k = 0; k < 2; ++k) {
         o->rays[k] = r[k];
         o->node_visits[k] = r[2 + k];
         o->tri_tests[k] = r[4 + k];
+    }
+    return RC_OK;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------- batch
+namespace {
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n)
+{
+    const uint8_t* b = static_cast<const uint8_t*>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    return h;
+}
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+int check_tune(rc_tune* t, int max_wps)
+{
+    if (t->tile_w == 0) t->tile_w = 8;
+    if (t->tile_h == 0) t->tile_h = 8;
+    if (t->queue_depth == 0) t->queue_depth = 256;
+    if (t->min_rays == 0) t->min_rays = 40;
+    if (t->waves_per_simd == 0 || t->waves_per_simd > (uint32_t)max_wps) t->waves_per_simd = (uint32_t)max_wps;
+    uint32_t tp = t->tile_w * t->tile_h;
+    if (tp < 16 || tp > 1024 || t->queue_depth < 64 || t->queue_depth > 4096 || t->queue_depth % 64 ||
+        t->min_rays > 64)
+        return RC_ERR_INVALID_ARG;
+    return RC_OK;
+}
+
+struct BatchPlan {
+    std::vector<DevScene> scenes;
+    std::vector<DevView> views;
+    uint32_t n_items = 0;
+    uint32_t max_stack = 0;
+    size_t bytes = 0, off_views = 0, off_lights = 0;
+};
+
+int plan_batch(rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,
+               const rc_point_light* lights, uint32_t n_lights_total, const rc_tune& t, BatchPlan& bp)
+{
+    if (!scenes || n_scenes == 0 || !views || n_views == 0) return RC_ERR_INVALID_ARG;
+    if (n_lights_total > 0 && !lights) return RC_ERR_INVALID_ARG;
+    for (uint32_t i = 0; i < n_scenes; ++i) {
+        if (!scenes[i]) return RC_ERR_INVALID_ARG;
+        if (!scenes[i]->built) return RC_ERR_NOT_BUILT;
+        bp.scenes.push_back(dev_scene(scenes[i]));
+        bp.max_stack = std::max(bp.max_stack, scenes[i]->hb.max_stack);
+    }
+    uint64_t items = 0;
+    for (uint32_t v = 0; v < n_views; ++v) {
+        const rc_view& V = views[v];
+        const rc_camera* cam = &V.camera;
+        if (V.scene >= n_scenes) return RC_ERR_INVALID_ARG;
+        if (cam->width <= 0 || cam->height <= 0 || (int64_t)cam->width * cam->height > (1ll << 28)) return RC_ERR_INVALID_ARG;
+        if (cam->ssaa != 1 && cam->ssaa != 2) return RC_ERR_UNSUPPORTED;
+        if (!(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f) || !finite3(cam->eye) || !finite3(cam->target) ||
+            !finite3(cam->up))
+            return RC_ERR_INVALID_VALUE;
+        if (V.n_lights > 16 || (uint64_t)V.light_first + V.n_lights > n_lights_total) return RC_ERR_INVALID_ARG;
+        if (!V.d_rgba || !V.d_hit || (V.n_lights > 0 && !V.d_shadow)) return RC_ERR_INVALID_ARG;
+        if ((reinterpret_cast<uintptr_t>(V.d_rgba) | reinterpret_cast<uintptr_t>(V.d_hit)) & 15u) return RC_ERR_INVALID_ARG;
+        DevView d;
+        memset(&d, 0, sizeof(d));
+        d.cam = make_camera(cam);
+        d.scene = V.scene;
+        d.light_first = V.light_first;
+        d.n_lights = V.n_lights;
+        d.tiles_x = ((uint32_t)cam->width + t.tile_w - 1) / t.tile_w;
+        uint32_t tiles_y = ((uint32_t)cam->height + t.tile_h - 1) / t.tile_h;
+        d.item_first = (uint32_t)items;
+        items += (uint64_t)d.tiles_x * tiles_y * t.tile_w * t.tile_h;
+        d.rgba = V.d_rgba;
+        d.hit = reinterpret_cast<uint4*>(V.d_hit);
+        d.shadow = V.n_lights > 0 ? V.d_shadow : nullptr;
+        bp.views.push_back(d);
+    }
+    if (items >= (1ull << 32) - 8192) return RC_ERR_UNSUPPORTED;
+    for (uint32_t l = 0; l < n_lights_total; ++l)
+        if (!finite3(lights[l].position) || !finite3(lights[l].intensity)) return RC_ERR_INVALID_VALUE;
+    bp.n_items = (uint32_t)items;
+    bp.off_views = align16(sizeof(DevScene) * n_scenes);
+    bp.off_lights = bp.off_views + align16(sizeof(DevView) * n_views);
+    bp.bytes = bp.off_lights + align16(sizeof(float) * 6 * std::max<uint32_t>(n_lights_total, 1));
+    return RC_OK;
+}
+
+int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,
+                 const rc_point_light* lights, uint32_t n_lights_total, const rc_tune* tune_in, uint32_t flags)
+{
+    if (!c) return RC_ERR_INVALID_ARG;
+    RC_HIP(hipSetDevice(c->device));
+    int n_cu = 0;
+    RC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+    int max_blocks = rc_batch_max_blocks_per_cu(c->device);
+    int max_wps = std::max(1, max_blocks * (RC_TRACE_BLOCK / 64) / 4);
+    rc_tune t = tune_in ? *tune_in : rc_tune{0, 0, 0, 0, 0};
+    int st = check_tune(&t, max_wps);
+    if (st != RC_OK) return st;
+    BatchPlan bp;
+    st = plan_batch(scenes, n_scenes, views, n_views, lights, n_lights_total, t, bp);
+    if (st != RC_OK) return st;
+    int blocks_per_cu = std::max(1, (int)(t.waves_per_simd * 4) / (RC_TRACE_BLOCK / 64));
+    blocks_per_cu = std::min(blocks_per_cu, max_blocks);
+    int grid = n_cu * blocks_per_cu;
+
+    // overflow stack area for this grid
+    uint32_t depth = bp.max_stack > RC_STACK_LDS ? bp.max_stack - RC_STACK_LDS : 0;
+    size_t words = (size_t)grid * RC_TRACE_BLOCK * depth * 2;
+    if (words > c->overflow_words || !c->d_overflow) {
+        RC_HIP(hipStreamSynchronize(c->stream));
+        dev_free(c->d_overflow);
+        c->overflow_words = 0;
+        st = dev_alloc(&c->d_overflow, words);
+        if (st != RC_OK) return st;
+        c->overflow_words = words;
+        c->graph_key = 0;   // the captured graph points at the old buffer
+    }
+    // table: device copy of scenes, views and lights, staged through pinned host memory
+    if (bp.bytes > c->table_cap) {
+        RC_HIP(hipStreamSynchronize(c->stream));
+        if (c->h_table) hipHostFree(c->h_table);
+        dev_free(c->d_table);
+        c->h_table = nullptr;
+        c->table_cap = 0;
+        RC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_table), bp.bytes, hipHostMallocDefault));
+        st = dev_alloc(&c->d_table, bp.bytes);
+        if (st != RC_OK) return st;
+        c->table_cap = bp.bytes;
+        c->graph_key = 0;
+    }
+    if (!c->ev_staging) RC_HIP(hipEventCreateWithFlags(&c->ev_staging, hipEventDisableTiming));
+    if (c->staging_pending) RC_HIP(hipEventSynchronize(c->ev_staging));
+    memcpy(c->h_table, bp.scenes.data(), sizeof(DevScene) * n_scenes);
+    memcpy(c->h_table + bp.off_views, bp.views.data(), sizeof(DevView) * n_views);
+    for (uint32_t l = 0; l < n_lights_total; ++l) {
+        float* L = reinterpret_cast<float*>(c->h_table + bp.off_lights) + 6 * l;
+        for (int k = 0; k < 3; ++k) { L[k] = lights[l].position[k]; L[3 + k] = lights[l].intensity[k]; }
+    }
+    RC_HIP(hipMemcpyAsync(c->d_table, c->h_table, bp.bytes, hipMemcpyHostToDevice, c->stream));
+    RC_HIP(hipEventRecord(c->ev_staging, c->stream));
+    c->staging_pending = true;
+
+    BatchParams P;
+    memset(&P, 0, sizeof(P));
+    P.scenes = reinterpret_cast<const DevScene*>(c->d_table);
+    P.views = reinterpret_cast<const DevView*>(c->d_table + bp.off_views);
+    P.lights = reinterpret_cast<const float*>(c->d_table + bp.off_lights);
+    P.n_views = n_views;
+    P.n_items = bp.n_items;
+    P.tune = BatchTune{t.tile_w, t.tile_h, t.queue_depth, t.min_rays, t.waves_per_simd};
+    P.w.counters = c->d_counters;
+    P.w.overflow = c->d_overflow;
+    P.w.overflow_depth = depth;
+    P.w.n_lanes = (uint32_t)grid * RC_TRACE_BLOCK;
+    P.w.error_flag = c->d_counters + 8;
+    P.w.ray_count = c->d_rays;
+
+    bool timing = (flags & RC_FLAG_TIMING) != 0;
+    if (timing) RC_HIP(hipEventRecord(c->ev[0], c->stream));
+    if (flags & RC_FLAG_GRAPH) {
+        uint64_t key = fnv1a(1469598103934665603ull, &P, sizeof(P));
+        key = fnv1a(key, &grid, sizeof(grid));
+        if (key != c->graph_key || !c->graph_exec) {
+            if (c->graph_exec) { hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+            if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+            if (!c->capture_stream) RC_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+            RC_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed));
+            rc_launch_fill_u32(c->d_counters, 0u, 8, c->capture_stream);
+            rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, c->capture_stream);
+            rc_launch_batch(P, grid, c->capture_stream);
+            hipError_t e = hipStreamEndCapture(c->capture_stream, &c->graph);
+            if (e != hipSuccess) return RC_ERR_HIP;
+            RC_HIP(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+            c->graph_key = key;
+        }
+        RC_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+    } else {
+        rc_launch_fill_u32(c->d_counters, 0u, 8, c->stream);
+        rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, c->stream);
+        rc_launch_batch(P, grid, c->stream);
+    }
+    if (timing) RC_HIP(hipEventRecord(c->ev[3], c->stream));
+    c->timed = timing;
+    c->timed_batch = true;
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+std::string tune_key(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views)
+{
+    hipDeviceProp_t prop;
+    memset(&prop, 0, sizeof(prop));
+    hipGetDeviceProperties(&prop, c->device);
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, &n_scenes, sizeof(n_scenes));
+    for (uint32_t i = 0; i < n_scenes; ++i) {
+        uint64_t sz[2] = {scenes[i]->nt, scenes[i]->hb.nodes.size()};
+        h = fnv1a(h, sz, sizeof(sz));
+    }
+    h = fnv1a(h, &n_views, sizeof(n_views));
+    for (uint32_t v = 0; v < n_views; ++v) {
+        int32_t f[5] = {(int32_t)views[v].scene, views[v].camera.width, views[v].camera.height, views[v].camera.ssaa,
+                        (int32_t)views[v].n_lights};
+        h = fnv1a(h, f, sizeof(f));
+    }
+    char arch[64];
+    snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+    for (char* p = arch; *p; ++p)
+        if (*p == ':' || *p == '"') { *p = 0; break; }
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%s:%d:%016llx", arch, prop.multiProcessorCount, (unsigned long long)h);
+    return buf;
+}
+
+bool read_field(const char* line, const char* name, double* out)
+{
+    char pat[64];
+    snprintf(pat, sizeof(pat), "\"%s\":", name);
+    const char* p = strstr(line, pat);
+    if (!p) return false;
+    return sscanf(p + strlen(pat), "%lf", out) == 1;
+}
+
+bool cache_lookup(const char* path, const std::string& key, rc_tune* t, float* ms)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    std::string pat = "\"key\":\"" + key + "\"";
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        if (!strstr(line, pat.c_str())) continue;
+        double a, b, q, m, w, x = 0;
+        if (read_field(line, "tile_w", &a) && read_field(line, "tile_h", &b) && read_field(line, "queue_depth", &q) &&
+            read_field(line, "min_rays", &m) && read_field(line, "waves_per_simd", &w)) {
+            read_field(line, "ms", &x);
+            *t = rc_tune{(uint32_t)a, (uint32_t)b, (uint32_t)q, (uint32_t)m, (uint32_t)w};
+            *ms = (float)x;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rc_render_batch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,
+                    const rc_point_light* lights, uint32_t n_lights_total, const rc_tune* tune, uint32_t flags)
+{
+    return batch_launch(c, scenes, n_scenes, views, n_views, lights, n_lights_total, tune, flags);
+}
+
+int rc_autotune(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,
+                const rc_point_light* lights, uint32_t n_lights_total, const rc_tune* candidates, uint32_t n_candidates,
+                uint32_t reps, const char* cache_path, rc_tune* best, float* best_ms)
+{
+    if (!c || !best) return RC_ERR_INVALID_ARG;
+    if (reps == 0) reps = 3;
+    RC_HIP(hipSetDevice(c->device));
+    std::string key;
+    if (cache_path) {
+        BatchPlan probe;
+        rc_tune d = {8, 8, 256, 40, 1};
+        int st = plan_batch(scenes, n_scenes, views, n_views, lights, n_lights_total, d, probe);
+        if (st != RC_OK) return st;
+        key = tune_key(c, scenes, n_scenes, views, n_views);
+        float ms = 0.0f;
+        if (cache_lookup(cache_path, key, best, &ms)) {
+            if (best_ms) *best_ms = ms;
+            return RC_OK;
+        }
+    }
+    std::vector<rc_tune> cand;
+    if (candidates && n_candidates) {
+        cand.assign(candidates, candidates + n_candidates);
+    } else {
+        int max_blocks = rc_batch_max_blocks_per_cu(c->device);
+        uint32_t max_wps = (uint32_t)std::max(1, max_blocks * (RC_TRACE_BLOCK / 64) / 4);
+        const uint32_t tiles[3][2] = {{8, 8}, {16, 8}, {16, 16}};
+        const uint32_t depths[3] = {64, 256, 1024};
+        const uint32_t mins[3] = {16, 32, 48};
+        for (auto& tl : tiles)
+            for (uint32_t q : depths)
+                for (uint32_t m : mins)
+                    for (uint32_t w = max_wps; w + 1 >= max_wps && w >= 1; --w) cand.push_back(rc_tune{tl[0], tl[1], q, m, w});
+    }
+    hipEvent_t e0, e1;
+    RC_HIP(hipEventCreate(&e0));
+    RC_HIP(hipEventCreate(&e1));
+    float best_t = INFINITY;
+    int st = RC_OK;
+    for (const rc_tune& t : cand) {
+        std::vector<float> times;
+        for (uint32_t r = 0; r <= reps && st == RC_OK; ++r) {
+            if (hipEventRecord(e0, c->stream) != hipSuccess) { st = RC_ERR_HIP; break; }
+            st = batch_launch(c, scenes, n_scenes, views, n_views, lights, n_lights_total, &t, 0);
+            if (st != RC_OK) break;
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = RC_ERR_HIP; break; }
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) times.push_back(ms);
+        }
+        if (st != RC_OK) break;
+        std::sort(times.begin(), times.end());
+        float med = times[times.size() / 2];
+        if (med < best_t) { best_t = med; *best = t; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != RC_OK) return st;
+    if (best_ms) *best_ms = best_t;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "{\"key\":\"%s\",\"tile_w\":%u,\"tile_h\":%u,\"queue_depth\":%u,\"min_rays\":%u,"
+                       "\"waves_per_simd\":%u,\"ms\":%.4f}\n",
+                    key.c_str(), best->tile_w, best->tile_h, best->queue_depth, best->min_rays, best->waves_per_simd,
+                    best_t);
+            fclose(f);
+        }
     }
     return RC_OK;
 }

@@ -95,6 +95,40 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
                       uint32_t* mask, float* visibility, const TraceWork& w, int grid, hipStream_t st);
 int rc_trace_grid(int device);
 
+// Batched rendering: one persistent launch over many views of several scenes.
+struct DevView {
+    DevCamera cam;
+    uint32_t scene;           // index into the scene table
+    uint32_t light_first;     // index of the first light (6 floats each) in the light table
+    uint32_t n_lights;
+    uint32_t item_first;      // first work item of this view (exclusive prefix over views)
+    uint32_t tiles_x;         // tiles per image row
+    uint32_t pad;
+    float* rgba;
+    uint4* hit;
+    uint32_t* shadow;
+};
+
+struct BatchTune {
+    uint32_t tile_w, tile_h;      // work-item tile in pixels
+    uint32_t queue_depth;         // items a wave claims per atomic (multiple of 64)
+    uint32_t min_rays;            // a wave refills its idle lanes once fewer rays are in flight
+    uint32_t waves_per_simd;      // resident waves per SIMD of the persistent grid
+};
+
+struct BatchParams {
+    const DevScene* scenes;
+    const DevView* views;
+    const float* lights;
+    uint32_t n_views;
+    uint32_t n_items;
+    BatchTune tune;
+    TraceWork w;
+};
+
+void rc_launch_batch(const BatchParams& P, int grid, hipStream_t st);
+int rc_batch_max_blocks_per_cu(int device);
+
 // Launchers (k_shade.hip)
 void rc_launch_shade(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
                      const uint32_t* mask, const float* visibility, float* rgba, float* sample_rgba,

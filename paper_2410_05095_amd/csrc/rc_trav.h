@@ -1,0 +1,239 @@
+// One traversal step of the 4-wide BVH, shared by the single-view kernels and the batched
+// megakernel so that both run exactly the same sequence of tests for a given ray.
+#pragma once
+
+#include "rc_device.h"
+
+#define RC_STACK_EMPTY 0xFFFFFFFEu
+
+// conservative growth of the far slab distance (covers FP32 rounding of the slab tests)
+#define RC_FAR_GROW 1.000001f
+
+struct TravRay {
+    float o[3], d[3], inv[3];
+};
+
+struct TravState {
+    uint32_t cur;       // child word being processed (node index or leaf), or RC_STACK_EMPTY
+    int sp;
+    uint32_t best_id;
+    float best_t, best_u, best_v;
+};
+
+// Per-lane stack: LDS part [depth][block] (lane-interleaved, conflict free) + global overflow.
+template <int SL, int BLOCK, bool HAS_T>
+struct TravStack {
+    uint32_t (*node)[BLOCK];
+    float (*t)[BLOCK];
+    int tid;
+    uint2* overflow;
+    uint32_t overflow_depth, n_lanes, glane;
+    uint32_t* error_flag;
+
+    __device__ inline void push(int& sp, uint32_t w, float tn)
+    {
+        if (sp < SL) {
+            node[sp][tid] = w;
+            if (HAS_T) t[sp][tid] = tn;
+        } else if ((uint32_t)(sp - SL) < overflow_depth) {
+            overflow[(size_t)(sp - SL) * n_lanes + glane] = make_uint2(w, __float_as_uint(tn));
+        } else {
+            *error_flag = 1u;   // bound exceeded: the entry is dropped and the error is reported
+            return;
+        }
+        ++sp;
+    }
+
+    // pop the next entry; closest-hit rays skip entries that start beyond the current hit
+    __device__ inline uint32_t pop(int& sp, bool cull, float best_t)
+    {
+        for (;;) {
+            if (sp == 0) return RC_STACK_EMPTY;
+            --sp;
+            uint32_t w;
+            float tn;
+            if (sp < SL) {
+                w = node[sp][tid];
+                tn = HAS_T ? t[sp][tid] : 0.0f;
+            } else {
+                uint2 g = overflow[(size_t)(sp - SL) * n_lanes + glane];
+                w = g.x;
+                tn = __uint_as_float(g.y);
+            }
+            if (!cull || tn <= best_t) return w;
+        }
+    }
+};
+
+__device__ inline void trav_begin(TravRay& r, TravState& s)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float dd = fabsf(r.d[a]) < 1e-20f ? copysignf(1e-20f, r.d[a]) : r.d[a];
+        r.inv[a] = 1.0f / dd;
+    }
+    s.cur = 0;
+    s.sp = 0;
+    s.best_id = RC_NO_HIT;
+    s.best_t = INFINITY;
+    s.best_u = s.best_v = 0.0f;
+}
+
+// Process s.cur (one internal node, or one leaf) and advance s.cur.  `any`: any-hit ray on the
+// segment 0 < t < 1 (sets `occluded` and ends at the first hit); otherwise closest hit with t > 0.
+// Returns true when the ray has ended.
+template <class Stack>
+__device__ inline bool trav_step(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool any,
+                                 bool& occluded, uint32_t& node_visits, uint32_t& tri_tests)
+{
+    occluded = false;
+    if (!rc_is_leaf(s.cur)) {
+        ++node_visits;
+        const float4* np = reinterpret_cast<const float4*>(sc.nodes + s.cur);
+        float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+        uint4 ch = reinterpret_cast<const uint4*>(np)[6];
+        const float bound = any ? 1.0f : s.best_t;
+        float lxs[4] = {lx.x, lx.y, lx.z, lx.w}, hxs[4] = {hx.x, hx.y, hx.z, hx.w};
+        float lys[4] = {ly.x, ly.y, ly.z, ly.w}, hys[4] = {hy.x, hy.y, hy.z, hy.w};
+        float lzs[4] = {lz.x, lz.y, lz.z, lz.w}, hzs[4] = {hz.x, hz.y, hz.z, hz.w};
+        uint32_t cw[4] = {ch.x, ch.y, ch.z, ch.w};
+        float tn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            float nx = r.inv[0] >= 0.0f ? lxs[c] : hxs[c], fx = r.inv[0] >= 0.0f ? hxs[c] : lxs[c];
+            float ny = r.inv[1] >= 0.0f ? lys[c] : hys[c], fy = r.inv[1] >= 0.0f ? hys[c] : lys[c];
+            float nz = r.inv[2] >= 0.0f ? lzs[c] : hzs[c], fz = r.inv[2] >= 0.0f ? hzs[c] : lzs[c];
+            float t0 = fmaxf(fmaxf((nx - r.o[0]) * r.inv[0], (ny - r.o[1]) * r.inv[1]),
+                             fmaxf((nz - r.o[2]) * r.inv[2], 0.0f));
+            float t1 = fminf(fminf((fx - r.o[0]) * r.inv[0], (fy - r.o[1]) * r.inv[1]), (fz - r.o[2]) * r.inv[2]);
+            bool hit = t0 <= fminf(t1 * RC_FAR_GROW, bound);
+            tn[c] = hit ? t0 : INFINITY;
+        }
+        // sort (distance, child) ascending with five comparators: misses (inf) sink to the end
+#define RC_CS(a, b)                                                                   \
+    {                                                                                 \
+        bool sw = tn[b] < tn[a];                                                      \
+        float ta = sw ? tn[b] : tn[a], tb = sw ? tn[a] : tn[b];                       \
+        uint32_t ca = sw ? cw[b] : cw[a], cb = sw ? cw[a] : cw[b];                    \
+        tn[a] = ta; tn[b] = tb; cw[a] = ca; cw[b] = cb;                               \
+    }
+        RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
+#undef RC_CS
+        if (tn[3] < INFINITY) st.push(s.sp, cw[3], tn[3]);
+        if (tn[2] < INFINITY) st.push(s.sp, cw[2], tn[2]);
+        if (tn[1] < INFINITY) st.push(s.sp, cw[1], tn[1]);
+        s.cur = tn[0] < INFINITY ? cw[0] : st.pop(s.sp, !any, s.best_t);
+    } else {
+        uint32_t first = rc_leaf_first(s.cur), cnt = rc_leaf_count(s.cur);
+        for (uint32_t i = 0; i < cnt; ++i) {
+            ++tri_tests;
+            const float4* tp = sc.tris + 3 * (size_t)(first + i);
+            float4 A = tp[0], B = tp[1], C = tp[2];
+            // Moller-Trumbore in FP32
+            float px_ = r.d[1] * C.z - r.d[2] * C.y;
+            float py_ = r.d[2] * C.x - r.d[0] * C.z;
+            float pz_ = r.d[0] * C.y - r.d[1] * C.x;
+            float det = B.x * px_ + B.y * py_;
+            det = det + B.z * pz_;
+            float idet = __builtin_amdgcn_rcpf(det);
+            float sx = r.o[0] - A.x, sy = r.o[1] - A.y, sz = r.o[2] - A.z;
+            float su = sx * px_ + sy * py_;
+            su = su + sz * pz_;
+            float u = su * idet;
+            float qx = sy * B.z - sz * B.y;
+            float qy = sz * B.x - sx * B.z;
+            float qz = sx * B.y - sy * B.x;
+            float sv = r.d[0] * qx + r.d[1] * qy;
+            sv = sv + r.d[2] * qz;
+            float v = sv * idet;
+            float stq = C.x * qx + C.y * qy;
+            stq = stq + C.z * qz;
+            float t = stq * idet;
+            bool hit = u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f;
+            if (any) {
+                if (hit && t < 1.0f) { occluded = true; break; }
+            } else {
+                uint32_t id = __float_as_uint(A.w);
+                if (hit && (t < s.best_t || (t == s.best_t && id < s.best_id))) {
+                    s.best_t = t; s.best_u = u; s.best_v = v; s.best_id = id;
+                }
+            }
+        }
+        s.cur = occluded ? RC_STACK_EMPTY : st.pop(s.sp, !any, s.best_t);
+    }
+    return s.cur == RC_STACK_EMPTY;
+}
+
+// Shadow-ray target for light index j of a shaded point: a point light, or sample j of the rect
+// light (Philox counter (pixel, j, 1 + stream, 0)).  Sets the ray (origin os, direction target - os)
+// and returns whether it is cast: n . d > 0 and, for the rect light, the light faces the point.
+__device__ inline bool rc_shadow_ray(const float* point_light, const float* rect, const float* nL, bool is_rect,
+                                     uint32_t pixel, uint32_t j, uint32_t stream, uint32_t seed, uint32_t frame,
+                                     const float os[3], const float nf[3], TravRay& r)
+{
+    float tgt[3];
+    if (!is_rect) {
+        tgt[0] = point_light[0]; tgt[1] = point_light[1]; tgt[2] = point_light[2];
+    } else {
+        uint32_t q[4];
+        rc_philox(pixel, j, 1u + stream, 0u, seed, frame, q);
+        float x1 = rc_unit24(q[0]) - 0.5f, x2 = rc_unit24(q[1]) - 0.5f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float t1 = x1 * rect[3 + a];
+            float t2 = x2 * rect[6 + a];
+            tgt[a] = (rect[a] + t1) + t2;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { r.o[a] = os[a]; r.d[a] = tgt[a] - os[a]; }
+    float nd = nf[0] * r.d[0] + nf[1] * r.d[1];
+    nd = nd + nf[2] * r.d[2];
+    bool ok = nd > 0.0f;
+    if (is_rect) {
+        float ld = nL[0] * r.d[0] + nL[1] * r.d[1];
+        ld = ld + nL[2] * r.d[2];
+        ok = ok && ld < 0.0f;
+    }
+    return ok;
+}
+
+// Radiance of one camera sample (FP64), as the shading stage defines it.
+__device__ inline float4 rc_shade_sample(const DevScene& sc, const DevCamera& cam, const float* lights, int n_point,
+                                         const float* rect, double vis, uint32_t pixel, uint32_t k, uint32_t tri,
+                                         uint32_t mask)
+{
+    Surface S = rc_surface(sc, cam, pixel, k, tri);
+    const float* mat = sc.mats + 5 * (size_t)sc.tri_mat[tri];
+    double rgb[3] = {0.0, 0.0, 0.0};
+    for (int l = 0; l < n_point; ++l) {
+        if (!((mask >> l) & 1u)) continue;
+        const float* L = lights + 6 * l;
+        D3 lp = d3(L[0], L[1], L[2]);
+        D3 tl = d3sub(lp, S.p);
+        double d2 = d3dot(tl, tl);
+        D3 wi = d3nrm(tl);
+        double f[3];
+        rc_brdf(S.n, S.wo, wi, mat, f);
+        double cosi = fmax(d3dot(S.n, wi), 0.0);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) rgb[ch] += f[ch] * (double)L[3 + ch] * cosi / d2;
+    }
+    if (rect) {
+        D3 C = d3(rect[0], rect[1], rect[2]);
+        D3 eu = d3(rect[3], rect[4], rect[5]), ev = d3(rect[6], rect[7], rect[8]);
+        D3 nraw = d3cross(eu, ev);
+        double area = sqrt(d3dot(nraw, nraw));
+        D3 nL = d3nrm(nraw);
+        D3 tl = d3sub(C, S.p);
+        double d2 = d3dot(tl, tl);
+        D3 wi = d3nrm(tl);
+        double cosl = fmax(-d3dot(nL, wi), 0.0);
+        double cosi = fmax(d3dot(S.n, wi), 0.0);
+        double f[3];
+        rc_brdf(S.n, S.wo, wi, mat, f);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) rgb[ch] += f[ch] * (double)rect[9 + ch] * area * cosl * cosi / d2 * vis;
+    }
+    return make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], 1.0f);
+}
