@@ -1,0 +1,114 @@
+"""Pins of the FP64 U-Net oracle: library correlation, adjointness, finite differences, Adam closed form,
+bfloat16 rounding against torch's conversion."""
+import numpy as np
+import pytest
+from scipy import signal
+
+from oracle import unet as U
+
+
+def test_parameter_count():
+    assert U.N_PARAMS == 472_993
+    assert U.flat(U.init_params(0)).size == U.N_PARAMS
+
+
+def test_conv3x3_is_zero_padded_correlation():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2, 7, 9, 3))
+    w = rng.normal(size=(4, 3, 3, 3))
+    b = rng.normal(size=4)
+    out = U.conv3x3(x, w, b)
+    for n in range(2):
+        for o in range(4):
+            want = b[o] + sum(signal.correlate2d(x[n, :, :, i], w[o, :, :, i], mode="same", boundary="fill")
+                              for i in range(3))
+            assert np.allclose(out[n, :, :, o], want, atol=1e-12)
+
+
+def test_pool_and_upsample_adjoints():
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(2, 8, 6, 5))
+    g = rng.normal(size=(2, 4, 3, 5))
+    assert np.isclose((U.pool2(x) * g).sum(), (x * U.pool2_backward(g)).sum())
+    y = rng.normal(size=(2, 4, 3, 5))
+    G = rng.normal(size=(2, 8, 6, 5))
+    assert np.isclose((U.up2(y) * G).sum(), (y * U.up2_backward(G)).sum())
+    assert np.allclose(U.pool2(U.up2(y)), y)
+
+
+def _loss(params, x, t, m):
+    y, _ = U.forward(params, x)
+    return U.masked_mse(y, t, m)
+
+
+def test_gradients_match_central_differences():
+    rng = np.random.default_rng(2)
+    p = U.init_params(3)
+    for k in p:                                   # non-zero biases so every bias path is exercised
+        if k.endswith(".b"):
+            p[k] = rng.normal(0, 0.05, p[k].shape)
+    x = rng.uniform(0, 1, (1, 8, 8, 8))
+    t = rng.uniform(0, 1, (1, 8, 8))
+    m = (rng.random((1, 8, 8)) < 0.8).astype(float)
+    y, cache = U.forward(p, x)
+    g, gx = U.backward(p, cache, t, m)
+    h = 1e-6
+    checked = 0
+    for k in U.param_names():
+        flat = p[k].ravel()
+        for idx in rng.choice(flat.size, min(4, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = _loss(p, x, t, m)
+            flat[idx] = old - h
+            lm = _loss(p, x, t, m)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[k].ravel()[idx]
+            assert abs(fd - an) <= 1e-6 * max(abs(fd), abs(an)) + 1e-11, (k, idx, fd, an)
+            checked += 1
+    xf = x.ravel()
+    for idx in rng.choice(xf.size, 10, replace=False):
+        old = xf[idx]
+        xf[idx] = old + h
+        lp = _loss(p, x, t, m)
+        xf[idx] = old - h
+        lm = _loss(p, x, t, m)
+        xf[idx] = old
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - gx.ravel()[idx]) <= 1e-6 * max(abs(fd), 1e-6) + 1e-11
+    assert checked >= 80
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g, bias-corrected moments are exactly g and g^2, so every step moves
+    the weight by lr * g / (|g| + eps)."""
+    p = {"w": np.array([1.0, -2.0, 0.5])}
+    g = {"w": np.array([0.3, -1e-3, 2.0])}
+    st = {}
+    lr = 1e-2
+    for t in range(1, 51):
+        U.adam_step(p, g, st, t, lr)
+    want = np.array([1.0, -2.0, 0.5]) - 50 * lr * g["w"] / (np.abs(g["w"]) + 1e-8)
+    assert np.allclose(p["w"], want, rtol=1e-10, atol=1e-12)
+
+
+def test_bf16_round_ties_even_and_matches_torch():
+    import torch
+    one = 1.0
+    assert U.bf16_round(np.array([one + 2.0 ** -8]))[0] == 1.0
+    assert U.bf16_round(np.array([one + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+    rng = np.random.default_rng(5)
+    x = (rng.normal(size=10000) * np.exp(rng.uniform(-20, 20, 10000))).astype(np.float32)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(U.bf16_round(x), want)
+
+
+def test_forward_bf16_close_to_fp64():
+    rng = np.random.default_rng(6)
+    p = U.init_params(1)
+    x = rng.uniform(0, 1, (1, 16, 16, 8))
+    y64, _ = U.forward(p, x)
+    y16, _ = U.forward(p, x, bf16=True)
+    assert np.abs(y64 - y16).max() < 0.05
+    assert np.abs(y64 - y16).max() > 0
