@@ -257,6 +257,44 @@ int rc_autotune(rc_ctx* ctx, rc_scene* const* scenes, uint32_t n_scenes, const r
                 const rc_point_light* lights, uint32_t n_lights_total, const rc_tune* candidates, uint32_t n_candidates,
                 uint32_t reps, const char* cache_path, rc_tune* best, float* best_ms);
 
+/* ---------------------------------------------------------- denoiser ---- */
+/* A U-Net that maps 1-sample area-light visibility plus G-buffer features to the many-sample
+ * visibility.  Input features: N x H x W x 8 bfloat16 (NHWC, 16-byte aligned): 1-spp visibility,
+ * log depth log(1+t)/log(1+depth_norm), shading normal xyz, albedo rgb; background pixels hold
+ * (1, 1, 0, 0, 0, 0, 0, 0).  H and W must be multiples of 4.  Architecture: two 3x3 conv + ReLU
+ * layers per level with 32/64/128 channels, 2x2 average pooling, nearest 2x upsampling with skip
+ * concatenation, 1x1 head + sigmoid; 472,993 parameters in the order (per layer w[Cout][3][3][Cin],
+ * b[Cout]) e1a e1b e2a e2b bna bnb d2a d2b d1a d1b, head w[32], head b[1].  BF16 weights and
+ * activations with FP32 accumulation on the matrix cores; FP32 master weights and Adam state. */
+typedef struct rc_denoiser rc_denoiser;
+int rc_denoiser_n_params(void);
+/* He-normal initialisation from `seed`, Adam state zero. */
+int rc_denoiser_create(rc_ctx* ctx, uint32_t seed, rc_denoiser** out);
+int rc_denoiser_destroy(rc_ctx* ctx, rc_denoiser* den);
+/* Host copies (rc_denoiser_n_params() floats) of the FP32 parameters / the gradients of the last
+ * training step; set_params also resets the Adam state.  Synchronous. */
+int rc_denoiser_get_params(rc_ctx* ctx, const rc_denoiser* den, float* out);
+int rc_denoiser_set_params(rc_ctx* ctx, rc_denoiser* den, const float* in);
+int rc_denoiser_get_grads(rc_ctx* ctx, const rc_denoiser* den, float* out);
+/* d_out: N*H*W float visibility in (0, 1). */
+int rc_denoiser_infer(rc_ctx* ctx, rc_denoiser* den, const uint16_t* d_features, uint32_t n, uint32_t h, uint32_t w,
+                      float* d_out);
+/* One Adam step (beta 0.9/0.999, eps 1e-8, bias-corrected) on the loss
+ * sum(mask (y - target)^2) / max(sum(mask), 1); d_target and d_mask are N*H*W floats.  *loss_out
+ * (optional, synchronises) receives the loss before the step. */
+int rc_denoiser_train_step(rc_ctx* ctx, rc_denoiser* den, const uint16_t* d_features, const float* d_target,
+                           const float* d_mask, uint32_t n, uint32_t h, uint32_t w, float lr, float* loss_out);
+/* Checkpoint: header (magic, version, parameter count, step), FP32 weights, Adam m and v, CRC-32.
+ * load rejects any mismatch with RC_ERR_BAD_CHECKPOINT and leaves the denoiser unchanged; the
+ * caller then falls back to the plain many-sample shadow path. */
+int rc_denoiser_save(rc_ctx* ctx, const rc_denoiser* den, const char* path);
+int rc_denoiser_load(rc_ctx* ctx, rc_denoiser* den, const char* path);
+
+/* Denoiser input features of a 1-sample-per-pixel render (d_hit and d_visibility as written by
+ * rc_render with a rect light) into d_features (W*H*8 bfloat16). */
+int rc_pack_features(rc_ctx* ctx, rc_scene* scene, const rc_camera* cam, const uint32_t* d_hit,
+                     const float* d_visibility, float depth_norm, uint16_t* d_features);
+
 #ifdef __cplusplus
 }
 #endif

@@ -122,8 +122,13 @@ def masked_mse(y, target, mask):
     return float((m * (y - target) ** 2).sum() / max(m.sum(), 1.0))
 
 
-def backward(params: dict, cache: dict, target, mask):
-    """Gradient of masked_mse w.r.t. every parameter (a dict like params) and the input features."""
+def backward(params: dict, cache: dict, target, mask, bf16_grads: bool = False):
+    """Gradient of masked_mse w.r.t. every parameter (a dict like params) and the input features.
+
+    With bf16_grads=True the activation gradients are rounded to bfloat16 where a BF16 pipeline
+    stores them: the head's gradient into the last ReLU, every convolution's input gradient, the
+    gradient of each upsampled tensor, and each pooled gradient plus its skip gradient."""
+    rd = bf16_round if bf16_grads else (lambda a: a)
     P = cache["P"]
     y = cache["y"]
     m = np.asarray(mask, np.float64)
@@ -133,26 +138,26 @@ def backward(params: dict, cache: dict, target, mask):
     d1 = cache["d1_b"]
     g["head.w"] = np.tensordot(dlogit, d1, axes=([0, 1, 2], [0, 1, 2]))
     g["head.b"] = np.array([dlogit.sum()])
-    gd1 = dlogit[..., None] * P["head.w"]
+    gd1 = rd(dlogit[..., None] * P["head.w"])
 
     def block_back(name_a, name_b, tag, gout):
         a, b, inp = cache[tag + "_a"], cache[tag + "_b"], cache[tag + "_in"]
         gpre = gout * (b > 0)
         ga, g[name_b + ".w"], g[name_b + ".b"] = conv3x3_backward(a, P[name_b + ".w"], gpre)
-        gpre = ga * (a > 0)
+        gpre = rd(ga) * (a > 0)
         gin, g[name_a + ".w"], g[name_a + ".b"] = conv3x3_backward(inp, P[name_a + ".w"], gpre)
-        return gin
+        return rd(gin)
 
     gu1 = block_back("d1a", "d1b", "d1", gd1)
-    gd2 = up2_backward(gu1[..., :64])
+    gd2 = rd(up2_backward(gu1[..., :64]))
     ge1_skip = gu1[..., 64:]
     gu2 = block_back("d2a", "d2b", "d2", gd2)
-    gbn = up2_backward(gu2[..., :128])
+    gbn = rd(up2_backward(gu2[..., :128]))
     ge2_skip = gu2[..., 128:]
     gp2 = block_back("bna", "bnb", "bn", gbn)
-    ge2 = pool2_backward(gp2) + ge2_skip
+    ge2 = rd(pool2_backward(gp2) + ge2_skip)
     gp1 = block_back("e2a", "e2b", "e2", ge2)
-    ge1 = pool2_backward(gp1) + ge1_skip
+    ge1 = rd(pool2_backward(gp1) + ge1_skip)
     gx = block_back("e1a", "e1b", "e1", ge1)
     return g, gx
 

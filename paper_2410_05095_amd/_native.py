@@ -108,6 +108,18 @@ SIGNATURES = {
     "rc_get_stage_times": (C.c_int, [P, C.POINTER(RcStageTimes)]),
     "rc_camera_rays": (C.c_int, [P, C.POINTER(RcCamera), P, P]),
     "rc_scene_get_positions": (C.c_int, [P, P, P]),
+    "rc_denoiser_n_params": (C.c_int, []),
+    "rc_denoiser_create": (C.c_int, [P, C.c_uint32, PP]),
+    "rc_denoiser_destroy": (C.c_int, [P, P]),
+    "rc_denoiser_get_params": (C.c_int, [P, P, P]),
+    "rc_denoiser_set_params": (C.c_int, [P, P, P]),
+    "rc_denoiser_get_grads": (C.c_int, [P, P, P]),
+    "rc_denoiser_infer": (C.c_int, [P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
+    "rc_denoiser_train_step": (C.c_int, [P, P, P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_float,
+                                         C.POINTER(C.c_float)]),
+    "rc_denoiser_save": (C.c_int, [P, P, C.c_char_p]),
+    "rc_denoiser_load": (C.c_int, [P, P, C.c_char_p]),
+    "rc_pack_features": (C.c_int, [P, P, C.POINTER(RcCamera), P, P, C.c_float, P]),
     "rc_render_batch": (C.c_int, [P, P, C.c_uint32, C.POINTER(RcView), C.c_uint32, C.POINTER(RcPointLight),
                                   C.c_uint32, C.POINTER(RcTune), C.c_uint32]),
     "rc_autotune": (C.c_int, [P, P, C.c_uint32, C.POINTER(RcView), C.c_uint32, C.POINTER(RcPointLight), C.c_uint32,
@@ -388,3 +400,88 @@ class Scene:
         order = np.zeros(self.n_tris, np.uint32)
         check(lib().rc_bvh_export(self.ctx.h, self.h, _ptr(nodes), _ptr(order)), "rc_bvh_export")
         return nodes, order
+
+
+class Denoiser:
+    """The U-Net shadow denoiser of the library (BF16 MFMA kernels, FP32 master weights, Adam)."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        self.ctx = ctx
+        self.n_params = int(lib().rc_denoiser_n_params())
+        ctx._sync_stream()
+        h = C.c_void_p()
+        check(lib().rc_denoiser_create(ctx.h, int(seed), C.byref(h)), "rc_denoiser_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            lib().rc_denoiser_destroy(self.ctx.h, self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        check(lib().rc_denoiser_get_params(self.ctx.h, self.h, _ptr(out)), "rc_denoiser_get_params")
+        return out
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.size == self.n_params
+        self.ctx._sync_stream()
+        check(lib().rc_denoiser_set_params(self.ctx.h, self.h, _ptr(p)), "rc_denoiser_set_params")
+
+    def grads(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        check(lib().rc_denoiser_get_grads(self.ctx.h, self.h, _ptr(out)), "rc_denoiser_get_grads")
+        return out
+
+    def infer(self, feat, out=None):
+        """feat: (N, H, W, 8) torch.bfloat16 on the GPU -> (N, H, W) float32."""
+        torch = self.ctx.torch
+        assert feat.dtype == torch.bfloat16 and feat.is_contiguous() and feat.shape[-1] == 8
+        n, h, w = (int(x) for x in feat.shape[:3])
+        if out is None:
+            out = torch.empty((n, h, w), dtype=torch.float32, device=feat.device)
+        self.ctx._sync_stream()
+        check(lib().rc_denoiser_infer(self.ctx.h, self.h, C.c_void_p(feat.data_ptr()), n, h, w,
+                                      C.c_void_p(out.data_ptr())), "rc_denoiser_infer")
+        return out
+
+    def train_step(self, feat, target, mask, lr: float, want_loss: bool = True):
+        torch = self.ctx.torch
+        assert feat.dtype == torch.bfloat16 and feat.is_contiguous()
+        assert target.dtype == torch.float32 and mask.dtype == torch.float32
+        n, h, w = (int(x) for x in feat.shape[:3])
+        loss = C.c_float(float("nan"))
+        self.ctx._sync_stream()
+        check(lib().rc_denoiser_train_step(self.ctx.h, self.h, C.c_void_p(feat.data_ptr()),
+                                           C.c_void_p(target.data_ptr()), C.c_void_p(mask.data_ptr()), n, h, w,
+                                           float(lr), C.byref(loss) if want_loss else None),
+              "rc_denoiser_train_step")
+        return float(loss.value)
+
+    def save(self, path: str):
+        check(lib().rc_denoiser_save(self.ctx.h, self.h, path.encode()), "rc_denoiser_save")
+
+    def load(self, path: str):
+        self.ctx._sync_stream()
+        check(lib().rc_denoiser_load(self.ctx.h, self.h, path.encode()), "rc_denoiser_load")
+
+
+def pack_features(ctx: Context, scene: Scene, cam, out: dict, depth_norm: float, feat=None):
+    """Denoiser features (H, W, 8) bfloat16 from a 1-spp rect-light render `out`."""
+    torch = ctx.torch
+    H, W = int(cam.height), int(cam.width)
+    if feat is None:
+        feat = torch.empty((H, W, 8), dtype=torch.bfloat16, device=out["hit"].device)
+    camc = camera_struct(cam)
+    ctx._sync_stream()
+    check(lib().rc_pack_features(ctx.h, scene.h, C.byref(camc), C.c_void_p(out["hit"].data_ptr()),
+                                 C.c_void_p(out["visibility"].data_ptr()), float(depth_norm),
+                                 C.c_void_p(feat.data_ptr())), "rc_pack_features")
+    return feat

@@ -126,6 +126,37 @@ __global__ __launch_bounds__(256) void k_camera_rays(DevCamera cam, float* o, fl
     for (int a = 0; a < 3; ++a) { o[3 * (size_t)s + a] = of[a]; d[3 * (size_t)s + a] = df[a]; }
 }
 
+__device__ inline uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+// denoiser features per pixel: 1-spp visibility, log depth, normal, albedo (background: 1, 1, 0...)
+__global__ __launch_bounds__(256) void k_pack_features(DevScene sc, DevCamera cam, const uint4* gbuf, const float* vis,
+                                                       float inv_log_norm, uint16_t* feat)
+{
+    uint32_t pixel = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pixel >= (uint32_t)(cam.width * cam.height)) return;
+    uint4 h = gbuf[pixel];
+    float f[8] = {1.0f, 1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (h.x != RC_NO_HIT) {
+        Surface S = rc_surface(sc, cam, pixel, 0, h.x);
+        const float* mat = sc.mats + 5 * (size_t)sc.tri_mat[h.x];
+        f[0] = vis[pixel];
+        f[1] = log1pf(__uint_as_float(h.y)) * inv_log_norm;
+        f[2] = (float)S.n.x; f[3] = (float)S.n.y; f[4] = (float)S.n.z;
+        f[5] = mat[0]; f[6] = mat[1]; f[7] = mat[2];
+    }
+    uint4 o;
+    o.x = (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
+    o.y = (uint32_t)f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
+    o.z = (uint32_t)f2bf(f[4]) | ((uint32_t)f2bf(f[5]) << 16);
+    o.w = (uint32_t)f2bf(f[6]) | ((uint32_t)f2bf(f[7]) << 16);
+    reinterpret_cast<uint4*>(feat)[pixel] = o;
+}
+
 inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -143,6 +174,13 @@ void rc_launch_camera_rays(const DevCamera& cam, float* o, float* d, uint32_t n,
 {
     if (n == 0) return;
     hipLaunchKernelGGL(k_camera_rays, dim3(blocks(n, 256)), dim3(256), 0, st, cam, o, d, n);
+}
+
+void rc_launch_pack_features(const DevScene& sc, const DevCamera& cam, const uint4* gbuf, const float* vis,
+                             float inv_log_norm, uint16_t* feat, hipStream_t st)
+{
+    size_t n = (size_t)cam.width * cam.height;
+    hipLaunchKernelGGL(k_pack_features, dim3(blocks(n, 256)), dim3(256), 0, st, sc, cam, gbuf, vis, inv_log_norm, feat);
 }
 
 void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris, float4* tris,

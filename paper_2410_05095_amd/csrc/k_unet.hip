@@ -1,0 +1,443 @@
+// U-Net shadow-denoiser kernels for gfx950: BF16 storage, FP32 accumulation.
+//
+// 3x3 convolutions are implicit GEMMs on the matrix cores (v_mfma_f32_16x16x32_bf16):
+//   forward      out[p][co] = sum_{tap,ci} in[p + off(tap)][ci] * W[co][tap][ci]     (M = pixels, N = Cout)
+//   input grad   gin[p][ci] = sum_{tap,co} g[p - off(tap)][co] * W[co][tap][ci]      = the forward kernel
+//                with the flipped, transposed weights Wf[ci][8 - tap][co]
+//   weight grad  dW[co][tap][ci] = sum_p g[p][co] * in[p + off(tap)][ci]            (K = pixels, split over
+//                chunks; the per-chunk partials are summed in chunk order, so the result is deterministic)
+// Tensors are NHWC; every reduction (bias, head, loss) is a fixed-order two-stage sum.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rc_unet.h"
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ inline uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline bf16x8 load8(const uint16_t* p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p)); }
+
+// ---------------------------------------------------------------- 3x3 convolution
+// Each wave computes 32 pixels (two 16-row MFMA tiles) x 16*NT output channels; a block has 4 waves.
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int P = a.N * a.H * a.W;
+    const int p0 = (blockIdx.x * 4 + wave) * 32;
+    if (p0 >= P) return;
+    const int K = 9 * a.Cin;
+    const int r = lane & 15, g = lane >> 4;
+    int ny[2], yy[2], xx[2];
+    bool pv[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        int p = p0 + 16 * mt + r;
+        pv[mt] = p < P;
+        int q = pv[mt] ? p : 0;
+        xx[mt] = q % a.W;
+        int t = q / a.W;
+        yy[mt] = t % a.H;
+        ny[mt] = t / a.H;
+    }
+    f32x4 acc[2][NT];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const int kk = k0 + 8 * g;
+        const bool kv = kk < K;
+        const int tap = kv ? kk / a.Cin : 0;
+        const int ci = kk - tap * a.Cin;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        bf16x8 A[2], B[NT];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            int y = yy[mt] + dy, x = xx[mt] + dx;
+            bool ok = pv[mt] && kv && y >= 0 && y < a.H && x >= 0 && x < a.W;
+            A[mt] = ok ? load8(a.in + ((size_t)(ny[mt] * a.H + y) * a.W + x) * a.Cin + ci) : zero;
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            int co = 16 * nt + r;
+            B[nt] = (kv && co < a.Cout) ? load8(a.wt + (size_t)co * K + kk) : zero;
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+    }
+    // D layout: lane holds column (channel) 16 nt + (lane & 15), rows (pixels) 4 (lane >> 4) + i
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            int co = 16 * nt + r;
+            if (co >= a.Cout) continue;
+            float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int p = p0 + 16 * mt + 4 * g + i;
+                if (p >= P) continue;
+                float v = acc[mt][nt][i] + b;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                size_t o = (size_t)p * a.Cout + co;
+                if (a.mask && !(bf2f(a.mask[o]) > 0.0f)) v = 0.0f;
+                a.out[o] = f2bf(v);
+            }
+        }
+}
+
+// ---------------------------------------------------------------- weight gradient
+// One wave per (pixel chunk, tap, 16-channel output tile, 16-channel input tile).
+__global__ __launch_bounds__(64) void k_wgrad(WgradArgs a)
+{
+    const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+    const int P = a.N * a.H * a.W;
+    const int chunk = blockIdx.x, tap = blockIdx.y;
+    const int ci_tiles = (a.Cin + 15) / 16;
+    const int co_t = blockIdx.z / ci_tiles, ci_t = blockIdx.z % ci_tiles;
+    const int co = co_t * 16 + r, ci = ci_t * 16 + r;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int pb0 = chunk * a.chunk, pe = min(P, pb0 + a.chunk);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int pb = pb0; pb < pe; pb += 32) {
+        uint16_t av[8], bv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int p = pb + 8 * g + e;
+            av[e] = 0;
+            bv[e] = 0;
+            if (p < pe) {
+                av[e] = a.g[(size_t)p * a.Cout + co];
+                int x = p % a.W, t = p / a.W, y = t % a.H, n = t / a.H;
+                int ys = y + dy, xs = x + dx;
+                if (ci < a.Cin && ys >= 0 && ys < a.H && xs >= 0 && xs < a.W)
+                    bv[e] = a.x[((size_t)(n * a.H + ys) * a.W + xs) * a.Cin + ci];
+            }
+        }
+        uint4 ua, ub;
+        ua.x = av[0] | ((uint32_t)av[1] << 16); ua.y = av[2] | ((uint32_t)av[3] << 16);
+        ua.z = av[4] | ((uint32_t)av[5] << 16); ua.w = av[6] | ((uint32_t)av[7] << 16);
+        ub.x = bv[0] | ((uint32_t)bv[1] << 16); ub.y = bv[2] | ((uint32_t)bv[3] << 16);
+        ub.z = bv[4] | ((uint32_t)bv[5] << 16); ub.w = bv[6] | ((uint32_t)bv[7] << 16);
+        bf16x8 A = __builtin_bit_cast(bf16x8, ua);
+        bf16x8 B = __builtin_bit_cast(bf16x8, ub);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc, 0, 0, 0);
+    }
+    // D[i = output channel][j = input channel]: lane holds j = lane & 15, rows 4 (lane >> 4) + i
+    int cio = ci_t * 16 + r;
+    if (cio >= a.Cin) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int coo = co_t * 16 + 4 * g + i;
+        a.partial[(((size_t)chunk * a.Cout + coo) * 9 + tap) * a.Cin + cio] = acc[i];
+    }
+}
+
+// out[i] (+)= sum over chunks c in order of partial[c][i]
+__global__ __launch_bounds__(256) void k_reduce_chunks(const float* partial, int n_chunks, int n, float* out, int add)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int c = 0; c < n_chunks; ++c) s += partial[(size_t)c * n + i];
+    out[i] = add ? out[i] + s : s;
+}
+
+// per-chunk column sums of a bf16 [P][C] tensor: partial[chunk][c]; fixed order within a chunk
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t* g, int P, int C, int chunk, float* partial)
+{
+    int c = blockIdx.y * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    int p0 = blockIdx.x * chunk, pe = min(P, p0 + chunk);
+    float s = 0.0f;
+    for (int p = p0; p < pe; ++p) s += bf2f(g[(size_t)p * C + c]);
+    partial[(size_t)blockIdx.x * C + c] = s;
+}
+
+// ---------------------------------------------------------------- pooling / upsampling / concat
+__global__ __launch_bounds__(256) void k_pool2(const uint16_t* in, int N, int H, int W, int C, uint16_t* out)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int h = H / 2, w = W / 2;
+    size_t total = (size_t)N * h * w * C;
+    if (i >= total) return;
+    int c = (int)(i % C);
+    size_t q = i / C;
+    int x = (int)(q % w), t = (int)(q / w), y = t % h, n = t / h;
+    const uint16_t* b = in + (((size_t)n * H + 2 * y) * W + 2 * x) * C + c;
+    float s = (bf2f(b[0]) + bf2f(b[C])) + (bf2f(b[(size_t)W * C]) + bf2f(b[(size_t)W * C + C]));
+    out[i] = f2bf(s * 0.25f);
+}
+
+// out[N,2h,2w,Ca+Cs] = [nearest-upsampled a (Ca channels), skip (Cs channels)]
+__global__ __launch_bounds__(256) void k_up2_concat(const uint16_t* a, const uint16_t* skip, int N, int H, int W,
+                                                    int Ca, int Cs, uint16_t* out)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int C = Ca + Cs;
+    size_t total = (size_t)N * H * W * C;
+    if (i >= total) return;
+    int c = (int)(i % C);
+    size_t q = i / C;
+    int x = (int)(q % W), t = (int)(q / W), y = t % H, n = t / H;
+    if (c < Ca) out[i] = a[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * Ca + c];
+    else out[i] = skip[q * Cs + (c - Ca)];
+}
+
+// gradient of the upsampled part of a concat: out[n,y,x,c] = mask * sum_{2x2} g[n,2y+a,2x+b, c0 + c]
+__global__ __launch_bounds__(256) void k_up_back_mask(const uint16_t* g, int N, int H2, int W2, int Ctot, int c0,
+                                                      int C, const uint16_t* mask, uint16_t* out)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int h = H2 / 2, w = W2 / 2;
+    size_t total = (size_t)N * h * w * C;
+    if (i >= total) return;
+    int c = (int)(i % C);
+    size_t q = i / C;
+    int x = (int)(q % w), t = (int)(q / w), y = t % h, n = t / h;
+    const uint16_t* b = g + (((size_t)n * H2 + 2 * y) * W2 + 2 * x) * Ctot + c0 + c;
+    float s = (bf2f(b[0]) + bf2f(b[Ctot])) + (bf2f(b[(size_t)W2 * Ctot]) + bf2f(b[(size_t)W2 * Ctot + Ctot]));
+    if (!(bf2f(mask[i]) > 0.0f)) s = 0.0f;
+    out[i] = f2bf(s);
+}
+
+// out[n,y,x,c] = mask * (gpool[n,y/2,x/2,c] / 4 + gcat[n,y,x,c0 + c])
+__global__ __launch_bounds__(256) void k_pool_back_add_mask(const uint16_t* gpool, const uint16_t* gcat, int N, int H,
+                                                            int W, int C, int Ctot, int c0, const uint16_t* mask,
+                                                            uint16_t* out)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t total = (size_t)N * H * W * C;
+    if (i >= total) return;
+    int c = (int)(i % C);
+    size_t q = i / C;
+    int x = (int)(q % W), t = (int)(q / W), y = t % H, n = t / H;
+    float v = bf2f(gpool[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]) * 0.25f;
+    v = v + bf2f(gcat[q * Ctot + c0 + c]);
+    if (!(bf2f(mask[i]) > 0.0f)) v = 0.0f;
+    out[i] = f2bf(v);
+}
+
+// ---------------------------------------------------------------- head, loss
+// y = sigmoid(sum_c d1[p][c] wh[c] + bh), wh rounded to BF16 like every weight, bh in FP32 like every bias
+__global__ __launch_bounds__(256) void k_head(const uint16_t* d1, const float* wh, const float* bh, int P, float* y)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float s = 0.0f;
+    const uint16_t* row = d1 + (size_t)p * 32;
+    for (int c = 0; c < 32; ++c) s += bf2f(row[c]) * bf2f(f2bf(wh[c]));
+    s += bh[0];
+    y[p] = 1.0f / (1.0f + expf(-s));
+}
+
+// per-chunk sums of mask and mask * (y - t)^2
+__global__ __launch_bounds__(256) void k_loss_partials(const float* y, const float* t, const float* m, int P, int chunk,
+                                                       float* partial)
+{
+    __shared__ float sm[256], sl[256];
+    int p0 = blockIdx.x * chunk, pe = min(P, p0 + chunk);
+    float a = 0.0f, b = 0.0f;
+    for (int p = p0 + threadIdx.x; p < pe; p += blockDim.x) {
+        float d = y[p] - t[p];
+        a += m[p];
+        b += m[p] * d * d;
+    }
+    sm[threadIdx.x] = a;
+    sl[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) { sm[threadIdx.x] += sm[threadIdx.x + s]; sl[threadIdx.x] += sl[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { partial[2 * blockIdx.x] = sm[0]; partial[2 * blockIdx.x + 1] = sl[0]; }
+}
+
+// sums[0] = sum mask, sums[1] = loss = sum m (y-t)^2 / max(sum m, 1)
+__global__ void k_loss_final(const float* partial, int n, float* sums)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float a = 0.0f, b = 0.0f;
+    for (int i = 0; i < n; ++i) { a += partial[2 * i]; b += partial[2 * i + 1]; }
+    sums[0] = a;
+    sums[1] = b / fmaxf(a, 1.0f);
+}
+
+// dlogit = 2 m (y - t) / max(sum m, 1) * y (1 - y); gpre_d1 = mask(d1 > 0) * dlogit * wh; per-chunk partial
+// head gradients (32 weights + bias) in fixed order
+__global__ __launch_bounds__(64) void k_head_back(const uint16_t* d1, const float* y, const float* t, const float* m,
+                                                  const float* sums, const float* wh, int P, int chunk,
+                                                  uint16_t* gpre, float* partial)
+{
+    const int c = threadIdx.x;   // 0..31 weights, 32 bias
+    int p0 = blockIdx.x * chunk, pe = min(P, p0 + chunk);
+    float inv = 2.0f / fmaxf(sums[0], 1.0f);
+    float whc = c < 32 ? bf2f(f2bf(wh[c])) : 0.0f;
+    float acc = 0.0f;
+    for (int p = p0; p < pe; ++p) {
+        float yy = y[p];
+        float dl = m[p] * (yy - t[p]) * inv * yy * (1.0f - yy);
+        if (c < 32) {
+            float a = bf2f(d1[(size_t)p * 32 + c]);
+            acc += dl * a;
+            gpre[(size_t)p * 32 + c] = f2bf(a > 0.0f ? dl * whc : 0.0f);
+        } else if (c == 32) {
+            acc += dl;
+        }
+    }
+    if (c < 33) partial[(size_t)blockIdx.x * 33 + c] = acc;
+}
+
+// ---------------------------------------------------------------- weights, Adam, features
+// FP32 master [Cout][9][Cin] -> BF16 copies: forward layout and flipped/transposed Wf[ci][8 - tap][co]
+__global__ __launch_bounds__(256) void k_weights_bf16(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t* wb)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = Cout * 9 * Cin;
+    if (i >= n) return;
+    int ci = i % Cin, tap = (i / Cin) % 9, co = i / (9 * Cin);
+    uint16_t v = f2bf(w[i]);
+    wf[i] = v;
+    if (wb) wb[((size_t)ci * 9 + (8 - tap)) * Cout + co] = v;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1,
+                                              float b2, float eps, float c1, float c2)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.0f - b1) * gi;
+    float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float mh = mi / c1, vh = vi / c2;
+    w[i] = w[i] - lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_fill_f32(float* p, float v, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned nb(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void unet_conv3x3(const ConvArgs& a, hipStream_t st)
+{
+    size_t P = (size_t)a.N * a.H * a.W;
+    dim3 grid(nb(P, 128)), block(256);
+    int nt = (a.Cout + 15) / 16;
+    switch (nt) {
+    case 1: hipLaunchKernelGGL(k_conv3x3<1>, grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_conv3x3<2>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_conv3x3<4>, grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL(k_conv3x3<6>, grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL(k_conv3x3<8>, grid, block, 0, st, a); break;
+    case 12: hipLaunchKernelGGL(k_conv3x3<12>, grid, block, 0, st, a); break;
+    default: break;   // channel counts of this network only
+    }
+}
+
+int unet_wgrad_chunks(size_t P, int chunk) { return (int)((P + chunk - 1) / chunk); }
+
+void unet_wgrad(const WgradArgs& a, hipStream_t st)
+{
+    size_t P = (size_t)a.N * a.H * a.W;
+    int chunks = unet_wgrad_chunks(P, a.chunk);
+    dim3 grid(chunks, 9, (a.Cout / 16) * ((a.Cin + 15) / 16));
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(64), 0, st, a);
+}
+
+void unet_reduce_chunks(const float* partial, int n_chunks, int n, float* out, int add, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nb(n, 256)), dim3(256), 0, st, partial, n_chunks, n, out, add);
+}
+
+void unet_colsum(const uint16_t* g, int P, int C, int chunk, float* partial, hipStream_t st)
+{
+    int chunks = (P + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_colsum, dim3(chunks, nb(C, 256)), dim3(256), 0, st, g, P, C, chunk, partial);
+}
+
+void unet_pool2(const uint16_t* in, int N, int H, int W, int C, uint16_t* out, hipStream_t st)
+{
+    size_t n = (size_t)N * (H / 2) * (W / 2) * C;
+    hipLaunchKernelGGL(k_pool2, dim3(nb(n, 256)), dim3(256), 0, st, in, N, H, W, C, out);
+}
+
+void unet_up2_concat(const uint16_t* a, const uint16_t* skip, int N, int H, int W, int Ca, int Cs, uint16_t* out,
+                     hipStream_t st)
+{
+    size_t n = (size_t)N * H * W * (Ca + Cs);
+    hipLaunchKernelGGL(k_up2_concat, dim3(nb(n, 256)), dim3(256), 0, st, a, skip, N, H, W, Ca, Cs, out);
+}
+
+void unet_up_back_mask(const uint16_t* g, int N, int H2, int W2, int Ctot, int c0, int C, const uint16_t* mask,
+                       uint16_t* out, hipStream_t st)
+{
+    size_t n = (size_t)N * (H2 / 2) * (W2 / 2) * C;
+    hipLaunchKernelGGL(k_up_back_mask, dim3(nb(n, 256)), dim3(256), 0, st, g, N, H2, W2, Ctot, c0, C, mask, out);
+}
+
+void unet_pool_back_add_mask(const uint16_t* gpool, const uint16_t* gcat, int N, int H, int W, int C, int Ctot, int c0,
+                             const uint16_t* mask, uint16_t* out, hipStream_t st)
+{
+    size_t n = (size_t)N * H * W * C;
+    hipLaunchKernelGGL(k_pool_back_add_mask, dim3(nb(n, 256)), dim3(256), 0, st, gpool, gcat, N, H, W, C, Ctot, c0,
+                       mask, out);
+}
+
+void unet_head(const uint16_t* d1, const float* wh, const float* bh, int P, float* y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_head, dim3(nb(P, 256)), dim3(256), 0, st, d1, wh, bh, P, y);
+}
+
+void unet_loss(const float* y, const float* t, const float* m, int P, int chunk, float* partial, float* sums,
+               hipStream_t st)
+{
+    int chunks = (P + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_loss_partials, dim3(chunks), dim3(256), 0, st, y, t, m, P, chunk, partial);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, partial, chunks, sums);
+}
+
+void unet_head_back(const uint16_t* d1, const float* y, const float* t, const float* m, const float* sums,
+                    const float* wh, int P, int chunk, uint16_t* gpre, float* partial, hipStream_t st)
+{
+    int chunks = (P + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_head_back, dim3(chunks), dim3(64), 0, st, d1, y, t, m, sums, wh, P, chunk, gpre, partial);
+}
+
+void unet_weights_bf16(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t* wb, hipStream_t st)
+{
+    int n = Cout * 9 * Cin;
+    hipLaunchKernelGGL(k_weights_bf16, dim3(nb(n, 256)), dim3(256), 0, st, w, Cout, Cin, wf, wb);
+}
+
+void unet_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps, float c1,
+               float c2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adam, dim3(nb(n, 256)), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+void unet_fill_f32(float* p, float v, size_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_f32, dim3(nb(n, 256)), dim3(256), 0, st, p, v, n);
+}

@@ -13,53 +13,7 @@
 
 #include "../../include/raycast.h"
 #include "rc_internal.h"
-
-struct rc_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int grid = 0;                         // persistent traversal grid (blocks)
-    uint32_t* d_counters = nullptr;       // [0..7] work queues, [8] error flag
-    unsigned long long* d_rays = nullptr; // [0] primary, [1] shadow rays cast
-    uint32_t* d_overflow = nullptr;
-    size_t overflow_words = 0;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    bool timed = false;
-    bool timed_batch = false;
-    int sticky = RC_OK;
-    // batched rendering: device table, pinned staging copy, captured graph
-    uint8_t* d_table = nullptr;
-    uint8_t* h_table = nullptr;
-    size_t table_cap = 0;
-    hipEvent_t ev_staging = nullptr;
-    bool staging_pending = false;
-    hipStream_t capture_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    uint64_t graph_key = 0;
-};
-
-struct rc_scene {
-    std::vector<float> pos;
-    std::vector<uint32_t> idx, tri_mat, body_vr;
-    std::vector<float> mats;
-    uint32_t nv = 0, nt = 0, nm = 0, nb = 0, max_body_verts = 0;
-    float* d_pos = nullptr;
-    float* d_rest = nullptr;
-    uint32_t* d_idx = nullptr;
-    uint32_t* d_tri_mat = nullptr;
-    float* d_mats = nullptr;
-    uint32_t* d_body_vr = nullptr;
-    bool host_pos_stale = false;
-    // BVH
-    bool built = false;
-    HostBvh hb;
-    Node4* d_nodes = nullptr;
-    uint32_t* d_order = nullptr;
-    float4* d_tris = nullptr;
-    double build_ms = 0.0;
-    float scale = 1.0f;
-    bool sah_stale = false;   // boxes refit on the device since the host copy was made
-};
+#include "rc_objects.h"
 
 namespace {
 
@@ -518,6 +472,23 @@ int rc_camera_rays(rc_ctx* c, const rc_camera* cam, float* d_o, float* d_d)
     RC_HIP(hipSetDevice(c->device));
     DevCamera dc = make_camera(cam);
     rc_launch_camera_rays(dc, d_o, d_d, (uint32_t)(cam->width * cam->height * cam->ssaa * cam->ssaa), c->stream);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+int rc_pack_features(rc_ctx* c, rc_scene* s, const rc_camera* cam, const uint32_t* d_hit, const float* d_vis,
+                     float depth_norm, uint16_t* d_feat)
+{
+    if (!c || !s || !cam || !d_hit || !d_vis || !d_feat) return RC_ERR_INVALID_ARG;
+    if (cam->width <= 0 || cam->height <= 0 || (int64_t)cam->width * cam->height > (1ll << 28)) return RC_ERR_INVALID_ARG;
+    if (cam->ssaa != 1) return RC_ERR_UNSUPPORTED;
+    if (!(depth_norm > 0.0f) || !isfinite(depth_norm)) return RC_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_hit) | reinterpret_cast<uintptr_t>(d_feat)) & 15u) return RC_ERR_INVALID_ARG;
+    RC_HIP(hipSetDevice(c->device));
+    DevCamera dc = make_camera(cam);
+    DevScene ds = dev_scene(s);
+    rc_launch_pack_features(ds, dc, reinterpret_cast<const uint4*>(d_hit), d_vis, (float)(1.0 / log1p((double)depth_norm)),
+                            d_feat, c->stream);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

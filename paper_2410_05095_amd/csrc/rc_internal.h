@@ -134,6 +134,8 @@ void rc_launch_shade(const DevScene& sc, const DevCamera& cam, const DevLights& 
                      const uint32_t* mask, const float* visibility, float* rgba, float* sample_rgba,
                      hipStream_t st);
 void rc_launch_camera_rays(const DevCamera& cam, float* o, float* d, uint32_t n, hipStream_t st);
+void rc_launch_pack_features(const DevScene& sc, const DevCamera& cam, const uint4* gbuf, const float* vis,
+                             float inv_log_norm, uint16_t* feat, hipStream_t st);
 void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris,
                     float4* tris, hipStream_t st);
 void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st);

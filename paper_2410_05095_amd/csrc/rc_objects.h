@@ -1,0 +1,53 @@
+// Library-owned objects behind the opaque handles of the C ABI.
+#pragma once
+
+#include <vector>
+
+#include "rc_internal.h"
+
+struct rc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int grid = 0;                         // persistent traversal grid (blocks)
+    uint32_t* d_counters = nullptr;       // [0..7] work queues, [8] error flag
+    unsigned long long* d_rays = nullptr; // [0] primary, [1] shadow rays cast
+    uint32_t* d_overflow = nullptr;
+    size_t overflow_words = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool timed = false;
+    bool timed_batch = false;
+    int sticky = RC_OK;
+    // batched rendering: device table, pinned staging copy, captured graph
+    uint8_t* d_table = nullptr;
+    uint8_t* h_table = nullptr;
+    size_t table_cap = 0;
+    hipEvent_t ev_staging = nullptr;
+    bool staging_pending = false;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_key = 0;
+};
+
+struct rc_scene {
+    std::vector<float> pos;
+    std::vector<uint32_t> idx, tri_mat, body_vr;
+    std::vector<float> mats;
+    uint32_t nv = 0, nt = 0, nm = 0, nb = 0, max_body_verts = 0;
+    float* d_pos = nullptr;
+    float* d_rest = nullptr;
+    uint32_t* d_idx = nullptr;
+    uint32_t* d_tri_mat = nullptr;
+    float* d_mats = nullptr;
+    uint32_t* d_body_vr = nullptr;
+    bool host_pos_stale = false;
+    // BVH
+    bool built = false;
+    HostBvh hb;
+    Node4* d_nodes = nullptr;
+    uint32_t* d_order = nullptr;
+    float4* d_tris = nullptr;
+    double build_ms = 0.0;
+    float scale = 1.0f;
+    bool sah_stale = false;   // boxes refit on the device since the host copy was made
+};

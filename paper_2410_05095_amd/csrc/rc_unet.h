@@ -1,0 +1,46 @@
+// Kernel launchers of the U-Net denoiser (k_unet.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+struct ConvArgs {
+    const uint16_t* in;     // NHWC bf16, Cin channels (Cin a multiple of 8)
+    int N, H, W, Cin;
+    const uint16_t* wt;     // [Cout][9][Cin] bf16
+    const float* bias;      // Cout floats or NULL
+    const uint16_t* mask;   // optional NHWC [Cout]: the output is zeroed where mask <= 0
+    uint16_t* out;          // NHWC bf16, Cout channels
+    int Cout;
+    int relu;
+};
+
+struct WgradArgs {
+    const uint16_t* x;      // layer input NHWC [Cin]
+    const uint16_t* g;      // gradient of the pre-activation NHWC [Cout]
+    int N, H, W, Cin, Cout;
+    int chunk;              // pixels per split-K chunk (multiple of 32)
+    float* partial;         // [chunks][Cout][9][Cin]
+};
+
+void unet_conv3x3(const ConvArgs& a, hipStream_t st);
+int unet_wgrad_chunks(size_t P, int chunk);
+void unet_wgrad(const WgradArgs& a, hipStream_t st);
+void unet_reduce_chunks(const float* partial, int n_chunks, int n, float* out, int add, hipStream_t st);
+void unet_colsum(const uint16_t* g, int P, int C, int chunk, float* partial, hipStream_t st);
+void unet_pool2(const uint16_t* in, int N, int H, int W, int C, uint16_t* out, hipStream_t st);
+void unet_up2_concat(const uint16_t* a, const uint16_t* skip, int N, int H, int W, int Ca, int Cs, uint16_t* out,
+                     hipStream_t st);
+void unet_up_back_mask(const uint16_t* g, int N, int H2, int W2, int Ctot, int c0, int C, const uint16_t* mask,
+                       uint16_t* out, hipStream_t st);
+void unet_pool_back_add_mask(const uint16_t* gpool, const uint16_t* gcat, int N, int H, int W, int C, int Ctot, int c0,
+                             const uint16_t* mask, uint16_t* out, hipStream_t st);
+void unet_head(const uint16_t* d1, const float* wh, const float* bh, int P, float* y, hipStream_t st);
+void unet_loss(const float* y, const float* t, const float* m, int P, int chunk, float* partial, float* sums,
+               hipStream_t st);
+void unet_head_back(const uint16_t* d1, const float* y, const float* t, const float* m, const float* sums,
+                    const float* wh, int P, int chunk, uint16_t* gpre, float* partial, hipStream_t st);
+void unet_weights_bf16(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t* wb, hipStream_t st);
+void unet_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps, float c1,
+               float c2, hipStream_t st);
+void unet_fill_f32(float* p, float v, size_t n, hipStream_t st);

@@ -1,0 +1,221 @@
+"""GPU U-Net denoiser (BF16 MFMA kernels) against the FP64 oracle in BF16-emulation mode:
+forward, every parameter gradient, the Adam step, checkpoints, feature packing, a short training run."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import unet as U
+from paper_2410_05095_amd import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_05095_amd import _native as N
+    c = N.Context(0)
+    yield c
+    c.close()
+
+
+def unflat(v):
+    p, o = {}, 0
+    shapes = {}
+    for name, ci, co in U.LAYERS:
+        shapes[name + ".w"] = (co, 3, 3, ci)
+        shapes[name + ".b"] = (co,)
+    shapes["head.w"] = (32,)
+    shapes["head.b"] = (1,)
+    for k in U.param_names():
+        n = int(np.prod(shapes[k]))
+        p[k] = np.asarray(v[o:o + n], np.float64).reshape(shapes[k])
+        o += n
+    assert o == v.size
+    return p
+
+
+def random_batch(seed, n=2, h=16, w=24):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, h, w, 8))
+    x[..., 0] = (rng.random((n, h, w)) < 0.5)
+    x[..., 1] = rng.uniform(0, 1, (n, h, w))
+    nrm = rng.normal(size=(n, h, w, 3))
+    x[..., 2:5] = nrm / np.linalg.norm(nrm, axis=-1, keepdims=True)
+    x[..., 5:8] = rng.uniform(0.2, 0.9, (n, h, w, 3))
+    t = rng.uniform(0, 1, (n, h, w))
+    m = (rng.random((n, h, w)) < 0.9).astype(np.float64)
+    return U.bf16_round(x), t.astype(np.float32).astype(np.float64), m
+
+
+def to_dev(ctx, x, t, m):
+    import torch
+    xf = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).cuda().contiguous()
+    return xf, torch.from_numpy(t.astype(np.float32)).cuda(), torch.from_numpy(m.astype(np.float32)).cuda()
+
+
+def oracle_params(seed):
+    p = U.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = rng.normal(0, 0.05, p[k].shape)
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
+def rel_frob(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def cosine(a, b):
+    return float((a.ravel() @ b.ravel()) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+
+
+def test_forward_matches_oracle(ctx):
+    from paper_2410_05095_amd import _native as N
+    den = N.Denoiser(ctx, seed=1)
+    assert den.n_params == U.N_PARAMS
+    p = oracle_params(3)
+    den.set_params(U.flat(p).astype(np.float32))
+    for seed, (n, h, w) in enumerate([(2, 16, 24), (1, 36, 20), (3, 8, 8)]):
+        x, t, m = random_batch(seed, n, h, w)
+        xd, td, md = to_dev(ctx, x, t, m)
+        y = den.infer(xd).cpu().numpy().astype(np.float64)
+        yo, _ = U.forward(p, x, bf16=True)
+        y64, _ = U.forward(p, x, bf16=False)
+        err = np.abs(y - yo)
+        say(f"[unet fwd {n}x{h}x{w}] max |gpu - oracle_bf16| {err.max():.2e} mean {err.mean():.2e}; "
+            f"bf16 vs fp64 {np.abs(yo - y64).max():.2e}")
+        assert err.max() < 2e-3 and err.mean() < 1e-4
+
+
+def test_gradients_match_oracle(ctx):
+    from paper_2410_05095_amd import _native as N
+    den = N.Denoiser(ctx, seed=2)
+    p = oracle_params(5)
+    den.set_params(U.flat(p).astype(np.float32))
+    x, t, m = random_batch(7, 2, 16, 24)
+    xd, td, md = to_dev(ctx, x, t, m)
+    loss = den.train_step(xd, td, md, lr=0.0)
+    g = unflat(den.grads())
+    yo, cache = U.forward(p, x, bf16=True)
+    go, _ = U.backward(p, cache, t, m, bf16_grads=True)
+    lo = U.masked_mse(yo, t, m)
+    say(f"[unet loss] gpu {loss:.6e} oracle {lo:.6e}")
+    assert abs(loss - lo) <= 1e-4 * lo
+    worst = 0.0
+    for k in U.param_names():
+        rf, cs = rel_frob(g[k], go[k]), cosine(g[k], go[k])
+        worst = max(worst, rf)
+        say(f"  {k:8s} rel_frob {rf:.2e} cos {cs:.8f}")
+        assert rf <= 5e-3 and cs >= 0.9999, k
+    say(f"[unet grads] worst relative Frobenius error {worst:.2e}")
+    # the lr = 0 step left the weights unchanged
+    assert np.array_equal(den.params(), U.flat(p).astype(np.float32))
+
+
+def test_adam_step_matches_oracle(ctx):
+    from paper_2410_05095_amd import _native as N
+    den = N.Denoiser(ctx, seed=3)
+    p = oracle_params(9)
+    den.set_params(U.flat(p).astype(np.float32))
+    x, t, m = random_batch(11, 2, 16, 16)
+    xd, td, md = to_dev(ctx, x, t, m)
+    state = {}
+    po = {k: v.copy() for k, v in p.items()}
+    for step in range(1, 4):
+        den.train_step(xd, td, md, lr=1e-3)
+        g = unflat(den.grads())
+        U.adam_step(po, g, state, step, 1e-3)
+        got = den.params().astype(np.float64)
+        want = U.flat(po)
+        err = np.abs(got - want) / np.maximum(np.abs(want), 1e-3)
+        say(f"[adam step {step}] max rel {err.max():.2e}")
+        assert err.max() <= 1e-5
+        po = unflat(got)   # continue from the GPU's FP32 weights
+
+
+def test_training_reduces_loss(ctx):
+    from paper_2410_05095_amd import _native as N
+    den = N.Denoiser(ctx, seed=4)
+    rng = np.random.default_rng(0)
+    n, h, w = 4, 32, 32
+    x, _, m = random_batch(13, n, h, w)
+    # target: a smooth function of the features (blurred visibility) the network can learn
+    t = 0.5 * x[..., 0] + 0.25 * x[..., 1] + 0.25 * x[..., 5]
+    xd, td, md = to_dev(ctx, x, t, m)
+    losses = [den.train_step(xd, td, md, lr=2e-3) for _ in range(60)]
+    say(f"[unet train] loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.2 * losses[0]
+    assert all(np.isfinite(losses))
+
+
+def test_checkpoint_roundtrip_and_rejection(ctx):
+    from paper_2410_05095_amd import _native as N
+    den = N.Denoiser(ctx, seed=5)
+    x, t, m = random_batch(17, 1, 16, 16)
+    xd, td, md = to_dev(ctx, x, t, m)
+    for _ in range(3):
+        den.train_step(xd, td, md, lr=1e-3, want_loss=False)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "den.ckpt")
+        den.save(path)
+        other = N.Denoiser(ctx, seed=99)
+        other.load(path)
+        assert np.array_equal(other.params(), den.params())
+        # resumed training continues bit-identically (same Adam state and step)
+        den.train_step(xd, td, md, lr=1e-3, want_loss=False)
+        other.train_step(xd, td, md, lr=1e-3, want_loss=False)
+        assert np.array_equal(other.params(), den.params())
+        raw = bytearray(open(path, "rb").read())
+        before = other.params()
+        bad_cases = {"flip": raw[:100] + bytes([raw[100] ^ 1]) + raw[101:], "truncated": raw[:-9],
+                     "version": raw[:4] + bytes([9, 0, 0, 0]) + raw[8:], "empty": b""}
+        for name, blob in bad_cases.items():
+            bp = os.path.join(d, name)
+            open(bp, "wb").write(bytes(blob))
+            with pytest.raises(N.RcError) as e:
+                other.load(bp)
+            assert e.value.status == -7, name
+        with pytest.raises(N.RcError) as e:
+            other.load(os.path.join(d, "missing"))
+        assert e.value.status == -7
+        assert np.array_equal(other.params(), before)
+
+
+def test_pack_features(ctx, oracle_mod):
+    import torch
+    from paper_2410_05095_amd import _native as N
+    O = oracle_mod
+    scene = sg.small_random_scene(2, n_instances=20, width=40, height=32, ssaa=1)
+    cam = scene.cameras[0]
+    gs = ctx.scene_from(scene).build()
+    out = ctx.render(gs, cam, (), rect=scene.rect_light, area_samples=1, area_stream=0)
+    feat = N.pack_features(ctx, gs, cam, out, depth_norm=60.0)
+    torch.cuda.synchronize()
+    f = feat.float().cpu().numpy().reshape(-1, 8)
+    hit = out["hit"].cpu().numpy().view(np.uint32)
+    vis = out["visibility"].cpu().numpy().reshape(-1)
+    ids = hit[:, 0]
+    miss = ids == 0xFFFFFFFF
+    assert (f[miss] == np.array([1, 1, 0, 0, 0, 0, 0, 0])).all()
+    h = ~miss
+    assert np.array_equal(f[h, 0], U.bf16_round(vis[h]).astype(np.float32))
+    t = hit[h, 1].view(np.float32).astype(np.float64)
+    assert np.allclose(f[h, 1], np.log1p(t) / np.log1p(60.0), rtol=1e-2)
+    o, d = O.gen_rays(cam, np.nonzero(h)[0])
+    P = scene.positions.astype(np.float64)
+    tri = scene.indices[ids[h]]
+    n = np.cross(P[tri[:, 1]] - P[tri[:, 0]], P[tri[:, 2]] - P[tri[:, 0]])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    n *= -np.sign((n * d.astype(np.float64)).sum(1))[:, None]
+    assert np.allclose(f[h, 2:5], n, atol=1e-2)
+    alb = scene.materials[scene.tri_material[ids[h]], :3]
+    assert np.allclose(f[h, 5:8], alb, rtol=1e-2)
