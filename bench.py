@@ -75,6 +75,38 @@ def cpu_baseline(scene, cam, args, budget_s=12.0):
                       f"{build_s:.1f} s not included"}
 
 
+def learned_path(ctx, gs, scene, cam, args):
+    """Train the denoiser on the method's own 1/256-sample renders of two other scene seeds, then compare
+    on this frame: shadow MSE against 256 samples and device frame time, learned 1 spp vs plain."""
+    import torch
+
+    from paper_2410_05095_amd import _native as N
+    from paper_2410_05095_amd import denoise as D
+    from paper_2410_05095_amd import scenegen as sg
+    t0 = time.perf_counter()
+    train_scenes = []
+    for seed in (args.seed + 1, args.seed + 2):
+        sc = sg.big_scene(seed)
+        train_scenes.append((sc, ctx.scene_from(sc).build()))
+    log(f"[bench] training scenes ready ({time.perf_counter() - t0:.1f} s)")
+    data = D.make_training_set(ctx, train_scenes, n_views=16, crops_per_view=12, crop=256, seed=args.seed, log=log)
+    for _, h in train_scenes:
+        h.close()
+    den = N.Denoiser(ctx, seed=args.seed)
+    t1 = time.perf_counter()
+    losses = D.train(den, data, steps=args.denoiser_steps, batch=8, lr=2e-3, seed=args.seed, log=log, log_every=300)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    del data
+    ev = D.evaluate(ctx, den, gs, scene, cam, plain_spp=args.spp, ref_spp=256, reps=5)
+    # plain sample count whose expected MSE (binomial, MSE_1 / N) equals the denoised MSE
+    ev["plain_spp_equivalent"] = ev["mse_raw_1spp"] / max(ev["mse_denoised_1spp"], 1e-12)
+    ev.update({"train_steps": args.denoiser_steps, "train_s": round(train_s, 1), "train_crops": 192,
+               "crop": 256, "final_loss": [x for x in losses if x == x][-1],
+               "weights": "bf16 (FP32 master)", "parity": "unpinned (statistical)"})
+    return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in ev.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +116,8 @@ def main():
     ap.add_argument("--spp", type=int, default=64, help="rect-light samples per pixel (big_7M)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--denoiser-steps", type=int, default=1200,
+                    help="training steps of the learned 1-spp path (0 = skip the learned-path comparison)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of rendering, copy a buffer of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -172,6 +206,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": MEASURED_TRAFFIC.get((args.workload, args.spp, kernel_hash()))},
     }
+    if args.workload == "big_7M" and args.denoiser_steps > 0:
+        res["denoiser"] = learned_path(ctx, gs, scene, cam, args)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
         res["cpu_baseline"] = cpu_baseline(scene, cam, args)

@@ -199,6 +199,12 @@ int rc_render(rc_ctx* ctx, rc_scene* scene, const rc_camera* cam,
               const rc_point_light* lights, uint32_t n_lights,
               const rc_rect_light* rect, const rc_render_opts* opts, const rc_outputs* out);
 
+/* The shading + resolve stage of rc_render alone, from given G-buffer, shadow masks and
+ * visibility (for example a denoised visibility).  Same layouts and rules as rc_render. */
+int rc_shade(rc_ctx* ctx, rc_scene* scene, const rc_camera* cam, const rc_point_light* lights, uint32_t n_lights,
+             const rc_rect_light* rect, const uint32_t* d_hit, const uint32_t* d_shadow, const float* d_visibility,
+             float* d_rgba, float* d_sample_rgba);
+
 /* Camera rays of every sample, exactly as the traversal generates them: d_origins and
  * d_dirs receive W*H*S x 3 float each (sample s = pixel * S + k).  For verification of the
  * FP32 ray definition. */

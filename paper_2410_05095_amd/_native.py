@@ -120,6 +120,8 @@ SIGNATURES = {
     "rc_denoiser_save": (C.c_int, [P, P, C.c_char_p]),
     "rc_denoiser_load": (C.c_int, [P, P, C.c_char_p]),
     "rc_pack_features": (C.c_int, [P, P, C.POINTER(RcCamera), P, P, C.c_float, P]),
+    "rc_shade": (C.c_int, [P, P, C.POINTER(RcCamera), C.POINTER(RcPointLight), C.c_uint32, C.POINTER(RcRectLight),
+                           P, P, P, P, P]),
     "rc_render_batch": (C.c_int, [P, P, C.c_uint32, C.POINTER(RcView), C.c_uint32, C.POINTER(RcPointLight),
                                   C.c_uint32, C.POINTER(RcTune), C.c_uint32]),
     "rc_autotune": (C.c_int, [P, P, C.c_uint32, C.POINTER(RcView), C.c_uint32, C.POINTER(RcPointLight), C.c_uint32,
@@ -260,6 +262,19 @@ class Context:
         rc = rect_struct(rect) if rect is not None else None
         check(lib().rc_render(self.h, scene.h, C.byref(camc), Larr, nl, C.byref(rc) if rc is not None else None,
                               C.byref(opts), C.byref(o)), "rc_render")
+        return out
+
+    def shade(self, scene: "Scene", cam, out: dict, lights=(), rect=None, visibility=None):
+        """Re-run shading + resolve into out["rgba"] from out["hit"], out["shadow"] and `visibility`."""
+        self._sync_stream()
+        Larr = light_array(lights)
+        nl = 0 if Larr is None else len(Larr)
+        vis = visibility if visibility is not None else out.get("visibility")
+        camc = camera_struct(cam)
+        rc = rect_struct(rect) if rect is not None else None
+        check(lib().rc_shade(self.h, scene.h, C.byref(camc), Larr, nl, C.byref(rc) if rc is not None else None,
+                             C.c_void_p(out["hit"].data_ptr()), _dptr(out.get("shadow")) if nl else None,
+                             _dptr(vis), C.c_void_p(out["rgba"].data_ptr()), None), "rc_shade")
         return out
 
     def camera_rays(self, cam):

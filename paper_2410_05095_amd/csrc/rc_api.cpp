@@ -464,6 +464,36 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     return RC_OK;
 }
 
+int rc_shade(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light* lights, uint32_t n_lights,
+             const rc_rect_light* rect, const uint32_t* d_hit, const uint32_t* d_shadow, const float* d_vis,
+             float* d_rgba, float* d_sample_rgba)
+{
+    if (!c || !s || !cam || !d_hit || !d_rgba) return RC_ERR_INVALID_ARG;
+    if (cam->width <= 0 || cam->height <= 0 || (int64_t)cam->width * cam->height > (1ll << 28)) return RC_ERR_INVALID_ARG;
+    if (cam->ssaa != 1 && cam->ssaa != 2) return RC_ERR_UNSUPPORTED;
+    if (n_lights > 16 || (n_lights > 0 && (!lights || !d_shadow))) return RC_ERR_INVALID_ARG;
+    if (rect && (!d_vis || cam->ssaa != 1)) return RC_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_rgba) | reinterpret_cast<uintptr_t>(d_hit) |
+         reinterpret_cast<uintptr_t>(d_sample_rgba)) & 15u)
+        return RC_ERR_INVALID_ARG;
+    RC_HIP(hipSetDevice(c->device));
+    DevCamera dc = make_camera(cam);
+    DevScene ds = dev_scene(s);
+    DevLights L;
+    memset(&L, 0, sizeof(L));
+    L.n_point = (int)n_lights;
+    for (uint32_t l = 0; l < n_lights; ++l)
+        for (int k = 0; k < 3; ++k) { L.point[l][k] = lights[l].position[k]; L.point[l][3 + k] = lights[l].intensity[k]; }
+    if (rect) {
+        L.has_rect = 1;
+        memcpy(L.rect, rect, sizeof(float) * 12);
+    }
+    rc_launch_shade(ds, dc, L, reinterpret_cast<const uint4*>(d_hit), n_lights ? d_shadow : nullptr, d_vis, d_rgba,
+                    d_sample_rgba, c->stream);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
 int rc_camera_rays(rc_ctx* c, const rc_camera* cam, float* d_o, float* d_d)
 {
     if (!c || !cam || !d_o || !d_d) return RC_ERR_INVALID_ARG;

@@ -351,8 +351,15 @@ def random_point_lights(rng: np.random.Generator, n: int, intensity: float = 400
     return out
 
 
-DEFAULT_RECT = RectLight(center=(0.0, 21.0, 0.0), edge_u=(1.0, 0.0, 0.0), edge_v=(0.0, 0.0, 1.0),
+# A 1x1 m light on the camera side of the instance volume, tilted to face it (normal edge_u x edge_v
+# = (0.5, -0.707, 0.5)).  Directly above the 20 m cube of instances almost every visible point would be
+# in shadow (the instances leave a ~5 m mean free path), so the light sits outside the volume.
+_S = 0.7071067811865476
+DEFAULT_RECT = RectLight(center=(-12.0, 26.0, -22.0), edge_u=(_S, 0.0, -_S), edge_v=(0.5, _S, 0.5),
                          radiance=(100.0, 100.0, 100.0))
+# A horizontal 1x1 m light facing down, for closed-form checks.
+OVERHEAD_RECT = RectLight(center=(0.0, 21.0, 0.0), edge_u=(1.0, 0.0, 0.0), edge_v=(0.0, 0.0, 1.0),
+                          radiance=(100.0, 100.0, 100.0))
 
 
 def city_scene(seed: int = 0, n_instances: int = 400, width: int = 1920, height: int = 1080,

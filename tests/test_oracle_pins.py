@@ -282,7 +282,7 @@ def test_area_streams_independent(oracle_mod):
     gv, gf = quad(0.0, 20.0)
     ov, of = quad(10.0, 0.25)   # partial shadow at (0.3, 0, 0.2): V = 1 - 0.695 * 0.805
     sc = tri_scene(O, gv + ov, gf + [(p + 4, q + 4, r + 4) for p, q, r in of])
-    rect = sg.DEFAULT_RECT
+    rect = sg.OVERHEAD_RECT
     a = [sc.rect_vis_point([0.3, 0, 0.2], [0, 1, 0], rect, 1, stream=0, pixel=k)[0] for k in range(400)]
     b = [sc.rect_vis_point([0.3, 0, 0.2], [0, 1, 0], rect, 1, stream=1, pixel=k)[0] for k in range(400)]
     assert 0.05 < np.mean(a) < 0.95
