@@ -92,11 +92,14 @@ int rc_scene_destroy(rc_ctx* ctx, rc_scene* scene);
 /* --------------------------------------------------------------- BVH ---- */
 /* Build the scene's BVH on the host: binned SAH (`bins` bins per axis, default 32),
  * leaves of at most `max_leaf` triangles (1..4, default 4), collapsed to a 4-wide BVH
- * with all four child boxes of a node in one 128-byte record.  Replaces any previous
- * BVH.  Synchronous with respect to the host (uploads on the context stream). */
+ * with all four child boxes of a node in one 128-byte record.  `node_cost` is the SAH
+ * cost of visiting a node relative to one triangle test (default 4, range (0, 64]); it
+ * decides when a range of at most max_leaf triangles becomes a leaf.  Replaces any
+ * previous BVH.  Synchronous with respect to the host (uploads on the context stream). */
 typedef struct rc_build_opts {
     uint32_t bins;
     uint32_t max_leaf;
+    float node_cost;
 } rc_build_opts;
 int rc_bvh_build(rc_ctx* ctx, rc_scene* scene, const rc_build_opts* opts);
 
@@ -164,7 +167,7 @@ enum {
 };
 
 typedef struct rc_render_opts {
-    uint32_t area_samples;   /* light samples per pixel for the rect light (>= 1 when rect != NULL) */
+    uint32_t area_samples;   /* light samples per pixel for the rect light (1..4096 when rect != NULL) */
     uint32_t area_stream;    /* independent Philox stream of the rect-light samples */
     uint32_t flags;
 } rc_render_opts;

@@ -36,7 +36,7 @@ class RcSceneDesc(C.Structure):
 
 
 class RcBuildOpts(C.Structure):
-    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32)]
+    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("node_cost", C.c_float)]
 
 
 class RcBvhStats(C.Structure):
@@ -382,9 +382,10 @@ class Scene:
         except Exception:
             pass
 
-    def build(self, bins: int = 32, max_leaf: int = 4):
+    def build(self, bins: int = 32, max_leaf: int = 4, node_cost: float = 4.0):
         self.ctx._sync_stream()
-        check(lib().rc_bvh_build(self.ctx.h, self.h, C.byref(RcBuildOpts(bins, max_leaf))), "rc_bvh_build")
+        check(lib().rc_bvh_build(self.ctx.h, self.h, C.byref(RcBuildOpts(bins, max_leaf, node_cost))),
+              "rc_bvh_build")
         return self
 
     def refit(self):

@@ -47,6 +47,7 @@ struct Builder {
     const std::vector<float>* cen;   // 3 per triangle
     uint32_t* ids;
     uint32_t bins, max_leaf;
+    double node_cost;
     std::vector<Node2> nodes;
     std::atomic<uint32_t> n_nodes{0};
 
@@ -110,7 +111,7 @@ struct Builder {
             }
         }
         double parea = nd.box.area();
-        double split_cost = parea > 0 ? 1.0 + best_cost / parea : (double)n;
+        double split_cost = parea > 0 ? node_cost + best_cost / parea : (double)n;
         if (n <= max_leaf && (best_axis < 0 || (double)n <= split_cost)) { nodes[id] = nd; return id; }
 
         uint32_t mid;
@@ -187,7 +188,7 @@ double rc_bvh_sah(const std::vector<Node4>& nodes)
 }
 
 bool rc_build_bvh_host(const float* pos, const uint32_t* idx, uint32_t n_tris, uint32_t bins,
-                       uint32_t max_leaf, HostBvh& out)
+                       uint32_t max_leaf, float node_cost, HostBvh& out)
 {
     out = HostBvh();
     if (n_tris == 0) return false;
@@ -212,6 +213,7 @@ bool rc_build_bvh_host(const float* pos, const uint32_t* idx, uint32_t n_tris, u
     B.ids = ids.data();
     B.bins = bins;
     B.max_leaf = max_leaf;
+    B.node_cost = node_cost;
     B.nodes.resize(2 * (size_t)n_tris);
     uint32_t root = B.build(0, n_tris, 0);
     const std::vector<Node2>& N2 = B.nodes;

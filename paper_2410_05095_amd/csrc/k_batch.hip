@@ -25,15 +25,12 @@ __device__ inline uint32_t find_view(const DevView* views, uint32_t n, uint32_t 
 
 __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
 {
-    __shared__ uint32_t s_node[SL][BLOCK];
-    __shared__ float s_t[SL][BLOCK];
-
     const int tid = threadIdx.x;
     const uint32_t lane = __lane_id();
     const uint32_t glane = blockIdx.x * BLOCK + tid;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    TravStack<SL, BLOCK, true> st{s_node, s_t, tid, reinterpret_cast<uint2*>(P.w.overflow), P.w.overflow_depth,
-                                  P.w.n_lanes, glane, P.w.error_flag};
+    TravStack<SL, BLOCK, true> st{tid, reinterpret_cast<uint2*>(P.w.overflow), P.w.overflow_depth, P.w.n_lanes,
+                                  glane, P.w.error_flag};
     const uint32_t tile_pix = P.tune.tile_w * P.tune.tile_h;
 
     int state = 0;                 // 0 idle, 1 camera ray, 2 shadow ray
@@ -174,10 +171,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
         if (__ballot(state != 0) == 0) break;
 
         for (;;) {
-            if (state != 0) {
-                bool occluded;
-                if (trav_step(sc, ray, ts, st, state == 2, occluded, node_visits, tri_tests)) end_ray(occluded);
-            }
+            bool occluded = false;
+            trav_advance(sc, ray, ts, st, state != 0, state == 2, occluded, node_visits, tri_tests);
+            if (state != 0 && ts.cur == RC_STACK_EMPTY) end_ray(occluded);
             uint32_t n_act = (uint32_t)__popcll(__ballot(state != 0));
             if (n_act == 0) break;
             if ((q_next < q_end || !queue_empty) && n_act < P.tune.min_rays) break;
@@ -201,11 +197,13 @@ int rc_batch_max_blocks_per_cu(int device)
 {
     int blocks = 0;
     (void)device;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_batch), BLOCK, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_batch), BLOCK,
+                                                 TravStack<SL, BLOCK, true>::lds_bytes());
     return blocks < 1 ? 1 : blocks;
 }
 
 void rc_launch_batch(const BatchParams& P, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), 0, st, P);
+    const size_t lds = TravStack<SL, BLOCK, true>::lds_bytes();
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), lds, st, P);
 }

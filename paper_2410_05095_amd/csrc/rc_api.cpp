@@ -180,6 +180,7 @@ int rc_destroy(rc_ctx* c)
     dev_free(c->d_counters);
     dev_free(c->d_rays);
     dev_free(c->d_overflow);
+    dev_free(c->d_counts);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
     delete c;
@@ -293,7 +294,9 @@ int rc_bvh_build(rc_ctx* c, rc_scene* s, const rc_build_opts* o)
     if (!c || !s) return RC_ERR_INVALID_ARG;
     uint32_t bins = o && o->bins ? o->bins : 32u;
     uint32_t max_leaf = o && o->max_leaf ? o->max_leaf : 4u;
-    if (bins < 2 || bins > 256 || max_leaf < 1 || max_leaf > 4) return RC_ERR_INVALID_ARG;
+    float node_cost = o && o->node_cost != 0.0f ? o->node_cost : 4.0f;
+    if (bins < 2 || bins > 256 || max_leaf < 1 || max_leaf > 4 || !(node_cost > 0.0f && node_cost <= 64.0f))
+        return RC_ERR_INVALID_ARG;
     RC_HIP(hipSetDevice(c->device));
     if (s->host_pos_stale) {
         RC_HIP(hipMemcpyAsync(s->pos.data(), s->d_pos, s->pos.size() * 4, hipMemcpyDeviceToHost, c->stream));
@@ -303,7 +306,8 @@ int rc_bvh_build(rc_ctx* c, rc_scene* s, const rc_build_opts* o)
     free_bvh(s);
     auto t0 = std::chrono::steady_clock::now();
     HostBvh hb;
-    if (!rc_build_bvh_host(s->pos.data(), s->idx.data(), s->nt, bins, max_leaf, hb)) return RC_ERR_INVALID_VALUE;
+    if (!rc_build_bvh_host(s->pos.data(), s->idx.data(), s->nt, bins, max_leaf, node_cost, hb))
+        return RC_ERR_INVALID_VALUE;
     s->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     int st = dev_alloc(&s->d_nodes, hb.nodes.size());
     if (st == RC_OK) st = dev_alloc(&s->d_order, hb.tri_order.size());
@@ -404,7 +408,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     if (!out->d_rgba || !out->d_hit) return RC_ERR_INVALID_ARG;
     if (n_lights > 0 && !out->d_shadow) return RC_ERR_INVALID_ARG;
     if (rect) {
-        if (!out->d_visibility || !opts || opts->area_samples == 0) return RC_ERR_INVALID_ARG;
+        if (!out->d_visibility || !opts || opts->area_samples == 0 || opts->area_samples > 4096) return RC_ERR_INVALID_ARG;
         if (cam->ssaa != 1) return RC_ERR_UNSUPPORTED;
     }
     if ((reinterpret_cast<uintptr_t>(out->d_rgba) | reinterpret_cast<uintptr_t>(out->d_hit) |
@@ -451,8 +455,17 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     rc_launch_primary(ds, dc, gbuf, w, c->grid, q);
     if (timing) RC_HIP(hipEventRecord(c->ev[1], q));
     if (n_lights > 0 || rect) {
+        size_t n_pix = (size_t)cam->width * cam->height;
+        if (rect && n_pix > c->counts_cap) {
+            RC_HIP(hipStreamSynchronize(q));
+            dev_free(c->d_counts);
+            c->counts_cap = 0;
+            st = dev_alloc(&c->d_counts, n_pix);
+            if (st != RC_OK) return st;
+            c->counts_cap = n_pix;
+        }
         w.ray_count = c->d_rays + 1;
-        rc_launch_shadow(ds, dc, L, gbuf, out->d_shadow, out->d_visibility, w, c->grid, q);
+        rc_launch_shadow(ds, dc, L, gbuf, out->d_shadow, out->d_visibility, c->d_counts, w, c->grid, q);
     }
     if (timing) RC_HIP(hipEventRecord(c->ev[2], q));
     rc_launch_shade(ds, dc, L, gbuf, n_lights ? out->d_shadow : nullptr, out->d_visibility, out->d_rgba,

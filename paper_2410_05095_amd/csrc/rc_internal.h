@@ -72,7 +72,7 @@ struct HostBvh {
 };
 
 bool rc_build_bvh_host(const float* pos, const uint32_t* idx, uint32_t n_tris,
-                       uint32_t bins, uint32_t max_leaf, HostBvh& out);
+                       uint32_t bins, uint32_t max_leaf, float node_cost, HostBvh& out);
 double rc_bvh_sah(const std::vector<Node4>& nodes);
 
 // Traversal launch geometry
@@ -92,7 +92,8 @@ struct TraceWork {
 void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, const TraceWork& w,
                        int grid, hipStream_t st);
 void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
-                      uint32_t* mask, float* visibility, const TraceWork& w, int grid, hipStream_t st);
+                      uint32_t* mask, float* visibility, uint32_t* counts, const TraceWork& w, int grid,
+                      hipStream_t st);
 int rc_trace_grid(int device);
 
 // Batched rendering: one persistent launch over many views of several scenes.

@@ -20,21 +20,25 @@ struct TravState {
     float best_t, best_u, best_v;
 };
 
-// Per-lane stack: LDS part [depth][block] (lane-interleaved, conflict free) + global overflow.
+// Dynamic LDS of the traversal kernels: the per-lane stacks.
+extern __shared__ uint32_t rc_lds[];
+
+// Per-lane stack: LDS part [depth][block] (lane-interleaved, conflict free; node words, then the entry
+// distances when HAS_T) + global overflow.  LDS bytes per block: rc_stack_lds_bytes<...>().
 template <int SL, int BLOCK, bool HAS_T>
 struct TravStack {
-    uint32_t (*node)[BLOCK];
-    float (*t)[BLOCK];
     int tid;
     uint2* overflow;
     uint32_t overflow_depth, n_lanes, glane;
     uint32_t* error_flag;
 
+    static constexpr size_t lds_bytes() { return (size_t)SL * BLOCK * 4 * (HAS_T ? 2 : 1); }
+
     __device__ inline void push(int& sp, uint32_t w, float tn)
     {
         if (sp < SL) {
-            node[sp][tid] = w;
-            if (HAS_T) t[sp][tid] = tn;
+            rc_lds[sp * BLOCK + tid] = w;
+            if (HAS_T) rc_lds[(SL + sp) * BLOCK + tid] = __float_as_uint(tn);
         } else if ((uint32_t)(sp - SL) < overflow_depth) {
             overflow[(size_t)(sp - SL) * n_lanes + glane] = make_uint2(w, __float_as_uint(tn));
         } else {
@@ -53,8 +57,8 @@ struct TravStack {
             uint32_t w;
             float tn;
             if (sp < SL) {
-                w = node[sp][tid];
-                tn = HAS_T ? t[sp][tid] : 0.0f;
+                w = rc_lds[sp * BLOCK + tid];
+                tn = HAS_T ? __uint_as_float(rc_lds[(SL + sp) * BLOCK + tid]) : 0.0f;
             } else {
                 uint2 g = overflow[(size_t)(sp - SL) * n_lanes + glane];
                 w = g.x;
@@ -79,37 +83,33 @@ __device__ inline void trav_begin(TravRay& r, TravState& s)
     s.best_u = s.best_v = 0.0f;
 }
 
-// Process s.cur (one internal node, or one leaf) and advance s.cur.  `any`: any-hit ray on the
-// segment 0 < t < 1 (sets `occluded` and ends at the first hit); otherwise closest hit with t > 0.
-// Returns true when the ray has ended.
+// Visit the internal node s.cur: test the four child boxes, continue with the nearest hit child and
+// push the others (farthest first), or pop.  `any`: any-hit ray on the segment 0 < t < 1, otherwise
+// closest hit (boxes beyond the current hit are culled).
 template <class Stack>
-__device__ inline bool trav_step(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool any,
-                                 bool& occluded, uint32_t& node_visits, uint32_t& tri_tests)
+__device__ inline void trav_visit_node(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool any)
 {
-    occluded = false;
-    if (!rc_is_leaf(s.cur)) {
-        ++node_visits;
-        const float4* np = reinterpret_cast<const float4*>(sc.nodes + s.cur);
-        float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-        uint4 ch = reinterpret_cast<const uint4*>(np)[6];
-        const float bound = any ? 1.0f : s.best_t;
-        float lxs[4] = {lx.x, lx.y, lx.z, lx.w}, hxs[4] = {hx.x, hx.y, hx.z, hx.w};
-        float lys[4] = {ly.x, ly.y, ly.z, ly.w}, hys[4] = {hy.x, hy.y, hy.z, hy.w};
-        float lzs[4] = {lz.x, lz.y, lz.z, lz.w}, hzs[4] = {hz.x, hz.y, hz.z, hz.w};
-        uint32_t cw[4] = {ch.x, ch.y, ch.z, ch.w};
-        float tn[4];
+    const float4* np = reinterpret_cast<const float4*>(sc.nodes + s.cur);
+    float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+    uint4 ch = reinterpret_cast<const uint4*>(np)[6];
+    const float bound = any ? 1.0f : s.best_t;
+    float lxs[4] = {lx.x, lx.y, lx.z, lx.w}, hxs[4] = {hx.x, hx.y, hx.z, hx.w};
+    float lys[4] = {ly.x, ly.y, ly.z, ly.w}, hys[4] = {hy.x, hy.y, hy.z, hy.w};
+    float lzs[4] = {lz.x, lz.y, lz.z, lz.w}, hzs[4] = {hz.x, hz.y, hz.z, hz.w};
+    uint32_t cw[4] = {ch.x, ch.y, ch.z, ch.w};
+    float tn[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            float nx = r.inv[0] >= 0.0f ? lxs[c] : hxs[c], fx = r.inv[0] >= 0.0f ? hxs[c] : lxs[c];
-            float ny = r.inv[1] >= 0.0f ? lys[c] : hys[c], fy = r.inv[1] >= 0.0f ? hys[c] : lys[c];
-            float nz = r.inv[2] >= 0.0f ? lzs[c] : hzs[c], fz = r.inv[2] >= 0.0f ? hzs[c] : lzs[c];
-            float t0 = fmaxf(fmaxf((nx - r.o[0]) * r.inv[0], (ny - r.o[1]) * r.inv[1]),
-                             fmaxf((nz - r.o[2]) * r.inv[2], 0.0f));
-            float t1 = fminf(fminf((fx - r.o[0]) * r.inv[0], (fy - r.o[1]) * r.inv[1]), (fz - r.o[2]) * r.inv[2]);
-            bool hit = t0 <= fminf(t1 * RC_FAR_GROW, bound);
-            tn[c] = hit ? t0 : INFINITY;
-        }
-        // sort (distance, child) ascending with five comparators: misses (inf) sink to the end
+    for (int c = 0; c < 4; ++c) {
+        float nx = r.inv[0] >= 0.0f ? lxs[c] : hxs[c], fx = r.inv[0] >= 0.0f ? hxs[c] : lxs[c];
+        float ny = r.inv[1] >= 0.0f ? lys[c] : hys[c], fy = r.inv[1] >= 0.0f ? hys[c] : lys[c];
+        float nz = r.inv[2] >= 0.0f ? lzs[c] : hzs[c], fz = r.inv[2] >= 0.0f ? hzs[c] : lzs[c];
+        float t0 = fmaxf(fmaxf((nx - r.o[0]) * r.inv[0], (ny - r.o[1]) * r.inv[1]),
+                         fmaxf((nz - r.o[2]) * r.inv[2], 0.0f));
+        float t1 = fminf(fminf((fx - r.o[0]) * r.inv[0], (fy - r.o[1]) * r.inv[1]), (fz - r.o[2]) * r.inv[2]);
+        bool hit = t0 <= fminf(t1 * RC_FAR_GROW, bound);
+        tn[c] = hit ? t0 : INFINITY;
+    }
+    // sort (distance, child) ascending with five comparators: misses (inf) sink to the end
 #define RC_CS(a, b)                                                                   \
     {                                                                                 \
         bool sw = tn[b] < tn[a];                                                      \
@@ -117,51 +117,78 @@ __device__ inline bool trav_step(const DevScene& sc, const TravRay& r, TravState
         uint32_t ca = sw ? cw[b] : cw[a], cb = sw ? cw[a] : cw[b];                    \
         tn[a] = ta; tn[b] = tb; cw[a] = ca; cw[b] = cb;                               \
     }
-        RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
+    RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
 #undef RC_CS
-        if (tn[3] < INFINITY) st.push(s.sp, cw[3], tn[3]);
-        if (tn[2] < INFINITY) st.push(s.sp, cw[2], tn[2]);
-        if (tn[1] < INFINITY) st.push(s.sp, cw[1], tn[1]);
-        s.cur = tn[0] < INFINITY ? cw[0] : st.pop(s.sp, !any, s.best_t);
-    } else {
-        uint32_t first = rc_leaf_first(s.cur), cnt = rc_leaf_count(s.cur);
-        for (uint32_t i = 0; i < cnt; ++i) {
-            ++tri_tests;
-            const float4* tp = sc.tris + 3 * (size_t)(first + i);
-            float4 A = tp[0], B = tp[1], C = tp[2];
-            // Moller-Trumbore in FP32
-            float px_ = r.d[1] * C.z - r.d[2] * C.y;
-            float py_ = r.d[2] * C.x - r.d[0] * C.z;
-            float pz_ = r.d[0] * C.y - r.d[1] * C.x;
-            float det = B.x * px_ + B.y * py_;
-            det = det + B.z * pz_;
-            float idet = __builtin_amdgcn_rcpf(det);
-            float sx = r.o[0] - A.x, sy = r.o[1] - A.y, sz = r.o[2] - A.z;
-            float su = sx * px_ + sy * py_;
-            su = su + sz * pz_;
-            float u = su * idet;
-            float qx = sy * B.z - sz * B.y;
-            float qy = sz * B.x - sx * B.z;
-            float qz = sx * B.y - sy * B.x;
-            float sv = r.d[0] * qx + r.d[1] * qy;
-            sv = sv + r.d[2] * qz;
-            float v = sv * idet;
-            float stq = C.x * qx + C.y * qy;
-            stq = stq + C.z * qz;
-            float t = stq * idet;
-            bool hit = u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f;
-            if (any) {
-                if (hit && t < 1.0f) { occluded = true; break; }
-            } else {
-                uint32_t id = __float_as_uint(A.w);
-                if (hit && (t < s.best_t || (t == s.best_t && id < s.best_id))) {
-                    s.best_t = t; s.best_u = u; s.best_v = v; s.best_id = id;
-                }
+    if (tn[3] < INFINITY) st.push(s.sp, cw[3], tn[3]);
+    if (tn[2] < INFINITY) st.push(s.sp, cw[2], tn[2]);
+    if (tn[1] < INFINITY) st.push(s.sp, cw[1], tn[1]);
+    s.cur = tn[0] < INFINITY ? cw[0] : st.pop(s.sp, !any, s.best_t);
+}
+
+// Test the triangles of the leaf s.cur (Moller-Trumbore in FP32), then pop; an any-hit ray ends at its
+// first hit (occluded = true, s.cur = RC_STACK_EMPTY).
+template <class Stack>
+__device__ inline void trav_test_leaf(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool any,
+                                      bool& occluded, uint32_t& tri_tests)
+{
+    uint32_t first = rc_leaf_first(s.cur), cnt = rc_leaf_count(s.cur);
+    for (uint32_t i = 0; i < cnt; ++i) {
+        ++tri_tests;
+        const float4* tp = sc.tris + 3 * (size_t)(first + i);
+        float4 A = tp[0], B = tp[1], C = tp[2];
+        float px_ = r.d[1] * C.z - r.d[2] * C.y;
+        float py_ = r.d[2] * C.x - r.d[0] * C.z;
+        float pz_ = r.d[0] * C.y - r.d[1] * C.x;
+        float det = B.x * px_ + B.y * py_;
+        det = det + B.z * pz_;
+        float idet = __builtin_amdgcn_rcpf(det);
+        float sx = r.o[0] - A.x, sy = r.o[1] - A.y, sz = r.o[2] - A.z;
+        float su = sx * px_ + sy * py_;
+        su = su + sz * pz_;
+        float u = su * idet;
+        float qx = sy * B.z - sz * B.y;
+        float qy = sz * B.x - sx * B.z;
+        float qz = sx * B.y - sy * B.x;
+        float sv = r.d[0] * qx + r.d[1] * qy;
+        sv = sv + r.d[2] * qz;
+        float v = sv * idet;
+        float stq = C.x * qx + C.y * qy;
+        stq = stq + C.z * qz;
+        float t = stq * idet;
+        bool hit = u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f;
+        if (any) {
+            if (hit && t < 1.0f) { occluded = true; break; }
+        } else {
+            uint32_t id = __float_as_uint(A.w);
+            if (hit && (t < s.best_t || (t == s.best_t && id < s.best_id))) {
+                s.best_t = t; s.best_u = u; s.best_v = v; s.best_id = id;
             }
         }
-        s.cur = occluded ? RC_STACK_EMPTY : st.pop(s.sp, !any, s.best_t);
     }
-    return s.cur == RC_STACK_EMPTY;
+    s.cur = occluded ? RC_STACK_EMPTY : st.pop(s.sp, !any, s.best_t);
+}
+
+// Advance every busy lane of the wave: first all lanes standing at an internal node visit nodes until
+// none does, then all lanes standing at a leaf test leaves until none does.  A lane's own sequence of
+// visits is the same as visiting one node or leaf at a time, whatever the other lanes do; only the
+// grouping of the work into SIMD steps changes (fewer steps that execute both code paths).
+template <class Stack>
+__device__ inline void trav_advance(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool busy,
+                                    bool any, bool& occluded, uint32_t& node_visits, uint32_t& tri_tests)
+{
+    for (;;) {
+        bool inner = busy && !rc_is_leaf(s.cur);
+        if (__ballot(inner) == 0) break;
+        if (inner) {
+            ++node_visits;
+            trav_visit_node(sc, r, s, st, any);
+        }
+    }
+    for (;;) {
+        bool leaf = busy && s.cur != RC_STACK_EMPTY && rc_is_leaf(s.cur);
+        if (__ballot(leaf) == 0) break;
+        if (leaf) trav_test_leaf(sc, r, s, st, any, occluded, tri_tests);
+    }
 }
 
 // Shadow-ray target for light index j of a shaded point: a point light, or sample j of the rect
