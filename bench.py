@@ -213,7 +213,7 @@ def main():
                     "shadow_tris": round(st["shadow_tris"] / max(st["shadow_rays"], 1), 2)},
         "bvh": {"build_ms": round(bst["build_ms"], 1), "nodes": int(bst["n_nodes"]), "depth": int(bst["depth"]),
                 "sah": round(bst["sah_cost"], 2)},
-        "roofline": ({"kernel": "k_rect_packets", "bound": "alu", "achieved": round(achieved, 3),
+        "roofline": ({"kernel": "k_rect_wave", "bound": "alu", "achieved": round(achieved, 3),
                       "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
                       "traffic": MEASURED_TRAFFIC.get((args.workload, args.spp, kernel_hash())),
                       "logical_node_tri_GBps": round(logical_bytes / (dom_ms / 1000.0) / 1e9, 1)}

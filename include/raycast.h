@@ -163,7 +163,10 @@ typedef struct rc_rect_light {
 } rc_rect_light;
 
 enum {
-    RC_FLAG_TIMING = 1u      /* record per-stage device times (rc_get_stage_times) */
+    RC_FLAG_TIMING = 1u,     /* record per-stage device times (rc_get_stage_times) */
+    RC_FLAG_PER_LANE_RECT = 4u /* trace rect-light samples one ray per lane with per-lane stacks even when
+                                  the wave-uniform traversal would be used (area_samples >= 64 and a BVH
+                                  of depth <= 42); same results, for comparison */
 };
 
 typedef struct rc_render_opts {

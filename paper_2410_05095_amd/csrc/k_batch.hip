@@ -171,9 +171,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
         if (__ballot(state != 0) == 0) break;
 
         for (;;) {
-            bool occluded = false;
+            uint32_t occluded = 0u;
             trav_advance(sc, ray, ts, st, state != 0, state == 2, occluded, node_visits, tri_tests);
-            if (state != 0 && ts.cur == RC_STACK_EMPTY) end_ray(occluded);
+            if (state != 0 && ts.cur == RC_STACK_EMPTY) end_ray(occluded != 0u);
             uint32_t n_act = (uint32_t)__popcll(__ballot(state != 0));
             if (n_act == 0) break;
             if ((q_next < q_end || !queue_empty) && n_act < P.tune.min_rays) break;

@@ -11,13 +11,45 @@
 // tests with the octant-selected near/far planes and a conservative far distance; ordered
 // descent (nearest child first) for closest hits; per-lane stack of (node, entry distance)
 // in LDS with a lane-interleaved global overflow area.  Triangles: Moller-Trumbore in FP32.
+#include <algorithm>
+
 #include "rc_trav.h"
 
 namespace {
 
 constexpr int BLOCK = RC_TRACE_BLOCK;
 constexpr int SL = RC_STACK_LDS;
-constexpr int REFILL_AT = 40;   // refill once a wave has at most this many busy lanes
+constexpr int REFILL_AT = 40;    // refill once a wave has at most this many busy lanes
+constexpr uint32_t ITEM_CHUNK = 256;
+constexpr uint32_t RECT_CHUNK = 64;   // packets per chunk dealt to one XCD
+
+// Work queue split over the XCDs.  Workgroups are dispatched to the XCDs round-robin, so workgroup b runs
+// on XCD g = b % RC_XCDS.  The work sequence (items, or 64-ray packets) is cut into chunks of CHUNK that
+// are dealt to the XCDs in turn; the waves of XCD g claim positions j = 0, 1, 2, ... of that XCD's share
+// from their own counter (one atomic per claim of several positions).  The waves of one XCD thus work
+// on neighbouring pixels and share its L2, the eight counters split the atomic traffic, and the fine
+// interleave of chunks keeps the XCDs' shares balanced.
+template <uint32_t CHUNK>
+struct XcdQueue {
+    uint32_t* ctr;
+    uint32_t g;
+    uint64_t n;
+    __device__ XcdQueue(uint32_t* counters, uint32_t slot, uint64_t n_work)
+        : ctr(counters + RC_QUEUE_BASE + (slot * RC_XCDS + blockIdx.x % RC_XCDS) * 64),
+          g(blockIdx.x % RC_XCDS), n(n_work) {}
+    __device__ uint64_t chunk_of(uint64_t j) const { return g + (uint64_t)RC_XCDS * (j / CHUNK); }
+    // work index at position j of this XCD's share (may be >= n inside the last chunk)
+    __device__ uint64_t at(uint64_t j) const { return chunk_of(j) * CHUNK + j % CHUNK; }
+    // no work at position j or beyond
+    __device__ bool exhausted(uint64_t j) const { return chunk_of(j) * CHUNK >= n; }
+    // wave-uniform claim of `count` positions (called by all lanes; lane 0 does the atomic)
+    __device__ uint32_t claim(uint32_t count) const
+    {
+        uint32_t b = 0;
+        if (__lane_id() == 0) b = atomicAdd(ctr, count);
+        return __builtin_amdgcn_readfirstlane(b);
+    }
+};
 
 enum { MODE_PRIMARY = 0, MODE_POINT = 1, MODE_RECT = 2 };
 
@@ -33,7 +65,17 @@ struct KParams {
     TraceWork w;
     uint32_t n_items;
     uint32_t slot;
+    uint32_t claim;           // work positions a wave claims with one atomic (set by the launcher)
 };
+
+// Positions per claim: large enough that the atomics stay few, small enough that every wave makes about
+// `per_wave` claims, so that the last claims of the waves end close together.
+inline uint32_t claim_size(uint64_t n_work, int grid, uint32_t per_wave, uint32_t lo, uint32_t hi)
+{
+    uint64_t waves = (uint64_t)grid * (BLOCK / 64);
+    uint64_t c = n_work / (waves * per_wave);
+    return (uint32_t)std::min<uint64_t>(hi, std::max<uint64_t>(lo, c));
+}
 
 template <int MODE>
 __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
@@ -56,6 +98,8 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
     TravRay ray;
     TravState ts;
     bool queue_empty = false;
+    const XcdQueue<ITEM_CHUNK> queue(P.w.counters, P.slot, P.n_items);
+    uint32_t pool_next = 0, pool_end = 0;   // wave-uniform range of claimed, not yet started positions
     uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
 
     // shadow items: set up the next ray that is cast, or return false
@@ -121,25 +165,29 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
         for (;;) {
             uint64_t need = __ballot(state == 0);
             if (need == 0 || queue_empty) break;
-            int leader = __ffsll((unsigned long long)need) - 1;
-            uint32_t cnt = (uint32_t)__popcll(need);
-            uint32_t base = 0;
-            if ((int)lane == leader) base = atomicAdd(&P.w.counters[P.slot], cnt);
-            base = __shfl(base, leader);
-            if (base + cnt >= P.n_items) queue_empty = true;
-            if (state == 0) {
-                uint32_t my = base + (uint32_t)__popcll(need & below);
-                if (my < P.n_items && start_item(my)) state = 1;
+            if (pool_next == pool_end) {   // the wave's pool is used up: claim the next POOL positions
+                pool_next = queue.claim(P.claim);
+                pool_end = pool_next + P.claim;
+                if (queue.exhausted(pool_next)) { queue_empty = true; break; }
             }
+            const uint32_t cnt = min((uint32_t)__popcll(need), pool_end - pool_next);
+            const uint32_t base = pool_next;
+            pool_next += cnt;
+            if (state == 0) {
+                uint32_t rank = (uint32_t)__popcll(need & below);
+                uint64_t my = queue.at(base + rank);
+                if (rank < cnt && my < P.n_items && start_item((uint32_t)my)) state = 1;
+            }
+            if (queue.exhausted(pool_next)) queue_empty = true;
         }
         if (__ballot(state == 1) == 0) break;
 
         // ---- traversal: node phase then leaf phase for all busy lanes, until enough lanes are idle
         for (;;) {
-            bool occluded = false;
+            uint32_t occluded = 0u;
             trav_advance(sc, ray, ts, st, state == 1, ANY, occluded, node_visits, tri_tests);
             if (state == 1 && ts.cur == RC_STACK_EMPTY) {
-                if (!end_ray(occluded)) state = 0;
+                if (!end_ray(occluded != 0u)) state = 0;
             }
             uint32_t n_act = (uint32_t)__popcll(__ballot(state == 1));
             if (n_act == 0) break;
@@ -177,11 +225,17 @@ __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* cou
     uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
     TravRay ray;
     TravState ts;
+    const XcdQueue<RECT_CHUNK> queue(P.w.counters, P.slot, n_blocks);
+    uint32_t pos = 0, pos_end = 0;   // wave-uniform range of claimed positions
     for (;;) {
-        uint32_t blk = 0;
-        if (lane == 0) blk = atomicAdd(&P.w.counters[P.slot], 1u);
-        blk = __shfl(blk, 0);
-        if (blk >= n_blocks) break;
+        if (pos == pos_end) {
+            pos = queue.claim(P.claim);
+            pos_end = pos + P.claim;
+        }
+        const uint32_t j = pos++;
+        if (queue.exhausted(j)) break;
+        const uint64_t blk = queue.at(j);
+        if (blk >= n_blocks) continue;
         const uint64_t r = (uint64_t)blk * 64 + lane;
         const uint32_t item = (uint32_t)(r / N), k = (uint32_t)(r % N);
         uint32_t px = 0, pk = 0;
@@ -202,10 +256,212 @@ __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* cou
                 }
             }
         }
-        bool occluded = false;
+        uint32_t occluded = 0u;
         while (__ballot(busy && ts.cur != RC_STACK_EMPTY) != 0)
             trav_advance(sc, ray, ts, st, busy, true, occluded, node_visits, tri_tests);
-        const uint64_t vis = __ballot(busy && !occluded);
+        const uint64_t vis = __ballot(busy && occluded == 0u);
+        if (in_image && (lane == 0 || k == 0)) {
+            uint32_t end = (uint32_t)min<uint64_t>(64, lane + (N - k));
+            uint64_t seg = (end >= 64 ? ~0ull : ((1ull << end) - 1)) & ~((1ull << lane) - 1);
+            uint32_t c = (uint32_t)__popcll(vis & seg);
+            if (c) atomicAdd(counts + px, c);
+        }
+    }
+    if (P.w.ray_count) {
+        unsigned long long cnt[3] = {rays_cast, node_visits, tri_tests};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            unsigned long long v = cnt[q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) atomicAdd(P.w.ray_count + 2 * q, v);
+        }
+    }
+}
+
+// Per-pixel shadow-ray setup of the rect-light pass: (origin, 1) and (unit normal, 0) in FP32 from the
+// FP64 surface reconstruction, or (0, 0, 0, 0) for pixels without a primary hit.  Keeps the FP64 code
+// (and its registers) out of the traversal kernel.
+__global__ __launch_bounds__(256) void k_shadow_setup(DevScene sc, DevCamera cam, const uint4* gbuf, uint32_t n_pix,
+                                                      float4* setup)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pix) return;
+    const uint4 h = gbuf[i];
+    float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+    if (h.x != RC_NO_HIT) {
+        Surface S = rc_surface(sc, cam, i, 0, h.x);
+        D3 O = rc_shadow_origin(S);
+        a = make_float4((float)O.x, (float)O.y, (float)O.z, 1.0f);
+        b = make_float4((float)S.n.x, (float)S.n.y, (float)S.n.z, 0.0f);
+    }
+    setup[2 * (size_t)i] = a;
+    setup[2 * (size_t)i + 1] = b;
+}
+
+// Rect-light visibility, wave-uniform traversal.  The 64 ray slots of a wave (the samples of one
+// pixel, or the single samples of an 8x8 pixel tile) walk the BVH together: the wave visits a node
+// when any of its live rays hits one of its boxes, so node and triangle records are read once per wave
+// through the scalar cache, and the traversal stack is wave-uniform, held one entry per lane in two
+// registers (128 entries; the host uses this kernel when 3 x depth + 1 entries fit).  Each lane still
+// tests its own ray against every box and triangle the wave visits, with the same FP32 arithmetic as
+// the per-lane traversal; a triangle that a lane's own boxes would not have led to can only report a
+// true crossing, so the occlusion result of every ray is the one the per-lane traversal finds.
+// Children are visited nearest first by the entry distance of the lowest lane that hits them; the
+// distances are non-negative, so their bit patterns order like the values and the sort runs on the
+// scalar unit.  When all live rays share a direction octant (the usual case for a small light), the
+// near/far planes are picked once per wave, also on the scalar unit.
+typedef float rc_v4f __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) rc_v4f rc_const_v4f;
+
+template <bool UNIFORM_OCTANT>
+__device__ inline void wave_node_keys(const rc_v4f& lx, const rc_v4f& hx, const rc_v4f& ly, const rc_v4f& hy,
+                                      const rc_v4f& lz, const rc_v4f& hz, const TravRay& ray, uint32_t oct,
+                                      bool live, uint32_t key[4])
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float nx, fx, ny, fy, nz, fz;
+        if (UNIFORM_OCTANT) {
+            nx = (oct & 1u) ? hx[c] : lx[c]; fx = (oct & 1u) ? lx[c] : hx[c];
+            ny = (oct & 2u) ? hy[c] : ly[c]; fy = (oct & 2u) ? ly[c] : hy[c];
+            nz = (oct & 4u) ? hz[c] : lz[c]; fz = (oct & 4u) ? lz[c] : hz[c];
+        } else {
+            nx = ray.inv[0] >= 0.0f ? lx[c] : hx[c]; fx = ray.inv[0] >= 0.0f ? hx[c] : lx[c];
+            ny = ray.inv[1] >= 0.0f ? ly[c] : hy[c]; fy = ray.inv[1] >= 0.0f ? hy[c] : ly[c];
+            nz = ray.inv[2] >= 0.0f ? lz[c] : hz[c]; fz = ray.inv[2] >= 0.0f ? hz[c] : lz[c];
+        }
+        float t0 = fmaxf(fmaxf((nx - ray.o[0]) * ray.inv[0], (ny - ray.o[1]) * ray.inv[1]),
+                         fmaxf((nz - ray.o[2]) * ray.inv[2], 0.0f));
+        float t1 = fminf(fminf((fx - ray.o[0]) * ray.inv[0], (fy - ray.o[1]) * ray.inv[1]),
+                         (fz - ray.o[2]) * ray.inv[2]);
+        bool hit = live && t0 <= fminf(t1 * RC_FAR_GROW, 1.0f);
+        uint64_t m = __ballot(hit);
+        uint32_t k = 0x7F800000u;   // +inf: no live ray hits this child
+        if (m != 0) {
+            int first = __builtin_ctzll(m);
+            k = (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(t0), first) & 0x7FFFFFFFu;
+        }
+        key[c] = k;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
+{
+    const uint32_t lane = __lane_id();
+    const DevScene sc = P.sc;
+    const uint64_t N = (uint64_t)P.L.area_samples;
+    const uint64_t total = (uint64_t)P.n_items * N;
+    const uint64_t n_blocks = (total + 63) / 64;
+    const uint32_t KEY_MISS = 0x7F800000u;
+    uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
+    const XcdQueue<RECT_CHUNK> queue(P.w.counters, P.slot, n_blocks);
+    uint32_t pos = 0, pos_end = 0;   // wave-uniform range of claimed positions
+    for (;;) {
+        if (pos == pos_end) {
+            pos = queue.claim(P.claim);
+            pos_end = pos + P.claim;
+        }
+        const uint32_t j = pos++;
+        if (queue.exhausted(j)) break;
+        const uint64_t blk = queue.at(j);
+        if (blk >= n_blocks) continue;
+        const uint64_t r = (uint64_t)blk * 64 + lane;
+        const uint32_t item = (uint32_t)(r / N), k = (uint32_t)(r % N);
+        uint32_t px = 0, pk = 0;
+        const bool in_image = r < total && rc_item_to_sample(P.cam, item, px, pk);
+        TravRay ray;
+        bool busy = false;
+        if (in_image) {
+            const float4 a = setup[2 * (size_t)px], b = setup[2 * (size_t)px + 1];
+            if (a.w != 0.0f) {
+                float os[3] = {a.x, a.y, a.z}, nf[3] = {b.x, b.y, b.z};
+                busy = rc_shadow_ray(P.L.point[0], P.L.rect, P.nL, true, px, k, P.L.area_stream, P.cam.seed,
+                                     P.cam.frame, os, nf, ray);
+                if (busy) {
+#pragma unroll
+                    for (int a3 = 0; a3 < 3; ++a3) {
+                        float dd = fabsf(ray.d[a3]) < 1e-20f ? copysignf(1e-20f, ray.d[a3]) : ray.d[a3];
+                        ray.inv[a3] = 1.0f / dd;
+                    }
+                    ++rays_cast;
+                }
+            }
+        }
+        const uint64_t busy_mask = __ballot(busy);
+        const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
+                                (ray.inv[2] < 0.0f ? 4u : 0u);
+        uint32_t oct = 0;
+        if (busy_mask != 0) oct = (uint32_t)__builtin_amdgcn_readlane((int)my_oct, __builtin_ctzll(busy_mask));
+        const bool uniform_oct = __ballot(busy && my_oct != oct) == 0;
+        bool occ = false;
+        uint32_t cur = busy_mask != 0 ? 0u : RC_STACK_EMPTY;
+        int sp = 0;
+        uint32_t stk0 = 0, stk1 = 0;   // entry e of the wave's stack lives in lane e % 64 of stk{e / 64}
+        while (cur != RC_STACK_EMPTY) {
+            const bool live = busy && !occ;
+            if (!rc_is_leaf(cur)) {
+                rc_const_v4f* np = (rc_const_v4f*)(const void*)(sc.nodes + cur);
+                const rc_v4f lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+                const rc_v4f chf = np[6];
+                uint32_t key[4], cw[4];
+                if (uniform_oct) wave_node_keys<true>(lx, hx, ly, hy, lz, hz, ray, oct, live, key);
+                else wave_node_keys<false>(lx, hx, ly, hy, lz, hz, ray, oct, live, key);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cw[c] = __float_as_uint(chf[c]);
+                if (live) ++node_visits;
+#define RC_CS(a, b)                                                                   \
+    {                                                                                 \
+        bool sw = key[b] < key[a];                                                    \
+        uint32_t ka = sw ? key[b] : key[a], kb = sw ? key[a] : key[b];                \
+        uint32_t ca = sw ? cw[b] : cw[a], cb = sw ? cw[a] : cw[b];                    \
+        key[a] = ka; key[b] = kb; cw[a] = ca; cw[b] = cb;                             \
+    }
+                RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
+#undef RC_CS
+#pragma unroll
+                for (int c = 3; c >= 1; --c) {
+                    if (key[c] < KEY_MISS) {
+                        if (sp < 64) {
+                            stk0 = (int)lane == sp ? cw[c] : stk0;
+                            ++sp;
+                        } else if (sp < 128) {
+                            stk1 = (int)lane == sp - 64 ? cw[c] : stk1;
+                            ++sp;
+                        } else if (lane == 0) {
+                            *P.w.error_flag = 1u;   // beyond the bound the host checked: entry dropped, reported
+                        }
+                    }
+                }
+                if (key[0] < KEY_MISS) {
+                    cur = cw[0];
+                } else if (sp == 0) {
+                    cur = RC_STACK_EMPTY;
+                } else {
+                    --sp;
+                    cur = (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63);
+                }
+            } else {
+                const uint32_t first = rc_leaf_first(cur), cnt = rc_leaf_count(cur);
+                for (uint32_t i = 0; i < cnt; ++i) {
+                    rc_const_v4f* tp = (rc_const_v4f*)(const void*)(sc.tris + 3 * (size_t)(first + i));
+                    const rc_v4f A = tp[0], B = tp[1], C = tp[2];
+                    if (busy && !occ) {
+                        ++tri_tests;
+                        float t, u, v;
+                        bool hit = rc_mt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
+                        occ = hit && t < 1.0f;
+                    }
+                }
+                if (__ballot(busy && !occ) == 0 || sp == 0) {
+                    cur = RC_STACK_EMPTY;
+                } else {
+                    --sp;
+                    cur = (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63);
+                }
+            }
+            cur = __builtin_amdgcn_readfirstlane(cur);
+        }
+        const uint64_t vis = __ballot(busy && !occ);
         if (in_image && (lane == 0 || k == 0)) {
             uint32_t end = (uint32_t)min<uint64_t>(64, lane + (N - k));
             uint64_t seg = (end >= 64 ? ~0ull : ((1ull << end) - 1)) & ~((1ull << lane) - 1);
@@ -255,7 +511,9 @@ int rc_trace_grid(int device)
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, reinterpret_cast<const void*>(&k_rect_packets), BLOCK,
                                                  TravStack<SL, BLOCK, false>::lds_bytes());
-    return std::max(std::max(a, d * n_cu), std::max(b, c));
+    int e = 0;
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave), BLOCK, 0);
+    return std::max(std::max(std::max(a, d * n_cu), std::max(b, c)), e * n_cu);
 }
 
 void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, const TraceWork& w, int grid,
@@ -268,12 +526,13 @@ void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, co
     P.w = w;
     P.n_items = rc_n_items(cam.width, cam.height, cam.ssaa);
     P.slot = 0;
+    P.claim = claim_size(P.n_items, grid, 16, 32, 128);
     hipLaunchKernelGGL(k_trace<MODE_PRIMARY>, dim3(grid), dim3(BLOCK), lds_bytes<MODE_PRIMARY>(), st, P);
 }
 
 void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
-                      uint32_t* mask, float* visibility, uint32_t* counts, const TraceWork& w, int grid,
-                      hipStream_t st)
+                      uint32_t* mask, float* visibility, uint32_t* counts, float4* setup, const TraceWork& w,
+                      int grid, bool per_lane_rect, hipStream_t st)
 {
     KParams P = {};
     P.sc = sc;
@@ -286,6 +545,7 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     P.n_items = rc_n_items(cam.width, cam.height, cam.ssaa);
     if (L.n_point > 0) {
         P.slot = 1;
+        P.claim = claim_size(P.n_items, grid, 16, 32, 128);
         hipLaunchKernelGGL(k_trace<MODE_POINT>, dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
     }
     if (L.has_rect) {
@@ -295,10 +555,19 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
         for (int a = 0; a < 3; ++a) P.nL[a] = (float)(n[a] / len);
         P.slot = 2;
+        const uint64_t n_packets = ((uint64_t)P.n_items * (uint64_t)L.area_samples + 63) / 64;
+        P.claim = claim_size(n_packets, grid, 64, 1, 4);
         uint32_t n_pix = (uint32_t)(cam.width * cam.height);
         rc_launch_fill_u32(counts, 0u, n_pix, st);
-        const size_t lds = TravStack<SL, BLOCK, false>::lds_bytes();
-        hipLaunchKernelGGL(k_rect_packets, dim3(grid), dim3(BLOCK), lds, st, P, counts);
+        // the wave-uniform traversal pays off when a wave holds the samples of one pixel (common origin)
+        if (sc.max_stack <= 128 && !per_lane_rect && L.area_samples >= 64) {
+            hipLaunchKernelGGL(k_shadow_setup, dim3((n_pix + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_pix,
+                               setup);
+            hipLaunchKernelGGL(k_rect_wave, dim3(grid), dim3(BLOCK), 0, st, P, counts, (const float4*)setup);
+        } else {
+            const size_t lds = TravStack<SL, BLOCK, false>::lds_bytes();
+            hipLaunchKernelGGL(k_rect_packets, dim3(grid), dim3(BLOCK), lds, st, P, counts);
+        }
         hipLaunchKernelGGL(k_rect_finish, dim3((n_pix + 255) / 256), dim3(256), 0, st, counts, n_pix,
                            (uint32_t)L.area_samples, visibility);
     }

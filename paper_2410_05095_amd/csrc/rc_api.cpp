@@ -154,11 +154,11 @@ int rc_create(rc_ctx** out, int device, void* hip_stream)
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->grid = rc_trace_grid(device);
-    int st = dev_alloc(&c->d_counters, 16);
+    int st = dev_alloc(&c->d_counters, RC_COUNTER_WORDS);
     if (st == RC_OK) st = dev_alloc(&c->d_rays, 8);
     for (int i = 0; i < 4 && st == RC_OK; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) st = RC_ERR_HIP;
-    if (st == RC_OK && hipMemset(c->d_counters, 0, 16 * sizeof(uint32_t)) != hipSuccess) st = RC_ERR_HIP;
+    if (st == RC_OK && hipMemset(c->d_counters, 0, RC_COUNTER_WORDS * sizeof(uint32_t)) != hipSuccess) st = RC_ERR_HIP;
     if (st == RC_OK && hipMemset(c->d_rays, 0, 8 * sizeof(unsigned long long)) != hipSuccess) st = RC_ERR_HIP;
     if (st != RC_OK) { rc_destroy(c); return st; }
     *out = c;
@@ -448,6 +448,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
 
     hipStream_t q = c->stream;
     rc_launch_fill_u32(c->d_counters, 0u, 8, q);
+    rc_launch_fill_u32(c->d_counters + RC_QUEUE_BASE, 0u, RC_COUNTER_WORDS - RC_QUEUE_BASE, q);
     rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, q);
     uint4* gbuf = reinterpret_cast<uint4*>(out->d_hit);
     if (timing) RC_HIP(hipEventRecord(c->ev[0], q));
@@ -456,16 +457,21 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     if (timing) RC_HIP(hipEventRecord(c->ev[1], q));
     if (n_lights > 0 || rect) {
         size_t n_pix = (size_t)cam->width * cam->height;
+        // per pixel: one visible-sample counter, then (16-byte aligned) two float4 of shadow-ray setup
+        const size_t setup_off = (n_pix + 3) & ~(size_t)3;
         if (rect && n_pix > c->counts_cap) {
             RC_HIP(hipStreamSynchronize(q));
             dev_free(c->d_counts);
             c->counts_cap = 0;
-            st = dev_alloc(&c->d_counts, n_pix);
+            st = dev_alloc(&c->d_counts, setup_off + 8 * n_pix);
             if (st != RC_OK) return st;
             c->counts_cap = n_pix;
         }
         w.ray_count = c->d_rays + 1;
-        rc_launch_shadow(ds, dc, L, gbuf, out->d_shadow, out->d_visibility, c->d_counts, w, c->grid, q);
+        bool per_lane = opts && (opts->flags & RC_FLAG_PER_LANE_RECT);
+        float4* setup = rect ? reinterpret_cast<float4*>(c->d_counts + setup_off) : nullptr;
+        rc_launch_shadow(ds, dc, L, gbuf, out->d_shadow, out->d_visibility, c->d_counts, setup, w, c->grid, per_lane,
+                         q);
     }
     if (timing) RC_HIP(hipEventRecord(c->ev[2], q));
     rc_launch_shade(ds, dc, L, gbuf, n_lights ? out->d_shadow : nullptr, out->d_visibility, out->d_rgba,

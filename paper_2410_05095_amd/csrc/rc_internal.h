@@ -77,6 +77,12 @@ double rc_bvh_sah(const std::vector<Node4>& nodes);
 
 // Traversal launch geometry
 #define RC_TRACE_BLOCK 128
+// Work-queue counters: words [0, 8) single queues, [8] error flag; from word RC_QUEUE_BASE, per queue slot
+// one counter per XCD, each on its own 256-byte line.
+#define RC_XCDS 8
+#define RC_QUEUE_SLOTS 4
+#define RC_QUEUE_BASE 64
+#define RC_COUNTER_WORDS (RC_QUEUE_BASE + RC_QUEUE_SLOTS * RC_XCDS * 64)
 #define RC_STACK_LDS 24
 
 struct TraceWork {
@@ -92,8 +98,8 @@ struct TraceWork {
 void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, const TraceWork& w,
                        int grid, hipStream_t st);
 void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
-                      uint32_t* mask, float* visibility, uint32_t* counts, const TraceWork& w, int grid,
-                      hipStream_t st);
+                      uint32_t* mask, float* visibility, uint32_t* counts, float4* setup, const TraceWork& w,
+                      int grid, bool per_lane_rect, hipStream_t st);
 int rc_trace_grid(int device);
 
 // Batched rendering: one persistent launch over many views of several scenes.

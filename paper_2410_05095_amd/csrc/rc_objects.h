@@ -9,7 +9,7 @@ struct rc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int grid = 0;                         // persistent traversal grid (blocks)
-    uint32_t* d_counters = nullptr;       // [0..7] work queues, [8] error flag
+    uint32_t* d_counters = nullptr;       // RC_COUNTER_WORDS: work queues and the error flag
     unsigned long long* d_rays = nullptr; // [0] primary, [1] shadow rays cast
     uint32_t* d_overflow = nullptr;
     size_t overflow_words = 0;

@@ -125,39 +125,48 @@ __device__ inline void trav_visit_node(const DevScene& sc, const TravRay& r, Tra
     s.cur = tn[0] < INFINITY ? cw[0] : st.pop(s.sp, !any, s.best_t);
 }
 
+// Moller-Trumbore in FP32 on a packed triangle (v0, e1, e2): the fixed operation order every traversal
+// kernel uses.  Returns whether the ray's line crosses the triangle at t > 0 (edges inclusive).
+__device__ inline bool rc_mt(const TravRay& r, float ax, float ay, float az, float bx, float by, float bz, float cx,
+                             float cy, float cz, float& t, float& u, float& v)
+{
+    float px_ = r.d[1] * cz - r.d[2] * cy;
+    float py_ = r.d[2] * cx - r.d[0] * cz;
+    float pz_ = r.d[0] * cy - r.d[1] * cx;
+    float det = bx * px_ + by * py_;
+    det = det + bz * pz_;
+    float idet = __builtin_amdgcn_rcpf(det);
+    float sx = r.o[0] - ax, sy = r.o[1] - ay, sz = r.o[2] - az;
+    float su = sx * px_ + sy * py_;
+    su = su + sz * pz_;
+    u = su * idet;
+    float qx = sy * bz - sz * by;
+    float qy = sz * bx - sx * bz;
+    float qz = sx * by - sy * bx;
+    float sv = r.d[0] * qx + r.d[1] * qy;
+    sv = sv + r.d[2] * qz;
+    v = sv * idet;
+    float stq = cx * qx + cy * qy;
+    stq = stq + cz * qz;
+    t = stq * idet;
+    return u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f;
+}
+
 // Test the triangles of the leaf s.cur (Moller-Trumbore in FP32), then pop; an any-hit ray ends at its
 // first hit (occluded = true, s.cur = RC_STACK_EMPTY).
 template <class Stack>
 __device__ inline void trav_test_leaf(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool any,
-                                      bool& occluded, uint32_t& tri_tests)
+                                      uint32_t& occluded, uint32_t& tri_tests)
 {
     uint32_t first = rc_leaf_first(s.cur), cnt = rc_leaf_count(s.cur);
     for (uint32_t i = 0; i < cnt; ++i) {
         ++tri_tests;
         const float4* tp = sc.tris + 3 * (size_t)(first + i);
         float4 A = tp[0], B = tp[1], C = tp[2];
-        float px_ = r.d[1] * C.z - r.d[2] * C.y;
-        float py_ = r.d[2] * C.x - r.d[0] * C.z;
-        float pz_ = r.d[0] * C.y - r.d[1] * C.x;
-        float det = B.x * px_ + B.y * py_;
-        det = det + B.z * pz_;
-        float idet = __builtin_amdgcn_rcpf(det);
-        float sx = r.o[0] - A.x, sy = r.o[1] - A.y, sz = r.o[2] - A.z;
-        float su = sx * px_ + sy * py_;
-        su = su + sz * pz_;
-        float u = su * idet;
-        float qx = sy * B.z - sz * B.y;
-        float qy = sz * B.x - sx * B.z;
-        float qz = sx * B.y - sy * B.x;
-        float sv = r.d[0] * qx + r.d[1] * qy;
-        sv = sv + r.d[2] * qz;
-        float v = sv * idet;
-        float stq = C.x * qx + C.y * qy;
-        stq = stq + C.z * qz;
-        float t = stq * idet;
-        bool hit = u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f;
+        float t, u, v;
+        bool hit = rc_mt(r, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
         if (any) {
-            if (hit && t < 1.0f) { occluded = true; break; }
+            if (hit && t < 1.0f) { occluded = 1u; break; }
         } else {
             uint32_t id = __float_as_uint(A.w);
             if (hit && (t < s.best_t || (t == s.best_t && id < s.best_id))) {
@@ -165,7 +174,7 @@ __device__ inline void trav_test_leaf(const DevScene& sc, const TravRay& r, Trav
             }
         }
     }
-    s.cur = occluded ? RC_STACK_EMPTY : st.pop(s.sp, !any, s.best_t);
+    s.cur = occluded != 0u ? RC_STACK_EMPTY : st.pop(s.sp, !any, s.best_t);
 }
 
 // Advance every busy lane of the wave: first all lanes standing at an internal node visit nodes until
@@ -174,7 +183,7 @@ __device__ inline void trav_test_leaf(const DevScene& sc, const TravRay& r, Trav
 // grouping of the work into SIMD steps changes (fewer steps that execute both code paths).
 template <class Stack>
 __device__ inline void trav_advance(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool busy,
-                                    bool any, bool& occluded, uint32_t& node_visits, uint32_t& tri_tests)
+                                    bool any, uint32_t& occluded, uint32_t& node_visits, uint32_t& tri_tests)
 {
     for (;;) {
         bool inner = busy && !rc_is_leaf(s.cur);
