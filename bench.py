@@ -33,7 +33,7 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # the copy-kernel calibration), keyed by (workload, spp, hash of the traversal kernel sources); the
 # value only applies while those sources are unchanged (summaries under profiles/).
 MEASURED_TRAFFIC = {
-    ("big_7M", 64, "9fe43f8d64813cde:96fd43948bc92d3c:4dd9def12c30784b"): 786_300_000,
+    ("big_7M", 64, "af5ccf3ef2c2b6ee:96fd43948bc92d3c:9ea5758bf1aaf9d1"): 426_146_000,
 }
 
 
