@@ -101,6 +101,104 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a)
         }
 }
 
+// ---------------------------------------------------------------- 3x3 convolution, LDS-tiled
+// Workgroup of 4 waves; output tile = 4 rows x TW = 16 MT columns of one image, wave w computes row w:
+// MT 16-pixel M-tiles x NT 16-channel N-tiles.  The input halo (6 rows x TW + 2 columns) of a chunk of
+// CC channels is staged in LDS, zero outside the image, and the 9 taps read their shifted pixels from
+// there (each input value is fetched from memory once per tile instead of once per tap).  With a second
+// source the halo loader reads channels [0, Ca) from the 2x nearest-upsampled low-resolution tensor and
+// the rest from the skip tensor, so the decoder's upsample + concat is never materialised.
+template <int MT, int NT, int CC>
+__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
+{
+    extern __shared__ uint4 conv_lds[];
+    constexpr int TW = 16 * MT, HW = TW + 2, HR = 6;
+    constexpr int PST = CC + 8;   // LDS pixel stride in bf16 elements (padding against bank conflicts)
+    uint16_t* lds = reinterpret_cast<uint16_t*>(conv_lds);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + 3) / 4;
+    int tt = blockIdx.x;
+    const int tx = tt % tiles_x;
+    tt /= tiles_x;
+    const int ty = tt % tiles_y, n = tt / tiles_y;
+    const int x0 = tx * TW, y0 = ty * 4;
+    const int r = lane & 15, g = lane >> 4;
+    const int K = 9 * a.Cin;
+    const int Cs = a.Cin - a.Ca;
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    for (int c0 = 0; c0 < a.Cin; c0 += CC) {
+        __syncthreads();
+        constexpr int GROUPS = CC / 8;
+        for (int i = threadIdx.x; i < HR * HW * GROUPS; i += 256) {
+            const int gg = i % GROUPS, pix = i / GROUPS;
+            const int hx = pix % HW, hy = pix / HW;
+            const int y = y0 - 1 + hy, x = x0 - 1 + hx;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
+                const int ci = c0 + 8 * gg;
+                if (a.in2 == nullptr)
+                    v = *reinterpret_cast<const uint4*>(a.in + ((size_t)(n * a.H + y) * a.W + x) * a.Cin + ci);
+                else if (ci < a.Ca)
+                    v = *reinterpret_cast<const uint4*>(
+                        a.in + ((size_t)(n * (a.H / 2) + y / 2) * (a.W / 2) + x / 2) * a.Ca + ci);
+                else
+                    v = *reinterpret_cast<const uint4*>(a.in2 + ((size_t)(n * a.H + y) * a.W + x) * Cs + (ci - a.Ca));
+            }
+            *reinterpret_cast<uint4*>(lds + pix * PST + 8 * gg) = v;
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < 9 * CC; k0 += 32) {
+            const int kk = k0 + 8 * g;
+            const bool kv = kk < 9 * CC;
+            const int tap = kv ? kk / CC : 0;
+            const int cl = kk - tap * CC;
+            const int dy = tap / 3, dx = tap % 3;
+            bf16x8 A[MT], B[NT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                A[mt] = kv ? __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                                 lds + ((wave + dy) * HW + 16 * mt + r + dx) * PST + cl))
+                           : zero;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = 16 * nt + r;
+                B[nt] = (kv && co < a.Cout) ? load8(a.wt + (size_t)co * K + tap * a.Cin + c0 + cl) : zero;
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+    // D layout: lane holds column (channel) 16 nt + (lane & 15), rows (pixels) 4 (lane >> 4) + i
+    const int y = y0 + wave;
+    if (y >= a.H) return;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = 16 * nt + r;
+            if (co >= a.Cout) continue;
+            const float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 16 * mt + 4 * g + i;
+                if (x >= a.W) continue;
+                float v = acc[mt][nt][i] + b;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                const size_t o = ((size_t)(n * a.H + y) * a.W + x) * a.Cout + co;
+                if (a.mask && !(bf2f(a.mask[o]) > 0.0f)) v = 0.0f;
+                a.out[o] = f2bf(v);
+            }
+        }
+}
+
 // ---------------------------------------------------------------- weight gradient
 // One wave per (pixel chunk, tap, 16-channel output tile, 16-channel input tile).
 __global__ __launch_bounds__(64) void k_wgrad(WgradArgs a)
@@ -158,30 +256,97 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const float* partial, int
     out[i] = add ? out[i] + s : s;
 }
 
-// per-chunk column sums of a bf16 [P][C] tensor: partial[chunk][c]; fixed order within a chunk
-__global__ __launch_bounds__(256) void k_colsum(const uint16_t* g, int P, int C, int chunk, float* partial)
+// Column sums of a bf16 [P][C] tensor (C a multiple of 8, at most 256), per block of COLSUM_ROWS pixels:
+// a thread sums 8 channels over every G-th pixel of the block (G = 2048 / C pixel groups), then the
+// groups are added in a fixed tree order, so the result does not depend on scheduling.
+constexpr int COLSUM_ROWS = 1024;
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t* g, int P, int C, float* partial)
 {
-    int c = blockIdx.y * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    int p0 = blockIdx.x * chunk, pe = min(P, p0 + chunk);
+    __shared__ float sm[8][256];
+    const int cg_n = C / 8, G = 256 / cg_n;
+    const int t = threadIdx.x, cg = t % cg_n, grp = t / cg_n;
+    const int p0 = blockIdx.x * COLSUM_ROWS, pe = min(P, p0 + COLSUM_ROWS);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (grp < G) {
+        for (int p = p0 + grp; p < pe; p += G) {
+            uint4 v = *reinterpret_cast<const uint4*>(g + (size_t)p * C + 8 * cg);
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                acc[2 * e] += __uint_as_float(w[e] << 16);
+                acc[2 * e + 1] += __uint_as_float(w[e] & 0xFFFF0000u);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sm[e][t] = acc[e];
+    __syncthreads();
+    for (int h = G / 2; h > 0; h >>= 1) {
+        if (grp < h) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sm[e][t] += sm[e][t + h * cg_n];
+        }
+        __syncthreads();
+    }
+    if (grp == 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) partial[(size_t)blockIdx.x * C + 8 * cg + e] = sm[e][t];
+    }
+}
+
+// out[o] (+)= sum over blocks b of partial[b][o], o < n: one workgroup per output, fixed-order tree
+__global__ __launch_bounds__(256) void k_reduce_blocks(const float* partial, int nb, int n, float* out, int add)
+{
+    __shared__ float sm[256];
+    const int o = blockIdx.x, t = threadIdx.x;
     float s = 0.0f;
-    for (int p = p0; p < pe; ++p) s += bf2f(g[(size_t)p * C + c]);
-    partial[(size_t)blockIdx.x * C + c] = s;
+    for (int b = t; b < nb; b += 256) s += partial[(size_t)b * n + o];
+    sm[t] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) sm[t] += sm[t + h];
+        __syncthreads();
+    }
+    if (t == 0) out[o] = add ? out[o] + sm[0] : sm[0];
 }
 
 // ---------------------------------------------------------------- pooling / upsampling / concat
+// All channel counts and offsets are multiples of 8: one thread handles 8 channels (16 bytes).
+__device__ inline void unpack8(uint4 v, float f[8])
+{
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        f[2 * e] = __uint_as_float(w[e] << 16);
+        f[2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
+    }
+}
+__device__ inline uint4 pack8(const float f[8])
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w[e] = (uint32_t)f2bf(f[2 * e]) | ((uint32_t)f2bf(f[2 * e + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+__device__ inline uint4 ld8(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ inline void st8(uint16_t* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; }
+
 __global__ __launch_bounds__(256) void k_pool2(const uint16_t* in, int N, int H, int W, int C, uint16_t* out)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int h = H / 2, w = W / 2;
-    size_t total = (size_t)N * h * w * C;
+    int h = H / 2, w = W / 2, C8 = C / 8;
+    size_t total = (size_t)N * h * w * C8;
     if (i >= total) return;
-    int c = (int)(i % C);
-    size_t q = i / C;
+    int c = (int)(i % C8) * 8;
+    size_t q = i / C8;
     int x = (int)(q % w), t = (int)(q / w), y = t % h, n = t / h;
     const uint16_t* b = in + (((size_t)n * H + 2 * y) * W + 2 * x) * C + c;
-    float s = (bf2f(b[0]) + bf2f(b[C])) + (bf2f(b[(size_t)W * C]) + bf2f(b[(size_t)W * C + C]));
-    out[i] = f2bf(s * 0.25f);
+    float a[8], bb[8], cc[8], d[8], r[8];
+    unpack8(ld8(b), a); unpack8(ld8(b + C), bb);
+    unpack8(ld8(b + (size_t)W * C), cc); unpack8(ld8(b + (size_t)W * C + C), d);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = ((a[e] + bb[e]) + (cc[e] + d[e])) * 0.25f;
+    st8(out + q * C + c, pack8(r));
 }
 
 // out[N,2h,2w,Ca+Cs] = [nearest-upsampled a (Ca channels), skip (Cs channels)]
@@ -189,14 +354,15 @@ __global__ __launch_bounds__(256) void k_up2_concat(const uint16_t* a, const uin
                                                     int Ca, int Cs, uint16_t* out)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int C = Ca + Cs;
-    size_t total = (size_t)N * H * W * C;
+    int C = Ca + Cs, C8 = C / 8;
+    size_t total = (size_t)N * H * W * C8;
     if (i >= total) return;
-    int c = (int)(i % C);
-    size_t q = i / C;
+    int c = (int)(i % C8) * 8;
+    size_t q = i / C8;
     int x = (int)(q % W), t = (int)(q / W), y = t % H, n = t / H;
-    if (c < Ca) out[i] = a[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * Ca + c];
-    else out[i] = skip[q * Cs + (c - Ca)];
+    uint4 v = c < Ca ? ld8(a + (((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * Ca + c)
+                     : ld8(skip + q * Cs + (c - Ca));
+    st8(out + q * C + c, v);
 }
 
 // gradient of the upsampled part of a concat: out[n,y,x,c] = mask * sum_{2x2} g[n,2y+a,2x+b, c0 + c]
@@ -204,16 +370,23 @@ __global__ __launch_bounds__(256) void k_up_back_mask(const uint16_t* g, int N, 
                                                       int C, const uint16_t* mask, uint16_t* out)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int h = H2 / 2, w = W2 / 2;
-    size_t total = (size_t)N * h * w * C;
+    int h = H2 / 2, w = W2 / 2, C8 = C / 8;
+    size_t total = (size_t)N * h * w * C8;
     if (i >= total) return;
-    int c = (int)(i % C);
-    size_t q = i / C;
+    int c = (int)(i % C8) * 8;
+    size_t q = i / C8;
     int x = (int)(q % w), t = (int)(q / w), y = t % h, n = t / h;
     const uint16_t* b = g + (((size_t)n * H2 + 2 * y) * W2 + 2 * x) * Ctot + c0 + c;
-    float s = (bf2f(b[0]) + bf2f(b[Ctot])) + (bf2f(b[(size_t)W2 * Ctot]) + bf2f(b[(size_t)W2 * Ctot + Ctot]));
-    if (!(bf2f(mask[i]) > 0.0f)) s = 0.0f;
-    out[i] = f2bf(s);
+    float a[8], bb[8], cc[8], d[8], mk[8], r[8];
+    unpack8(ld8(b), a); unpack8(ld8(b + Ctot), bb);
+    unpack8(ld8(b + (size_t)W2 * Ctot), cc); unpack8(ld8(b + (size_t)W2 * Ctot + Ctot), d);
+    unpack8(ld8(mask + q * C + c), mk);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        float s = (a[e] + bb[e]) + (cc[e] + d[e]);
+        r[e] = mk[e] > 0.0f ? s : 0.0f;
+    }
+    st8(out + q * C + c, pack8(r));
 }
 
 // out[n,y,x,c] = mask * (gpool[n,y/2,x/2,c] / 4 + gcat[n,y,x,c0 + c])
@@ -222,15 +395,23 @@ __global__ __launch_bounds__(256) void k_pool_back_add_mask(const uint16_t* gpoo
                                                             uint16_t* out)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t total = (size_t)N * H * W * C;
+    int C8 = C / 8;
+    size_t total = (size_t)N * H * W * C8;
     if (i >= total) return;
-    int c = (int)(i % C);
-    size_t q = i / C;
+    int c = (int)(i % C8) * 8;
+    size_t q = i / C8;
     int x = (int)(q % W), t = (int)(q / W), y = t % H, n = t / H;
-    float v = bf2f(gpool[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]) * 0.25f;
-    v = v + bf2f(gcat[q * Ctot + c0 + c]);
-    if (!(bf2f(mask[i]) > 0.0f)) v = 0.0f;
-    out[i] = f2bf(v);
+    float gp[8], gc[8], mk[8], r[8];
+    unpack8(ld8(gpool + (((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c), gp);
+    unpack8(ld8(gcat + q * Ctot + c0 + c), gc);
+    unpack8(ld8(mask + q * C + c), mk);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        float v = gp[e] * 0.25f;
+        v = v + gc[e];
+        r[e] = mk[e] > 0.0f ? v : 0.0f;
+    }
+    st8(out + q * C + c, pack8(r));
 }
 
 // ---------------------------------------------------------------- head, loss
@@ -278,29 +459,54 @@ __global__ void k_loss_final(const float* partial, int n, float* sums)
     sums[1] = b / fmaxf(a, 1.0f);
 }
 
-// dlogit = 2 m (y - t) / max(sum m, 1) * y (1 - y); gpre_d1 = mask(d1 > 0) * dlogit * wh; per-chunk partial
-// head gradients (32 weights + bias) in fixed order
-__global__ __launch_bounds__(64) void k_head_back(const uint16_t* d1, const float* y, const float* t, const float* m,
-                                                  const float* sums, const float* wh, int P, int chunk,
-                                                  uint16_t* gpre, float* partial)
+// dlogit = 2 m (y - t) / max(sum m, 1) * y (1 - y); gpre_d1 = mask(d1 > 0) * dlogit * wh; one pixel per
+// thread, and per block of 256 pixels the partial head gradients (32 weights, then the bias) summed in a
+// fixed tree order
+__global__ __launch_bounds__(256) void k_head_back(const uint16_t* d1, const float* y, const float* t, const float* m,
+                                                   const float* sums, const float* wh, int P, uint16_t* gpre,
+                                                   float* partial)
 {
-    const int c = threadIdx.x;   // 0..31 weights, 32 bias
-    int p0 = blockIdx.x * chunk, pe = min(P, p0 + chunk);
-    float inv = 2.0f / fmaxf(sums[0], 1.0f);
-    float whc = c < 32 ? bf2f(f2bf(wh[c])) : 0.0f;
-    float acc = 0.0f;
-    for (int p = p0; p < pe; ++p) {
-        float yy = y[p];
-        float dl = m[p] * (yy - t[p]) * inv * yy * (1.0f - yy);
-        if (c < 32) {
-            float a = bf2f(d1[(size_t)p * 32 + c]);
-            acc += dl * a;
-            gpre[(size_t)p * 32 + c] = f2bf(a > 0.0f ? dl * whc : 0.0f);
-        } else if (c == 32) {
-            acc += dl;
+    __shared__ float sm[33][256];
+    const int tid = threadIdx.x;
+    const int p = blockIdx.x * 256 + tid;
+    float v[33];
+#pragma unroll
+    for (int c = 0; c < 33; ++c) v[c] = 0.0f;
+    if (p < P) {
+        const float inv = 2.0f / fmaxf(sums[0], 1.0f);
+        const float yy = y[p];
+        const float dl = m[p] * (yy - t[p]) * inv * yy * (1.0f - yy);
+        const uint4* row = reinterpret_cast<const uint4*>(d1 + (size_t)p * 32);
+        uint4* out = reinterpret_cast<uint4*>(gpre + (size_t)p * 32);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint4 r = row[q];
+            uint32_t w[4] = {r.x, r.y, r.z, r.w}, o[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float a0 = __uint_as_float(w[e] << 16), a1 = __uint_as_float(w[e] & 0xFFFF0000u);
+                int c = 8 * q + 2 * e;
+                v[c] = dl * a0;
+                v[c + 1] = dl * a1;
+                uint32_t g0 = a0 > 0.0f ? f2bf(dl * bf2f(f2bf(wh[c]))) : 0u;
+                uint32_t g1 = a1 > 0.0f ? f2bf(dl * bf2f(f2bf(wh[c + 1]))) : 0u;
+                o[e] = g0 | (g1 << 16);
+            }
+            out[q] = make_uint4(o[0], o[1], o[2], o[3]);
         }
+        v[32] = dl;
     }
-    if (c < 33) partial[(size_t)blockIdx.x * 33 + c] = acc;
+#pragma unroll
+    for (int c = 0; c < 33; ++c) sm[c][tid] = v[c];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+#pragma unroll
+            for (int c = 0; c < 33; ++c) sm[c][tid] += sm[c][tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid < 33) partial[(size_t)blockIdx.x * 33 + tid] = sm[tid][0];
 }
 
 // ---------------------------------------------------------------- weights, Adam, features
@@ -340,7 +546,34 @@ inline unsigned nb(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
+template <int MT, int NT, int CC>
+void launch_conv_lds(const ConvArgs& a, hipStream_t st)
+{
+    constexpr int TW = 16 * MT;
+    const size_t tiles = (size_t)a.N * ((a.H + 3) / 4) * ((a.W + TW - 1) / TW);
+    const size_t lds = (size_t)6 * (TW + 2) * (CC + 8) * 2;
+    hipLaunchKernelGGL((k_conv_lds<MT, NT, CC>), dim3((unsigned)tiles), dim3(256), lds, st, a);
+}
+
 void unet_conv3x3(const ConvArgs& a, hipStream_t st)
+{
+    const int nt = (a.Cout + 15) / 16;
+    const int cc = a.Cin % 64 == 0 ? 64 : (a.Cin % 32 == 0 ? 32 : 8);
+    switch (nt * 100 + cc) {
+    case 208: launch_conv_lds<4, 2, 8>(a, st); return;
+    case 232: launch_conv_lds<4, 2, 32>(a, st); return;
+    case 264: launch_conv_lds<4, 2, 64>(a, st); return;
+    case 432: launch_conv_lds<4, 4, 32>(a, st); return;
+    case 464: launch_conv_lds<4, 4, 64>(a, st); return;
+    case 632: launch_conv_lds<2, 6, 32>(a, st); return;
+    case 864: launch_conv_lds<2, 8, 64>(a, st); return;
+    case 1264: launch_conv_lds<2, 12, 64>(a, st); return;
+    default: break;
+    }
+    unet_conv3x3_direct(a, st);
+}
+
+void unet_conv3x3_direct(const ConvArgs& a, hipStream_t st)
 {
     size_t P = (size_t)a.N * a.H * a.W;
     dim3 grid(nb(P, 128)), block(256);
@@ -371,36 +604,42 @@ void unet_reduce_chunks(const float* partial, int n_chunks, int n, float* out, i
     hipLaunchKernelGGL(k_reduce_chunks, dim3(nb(n, 256)), dim3(256), 0, st, partial, n_chunks, n, out, add);
 }
 
-void unet_colsum(const uint16_t* g, int P, int C, int chunk, float* partial, hipStream_t st)
+int unet_colsum_blocks(int P) { return (P + COLSUM_ROWS - 1) / COLSUM_ROWS; }
+
+void unet_colsum(const uint16_t* g, int P, int C, float* partial, hipStream_t st)
 {
-    int chunks = (P + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_colsum, dim3(chunks, nb(C, 256)), dim3(256), 0, st, g, P, C, chunk, partial);
+    hipLaunchKernelGGL(k_colsum, dim3(unet_colsum_blocks(P)), dim3(256), 0, st, g, P, C, partial);
+}
+
+void unet_reduce_blocks(const float* partial, int n_blocks, int n, float* out, int add, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_blocks, dim3(n), dim3(256), 0, st, partial, n_blocks, n, out, add);
 }
 
 void unet_pool2(const uint16_t* in, int N, int H, int W, int C, uint16_t* out, hipStream_t st)
 {
-    size_t n = (size_t)N * (H / 2) * (W / 2) * C;
+    size_t n = (size_t)N * (H / 2) * (W / 2) * (C / 8);
     hipLaunchKernelGGL(k_pool2, dim3(nb(n, 256)), dim3(256), 0, st, in, N, H, W, C, out);
 }
 
 void unet_up2_concat(const uint16_t* a, const uint16_t* skip, int N, int H, int W, int Ca, int Cs, uint16_t* out,
                      hipStream_t st)
 {
-    size_t n = (size_t)N * H * W * (Ca + Cs);
+    size_t n = (size_t)N * H * W * ((Ca + Cs) / 8);
     hipLaunchKernelGGL(k_up2_concat, dim3(nb(n, 256)), dim3(256), 0, st, a, skip, N, H, W, Ca, Cs, out);
 }
 
 void unet_up_back_mask(const uint16_t* g, int N, int H2, int W2, int Ctot, int c0, int C, const uint16_t* mask,
                        uint16_t* out, hipStream_t st)
 {
-    size_t n = (size_t)N * (H2 / 2) * (W2 / 2) * C;
+    size_t n = (size_t)N * (H2 / 2) * (W2 / 2) * (C / 8);
     hipLaunchKernelGGL(k_up_back_mask, dim3(nb(n, 256)), dim3(256), 0, st, g, N, H2, W2, Ctot, c0, C, mask, out);
 }
 
 void unet_pool_back_add_mask(const uint16_t* gpool, const uint16_t* gcat, int N, int H, int W, int C, int Ctot, int c0,
                              const uint16_t* mask, uint16_t* out, hipStream_t st)
 {
-    size_t n = (size_t)N * H * W * C;
+    size_t n = (size_t)N * H * W * (C / 8);
     hipLaunchKernelGGL(k_pool_back_add_mask, dim3(nb(n, 256)), dim3(256), 0, st, gpool, gcat, N, H, W, C, Ctot, c0,
                        mask, out);
 }
@@ -418,11 +657,13 @@ void unet_loss(const float* y, const float* t, const float* m, int P, int chunk,
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, partial, chunks, sums);
 }
 
+int unet_head_blocks(int P) { return (P + 255) / 256; }
+
 void unet_head_back(const uint16_t* d1, const float* y, const float* t, const float* m, const float* sums,
-                    const float* wh, int P, int chunk, uint16_t* gpre, float* partial, hipStream_t st)
+                    const float* wh, int P, uint16_t* gpre, float* partial, hipStream_t st)
 {
-    int chunks = (P + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_head_back, dim3(chunks), dim3(64), 0, st, d1, y, t, m, sums, wh, P, chunk, gpre, partial);
+    hipLaunchKernelGGL(k_head_back, dim3(unet_head_blocks(P)), dim3(256), 0, st, d1, y, t, m, sums, wh, P, gpre,
+                       partial);
 }
 
 void unet_weights_bf16(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t* wb, hipStream_t st)

@@ -137,10 +137,13 @@ int chunk_for(size_t P)
     return (int)((c + 31) & ~size_t(31));
 }
 
-void conv(rc_denoiser* d, const uint16_t* in, int n, int h, int w, int l, uint16_t* out, hipStream_t st)
+// layer l; with `skip`, the input is [2x nearest-upsampled `in` (Ca channels), skip] read directly
+void conv(rc_denoiser* d, const uint16_t* in, int n, int h, int w, int l, uint16_t* out, hipStream_t st,
+          const uint16_t* skip = nullptr, int Ca = 0)
 {
-    ConvArgs a;
-    a.in = in; a.N = n; a.H = h; a.W = w; a.Cin = LAYERS[l].cin;
+    ConvArgs a = {};
+    a.in = in; a.in2 = skip; a.Ca = Ca;
+    a.N = n; a.H = h; a.W = w; a.Cin = LAYERS[l].cin;
     a.wt = d->d_wbf + d->off_bf[l];
     a.bias = d->d_w + d->off_b[l];
     a.mask = nullptr;
@@ -154,7 +157,7 @@ void conv(rc_denoiser* d, const uint16_t* in, int n, int h, int w, int l, uint16
 void conv_back_data(rc_denoiser* d, const uint16_t* g, int n, int h, int w, int l, const uint16_t* mask,
                     uint16_t* out, hipStream_t st)
 {
-    ConvArgs a;
+    ConvArgs a = {};
     a.in = g; a.N = n; a.H = h; a.W = w; a.Cin = LAYERS[l].cout;
     a.wt = d->d_wfl + d->off_bf[l];
     a.bias = nullptr;
@@ -177,11 +180,12 @@ void conv_back_weights(rc_denoiser* d, const uint16_t* x, const uint16_t* g, int
     a.partial = d->d_partial;
     unet_wgrad(a, st);
     unet_reduce_chunks(d->d_partial, chunks, (int)layer_w(l), d->d_g + d->off_w[l], 0, st);
-    unet_colsum(g, (int)P, LAYERS[l].cout, chunk, d->d_partial, st);
-    unet_reduce_chunks(d->d_partial, chunks, LAYERS[l].cout, d->d_g + d->off_b[l], 0, st);
+    unet_colsum(g, (int)P, LAYERS[l].cout, d->d_partial, st);
+    unet_reduce_blocks(d->d_partial, unet_colsum_blocks((int)P), LAYERS[l].cout, d->d_g + d->off_b[l], 0, st);
 }
 
-int forward(rc_denoiser* d, const uint16_t* x, int n, int h, int w, hipStream_t st)
+// keep_concat: also materialise the decoder's concatenated inputs (the weight gradients read them)
+int forward(rc_denoiser* d, const uint16_t* x, int n, int h, int w, hipStream_t st, bool keep_concat)
 {
     int st_ = ensure_workspace(d, n, h, w);
     if (st_ != RC_OK) return st_;
@@ -195,11 +199,11 @@ int forward(rc_denoiser* d, const uint16_t* x, int n, int h, int w, hipStream_t 
     unet_pool2(A + d->a_e2b, n, h2, w2, 64, A + d->a_p2, st);
     conv(d, A + d->a_p2, n, h4, w4, BNA, A + d->a_bna, st);
     conv(d, A + d->a_bna, n, h4, w4, BNB, A + d->a_bnb, st);
-    unet_up2_concat(A + d->a_bnb, A + d->a_e2b, n, h2, w2, 128, 64, A + d->a_u2, st);
-    conv(d, A + d->a_u2, n, h2, w2, D2A, A + d->a_d2a, st);
+    if (keep_concat) unet_up2_concat(A + d->a_bnb, A + d->a_e2b, n, h2, w2, 128, 64, A + d->a_u2, st);
+    conv(d, A + d->a_bnb, n, h2, w2, D2A, A + d->a_d2a, st, A + d->a_e2b, 128);
     conv(d, A + d->a_d2a, n, h2, w2, D2B, A + d->a_d2b, st);
-    unet_up2_concat(A + d->a_d2b, A + d->a_e1b, n, h, w, 64, 32, A + d->a_u1, st);
-    conv(d, A + d->a_u1, n, h, w, D1A, A + d->a_d1a, st);
+    if (keep_concat) unet_up2_concat(A + d->a_d2b, A + d->a_e1b, n, h, w, 64, 32, A + d->a_u1, st);
+    conv(d, A + d->a_d2b, n, h, w, D1A, A + d->a_d1a, st, A + d->a_e1b, 64);
     conv(d, A + d->a_d1a, n, h, w, D1B, A + d->a_d1b, st);
     unet_head(A + d->a_d1b, d->d_w + d->off_w[N_LAYERS], d->d_w + d->off_b[N_LAYERS], n * h * w, d->d_y, st);
     DN_HIP(hipGetLastError());
@@ -217,14 +221,16 @@ int backward(rc_denoiser* d, const uint16_t* x, const float* t, const float* m, 
     size_t need = 0;
     for (int l = 0; l < N_LAYERS; ++l) need = std::max(need, (size_t)chunks * layer_w(l));
     need = std::max(need, (size_t)chunks * 64);
+    need = std::max(need, (size_t)unet_colsum_blocks((int)P) * 128);
+    need = std::max(need, (size_t)unet_head_blocks((int)P) * 33);
     int st_ = ensure_partial(d, need);
     if (st_ != RC_OK) return st_;
     if (!d->d_sums) DN_HIP(hipMalloc(reinterpret_cast<void**>(&d->d_sums), 64));
     // loss and head
     unet_loss(d->d_y, t, m, (int)P, chunk, d->d_partial, d->d_sums, st);
-    unet_head_back(A + d->a_d1b, d->d_y, t, m, d->d_sums, d->d_w + d->off_w[N_LAYERS], (int)P, chunk, G + d->g_d1b,
+    unet_head_back(A + d->a_d1b, d->d_y, t, m, d->d_sums, d->d_w + d->off_w[N_LAYERS], (int)P, G + d->g_d1b,
                    d->d_partial, st);
-    unet_reduce_chunks(d->d_partial, chunks, 33, d->d_g + d->off_w[N_LAYERS], 0, st);   // head.w then head.b
+    unet_reduce_blocks(d->d_partial, unet_head_blocks((int)P), 33, d->d_g + d->off_w[N_LAYERS], 0, st);   // head.w, head.b
     // decoder level 1
     conv_back_weights(d, A + d->a_d1a, G + d->g_d1b, n, h, w, D1B, st);
     conv_back_data(d, G + d->g_d1b, n, h, w, D1B, A + d->a_d1a, G + d->g_d1a, st);
@@ -380,7 +386,7 @@ int rc_denoiser_infer(rc_ctx* c, rc_denoiser* d, const uint16_t* d_feat, uint32_
     if (reinterpret_cast<uintptr_t>(d_feat) & 15u) return RC_ERR_INVALID_ARG;
     DN_HIP(hipSetDevice(d->device));
     hipStream_t s = ctx_stream(c);
-    int st = forward(d, d_feat, (int)n, (int)h, (int)w, s);
+    int st = forward(d, d_feat, (int)n, (int)h, (int)w, s, false);
     if (st != RC_OK) return st;
     DN_HIP(hipMemcpyAsync(d_out, d->d_y, (size_t)n * h * w * 4, hipMemcpyDeviceToDevice, s));
     return RC_OK;
@@ -394,7 +400,7 @@ int rc_denoiser_train_step(rc_ctx* c, rc_denoiser* d, const uint16_t* d_feat, co
     if (reinterpret_cast<uintptr_t>(d_feat) & 15u) return RC_ERR_INVALID_ARG;
     DN_HIP(hipSetDevice(d->device));
     hipStream_t s = ctx_stream(c);
-    int st = forward(d, d_feat, (int)n, (int)h, (int)w, s);
+    int st = forward(d, d_feat, (int)n, (int)h, (int)w, s, true);
     if (st == RC_OK) st = backward(d, d_feat, d_target, d_mask, (int)n, (int)h, (int)w, s);
     if (st != RC_OK) return st;
     d->step++;

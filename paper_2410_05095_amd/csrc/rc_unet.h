@@ -5,7 +5,10 @@
 #include <stdint.h>
 
 struct ConvArgs {
-    const uint16_t* in;     // NHWC bf16, Cin channels (Cin a multiple of 8)
+    const uint16_t* in;     // NHWC bf16, Cin channels (Cin a multiple of 8); with in2: N x H/2 x W/2 x Ca
+    const uint16_t* in2;    // optional second source: the input is the concatenation of the 2x nearest-
+                            // upsampled `in` (channels [0, Ca)) and in2 (N x H x W x (Cin - Ca))
+    int Ca;
     int N, H, W, Cin;
     const uint16_t* wt;     // [Cout][9][Cin] bf16
     const float* bias;      // Cout floats or NULL
@@ -23,11 +26,17 @@ struct WgradArgs {
     float* partial;         // [chunks][Cout][9][Cin]
 };
 
+// LDS-tiled kernel for the channel counts of this network (any in2); unet_conv3x3_direct: the direct
+// kernel without LDS staging (no second source)
 void unet_conv3x3(const ConvArgs& a, hipStream_t st);
+void unet_conv3x3_direct(const ConvArgs& a, hipStream_t st);
 int unet_wgrad_chunks(size_t P, int chunk);
 void unet_wgrad(const WgradArgs& a, hipStream_t st);
 void unet_reduce_chunks(const float* partial, int n_chunks, int n, float* out, int add, hipStream_t st);
-void unet_colsum(const uint16_t* g, int P, int C, int chunk, float* partial, hipStream_t st);
+// bias gradients: per-block column sums, then a fixed-order reduction over the blocks
+int unet_colsum_blocks(int P);
+void unet_colsum(const uint16_t* g, int P, int C, float* partial, hipStream_t st);
+void unet_reduce_blocks(const float* partial, int n_blocks, int n, float* out, int add, hipStream_t st);
 void unet_pool2(const uint16_t* in, int N, int H, int W, int C, uint16_t* out, hipStream_t st);
 void unet_up2_concat(const uint16_t* a, const uint16_t* skip, int N, int H, int W, int Ca, int Cs, uint16_t* out,
                      hipStream_t st);
@@ -38,8 +47,9 @@ void unet_pool_back_add_mask(const uint16_t* gpool, const uint16_t* gcat, int N,
 void unet_head(const uint16_t* d1, const float* wh, const float* bh, int P, float* y, hipStream_t st);
 void unet_loss(const float* y, const float* t, const float* m, int P, int chunk, float* partial, float* sums,
                hipStream_t st);
+int unet_head_blocks(int P);
 void unet_head_back(const uint16_t* d1, const float* y, const float* t, const float* m, const float* sums,
-                    const float* wh, int P, int chunk, uint16_t* gpre, float* partial, hipStream_t st);
+                    const float* wh, int P, uint16_t* gpre, float* partial, hipStream_t st);
 void unet_weights_bf16(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t* wb, hipStream_t st);
 void unet_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps, float c1,
                float c2, hipStream_t st);
