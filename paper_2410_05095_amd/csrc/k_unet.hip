@@ -8,6 +8,8 @@
 //                chunks; the per-chunk partials are summed in chunk order, so the result is deterministic)
 // Tensors are NHWC; every reduction (bias, head, loss) is a fixed-order two-stage sum.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "rc_unet.h"
@@ -26,6 +28,23 @@ __device__ inline uint16_t f2bf(float f)
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ inline bf16x8 load8(const uint16_t* p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p)); }
+
+__device__ inline void unpack8(uint4 v, float f[8])
+{
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        f[2 * e] = __uint_as_float(w[e] << 16);
+        f[2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
+    }
+}
+__device__ inline uint4 pack8(const float f[8])
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w[e] = (uint32_t)f2bf(f[2 * e]) | ((uint32_t)f2bf(f[2 * e + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
 
 // ---------------------------------------------------------------- 3x3 convolution
 // Each wave computes 32 pixels (two 16-row MFMA tiles) x 16*NT output channels; a block has 4 waves.
@@ -152,51 +171,82 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
             *reinterpret_cast<uint4*>(lds + pix * PST + 8 * gg) = v;
         }
         __syncthreads();
+        // weight fragments of step k0 + 32 are loaded while the MFMAs of step k0 run
+        auto load_b = [&](int k0, bf16x8* B) {
+            const int kk = k0 + 8 * g;
+            const bool kv = kk < 9 * CC;
+            const int tap = kv ? kk / CC : 0;
+            const int cl = kk - tap * CC;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = 16 * nt + r;
+                B[nt] = (kv && co < a.Cout) ? load8(a.wt + (size_t)co * K + tap * a.Cin + c0 + cl) : zero;
+            }
+        };
+        bf16x8 B[NT], Bn[NT];
+        load_b(0, B);
         for (int k0 = 0; k0 < 9 * CC; k0 += 32) {
+            if (k0 + 32 < 9 * CC) load_b(k0 + 32, Bn);
             const int kk = k0 + 8 * g;
             const bool kv = kk < 9 * CC;
             const int tap = kv ? kk / CC : 0;
             const int cl = kk - tap * CC;
             const int dy = tap / 3, dx = tap % 3;
-            bf16x8 A[MT], B[NT];
+            bf16x8 A[MT];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 A[mt] = kv ? __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
                                  lds + ((wave + dy) * HW + 16 * mt + r + dx) * PST + cl))
                            : zero;
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = 16 * nt + r;
-                B[nt] = (kv && co < a.Cout) ? load8(a.wt + (size_t)co * K + tap * a.Cin + c0 + cl) : zero;
-            }
-#pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) B[nt] = Bn[nt];
         }
     }
-    // D layout: lane holds column (channel) 16 nt + (lane & 15), rows (pixels) 4 (lane >> 4) + i
-    const int y = y0 + wave;
-    if (y >= a.H) return;
+    // Epilogue through LDS: each wave writes its 16 MT pixels x 16 NT channels (bias, ReLU applied) as
+    // bf16 rows of a [pixel][channel] tile, then the tile leaves in 16-byte chunks, consecutive pixels of
+    // one image row being contiguous in NHWC.
+    constexpr int TC = 16 * NT;                 // channels of the tile
+    constexpr int TPX = 16 * MT;                // pixels per wave
+    __syncthreads();                            // every wave is done with the halo
+    uint16_t* tile = lds + (size_t)wave * TPX * TC;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int nt = 0; nt < NT; ++nt) {
+        const int co = 16 * nt + r;
+        const float b = (a.bias && co < a.Cout) ? a.bias[co] : 0.0f;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int co = 16 * nt + r;
-            if (co >= a.Cout) continue;
-            const float b = a.bias ? a.bias[co] : 0.0f;
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int x = x0 + 16 * mt + 4 * g + i;
-                if (x >= a.W) continue;
                 float v = acc[mt][nt][i] + b;
                 if (a.relu) v = fmaxf(v, 0.0f);
-                const size_t o = ((size_t)(n * a.H + y) * a.W + x) * a.Cout + co;
-                if (a.mask && !(bf2f(a.mask[o]) > 0.0f)) v = 0.0f;
-                a.out[o] = f2bf(v);
+                tile[(16 * mt + 4 * g + i) * TC + co] = f2bf(v);
             }
+    }
+    __syncthreads();
+    const int y = y0 + wave;
+    if (y >= a.H) return;
+    const int c8n = a.Cout / 8;
+    for (int q = lane; q < TPX * c8n; q += 64) {
+        const int px = q / c8n, c8 = q - px * c8n;
+        const int x = x0 + px;
+        if (x >= a.W) continue;
+        uint4 v = *reinterpret_cast<const uint4*>(tile + px * TC + 8 * c8);
+        const size_t o = ((size_t)(n * a.H + y) * a.W + x) * a.Cout + 8 * c8;
+        if (a.mask) {
+            float f[8], mk[8];
+            unpack8(v, f);
+            unpack8(*reinterpret_cast<const uint4*>(a.mask + o), mk);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) f[e] = mk[e] > 0.0f ? f[e] : 0.0f;
+            v = pack8(f);
         }
+        *reinterpret_cast<uint4*>(a.out + o) = v;
+    }
 }
 
 // ---------------------------------------------------------------- weight gradient
@@ -244,6 +294,118 @@ __global__ __launch_bounds__(64) void k_wgrad(WgradArgs a)
         int coo = co_t * 16 + 4 * g + i;
         a.partial[(((size_t)chunk * a.Cout + coo) * 9 + tap) * a.Cin + cio] = acc[i];
     }
+}
+
+// ---------------------------------------------------------------- weight gradient, LDS-tiled
+// dW[co][tap][ci] = sum_p g[p][co] x[p + off(tap)][ci] as MFMA GEMMs with K = pixels.  Workgroup of 3
+// waves; wave w owns the taps of kernel row dy = w.  Pixel tiles are 2 rows x 64 columns; for each tile
+// the gradient (all Cout channels) is staged in LDS transposed to [channel][pixel], and the input halo
+// (4 rows x 66 columns, 16 CI_T channels) in three copies shifted by dx = 0, 1, 2, also [channel][pixel],
+// so that every MFMA operand (8 consecutive pixels of one channel) is one aligned 16-byte LDS read.  A
+// workgroup accumulates a chunk of consecutive tiles for one group of input channels and writes its
+// partial sums; the chunks are then added in chunk order, so the result is deterministic.
+constexpr int WG_TW = 64, WG_R = 2;
+template <int CO_T, int CI_T>
+__global__ __launch_bounds__(192) void k_wgrad_lds(WgradArgs a, int tiles_per_chunk)
+{
+    extern __shared__ uint4 wg_lds[];
+    constexpr int TW = WG_TW, R = WG_R, HRW = R + 2, HC = TW + 2;
+    constexpr int CIN_T = 16 * CI_T, COUT = 16 * CO_T;
+    constexpr int GS_CO = R * TW + 8;      // bf16 elements per gradient channel row (padded)
+    constexpr int XS_CI = HRW * TW + 8;    // bf16 elements per input channel (4 halo rows, padded)
+    constexpr int XS_DX = CIN_T * XS_CI;
+    uint16_t* gs = reinterpret_cast<uint16_t*>(wg_lds);
+    uint16_t* xs = gs + COUT * GS_CO;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int ci0 = blockIdx.y * CIN_T;
+    const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + R - 1) / R;
+    const int n_tiles = a.N * tiles_x * tiles_y;
+    const int t_begin = blockIdx.x * tiles_per_chunk, t_end = min(n_tiles, t_begin + tiles_per_chunk);
+    const int c8_out = a.Cout / 8;
+    f32x4 acc[3][CO_T][CI_T];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int i = 0; i < CO_T; ++i)
+#pragma unroll
+            for (int j = 0; j < CI_T; ++j) acc[dx][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = t_begin; t < t_end; ++t) {
+        const int tx = t % tiles_x, rest = t / tiles_x, ty = rest % tiles_y, n = rest / tiles_y;
+        const int x0 = tx * TW, y0 = ty * R;
+        __syncthreads();
+        for (int i = threadIdx.x; i < R * TW * c8_out; i += 192) {
+            const int c8 = i % c8_out, px = i / c8_out;
+            const int y = y0 + px / TW, x = x0 + px % TW;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (y < a.H && x < a.W) v = *reinterpret_cast<const uint4*>(a.g + ((size_t)(n * a.H + y) * a.W + x) * a.Cout + 8 * c8);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                gs[(8 * c8 + 2 * e) * GS_CO + px] = (uint16_t)(w[e] & 0xFFFFu);
+                gs[(8 * c8 + 2 * e + 1) * GS_CO + px] = (uint16_t)(w[e] >> 16);
+            }
+        }
+        for (int i = threadIdx.x; i < HRW * HC * (CIN_T / 8); i += 192) {
+            const int c8 = i % (CIN_T / 8), hp = i / (CIN_T / 8);
+            const int hc = hp % HC, hrow = hp / HC;
+            const int y = y0 - 1 + hrow, x = x0 - 1 + hc, ci = ci0 + 8 * c8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (y >= 0 && y < a.H && x >= 0 && x < a.W && ci < a.Cin)
+                v = *reinterpret_cast<const uint4*>(a.x + ((size_t)(n * a.H + y) * a.W + x) * a.Cin + ci);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int c = hc - dx;
+                if (c < 0 || c >= TW) continue;
+                uint16_t* dst = xs + dx * XS_DX + (8 * c8) * XS_CI + hrow * TW + c;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    dst[(2 * e) * XS_CI] = (uint16_t)(w[e] & 0xFFFFu);
+                    dst[(2 * e + 1) * XS_CI] = (uint16_t)(w[e] >> 16);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < R * TW / 32; ++s) {
+            const int row = s / (TW / 32), c0 = 32 * (s % (TW / 32));
+            bf16x8 A[CO_T], B[3][CI_T];
+#pragma unroll
+            for (int i = 0; i < CO_T; ++i)
+                A[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                                                       gs + (16 * i + r) * GS_CO + row * TW + c0 + 8 * g));
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int j = 0; j < CI_T; ++j)
+                    B[dx][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                                   xs + dx * XS_DX + (16 * j + r) * XS_CI + (row + wave) * TW + c0 + 8 * g));
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int i = 0; i < CO_T; ++i)
+#pragma unroll
+                    for (int j = 0; j < CI_T; ++j)
+                        acc[dx][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], B[dx][j], acc[dx][i][j], 0, 0, 0);
+        }
+    }
+    // D[i = output channel][j = input channel]: lane holds j = lane & 15, rows 4 (lane >> 4) + e
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int i = 0; i < CO_T; ++i)
+#pragma unroll
+            for (int j = 0; j < CI_T; ++j) {
+                const int ci = ci0 + 16 * j + r;
+                if (ci >= a.Cin) continue;
+                const int tap = 3 * wave + dx;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int co = 16 * i + 4 * g + e;
+                    a.partial[(((size_t)blockIdx.x * a.Cout + co) * 9 + tap) * a.Cin + ci] = acc[dx][i][j][e];
+                }
+            }
 }
 
 // out[i] (+)= sum over chunks c in order of partial[c][i]
@@ -312,22 +474,6 @@ __global__ __launch_bounds__(256) void k_reduce_blocks(const float* partial, int
 
 // ---------------------------------------------------------------- pooling / upsampling / concat
 // All channel counts and offsets are multiples of 8: one thread handles 8 channels (16 bytes).
-__device__ inline void unpack8(uint4 v, float f[8])
-{
-    uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        f[2 * e] = __uint_as_float(w[e] << 16);
-        f[2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
-    }
-}
-__device__ inline uint4 pack8(const float f[8])
-{
-    uint32_t w[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) w[e] = (uint32_t)f2bf(f[2 * e]) | ((uint32_t)f2bf(f[2 * e + 1]) << 16);
-    return make_uint4(w[0], w[1], w[2], w[3]);
-}
 __device__ inline uint4 ld8(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
 __device__ inline void st8(uint16_t* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; }
 
@@ -551,7 +697,8 @@ void launch_conv_lds(const ConvArgs& a, hipStream_t st)
 {
     constexpr int TW = 16 * MT;
     const size_t tiles = (size_t)a.N * ((a.H + 3) / 4) * ((a.W + TW - 1) / TW);
-    const size_t lds = (size_t)6 * (TW + 2) * (CC + 8) * 2;
+    const size_t halo = (size_t)6 * (TW + 2) * (CC + 8) * 2, out_tile = (size_t)4 * TW * 16 * NT * 2;
+    const size_t lds = halo > out_tile ? halo : out_tile;
     hipLaunchKernelGGL((k_conv_lds<MT, NT, CC>), dim3((unsigned)tiles), dim3(256), lds, st, a);
 }
 
@@ -597,6 +744,40 @@ void unet_wgrad(const WgradArgs& a, hipStream_t st)
     int chunks = unet_wgrad_chunks(P, a.chunk);
     dim3 grid(chunks, 9, (a.Cout / 16) * ((a.Cin + 15) / 16));
     hipLaunchKernelGGL(k_wgrad, grid, dim3(64), 0, st, a);
+}
+
+namespace {
+struct WgradShape {
+    int co_t, ci_t, ci_groups, tiles_per_chunk, chunks;
+};
+WgradShape wgrad_shape(const WgradArgs& a)
+{
+    WgradShape w;
+    w.co_t = a.Cout / 16;
+    w.ci_t = w.co_t >= 8 ? 1 : (a.Cin <= 16 ? 1 : 2);
+    w.ci_groups = (a.Cin + 16 * w.ci_t - 1) / (16 * w.ci_t);
+    const int tiles = a.N * ((a.H + WG_R - 1) / WG_R) * ((a.W + WG_TW - 1) / WG_TW);
+    const int target = std::max(1, 1024 / w.ci_groups);
+    w.tiles_per_chunk = std::max(1, (tiles + target - 1) / target);
+    w.chunks = (tiles + w.tiles_per_chunk - 1) / w.tiles_per_chunk;
+    return w;
+}
+}  // namespace
+
+int unet_wgrad_lds_chunks(const WgradArgs& a) { return wgrad_shape(a).chunks; }
+
+bool unet_wgrad_lds(const WgradArgs& a, hipStream_t st)
+{
+    const WgradShape w = wgrad_shape(a);
+    const size_t lds = ((size_t)16 * w.co_t * (WG_R * WG_TW + 8) + (size_t)3 * 16 * w.ci_t * ((WG_R + 2) * WG_TW + 8)) * 2;
+    const dim3 grid(w.chunks, w.ci_groups);
+    switch (w.co_t * 10 + w.ci_t) {
+    case 21: hipLaunchKernelGGL((k_wgrad_lds<2, 1>), grid, dim3(192), lds, st, a, w.tiles_per_chunk); return true;
+    case 22: hipLaunchKernelGGL((k_wgrad_lds<2, 2>), grid, dim3(192), lds, st, a, w.tiles_per_chunk); return true;
+    case 42: hipLaunchKernelGGL((k_wgrad_lds<4, 2>), grid, dim3(192), lds, st, a, w.tiles_per_chunk); return true;
+    case 81: hipLaunchKernelGGL((k_wgrad_lds<8, 1>), grid, dim3(192), lds, st, a, w.tiles_per_chunk); return true;
+    default: return false;
+    }
 }
 
 void unet_reduce_chunks(const float* partial, int n_chunks, int n, float* out, int add, hipStream_t st)

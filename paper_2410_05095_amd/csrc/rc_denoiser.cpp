@@ -178,8 +178,12 @@ void conv_back_weights(rc_denoiser* d, const uint16_t* x, const uint16_t* g, int
     a.x = x; a.g = g; a.N = n; a.H = h; a.W = w; a.Cin = LAYERS[l].cin; a.Cout = LAYERS[l].cout;
     a.chunk = chunk;
     a.partial = d->d_partial;
-    unet_wgrad(a, st);
-    unet_reduce_chunks(d->d_partial, chunks, (int)layer_w(l), d->d_g + d->off_w[l], 0, st);
+    if (unet_wgrad_lds(a, st)) {
+        unet_reduce_chunks(d->d_partial, unet_wgrad_lds_chunks(a), (int)layer_w(l), d->d_g + d->off_w[l], 0, st);
+    } else {
+        unet_wgrad(a, st);
+        unet_reduce_chunks(d->d_partial, chunks, (int)layer_w(l), d->d_g + d->off_w[l], 0, st);
+    }
     unet_colsum(g, (int)P, LAYERS[l].cout, d->d_partial, st);
     unet_reduce_blocks(d->d_partial, unet_colsum_blocks((int)P), LAYERS[l].cout, d->d_g + d->off_b[l], 0, st);
 }
@@ -219,7 +223,13 @@ int backward(rc_denoiser* d, const uint16_t* x, const float* t, const float* m, 
     int chunk = chunk_for(P);
     int chunks = unet_wgrad_chunks(P, chunk);
     size_t need = 0;
-    for (int l = 0; l < N_LAYERS; ++l) need = std::max(need, (size_t)chunks * layer_w(l));
+    for (int l = 0; l < N_LAYERS; ++l) {
+        need = std::max(need, (size_t)chunks * layer_w(l));
+        const int s = (l == E1A || l == E1B || l == D1A || l == D1B) ? 1 : (l == BNA || l == BNB ? 4 : 2);
+        WgradArgs q = {};
+        q.N = n; q.H = h / s; q.W = w / s; q.Cin = LAYERS[l].cin; q.Cout = LAYERS[l].cout;
+        need = std::max(need, (size_t)unet_wgrad_lds_chunks(q) * layer_w(l));
+    }
     need = std::max(need, (size_t)chunks * 64);
     need = std::max(need, (size_t)unet_colsum_blocks((int)P) * 128);
     need = std::max(need, (size_t)unet_head_blocks((int)P) * 33);

@@ -31,6 +31,10 @@ struct WgradArgs {
 void unet_conv3x3(const ConvArgs& a, hipStream_t st);
 void unet_conv3x3_direct(const ConvArgs& a, hipStream_t st);
 int unet_wgrad_chunks(size_t P, int chunk);
+// LDS-tiled weight gradient: partial sums per chunk of pixel tiles ([chunks][Cout][9][Cin], `chunk`
+// unused); returns false for channel counts it has no instance for
+int unet_wgrad_lds_chunks(const WgradArgs& a);
+bool unet_wgrad_lds(const WgradArgs& a, hipStream_t st);
 void unet_wgrad(const WgradArgs& a, hipStream_t st);
 void unet_reduce_chunks(const float* partial, int n_chunks, int n, float* out, int add, hipStream_t st);
 // bias gradients: per-block column sums, then a fixed-order reduction over the blocks
