@@ -97,7 +97,9 @@ def learned_path(ctx, gs, scene, cam, args):
         sc = sg.big_scene(seed)
         train_scenes.append((sc, ctx.scene_from(sc).build()))
     log(f"[bench] training scenes ready ({time.perf_counter() - t0:.1f} s)")
-    data = D.make_training_set(ctx, train_scenes, n_views=16, crops_per_view=12, crop=256, seed=args.seed, log=log)
+    data = D.make_training_set(ctx, train_scenes, n_views=args.denoiser_views, crops_per_view=12, crop=256,
+                               seed=args.seed, log=log)
+    n_crops = len(data)
     for _, h in train_scenes:
         h.close()
     den = N.Denoiser(ctx, seed=args.seed)
@@ -107,12 +109,11 @@ def learned_path(ctx, gs, scene, cam, args):
     train_s = time.perf_counter() - t1
     del data
     ev = D.evaluate(ctx, den, gs, scene, cam, plain_spp=args.spp, ref_spp=256, reps=5)
-    # plain sample count whose expected MSE (binomial, MSE_1 / N) equals the denoised MSE
-    ev["plain_spp_equivalent"] = ev["mse_raw_1spp"] / max(ev["mse_denoised_1spp"], 1e-12)
-    ev.update({"train_steps": args.denoiser_steps, "train_s": round(train_s, 1), "train_crops": 192,
+    ev.update({"train_steps": args.denoiser_steps, "train_s": round(train_s, 1), "train_crops": n_crops,
                "crop": 256, "final_loss": [x for x in losses if x == x][-1],
                "weights": "bf16 (FP32 master)", "parity": "unpinned (statistical)"})
-    return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in ev.items()}
+    rnd = lambda v: round(v, 6) if isinstance(v, float) else v
+    return {k: ({a: rnd(b) for a, b in v.items()} if isinstance(v, dict) else rnd(v)) for k, v in ev.items()}
 
 
 def main():
@@ -124,8 +125,10 @@ def main():
     ap.add_argument("--spp", type=int, default=64, help="rect-light samples per pixel (big_7M)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--denoiser-steps", type=int, default=1200,
+    ap.add_argument("--denoiser-steps", type=int, default=6000,
                     help="training steps of the learned 1-spp path (0 = skip the learned-path comparison)")
+    ap.add_argument("--denoiser-views", type=int, default=200,
+                    help="1080p views of the training scenes rendered for the denoiser's training set (12 crops each)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of rendering, copy a buffer of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()

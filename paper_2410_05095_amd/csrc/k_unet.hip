@@ -408,14 +408,23 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(WgradArgs a, int tiles_per_ch
             }
 }
 
-// out[i] (+)= sum over chunks c in order of partial[c][i]
+// out[i] (+)= sum over chunks c of partial[c][i]: 16 outputs per workgroup, 16 lanes per output summing
+// chunks q, q + 16, q + 32, ... in order, then a fixed-order tree over the 16 lanes
 __global__ __launch_bounds__(256) void k_reduce_chunks(const float* partial, int n_chunks, int n, float* out, int add)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float sm[16][17];
+    const int o = threadIdx.x & 15, q = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + o;
     float s = 0.0f;
-    for (int c = 0; c < n_chunks; ++c) s += partial[(size_t)c * n + i];
-    out[i] = add ? out[i] + s : s;
+    if (i < n)
+        for (int c = q; c < n_chunks; c += 16) s += partial[(size_t)c * n + i];
+    sm[q][o] = s;
+    __syncthreads();
+    for (int h = 8; h > 0; h >>= 1) {
+        if (q < h) sm[q][o] += sm[q + h][o];
+        __syncthreads();
+    }
+    if (q == 0 && i < n) out[i] = add ? out[i] + sm[0][o] : sm[0][o];
 }
 
 // Column sums of a bf16 [P][C] tensor (C a multiple of 8, at most 256), per block of COLSUM_ROWS pixels:
@@ -782,7 +791,7 @@ bool unet_wgrad_lds(const WgradArgs& a, hipStream_t st)
 
 void unet_reduce_chunks(const float* partial, int n_chunks, int n, float* out, int add, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(nb(n, 256)), dim3(256), 0, st, partial, n_chunks, n, out, add);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nb(n, 16)), dim3(256), 0, st, partial, n_chunks, n, out, add);
 }
 
 int unet_colsum_blocks(int P) { return (P + COLSUM_ROWS - 1) / COLSUM_ROWS; }

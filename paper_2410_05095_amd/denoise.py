@@ -103,6 +103,24 @@ def train(den: N.Denoiser, data: TrainingSet, steps: int, batch: int = 8, lr: fl
     return losses
 
 
+def plain_frame(ctx: N.Context, gs: N.Scene, scene: sg.Scene, cam, spp: int, ref, mask, reps: int = 5) -> dict:
+    """The plain path at `spp` light samples per pixel: shadow MSE against `ref` and the device frame time
+    (camera rays, shadow rays, shading; median of reps)."""
+    torch = ctx.torch
+    out = {}
+    render_visibility(ctx, gs, cam, scene.rect_light, spp, STREAM_PLAIN, out=out)
+    mse = masked_mse(out["visibility"], ref, mask)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        render_visibility(ctx, gs, cam, scene.rect_light, spp, STREAM_PLAIN, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return {"spp": spp, "mse": mse, "frame_ms": float(np.median(ts))}
+
+
 def masked_mse(a, b, mask) -> float:
     m = mask.double()
     return float(((a.double() - b.double()) ** 2 * m).sum() / m.sum().clamp(min=1.0))
@@ -150,4 +168,8 @@ def evaluate(ctx: N.Context, den: N.Denoiser, gs: N.Scene, scene: sg.Scene, cam,
     res["frame_ms_learned"] = float(np.median(learned[1:]))
     res["denoiser_ms"] = float(np.median(den_ms[1:]))
     res[f"frame_ms_plain_{plain_spp}spp"] = float(np.median(plain[1:]))
+    # the plain path at the sample count whose binomial MSE (MSE_1 / N) matches the denoised MSE
+    n_eq = int(math.ceil(res["mse_raw_1spp"] / max(res["mse_denoised_1spp"], 1e-12)))
+    res["plain_spp_equivalent"] = res["mse_raw_1spp"] / max(res["mse_denoised_1spp"], 1e-12)
+    res["plain_at_equal_mse"] = plain_frame(ctx, gs, scene, cam, max(1, min(n_eq, 4096)), ref, mask, reps)
     return res
