@@ -291,6 +291,11 @@ int rc_denoiser_get_grads(rc_ctx* ctx, const rc_denoiser* den, float* out);
 /* d_out: N*H*W float visibility in (0, 1). */
 int rc_denoiser_infer(rc_ctx* ctx, rc_denoiser* den, const uint16_t* d_features, uint32_t n, uint32_t h, uint32_t w,
                       float* d_out);
+/* The same network evaluated in FP32 from the FP32 master weights (FP32 activations and accumulation,
+ * the BF16 features as input): the full-precision copy that the BF16 inference is compared against.
+ * Arguments as rc_denoiser_infer. */
+int rc_denoiser_infer_fp32(rc_ctx* ctx, rc_denoiser* den, const uint16_t* d_features, uint32_t n, uint32_t h,
+                           uint32_t w, float* d_out);
 /* One Adam step (beta 0.9/0.999, eps 1e-8, bias-corrected) on the loss
  * sum(mask (y - target)^2) / max(sum(mask), 1); d_target and d_mask are N*H*W floats.  *loss_out
  * (optional, synchronises) receives the loss before the step. */

@@ -116,6 +116,7 @@ SIGNATURES = {
     "rc_denoiser_set_params": (C.c_int, [P, P, P]),
     "rc_denoiser_get_grads": (C.c_int, [P, P, P]),
     "rc_denoiser_infer": (C.c_int, [P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
+    "rc_denoiser_infer_fp32": (C.c_int, [P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
     "rc_denoiser_train_step": (C.c_int, [P, P, P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_float,
                                          C.POINTER(C.c_float)]),
     "rc_denoiser_save": (C.c_int, [P, P, C.c_char_p]),
@@ -459,16 +460,18 @@ class Denoiser:
         check(lib().rc_denoiser_get_grads(self.ctx.h, self.h, _ptr(out)), "rc_denoiser_get_grads")
         return out
 
-    def infer(self, feat, out=None):
-        """feat: (N, H, W, 8) torch.bfloat16 on the GPU -> (N, H, W) float32."""
+    def infer(self, feat, out=None, fp32: bool = False):
+        """feat: (N, H, W, 8) torch.bfloat16 on the GPU -> (N, H, W) float32.  fp32: evaluate the FP32 copy of
+        the network (FP32 master weights and activations) instead of the BF16 one."""
         torch = self.ctx.torch
         assert feat.dtype == torch.bfloat16 and feat.is_contiguous() and feat.shape[-1] == 8
         n, h, w = (int(x) for x in feat.shape[:3])
         if out is None:
             out = torch.empty((n, h, w), dtype=torch.float32, device=feat.device)
         self.ctx._sync_stream()
-        check(lib().rc_denoiser_infer(self.ctx.h, self.h, C.c_void_p(feat.data_ptr()), n, h, w,
-                                      C.c_void_p(out.data_ptr())), "rc_denoiser_infer")
+        fn = lib().rc_denoiser_infer_fp32 if fp32 else lib().rc_denoiser_infer
+        check(fn(self.ctx.h, self.h, C.c_void_p(feat.data_ptr()), n, h, w, C.c_void_p(out.data_ptr())),
+              "rc_denoiser_infer_fp32" if fp32 else "rc_denoiser_infer")
         return out
 
     def train_step(self, feat, target, mask, lr: float, want_loss: bool = True):

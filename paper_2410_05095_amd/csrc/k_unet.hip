@@ -249,6 +249,130 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
     }
 }
 
+// ---------------------------------------------------------------- FP32 copy of the network
+// 3x3 convolution in FP32 on v_mfma_f32_16x16x4_f32: FP32 activations and weights (the master copy,
+// transposed to [tap][ci][co]), FP32 accumulation.  Same tiling as k_conv_lds with one 16-pixel M-tile
+// per wave; the halo of a CC-channel chunk is staged in LDS; the first layer reads the BF16 features, and
+// the decoder's upsample + concat is fused into the halo load as in the BF16 kernel.
+template <int NT, int CC>
+__global__ __launch_bounds__(256) void k_conv_f32(ConvArgsF32 a)
+{
+    extern __shared__ float cf_lds[];
+    constexpr int TW = 16, HW = TW + 2, HR = 6, PST = CC + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + 3) / 4;
+    int tt = blockIdx.x;
+    const int tx = tt % tiles_x;
+    tt /= tiles_x;
+    const int ty = tt % tiles_y, n = tt / tiles_y;
+    const int x0 = tx * TW, y0 = ty * 4;
+    const int r = lane & 15, kq = lane >> 4;
+    const int Cs = a.Cin - a.Ca;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < a.Cin; c0 += CC) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < HR * HW * (CC / 4); i += 256) {
+            const int g4 = i % (CC / 4), pix = i / (CC / 4);
+            const int hx = pix % HW, hy = pix / HW;
+            const int y = y0 - 1 + hy, x = x0 - 1 + hx, ci = c0 + 4 * g4;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
+                if (a.in_bf16) {
+                    const uint2 q = *reinterpret_cast<const uint2*>(
+                        static_cast<const uint16_t*>(a.in) + ((size_t)(n * a.H + y) * a.W + x) * a.Cin + ci);
+                    v[0] = __uint_as_float(q.x << 16); v[1] = __uint_as_float(q.x & 0xFFFF0000u);
+                    v[2] = __uint_as_float(q.y << 16); v[3] = __uint_as_float(q.y & 0xFFFF0000u);
+                } else {
+                    const float* src;
+                    if (a.in2 == nullptr)
+                        src = static_cast<const float*>(a.in) + ((size_t)(n * a.H + y) * a.W + x) * a.Cin + ci;
+                    else if (ci < a.Ca)
+                        src = static_cast<const float*>(a.in) +
+                              ((size_t)(n * (a.H / 2) + y / 2) * (a.W / 2) + x / 2) * a.Ca + ci;
+                    else
+                        src = a.in2 + ((size_t)(n * a.H + y) * a.W + x) * Cs + (ci - a.Ca);
+                    const float4 q = *reinterpret_cast<const float4*>(src);
+                    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cf_lds[pix * PST + 4 * g4 + e] = v[e];
+        }
+        __syncthreads();
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            const float* arow = cf_lds + ((wave + dy) * HW + r + dx) * PST;
+            const float* wrow = a.wt + ((size_t)tap * a.Cin + c0) * a.Cout + r;
+            for (int kc = 0; kc < CC; kc += 4) {
+                const float A = arow[kc + kq];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const float B = wrow[(size_t)(kc + kq) * a.Cout + 16 * nt];
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A, B, acc[nt], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D layout: lane holds column (channel) 16 nt + (lane & 15), rows (pixels) 4 (lane >> 4) + e
+    const int y = y0 + wave;
+    if (y >= a.H) return;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int co = 16 * nt + r;
+        const float b = a.bias[co];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int x = x0 + 4 * kq + e;
+            if (x >= a.W) continue;
+            a.out[((size_t)(n * a.H + y) * a.W + x) * a.Cout + co] = fmaxf(acc[nt][e] + b, 0.0f);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pool2_f32(const float* in, int N, int H, int W, int C, float* out)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int h = H / 2, w = W / 2, C4 = C / 4;
+    size_t total = (size_t)N * h * w * C4;
+    if (i >= total) return;
+    int c = (int)(i % C4) * 4;
+    size_t q = i / C4;
+    int x = (int)(q % w), t = (int)(q / w), y = t % h, n = t / h;
+    const float* b = in + (((size_t)n * H + 2 * y) * W + 2 * x) * C + c;
+    float4 p0 = *reinterpret_cast<const float4*>(b), p1 = *reinterpret_cast<const float4*>(b + C);
+    float4 p2 = *reinterpret_cast<const float4*>(b + (size_t)W * C), p3 = *reinterpret_cast<const float4*>(b + (size_t)W * C + C);
+    float4 o;
+    o.x = ((p0.x + p1.x) + (p2.x + p3.x)) * 0.25f;
+    o.y = ((p0.y + p1.y) + (p2.y + p3.y)) * 0.25f;
+    o.z = ((p0.z + p1.z) + (p2.z + p3.z)) * 0.25f;
+    o.w = ((p0.w + p1.w) + (p2.w + p3.w)) * 0.25f;
+    *reinterpret_cast<float4*>(out + q * C + c) = o;
+}
+
+// y = sigmoid(sum_c d1[p][c] wh[c] + bh) with the FP32 head weights
+__global__ __launch_bounds__(256) void k_head_f32(const float* d1, const float* wh, const float* bh, int P, float* y)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float s = 0.0f;
+    const float* row = d1 + (size_t)p * 32;
+    for (int c = 0; c < 32; ++c) s += row[c] * wh[c];
+    s += bh[0];
+    y[p] = 1.0f / (1.0f + expf(-s));
+}
+
+// FP32 master [Cout][9][Cin] -> [9][Cin][Cout]
+__global__ __launch_bounds__(256) void k_weights_f32t(const float* w, int Cout, int Cin, float* wt)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = Cout * 9 * Cin;
+    if (i >= n) return;
+    int ci = i % Cin, tap = (i / Cin) % 9, co = i / (9 * Cin);
+    wt[((size_t)tap * Cin + ci) * Cout + co] = w[i];
+}
+
 // ---------------------------------------------------------------- weight gradient
 // One wave per (pixel chunk, tap, 16-channel output tile, 16-channel input tile).
 __global__ __launch_bounds__(64) void k_wgrad(WgradArgs a)
@@ -866,6 +990,37 @@ void unet_adam(float* w, const float* g, float* m, float* v, int n, float lr, fl
                float c2, hipStream_t st)
 {
     hipLaunchKernelGGL(k_adam, dim3(nb(n, 256)), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+void unet_conv3x3_f32(const ConvArgsF32& a, hipStream_t st)
+{
+    const int nt = a.Cout / 16, cc = a.Cin % 32 == 0 ? 32 : 8;
+    const size_t tiles = (size_t)a.N * ((a.H + 3) / 4) * ((a.W + 15) / 16);
+    const size_t lds = (size_t)6 * 18 * (cc + 1) * 4;
+    switch (nt * 100 + cc) {
+    case 208: hipLaunchKernelGGL((k_conv_f32<2, 8>), dim3((unsigned)tiles), dim3(256), lds, st, a); break;
+    case 232: hipLaunchKernelGGL((k_conv_f32<2, 32>), dim3((unsigned)tiles), dim3(256), lds, st, a); break;
+    case 432: hipLaunchKernelGGL((k_conv_f32<4, 32>), dim3((unsigned)tiles), dim3(256), lds, st, a); break;
+    case 832: hipLaunchKernelGGL((k_conv_f32<8, 32>), dim3((unsigned)tiles), dim3(256), lds, st, a); break;
+    default: break;   // channel counts of this network only
+    }
+}
+
+void unet_pool2_f32(const float* in, int N, int H, int W, int C, float* out, hipStream_t st)
+{
+    size_t n = (size_t)N * (H / 2) * (W / 2) * (C / 4);
+    hipLaunchKernelGGL(k_pool2_f32, dim3(nb(n, 256)), dim3(256), 0, st, in, N, H, W, C, out);
+}
+
+void unet_head_f32(const float* d1, const float* wh, const float* bh, int P, float* y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_head_f32, dim3(nb(P, 256)), dim3(256), 0, st, d1, wh, bh, P, y);
+}
+
+void unet_weights_f32t(const float* w, int Cout, int Cin, float* wt, hipStream_t st)
+{
+    int n = Cout * 9 * Cin;
+    hipLaunchKernelGGL(k_weights_f32t, dim3(nb(n, 256)), dim3(256), 0, st, w, Cout, Cin, wt);
 }
 
 void unet_fill_f32(float* p, float v, size_t n, hipStream_t st)

@@ -72,6 +72,11 @@ struct rc_denoiser {
     // activation offsets (elements) within act / grad
     size_t a_e1a, a_e1b, a_p1, a_e2a, a_e2b, a_p2, a_bna, a_bnb, a_u2, a_d2a, a_d2b, a_u1, a_d1a, a_d1b, a_total;
     size_t g_d1b, g_d1a, g_u1, g_d2b, g_d2a, g_u2, g_bnb, g_bna, g_p2, g_e2b, g_e2a, g_p1, g_e1b, g_e1a, g_total;
+    // FP32 copy of the forward pass: transposed FP32 weights and an FP32 activation workspace
+    float* d_wt32 = nullptr;
+    float* act32 = nullptr;
+    int fn = 0, fh = 0, fw = 0;
+    size_t f_e1a, f_e1b, f_p1, f_e2a, f_e2b, f_p2, f_bna, f_bnb, f_d2a, f_d2b, f_d1a, f_d1b, f_y, f_total;
 };
 
 namespace {
@@ -116,6 +121,27 @@ int ensure_workspace(rc_denoiser* d, int n, int h, int w)
     DN_HIP(hipMalloc(reinterpret_cast<void**>(&d->grad), d->g_total * 2));
     DN_HIP(hipMalloc(reinterpret_cast<void**>(&d->d_y), P * 4));
     d->wn = n; d->wh = h; d->ww = w;
+    return RC_OK;
+}
+
+int ensure_workspace_f32(rc_denoiser* d, int n, int h, int w)
+{
+    if (!d->d_wt32) DN_HIP(hipMalloc(reinterpret_cast<void**>(&d->d_wt32), d->off_bf[N_LAYERS - 1] * 4 +
+                                                                               layer_w(N_LAYERS - 1) * 4));
+    if (d->fn == n && d->fh == h && d->fw == w && d->act32) return RC_OK;
+    hipFree(d->act32);
+    d->act32 = nullptr;
+    size_t P = (size_t)n * h * w, P2 = P / 4, P4 = P / 16;
+    size_t o = 0;
+    auto take = [&](size_t elems) { size_t r = o; o += (elems + 63) & ~size_t(63); return r; };
+    d->f_e1a = take(P * 32); d->f_e1b = take(P * 32); d->f_p1 = take(P2 * 32);
+    d->f_e2a = take(P2 * 64); d->f_e2b = take(P2 * 64); d->f_p2 = take(P4 * 64);
+    d->f_bna = take(P4 * 128); d->f_bnb = take(P4 * 128);
+    d->f_d2a = take(P2 * 64); d->f_d2b = take(P2 * 64); d->f_d1a = take(P * 32); d->f_d1b = take(P * 32);
+    d->f_y = take(P);
+    d->f_total = o;
+    DN_HIP(hipMalloc(reinterpret_cast<void**>(&d->act32), d->f_total * 4));
+    d->fn = n; d->fh = h; d->fw = w;
     return RC_OK;
 }
 
@@ -210,6 +236,46 @@ int forward(rc_denoiser* d, const uint16_t* x, int n, int h, int w, hipStream_t 
     conv(d, A + d->a_d2b, n, h, w, D1A, A + d->a_d1a, st, A + d->a_e1b, 64);
     conv(d, A + d->a_d1a, n, h, w, D1B, A + d->a_d1b, st);
     unet_head(A + d->a_d1b, d->d_w + d->off_w[N_LAYERS], d->d_w + d->off_b[N_LAYERS], n * h * w, d->d_y, st);
+    DN_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+// layer l in FP32 (input `in` float, or the BF16 features for the first layer)
+void conv_f32(rc_denoiser* d, const void* in, bool in_bf16, int n, int h, int w, int l, float* out, hipStream_t st,
+              const float* skip = nullptr, int Ca = 0)
+{
+    ConvArgsF32 a = {};
+    a.in = in; a.in_bf16 = in_bf16 ? 1 : 0; a.in2 = skip; a.Ca = Ca;
+    a.N = n; a.H = h; a.W = w; a.Cin = LAYERS[l].cin;
+    a.wt = d->d_wt32 + d->off_bf[l];
+    a.bias = d->d_w + d->off_b[l];
+    a.out = out;
+    a.Cout = LAYERS[l].cout;
+    unet_conv3x3_f32(a, st);
+}
+
+int forward_f32(rc_denoiser* d, const uint16_t* x, int n, int h, int w, hipStream_t st)
+{
+    int st_ = ensure_workspace_f32(d, n, h, w);
+    if (st_ != RC_OK) return st_;
+    for (int l = 0; l < N_LAYERS; ++l)
+        unet_weights_f32t(d->d_w + d->off_w[l], LAYERS[l].cout, LAYERS[l].cin, d->d_wt32 + d->off_bf[l], st);
+    float* F = d->act32;
+    int h2 = h / 2, w2 = w / 2, h4 = h / 4, w4 = w / 4;
+    conv_f32(d, x, true, n, h, w, E1A, F + d->f_e1a, st);
+    conv_f32(d, F + d->f_e1a, false, n, h, w, E1B, F + d->f_e1b, st);
+    unet_pool2_f32(F + d->f_e1b, n, h, w, 32, F + d->f_p1, st);
+    conv_f32(d, F + d->f_p1, false, n, h2, w2, E2A, F + d->f_e2a, st);
+    conv_f32(d, F + d->f_e2a, false, n, h2, w2, E2B, F + d->f_e2b, st);
+    unet_pool2_f32(F + d->f_e2b, n, h2, w2, 64, F + d->f_p2, st);
+    conv_f32(d, F + d->f_p2, false, n, h4, w4, BNA, F + d->f_bna, st);
+    conv_f32(d, F + d->f_bna, false, n, h4, w4, BNB, F + d->f_bnb, st);
+    conv_f32(d, F + d->f_bnb, false, n, h2, w2, D2A, F + d->f_d2a, st, F + d->f_e2b, 128);
+    conv_f32(d, F + d->f_d2a, false, n, h2, w2, D2B, F + d->f_d2b, st);
+    conv_f32(d, F + d->f_d2b, false, n, h, w, D1A, F + d->f_d1a, st, F + d->f_e1b, 64);
+    conv_f32(d, F + d->f_d1a, false, n, h, w, D1B, F + d->f_d1b, st);
+    unet_head_f32(F + d->f_d1b, d->d_w + d->off_w[N_LAYERS], d->d_w + d->off_b[N_LAYERS], n * h * w,
+                  F + d->f_y, st);
     DN_HIP(hipGetLastError());
     return RC_OK;
 }
@@ -352,6 +418,7 @@ int rc_denoiser_destroy(rc_ctx* c, rc_denoiser* d)
     hipFree(d->d_w); hipFree(d->d_g); hipFree(d->d_m); hipFree(d->d_v);
     hipFree(d->d_wbf); hipFree(d->d_wfl);
     hipFree(d->act); hipFree(d->grad); hipFree(d->d_y); hipFree(d->d_partial); hipFree(d->d_sums);
+    hipFree(d->d_wt32); hipFree(d->act32);
     delete d;
     return RC_OK;
 }
@@ -399,6 +466,20 @@ int rc_denoiser_infer(rc_ctx* c, rc_denoiser* d, const uint16_t* d_feat, uint32_
     int st = forward(d, d_feat, (int)n, (int)h, (int)w, s, false);
     if (st != RC_OK) return st;
     DN_HIP(hipMemcpyAsync(d_out, d->d_y, (size_t)n * h * w * 4, hipMemcpyDeviceToDevice, s));
+    return RC_OK;
+}
+
+int rc_denoiser_infer_fp32(rc_ctx* c, rc_denoiser* d, const uint16_t* d_feat, uint32_t n, uint32_t h, uint32_t w,
+                           float* d_out)
+{
+    if (!c || !d || !d_feat || !d_out) return RC_ERR_INVALID_ARG;
+    if (!dims_ok(n, h, w)) return RC_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(d_feat) & 15u) return RC_ERR_INVALID_ARG;
+    DN_HIP(hipSetDevice(d->device));
+    hipStream_t s = ctx_stream(c);
+    int st = forward_f32(d, d_feat, (int)n, (int)h, (int)w, s);
+    if (st != RC_OK) return st;
+    DN_HIP(hipMemcpyAsync(d_out, d->act32 + d->f_y, (size_t)n * h * w * 4, hipMemcpyDeviceToDevice, s));
     return RC_OK;
 }
 

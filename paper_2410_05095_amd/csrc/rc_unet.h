@@ -18,6 +18,18 @@ struct ConvArgs {
     int relu;
 };
 
+struct ConvArgsF32 {
+    const void* in;         // NHWC float (bf16 when in_bf16), Cin channels; with in2: N x H/2 x W/2 x Ca float
+    int in_bf16;
+    const float* in2;       // optional skip tensor N x H x W x (Cin - Ca) (concatenated after upsampled `in`)
+    int Ca;
+    int N, H, W, Cin;
+    const float* wt;        // [9][Cin][Cout] float
+    const float* bias;      // Cout floats
+    float* out;             // NHWC float, Cout channels (ReLU applied)
+    int Cout;
+};
+
 struct WgradArgs {
     const uint16_t* x;      // layer input NHWC [Cin]
     const uint16_t* g;      // gradient of the pre-activation NHWC [Cout]
@@ -58,3 +70,8 @@ void unet_weights_bf16(const float* w, int Cout, int Cin, uint16_t* wf, uint16_t
 void unet_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps, float c1,
                float c2, hipStream_t st);
 void unet_fill_f32(float* p, float v, size_t n, hipStream_t st);
+// FP32 copy of the forward pass
+void unet_conv3x3_f32(const ConvArgsF32& a, hipStream_t st);
+void unet_pool2_f32(const float* in, int N, int H, int W, int C, float* out, hipStream_t st);
+void unet_head_f32(const float* d1, const float* wh, const float* bh, int P, float* y, hipStream_t st);
+void unet_weights_f32t(const float* w, int Cout, int Cin, float* wt, hipStream_t st);

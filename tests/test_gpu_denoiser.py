@@ -96,6 +96,26 @@ def test_forward_matches_oracle(ctx):
         assert err.max() < 2e-3 and err.mean() < 1e-4
 
 
+def test_fp32_copy_matches_oracle(ctx):
+    """The FP32 copy of the network (FP32 master weights, FP32 activations) against the FP64 oracle without
+    BF16 emulation; the BF16 inference differs from it by BF16 rounding only."""
+    from paper_2410_05095_amd import _native as N
+    den = N.Denoiser(ctx, seed=1)
+    p = oracle_params(4)
+    den.set_params(U.flat(p).astype(np.float32))
+    for seed, (n, h, w) in enumerate([(2, 16, 24), (1, 36, 20), (3, 8, 8), (1, 20, 52)]):
+        x, t, m = random_batch(30 + seed, n, h, w)
+        xd, td, md = to_dev(ctx, x, t, m)
+        y32 = den.infer(xd, fp32=True).cpu().numpy().astype(np.float64)
+        y16 = den.infer(xd).cpu().numpy().astype(np.float64)
+        yo, _ = U.forward(p, x, bf16=False)
+        err = np.abs(y32 - yo)
+        say(f"[unet fp32 {n}x{h}x{w}] max |gpu_fp32 - oracle_fp64| {err.max():.2e}; "
+            f"bf16 vs fp32 on the GPU {np.abs(y16 - y32).max():.2e}")
+        assert err.max() < 2e-5
+        assert np.abs(y16 - y32).max() < 2e-2
+
+
 def test_gradients_match_oracle(ctx):
     from paper_2410_05095_amd import _native as N
     den = N.Denoiser(ctx, seed=2)
