@@ -109,11 +109,32 @@ def learned_path(ctx, gs, scene, cam, args):
     train_s = time.perf_counter() - t1
     del data
     ev = D.evaluate(ctx, den, gs, scene, cam, plain_spp=args.spp, ref_spp=256, reps=5)
+    if args.anim_frames > 0:
+        ev["animated"] = animated(ctx, gs, scene, den, args)
     ev.update({"train_steps": args.denoiser_steps, "train_s": round(train_s, 1), "train_crops": n_crops,
                "crop": 256, "final_loss": [x for x in losses if x == x][-1],
                "weights": "bf16 (FP32 master)", "parity": "unpinned (statistical)"})
     rnd = lambda v: round(v, 6) if isinstance(v, float) else v
     return {k: ({a: rnd(b) for a, b in v.items()} if isinstance(v, dict) else rnd(v)) for k, v in ev.items()}
+
+
+def animated(ctx, gs, scene, den, args):
+    """The same scene with 300 rigid bodies moving (<= 5 cm, <= 2 degrees per frame), BVH refit every frame,
+    args.anim_views 1080p views per frame on the learned 1-spp path; per-frame shadow MSE of the BF16
+    denoiser and of its FP32 copy against 256 samples, for view f mod V of frame f and for every view of the
+    first and last frame."""
+    import numpy as np
+
+    from paper_2410_05095_amd import animate as A
+    from paper_2410_05095_amd import denoise as D
+    from paper_2410_05095_amd import scenegen as sg
+    anim = sg.RigidAnimation(scene, n_bodies=300, seed=args.seed)
+    views = D.orbit_views(np.random.default_rng(args.seed + 77), args.anim_views, 1920, 1080, seed0=5000)
+    F, V = args.anim_frames, args.anim_views
+    plan = lambda f: list(range(V)) if f in (0, F - 1) else [f % V]
+    res = A.run(ctx, scene, gs, den, anim, views, F, plan, log=log)
+    rnd = lambda v: round(v, 6) if isinstance(v, float) else v
+    return {k: rnd(v) for k, v in res.items()}
 
 
 def main():
@@ -129,6 +150,9 @@ def main():
                     help="training steps of the learned 1-spp path (0 = skip the learned-path comparison)")
     ap.add_argument("--denoiser-views", type=int, default=200,
                     help="1080p views of the training scenes rendered for the denoiser's training set (12 crops each)")
+    ap.add_argument("--anim-frames", type=int, default=12,
+                    help="animated frames (moving bodies, refit) rendered after the learned-path comparison")
+    ap.add_argument("--anim-views", type=int, default=16, help="1080p views per animated frame")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of rendering, copy a buffer of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
