@@ -164,9 +164,10 @@ typedef struct rc_rect_light {
 
 enum {
     RC_FLAG_TIMING = 1u,     /* record per-stage device times (rc_get_stage_times) */
-    RC_FLAG_PER_LANE_RECT = 4u /* trace rect-light samples one ray per lane with per-lane stacks even when
-                                  the wave-uniform traversal would be used (area_samples >= 64 and a BVH
-                                  of depth <= 42); same results, for comparison */
+    RC_FLAG_PER_LANE = 4u      /* trace camera rays and rect-light samples one ray per lane with per-lane
+                                  stacks even where the wave-uniform traversal would be used (camera rays
+                                  with ssaa = 2, rect light from 64 samples per pixel; BVH depth <= 42); same
+                                  results outside the FP32 band, for comparison */
 };
 
 typedef struct rc_render_opts {
@@ -256,7 +257,7 @@ enum {
 
 /* Render all views in one persistent kernel launch fed by a device work queue (point lights and
  * 2x2 or 1 sample per pixel).  Every view's outputs are bit-identical to rc_render of that view
- * alone, for any tuning.  flags: RC_FLAG_TIMING (rc_get_stage_times ms[3]), RC_FLAG_GRAPH.  All
+ * alone with RC_FLAG_PER_LANE (the same per-lane traversal), for any tuning.  flags: RC_FLAG_TIMING (rc_get_stage_times ms[3]), RC_FLAG_GRAPH.  All
  * scenes must be built.  Errors: RC_ERR_INVALID_ARG, RC_ERR_NOT_BUILT, RC_ERR_UNSUPPORTED, RC_ERR_HIP. */
 int rc_render_batch(rc_ctx* ctx, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,
                     const rc_point_light* lights, uint32_t n_lights_total, const rc_tune* tune, uint32_t flags);

@@ -480,6 +480,164 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
     }
 }
 
+// Camera rays, wave-uniform closest-hit traversal.  The 64 samples of a packet (an 8x8-pixel tile, or 4x4
+// pixels x 4 samples) share the eye point and walk the BVH together, reading nodes and triangles once per
+// wave through the scalar cache; every lane keeps its own closest hit (t, then the smaller id) and tests
+// only what its own bound allows.  A child that any lane's box test accepts is pushed with a bound shared
+// by all lanes: the squared distance from the eye to its box, a lower bound on every lane's entry distance.
+// A popped entry is skipped when that bound exceeds the largest closest-hit distance of the wave (with a
+// relative margin of 1e-5 that covers the FP32 rounding of the slab tests and of |d| = 1).  Results equal
+// the per-lane traversal's: extra triangle tests can only report true crossings.
+__global__ __launch_bounds__(BLOCK) void k_primary_wave(KParams P)
+{
+    const uint32_t lane = __lane_id();
+    const DevScene sc = P.sc;
+    const uint32_t n_packets = (P.n_items + 63) / 64;
+    const uint32_t KEY_MISS = 0x7F800000u;
+    const float ex = P.cam.eye[0], ey = P.cam.eye[1], ez = P.cam.eye[2];
+    uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
+    const XcdQueue<RECT_CHUNK> queue(P.w.counters, P.slot, n_packets);
+    uint32_t pos = 0, pos_end = 0;
+    for (;;) {
+        if (pos == pos_end) {
+            pos = queue.claim(P.claim);
+            pos_end = pos + P.claim;
+        }
+        const uint32_t j = pos++;
+        if (queue.exhausted(j)) break;
+        const uint64_t blk = queue.at(j);
+        if (blk >= n_packets) continue;
+        const uint32_t item = (uint32_t)blk * 64 + lane;
+        uint32_t px = 0, pk = 0;
+        const bool valid = item < P.n_items && rc_item_to_sample(P.cam, item, px, pk);
+        TravRay ray;
+        ray.o[0] = ex; ray.o[1] = ey; ray.o[2] = ez;
+        ray.d[0] = 1.0f; ray.d[1] = 0.0f; ray.d[2] = 0.0f;
+        float best_t = -INFINITY, best_u = 0.0f, best_v = 0.0f;   // invalid lanes accept nothing
+        uint32_t best_id = RC_NO_HIT;
+        if (valid) {
+            rc_camera_ray(P.cam, px, pk, ray.o, ray.d);
+            best_t = INFINITY;
+            ++rays_cast;
+        }
+#pragma unroll
+        for (int a3 = 0; a3 < 3; ++a3) {
+            float dd = fabsf(ray.d[a3]) < 1e-20f ? copysignf(1e-20f, ray.d[a3]) : ray.d[a3];
+            ray.inv[a3] = 1.0f / dd;
+        }
+        float wmax = INFINITY;                                    // largest closest-hit distance of the wave
+        uint32_t cur = __ballot(valid) != 0 ? 0u : RC_STACK_EMPTY;
+        int sp = 0;
+        uint32_t stk0 = 0, stk1 = 0, lbs0 = 0, lbs1 = 0;         // entry e: lane e % 64 of {stk,lbs}{e / 64}
+        auto pop = [&]() -> uint32_t {
+            const float lim = wmax * 1.00001f;
+            const float lim2 = lim * lim;
+            while (sp > 0) {
+                --sp;
+                const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63);
+                const float lb = __uint_as_float(
+                    (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? lbs0 : lbs1), sp & 63));
+                if (!(lb > lim2)) return w;
+            }
+            return RC_STACK_EMPTY;
+        };
+        while (cur != RC_STACK_EMPTY) {
+            if (!rc_is_leaf(cur)) {
+                rc_const_v4f* np = (rc_const_v4f*)(const void*)(sc.nodes + cur);
+                const rc_v4f lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+                const rc_v4f chf = np[6];
+                uint32_t key[4], cw[4];
+                float lb[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    float nx = ray.inv[0] >= 0.0f ? lx[c] : hx[c], fx = ray.inv[0] >= 0.0f ? hx[c] : lx[c];
+                    float ny = ray.inv[1] >= 0.0f ? ly[c] : hy[c], fy = ray.inv[1] >= 0.0f ? hy[c] : ly[c];
+                    float nz = ray.inv[2] >= 0.0f ? lz[c] : hz[c], fz = ray.inv[2] >= 0.0f ? hz[c] : lz[c];
+                    float t0 = fmaxf(fmaxf((nx - ray.o[0]) * ray.inv[0], (ny - ray.o[1]) * ray.inv[1]),
+                                     fmaxf((nz - ray.o[2]) * ray.inv[2], 0.0f));
+                    float t1 = fminf(fminf((fx - ray.o[0]) * ray.inv[0], (fy - ray.o[1]) * ray.inv[1]),
+                                     (fz - ray.o[2]) * ray.inv[2]);
+                    bool hit = t0 <= fminf(t1 * RC_FAR_GROW, best_t);
+                    uint64_t m = __ballot(hit);
+                    uint32_t k = KEY_MISS;
+                    if (m != 0) {
+                        int first = __builtin_ctzll(m);
+                        k = (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(t0), first) & 0x7FFFFFFFu;
+                    }
+                    key[c] = k;
+                    cw[c] = __float_as_uint(chf[c]);
+                    // squared distance from the eye to the child box (uniform)
+                    float qx = fmaxf(fmaxf(lx[c] - ex, ex - hx[c]), 0.0f);
+                    float qy = fmaxf(fmaxf(ly[c] - ey, ey - hy[c]), 0.0f);
+                    float qz = fmaxf(fmaxf(lz[c] - ez, ez - hz[c]), 0.0f);
+                    float q2 = qx * qx + qy * qy;
+                    lb[c] = q2 + qz * qz;
+                }
+                if (valid) ++node_visits;
+#define RC_CS(a, b)                                                                   \
+    {                                                                                 \
+        bool sw = key[b] < key[a];                                                    \
+        uint32_t ka = sw ? key[b] : key[a], kb = sw ? key[a] : key[b];                \
+        uint32_t ca = sw ? cw[b] : cw[a], cb = sw ? cw[a] : cw[b];                    \
+        float la = sw ? lb[b] : lb[a], lbb = sw ? lb[a] : lb[b];                      \
+        key[a] = ka; key[b] = kb; cw[a] = ca; cw[b] = cb; lb[a] = la; lb[b] = lbb;    \
+    }
+                RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
+#undef RC_CS
+#pragma unroll
+                for (int c = 3; c >= 1; --c) {
+                    if (key[c] < KEY_MISS) {
+                        if (sp < 64) {
+                            stk0 = (int)lane == sp ? cw[c] : stk0;
+                            lbs0 = (int)lane == sp ? __float_as_uint(lb[c]) : lbs0;
+                            ++sp;
+                        } else if (sp < 128) {
+                            stk1 = (int)lane == sp - 64 ? cw[c] : stk1;
+                            lbs1 = (int)lane == sp - 64 ? __float_as_uint(lb[c]) : lbs1;
+                            ++sp;
+                        } else if (lane == 0) {
+                            *P.w.error_flag = 1u;   // beyond the bound the host checked: entry dropped, reported
+                        }
+                    }
+                }
+                cur = key[0] < KEY_MISS ? cw[0] : pop();
+            } else {
+                const uint32_t first = rc_leaf_first(cur), cnt = rc_leaf_count(cur);
+                for (uint32_t i = 0; i < cnt; ++i) {
+                    rc_const_v4f* tp = (rc_const_v4f*)(const void*)(sc.tris + 3 * (size_t)(first + i));
+                    const rc_v4f A = tp[0], B = tp[1], C = tp[2];
+                    if (valid) {
+                        ++tri_tests;
+                        float t, u, v;
+                        bool hit = rc_mt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
+                        const uint32_t id = __float_as_uint(A.w);
+                        if (hit && (t < best_t || (t == best_t && id < best_id))) {
+                            best_t = t; best_u = u; best_v = v; best_id = id;
+                        }
+                    }
+                }
+                float m = best_t;
+                for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+                wmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m)));   // equal in every lane
+                cur = pop();
+            }
+            cur = __builtin_amdgcn_readfirstlane(cur);
+        }
+        if (valid)
+            P.gbuf_out[(size_t)px * (P.cam.ssaa * P.cam.ssaa) + pk] =
+                make_uint4(best_id, __float_as_uint(best_t), __float_as_uint(best_u), __float_as_uint(best_v));
+    }
+    if (P.w.ray_count) {
+        unsigned long long cnt[3] = {rays_cast, node_visits, tri_tests};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            unsigned long long v = cnt[q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) atomicAdd(P.w.ray_count + 2 * q, v);
+        }
+    }
+}
+
 __global__ void k_rect_finish(const uint32_t* counts, uint32_t n_pix, uint32_t N, float* vis)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -511,13 +669,15 @@ int rc_trace_grid(int device)
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, reinterpret_cast<const void*>(&k_rect_packets), BLOCK,
                                                  TravStack<SL, BLOCK, false>::lds_bytes());
-    int e = 0;
+    int e = 0, f = 0;
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave), BLOCK, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, reinterpret_cast<const void*>(&k_primary_wave), BLOCK, 0);
+    e = std::max(e, f);
     return std::max(std::max(std::max(a, d * n_cu), std::max(b, c)), e * n_cu);
 }
 
 void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, const TraceWork& w, int grid,
-                       hipStream_t st)
+                       bool per_lane, hipStream_t st)
 {
     KParams P = {};
     P.sc = sc;
@@ -526,8 +686,15 @@ void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, co
     P.w = w;
     P.n_items = rc_n_items(cam.width, cam.height, cam.ssaa);
     P.slot = 0;
-    P.claim = claim_size(P.n_items, grid, 16, 32, 128);
-    hipLaunchKernelGGL(k_trace<MODE_PRIMARY>, dim3(grid), dim3(BLOCK), lds_bytes<MODE_PRIMARY>(), st, P);
+    // the wave-uniform traversal pays off with 2x2 supersampling (a wave holds 4 samples of each of 16
+    // neighbouring pixels); with one sample per pixel, 8x8-pixel tiles diverge more and per-lane is faster
+    if (sc.max_stack <= 128 && !per_lane && cam.ssaa > 1) {
+        P.claim = claim_size((P.n_items + 63) / 64, grid, 64, 1, 4);
+        hipLaunchKernelGGL(k_primary_wave, dim3(grid), dim3(BLOCK), 0, st, P);
+    } else {
+        P.claim = claim_size(P.n_items, grid, 16, 32, 128);
+        hipLaunchKernelGGL(k_trace<MODE_PRIMARY>, dim3(grid), dim3(BLOCK), lds_bytes<MODE_PRIMARY>(), st, P);
+    }
 }
 
 void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,

@@ -453,7 +453,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     uint4* gbuf = reinterpret_cast<uint4*>(out->d_hit);
     if (timing) RC_HIP(hipEventRecord(c->ev[0], q));
     w.ray_count = c->d_rays + 0;
-    rc_launch_primary(ds, dc, gbuf, w, c->grid, q);
+    rc_launch_primary(ds, dc, gbuf, w, c->grid, opts && (opts->flags & RC_FLAG_PER_LANE), q);
     if (timing) RC_HIP(hipEventRecord(c->ev[1], q));
     if (n_lights > 0 || rect) {
         size_t n_pix = (size_t)cam->width * cam->height;
@@ -468,7 +468,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
             c->counts_cap = n_pix;
         }
         w.ray_count = c->d_rays + 1;
-        bool per_lane = opts && (opts->flags & RC_FLAG_PER_LANE_RECT);
+        bool per_lane = opts && (opts->flags & RC_FLAG_PER_LANE);
         float4* setup = rect ? reinterpret_cast<float4*>(c->d_counts + setup_off) : nullptr;
         rc_launch_shadow(ds, dc, L, gbuf, out->d_shadow, out->d_visibility, c->d_counts, setup, w, c->grid, per_lane,
                          q);

@@ -83,7 +83,7 @@ double rc_bvh_sah(const std::vector<Node4>& nodes);
 #define RC_QUEUE_SLOTS 4
 #define RC_QUEUE_BASE 64
 #define RC_COUNTER_WORDS (RC_QUEUE_BASE + RC_QUEUE_SLOTS * RC_XCDS * 64)
-#define RC_STACK_LDS 24
+#define RC_STACK_LDS 12
 
 struct TraceWork {
     uint32_t* counters;       // device work-queue counters
@@ -96,7 +96,7 @@ struct TraceWork {
 
 // Launchers (k_trace.hip)
 void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, const TraceWork& w,
-                       int grid, hipStream_t st);
+                       int grid, bool per_lane, hipStream_t st);
 void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
                       uint32_t* mask, float* visibility, uint32_t* counts, float4* setup, const TraceWork& w,
                       int grid, bool per_lane_rect, hipStream_t st);

@@ -42,7 +42,7 @@ def single_renders(ctx, scenes, handles, views):
     import torch
     out = []
     for si, cam, lf, nl in views:
-        o = ctx.render(handles[si], cam, scenes[si].point_lights)
+        o = ctx.render(handles[si], cam, scenes[si].point_lights, per_lane=True)
         out.append({k: v.clone() for k, v in o.items() if v is not None})
     torch.cuda.synchronize()
     return out
@@ -156,7 +156,7 @@ def test_batch_64_views_4_scenes(ctx, oracle_mod):
         si, cam, lf, nl = views[i]
         smp = np.sort(rng.choice(cam.n_samples, 3000, replace=False))
         orc = O.OracleScene.from_scene(scenes[si]).render_point(cam, scenes[si].point_lights, smp)
-        o = ctx.render(handles[si], cam, scenes[si].point_lights, sample_rgba=True)
+        o = ctx.render(handles[si], cam, scenes[si].point_lights, sample_rgba=True, per_lane=True)
         torch.cuda.synchronize()
         stt = compare_point(to_np(outs[i]["hit"])[smp], to_np(outs[i]["shadow"])[smp],
                             to_np(o["sample_rgba"])[smp], orc, nl)

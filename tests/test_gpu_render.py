@@ -24,22 +24,25 @@ def ctx():
 
 
 def render_and_compare(ctx, O, scene, cam, rtol=1e-4, sample_idx=None, brute=False):
+    """Render with the default kernels (wave-uniform camera rays) and with per-lane traversal, and check both
+    against one oracle run."""
     import torch
     say(f"[render] {scene.name} {cam.width}x{cam.height} ssaa={cam.ssaa} tris={scene.n_tris}")
     gs = ctx.scene_from(scene).build()
-    out = ctx.render(gs, cam, scene.point_lights, sample_rgba=True)
-    torch.cuda.synchronize()
-    assert ctx.last_error() == 0
     n = cam.n_samples
     smp = np.arange(n) if sample_idx is None else np.asarray(sample_idx)
     osc = O.OracleScene.from_scene(scene, use_bvh=not brute)
     orc = osc.render_point(cam, scene.point_lights, smp, brute=brute)
-    hit = to_np(out["hit"])[smp]
-    mask = to_np(out["shadow"])[smp] if len(scene.point_lights) else None
-    srgba = to_np(out["sample_rgba"])[smp]
-    st = compare_point(hit, mask, srgba, orc, len(scene.point_lights), rtol=rtol)
-    say("[parity]", st)
-    assert_clean(st)
+    for per_lane in (True, False):
+        out = ctx.render(gs, cam, scene.point_lights, sample_rgba=True, per_lane=per_lane)
+        torch.cuda.synchronize()
+        assert ctx.last_error() == 0
+        hit = to_np(out["hit"])[smp]
+        mask = to_np(out["shadow"])[smp] if len(scene.point_lights) else None
+        srgba = to_np(out["sample_rgba"])[smp]
+        st = compare_point(hit, mask, srgba, orc, len(scene.point_lights), rtol=rtol)
+        say("[parity]", "per-lane" if per_lane else "wave", st)
+        assert_clean(st)
     # resolve: bit-exact against the fixed FP32 order applied to the GPU's own samples
     spp = cam.ssaa ** 2
     want = O.resolve_f32(to_np(out["sample_rgba"]).reshape(-1, spp, 4), spp)
@@ -168,7 +171,7 @@ def compare_rect(ctx, O, scene, cam, N, stream, pixels=None):
     outs = {}
     for per_lane in (False, True):
         outs[per_lane] = ctx.render(gs, cam, (), rect=scene.rect_light, area_samples=N, area_stream=stream,
-                                    sample_rgba=True, per_lane_rect=per_lane)
+                                    sample_rgba=True, per_lane=per_lane)
         torch.cuda.synchronize()
         assert ctx.last_error() == 0
     npix = cam.width * cam.height
