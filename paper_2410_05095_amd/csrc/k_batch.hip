@@ -1,7 +1,7 @@
 // Batched rendering megakernel: every view of every scene in one persistent launch.
 //
 // Work items are pixels of all views, numbered view by view in tiles of tile_w x tile_h pixels; a
-// wave claims `queue_depth` items per atomicAdd on the device counter and hands them to its idle
+// wave claims `queue_depth` items per atomicAdd on its XCD's counter (XcdQueue) and hands them to its idle
 // lanes.  A lane renders its pixel completely: for each sample the camera ray (closest hit), the
 // shadow rays towards the view's point lights (any hit), FP64 shading, and finally the fixed-order
 // resolve.  The traversal, shading and resolve use the same device code as the single-view kernels,
@@ -42,7 +42,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
     sc.tris = nullptr;
     TravRay ray;
     TravState ts;
-    uint32_t q_next = 0, q_end = 0;   // wave-local range of claimed items (wave-uniform)
+    const XcdQueue<256> queue(P.w.counters, 3, P.n_items);
+    uint32_t q_next = 0, q_end = 0;   // wave-local range of claimed positions of the XCD's share (wave-uniform)
     bool queue_empty = false;
     uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
 
@@ -153,18 +154,17 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
             if (need == 0) break;
             if (q_next >= q_end) {
                 if (queue_empty) break;
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&P.w.counters[3], P.tune.queue_depth);
-                base = __shfl(base, 0);
-                if (base >= P.n_items) { queue_empty = true; break; }
+                const uint32_t base = queue.claim(P.tune.queue_depth);
+                if (queue.exhausted(base)) { queue_empty = true; break; }
                 q_next = base;
-                q_end = min(base + P.tune.queue_depth, P.n_items);
-                if (q_end >= P.n_items) queue_empty = true;
+                q_end = base + P.tune.queue_depth;
+                if (queue.exhausted(q_end)) queue_empty = true;   // no later claim can hold work
             }
             uint32_t avail = q_end - q_next;
             uint32_t rank = (uint32_t)__popcll(need & below);
             if (state == 0 && rank < avail) {
-                if (!start_item(q_next + rank)) state = 0;
+                const uint64_t item = queue.at(q_next + rank);
+                if (item >= P.n_items || !start_item((uint32_t)item)) state = 0;
             }
             q_next += min(avail, (uint32_t)__popcll(need));
         }
@@ -205,5 +205,6 @@ int rc_batch_max_blocks_per_cu(int device)
 void rc_launch_batch(const BatchParams& P, int grid, hipStream_t st)
 {
     const size_t lds = TravStack<SL, BLOCK, true>::lds_bytes();
+    if (grid < (int)RC_XCDS) grid = RC_XCDS;   // every XCD share of the queue needs workgroups
     hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), lds, st, P);
 }

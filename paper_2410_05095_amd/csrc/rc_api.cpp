@@ -731,7 +731,8 @@ int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc
             if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
             if (!c->capture_stream) RC_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
             RC_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed));
-            rc_launch_fill_u32(c->d_counters, 0u, 8, c->capture_stream);
+            rc_launch_fill_u32(c->d_counters, 0u, 8, c->capture_stream);   // not word 8: the sticky error flag
+            rc_launch_fill_u32(c->d_counters + RC_QUEUE_BASE, 0u, RC_COUNTER_WORDS - RC_QUEUE_BASE, c->capture_stream);
             rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, c->capture_stream);
             rc_launch_batch(P, grid, c->capture_stream);
             hipError_t e = hipStreamEndCapture(c->capture_stream, &c->graph);
@@ -741,7 +742,8 @@ int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc
         }
         RC_HIP(hipGraphLaunch(c->graph_exec, c->stream));
     } else {
-        rc_launch_fill_u32(c->d_counters, 0u, 8, c->stream);
+        rc_launch_fill_u32(c->d_counters, 0u, 8, c->stream);   // not word 8: the sticky error flag
+        rc_launch_fill_u32(c->d_counters + RC_QUEUE_BASE, 0u, RC_COUNTER_WORDS - RC_QUEUE_BASE, c->stream);
         rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, c->stream);
         rc_launch_batch(P, grid, c->stream);
     }

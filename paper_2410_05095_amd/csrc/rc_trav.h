@@ -20,6 +20,34 @@ struct TravState {
     float best_t, best_u, best_v;
 };
 
+// Work queue split over the XCDs.  Workgroups are dispatched to the XCDs round-robin, so workgroup b runs
+// on XCD g = b % RC_XCDS.  The work sequence (items, or 64-ray packets) is cut into chunks of CHUNK that
+// are dealt to the XCDs in turn; the waves of XCD g claim positions j = 0, 1, 2, ... of that XCD's share
+// from their own counter (one atomic per claim of several positions).  The waves of one XCD thus work
+// on neighbouring pixels and share its L2, the eight counters split the atomic traffic, and the fine
+// interleave of chunks keeps the XCDs' shares balanced.
+template <uint32_t CHUNK>
+struct XcdQueue {
+    uint32_t* ctr;
+    uint32_t g;
+    uint64_t n;
+    __device__ XcdQueue(uint32_t* counters, uint32_t slot, uint64_t n_work)
+        : ctr(counters + RC_QUEUE_BASE + (slot * RC_XCDS + blockIdx.x % RC_XCDS) * 64),
+          g(blockIdx.x % RC_XCDS), n(n_work) {}
+    __device__ uint64_t chunk_of(uint64_t j) const { return g + (uint64_t)RC_XCDS * (j / CHUNK); }
+    // work index at position j of this XCD's share (may be >= n inside the last chunk)
+    __device__ uint64_t at(uint64_t j) const { return chunk_of(j) * CHUNK + j % CHUNK; }
+    // no work at position j or beyond
+    __device__ bool exhausted(uint64_t j) const { return chunk_of(j) * CHUNK >= n; }
+    // wave-uniform claim of `count` positions (called by all lanes; lane 0 does the atomic)
+    __device__ uint32_t claim(uint32_t count) const
+    {
+        uint32_t b = 0;
+        if (__lane_id() == 0) b = atomicAdd(ctr, count);
+        return __builtin_amdgcn_readfirstlane(b);
+    }
+};
+
 // Dynamic LDS of the traversal kernels: the per-lane stacks.
 extern __shared__ uint32_t rc_lds[];
 
