@@ -33,7 +33,7 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # the copy-kernel calibration), keyed by (workload, spp, hash of the traversal kernel sources); the
 # value only applies while those sources are unchanged (summaries under profiles/).
 MEASURED_TRAFFIC = {
-    ("big_7M", 64, "af5ccf3ef2c2b6ee:96fd43948bc92d3c:9ea5758bf1aaf9d1"): 426_146_000,
+    ("big_7M", 64, "54ccd231847f07b8:96fd43948bc92d3c:b293fc24f86445cf"): 425_923_000,
 }
 
 
@@ -153,6 +153,9 @@ def main():
     ap.add_argument("--anim-frames", type=int, default=12,
                     help="animated frames (moving bodies, refit) rendered after the learned-path comparison")
     ap.add_argument("--anim-views", type=int, default=16, help="1080p views per animated frame")
+    ap.add_argument("--profile-denoiser", type=int, default=0,
+                    help="instead of rendering, run this many BF16 denoiser inferences of one 1080p view (twice: "
+                         "warm-up, timed) and one FP32-copy inference")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of rendering, copy a buffer of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -176,6 +179,26 @@ def main():
 
     from paper_2410_05095_amd import _native as N
     from paper_2410_05095_amd import scenegen as sg
+
+    if args.profile_denoiser:
+        # the denoiser alone (for profilers): BF16 inference of a 1920x1080 view, then the FP32 copy
+        ctx = N.Context(0)
+        den = N.Denoiser(ctx, seed=args.seed)
+        g = torch.Generator(device="cuda").manual_seed(args.seed)
+        feat = torch.rand((1, 1080, 1920, 8), device="cuda", generator=g).to(torch.bfloat16).contiguous()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        for _ in range(args.profile_denoiser):
+            den.infer(feat)
+        ev[0].record()
+        for _ in range(args.profile_denoiser):
+            den.infer(feat)
+        ev[1].record()
+        den.infer(feat, fp32=True)
+        ev[2].record()
+        torch.cuda.synchronize()
+        print(json.dumps({"denoiser_bf16_ms": ev[0].elapsed_time(ev[1]) / args.profile_denoiser,
+                          "denoiser_fp32_ms": ev[1].elapsed_time(ev[2]), "width": 1920, "height": 1080}), flush=True)
+        return
 
     t0 = time.perf_counter()
     scene = sg.big_scene(args.seed) if args.workload == "big_7M" else sg.city_scene(args.seed)
