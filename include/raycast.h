@@ -212,6 +212,29 @@ int rc_shade(rc_ctx* ctx, rc_scene* scene, const rc_camera* cam, const rc_point_
              const rc_rect_light* rect, const uint32_t* d_hit, const uint32_t* d_shadow, const float* d_visibility,
              float* d_rgba, float* d_sample_rgba);
 
+/* Display post pass of a rendered image (Sec. IV-B: the main pass tone maps and gamma-corrects, the
+ * post-processing pass applies FXAA).  d_rgba: W*H*4 float linear RGBA (16-byte aligned), e.g.
+ * rc_render's d_rgba; d_out: W*H*4 uint8 sRGB RGBA.
+ *  1. Per channel r = c / (1 + c) in FP32 with c = max(c, 0) (Reinhard); the sRGB transfer function of
+ *     IEC 61966-2-1 in FP64 (12.92 v for v <= 0.0031308, else 1.055 v^(1/2.4) - 0.055) quantised as
+ *     floor(255 s + 0.5); alpha quantised as floor(255 clamp(a, 0, 1) + 0.5).
+ *  2. With flags & RC_POST_FXAA, fast approximate anti-aliasing on that 8-bit image (borders clamp):
+ *     integer luma 77 R + 150 G + 29 B; a pixel is processed when the luma range of itself and its four
+ *     neighbours is >= 2048 and 8 x range >= their maximum.  The edge runs along x when the second
+ *     differences across rows, |NW - 2W + SW| + 2 |N - 2C + S| + |NE - 2E + SE|, are >= those across
+ *     columns; the side is the neighbour across the edge with the larger luma step (N, or W, on ties);
+ *     S2 = C + side, grad = that step.  Along the edge, for i = 1..12 in each direction, the sum of the
+ *     luma at i and of its side neighbour ends the search where 2 |sum - S2| >= grad.  With d+, d- the
+ *     end distances (13 when not found) and the nearer end (d+ < d-, else d-) found and departing from
+ *     S2 in the opposite sense to 2C - S2, w_edge = 0.5f - (float)min(d+, d-) / (float)(d+ + d-), else 0.
+ *     Sub-pixel: s = fminf((float)|2(N+S+E+W) + (NE+NW+SE+SW) - 12 C| / (float)(12 range), 1),
+ *     t = ((-2 s + 3) s) s, w_sub = (t t) 0.75 (FP32, in that order); w = max(w_edge, w_sub);
+ *     each colour channel a becomes floor(a + w (b - a) + 0.5) with b the side neighbour's; alpha kept.
+ * Allocates a W*H*4-byte image on first use of a larger size (with FXAA).  Errors: RC_ERR_INVALID_ARG. */
+enum { RC_POST_FXAA = 1u };
+int rc_postprocess(rc_ctx* ctx, const float* d_rgba, uint32_t width, uint32_t height, uint32_t flags,
+                   uint8_t* d_out);
+
 /* Camera rays of every sample, exactly as the traversal generates them: d_origins and
  * d_dirs receive W*H*S x 3 float each (sample s = pixel * S + k).  For verification of the
  * FP32 ray definition. */

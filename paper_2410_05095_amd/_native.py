@@ -115,6 +115,7 @@ SIGNATURES = {
     "rc_denoiser_get_params": (C.c_int, [P, P, P]),
     "rc_denoiser_set_params": (C.c_int, [P, P, P]),
     "rc_denoiser_get_grads": (C.c_int, [P, P, P]),
+    "rc_postprocess": (C.c_int, [P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
     "rc_denoiser_infer": (C.c_int, [P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
     "rc_denoiser_infer_fp32": (C.c_int, [P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
     "rc_denoiser_train_step": (C.c_int, [P, P, P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_float,
@@ -348,6 +349,19 @@ class Context:
                                 cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms)),
               "rc_autotune")
         return best.as_dict(), float(ms.value)
+
+    def postprocess(self, rgba, fxaa: bool = True, out=None):
+        """Display post pass: (H, W, 4) float32 linear RGBA on the GPU -> (H, W, 4) uint8 sRGB (Reinhard tone
+        map, sRGB encoding, then FXAA unless fxaa=False)."""
+        torch = self.torch
+        assert rgba.dtype == torch.float32 and rgba.is_contiguous() and rgba.shape[-1] == 4
+        H, W = int(rgba.shape[0]), int(rgba.shape[1])
+        if out is None:
+            out = torch.empty((H, W, 4), dtype=torch.uint8, device=rgba.device)
+        self._sync_stream()
+        check(lib().rc_postprocess(self.h, C.c_void_p(rgba.data_ptr()), W, H, 1 if fxaa else 0,
+                                   C.c_void_p(out.data_ptr())), "rc_postprocess")
+        return out
 
     def stage_times(self) -> dict:
         t = RcStageTimes()

@@ -180,6 +180,7 @@ int rc_destroy(rc_ctx* c)
     dev_free(c->d_counters);
     dev_free(c->d_rays);
     dev_free(c->d_overflow);
+    dev_free(c->d_post);
     dev_free(c->d_counts);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
@@ -509,6 +510,28 @@ int rc_shade(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light*
     }
     rc_launch_shade(ds, dc, L, reinterpret_cast<const uint4*>(d_hit), n_lights ? d_shadow : nullptr, d_vis, d_rgba,
                     d_sample_rgba, c->stream);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+int rc_postprocess(rc_ctx* c, const float* d_rgba, uint32_t width, uint32_t height, uint32_t flags, uint8_t* d_out)
+{
+    if (!c || !d_rgba || !d_out || width == 0 || height == 0) return RC_ERR_INVALID_ARG;
+    if ((flags & ~(uint32_t)RC_POST_FXAA) != 0) return RC_ERR_INVALID_ARG;
+    if ((uint64_t)width * height > (1ull << 30)) return RC_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(d_rgba) & 15u || reinterpret_cast<uintptr_t>(d_out) & 3u) return RC_ERR_INVALID_ARG;
+    RC_HIP(hipSetDevice(c->device));
+    const bool fxaa = (flags & RC_POST_FXAA) != 0;
+    const size_t bytes = (size_t)width * height * 4;
+    if (fxaa && bytes > c->post_cap) {
+        RC_HIP(hipStreamSynchronize(c->stream));
+        dev_free(c->d_post);
+        c->post_cap = 0;
+        int st = dev_alloc(&c->d_post, bytes);
+        if (st != RC_OK) return st;
+        c->post_cap = bytes;
+    }
+    rc_launch_postprocess(d_rgba, width, height, fxaa, c->d_post, d_out, c->stream);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

@@ -15,6 +15,8 @@ struct rc_ctx {
     size_t overflow_words = 0;
     uint32_t* d_counts = nullptr;         // per-pixel visible-sample counters of the rect light
     size_t counts_cap = 0;
+    uint8_t* d_post = nullptr;            // tone-mapped image between the two post-pass kernels
+    size_t post_cap = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
     bool timed_batch = false;
