@@ -120,6 +120,15 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a)
         }
 }
 
+// Tile of workgroup b among n: workgroups are dispatched to the 8 XCDs round-robin (b % 8), so XCD g is
+// given the contiguous range of tiles [g q + min(g, r), ...) with q = n / 8, r = n % 8.  Tiles that share
+// halo rows then run on the same XCD and meet in its L2.
+__device__ inline int xcd_tile(int b, int n)
+{
+    const int g = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+    return g * q + min(g, r) + k;
+}
+
 // ---------------------------------------------------------------- 3x3 convolution, LDS-tiled
 // Workgroup of 4 waves; output tile = 4 rows x TW = 16 MT columns of one image, wave w computes row w:
 // MT 16-pixel M-tiles x NT 16-channel N-tiles.  The input halo (6 rows x TW + 2 columns) of a chunk of
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
     uint16_t* lds = reinterpret_cast<uint16_t*>(conv_lds);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + 3) / 4;
-    int tt = blockIdx.x;
+    int tt = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tt % tiles_x;
     tt /= tiles_x;
     const int ty = tt % tiles_y, n = tt / tiles_y;
