@@ -84,7 +84,7 @@ def cpu_baseline(scene, cam, args, budget_s=12.0):
 
 
 def learned_path(ctx, gs, scene, cam, args):
-    """Train the denoiser on the method's own 1/256-sample renders of two other scene seeds, then compare
+    """Train the denoiser on the method's own 1/256-sample renders of other scene seeds, then compare
     on this frame: shadow MSE against 256 samples and device frame time, learned 1 spp vs plain."""
     import torch
 
@@ -93,7 +93,7 @@ def learned_path(ctx, gs, scene, cam, args):
     from paper_2410_05095_amd import scenegen as sg
     t0 = time.perf_counter()
     train_scenes = []
-    for seed in (args.seed + 1, args.seed + 2):
+    for seed in range(args.seed + 1, args.seed + 1 + args.denoiser_scenes):
         sc = sg.big_scene(seed)
         train_scenes.append((sc, ctx.scene_from(sc).build()))
     log(f"[bench] training scenes ready ({time.perf_counter() - t0:.1f} s)")
@@ -198,9 +198,11 @@ def main():
     ap.add_argument("--spp", type=int, default=64, help="rect-light samples per pixel (big_7M)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--denoiser-steps", type=int, default=6000,
+    ap.add_argument("--denoiser-steps", type=int, default=12000,
                     help="training steps of the learned 1-spp path (0 = skip the learned-path comparison)")
-    ap.add_argument("--denoiser-views", type=int, default=200,
+    ap.add_argument("--denoiser-scenes", type=int, default=4,
+                    help="training scenes (seeds after the evaluation seed) of the denoiser's training set")
+    ap.add_argument("--denoiser-views", type=int, default=400,
                     help="1080p views of the training scenes rendered for the denoiser's training set (12 crops each)")
     ap.add_argument("--anim-frames", type=int, default=12,
                     help="animated frames (moving bodies, refit) rendered after the learned-path comparison")
