@@ -170,6 +170,32 @@ def hard_shadows(ctx, gs, scene, cam, args):
                              "(raster + hardware ray queries; resolution not stated)"}
 
 
+def device_build(ctx, scene, cam, kw, args):
+    """The GPU LBVH build of the same scene (positions already in HBM): build time (median of 3, from the
+    first kernel to the finished tree, allocation included), tree size and SAH cost, and the frame's
+    device time rendered through that tree (median of args.steps frames)."""
+    import numpy as np
+    gs = ctx.scene_from(scene)
+    ms = []
+    for _ in range(3):
+        gs.build(device=True)
+        ms.append(gs.stats()["build_ms"])
+    st = gs.stats()
+    out = {}
+    for _ in range(args.warmup):
+        ctx.render(gs, cam, out=out, timing=True, **kw)
+    frames = []
+    for _ in range(args.steps):
+        ctx.render(gs, cam, out=out, timing=True, **kw)
+        frames.append(ctx.stage_times())
+    assert ctx.last_error() == 0
+    gs.close()
+    med = lambda k: round(float(np.median([f[k] for f in frames])), 4)
+    return {"build_ms": round(float(np.median(ms)), 2), "nodes": int(st["n_nodes"]), "depth": int(st["depth"]),
+            "sah": round(st["sah_cost"], 2), "frame_device_ms": med("total_ms"), "shadow_ms": med("shadow_ms"),
+            "primary_ms": med("primary_ms")}
+
+
 def animated(ctx, gs, scene, den, args):
     """The same scene with 300 rigid bodies moving (<= 5 cm, <= 2 degrees per frame), BVH refit every frame,
     args.anim_views 1080p views per frame on the learned 1-spp path; per-frame shadow MSE of the BF16
@@ -210,6 +236,8 @@ def main():
     ap.add_argument("--profile-denoiser", type=int, default=0,
                     help="instead of rendering, run this many BF16 denoiser inferences of one 1080p view (twice: "
                          "warm-up, timed) and one FP32-copy inference")
+    ap.add_argument("--build-only", type=int, default=0,
+                    help="instead of rendering, build the scene's BVH on the GPU this many times (for profilers)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of rendering, copy a buffer of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -259,6 +287,14 @@ def main():
     cam = scene.cameras[0]
     log(f"[bench] scene {scene.name}: {scene.n_tris} tris, generated in {time.perf_counter() - t0:.1f} s")
     ctx = N.Context(0)
+    if args.build_only:
+        gs = ctx.scene_from(scene)
+        ms = []
+        for _ in range(args.build_only):
+            gs.build(device=True)
+            ms.append(gs.stats()["build_ms"])
+        print(json.dumps({"device_build_ms": ms, "tris": scene.n_tris, **gs.stats()}), flush=True)
+        return
     gs = ctx.scene_from(scene).build()
     bst = gs.stats()
     log(f"[bench] BVH: {bst}")
@@ -328,6 +364,7 @@ def main():
                       "logical_node_tri_GBps": round(logical_bytes / (dom_ms / 1000.0) / 1e9, 1)}),
     }
     res["post"] = post_pass(ctx, out, args)
+    res["device_bvh"] = device_build(ctx, scene, cam, kw, args)
     if args.workload == "big_7M":
         res["hard_shadows"] = hard_shadows(ctx, gs, scene, cam, args)
     if args.workload == "big_7M" and args.denoiser_steps > 0:

@@ -90,16 +90,28 @@ int rc_scene_create(rc_ctx* ctx, const rc_scene_desc* desc, rc_scene** out);
 int rc_scene_destroy(rc_ctx* ctx, rc_scene* scene);
 
 /* --------------------------------------------------------------- BVH ---- */
-/* Build the scene's BVH on the host: binned SAH (`bins` bins per axis, default 32),
- * leaves of at most `max_leaf` triangles (1..4, default 4), collapsed to a 4-wide BVH
- * with all four child boxes of a node in one 128-byte record.  `node_cost` is the SAH
- * cost of visiting a node relative to one triangle test (default 4, range (0, 64]); it
- * decides when a range of at most max_leaf triangles becomes a leaf.  Replaces any
- * previous BVH.  Synchronous with respect to the host (uploads on the context stream). */
+/* Build the scene's BVH, the acceleration structure that lets a ray find its hits in
+ * logarithmic time (Sec. IV-B, "Ray-traced shadows"), as a 4-wide BVH with all four
+ * child boxes of a node in one 128-byte record, nodes in breadth-first level order.
+ * `method` RC_BUILD_HOST_SAH (0, default): binned SAH on the host (`bins` bins per axis,
+ * default 32; `node_cost` = SAH cost of visiting a node relative to one triangle test,
+ * default 4, range (0, 64], deciding when a range of at most max_leaf triangles becomes a
+ * leaf), then uploaded.  RC_BUILD_DEVICE_LBVH (1): built on the GPU from the positions
+ * already there: triangles sorted by the 63-bit Morton code of their box centroid in the
+ * centroid bounds (stable, ties by triangle id), the binary radix tree over the sorted
+ * codes, exact FP32 boxes bottom-up, then collapsed level by level to 4-wide (a node
+ * repeatedly opens its child of largest box surface that holds more than max_leaf
+ * triangles, until it has four children); every subtree of at most max_leaf triangles
+ * is one leaf (`bins` and `node_cost` are ignored).  Both give exact child boxes (FP32
+ * min/max of what the child holds) and leaves of at most `max_leaf` (1..4, default 4)
+ * triangles.  Replaces any previous BVH.  Synchronous with respect to the host (works on
+ * the context stream and waits for it). */
+enum { RC_BUILD_HOST_SAH = 0u, RC_BUILD_DEVICE_LBVH = 1u };
 typedef struct rc_build_opts {
     uint32_t bins;
     uint32_t max_leaf;
     float node_cost;
+    uint32_t method;
 } rc_build_opts;
 int rc_bvh_build(rc_ctx* ctx, rc_scene* scene, const rc_build_opts* opts);
 

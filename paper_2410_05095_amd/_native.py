@@ -37,7 +37,7 @@ class RcSceneDesc(C.Structure):
 
 
 class RcBuildOpts(C.Structure):
-    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("node_cost", C.c_float)]
+    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("node_cost", C.c_float), ("method", C.c_uint32)]
 
 
 class RcBvhStats(C.Structure):
@@ -400,10 +400,11 @@ class Scene:
         except Exception:
             pass
 
-    def build(self, bins: int = 32, max_leaf: int = 4, node_cost: float = 4.0):
+    def build(self, bins: int = 32, max_leaf: int = 4, node_cost: float = 4.0, device: bool = False):
+        """Host binned-SAH build, or with device=True the GPU LBVH build (RC_BUILD_DEVICE_LBVH)."""
         self.ctx._sync_stream()
-        check(lib().rc_bvh_build(self.ctx.h, self.h, C.byref(RcBuildOpts(bins, max_leaf, node_cost))),
-              "rc_bvh_build")
+        opts = RcBuildOpts(bins, max_leaf, node_cost, 1 if device else 0)
+        check(lib().rc_bvh_build(self.ctx.h, self.h, C.byref(opts)), "rc_bvh_build")
         return self
 
     def refit(self):

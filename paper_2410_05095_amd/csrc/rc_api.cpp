@@ -290,15 +290,54 @@ int rc_scene_destroy(rc_ctx* c, rc_scene* s)
     return RC_OK;
 }
 
+// Device build (k_build.hip): the tree and leaf order stay on the GPU; the nodes are read back once for the
+// host-side statistics (leaf count, SAH cost), after the build time is taken.
+static int build_device(rc_ctx* c, rc_scene* s, uint32_t max_leaf)
+{
+    free_bvh(s);
+    RC_HIP(hipStreamSynchronize(c->stream));
+    auto t0 = std::chrono::steady_clock::now();
+    HostBvh hb;
+    int st = dev_alloc(&s->d_order, s->nt);
+    if (st == RC_OK) st = dev_alloc(&s->d_tris, 3 * (size_t)s->nt);
+    if (st != RC_OK) { free_bvh(s); return st; }
+    Node4* d_nodes = nullptr;
+    uint32_t n_nodes = 0;
+    hipError_t e = rc_build_bvh_device(s->d_pos, s->d_idx, s->nt, max_leaf, &d_nodes, &n_nodes, s->d_order,
+                                       hb.level_start, c->stream);
+    if (e != hipSuccess) { free_bvh(s); return hip_status(e); }
+    s->d_nodes = d_nodes;
+    rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, c->stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) { free_bvh(s); return RC_ERR_HIP; }
+    s->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    hb.nodes.resize(n_nodes);
+    if (hipMemcpy(hb.nodes.data(), d_nodes, (size_t)n_nodes * sizeof(Node4), hipMemcpyDeviceToHost) != hipSuccess) {
+        free_bvh(s);
+        return RC_ERR_HIP;
+    }
+    hb.depth = (uint32_t)hb.level_start.size() - 1;
+    hb.max_stack = 3 * hb.depth + 1;
+    for (const Node4& nd : hb.nodes)
+        for (int k = 0; k < 4; ++k) hb.n_leaves += rc_is_leaf(nd.child[k]) ? 1u : 0u;
+    hb.sah_cost = rc_bvh_sah(hb.nodes);
+    s->hb = std::move(hb);
+    s->built = true;
+    s->sah_stale = false;
+    return ensure_overflow(c, s->hb.max_stack);
+}
+
 int rc_bvh_build(rc_ctx* c, rc_scene* s, const rc_build_opts* o)
 {
     if (!c || !s) return RC_ERR_INVALID_ARG;
     uint32_t bins = o && o->bins ? o->bins : 32u;
     uint32_t max_leaf = o && o->max_leaf ? o->max_leaf : 4u;
     float node_cost = o && o->node_cost != 0.0f ? o->node_cost : 4.0f;
-    if (bins < 2 || bins > 256 || max_leaf < 1 || max_leaf > 4 || !(node_cost > 0.0f && node_cost <= 64.0f))
+    const uint32_t method = o ? o->method : RC_BUILD_HOST_SAH;
+    if (bins < 2 || bins > 256 || max_leaf < 1 || max_leaf > 4 || !(node_cost > 0.0f && node_cost <= 64.0f) ||
+        method > RC_BUILD_DEVICE_LBVH)
         return RC_ERR_INVALID_ARG;
     RC_HIP(hipSetDevice(c->device));
+    if (method == RC_BUILD_DEVICE_LBVH) return build_device(c, s, max_leaf);
     if (s->host_pos_stale) {
         RC_HIP(hipMemcpyAsync(s->pos.data(), s->d_pos, s->pos.size() * 4, hipMemcpyDeviceToHost, c->stream));
         RC_HIP(hipStreamSynchronize(c->stream));

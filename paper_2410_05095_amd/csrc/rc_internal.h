@@ -74,6 +74,10 @@ struct HostBvh {
 bool rc_build_bvh_host(const float* pos, const uint32_t* idx, uint32_t n_tris,
                        uint32_t bins, uint32_t max_leaf, float node_cost, HostBvh& out);
 double rc_bvh_sah(const std::vector<Node4>& nodes);
+// Device LBVH build (k_build.hip); see rc_bvh_build with RC_BUILD_DEVICE_LBVH.
+hipError_t rc_build_bvh_device(const float* d_pos, const uint32_t* d_idx, uint32_t n, uint32_t max_leaf,
+                               Node4** d_nodes_out, uint32_t* n_nodes_out, uint32_t* d_order,
+                               std::vector<uint32_t>& level_start, hipStream_t st);
 
 // Traversal launch geometry
 #define RC_TRACE_BLOCK 128

@@ -23,12 +23,13 @@ def ctx():
     c.close()
 
 
-def render_and_compare(ctx, O, scene, cam, rtol=1e-4, sample_idx=None, brute=False):
+def render_and_compare(ctx, O, scene, cam, rtol=1e-4, sample_idx=None, brute=False, device_build=False):
     """Render with the default kernels (wave-uniform camera rays) and with per-lane traversal, and check both
     against one oracle run."""
     import torch
-    say(f"[render] {scene.name} {cam.width}x{cam.height} ssaa={cam.ssaa} tris={scene.n_tris}")
-    gs = ctx.scene_from(scene).build()
+    say(f"[render] {scene.name} {cam.width}x{cam.height} ssaa={cam.ssaa} tris={scene.n_tris} "
+        f"build={'device' if device_build else 'host'}")
+    gs = ctx.scene_from(scene).build(device=device_build)
     n = cam.n_samples
     smp = np.arange(n) if sample_idx is None else np.asarray(sample_idx)
     osc = O.OracleScene.from_scene(scene, use_bvh=not brute)
@@ -161,13 +162,14 @@ def test_render_error_paths(ctx):
     assert ctx.last_error() == 0
 
 
-def compare_rect(ctx, O, scene, cam, N, stream, pixels=None):
+def compare_rect(ctx, O, scene, cam, N, stream, pixels=None, device_build=False):
     """Both rect-light kernels (wave-uniform traversal, used from 64 samples per pixel; per-lane stacks)
     against one oracle run: hit ids and visible-sample counts exact outside the FP32 band, radiance within
     1e-4."""
     import torch
-    say(f"[rect] {scene.name} {cam.width}x{cam.height} N={N} tris={scene.n_tris}")
-    gs = ctx.scene_from(scene).build()
+    say(f"[rect] {scene.name} {cam.width}x{cam.height} N={N} tris={scene.n_tris} "
+        f"build={'device' if device_build else 'host'}")
+    gs = ctx.scene_from(scene).build(device=device_build)
     outs = {}
     for per_lane in (False, True):
         outs[per_lane] = ctx.render(gs, cam, (), rect=scene.rect_light, area_samples=N, area_stream=stream,
