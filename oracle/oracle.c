@@ -189,11 +189,13 @@ static ev3 ev3_rounded(v3 a) { ev3 r = {{a.x, U32R * fabs(a.x)}, {a.y, U32R * fa
 /* ------------------------------------------------------------------------- */
 /* Triangles and the exact Moller-Trumbore test with FP32 certainty.          */
 /* ------------------------------------------------------------------------- */
+struct or_inst;
 typedef struct {
     const float* pos; int64_t nv;
     const uint32_t* idx; int64_t nt;
     const uint32_t* tri_mat;
     const float* mats; int64_t nmat;    /* albedo rgb, roughness, metallic */
+    const struct or_inst* inst;         /* NULL, or the instances that answer hit queries (two-level) */
 } or_scene;
 
 static void tri_verts(const or_scene* s, uint32_t t, v3* a, v3* b, v3* c)
@@ -301,7 +303,8 @@ typedef struct or_bvh {
     const or_scene* scene;
     bnode* nodes; int64_t n_nodes, cap;
     uint32_t* tris;
-    double* cen;    /* centroids, 3 per triangle */
+    double* cen;    /* centroids, 3 per triangle of the range, indexed by id - tri0 */
+    int64_t tri0;   /* first triangle id of the range */
     double margin;  /* absolute box padding */
     int depth;
 } or_bvh;
@@ -317,15 +320,15 @@ static void tri_bounds(const or_scene* s, uint32_t t, double lo[3], double hi[3]
     }
 }
 
-static void select_kth(uint32_t* t, const double* cen, int axis, int64_t lo, int64_t hi, int64_t k)
+static void select_kth(uint32_t* t, const double* cen, int64_t base, int axis, int64_t lo, int64_t hi, int64_t k)
 {
     /* quickselect: afterwards t[lo..k) <= t[k] <= t[k+1..hi) on the centroid axis */
     while (hi - lo > 1) {
-        double pv = cen[3 * (int64_t)t[lo + (hi - lo) / 2] + axis];
+        double pv = cen[3 * ((int64_t)t[lo + (hi - lo) / 2] - base) + axis];
         int64_t i = lo, j = hi - 1;
         while (i <= j) {
-            while (cen[3 * (int64_t)t[i] + axis] < pv) ++i;
-            while (cen[3 * (int64_t)t[j] + axis] > pv) --j;
+            while (cen[3 * ((int64_t)t[i] - base) + axis] < pv) ++i;
+            while (cen[3 * ((int64_t)t[j] - base) + axis] > pv) --j;
             if (i <= j) { uint32_t tmp = t[i]; t[i] = t[j]; t[j] = tmp; ++i; --j; }
         }
         if (k <= j) hi = j + 1;
@@ -350,7 +353,7 @@ static int32_t build_rec(or_bvh* B, int64_t first, int64_t count, int depth)
         tri_bounds(B->scene, B->tris[i], lo, hi);
         for (int k = 0; k < 3; ++k) {
             nd.lo[k] = fmin(nd.lo[k], lo[k]); nd.hi[k] = fmax(nd.hi[k], hi[k]);
-            double cv = B->cen[3 * (int64_t)B->tris[i] + k];
+            double cv = B->cen[3 * ((int64_t)B->tris[i] - B->tri0) + k];
             clo[k] = fmin(clo[k], cv); chi[k] = fmax(chi[k], cv);
         }
     }
@@ -360,7 +363,7 @@ static int32_t build_rec(or_bvh* B, int64_t first, int64_t count, int depth)
         int axis = 0;
         for (int k = 1; k < 3; ++k) if (chi[k] - clo[k] > chi[axis] - clo[axis]) axis = k;
         int64_t mid = first + count / 2;
-        select_kth(B->tris, B->cen, axis, first, first + count, mid);
+        select_kth(B->tris, B->cen, B->tri0, axis, first, first + count, mid);
         nd.count = 0;
         B->nodes[id] = nd;
         int32_t l = build_rec(B, first, mid - first, depth + 1);
@@ -372,29 +375,39 @@ static int32_t build_rec(or_bvh* B, int64_t first, int64_t count, int depth)
     return id;
 }
 
-OR_API or_bvh* or_bvh_build(const or_scene* s)
+/* BVH over the triangles first .. first + count - 1 of the scene (ids stay the scene's) */
+static or_bvh* bvh_build_range(const or_scene* s, int64_t first, int64_t count, double scale)
 {
     or_bvh* B = (or_bvh*)calloc(1, sizeof(or_bvh));
     B->scene = s;
     B->cap = 1024;
     B->nodes = (bnode*)malloc((size_t)B->cap * sizeof(bnode));
-    B->tris = (uint32_t*)malloc((size_t)(s->nt > 0 ? s->nt : 1) * sizeof(uint32_t));
-    B->cen = (double*)malloc((size_t)(s->nt > 0 ? s->nt : 1) * 3 * sizeof(double));
-    double scale = 1.0;
-    for (int64_t i = 0; i < 3 * s->nv; ++i) scale = fmax(scale, fabs((double)s->pos[i]));
+    B->tris = (uint32_t*)malloc((size_t)(count > 0 ? count : 1) * sizeof(uint32_t));
+    B->cen = (double*)malloc((size_t)(count > 0 ? count : 1) * 3 * sizeof(double));
+    B->tri0 = first;
     /* pad boxes well beyond FP32 rounding of the GPU box test and of the hit decisions */
     B->margin = 1e-4 * scale;
-    for (int64_t t = 0; t < s->nt; ++t) {
+    for (int64_t i = 0; i < count; ++i) {
+        int64_t t = first + i;
         v3 a, b, c;
         tri_verts(s, (uint32_t)t, &a, &b, &c);
-        B->tris[t] = (uint32_t)t;
-        B->cen[3 * t + 0] = (a.x + b.x + c.x) / 3.0;
-        B->cen[3 * t + 1] = (a.y + b.y + c.y) / 3.0;
-        B->cen[3 * t + 2] = (a.z + b.z + c.z) / 3.0;
+        B->tris[i] = (uint32_t)t;
+        B->cen[3 * i + 0] = (a.x + b.x + c.x) / 3.0;
+        B->cen[3 * i + 1] = (a.y + b.y + c.y) / 3.0;
+        B->cen[3 * i + 2] = (a.z + b.z + c.z) / 3.0;
     }
-    if (s->nt > 0) build_rec(B, 0, s->nt, 0);
+    if (count > 0) build_rec(B, 0, count, 0);
     return B;
 }
+
+static double scene_scale(const or_scene* s)
+{
+    double scale = 1.0;
+    for (int64_t i = 0; i < 3 * s->nv; ++i) scale = fmax(scale, fabs((double)s->pos[i]));
+    return scale;
+}
+
+OR_API or_bvh* or_bvh_build(const or_scene* s) { return bvh_build_range(s, 0, s->nt, scene_scale(s)); }
 
 OR_API void or_bvh_free(or_bvh* B)
 {
@@ -483,10 +496,9 @@ static void acc_init(closest_acc* A)
     A->pass_id1 = NO_HIT;
 }
 
-static void closest_bvh(const or_bvh* B, const ray_ev* r, double tmin, double tmax, double c, hit_rec* out)
+static void closest_bvh_acc(const or_bvh* B, const ray_ev* r, double tmin, double tmax, double c, closest_acc* Ap)
 {
-    closest_acc A;
-    acc_init(&A);
+    closest_acc A = *Ap;
     if (B->n_nodes > 0) {
         int32_t stack[256];
         int sp = 0;
@@ -511,6 +523,14 @@ static void closest_bvh(const or_bvh* B, const ray_ev* r, double tmin, double tm
             }
         }
     }
+    *Ap = A;
+}
+
+static void closest_bvh(const or_bvh* B, const ray_ev* r, double tmin, double tmax, double c, hit_rec* out)
+{
+    closest_acc A;
+    acc_init(&A);
+    closest_bvh_acc(B, r, tmin, tmax, c, &A);
     closest_finish(&A, out);
 }
 
@@ -567,6 +587,200 @@ static int any_bvh(const or_scene* s, const or_bvh* B, const ray_ev* r, double t
     return occluded;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Two-level scenes (Sec. IV-B, "Ray-traced shadows": one acceleration       */
+/* structure per mesh, instanced with a transform under a top level).        */
+/* Instance i holds the contiguous triangles first_i .. first_i + count_i - 1 */
+/* of the rest-frame scene and a world-to-object map x' = M x + m (FP32).    */
+/* A world ray is mapped into each instance as o' = M o + m, d' = M d (the   */
+/* FP32 side evaluates every component as ((M0 a0 + M1 a1) + M2 a2) [+ m])   */
+/* and tested there; t is the parameter along the mapped ray.  The answer is */
+/* the closest (resp. any) hit over all instances, ties to the smaller id.   */
+/* ------------------------------------------------------------------------- */
+typedef struct or_inst {
+    const or_scene* rest;
+    int64_t n;
+    uint32_t* range;     /* first, count per instance */
+    float* w2o;          /* 12 per instance, row-major [M | m] */
+    bnode* wbox;         /* padded world box of each instance (only lo/hi used) */
+    or_bvh** bvh;        /* per-instance BVH over its rest triangles */
+    double margin;
+} or_inst;
+
+/* x' = M x + m in FP32 for the rigid map x = R x' + t given as [R | t]: M = R^T, m = -(R^T t), each
+ * component of R^T t evaluated as ((R0k t0 + R1k t1) + R2k t2) */
+OR_API void or_w2o_f32(const float* o2w, int64_t n, float* w2o)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const float* X = o2w + 12 * i;
+        float* W = w2o + 12 * i;
+        for (int k = 0; k < 3; ++k) {
+            for (int j = 0; j < 3; ++j) W[4 * k + j] = X[4 * j + k];
+            float a = X[k] * X[3];
+            float b = X[4 + k] * X[7];
+            float c = X[8 + k] * X[11];
+            W[4 * k + 3] = -((a + b) + c);
+        }
+    }
+}
+
+static ev3 xform_pt(const float* W, ev3 p, int affine)
+{
+    ev3 r;
+    ev* out[3] = {&r.x, &r.y, &r.z};
+    for (int k = 0; k < 3; ++k) {
+        ev3 row = {{W[4 * k], 0.0}, {W[4 * k + 1], 0.0}, {W[4 * k + 2], 0.0}};
+        ev v = ev3_dot(row, p);
+        if (affine) v = ev_add(v, ev_x(W[4 * k + 3], 0.0));
+        *out[k] = v;
+    }
+    return r;
+}
+
+static ray_ev xform_ray(const float* W, const ray_ev* r)
+{
+    ray_ev q;
+    q.eo = xform_pt(W, r->eo, 1);
+    q.ed = xform_pt(W, r->ed, 0);
+    /* the values are the FP64 images of the world ray's values */
+    ev3 o = xform_pt(W, ev3_exact(r->o), 1), d = xform_pt(W, ev3_exact(r->d), 0);
+    q.o = mk(o.x.v, o.y.v, o.z.v);
+    q.d = mk(d.x.v, d.y.v, d.z.v);
+    return q;
+}
+
+/* world box: the corners of the instance's rest box mapped by the exact inverse of x' = M x + m */
+static void inst_world_box(const float* W, const double lo[3], const double hi[3], double margin, bnode* out)
+{
+    double M[3][3], Mi[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[a][b] = W[4 * a + b];
+    double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                 M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+    Mi[0][0] = (M[1][1] * M[2][2] - M[1][2] * M[2][1]) / det;
+    Mi[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) / det;
+    Mi[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) / det;
+    Mi[1][0] = (M[1][2] * M[2][0] - M[1][0] * M[2][2]) / det;
+    Mi[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) / det;
+    Mi[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / det;
+    Mi[2][0] = (M[1][0] * M[2][1] - M[1][1] * M[2][0]) / det;
+    Mi[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) / det;
+    Mi[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / det;
+    for (int k = 0; k < 3; ++k) { out->lo[k] = INFINITY; out->hi[k] = -INFINITY; }
+    for (int corner = 0; corner < 8; ++corner) {
+        double x[3];
+        for (int k = 0; k < 3; ++k) x[k] = ((corner >> k) & 1 ? hi[k] : lo[k]) - W[4 * k + 3];
+        for (int a = 0; a < 3; ++a) {
+            double p = Mi[a][0] * x[0] + Mi[a][1] * x[1] + Mi[a][2] * x[2];
+            out->lo[a] = fmin(out->lo[a], p);
+            out->hi[a] = fmax(out->hi[a], p);
+        }
+    }
+    for (int k = 0; k < 3; ++k) { out->lo[k] -= margin; out->hi[k] += margin; }
+    out->left = out->right = -1;
+    out->first = out->count = 0;
+}
+
+OR_API or_inst* or_inst_create(const or_scene* rest, int64_t n, const uint32_t* range, const float* w2o, int use_bvh)
+{
+    or_inst* I = (or_inst*)calloc(1, sizeof(or_inst));
+    I->rest = rest;
+    I->n = n;
+    I->range = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * 2 * sizeof(uint32_t));
+    I->w2o = (float*)malloc((size_t)(n > 0 ? n : 1) * 12 * sizeof(float));
+    I->wbox = (bnode*)malloc((size_t)(n > 0 ? n : 1) * sizeof(bnode));
+    I->bvh = (or_bvh**)calloc((size_t)(n > 0 ? n : 1), sizeof(or_bvh*));
+    memcpy(I->range, range, (size_t)n * 2 * sizeof(uint32_t));
+    memcpy(I->w2o, w2o, (size_t)n * 12 * sizeof(float));
+    double scale = scene_scale(rest);
+    I->margin = 1e-4 * scale;
+    for (int64_t i = 0; i < n; ++i) {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (uint32_t t = range[2 * i]; t < range[2 * i] + range[2 * i + 1]; ++t) {
+            double tl[3], th[3];
+            tri_bounds(rest, t, tl, th);
+            for (int k = 0; k < 3; ++k) { lo[k] = fmin(lo[k], tl[k]); hi[k] = fmax(hi[k], th[k]); }
+        }
+        inst_world_box(I->w2o + 12 * i, lo, hi, I->margin, &I->wbox[i]);
+        if (use_bvh) I->bvh[i] = bvh_build_range(rest, range[2 * i], range[2 * i + 1], scale);
+    }
+    return I;
+}
+
+OR_API void or_inst_free(or_inst* I)
+{
+    if (!I) return;
+    for (int64_t i = 0; i < I->n; ++i) or_bvh_free(I->bvh[i]);
+    free(I->bvh); free(I->wbox); free(I->w2o); free(I->range); free(I);
+}
+
+static void closest_inst(const or_inst* I, int use_bvh, const ray_ev* r, double tmin, double tmax, double c,
+                         hit_rec* out)
+{
+    closest_acc A;
+    acc_init(&A);
+    for (int64_t i = 0; i < I->n; ++i) {
+        double te = box_enter(&I->wbox[i], r, tmin - I->margin, tmax);
+        if (te == INFINITY) continue;
+        if (A.have_best && te > A.best_thi + I->margin) continue;
+        ray_ev q = xform_ray(I->w2o + 12 * i, r);
+        if (use_bvh && I->bvh[i]) {
+            closest_bvh_acc(I->bvh[i], &q, tmin, tmax, c, &A);
+        } else {
+            for (uint32_t t = I->range[2 * i]; t < I->range[2 * i] + I->range[2 * i + 1]; ++t) {
+                tri_test tt;
+                mt_test(I->rest, t, &q, tmin, tmax, c, &tt);
+                closest_consider(&A, t, &tt);
+            }
+        }
+    }
+    closest_finish(&A, out);
+}
+
+static int any_inst(const or_inst* I, int use_bvh, const ray_ev* r, double tmin, double tmax, double c, int* band)
+{
+    int occluded = 0, unc = 0;
+    for (int64_t i = 0; i < I->n; ++i) {
+        if (box_enter(&I->wbox[i], r, tmin - I->margin, tmax + I->margin) == INFINITY) continue;
+        ray_ev q = xform_ray(I->w2o + 12 * i, r);
+        int b = 0, occ = 0;
+        uint32_t who;
+        if (use_bvh && I->bvh[i]) {
+            occ = any_bvh(I->rest, I->bvh[i], &q, tmin, tmax, c, &b, &who);
+        } else {
+            for (uint32_t t = I->range[2 * i]; t < I->range[2 * i] + I->range[2 * i + 1]; ++t) {
+                tri_test tt;
+                mt_test(I->rest, t, &q, tmin, tmax, c, &tt);
+                if (tt.exact_hit) occ = 1;
+                if (tt.status == ST_PASS) { occ = 1; b = 0; break; }
+                if (tt.status == ST_UNC) b = 1;
+            }
+        }
+        if (occ && !b) { *band = 0; return 1; }   /* a certain occluder */
+        occluded |= occ;
+        unc |= b;
+    }
+    *band = unc;
+    return occluded;
+}
+
+/* Hit queries of a scene: through its instances when it has them, else over its own triangles with the
+ * BVH B (NULL = brute force; for instanced scenes B only selects per-instance BVHs vs brute force). */
+static void closest_q(const or_scene* s, const void* B, const ray_ev* r, double tmin, double tmax, double c,
+                      hit_rec* out)
+{
+    if (s->inst) closest_inst(s->inst, B != NULL, r, tmin, tmax, c, out);
+    else if (B) closest_bvh((const or_bvh*)B, r, tmin, tmax, c, out);
+    else closest_brute(s, r, tmin, tmax, c, out);
+}
+
+static int any_q(const or_scene* s, const void* B, const ray_ev* r, double tmin, double tmax, double c, int* band)
+{
+    uint32_t who;
+    if (s->inst) return any_inst(s->inst, B != NULL, r, tmin, tmax, c, band);
+    return any_bvh(s, (const or_bvh*)B, r, tmin, tmax, c, band, &who);
+}
+
 static ray_ev exact_ray(v3 o, v3 d)
 {
     ray_ev r;
@@ -581,8 +795,7 @@ OR_API void or_closest(const or_scene* s, const or_bvh* B, const float o[3], con
 {
     ray_ev r = exact_ray(from_f(o), from_f(d));
     hit_rec h;
-    if (B) closest_bvh(B, &r, tmin, tmax, c, &h);
-    else closest_brute(s, &r, tmin, tmax, c, &h);
+    closest_q(s, B, &r, tmin, tmax, c, &h);
     *id = h.id; tuv[0] = h.t; tuv[1] = h.u; tuv[2] = h.v;
     err[0] = h.et; err[1] = h.eu; err[2] = h.ev;
     *band = h.band;
@@ -596,8 +809,7 @@ OR_API int or_any(const or_scene* s, const or_bvh* B, const double o[3], const d
     v3 O = mk(o[0], o[1], o[2]), D = mk(d[0], d[1], d[2]);
     ray_ev r;
     r.o = O; r.d = D; r.eo = ev3_rounded(O); r.ed = ev3_rounded(D);
-    uint32_t who;
-    return any_bvh(s, B, &r, tmin, tmax, c, band, &who);
+    return any_q(s, B, &r, tmin, tmax, c, band);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -702,8 +914,7 @@ static int shadow_test(const or_scene* s, const or_bvh* B, const surface* S, v3 
     if (fabs(nd.v) <= c * nd.e) *band = 1;
     if (!*cast) return 0;
     int b2 = 0;
-    uint32_t who;
-    int occ = any_bvh(s, B, &r, 0.0, 1.0, c, &b2, &who);
+    int occ = any_q(s, B, &r, 0.0, 1.0, c, &b2);
     if (b2) *band = 1;
     return occ;
 }
@@ -724,8 +935,7 @@ OR_API void or_render_point(const or_scene* s, const or_bvh* B, const or_camera*
         gen_ray(cam, &cb, samples[q], of, df);
         ray_ev r = exact_ray(from_f(of), from_f(df));
         hit_rec h;
-        if (B) closest_bvh(B, &r, 0.0, INFINITY, c, &h);
-        else closest_brute(s, &r, 0.0, INFINITY, c, &h);
+        closest_q(s, B, &r, 0.0, INFINITY, c, &h);
         hit_id[q] = h.id;
         tuv[3 * q + 0] = h.t; tuv[3 * q + 1] = h.u; tuv[3 * q + 2] = h.v;
         tuv_err[3 * q + 0] = h.et; tuv_err[3 * q + 1] = h.eu; tuv_err[3 * q + 2] = h.ev;
@@ -834,8 +1044,7 @@ OR_API void or_render_rect(const or_scene* s, const or_bvh* B, const or_camera* 
         gen_ray(cam, &cb, pix, of, df);   /* 1 sample per pixel */
         ray_ev r = exact_ray(from_f(of), from_f(df));
         hit_rec h;
-        if (B) closest_bvh(B, &r, 0.0, INFINITY, c, &h);
-        else closest_brute(s, &r, 0.0, INFINITY, c, &h);
+        closest_q(s, B, &r, 0.0, INFINITY, c, &h);
         hit_id[q] = h.id;
         band_primary[q] = (uint8_t)h.band;
         vis_count[q] = 0; band_count[q] = 0; cast_count[q] = 0;

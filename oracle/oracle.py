@@ -34,7 +34,7 @@ def lib():
 
 class OrScene(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("nv", C.c_int64), ("idx", C.c_void_p), ("nt", C.c_int64),
-                ("tri_mat", C.c_void_p), ("mats", C.c_void_p), ("nmat", C.c_int64)]
+                ("tri_mat", C.c_void_p), ("mats", C.c_void_p), ("nmat", C.c_int64), ("inst", C.c_void_p)]
 
 
 class OrCamera(C.Structure):
@@ -58,6 +58,10 @@ def _declare(L):
     L.or_bvh_depth.restype = C.c_int
     L.or_closest.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, P, P, P, P, P]
     L.or_any.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, P]
+    L.or_inst_create.argtypes = [P, C.c_int64, P, P, C.c_int]
+    L.or_inst_create.restype = P
+    L.or_inst_free.argtypes = [P]
+    L.or_w2o_f32.argtypes = [P, C.c_int64, P]
     L.or_any.restype = C.c_int
     L.or_brdf.argtypes = [P, P, P, P, C.c_double, C.c_double, P]
     L.or_brdf_k.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, P]
@@ -128,18 +132,44 @@ class OracleScene:
         self.tri_mat = np.ascontiguousarray(tri_material, dtype=np.uint32)
         self.mats = np.ascontiguousarray(materials, dtype=np.float32)
         self.s = OrScene(_p(self.pos).value, self.pos.shape[0], _p(self.idx).value, self.idx.shape[0],
-                         _p(self.tri_mat).value, _p(self.mats).value, self.mats.shape[0])
+                         _p(self.tri_mat).value, _p(self.mats).value, self.mats.shape[0], None)
         self.bvh = lib().or_bvh_build(C.byref(self.s)) if use_bvh else None
+        self.inst = None
 
     @classmethod
     def from_scene(cls, scene, use_bvh: bool = True):
         return cls(scene.positions, scene.indices, scene.tri_material, scene.materials, use_bvh)
+
+    @classmethod
+    def two_level(cls, world_positions, rest_positions, indices, tri_material, materials, tri_range, o2w,
+                  use_bvh: bool = True):
+        """A scene whose hit queries go through instances: instance i is triangles tri_range[i] =
+        (first, count) of the rest-frame positions, placed by the rigid map [R | t] = o2w[i] (3x4, FP32)
+        and tested in its own frame through the world-to-object map w2o_f32(o2w).  Surfaces and
+        materials come from the world positions (the FP32 transform of the rest positions)."""
+        self = cls(world_positions, indices, tri_material, materials, use_bvh=False)
+        self.rest = cls(rest_positions, indices, tri_material, materials, use_bvh=False)
+        self.tri_range = np.ascontiguousarray(tri_range, np.uint32).reshape(-1, 2)
+        self.w2o = w2o_f32(o2w)
+        self.inst = lib().or_inst_create(C.byref(self.rest.s), self.tri_range.shape[0], _p(self.tri_range),
+                                         _p(self.w2o), int(use_bvh))
+        self.s.inst = self.inst
+        self._inst_bvh = use_bvh
+        return self
+
+    def _query_bvh(self, brute: bool):
+        if self.inst:   # for instanced scenes a non-null pointer selects the per-instance BVHs
+            return None if (brute or not self._inst_bvh) else self.inst
+        return None if brute else self.bvh
 
     def set_positions(self, positions):
         """Replace vertex positions (same topology) and rebuild the oracle BVH."""
         self.__init__(positions, self.idx, self.tri_mat, self.mats, self.bvh is not None)
 
     def __del__(self):
+        if getattr(self, "inst", None):
+            lib().or_inst_free(self.inst)
+            self.inst = None
         if getattr(self, "bvh", None):
             lib().or_bvh_free(self.bvh)
             self.bvh = None
@@ -153,7 +183,7 @@ class OracleScene:
         err = np.zeros(3)
         band = C.c_int()
         nc = C.c_int64()
-        lib().or_closest(C.byref(self.s), None if brute else self.bvh, _p(of), _p(df), tmin, tmax, c,
+        lib().or_closest(C.byref(self.s), self._query_bvh(brute), _p(of), _p(df), tmin, tmax, c,
                          C.byref(hid), _p(tuv), _p(err), C.byref(band), C.byref(nc))
         return int(hid.value), tuv, err, bool(band.value)
 
@@ -169,7 +199,7 @@ class OracleScene:
         od = np.ascontiguousarray(o, np.float64)
         dd = np.ascontiguousarray(d, np.float64)
         band = C.c_int()
-        occ = lib().or_any(C.byref(self.s), None if brute else self.bvh, _p(od), _p(dd), tmin, tmax, c,
+        occ = lib().or_any(C.byref(self.s), self._query_bvh(brute), _p(od), _p(dd), tmin, tmax, c,
                            C.byref(band))
         return bool(occ), bool(band.value)
 
@@ -179,7 +209,7 @@ class OracleScene:
         nn = np.ascontiguousarray(n, np.float64)
         R = rect_array(rect)
         bc = C.c_int()
-        v = lib().or_rect_vis_point(C.byref(self.s), None if brute else self.bvh, _p(pp), _p(nn), _p(R), int(N),
+        v = lib().or_rect_vis_point(C.byref(self.s), self._query_bvh(brute), _p(pp), _p(nn), _p(R), int(N),
                                     int(stream), int(pixel), int(seed), int(frame), c, C.byref(bc))
         return int(v), int(bc.value)
 
@@ -194,7 +224,7 @@ class OracleScene:
                    band_primary=np.zeros(n, np.uint8), mask=np.zeros(n, np.uint32),
                    band_shadow=np.zeros(n, np.uint32), rgb=np.zeros((n, 3)))
         cs = camera_struct(cam)
-        bvh = None if brute else self.bvh
+        bvh = self._query_bvh(brute)
 
         def run(a, b):
             if b <= a:
@@ -219,7 +249,7 @@ class OracleScene:
                    vis_count=np.zeros(n, np.int32), band_count=np.zeros(n, np.int32),
                    cast_count=np.zeros(n, np.int32), rgb_unshadowed=np.zeros((n, 3)))
         cs = camera_struct(cam)
-        bvh = None if brute else self.bvh
+        bvh = self._query_bvh(brute)
 
         def run(a, b):
             if b <= a:
@@ -277,6 +307,14 @@ def resolve_f32(samples: np.ndarray, n_per: int) -> np.ndarray:
     n_pix = s.size // (4 * n_per)
     out = np.zeros((n_pix, 4), np.float32)
     lib().or_resolve_f32(_p(s), n_pix, n_per, _p(out))
+    return out
+
+
+def w2o_f32(o2w) -> np.ndarray:
+    """World-to-object maps [M | m] (n, 12) of rigid maps [R | t] (FP32 mirror: M = R^T, m = -(R^T t))."""
+    x = np.ascontiguousarray(o2w, np.float32).reshape(-1, 12)
+    out = np.zeros_like(x)
+    lib().or_w2o_f32(_p(x), x.shape[0], _p(out))
     return out
 
 
