@@ -102,11 +102,22 @@ int rc_scene_destroy(rc_ctx* ctx, rc_scene* scene);
  * codes, exact FP32 boxes bottom-up, then collapsed level by level to 4-wide (a node
  * repeatedly opens its child of largest box surface that holds more than max_leaf
  * triangles, until it has four children); every subtree of at most max_leaf triangles
- * is one leaf (`bins` and `node_cost` are ignored).  Both give exact child boxes (FP32
- * min/max of what the child holds) and leaves of at most `max_leaf` (1..4, default 4)
- * triangles.  Replaces any previous BVH.  Synchronous with respect to the host (works on
- * the context stream and waits for it). */
-enum { RC_BUILD_HOST_SAH = 0u, RC_BUILD_DEVICE_LBVH = 1u };
+ * is one leaf (`bins` and `node_cost` are ignored).  RC_BUILD_TWO_LEVEL (2): the paper's
+ * two-level structure (Sec. IV-B "Ray-traced shadows": one structure per mesh, instances
+ * with transforms under a top level rebuilt every frame): one bottom-level tree per body
+ * over its rest-frame triangles (the positions given at creation), built on the GPU like
+ * RC_BUILD_DEVICE_LBVH in one pass over all bodies, and a top level with one leaf per body
+ * over the bodies' world boxes (the rest box's corners mapped by the body's current rigid
+ * map [R | t] in FP32, padded by 2^-18 of the largest coordinate magnitude, at least 1).
+ * Rays meet a body in its own frame: o' = M o + m, d' = M d with M = R^T and
+ * m = -(R^T t), every component evaluated in FP32 as ((M0 a0 + M1 a1) + M2 a2) [+ m_k]
+ * (m_k likewise from R and t), then the same FP32 box and triangle tests.  Every triangle
+ * must belong to a body (all three vertices in one body's vertex range) and the bodies
+ * must own consecutive triangle ranges in body order (else RC_ERR_INVALID_VALUE; no bodies:
+ * RC_ERR_INVALID_ARG).  All methods give exact child boxes (FP32 min/max of what the child
+ * holds) and leaves of at most `max_leaf` (1..4, default 4) triangles.  Replaces any previous
+ * BVH.  Synchronous with respect to the host (works on the context stream and waits for it). */
+enum { RC_BUILD_HOST_SAH = 0u, RC_BUILD_DEVICE_LBVH = 1u, RC_BUILD_TWO_LEVEL = 2u };
 typedef struct rc_build_opts {
     uint32_t bins;
     uint32_t max_leaf;
@@ -117,8 +128,9 @@ int rc_bvh_build(rc_ctx* ctx, rc_scene* scene, const rc_build_opts* opts);
 
 /* Rigid motion of bodies: for i < n, body d_body_ids[i] gets vertices
  * x' = R x_rest + t with d_xforms[12 i ..] = row-major [R | t] (3x4 float), where
- * x_rest are the positions given at creation.  Bodies not listed keep their current
- * positions.  Does not touch the BVH: call rc_bvh_refit before rendering. */
+ * x_rest are the positions given at creation, and [R | t] becomes the body's current map
+ * (read by two-level structures).  Bodies not listed keep their current positions and map.
+ * Does not touch the BVH: call rc_bvh_refit (or rc_tlas_rebuild) before rendering. */
 int rc_scene_set_transforms(rc_ctx* ctx, rc_scene* scene, const float* d_xforms,
                             const uint32_t* d_body_ids, uint32_t n);
 
@@ -127,8 +139,24 @@ int rc_scene_get_positions(rc_ctx* ctx, const rc_scene* scene, float* out);
 
 /* Recompute every node box bottom-up from the current vertex positions, keeping the
  * tree topology (exact FP32 min/max, so boxes equal a fresh computation bit for bit).
- * RC_ERR_NOT_BUILT without a prior rc_bvh_build. */
+ * For a two-level structure: rebuild the top level from the bodies' current maps
+ * (rc_tlas_rebuild on the context stream).  RC_ERR_NOT_BUILT without a prior rc_bvh_build. */
 int rc_bvh_refit(rc_ctx* ctx, rc_scene* scene);
+
+/* Rebuild the top level of a two-level structure from the bodies' current maps on `stream`
+ * (a hipStream_t; NULL = the context stream): instance records, then the top-level tree
+ * (LBVH over the bodies' world boxes, collapsed in one workgroup).  Enqueues only: no host
+ * synchronisation and no allocation, so it can run on a second stream beside other work.
+ * The caller orders it after the rc_scene_set_transforms it depends on and before the
+ * renders that read it (events), and does not render the scene while it runs.  A top level
+ * deeper than 24 levels leaves an empty tree and sets the context's error flag.
+ * RC_ERR_UNSUPPORTED for scenes without a two-level structure. */
+int rc_tlas_rebuild(rc_ctx* ctx, rc_scene* scene, void* stream);
+
+/* Copy the instance records of a two-level structure to host memory: 16 words per body,
+ * the world-to-object map [M | m] (12 floats, row-major) then the body's root node index
+ * (uint32) and 3 zero words.  Synchronous. */
+int rc_tlas_export(rc_ctx* ctx, const rc_scene* scene, float* inst_out);
 
 typedef struct rc_bvh_stats {
     uint64_t n_nodes;      /* 4-wide internal nodes */
@@ -138,7 +166,13 @@ typedef struct rc_bvh_stats {
     uint32_t max_stack;    /* traversal stack entries that suffice for any ray */
     double sah_cost;       /* SAH cost (node 1, triangle 1) relative to the root box, of the current
                               (possibly refit) boxes */
-    double build_ms;       /* host build time of the last rc_bvh_build */
+    double build_ms;       /* time of the last rc_bvh_build (first kernel or host step to finished tree) */
+    uint32_t n_instances;  /* two-level structures: bodies under the top level (0 for a flat BVH) */
+    uint32_t tlas_levels;  /* two-level structures: levels of the current top level.  For these, n_nodes
+                              counts bottom- and top-level nodes, depth = deepest bottom level + top
+                              levels, and sah_cost is 0 (not computed) */
+    uint32_t tlas_root;    /* two-level structures: node index of the top level's root (= bottom-level nodes) */
+    uint32_t reserved;
 } rc_bvh_stats;
 int rc_bvh_get_stats(rc_ctx* ctx, const rc_scene* scene, rc_bvh_stats* out);
 
@@ -146,7 +180,10 @@ int rc_bvh_get_stats(rc_ctx* ctx, const rc_scene* scene, rc_bvh_stats* out);
  * (lo_x[4] hi_x[4] lo_y[4] hi_y[4] lo_z[4] hi_z[4] child[4] meta[4]) and the
  * triangle order (n_tris uint32, original triangle id per leaf slot).  Either pointer
  * may be NULL.  Child word: bit 31 set = leaf with (bits 28..30) = count - 1 and
- * (bits 0..27) = first slot; 0xFFFFFFFF = empty; otherwise an internal node index. */
+ * (bits 0..27) = first slot; 0xFFFFFFFF = empty; otherwise an internal node index.
+ * Two-level structures: the bottom-level nodes (body b's root is node b) followed by the
+ * current top level (root at node n_nodes - top-level nodes); top-level leaf words hold
+ * the body index in bits 0..27 (count 1). */
 int rc_bvh_export(rc_ctx* ctx, const rc_scene* scene, uint32_t* nodes_out, uint32_t* tri_order_out);
 
 /* ------------------------------------------------------------- render ---- */
@@ -293,7 +330,8 @@ enum {
 /* Render all views in one persistent kernel launch fed by a device work queue (point lights and
  * 2x2 or 1 sample per pixel).  Every view's outputs are bit-identical to rc_render of that view
  * alone with RC_FLAG_PER_LANE (the same per-lane traversal), for any tuning.  flags: RC_FLAG_TIMING (rc_get_stage_times ms[3]), RC_FLAG_GRAPH.  All
- * scenes must be built.  Errors: RC_ERR_INVALID_ARG, RC_ERR_NOT_BUILT, RC_ERR_UNSUPPORTED, RC_ERR_HIP. */
+ * scenes must be built (flat BVHs: two-level structures give RC_ERR_UNSUPPORTED).  Errors:
+ * RC_ERR_INVALID_ARG, RC_ERR_NOT_BUILT, RC_ERR_UNSUPPORTED, RC_ERR_HIP. */
 int rc_render_batch(rc_ctx* ctx, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,
                     const rc_point_light* lights, uint32_t n_lights_total, const rc_tune* tune, uint32_t flags);
 

@@ -43,7 +43,8 @@ class RcBuildOpts(C.Structure):
 class RcBvhStats(C.Structure):
     _fields_ = [("n_nodes", C.c_uint64), ("n_leaves", C.c_uint64), ("n_tris", C.c_uint64),
                 ("depth", C.c_uint32), ("max_stack", C.c_uint32), ("sah_cost", C.c_double),
-                ("build_ms", C.c_double)]
+                ("build_ms", C.c_double), ("n_instances", C.c_uint32), ("tlas_levels", C.c_uint32),
+                ("tlas_root", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class RcCamera(C.Structure):
@@ -102,6 +103,8 @@ SIGNATURES = {
     "rc_bvh_build": (C.c_int, [P, P, C.POINTER(RcBuildOpts)]),
     "rc_scene_set_transforms": (C.c_int, [P, P, P, P, C.c_uint32]),
     "rc_bvh_refit": (C.c_int, [P, P]),
+    "rc_tlas_rebuild": (C.c_int, [P, P, P]),
+    "rc_tlas_export": (C.c_int, [P, P, P]),
     "rc_bvh_get_stats": (C.c_int, [P, P, C.POINTER(RcBvhStats)]),
     "rc_bvh_export": (C.c_int, [P, P, P, P]),
     "rc_render": (C.c_int, [P, P, C.POINTER(RcCamera), C.POINTER(RcPointLight), C.c_uint32,
@@ -400,12 +403,29 @@ class Scene:
         except Exception:
             pass
 
-    def build(self, bins: int = 32, max_leaf: int = 4, node_cost: float = 4.0, device: bool = False):
-        """Host binned-SAH build, or with device=True the GPU LBVH build (RC_BUILD_DEVICE_LBVH)."""
+    def build(self, bins: int = 32, max_leaf: int = 4, node_cost: float = 4.0, device: bool = False,
+              two_level: bool = False):
+        """Host binned-SAH build; device=True: the GPU LBVH build (RC_BUILD_DEVICE_LBVH); two_level=True: one
+        GPU-built tree per body under a top level over the bodies (RC_BUILD_TWO_LEVEL)."""
         self.ctx._sync_stream()
-        opts = RcBuildOpts(bins, max_leaf, node_cost, 1 if device else 0)
+        opts = RcBuildOpts(bins, max_leaf, node_cost, 2 if two_level else (1 if device else 0))
         check(lib().rc_bvh_build(self.ctx.h, self.h, C.byref(opts)), "rc_bvh_build")
         return self
+
+    def tlas_rebuild(self, stream=None):
+        """Rebuild the top level of a two-level structure from the bodies' current maps, enqueued on `stream`
+        (a torch.cuda.Stream; None = the context stream) without host synchronisation."""
+        h = None if stream is None else C.c_void_p(stream.cuda_stream)
+        if stream is None:
+            self.ctx._sync_stream()
+        check(lib().rc_tlas_rebuild(self.ctx.h, self.h, h), "rc_tlas_rebuild")
+
+    def tlas_export(self) -> np.ndarray:
+        """Instance records (n_bodies, 16) float32: world-to-object map [M | m] then the root index bits."""
+        n = int(self.stats()["n_instances"])
+        out = np.zeros((n, 16), np.float32)
+        check(lib().rc_tlas_export(self.ctx.h, self.h, _ptr(out)), "rc_tlas_export")
+        return out
 
     def refit(self):
         self.ctx._sync_stream()

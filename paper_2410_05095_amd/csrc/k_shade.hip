@@ -80,6 +80,14 @@ __global__ __launch_bounds__(256) void k_transform(const float* rest, float* pos
     }
 }
 
+// The current rigid map of each moved body (read by the top level of two-level structures).
+__global__ __launch_bounds__(256) void k_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, float* o2w)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 12 * n) return;
+    o2w[12 * (size_t)body_ids[q / 12] + q % 12] = xf[q];
+}
+
 // One thread per node of one BVH level: child boxes from the triangles of leaf children and
 // from the (already refit) boxes of internal children.  Exact FP32 min/max.
 __global__ __launch_bounds__(256) void k_refit(Node4* nodes, const float* pos, const uint32_t* idx,
@@ -202,6 +210,12 @@ void rc_launch_transform(const float* rest, float* pos, const uint32_t* body_vra
     if (n_bodies == 0 || max_count == 0) return;
     unsigned gx = std::min(blocks(max_count, 256), 64u);
     hipLaunchKernelGGL(k_transform, dim3(gx, n_bodies), dim3(256), 0, st, rest, pos, body_vrange, xf, body_ids);
+}
+
+void rc_launch_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, float* o2w, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_record_o2w, dim3(blocks(12 * n, 256)), dim3(256), 0, st, xf, body_ids, n, o2w);
 }
 
 void rc_launch_refit_level(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order,

@@ -49,7 +49,7 @@ inline uint32_t claim_size(uint64_t n_work, int grid, uint32_t per_wave, uint32_
     return (uint32_t)std::min<uint64_t>(hi, std::max<uint64_t>(lo, c));
 }
 
-template <int MODE>
+template <int MODE, bool TWO>
 __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
 {
     constexpr bool ANY = MODE != MODE_PRIMARY;
@@ -69,6 +69,9 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
     float os[3] = {0, 0, 0}, nf[3] = {0, 0, 0};
     TravRay ray;
     TravState ts;
+    TravWorld tw;
+    TravWorld* twp = TWO ? &tw : nullptr;
+    const uint32_t root = TWO ? sc.tlas_root : 0u;
     bool queue_empty = false;
     const XcdQueue<ITEM_CHUNK> queue(P.w.counters, P.slot, P.n_items);
     uint32_t pool_next = 0, pool_end = 0;   // wave-uniform range of claimed, not yet started positions
@@ -79,7 +82,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
         while (j < n_rays) {
             if (rc_shadow_ray(P.L.point[MODE == MODE_POINT ? j : 0], P.L.rect, P.nL, MODE == MODE_RECT, px, j,
                               P.L.area_stream, P.cam.seed, P.cam.frame, os, nf, ray)) {
-                trav_begin(ray, ts);
+                trav_begin(ray, ts, root, twp);
                 ++rays_cast;
                 return true;
             }
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
         if (!rc_item_to_sample(P.cam, item, px, pk)) return false;
         if (MODE == MODE_PRIMARY) {
             rc_camera_ray(P.cam, px, pk, ray.o, ray.d);
-            trav_begin(ray, ts);
+            trav_begin(ray, ts, root, twp);
             ++rays_cast;
             return true;
         } else {
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
         // ---- traversal: node phase then leaf phase for all busy lanes, until enough lanes are idle
         for (;;) {
             uint32_t occluded = 0u;
-            trav_advance(sc, ray, ts, st, state == 1, ANY, occluded, node_visits, tri_tests);
+            trav_advance<TWO>(sc, ray, ts, st, state == 1, ANY, occluded, node_visits, tri_tests, twp);
             if (state == 1 && ts.cur == RC_STACK_EMPTY) {
                 if (!end_ray(occluded != 0u)) state = 0;
             }
@@ -183,6 +186,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
 // together: its lanes start from the same point towards nearby targets and mostly fetch the same
 // nodes.  A wave claims 64 ray slots at a time, advances them to completion, and adds the visible
 // count of each pixel segment (ballot + popcount) to a per-pixel counter.
+template <bool TWO>
 __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* counts)
 {
     const int tid = threadIdx.x;
@@ -197,6 +201,8 @@ __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* cou
     uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
     TravRay ray;
     TravState ts;
+    TravWorld tw;
+    TravWorld* twp = TWO ? &tw : nullptr;
     const XcdQueue<RECT_CHUNK> queue(P.w.counters, P.slot, n_blocks);
     uint32_t pos = 0, pos_end = 0;   // wave-uniform range of claimed positions
     for (;;) {
@@ -223,14 +229,14 @@ __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* cou
                 busy = rc_shadow_ray(P.L.point[0], P.L.rect, P.nL, true, px, k, P.L.area_stream, P.cam.seed,
                                      P.cam.frame, os, nf, ray);
                 if (busy) {
-                    trav_begin(ray, ts);
+                    trav_begin(ray, ts, TWO ? sc.tlas_root : 0u, twp);
                     ++rays_cast;
                 }
             }
         }
         uint32_t occluded = 0u;
         while (__ballot(busy && ts.cur != RC_STACK_EMPTY) != 0)
-            trav_advance(sc, ray, ts, st, busy, true, occluded, node_visits, tri_tests);
+            trav_advance<TWO>(sc, ray, ts, st, busy, true, occluded, node_visits, tri_tests, twp);
         const uint64_t vis = __ballot(busy && occluded == 0u);
         if (in_image && (lane == 0 || k == 0)) {
             uint32_t end = (uint32_t)min<uint64_t>(64, lane + (N - k));
@@ -317,6 +323,10 @@ __device__ inline void wave_node_keys(const rc_v4f& lx, const rc_v4f& hx, const 
     }
 }
 
+// Two-level structures: at a top-level leaf every lane maps its ray into the instance (rc_map_ray), the
+// wave pushes an end marker and descends into the instance's tree; popping the marker restores the world
+// rays (and the wave's octant).
+template <bool TWO>
 __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
 {
     const uint32_t lane = __lane_id();
@@ -360,15 +370,47 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
             }
         }
         const uint64_t busy_mask = __ballot(busy);
-        const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
-                                (ray.inv[2] < 0.0f ? 4u : 0u);
         uint32_t oct = 0;
-        if (busy_mask != 0) oct = (uint32_t)__builtin_amdgcn_readlane((int)my_oct, __builtin_ctzll(busy_mask));
-        const bool uniform_oct = __ballot(busy && my_oct != oct) == 0;
+        bool uniform_oct = false;
+        auto set_octant = [&]() {
+            const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
+                                    (ray.inv[2] < 0.0f ? 4u : 0u);
+            oct = 0;
+            if (busy_mask != 0) oct = (uint32_t)__builtin_amdgcn_readlane((int)my_oct, __builtin_ctzll(busy_mask));
+            uniform_oct = __ballot(busy && my_oct != oct) == 0;
+        };
+        set_octant();
+        float wo[3] = {ray.o[0], ray.o[1], ray.o[2]}, wd[3] = {ray.d[0], ray.d[1], ray.d[2]};   // world ray
+        uint32_t in_blas = 0u;
         bool occ = false;
-        uint32_t cur = busy_mask != 0 ? 0u : RC_STACK_EMPTY;
+        uint32_t cur = busy_mask != 0 ? (TWO ? sc.tlas_root : 0u) : RC_STACK_EMPTY;
         int sp = 0;
         uint32_t stk0 = 0, stk1 = 0;   // entry e of the wave's stack lives in lane e % 64 of stk{e / 64}
+        // next entry of the wave's stack (an instance's end marker returns the rays to world space)
+        auto pop_next = [&]() -> uint32_t {
+            for (;;) {
+                if (sp == 0) return RC_STACK_EMPTY;
+                --sp;
+                const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63);
+                if (!TWO || c != RC_INST_RETURN) return c;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) { ray.o[a] = wo[a]; ray.d[a] = wd[a]; }
+                rc_ray_inv(ray);
+                set_octant();
+                in_blas = 0u;
+            }
+        };
+        auto push_entry = [&](uint32_t w) {
+            if (sp < 64) {
+                stk0 = (int)lane == sp ? w : stk0;
+                ++sp;
+            } else if (sp < 128) {
+                stk1 = (int)lane == sp - 64 ? w : stk1;
+                ++sp;
+            } else if (lane == 0) {
+                *P.w.error_flag = 1u;   // beyond the bound the host checked: entry dropped, reported
+            }
+        };
         while (cur != RC_STACK_EMPTY) {
             const bool live = busy && !occ;
             if (!rc_is_leaf(cur)) {
@@ -391,27 +433,20 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
                 RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
 #undef RC_CS
 #pragma unroll
-                for (int c = 3; c >= 1; --c) {
-                    if (key[c] < KEY_MISS) {
-                        if (sp < 64) {
-                            stk0 = (int)lane == sp ? cw[c] : stk0;
-                            ++sp;
-                        } else if (sp < 128) {
-                            stk1 = (int)lane == sp - 64 ? cw[c] : stk1;
-                            ++sp;
-                        } else if (lane == 0) {
-                            *P.w.error_flag = 1u;   // beyond the bound the host checked: entry dropped, reported
-                        }
-                    }
-                }
-                if (key[0] < KEY_MISS) {
-                    cur = cw[0];
-                } else if (sp == 0) {
-                    cur = RC_STACK_EMPTY;
-                } else {
-                    --sp;
-                    cur = (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63);
-                }
+                for (int c = 3; c >= 1; --c)
+                    if (key[c] < KEY_MISS) push_entry(cw[c]);
+                cur = key[0] < KEY_MISS ? cw[0] : pop_next();
+            } else if (TWO && in_blas == 0u) {
+                // top-level leaf: map every ray into the instance and descend into its tree
+                rc_const_v4f* ip = (rc_const_v4f*)(const void*)(sc.inst + rc_leaf_first(cur));
+                const rc_v4f q0 = ip[0], q1 = ip[1], q2 = ip[2], q3 = ip[3];
+                const float W[12] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3],
+                                     q2[0], q2[1], q2[2], q2[3]};
+                rc_map_ray(W, wo, wd, ray);
+                set_octant();
+                push_entry(RC_INST_RETURN);
+                in_blas = 1u;
+                cur = __float_as_uint(q3[0]);
             } else {
                 const uint32_t first = rc_leaf_first(cur), cnt = rc_leaf_count(cur);
                 for (uint32_t i = 0; i < cnt; ++i) {
@@ -424,12 +459,7 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
                         occ = hit && t < 1.0f;
                     }
                 }
-                if (__ballot(busy && !occ) == 0 || sp == 0) {
-                    cur = RC_STACK_EMPTY;
-                } else {
-                    --sp;
-                    cur = (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63);
-                }
+                cur = __ballot(busy && !occ) == 0 ? RC_STACK_EMPTY : pop_next();
             }
             cur = __builtin_amdgcn_readfirstlane(cur);
         }
@@ -624,7 +654,7 @@ int occupancy_grid(int device)
 {
     int n_cu = 0, blocks = 0;
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_trace<MODE>), BLOCK,
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_trace<MODE, false>), BLOCK,
                                                  lds_bytes<MODE>());
     if (blocks < 1) blocks = 1;
     return n_cu * blocks;
@@ -639,10 +669,10 @@ int rc_trace_grid(int device)
     int c = occupancy_grid<MODE_RECT>(device);
     int d = 0, n_cu = 0;
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, reinterpret_cast<const void*>(&k_rect_packets), BLOCK,
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, reinterpret_cast<const void*>(&k_rect_packets<false>), BLOCK,
                                                  TravStack<SL, BLOCK, false>::lds_bytes());
     int e = 0, f = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave), BLOCK, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave<false>), BLOCK, 0);
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, reinterpret_cast<const void*>(&k_primary_wave), BLOCK, 0);
     e = std::max(e, f);
     return std::max(std::max(std::max(a, d * n_cu), std::max(b, c)), e * n_cu);
@@ -660,12 +690,18 @@ void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, co
     P.slot = 0;
     // the wave-uniform traversal pays off with 2x2 supersampling (a wave holds 4 samples of each of 16
     // neighbouring pixels); with one sample per pixel, 8x8-pixel tiles diverge more and per-lane is faster
-    if (sc.max_stack <= 128 && !per_lane && cam.ssaa > 1) {
+    // (two-level structures always use the per-lane kernel for camera rays)
+    const bool two = sc.inst != nullptr;
+    if (sc.max_stack <= 128 && !per_lane && cam.ssaa > 1 && !two) {
         P.claim = claim_size((P.n_items + 63) / 64, grid, 64, 1, 4);
         hipLaunchKernelGGL(k_primary_wave, dim3(grid), dim3(BLOCK), 0, st, P);
     } else {
         P.claim = claim_size(P.n_items, grid, 16, 32, 128);
-        hipLaunchKernelGGL(k_trace<MODE_PRIMARY>, dim3(grid), dim3(BLOCK), lds_bytes<MODE_PRIMARY>(), st, P);
+        if (two)
+            hipLaunchKernelGGL((k_trace<MODE_PRIMARY, true>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_PRIMARY>(), st, P);
+        else
+            hipLaunchKernelGGL((k_trace<MODE_PRIMARY, false>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_PRIMARY>(), st,
+                               P);
     }
 }
 
@@ -682,10 +718,14 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     P.vis = visibility;
     P.w = w;
     P.n_items = rc_n_items(cam.width, cam.height, cam.ssaa);
+    const bool two = sc.inst != nullptr;
     if (L.n_point > 0) {
         P.slot = 1;
         P.claim = claim_size(P.n_items, grid, 16, 32, 128);
-        hipLaunchKernelGGL(k_trace<MODE_POINT>, dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
+        if (two)
+            hipLaunchKernelGGL((k_trace<MODE_POINT, true>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
+        else
+            hipLaunchKernelGGL((k_trace<MODE_POINT, false>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
     }
     if (L.has_rect) {
         // unit normal of the emitting side, from FP64 and rounded once
@@ -702,10 +742,16 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         if (sc.max_stack <= 128 && !per_lane_rect && L.area_samples >= 64) {
             hipLaunchKernelGGL(k_shadow_setup, dim3((n_pix + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_pix,
                                setup);
-            hipLaunchKernelGGL(k_rect_wave, dim3(grid), dim3(BLOCK), 0, st, P, counts, (const float4*)setup);
+            if (two)
+                hipLaunchKernelGGL(k_rect_wave<true>, dim3(grid), dim3(BLOCK), 0, st, P, counts, (const float4*)setup);
+            else
+                hipLaunchKernelGGL(k_rect_wave<false>, dim3(grid), dim3(BLOCK), 0, st, P, counts, (const float4*)setup);
         } else {
             const size_t lds = TravStack<SL, BLOCK, false>::lds_bytes();
-            hipLaunchKernelGGL(k_rect_packets, dim3(grid), dim3(BLOCK), lds, st, P, counts);
+            if (two)
+                hipLaunchKernelGGL(k_rect_packets<true>, dim3(grid), dim3(BLOCK), lds, st, P, counts);
+            else
+                hipLaunchKernelGGL(k_rect_packets<false>, dim3(grid), dim3(BLOCK), lds, st, P, counts);
         }
         hipLaunchKernelGGL(k_rect_finish, dim3((n_pix + 255) / 256), dim3(256), 0, st, counts, n_pix,
                            (uint32_t)L.area_samples, visibility);

@@ -47,6 +47,10 @@ void free_bvh(rc_scene* s)
     dev_free(s->d_nodes);
     dev_free(s->d_order);
     dev_free(s->d_tris);
+    dev_free(s->d_inst);
+    rc_tlas_free(s->tlas);
+    s->two_level = false;
+    s->blas_nodes = s->blas_depth = 0;
     s->built = false;
     s->hb = HostBvh();
 }
@@ -103,6 +107,8 @@ DevScene dev_scene(const rc_scene* s)
     d.n_nodes = (uint32_t)s->hb.nodes.size();
     d.max_stack = s->hb.max_stack;
     d.scale = s->scale;
+    d.inst = s->two_level ? s->d_inst : nullptr;
+    d.tlas_root = s->blas_nodes;
     return d;
 }
 
@@ -257,6 +263,12 @@ int rc_scene_create(rc_ctx* c, const rc_scene_desc* d, rc_scene** out)
     if (st == RC_OK) st = dev_alloc(&s->d_mats, s->mats.size());
     if (st == RC_OK && s->nb) st = dev_alloc(&s->d_rest, s->pos.size());
     if (st == RC_OK && s->nb) st = dev_alloc(&s->d_body_vr, s->body_vr.size());
+    if (st == RC_OK && s->nb) st = dev_alloc(&s->d_o2w, 12 * (size_t)s->nb);
+    std::vector<float> ident;
+    if (s->nb) {
+        ident.assign(12 * (size_t)s->nb, 0.0f);
+        for (uint32_t b = 0; b < s->nb; ++b) ident[12 * (size_t)b] = ident[12 * (size_t)b + 5] = ident[12 * (size_t)b + 10] = 1.0f;
+    }
     auto up = [&](void* dst, const void* src, size_t bytes) {
         if (st == RC_OK && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess) st = RC_ERR_HIP;
     };
@@ -267,6 +279,7 @@ int rc_scene_create(rc_ctx* c, const rc_scene_desc* d, rc_scene** out)
     if (s->nb) {
         up(s->d_rest, s->pos.data(), s->pos.size() * 4);
         up(s->d_body_vr, s->body_vr.data(), s->body_vr.size() * 4);
+        up(s->d_o2w, ident.data(), ident.size() * 4);
     }
     if (st == RC_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = RC_ERR_HIP;
     if (st != RC_OK) { rc_scene_destroy(c, s); return st; }
@@ -286,6 +299,7 @@ int rc_scene_destroy(rc_ctx* c, rc_scene* s)
     dev_free(s->d_tri_mat);
     dev_free(s->d_mats);
     dev_free(s->d_body_vr);
+    dev_free(s->d_o2w);
     delete s;
     return RC_OK;
 }
@@ -303,8 +317,8 @@ static int build_device(rc_ctx* c, rc_scene* s, uint32_t max_leaf)
     if (st != RC_OK) { free_bvh(s); return st; }
     Node4* d_nodes = nullptr;
     uint32_t n_nodes = 0;
-    hipError_t e = rc_build_bvh_device(s->d_pos, s->d_idx, s->nt, max_leaf, &d_nodes, &n_nodes, s->d_order,
-                                       hb.level_start, c->stream);
+    hipError_t e = rc_build_bvh_device(s->d_pos, s->d_idx, s->nt, max_leaf, nullptr, {}, {}, &d_nodes, &n_nodes,
+                                       s->d_order, hb.level_start, c->stream);
     if (e != hipSuccess) { free_bvh(s); return hip_status(e); }
     s->d_nodes = d_nodes;
     rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, c->stream);
@@ -326,6 +340,103 @@ static int build_device(rc_ctx* c, rc_scene* s, uint32_t max_leaf)
     return ensure_overflow(c, s->hb.max_stack);
 }
 
+// Two-level build (k_build.hip): the bottom-level trees of all bodies in one pass over their rest positions,
+// then the top level over the bodies' current maps.  Every triangle must belong to one body (all three
+// vertices in its vertex range), and the bodies must own consecutive triangle ranges in body order.
+static int build_two_level(rc_ctx* c, rc_scene* s, uint32_t max_leaf)
+{
+    if (s->nb == 0) return RC_ERR_INVALID_ARG;
+    const uint32_t NONE = 0xFFFFFFFFu;
+    std::vector<uint32_t> vb(s->nv, NONE);
+    for (uint32_t b = 0; b < s->nb; ++b)
+        for (uint32_t v = s->body_vr[2 * (size_t)b]; v < s->body_vr[2 * (size_t)b] + s->body_vr[2 * (size_t)b + 1]; ++v) {
+            if (vb[v] != NONE) return RC_ERR_INVALID_VALUE;   // overlapping bodies
+            vb[v] = b;
+        }
+    std::vector<uint32_t> seg(s->nt), first(s->nb, 0), count(s->nb, 0);
+    for (uint32_t t = 0; t < s->nt; ++t) {
+        const uint32_t b = vb[s->idx[3 * (size_t)t]];
+        if (b == NONE || vb[s->idx[3 * (size_t)t + 1]] != b || vb[s->idx[3 * (size_t)t + 2]] != b) return RC_ERR_INVALID_VALUE;
+        if (t > 0 && b < seg[t - 1]) return RC_ERR_INVALID_VALUE;   // triangle ranges out of body order
+        seg[t] = b;
+        ++count[b];
+    }
+    for (uint32_t b = 0, f = 0; b < s->nb; ++b) {
+        if (count[b] == 0) return RC_ERR_INVALID_VALUE;
+        first[b] = f;
+        f += count[b];
+    }
+    free_bvh(s);
+    RC_HIP(hipStreamSynchronize(c->stream));
+    auto t0 = std::chrono::steady_clock::now();
+    uint32_t* d_seg = nullptr;
+    int st = dev_alloc(&d_seg, s->nt);
+    if (st == RC_OK) st = dev_alloc(&s->d_order, s->nt);
+    if (st == RC_OK) st = dev_alloc(&s->d_tris, 3 * (size_t)s->nt);
+    if (st == RC_OK) st = dev_alloc(&s->d_inst, s->nb);
+    if (st == RC_OK && hipMemcpyAsync(d_seg, seg.data(), seg.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        st = RC_ERR_HIP;
+    HostBvh hb;
+    Node4* d_blas = nullptr;
+    uint32_t n_blas = 0;
+    if (st == RC_OK) {
+        hipError_t e = rc_build_bvh_device(s->d_rest, s->d_idx, s->nt, max_leaf, d_seg, first, count, &d_blas, &n_blas,
+                                           s->d_order, hb.level_start, c->stream);
+        if (e != hipSuccess) st = hip_status(e);
+    }
+    dev_free(d_seg);
+    if (st == RC_OK && rc_tlas_alloc(s->tlas, s->nb) != hipSuccess) st = RC_ERR_OUT_OF_MEMORY;
+    if (st == RC_OK) st = dev_alloc(&s->d_nodes, (size_t)n_blas + s->tlas.cap);
+    if (st == RC_OK && hipMemcpyAsync(s->d_nodes, d_blas, (size_t)n_blas * sizeof(Node4), hipMemcpyDeviceToDevice,
+                                      c->stream) != hipSuccess)
+        st = RC_ERR_HIP;
+    if (st == RC_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = RC_ERR_HIP;
+    dev_free(d_blas);
+    if (st != RC_OK) { free_bvh(s); return st; }
+    s->blas_nodes = n_blas;
+    s->blas_depth = (uint32_t)hb.level_start.size() - 1;
+    rc_launch_pack(s->d_rest, s->d_idx, s->d_order, s->nt, s->d_tris, c->stream);
+    if (hipGetLastError() != hipSuccess ||
+        rc_tlas_build(s->tlas, s->d_o2w, s->d_nodes, n_blas, s->d_inst, RC_TLAS_MAX_LEVELS, c->d_counters + 8,
+                      c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        free_bvh(s);
+        return RC_ERR_HIP;
+    }
+    s->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    uint32_t info[3] = {0, 0, 0};
+    if (hipMemcpy(info, s->tlas.info, sizeof(info), hipMemcpyDeviceToHost) != hipSuccess) { free_bvh(s); return RC_ERR_HIP; }
+    if (info[2]) { free_bvh(s); return RC_ERR_QUEUE_OVERFLOW; }
+    hb.nodes.resize((size_t)n_blas + info[0]);
+    if (hipMemcpy(hb.nodes.data(), s->d_nodes, hb.nodes.size() * sizeof(Node4), hipMemcpyDeviceToHost) != hipSuccess) {
+        free_bvh(s);
+        return RC_ERR_HIP;
+    }
+    for (const Node4& nd : hb.nodes)
+        for (int k = 0; k < 4; ++k) hb.n_leaves += rc_is_leaf(nd.child[k]) ? 1u : 0u;
+    hb.depth = s->blas_depth + info[1];
+    // a path crosses at most the top level's bound of levels and one bottom-level tree, plus the end marker
+    hb.max_stack = 3 * (s->blas_depth + RC_TLAS_MAX_LEVELS) + 2;
+    hb.sah_cost = 0.0;
+    s->hb = std::move(hb);
+    s->two_level = true;
+    s->built = true;
+    s->sah_stale = false;
+    return ensure_overflow(c, s->hb.max_stack);
+}
+
+int rc_tlas_rebuild(rc_ctx* c, rc_scene* s, void* stream)
+{
+    if (!c || !s) return RC_ERR_INVALID_ARG;
+    if (!s->built) return RC_ERR_NOT_BUILT;
+    if (!s->two_level) return RC_ERR_UNSUPPORTED;
+    RC_HIP(hipSetDevice(c->device));
+    hipStream_t st = stream ? reinterpret_cast<hipStream_t>(stream) : c->stream;
+    RC_HIP(rc_tlas_build(s->tlas, s->d_o2w, s->d_nodes, s->blas_nodes, s->d_inst, RC_TLAS_MAX_LEVELS,
+                         c->d_counters + 8, st));
+    return RC_OK;
+}
+
 int rc_bvh_build(rc_ctx* c, rc_scene* s, const rc_build_opts* o)
 {
     if (!c || !s) return RC_ERR_INVALID_ARG;
@@ -334,10 +445,11 @@ int rc_bvh_build(rc_ctx* c, rc_scene* s, const rc_build_opts* o)
     float node_cost = o && o->node_cost != 0.0f ? o->node_cost : 4.0f;
     const uint32_t method = o ? o->method : RC_BUILD_HOST_SAH;
     if (bins < 2 || bins > 256 || max_leaf < 1 || max_leaf > 4 || !(node_cost > 0.0f && node_cost <= 64.0f) ||
-        method > RC_BUILD_DEVICE_LBVH)
+        method > RC_BUILD_TWO_LEVEL)
         return RC_ERR_INVALID_ARG;
     RC_HIP(hipSetDevice(c->device));
     if (method == RC_BUILD_DEVICE_LBVH) return build_device(c, s, max_leaf);
+    if (method == RC_BUILD_TWO_LEVEL) return build_two_level(c, s, max_leaf);
     if (s->host_pos_stale) {
         RC_HIP(hipMemcpyAsync(s->pos.data(), s->d_pos, s->pos.size() * 4, hipMemcpyDeviceToHost, c->stream));
         RC_HIP(hipStreamSynchronize(c->stream));
@@ -371,6 +483,7 @@ int rc_scene_set_transforms(rc_ctx* c, rc_scene* s, const float* d_xforms, const
     if (!d_xforms || !d_body_ids || n > s->nb || s->nb == 0) return RC_ERR_INVALID_ARG;
     RC_HIP(hipSetDevice(c->device));
     rc_launch_transform(s->d_rest, s->d_pos, s->d_body_vr, d_xforms, d_body_ids, n, s->max_body_verts, c->stream);
+    rc_launch_record_o2w(d_xforms, d_body_ids, n, s->d_o2w, c->stream);
     RC_HIP(hipGetLastError());
     s->host_pos_stale = true;
     return RC_OK;
@@ -381,6 +494,7 @@ int rc_bvh_refit(rc_ctx* c, rc_scene* s)
     if (!c || !s) return RC_ERR_INVALID_ARG;
     if (!s->built) return RC_ERR_NOT_BUILT;
     RC_HIP(hipSetDevice(c->device));
+    if (s->two_level) return rc_tlas_rebuild(c, s, nullptr);
     rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, c->stream);
     const auto& ls = s->hb.level_start;
     for (int lv = (int)s->hb.depth - 1; lv >= 0; --lv)
@@ -404,6 +518,25 @@ int rc_bvh_get_stats(rc_ctx* c, const rc_scene* s_, rc_bvh_stats* o)
     if (!c || !s_ || !o) return RC_ERR_INVALID_ARG;
     if (!s_->built) return RC_ERR_NOT_BUILT;
     rc_scene* s = const_cast<rc_scene*>(s_);
+    o->n_instances = s->two_level ? s->nb : 0u;
+    o->tlas_levels = 0;
+    o->tlas_root = s->two_level ? s->blas_nodes : 0u;
+    o->reserved = 0;
+    if (s->two_level) {
+        uint32_t info[3] = {0, 0, 0};
+        RC_HIP(hipSetDevice(c->device));
+        RC_HIP(hipStreamSynchronize(c->stream));
+        RC_HIP(hipMemcpy(info, s->tlas.info, sizeof(info), hipMemcpyDeviceToHost));
+        o->n_nodes = (uint64_t)s->blas_nodes + info[0];
+        o->n_leaves = s->hb.n_leaves;
+        o->n_tris = s->nt;
+        o->depth = s->blas_depth + info[1];
+        o->max_stack = s->hb.max_stack;
+        o->sah_cost = 0.0;
+        o->build_ms = s->build_ms;
+        o->tlas_levels = info[1];
+        return RC_OK;
+    }
     if (s->sah_stale) {
         RC_HIP(hipSetDevice(c->device));
         RC_HIP(hipMemcpyAsync(s->hb.nodes.data(), s->d_nodes, s->hb.nodes.size() * sizeof(Node4),
@@ -422,13 +555,31 @@ int rc_bvh_get_stats(rc_ctx* c, const rc_scene* s_, rc_bvh_stats* o)
     return RC_OK;
 }
 
+int rc_tlas_export(rc_ctx* c, const rc_scene* s, float* inst_out)
+{
+    if (!c || !s || !inst_out) return RC_ERR_INVALID_ARG;
+    if (!s->built) return RC_ERR_NOT_BUILT;
+    if (!s->two_level) return RC_ERR_UNSUPPORTED;
+    RC_HIP(hipSetDevice(c->device));
+    RC_HIP(hipMemcpyAsync(inst_out, s->d_inst, (size_t)s->nb * sizeof(DevInst), hipMemcpyDeviceToHost, c->stream));
+    RC_HIP(hipStreamSynchronize(c->stream));
+    return RC_OK;
+}
+
 int rc_bvh_export(rc_ctx* c, const rc_scene* s, uint32_t* nodes_out, uint32_t* order_out)
 {
     if (!c || !s) return RC_ERR_INVALID_ARG;
     if (!s->built) return RC_ERR_NOT_BUILT;
     RC_HIP(hipSetDevice(c->device));
+    size_t n_nodes = s->hb.nodes.size();
+    if (s->two_level) {
+        uint32_t info[3] = {0, 0, 0};
+        RC_HIP(hipStreamSynchronize(c->stream));
+        RC_HIP(hipMemcpy(info, s->tlas.info, sizeof(info), hipMemcpyDeviceToHost));
+        n_nodes = (size_t)s->blas_nodes + info[0];
+    }
     if (nodes_out)
-        RC_HIP(hipMemcpyAsync(nodes_out, s->d_nodes, s->hb.nodes.size() * sizeof(Node4), hipMemcpyDeviceToHost, c->stream));
+        RC_HIP(hipMemcpyAsync(nodes_out, s->d_nodes, n_nodes * sizeof(Node4), hipMemcpyDeviceToHost, c->stream));
     if (order_out)
         RC_HIP(hipMemcpyAsync(order_out, s->d_order, (size_t)s->nt * 4, hipMemcpyDeviceToHost, c->stream));
     RC_HIP(hipStreamSynchronize(c->stream));
@@ -671,6 +822,7 @@ int plan_batch(rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views,
     for (uint32_t i = 0; i < n_scenes; ++i) {
         if (!scenes[i]) return RC_ERR_INVALID_ARG;
         if (!scenes[i]->built) return RC_ERR_NOT_BUILT;
+        if (scenes[i]->two_level) return RC_ERR_UNSUPPORTED;
         bp.scenes.push_back(dev_scene(scenes[i]));
         bp.max_stack = std::max(bp.max_stack, scenes[i]->hb.max_stack);
     }

@@ -32,6 +32,14 @@ __host__ __device__ inline uint32_t rc_make_leaf(uint32_t first, uint32_t count)
 // Packed triangle in leaf order: three float4 = 48 bytes,
 // (v0.xyz, original id as bits), (e1.xyz, 0), (e2.xyz, 0) with e1 = v1 - v0, e2 = v2 - v0 in FP32.
 
+// Instance of a two-level structure: world-to-object map [M | m] (row-major 3x4) and the root node of
+// its bottom-level tree.  64 bytes.
+struct alignas(64) DevInst {
+    float w2o[12];
+    uint32_t root;
+    uint32_t pad[3];
+};
+
 struct DevScene {
     const float* pos;         // n_vertices x 3 (current positions)
     const uint32_t* idx;      // n_tris x 3
@@ -42,6 +50,8 @@ struct DevScene {
     uint32_t n_tris, n_nodes;
     uint32_t max_stack;
     float scale;              // max |coordinate| of the scene (for diagnostics)
+    const DevInst* inst;      // two-level structures: instances (NULL for a flat BVH)
+    uint32_t tlas_root;       // two-level structures: root node of the top level
 };
 
 struct DevCamera {
@@ -74,10 +84,24 @@ struct HostBvh {
 bool rc_build_bvh_host(const float* pos, const uint32_t* idx, uint32_t n_tris,
                        uint32_t bins, uint32_t max_leaf, float node_cost, HostBvh& out);
 double rc_bvh_sah(const std::vector<Node4>& nodes);
-// Device LBVH build (k_build.hip); see rc_bvh_build with RC_BUILD_DEVICE_LBVH.
+// Device LBVH builds (k_build.hip); see rc_bvh_build.
 hipError_t rc_build_bvh_device(const float* d_pos, const uint32_t* d_idx, uint32_t n, uint32_t max_leaf,
-                               Node4** d_nodes_out, uint32_t* n_nodes_out, uint32_t* d_order,
-                               std::vector<uint32_t>& level_start, hipStream_t st);
+                               const uint32_t* d_seg, const std::vector<uint32_t>& seg_first,
+                               const std::vector<uint32_t>& seg_count, Node4** d_nodes_out, uint32_t* n_nodes_out,
+                               uint32_t* d_order, std::vector<uint32_t>& level_start, hipStream_t st);
+// Top-level workspace (all device memory, sized for n instances at allocation).
+struct TlasWork {
+    uint32_t n = 0, cap = 0;
+    size_t temp_bytes = 0;
+    void *box = nullptr, *cen = nullptr, *partial = nullptr, *bounds = nullptr, *keys = nullptr, *keys_s = nullptr,
+         *vals = nullptr, *order = nullptr, *flags = nullptr, *child = nullptr, *range = nullptr, *parent = nullptr,
+         *nbox = nullptr, *lvl = nullptr, *info = nullptr, *temp = nullptr;   // info: {nodes, levels, error}
+};
+#define RC_TLAS_MAX_LEVELS 24
+hipError_t rc_tlas_alloc(TlasWork& w, uint32_t n);
+void rc_tlas_free(TlasWork& w);
+hipError_t rc_tlas_build(TlasWork& w, const float* o2w, Node4* nodes, uint32_t tlas_base, DevInst* inst,
+                         uint32_t max_levels, uint32_t* error_flag, hipStream_t st);
 
 // Traversal launch geometry
 #define RC_TRACE_BLOCK 128
@@ -153,6 +177,7 @@ void rc_launch_pack_features(const DevScene& sc, const DevCamera& cam, const uin
 void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris,
                     float4* tris, hipStream_t st);
 void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st);
+void rc_launch_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, float* o2w, hipStream_t st);
 void rc_launch_transform(const float* rest, float* pos, const uint32_t* body_vrange, const float* xf,
                          const uint32_t* body_ids, uint32_t n_bodies, uint32_t max_count, hipStream_t st);
 void rc_launch_refit_level(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order,

@@ -54,4 +54,11 @@ struct rc_scene {
     double build_ms = 0.0;
     float scale = 1.0f;
     bool sah_stale = false;   // boxes refit on the device since the host copy was made
+    // two-level structure (RC_BUILD_TWO_LEVEL): bottom-level trees = nodes 0 .. blas_nodes-1 (body b's root
+    // is node b, over rest positions), top level from node blas_nodes on, rebuilt from the bodies' maps
+    float* d_o2w = nullptr;   // per body [R | t], row-major 3x4 (identity until the body is moved)
+    bool two_level = false;
+    DevInst* d_inst = nullptr;
+    uint32_t blas_nodes = 0, blas_depth = 0;
+    TlasWork tlas;
 };

@@ -5,6 +5,8 @@
 #include "rc_device.h"
 
 #define RC_STACK_EMPTY 0xFFFFFFFEu
+// stack entry that ends a bottom-level traversal (two-level structures): the ray returns to world space
+#define RC_INST_RETURN 0xFFFFFFFDu
 
 // conservative growth of the far slab distance (covers FP32 rounding of the slab tests)
 #define RC_FAR_GROW 1.000001f
@@ -19,6 +21,41 @@ struct TravState {
     uint32_t best_id;
     float best_t, best_u, best_v;
 };
+
+// World-space ray of a two-level traversal while the working ray is mapped into an instance.  The flag is
+// a 32-bit word: per-lane bool state carried through the divergent traversal loops has been mishandled
+// by the compiler (lanes losing their value), 32-bit words have not.
+struct TravWorld {
+    float o[3], d[3];
+    uint32_t in_blas;
+};
+
+__device__ inline void rc_ray_inv(TravRay& r)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float dd = fabsf(r.d[a]) < 1e-20f ? copysignf(1e-20f, r.d[a]) : r.d[a];
+        r.inv[a] = 1.0f / dd;
+    }
+}
+
+// The world ray (o, d) mapped into an instance by its world-to-object map W = [M | m] (row-major 3x4):
+// o' = M o + m, d' = M d, each component as ((M0 a0 + M1 a1) + M2 a2) [+ m] in FP32.
+__device__ inline void rc_map_ray(const float* W, const float o[3], const float d[3], TravRay& r)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float a = W[4 * k] * o[0];
+        const float b = W[4 * k + 1] * o[1];
+        const float c = W[4 * k + 2] * o[2];
+        r.o[k] = ((a + b) + c) + W[4 * k + 3];
+        const float e = W[4 * k] * d[0];
+        const float f = W[4 * k + 1] * d[1];
+        const float g = W[4 * k + 2] * d[2];
+        r.d[k] = (e + f) + g;
+    }
+    rc_ray_inv(r);
+}
 
 // Work queue split over the XCDs.  Workgroups are dispatched to the XCDs round-robin, so workgroup b runs
 // on XCD g = b % RC_XCDS.  The work sequence (items, or 64-ray packets) is cut into chunks of CHUNK that
@@ -97,25 +134,43 @@ struct TravStack {
     }
 };
 
-__device__ inline void trav_begin(TravRay& r, TravState& s)
+// Start a ray at node `root` (0 for a flat BVH, the top-level root of a two-level structure); w (two-level
+// traversals only) keeps the world ray.
+__device__ inline void trav_begin(TravRay& r, TravState& s, uint32_t root = 0u, TravWorld* w = nullptr)
 {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float dd = fabsf(r.d[a]) < 1e-20f ? copysignf(1e-20f, r.d[a]) : r.d[a];
-        r.inv[a] = 1.0f / dd;
-    }
-    s.cur = 0;
+    rc_ray_inv(r);
+    s.cur = root;
     s.sp = 0;
     s.best_id = RC_NO_HIT;
     s.best_t = INFINITY;
     s.best_u = s.best_v = 0.0f;
+    if (w) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { w->o[a] = r.o[a]; w->d[a] = r.d[a]; }
+        w->in_blas = 0u;
+    }
+}
+
+// Next stack entry; in a two-level traversal an instance's end marker restores the world ray.
+template <bool TWO, class Stack>
+__device__ inline uint32_t trav_pop(TravRay& r, TravState& s, Stack& st, bool any, TravWorld* w)
+{
+    for (;;) {
+        const uint32_t c = st.pop(s.sp, !any, s.best_t);
+        if (!TWO || c != RC_INST_RETURN) return c;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { r.o[a] = w->o[a]; r.d[a] = w->d[a]; }
+        rc_ray_inv(r);
+        w->in_blas = 0u;
+    }
 }
 
 // Visit the internal node s.cur: test the four child boxes, continue with the nearest hit child and
 // push the others (farthest first), or pop.  `any`: any-hit ray on the segment 0 < t < 1, otherwise
 // closest hit (boxes beyond the current hit are culled).
-template <class Stack>
-__device__ inline void trav_visit_node(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool any)
+template <bool TWO = false, class Stack>
+__device__ inline void trav_visit_node(const DevScene& sc, TravRay& r, TravState& s, Stack& st, bool any,
+                                       TravWorld* w = nullptr)
 {
     const float4* np = reinterpret_cast<const float4*>(sc.nodes + s.cur);
     float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
@@ -150,7 +205,7 @@ __device__ inline void trav_visit_node(const DevScene& sc, const TravRay& r, Tra
     if (tn[3] < INFINITY) st.push(s.sp, cw[3], tn[3]);
     if (tn[2] < INFINITY) st.push(s.sp, cw[2], tn[2]);
     if (tn[1] < INFINITY) st.push(s.sp, cw[1], tn[1]);
-    s.cur = tn[0] < INFINITY ? cw[0] : st.pop(s.sp, !any, s.best_t);
+    s.cur = tn[0] < INFINITY ? cw[0] : trav_pop<TWO>(r, s, st, any, w);
 }
 
 // Moller-Trumbore in FP32 on a packed triangle (v0, e1, e2): the fixed operation order every traversal
@@ -182,10 +237,19 @@ __device__ inline bool rc_mt(const TravRay& r, float ax, float ay, float az, flo
 
 // Test the triangles of the leaf s.cur (Moller-Trumbore in FP32), then pop; an any-hit ray ends at its
 // first hit (occluded = true, s.cur = RC_STACK_EMPTY).
-template <class Stack>
-__device__ inline void trav_test_leaf(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool any,
-                                      uint32_t& occluded, uint32_t& tri_tests)
+template <bool TWO = false, class Stack>
+__device__ inline void trav_test_leaf(const DevScene& sc, TravRay& r, TravState& s, Stack& st, bool any,
+                                      uint32_t& occluded, uint32_t& tri_tests, TravWorld* w = nullptr)
 {
+    if (TWO && w->in_blas == 0u) {
+        // top-level leaf: enter the instance (map the ray, mark the return point on the stack)
+        const DevInst& I = sc.inst[rc_leaf_first(s.cur)];
+        rc_map_ray(I.w2o, w->o, w->d, r);
+        st.push(s.sp, RC_INST_RETURN, -INFINITY);
+        w->in_blas = 1u;
+        s.cur = I.root;
+        return;
+    }
     uint32_t first = rc_leaf_first(s.cur), cnt = rc_leaf_count(s.cur);
     for (uint32_t i = 0; i < cnt; ++i) {
         ++tri_tests;
@@ -202,29 +266,30 @@ __device__ inline void trav_test_leaf(const DevScene& sc, const TravRay& r, Trav
             }
         }
     }
-    s.cur = occluded != 0u ? RC_STACK_EMPTY : st.pop(s.sp, !any, s.best_t);
+    s.cur = occluded != 0u ? RC_STACK_EMPTY : trav_pop<TWO>(r, s, st, any, w);
 }
 
 // Advance every busy lane of the wave: first all lanes standing at an internal node visit nodes until
 // none does, then all lanes standing at a leaf test leaves until none does.  A lane's own sequence of
 // visits is the same as visiting one node or leaf at a time, whatever the other lanes do; only the
 // grouping of the work into SIMD steps changes (fewer steps that execute both code paths).
-template <class Stack>
-__device__ inline void trav_advance(const DevScene& sc, const TravRay& r, TravState& s, Stack& st, bool busy,
-                                    bool any, uint32_t& occluded, uint32_t& node_visits, uint32_t& tri_tests)
+template <bool TWO = false, class Stack>
+__device__ inline void trav_advance(const DevScene& sc, TravRay& r, TravState& s, Stack& st, bool busy,
+                                    bool any, uint32_t& occluded, uint32_t& node_visits, uint32_t& tri_tests,
+                                    TravWorld* w = nullptr)
 {
     for (;;) {
         bool inner = busy && !rc_is_leaf(s.cur);
         if (__ballot(inner) == 0) break;
         if (inner) {
             ++node_visits;
-            trav_visit_node(sc, r, s, st, any);
+            trav_visit_node<TWO>(sc, r, s, st, any, w);
         }
     }
     for (;;) {
         bool leaf = busy && s.cur != RC_STACK_EMPTY && rc_is_leaf(s.cur);
         if (__ballot(leaf) == 0) break;
-        if (leaf) trav_test_leaf(sc, r, s, st, any, occluded, tri_tests);
+        if (leaf) trav_test_leaf<TWO>(sc, r, s, st, any, occluded, tri_tests, w);
     }
 }
 

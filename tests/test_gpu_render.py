@@ -23,16 +23,19 @@ def ctx():
     c.close()
 
 
-def render_and_compare(ctx, O, scene, cam, rtol=1e-4, sample_idx=None, brute=False, device_build=False):
+def render_and_compare(ctx, O, scene, cam, rtol=1e-4, sample_idx=None, brute=False, device_build=False, gs=None,
+                       osc=None):
     """Render with the default kernels (wave-uniform camera rays) and with per-lane traversal, and check both
-    against one oracle run."""
+    against one oracle run.  gs / osc: an already built GPU scene / oracle scene to use instead."""
     import torch
     say(f"[render] {scene.name} {cam.width}x{cam.height} ssaa={cam.ssaa} tris={scene.n_tris} "
-        f"build={'device' if device_build else 'host'}")
-    gs = ctx.scene_from(scene).build(device=device_build)
+        f"build={'given' if gs is not None else ('device' if device_build else 'host')}")
+    if gs is None:
+        gs = ctx.scene_from(scene).build(device=device_build)
     n = cam.n_samples
     smp = np.arange(n) if sample_idx is None else np.asarray(sample_idx)
-    osc = O.OracleScene.from_scene(scene, use_bvh=not brute)
+    if osc is None:
+        osc = O.OracleScene.from_scene(scene, use_bvh=not brute)
     orc = osc.render_point(cam, scene.point_lights, smp, brute=brute)
     for per_lane in (True, False):
         out = ctx.render(gs, cam, scene.point_lights, sample_rgba=True, per_lane=per_lane)
@@ -162,14 +165,15 @@ def test_render_error_paths(ctx):
     assert ctx.last_error() == 0
 
 
-def compare_rect(ctx, O, scene, cam, N, stream, pixels=None, device_build=False):
+def compare_rect(ctx, O, scene, cam, N, stream, pixels=None, device_build=False, gs=None, osc=None):
     """Both rect-light kernels (wave-uniform traversal, used from 64 samples per pixel; per-lane stacks)
     against one oracle run: hit ids and visible-sample counts exact outside the FP32 band, radiance within
-    1e-4."""
+    1e-4.  gs / osc: an already built GPU scene / oracle scene to use instead."""
     import torch
     say(f"[rect] {scene.name} {cam.width}x{cam.height} N={N} tris={scene.n_tris} "
-        f"build={'device' if device_build else 'host'}")
-    gs = ctx.scene_from(scene).build(device=device_build)
+        f"build={'given' if gs is not None else ('device' if device_build else 'host')}")
+    if gs is None:
+        gs = ctx.scene_from(scene).build(device=device_build)
     outs = {}
     for per_lane in (False, True):
         outs[per_lane] = ctx.render(gs, cam, (), rect=scene.rect_light, area_samples=N, area_stream=stream,
@@ -178,7 +182,8 @@ def compare_rect(ctx, O, scene, cam, N, stream, pixels=None, device_build=False)
         assert ctx.last_error() == 0
     npix = cam.width * cam.height
     pix = np.arange(npix) if pixels is None else np.asarray(pixels)
-    osc = O.OracleScene.from_scene(scene)
+    if osc is None:
+        osc = O.OracleScene.from_scene(scene)
     orc = osc.render_rect(cam, scene.rect_light, N, stream, pix)
     bp = orc["band_primary"].astype(bool)
     ok = ~bp
