@@ -33,7 +33,7 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # the copy-kernel calibration), keyed by (workload, spp, hash of the traversal kernel sources); the
 # value only applies while those sources are unchanged (summaries under profiles/).
 MEASURED_TRAFFIC = {
-    ("big_7M", 64, "54ccd231847f07b8:96fd43948bc92d3c:b293fc24f86445cf"): 425_923_000,
+    ("big_7M", 64, "0a586d4eb4e3d6ca:96fd43948bc92d3c:ed4254a5d1e3e117"): 425_663_000,
 }
 
 
@@ -196,6 +196,105 @@ def device_build(ctx, scene, cam, kw, args):
             "primary_ms": med("primary_ms")}
 
 
+def dynamic_structures(ctx, gs_flat, scene, cam, args):
+    """Moving bodies with the paper's structure choice (Sec. IV-B, "Ray-traced shadows"): a top level over
+    per-body trees rebuilt every frame on an asynchronous queue, against updating (refitting) one flat BVH.
+    300 of the 1501 bodies move (<= 5 cm, <= 2 degrees per frame, the same motion as the animated frames).
+    Per frame: move the bodies, update the structure, render the paper's timed configuration (one camera ray
+    and one hard-shadow ray per pixel, 1080p) or the 64-sample soft-shadow frame.  Device time per frame,
+    mean over the frames after a warm-up frame; node visits and triangle tests per ray of the last frame.
+    Paths: flat BVH + refit; two-level + top-level rebuild in line; two-level with the rebuild of frame f+1
+    on a second stream beside the render of frame f (two scene copies, alternating)."""
+    import numpy as np
+    import torch
+
+    from paper_2410_05095_amd import scenegen as sg
+    c = scene.rect_light.center
+    hard = dict(lights=np.array([[c[0], c[1], c[2], 400.0, 400.0, 400.0]], np.float32))
+    soft = dict(lights=(), rect=scene.rect_light, area_samples=args.spp, area_stream=0)
+    anim = sg.RigidAnimation(scene, n_bodies=300, seed=args.seed)
+    F = args.dyn_frames
+    xfs = [torch.from_numpy(anim.transforms(f)).cuda() for f in range(1, F + 2)]
+    ids = torch.from_numpy(anim.body_ids.astype(np.int32)).cuda()
+    rest = torch.eye(3, 4, dtype=torch.float32).repeat(len(anim.body_ids), 1, 1).reshape(-1, 12).cuda()
+    main = torch.cuda.current_stream()
+    res = {}
+
+    def per_ray(st):
+        return {"primary_nodes": round(st["primary_nodes"] / max(st["primary_rays"], 1), 2),
+                "shadow_nodes": round(st["shadow_nodes"] / max(st["shadow_rays"], 1), 2),
+                "shadow_tris": round(st["shadow_tris"] / max(st["shadow_rays"], 1), 2)}
+
+    def inline(g, kw, update):
+        g.set_transforms(rest, ids)
+        update(g)
+        out = {}
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        upd, tot = [], []
+        for f in range(F):
+            ev[0].record(main)
+            g.set_transforms(xfs[f], ids)
+            update(g)
+            ev[1].record(main)
+            ctx.render(g, cam, out=out, **kw)
+            ev[2].record(main)
+            torch.cuda.synchronize()
+            if f > 0:
+                upd.append(ev[0].elapsed_time(ev[1]))
+                tot.append(ev[0].elapsed_time(ev[2]))
+        ctx.render(g, cam, out=out, timing=True, **kw)
+        st = ctx.stage_times()
+        assert ctx.last_error() == 0
+        return {"update_ms": round(float(np.mean(upd)), 4), "frame_ms": round(float(np.mean(tot)), 4), **per_ray(st)}
+
+    def overlapped(pair, kw):
+        side = torch.cuda.Stream()
+        for g in pair:
+            g.set_transforms(rest, ids)
+            g.tlas_rebuild()
+        pair[0].set_transforms(xfs[0], ids)
+        pair[0].tlas_rebuild()
+        torch.cuda.synchronize()
+        out = {}
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for f in range(F):
+            if f == 1:
+                e0.record(main)
+            cur, nxt = pair[f % 2], pair[(f + 1) % 2]
+            side.wait_stream(main)              # nxt's previous render is done before it moves
+            with torch.cuda.stream(side):
+                nxt.set_transforms(xfs[f + 1], ids)
+                nxt.tlas_rebuild(stream=side)
+            ctx.render(cur, cam, out=out, **kw)
+            main.wait_stream(side)              # the next frame renders nxt
+        e1.record(main)
+        torch.cuda.synchronize()
+        assert ctx.last_error() == 0
+        return {"frame_ms": round(e0.elapsed_time(e1) / (F - 1), 4)}
+
+    refit = lambda g: g.refit()
+    rebuild = lambda g: g.tlas_rebuild()
+    two = ctx.scene_from(scene).build(two_level=True)
+    two_b = ctx.scene_from(scene).build(two_level=True)
+    tst = two.stats()
+    for name, kw in (("hard_1080p", hard), ("soft_64spp", soft)):
+        r = {"flat_refit": inline(gs_flat, kw, refit), "two_level_rebuild": inline(two, kw, rebuild),
+             "two_level_rebuild_async": overlapped((two, two_b), kw)}
+        res[name] = r
+        log(f"[bench] dynamic structures {name}: {r}")
+    gs_flat.set_transforms(rest, ids)
+    gs_flat.refit()
+    torch.cuda.synchronize()
+    two.close()
+    two_b.close()
+    res["two_level_build_ms"] = round(tst["build_ms"], 2)
+    res["tlas_levels"] = int(tst["tlas_levels"])
+    res["bodies"] = int(tst["n_instances"])
+    res["moving_bodies"] = int(len(anim.body_ids))
+    res["frames"] = F
+    return res
+
+
 def animated(ctx, gs, scene, den, args):
     """The same scene with 300 rigid bodies moving (<= 5 cm, <= 2 degrees per frame), BVH refit every frame,
     args.anim_views 1080p views per frame on the learned 1-spp path; per-frame shadow MSE of the BF16
@@ -233,6 +332,8 @@ def main():
     ap.add_argument("--anim-frames", type=int, default=12,
                     help="animated frames (moving bodies, refit) rendered after the learned-path comparison")
     ap.add_argument("--anim-views", type=int, default=16, help="1080p views per animated frame")
+    ap.add_argument("--dyn-frames", type=int, default=24,
+                    help="frames of the moving-body comparison of flat refit and two-level rebuild (0 = skip)")
     ap.add_argument("--profile-denoiser", type=int, default=0,
                     help="instead of rendering, run this many BF16 denoiser inferences of one 1080p view (twice: "
                          "warm-up, timed) and one FP32-copy inference")
@@ -365,6 +466,8 @@ def main():
     }
     res["post"] = post_pass(ctx, out, args)
     res["device_bvh"] = device_build(ctx, scene, cam, kw, args)
+    if args.workload == "big_7M" and args.dyn_frames > 1:
+        res["dynamic_structures"] = dynamic_structures(ctx, gs, scene, cam, args)
     if args.workload == "big_7M":
         res["hard_shadows"] = hard_shadows(ctx, gs, scene, cam, args)
     if args.workload == "big_7M" and args.denoiser_steps > 0:
