@@ -183,6 +183,15 @@ static ev3 ev3_cross(ev3 a, ev3 b)
     return r;
 }
 static ev3 ev3_exact(v3 a) { ev3 r = {{a.x, 0}, {a.y, 0}, {a.z, 0}}; return r; }
+/* correctly rounded FP32 quotient; the divisor's interval must exclude zero (else the bound is infinite) */
+static ev ev_div(ev a, ev b)
+{
+    double v = a.v / b.v;
+    double lo = fabs(b.v) - b.e;
+    double e = lo > 0.0 ? (a.e + fabs(v) * b.e) / lo : INFINITY;
+    return ev_x(v, e + U32R * (fabs(v) + e));
+}
+static ev ev3_comp(ev3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
 /* an FP64 vector that the FP32 side holds rounded to FP32 (<= half an ulp per component) */
 static ev3 ev3_rounded(v3 a) { ev3 r = {{a.x, U32R * fabs(a.x)}, {a.y, U32R * fabs(a.y)}, {a.z, U32R * fabs(a.z)}}; return r; }
 
@@ -196,6 +205,7 @@ typedef struct {
     const uint32_t* tri_mat;
     const float* mats; int64_t nmat;    /* albedo rgb, roughness, metallic */
     const struct or_inst* inst;         /* NULL, or the instances that answer hit queries (two-level) */
+    int64_t flags;                      /* bit 0: the FP32 side tests triangles watertight (band model) */
 } or_scene;
 
 static void tri_verts(const or_scene* s, uint32_t t, v3* a, v3* b, v3* c)
@@ -291,6 +301,114 @@ static void mt_test(const or_scene* s, uint32_t tri, const ray_ev* r, double tmi
         out->et = INFINITY; out->eu = INFINITY; out->ev = INFINITY;
     }
     if (out->status == ST_PASS && !out->exact_hit) out->status = ST_UNC; /* cannot happen; stay safe */
+}
+
+/* ------------------------------------------------------------------------- */
+/* Watertight ray/triangle test (Woop, Benthin and Wald, JCGT 2013) as the    */
+/* FP32 side evaluates it: kz = axis of the largest |d| (first on ties),      */
+/* kx, ky the next axes cyclically, swapped when d[kz] < 0; Sx = d[kx]/d[kz], */
+/* Sy = d[ky]/d[kz], Sz = 1/d[kz]; vertices relative to the origin, sheared:  */
+/* X' = X[kx] - Sx X[kz], Y' = X[ky] - Sy X[kz]; edge functions               */
+/* U = Cx By - Cy Bx, V = Ax Cy - Ay Cx, W = Bx Ay - By Ax (recomputed in FP64 */
+/* when one is exactly zero); a hit needs U, V, W of one sign (not all zero); */
+/* det = (U + V) + W, T = (U Sz A[kz] + V Sz B[kz]) + W Sz C[kz], t = T / det */
+/* (reciprocal within 1 ulp), u = V / det, v = W / det.  In exact arithmetic  */
+/* it decides the same geometric crossing as Moller-Trumbore, so only the     */
+/* FP32 certainty (the band) depends on the test.                             */
+/* ------------------------------------------------------------------------- */
+static int wt_band_perm(const ray_ev* r, int kx, int ky, int kz, v3 a, v3 b, v3 cc, double tmin, double tmax,
+                        double c, double* et, double* eu, double* evv)
+{
+    *et = *eu = *evv = INFINITY;
+    ev dz = ev3_comp(r->ed, kz);
+    if (fabs(dz.v) <= c * dz.e) return ST_UNC;
+    ev Sx = ev_div(ev3_comp(r->ed, kx), dz), Sy = ev_div(ev3_comp(r->ed, ky), dz), Sz = ev_div(ev_x(1.0, 0.0), dz);
+    ev3 V0 = ev3_sub(ev3_exact(a), r->eo), V1 = ev3_sub(ev3_exact(b), r->eo), V2 = ev3_sub(ev3_exact(cc), r->eo);
+    ev Ax = ev_sub(ev3_comp(V0, kx), ev_mul(Sx, ev3_comp(V0, kz)));
+    ev Ay = ev_sub(ev3_comp(V0, ky), ev_mul(Sy, ev3_comp(V0, kz)));
+    ev Bx = ev_sub(ev3_comp(V1, kx), ev_mul(Sx, ev3_comp(V1, kz)));
+    ev By = ev_sub(ev3_comp(V1, ky), ev_mul(Sy, ev3_comp(V1, kz)));
+    ev Cx = ev_sub(ev3_comp(V2, kx), ev_mul(Sx, ev3_comp(V2, kz)));
+    ev Cy = ev_sub(ev3_comp(V2, ky), ev_mul(Sy, ev3_comp(V2, kz)));
+    ev U = ev_sub(ev_mul(Cx, By), ev_mul(Cy, Bx));
+    ev V = ev_sub(ev_mul(Ax, Cy), ev_mul(Ay, Cx));
+    ev W = ev_sub(ev_mul(Bx, Ay), ev_mul(By, Ax));
+    const ev E[3] = {U, V, W};
+    int pos = 0, neg = 0, unk = 0;
+    for (int k = 0; k < 3; ++k) {
+        if (E[k].v > c * E[k].e) ++pos;
+        else if (E[k].v < -c * E[k].e) ++neg;
+        else ++unk;
+    }
+    if (pos > 0 && neg > 0) return ST_FAIL;          /* certainly on both sides of some edge */
+    if (unk > 0) return ST_UNC;
+    ev det = ev_add(ev_add(U, V), W);
+    ev Az = ev_mul(Sz, ev3_comp(V0, kz)), Bz = ev_mul(Sz, ev3_comp(V1, kz)), Cz = ev_mul(Sz, ev3_comp(V2, kz));
+    ev T = ev_add(ev_add(ev_mul(U, Az), ev_mul(V, Bz)), ev_mul(W, Cz));
+    double edet = c * det.e;
+    if (!(fabs(det.v) > edet)) return ST_UNC;
+    double sg = det.v > 0 ? 1.0 : -1.0;
+    double dlo = fabs(det.v) - edet, dhi = fabs(det.v) + edet;
+    const double num[3] = {sg * T.v, sg * V.v, sg * W.v}, en[3] = {c * T.e, c * V.e, c * W.e};
+    double qlo[3], qhi[3];
+    for (int k = 0; k < 3; ++k) {
+        double lo_ = num[k] - en[k], hi_ = num[k] + en[k];
+        double lo = fmin(lo_ / dlo, lo_ / dhi), hi = fmax(hi_ / dlo, hi_ / dhi);
+        double w = 4.0 * c * U32R;
+        qlo[k] = lo - w * fabs(lo);
+        qhi[k] = hi + w * fabs(hi);
+    }
+    int st0 = qlo[0] > tmin ? ST_PASS : (qhi[0] <= tmin ? ST_FAIL : ST_UNC);
+    int st1 = isinf(tmax) ? ST_PASS : (qhi[0] < tmax ? ST_PASS : (qlo[0] >= tmax ? ST_FAIL : ST_UNC));
+    double t = num[0] / fabs(det.v), u = num[1] / fabs(det.v), v = num[2] / fabs(det.v);
+    *et = fmax(t - qlo[0], qhi[0] - t);
+    *eu = fmax(u - qlo[1], qhi[1] - u);
+    *evv = fmax(v - qlo[2], qhi[2] - v);
+    if (st0 == ST_FAIL || st1 == ST_FAIL) return ST_FAIL;
+    if (st0 == ST_UNC || st1 == ST_UNC) return ST_UNC;
+    return ST_PASS;
+}
+
+static void wt_band(const or_scene* s, uint32_t tri, const ray_ev* r, double tmin, double tmax, double c, tri_test* out)
+{
+    v3 a, b, cc;
+    tri_verts(s, tri, &a, &b, &cc);
+    const double dv[3] = {r->ed.x.v, r->ed.y.v, r->ed.z.v}, de[3] = {r->ed.x.e, r->ed.y.e, r->ed.z.e};
+    int kz = 0;
+    if (fabs(dv[1]) > fabs(dv[kz])) kz = 1;
+    if (fabs(dv[2]) > fabs(dv[kz])) kz = 2;
+    /* axes whose |d| may be the FP32 side's largest (its rounded values can order a near tie differently) */
+    int cand[3], nc = 0;
+    for (int k = 0; k < 3; ++k)
+        if (k == kz || fabs(dv[k]) + de[k] * c >= fabs(dv[kz]) - de[kz] * c) cand[nc++] = k;
+    int status = -1;
+    double et = 0, eu = 0, evv = 0;
+    for (int q = 0; q < nc; ++q) {
+        const int z = cand[q];
+        int x = (z + 1) % 3, y = (z + 2) % 3;
+        /* the swap follows the sign of d[z]; an uncertain sign is covered by evaluating both orders */
+        int orders = fabs(dv[z]) > c * de[z] ? 1 : 2;
+        for (int o = 0; o < orders; ++o) {
+            int sw = (dv[z] < 0.0) ^ (o == 1);
+            int kx = sw ? y : x, ky = sw ? x : y;
+            double a_, b_, c_;
+            int st = wt_band_perm(r, kx, ky, z, a, b, cc, tmin, tmax, c, &a_, &b_, &c_);
+            if (status < 0) status = st;
+            else if (st != status) status = ST_UNC;
+            et = fmax(et, a_); eu = fmax(eu, b_); evv = fmax(evv, c_);
+        }
+    }
+    out->status = status;
+    out->et = et; out->eu = eu; out->ev = evv;
+    if (out->status == ST_PASS && !out->exact_hit) out->status = ST_UNC;   /* cannot happen; stay safe */
+    if (out->status == ST_FAIL && out->exact_hit) out->status = ST_UNC;
+}
+
+/* the triangle test of the scene's FP32 side: exact answer + certainty */
+static void tri_check(const or_scene* s, uint32_t tri, const ray_ev* r, double tmin, double tmax, double c, tri_test* out)
+{
+    mt_test(s, tri, r, tmin, tmax, c, out);
+    if (s->flags & 1) wt_band(s, tri, r, tmin, tmax, c, out);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -514,7 +632,7 @@ static void closest_bvh_acc(const or_bvh* B, const ray_ev* r, double tmin, doubl
                 for (int32_t i = 0; i < n->count; ++i) {
                     uint32_t tri = B->tris[n->first + i];
                     tri_test tt;
-                    mt_test(B->scene, tri, r, tmin, tmax, c, &tt);
+                    tri_check(B->scene, tri, r, tmin, tmax, c, &tt);
                     closest_consider(&A, tri, &tt);
                 }
             } else {
@@ -540,7 +658,7 @@ static void closest_brute(const or_scene* s, const ray_ev* r, double tmin, doubl
     acc_init(&A);
     for (int64_t t = 0; t < s->nt; ++t) {
         tri_test tt;
-        mt_test(s, (uint32_t)t, r, tmin, tmax, c, &tt);
+        tri_check(s, (uint32_t)t, r, tmin, tmax, c, &tt);
         closest_consider(&A, (uint32_t)t, &tt);
     }
     closest_finish(&A, out);
@@ -554,7 +672,7 @@ static int any_bvh(const or_scene* s, const or_bvh* B, const ray_ev* r, double t
     if (B == NULL) {
         for (int64_t t = 0; t < s->nt; ++t) {
             tri_test tt;
-            mt_test(s, (uint32_t)t, r, tmin, tmax, c, &tt);
+            tri_check(s, (uint32_t)t, r, tmin, tmax, c, &tt);
             if (tt.exact_hit) { occluded = 1; if (*who == NO_HIT) *who = (uint32_t)t; }
             if (tt.status == ST_PASS) { *band = 0; return 1; }
             if (tt.status == ST_UNC) unc = 1;
@@ -573,7 +691,7 @@ static int any_bvh(const or_scene* s, const or_bvh* B, const ray_ev* r, double t
             for (int32_t i = 0; i < n->count; ++i) {
                 uint32_t tri = B->tris[n->first + i];
                 tri_test tt;
-                mt_test(s, tri, r, tmin, tmax, c, &tt);
+                tri_check(s, tri, r, tmin, tmax, c, &tt);
                 if (tt.exact_hit) { occluded = 1; if (*who == NO_HIT) *who = tri; }
                 if (tt.status == ST_PASS) { *band = 0; *who = tri; return 1; }
                 if (tt.status == ST_UNC) unc = 1;
@@ -729,7 +847,7 @@ static void closest_inst(const or_inst* I, int use_bvh, const ray_ev* r, double 
         } else {
             for (uint32_t t = I->range[2 * i]; t < I->range[2 * i] + I->range[2 * i + 1]; ++t) {
                 tri_test tt;
-                mt_test(I->rest, t, &q, tmin, tmax, c, &tt);
+                tri_check(I->rest, t, &q, tmin, tmax, c, &tt);
                 closest_consider(&A, t, &tt);
             }
         }
@@ -750,7 +868,7 @@ static int any_inst(const or_inst* I, int use_bvh, const ray_ev* r, double tmin,
         } else {
             for (uint32_t t = I->range[2 * i]; t < I->range[2 * i] + I->range[2 * i + 1]; ++t) {
                 tri_test tt;
-                mt_test(I->rest, t, &q, tmin, tmax, c, &tt);
+                tri_check(I->rest, t, &q, tmin, tmax, c, &tt);
                 if (tt.exact_hit) occ = 1;
                 if (tt.status == ST_PASS) { occ = 1; b = 0; break; }
                 if (tt.status == ST_UNC) b = 1;
@@ -1114,7 +1232,7 @@ OR_API void or_tri_test(const or_scene* s, uint32_t tri, const float o[3], const
 {
     ray_ev r = exact_ray(from_f(o), from_f(d));
     tri_test tt;
-    mt_test(s, tri, &r, tmin, tmax, c, &tt);
+    tri_check(s, tri, &r, tmin, tmax, c, &tt);
     out[0] = tt.exact_hit; out[1] = tt.status; out[2] = tt.t; out[3] = tt.u; out[4] = tt.v;
     out[5] = tt.et; out[6] = tt.eu; out[7] = tt.ev;
 }

@@ -34,7 +34,8 @@ def lib():
 
 class OrScene(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("nv", C.c_int64), ("idx", C.c_void_p), ("nt", C.c_int64),
-                ("tri_mat", C.c_void_p), ("mats", C.c_void_p), ("nmat", C.c_int64), ("inst", C.c_void_p)]
+                ("tri_mat", C.c_void_p), ("mats", C.c_void_p), ("nmat", C.c_int64), ("inst", C.c_void_p),
+                ("flags", C.c_int64)]
 
 
 class OrCamera(C.Structure):
@@ -126,29 +127,32 @@ def gen_rays(cam, samples: np.ndarray):
 class OracleScene:
     """Holds the FP32 arrays of a scene and (optionally) the oracle's own BVH."""
 
-    def __init__(self, positions, indices, tri_material, materials, use_bvh: bool = True):
+    def __init__(self, positions, indices, tri_material, materials, use_bvh: bool = True, watertight: bool = False):
         self.pos = np.ascontiguousarray(positions, dtype=np.float32)
         self.idx = np.ascontiguousarray(indices, dtype=np.uint32)
         self.tri_mat = np.ascontiguousarray(tri_material, dtype=np.uint32)
         self.mats = np.ascontiguousarray(materials, dtype=np.float32)
         self.s = OrScene(_p(self.pos).value, self.pos.shape[0], _p(self.idx).value, self.idx.shape[0],
-                         _p(self.tri_mat).value, _p(self.mats).value, self.mats.shape[0], None)
+                         _p(self.tri_mat).value, _p(self.mats).value, self.mats.shape[0], None,
+                         1 if watertight else 0)
+        self.watertight = watertight
         self.bvh = lib().or_bvh_build(C.byref(self.s)) if use_bvh else None
         self.inst = None
 
     @classmethod
-    def from_scene(cls, scene, use_bvh: bool = True):
-        return cls(scene.positions, scene.indices, scene.tri_material, scene.materials, use_bvh)
+    def from_scene(cls, scene, use_bvh: bool = True, watertight: bool = False):
+        """watertight: the FP32 side tests triangles with the watertight test (its band model)."""
+        return cls(scene.positions, scene.indices, scene.tri_material, scene.materials, use_bvh, watertight)
 
     @classmethod
     def two_level(cls, world_positions, rest_positions, indices, tri_material, materials, tri_range, o2w,
-                  use_bvh: bool = True):
+                  use_bvh: bool = True, watertight: bool = False):
         """A scene whose hit queries go through instances: instance i is triangles tri_range[i] =
         (first, count) of the rest-frame positions, placed by the rigid map [R | t] = o2w[i] (3x4, FP32)
         and tested in its own frame through the world-to-object map w2o_f32(o2w).  Surfaces and
         materials come from the world positions (the FP32 transform of the rest positions)."""
-        self = cls(world_positions, indices, tri_material, materials, use_bvh=False)
-        self.rest = cls(rest_positions, indices, tri_material, materials, use_bvh=False)
+        self = cls(world_positions, indices, tri_material, materials, use_bvh=False, watertight=watertight)
+        self.rest = cls(rest_positions, indices, tri_material, materials, use_bvh=False, watertight=watertight)
         self.tri_range = np.ascontiguousarray(tri_range, np.uint32).reshape(-1, 2)
         self.w2o = w2o_f32(o2w)
         self.inst = lib().or_inst_create(C.byref(self.rest.s), self.tri_range.shape[0], _p(self.tri_range),
@@ -164,7 +168,7 @@ class OracleScene:
 
     def set_positions(self, positions):
         """Replace vertex positions (same topology) and rebuild the oracle BVH."""
-        self.__init__(positions, self.idx, self.tri_mat, self.mats, self.bvh is not None)
+        self.__init__(positions, self.idx, self.tri_mat, self.mats, self.bvh is not None, self.watertight)
 
     def __del__(self):
         if getattr(self, "inst", None):
