@@ -118,11 +118,26 @@ int rc_scene_destroy(rc_ctx* ctx, rc_scene* scene);
  * holds) and leaves of at most `max_leaf` (1..4, default 4) triangles.  Replaces any previous
  * BVH.  Synchronous with respect to the host (works on the context stream and waits for it). */
 enum { RC_BUILD_HOST_SAH = 0u, RC_BUILD_DEVICE_LBVH = 1u, RC_BUILD_TWO_LEVEL = 2u };
+/* flags: RC_BUILD_WATERTIGHT makes every ray/triangle test of the scene the watertight test
+ * of Woop, Benthin and Wald (JCGT 2013) instead of Moller-Trumbore: vertices relative to the
+ * ray origin, sheared with kz = axis of the largest |d| (first on ties), kx and ky the next
+ * axes cyclically (swapped when d[kz] < 0), Sx = d[kx]/d[kz], Sy = d[ky]/d[kz], Sz = 1/d[kz]
+ * (FP32, correctly rounded), X' = X[kx] - Sx X[kz], Y' = X[ky] - Sy X[kz]; edge functions
+ * U = C'x B'y - C'y B'x, V = A'x C'y - A'y C'x, W = B'x A'y - B'y A'x (each product rounded,
+ * then the difference; all three recomputed in FP64 and rounded to FP32 when one is zero);
+ * a crossing needs U, V, W of one sign (zeros allowed, not all); det = (U + V) + W != 0,
+ * T = (U Sz A[kz] + V Sz B[kz]) + W Sz C[kz] (products rounded, sums left to right),
+ * t = T rcp(det), u = V rcp(det), v = W rcp(det) with the hardware reciprocal, hit when
+ * t > 0 and within the ray's range.  Rays aimed at a shared edge or vertex of a mesh then
+ * never pass between its triangles.  Triangles are stored as raw vertices; batched
+ * rendering (rc_render_batch) does not support such scenes (RC_ERR_UNSUPPORTED). */
+enum { RC_BUILD_WATERTIGHT = 1u };
 typedef struct rc_build_opts {
     uint32_t bins;
     uint32_t max_leaf;
     float node_cost;
     uint32_t method;
+    uint32_t flags;
 } rc_build_opts;
 int rc_bvh_build(rc_ctx* ctx, rc_scene* scene, const rc_build_opts* opts);
 

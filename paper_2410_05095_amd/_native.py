@@ -37,7 +37,8 @@ class RcSceneDesc(C.Structure):
 
 
 class RcBuildOpts(C.Structure):
-    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("node_cost", C.c_float), ("method", C.c_uint32)]
+    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("node_cost", C.c_float), ("method", C.c_uint32),
+                ("flags", C.c_uint32)]
 
 
 class RcBvhStats(C.Structure):
@@ -404,11 +405,13 @@ class Scene:
             pass
 
     def build(self, bins: int = 32, max_leaf: int = 4, node_cost: float = 4.0, device: bool = False,
-              two_level: bool = False):
+              two_level: bool = False, watertight: bool = False):
         """Host binned-SAH build; device=True: the GPU LBVH build (RC_BUILD_DEVICE_LBVH); two_level=True: one
-        GPU-built tree per body under a top level over the bodies (RC_BUILD_TWO_LEVEL)."""
+        GPU-built tree per body under a top level over the bodies (RC_BUILD_TWO_LEVEL); watertight=True: the
+        scene's ray/triangle tests use the watertight test (RC_BUILD_WATERTIGHT)."""
         self.ctx._sync_stream()
-        opts = RcBuildOpts(bins, max_leaf, node_cost, 2 if two_level else (1 if device else 0))
+        opts = RcBuildOpts(bins, max_leaf, node_cost, 2 if two_level else (1 if device else 0),
+                           1 if watertight else 0)
         check(lib().rc_bvh_build(self.ctx.h, self.h, C.byref(opts)), "rc_bvh_build")
         return self
 

@@ -38,8 +38,10 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, DevCamera cam, DevLi
 }
 
 // slot i of the leaf order: (v0, id), (v1 - v0, 0), (v2 - v0, 0)
+// Triangle records in leaf order: (v0, id), then the FP32 edges (v1 - v0), (v2 - v0) for Moller-Trumbore, or
+// the vertices v1, v2 themselves for the watertight test (raw), whose shared edges must see identical values.
 __global__ __launch_bounds__(256) void k_pack(const float* pos, const uint32_t* idx, const uint32_t* order,
-                                              uint32_t n, float4* tris)
+                                              uint32_t n, uint32_t raw, float4* tris)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -49,8 +51,13 @@ __global__ __launch_bounds__(256) void k_pack(const float* pos, const uint32_t* 
     const float* b = pos + 3 * (size_t)ix[1];
     const float* c = pos + 3 * (size_t)ix[2];
     tris[3 * (size_t)i + 0] = make_float4(a[0], a[1], a[2], __uint_as_float(t));
-    tris[3 * (size_t)i + 1] = make_float4(b[0] - a[0], b[1] - a[1], b[2] - a[2], 0.0f);
-    tris[3 * (size_t)i + 2] = make_float4(c[0] - a[0], c[1] - a[1], c[2] - a[2], 0.0f);
+    if (raw) {
+        tris[3 * (size_t)i + 1] = make_float4(b[0], b[1], b[2], 0.0f);
+        tris[3 * (size_t)i + 2] = make_float4(c[0], c[1], c[2], 0.0f);
+    } else {
+        tris[3 * (size_t)i + 1] = make_float4(b[0] - a[0], b[1] - a[1], b[2] - a[2], 0.0f);
+        tris[3 * (size_t)i + 2] = make_float4(c[0] - a[0], c[1] - a[1], c[2] - a[2], 0.0f);
+    }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, uint32_t n)
@@ -192,10 +199,10 @@ void rc_launch_pack_features(const DevScene& sc, const DevCamera& cam, const uin
 }
 
 void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris, float4* tris,
-                    hipStream_t st)
+                    bool raw, hipStream_t st)
 {
     if (n_tris == 0) return;
-    hipLaunchKernelGGL(k_pack, dim3(blocks(n_tris, 256)), dim3(256), 0, st, pos, idx, order, n_tris, tris);
+    hipLaunchKernelGGL(k_pack, dim3(blocks(n_tris, 256)), dim3(256), 0, st, pos, idx, order, n_tris, raw ? 1u : 0u, tris);
 }
 
 void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st)

@@ -49,7 +49,7 @@ inline uint32_t claim_size(uint64_t n_work, int grid, uint32_t per_wave, uint32_
     return (uint32_t)std::min<uint64_t>(hi, std::max<uint64_t>(lo, c));
 }
 
-template <int MODE, bool TWO>
+template <int MODE, bool TWO, bool WT>
 __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
 {
     constexpr bool ANY = MODE != MODE_PRIMARY;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
         // ---- traversal: node phase then leaf phase for all busy lanes, until enough lanes are idle
         for (;;) {
             uint32_t occluded = 0u;
-            trav_advance<TWO>(sc, ray, ts, st, state == 1, ANY, occluded, node_visits, tri_tests, twp);
+            trav_advance<TWO, WT>(sc, ray, ts, st, state == 1, ANY, occluded, node_visits, tri_tests, twp);
             if (state == 1 && ts.cur == RC_STACK_EMPTY) {
                 if (!end_ray(occluded != 0u)) state = 0;
             }
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
 // together: its lanes start from the same point towards nearby targets and mostly fetch the same
 // nodes.  A wave claims 64 ray slots at a time, advances them to completion, and adds the visible
 // count of each pixel segment (ballot + popcount) to a per-pixel counter.
-template <bool TWO>
+template <bool TWO, bool WT>
 __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* counts)
 {
     const int tid = threadIdx.x;
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* cou
         }
         uint32_t occluded = 0u;
         while (__ballot(busy && ts.cur != RC_STACK_EMPTY) != 0)
-            trav_advance<TWO>(sc, ray, ts, st, busy, true, occluded, node_visits, tri_tests, twp);
+            trav_advance<TWO, WT>(sc, ray, ts, st, busy, true, occluded, node_visits, tri_tests, twp);
         const uint64_t vis = __ballot(busy && occluded == 0u);
         if (in_image && (lane == 0 || k == 0)) {
             uint32_t end = (uint32_t)min<uint64_t>(64, lane + (N - k));
@@ -326,7 +326,7 @@ __device__ inline void wave_node_keys(const rc_v4f& lx, const rc_v4f& hx, const 
 // Two-level structures: at a top-level leaf every lane maps its ray into the instance (rc_map_ray), the
 // wave pushes an end marker and descends into the instance's tree; popping the marker restores the world
 // rays (and the wave's octant).
-template <bool TWO>
+template <bool TWO, bool WT>
 __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
 {
     const uint32_t lane = __lane_id();
@@ -360,11 +360,7 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
                 busy = rc_shadow_ray(P.L.point[0], P.L.rect, P.nL, true, px, k, P.L.area_stream, P.cam.seed,
                                      P.cam.frame, os, nf, ray);
                 if (busy) {
-#pragma unroll
-                    for (int a3 = 0; a3 < 3; ++a3) {
-                        float dd = fabsf(ray.d[a3]) < 1e-20f ? copysignf(1e-20f, ray.d[a3]) : ray.d[a3];
-                        ray.inv[a3] = 1.0f / dd;
-                    }
+                    rc_ray_inv(ray);
                     ++rays_cast;
                 }
             }
@@ -455,7 +451,8 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
                     if (busy && !occ) {
                         ++tri_tests;
                         float t, u, v;
-                        bool hit = rc_mt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
+                        bool hit = WT ? rc_wt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v)
+                                      : rc_mt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
                         occ = hit && t < 1.0f;
                     }
                 }
@@ -490,6 +487,7 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
 // A popped entry is skipped when that bound exceeds the largest closest-hit distance of the wave (with a
 // relative margin of 1e-5 that covers the FP32 rounding of the slab tests and of |d| = 1).  Results equal
 // the per-lane traversal's: extra triangle tests can only report true crossings.
+template <bool WT>
 __global__ __launch_bounds__(BLOCK) void k_primary_wave(KParams P)
 {
     const uint32_t lane = __lane_id();
@@ -522,11 +520,7 @@ __global__ __launch_bounds__(BLOCK) void k_primary_wave(KParams P)
             best_t = INFINITY;
             ++rays_cast;
         }
-#pragma unroll
-        for (int a3 = 0; a3 < 3; ++a3) {
-            float dd = fabsf(ray.d[a3]) < 1e-20f ? copysignf(1e-20f, ray.d[a3]) : ray.d[a3];
-            ray.inv[a3] = 1.0f / dd;
-        }
+        rc_ray_inv(ray);
         float wmax = INFINITY;                                    // largest closest-hit distance of the wave
         uint32_t cur = __ballot(valid) != 0 ? 0u : RC_STACK_EMPTY;
         int sp = 0;
@@ -611,7 +605,8 @@ __global__ __launch_bounds__(BLOCK) void k_primary_wave(KParams P)
                     if (valid) {
                         ++tri_tests;
                         float t, u, v;
-                        bool hit = rc_mt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
+                        bool hit = WT ? rc_wt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v)
+                                      : rc_mt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
                         const uint32_t id = __float_as_uint(A.w);
                         if (hit && (t < best_t || (t == best_t && id < best_id))) {
                             best_t = t; best_u = u; best_v = v; best_id = id;
@@ -654,13 +649,31 @@ int occupancy_grid(int device)
 {
     int n_cu = 0, blocks = 0;
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_trace<MODE, false>), BLOCK,
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_trace<MODE, false, false>), BLOCK,
                                                  lds_bytes<MODE>());
     if (blocks < 1) blocks = 1;
     return n_cu * blocks;
 }
 
 }  // namespace
+
+// Launch the instance of KERNEL (written with RC_TWO and RC_WT in its template arguments) that matches the
+// scene: flat or two-level structure, Moller-Trumbore or watertight triangle test (`two`, `wt` in scope).
+#define RC_LAUNCH_ONE(TWO_, WT_, KERNEL, ...)                   \
+    do {                                                         \
+        constexpr bool RC_TWO = TWO_, RC_WT = WT_;               \
+        hipLaunchKernelGGL(KERNEL, __VA_ARGS__);                 \
+    } while (0)
+#define RC_LAUNCH_TW(KERNEL, ...)                                                  \
+    do {                                                                           \
+        if (two) {                                                                 \
+            if (wt) RC_LAUNCH_ONE(true, true, KERNEL, __VA_ARGS__);                \
+            else RC_LAUNCH_ONE(true, false, KERNEL, __VA_ARGS__);                  \
+        } else {                                                                   \
+            if (wt) RC_LAUNCH_ONE(false, true, KERNEL, __VA_ARGS__);               \
+            else RC_LAUNCH_ONE(false, false, KERNEL, __VA_ARGS__);                 \
+        }                                                                          \
+    } while (0)
 
 int rc_trace_grid(int device)
 {
@@ -669,11 +682,11 @@ int rc_trace_grid(int device)
     int c = occupancy_grid<MODE_RECT>(device);
     int d = 0, n_cu = 0;
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, reinterpret_cast<const void*>(&k_rect_packets<false>), BLOCK,
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, reinterpret_cast<const void*>(&k_rect_packets<false, false>), BLOCK,
                                                  TravStack<SL, BLOCK, false>::lds_bytes());
     int e = 0, f = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave<false>), BLOCK, 0);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, reinterpret_cast<const void*>(&k_primary_wave), BLOCK, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave<false, false>), BLOCK, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, reinterpret_cast<const void*>(&k_primary_wave<false>), BLOCK, 0);
     e = std::max(e, f);
     return std::max(std::max(std::max(a, d * n_cu), std::max(b, c)), e * n_cu);
 }
@@ -691,17 +704,16 @@ void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, co
     // the wave-uniform traversal pays off with 2x2 supersampling (a wave holds 4 samples of each of 16
     // neighbouring pixels); with one sample per pixel, 8x8-pixel tiles diverge more and per-lane is faster
     // (two-level structures always use the per-lane kernel for camera rays)
-    const bool two = sc.inst != nullptr;
+    const bool two = sc.inst != nullptr, wt = sc.watertight != 0u;
     if (sc.max_stack <= 128 && !per_lane && cam.ssaa > 1 && !two) {
         P.claim = claim_size((P.n_items + 63) / 64, grid, 64, 1, 4);
-        hipLaunchKernelGGL(k_primary_wave, dim3(grid), dim3(BLOCK), 0, st, P);
+        if (wt)
+            hipLaunchKernelGGL(k_primary_wave<true>, dim3(grid), dim3(BLOCK), 0, st, P);
+        else
+            hipLaunchKernelGGL(k_primary_wave<false>, dim3(grid), dim3(BLOCK), 0, st, P);
     } else {
         P.claim = claim_size(P.n_items, grid, 16, 32, 128);
-        if (two)
-            hipLaunchKernelGGL((k_trace<MODE_PRIMARY, true>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_PRIMARY>(), st, P);
-        else
-            hipLaunchKernelGGL((k_trace<MODE_PRIMARY, false>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_PRIMARY>(), st,
-                               P);
+        RC_LAUNCH_TW((k_trace<MODE_PRIMARY, RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_PRIMARY>(), st, P);
     }
 }
 
@@ -718,14 +730,11 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     P.vis = visibility;
     P.w = w;
     P.n_items = rc_n_items(cam.width, cam.height, cam.ssaa);
-    const bool two = sc.inst != nullptr;
+    const bool two = sc.inst != nullptr, wt = sc.watertight != 0u;
     if (L.n_point > 0) {
         P.slot = 1;
         P.claim = claim_size(P.n_items, grid, 16, 32, 128);
-        if (two)
-            hipLaunchKernelGGL((k_trace<MODE_POINT, true>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
-        else
-            hipLaunchKernelGGL((k_trace<MODE_POINT, false>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
+        RC_LAUNCH_TW((k_trace<MODE_POINT, RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
     }
     if (L.has_rect) {
         // unit normal of the emitting side, from FP64 and rounded once
@@ -742,16 +751,10 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         if (sc.max_stack <= 128 && !per_lane_rect && L.area_samples >= 64) {
             hipLaunchKernelGGL(k_shadow_setup, dim3((n_pix + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_pix,
                                setup);
-            if (two)
-                hipLaunchKernelGGL(k_rect_wave<true>, dim3(grid), dim3(BLOCK), 0, st, P, counts, (const float4*)setup);
-            else
-                hipLaunchKernelGGL(k_rect_wave<false>, dim3(grid), dim3(BLOCK), 0, st, P, counts, (const float4*)setup);
+            RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), 0, st, P, counts, (const float4*)setup);
         } else {
             const size_t lds = TravStack<SL, BLOCK, false>::lds_bytes();
-            if (two)
-                hipLaunchKernelGGL(k_rect_packets<true>, dim3(grid), dim3(BLOCK), lds, st, P, counts);
-            else
-                hipLaunchKernelGGL(k_rect_packets<false>, dim3(grid), dim3(BLOCK), lds, st, P, counts);
+            RC_LAUNCH_TW((k_rect_packets<RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), lds, st, P, counts);
         }
         hipLaunchKernelGGL(k_rect_finish, dim3((n_pix + 255) / 256), dim3(256), 0, st, counts, n_pix,
                            (uint32_t)L.area_samples, visibility);

@@ -109,6 +109,7 @@ DevScene dev_scene(const rc_scene* s)
     d.scale = s->scale;
     d.inst = s->two_level ? s->d_inst : nullptr;
     d.tlas_root = s->blas_nodes;
+    d.watertight = s->watertight ? 1u : 0u;
     return d;
 }
 
@@ -321,7 +322,7 @@ static int build_device(rc_ctx* c, rc_scene* s, uint32_t max_leaf)
                                        s->d_order, hb.level_start, c->stream);
     if (e != hipSuccess) { free_bvh(s); return hip_status(e); }
     s->d_nodes = d_nodes;
-    rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, c->stream);
+    rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, s->watertight, c->stream);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) { free_bvh(s); return RC_ERR_HIP; }
     s->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     hb.nodes.resize(n_nodes);
@@ -395,7 +396,7 @@ static int build_two_level(rc_ctx* c, rc_scene* s, uint32_t max_leaf)
     if (st != RC_OK) { free_bvh(s); return st; }
     s->blas_nodes = n_blas;
     s->blas_depth = (uint32_t)hb.level_start.size() - 1;
-    rc_launch_pack(s->d_rest, s->d_idx, s->d_order, s->nt, s->d_tris, c->stream);
+    rc_launch_pack(s->d_rest, s->d_idx, s->d_order, s->nt, s->d_tris, s->watertight, c->stream);
     if (hipGetLastError() != hipSuccess ||
         rc_tlas_build(s->tlas, s->d_o2w, s->d_nodes, n_blas, s->d_inst, RC_TLAS_MAX_LEVELS, c->d_counters + 8,
                       c->stream) != hipSuccess ||
@@ -445,9 +446,10 @@ int rc_bvh_build(rc_ctx* c, rc_scene* s, const rc_build_opts* o)
     float node_cost = o && o->node_cost != 0.0f ? o->node_cost : 4.0f;
     const uint32_t method = o ? o->method : RC_BUILD_HOST_SAH;
     if (bins < 2 || bins > 256 || max_leaf < 1 || max_leaf > 4 || !(node_cost > 0.0f && node_cost <= 64.0f) ||
-        method > RC_BUILD_TWO_LEVEL)
+        method > RC_BUILD_TWO_LEVEL || (o && (o->flags & ~(uint32_t)RC_BUILD_WATERTIGHT)))
         return RC_ERR_INVALID_ARG;
     RC_HIP(hipSetDevice(c->device));
+    s->watertight = o && (o->flags & RC_BUILD_WATERTIGHT);
     if (method == RC_BUILD_DEVICE_LBVH) return build_device(c, s, max_leaf);
     if (method == RC_BUILD_TWO_LEVEL) return build_two_level(c, s, max_leaf);
     if (s->host_pos_stale) {
@@ -469,7 +471,7 @@ int rc_bvh_build(rc_ctx* c, rc_scene* s, const rc_build_opts* o)
     if (st == RC_OK && hipMemcpyAsync(s->d_order, hb.tri_order.data(), hb.tri_order.size() * 4,
                                       hipMemcpyHostToDevice, c->stream) != hipSuccess) st = RC_ERR_HIP;
     if (st != RC_OK) { free_bvh(s); return st; }
-    rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, c->stream);
+    rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, s->watertight, c->stream);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) { free_bvh(s); return RC_ERR_HIP; }
     s->hb = std::move(hb);
     s->built = true;
@@ -495,7 +497,7 @@ int rc_bvh_refit(rc_ctx* c, rc_scene* s)
     if (!s->built) return RC_ERR_NOT_BUILT;
     RC_HIP(hipSetDevice(c->device));
     if (s->two_level) return rc_tlas_rebuild(c, s, nullptr);
-    rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, c->stream);
+    rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, s->watertight, c->stream);
     const auto& ls = s->hb.level_start;
     for (int lv = (int)s->hb.depth - 1; lv >= 0; --lv)
         rc_launch_refit_level(s->d_nodes, s->d_pos, s->d_idx, s->d_order, ls[lv], ls[lv + 1] - ls[lv], c->stream);
@@ -822,7 +824,7 @@ int plan_batch(rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views,
     for (uint32_t i = 0; i < n_scenes; ++i) {
         if (!scenes[i]) return RC_ERR_INVALID_ARG;
         if (!scenes[i]->built) return RC_ERR_NOT_BUILT;
-        if (scenes[i]->two_level) return RC_ERR_UNSUPPORTED;
+        if (scenes[i]->two_level || scenes[i]->watertight) return RC_ERR_UNSUPPORTED;
         bp.scenes.push_back(dev_scene(scenes[i]));
         bp.max_stack = std::max(bp.max_stack, scenes[i]->hb.max_stack);
     }

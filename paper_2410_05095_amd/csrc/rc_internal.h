@@ -52,6 +52,7 @@ struct DevScene {
     float scale;              // max |coordinate| of the scene (for diagnostics)
     const DevInst* inst;      // two-level structures: instances (NULL for a flat BVH)
     uint32_t tlas_root;       // two-level structures: root node of the top level
+    uint32_t watertight;      // triangles packed as (v0, v1, v2) and tested watertight (else (v0, e1, e2), MT)
 };
 
 struct DevCamera {
@@ -175,7 +176,7 @@ void rc_launch_camera_rays(const DevCamera& cam, float* o, float* d, uint32_t n,
 void rc_launch_pack_features(const DevScene& sc, const DevCamera& cam, const uint4* gbuf, const float* vis,
                              float inv_log_norm, uint16_t* feat, hipStream_t st);
 void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris,
-                    float4* tris, hipStream_t st);
+                    float4* tris, bool raw, hipStream_t st);
 void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st);
 void rc_launch_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, float* o2w, hipStream_t st);
 void rc_launch_transform(const float* rest, float* pos, const uint32_t* body_vrange, const float* xf,

@@ -58,6 +58,7 @@ struct rc_scene {
     // is node b, over rest positions), top level from node blas_nodes on, rebuilt from the bodies' maps
     float* d_o2w = nullptr;   // per body [R | t], row-major 3x4 (identity until the body is moved)
     bool two_level = false;
+    bool watertight = false;  // triangle records (v0, v1, v2) and the watertight test (RC_BUILD_WATERTIGHT)
     DevInst* d_inst = nullptr;
     uint32_t blas_nodes = 0, blas_depth = 0;
     TlasWork tlas;

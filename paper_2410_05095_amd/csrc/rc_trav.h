@@ -13,7 +13,11 @@
 
 struct TravRay {
     float o[3], d[3], inv[3];
+    float sx, sy, sz;         // watertight test: shear constants (set with inv by rc_ray_inv)
+    uint32_t kx, ky, kz;      // watertight test: axes
 };
+
+__device__ inline float rc_axis(const float v[3], uint32_t k) { return k == 0u ? v[0] : (k == 1u ? v[1] : v[2]); }
 
 struct TravState {
     uint32_t cur;       // child word being processed (node index or leaf), or RC_STACK_EMPTY
@@ -30,6 +34,10 @@ struct TravWorld {
     uint32_t in_blas;
 };
 
+// Per-ray constants of the traversal: the clamped reciprocals of the slab tests and, for the watertight
+// triangle test, the axis kz of the largest |d| (first on ties), kx and ky the next axes cyclically (swapped
+// when d[kz] < 0), Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1 / d[kz] (correctly rounded).  Kernels that
+// test triangles with Moller-Trumbore never read the shear constants, so their computation is dropped.
 __device__ inline void rc_ray_inv(TravRay& r)
 {
 #pragma unroll
@@ -37,6 +45,17 @@ __device__ inline void rc_ray_inv(TravRay& r)
         float dd = fabsf(r.d[a]) < 1e-20f ? copysignf(1e-20f, r.d[a]) : r.d[a];
         r.inv[a] = 1.0f / dd;
     }
+    uint32_t kz = 0u;
+    if (fabsf(r.d[1]) > fabsf(r.d[0])) kz = 1u;
+    if (fabsf(r.d[2]) > fabsf(rc_axis(r.d, kz))) kz = 2u;
+    uint32_t kx = kz == 2u ? 0u : kz + 1u;
+    uint32_t ky = kx == 2u ? 0u : kx + 1u;
+    const float dz = rc_axis(r.d, kz);
+    if (dz < 0.0f) { const uint32_t t = kx; kx = ky; ky = t; }
+    r.kx = kx; r.ky = ky; r.kz = kz;
+    r.sx = rc_axis(r.d, kx) / dz;
+    r.sy = rc_axis(r.d, ky) / dz;
+    r.sz = 1.0f / dz;
 }
 
 // The world ray (o, d) mapped into an instance by its world-to-object map W = [M | m] (row-major 3x4):
@@ -235,9 +254,63 @@ __device__ inline bool rc_mt(const TravRay& r, float ax, float ay, float az, flo
     return u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f;
 }
 
-// Test the triangles of the leaf s.cur (Moller-Trumbore in FP32), then pop; an any-hit ray ends at its
+// Watertight ray/triangle test (Woop, Benthin and Wald, JCGT 2013) in FP32 on a triangle given by its three
+// vertices: vertices relative to the origin, sheared so the ray runs along +z, 2D edge functions (recomputed
+// in FP64 when one is exactly zero, so shared edges are decided consistently), a crossing when all three have
+// one sign; det = (U + V) + W, T = (U Az + V Bz) + W Cz, t = T rcp(det), u = V rcp(det), v = W rcp(det).
+// Returns whether the ray's line crosses the triangle at t > 0.
+__device__ inline bool rc_wt(const TravRay& r, float ax, float ay, float az, float bx, float by, float bz, float cx,
+                             float cy, float cz, float& t, float& u, float& v)
+{
+    const float A[3] = {ax - r.o[0], ay - r.o[1], az - r.o[2]};
+    const float B[3] = {bx - r.o[0], by - r.o[1], bz - r.o[2]};
+    const float C[3] = {cx - r.o[0], cy - r.o[1], cz - r.o[2]};
+    const float Akz = rc_axis(A, r.kz), Bkz = rc_axis(B, r.kz), Ckz = rc_axis(C, r.kz);
+    float p, q;
+    p = r.sx * Akz; const float Ax = rc_axis(A, r.kx) - p;
+    p = r.sy * Akz; const float Ay = rc_axis(A, r.ky) - p;
+    p = r.sx * Bkz; const float Bx = rc_axis(B, r.kx) - p;
+    p = r.sy * Bkz; const float By = rc_axis(B, r.ky) - p;
+    p = r.sx * Ckz; const float Cx = rc_axis(C, r.kx) - p;
+    p = r.sy * Ckz; const float Cy = rc_axis(C, r.ky) - p;
+    p = Cx * By; q = Cy * Bx; float U = p - q;
+    p = Ax * Cy; q = Ay * Cx; float V = p - q;
+    p = Bx * Ay; q = By * Ax; float W = p - q;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    float det = U + V;
+    det = det + W;
+    if (det == 0.0f) return false;
+    const float Az = r.sz * Akz, Bz = r.sz * Bkz, Cz = r.sz * Ckz;
+    p = U * Az;
+    q = V * Bz;
+    float T = p + q;
+    p = W * Cz;
+    T = T + p;
+    const float rcp = __builtin_amdgcn_rcpf(det);
+    t = T * rcp;
+    u = V * rcp;
+    v = W * rcp;
+    return t > 0.0f;
+}
+
+// The triangle test of the scene: Moller-Trumbore on (v0, e1, e2) records, or the watertight test on
+// (v0, v1, v2) records.
+template <bool WT>
+__device__ inline bool rc_tri(const TravRay& r, const float4& A, const float4& B, const float4& C, float& t, float& u,
+                              float& v)
+{
+    if (WT) return rc_wt(r, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
+    return rc_mt(r, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
+}
+
+// Test the triangles of the leaf s.cur (FP32, the scene's triangle test), then pop; an any-hit ray ends at its
 // first hit (occluded = true, s.cur = RC_STACK_EMPTY).
-template <bool TWO = false, class Stack>
+template <bool TWO = false, bool WT = false, class Stack>
 __device__ inline void trav_test_leaf(const DevScene& sc, TravRay& r, TravState& s, Stack& st, bool any,
                                       uint32_t& occluded, uint32_t& tri_tests, TravWorld* w = nullptr)
 {
@@ -256,7 +329,7 @@ __device__ inline void trav_test_leaf(const DevScene& sc, TravRay& r, TravState&
         const float4* tp = sc.tris + 3 * (size_t)(first + i);
         float4 A = tp[0], B = tp[1], C = tp[2];
         float t, u, v;
-        bool hit = rc_mt(r, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
+        bool hit = rc_tri<WT>(r, A, B, C, t, u, v);
         if (any) {
             if (hit && t < 1.0f) { occluded = 1u; break; }
         } else {
@@ -273,7 +346,7 @@ __device__ inline void trav_test_leaf(const DevScene& sc, TravRay& r, TravState&
 // none does, then all lanes standing at a leaf test leaves until none does.  A lane's own sequence of
 // visits is the same as visiting one node or leaf at a time, whatever the other lanes do; only the
 // grouping of the work into SIMD steps changes (fewer steps that execute both code paths).
-template <bool TWO = false, class Stack>
+template <bool TWO = false, bool WT = false, class Stack>
 __device__ inline void trav_advance(const DevScene& sc, TravRay& r, TravState& s, Stack& st, bool busy,
                                     bool any, uint32_t& occluded, uint32_t& node_visits, uint32_t& tri_tests,
                                     TravWorld* w = nullptr)
@@ -289,7 +362,7 @@ __device__ inline void trav_advance(const DevScene& sc, TravRay& r, TravState& s
     for (;;) {
         bool leaf = busy && s.cur != RC_STACK_EMPTY && rc_is_leaf(s.cur);
         if (__ballot(leaf) == 0) break;
-        if (leaf) trav_test_leaf<TWO>(sc, r, s, st, any, occluded, tri_tests, w);
+        if (leaf) trav_test_leaf<TWO, WT>(sc, r, s, st, any, occluded, tri_tests, w);
     }
 }
 
