@@ -72,6 +72,9 @@ int rc_get_last_error(rc_ctx* ctx);
  *                 [0.01,1] (GGX alpha = r^2), metallic in [0,1] (glTF metallic-roughness)
  *  body_vertex_range  n_bodies x 2 uint32 (first vertex, count): the rigid bodies that
  *                 rc_scene_set_transforms may move (may be NULL when n_bodies = 0).
+ *  normals        NULL, or n_vertices x 3 float vertex normals (finite, not zero; need not
+ *                 be unit): the shading normal of a hit is then their barycentric
+ *                 interpolation (see rc_render); moved bodies rotate them with R.
  * Zero-area triangles are accepted and never hit.  Errors: RC_ERR_INVALID_ARG,
  * RC_ERR_INVALID_VALUE, RC_ERR_OUT_OF_MEMORY. */
 typedef struct rc_scene_desc {
@@ -84,6 +87,7 @@ typedef struct rc_scene_desc {
     uint32_t n_materials;
     const uint32_t* body_vertex_range;
     uint32_t n_bodies;
+    const float* normals;
 } rc_scene_desc;
 
 int rc_scene_create(rc_ctx* ctx, const rc_scene_desc* desc, rc_scene** out);
@@ -142,8 +146,10 @@ typedef struct rc_build_opts {
 int rc_bvh_build(rc_ctx* ctx, rc_scene* scene, const rc_build_opts* opts);
 
 /* Rigid motion of bodies: for i < n, body d_body_ids[i] gets vertices
- * x' = R x_rest + t with d_xforms[12 i ..] = row-major [R | t] (3x4 float), where
- * x_rest are the positions given at creation, and [R | t] becomes the body's current map
+ * x' = R x_rest + t with d_xforms[12 i ..] = row-major [R | t] (3x4 float), each component
+ * as ((R_k0 x + R_k1 y) + R_k2 z) + t_k in FP32, where x_rest are the positions given at
+ * creation; vertex normals (if any) become ((R_k0 nx + R_k1 ny) + R_k2 nz) of the normals
+ * given at creation; and [R | t] becomes the body's current map
  * (read by two-level structures).  Bodies not listed keep their current positions and map.
  * Does not touch the BVH: call rc_bvh_refit (or rc_tlas_rebuild) before rendering. */
 int rc_scene_set_transforms(rc_ctx* ctx, rc_scene* scene, const float* d_xforms,
@@ -262,8 +268,12 @@ typedef struct rc_outputs {
  * + Cook-Torrance D F G / (4 (n.wo)(n.wi)): D = GGX with alpha = r^2, F = Schlick with
  * F0 = mix(0.04, albedo, m), G = Schlick-GGX with k = (r + 1)^2 / 8.  A rect light
  * adds its unshadowed centre-point term (intensity L_e A cos_L) times the visibility.
- * Shadow rays start at p + n 2^-18 max(1, |p|_inf) and test hits with 0 < t < 1 on
- * the segment to the light (or light sample); they are cast only when n . d > 0.
+ * In f and cos, n is the shading normal: with vertex normals n0, n1, n2 (current pose,
+ * FP32), normalize((1 - u - v) n0 + u n1 + v n2) in FP64 with the hit's barycentrics,
+ * negated when it points away from the geometric normal ng (unit e1 x e2 turned towards
+ * the viewer); without vertex normals, ng.  Shadow rays use ng: they start at
+ * p + ng 2^-18 max(1, |p|_inf) and test hits with 0 < t < 1 on the segment to the light
+ * (or light sample); they are cast only when ng . d > 0.
  * Errors: RC_ERR_INVALID_ARG, RC_ERR_NOT_BUILT, RC_ERR_UNSUPPORTED (ssaa not 1/2, or
  * ssaa 2 with a rect light), RC_ERR_HIP. */
 int rc_render(rc_ctx* ctx, rc_scene* scene, const rc_camera* cam,

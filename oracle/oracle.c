@@ -206,6 +206,7 @@ typedef struct {
     const float* mats; int64_t nmat;    /* albedo rgb, roughness, metallic */
     const struct or_inst* inst;         /* NULL, or the instances that answer hit queries (two-level) */
     int64_t flags;                      /* bit 0: the FP32 side tests triangles watertight (band model) */
+    const float* nrm;                   /* NULL, or nv x 3 vertex normals (smooth shading normal) */
 } or_scene;
 
 static void tri_verts(const or_scene* s, uint32_t t, v3* a, v3* b, v3* c)
@@ -996,9 +997,12 @@ static void brdf_v(v3 n, v3 wo, v3 wi, const float* mat, double out[3])
 
 /* ------------------------------------------------------------------------- */
 /* Surface point of a primary hit (FP64): barycentric point, two-sided       */
-/* geometric normal facing the viewer, shadow-ray origin offset.              */
+/* geometric normal facing the viewer, shadow-ray origin offset, and the     */
+/* shading normal: with vertex normals their barycentric interpolation,      */
+/* normalised and turned to the geometric normal's side; else the geometric  */
+/* normal.  Shading uses ns; the shadow origin and cast test use n.           */
 /* ------------------------------------------------------------------------- */
-typedef struct { v3 p, n, wo, os; } surface;
+typedef struct { v3 p, n, wo, os, ns; } surface;
 
 static void make_surface(const or_scene* s, uint32_t tri, double u, double v, v3 dir, surface* S)
 {
@@ -1011,6 +1015,15 @@ static void make_surface(const or_scene* s, uint32_t tri, double u, double v, v3
     S->wo = nrm(scl(dir, -1.0));
     double off = ldexp(fmax(1.0, amax(S->p)), -18);
     S->os = add(S->p, scl(S->n, off));
+    S->ns = ng;
+    if (s->nrm) {
+        const uint32_t* ix = s->idx + 3 * (int64_t)tri;
+        v3 na = from_f(s->nrm + 3 * (int64_t)ix[0]), nb = from_f(s->nrm + 3 * (int64_t)ix[1]);
+        v3 nc = from_f(s->nrm + 3 * (int64_t)ix[2]);
+        v3 ns = nrm(add(add(scl(na, 1.0 - u - v), scl(nb, u)), scl(nc, v)));
+        if (dot(ns, ng) < 0.0) ns = scl(ns, -1.0);
+        S->ns = ns;
+    }
 }
 
 /* Shadow segment from the surface origin to a target point; the FP32 side holds the origin
@@ -1076,8 +1089,8 @@ OR_API void or_render_point(const or_scene* s, const or_bvh* B, const or_camera*
             double d2 = dot(tl, tl);
             v3 wi = nrm(tl);
             double f[3];
-            brdf_v(S.n, S.wo, wi, mat, f);
-            double cosi = fmax(dot(S.n, wi), 0.0);
+            brdf_v(S.ns, S.wo, wi, mat, f);
+            double cosi = fmax(dot(S.ns, wi), 0.0);
             for (int ch = 0; ch < 3; ++ch) rgb[3 * q + ch] += f[ch] * (double)L[3 + ch] * cosi / d2;
         }
     }
@@ -1138,6 +1151,7 @@ OR_API int or_rect_vis_point(const or_scene* s, const or_bvh* B, const double p[
     S.p = mk(p[0], p[1], p[2]);
     S.n = nrm(mk(n[0], n[1], n[2]));
     S.wo = S.n;
+    S.ns = S.n;
     double off = ldexp(fmax(1.0, amax(S.p)), -18);
     S.os = add(S.p, scl(S.n, off));
     rect_geo R;
@@ -1181,9 +1195,9 @@ OR_API void or_render_rect(const or_scene* s, const or_bvh* B, const or_camera* 
         double d2 = dot(tl, tl);
         v3 wi = nrm(tl);
         double cosl = fmax(-dot(R.nL, wi), 0.0);
-        double cosi = fmax(dot(S.n, wi), 0.0);
+        double cosi = fmax(dot(S.ns, wi), 0.0);
         double f[3];
-        brdf_v(S.n, S.wo, wi, mat, f);
+        brdf_v(S.ns, S.wo, wi, mat, f);
         for (int ch = 0; ch < 3; ++ch)
             rgb_unshadowed[3 * q + ch] = f[ch] * (double)rect[9 + ch] * R.area * cosl * cosi / d2;
     }
@@ -1221,6 +1235,25 @@ OR_API void or_transform_f32(const float* rest, const uint32_t* body_vrange, con
                 float bb = M[4 * r + 1] * p[1];
                 float cc = M[4 * r + 2] * p[2];
                 out[3 * (int64_t)i + r] = ((a + bb) + cc) + M[4 * r + 3];
+            }
+        }
+    }
+}
+
+/* rest normals (nv x 3) -> out for the vertex ranges of the given bodies: n' = ((R00 x + R01 y) + R02 z), etc. */
+OR_API void or_rotate_f32(const float* rest, const uint32_t* body_vrange, const uint32_t* body_ids,
+                          const float* xf, int64_t n_bodies, float* out)
+{
+    for (int64_t b = 0; b < n_bodies; ++b) {
+        const float* M = xf + 12 * b;
+        uint32_t first = body_vrange[2 * (int64_t)body_ids[b]], count = body_vrange[2 * (int64_t)body_ids[b] + 1];
+        for (uint32_t i = first; i < first + count; ++i) {
+            const float* p = rest + 3 * (int64_t)i;
+            for (int r = 0; r < 3; ++r) {
+                float a = M[4 * r + 0] * p[0];
+                float bb = M[4 * r + 1] * p[1];
+                float cc = M[4 * r + 2] * p[2];
+                out[3 * (int64_t)i + r] = (a + bb) + cc;
             }
         }
     }

@@ -35,7 +35,7 @@ def lib():
 class OrScene(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("nv", C.c_int64), ("idx", C.c_void_p), ("nt", C.c_int64),
                 ("tri_mat", C.c_void_p), ("mats", C.c_void_p), ("nmat", C.c_int64), ("inst", C.c_void_p),
-                ("flags", C.c_int64)]
+                ("flags", C.c_int64), ("nrm", C.c_void_p)]
 
 
 class OrCamera(C.Structure):
@@ -63,6 +63,8 @@ def _declare(L):
     L.or_inst_create.restype = P
     L.or_inst_free.argtypes = [P]
     L.or_w2o_f32.argtypes = [P, C.c_int64, P]
+    L.or_rotate_f32.argtypes = [P, P, P, P, C.c_int64, P]
+    L.or_transform_f32.argtypes = [P, P, P, P, C.c_int64, P]
     L.or_any.restype = C.c_int
     L.or_brdf.argtypes = [P, P, P, P, C.c_double, C.c_double, P]
     L.or_brdf_k.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, P]
@@ -127,31 +129,38 @@ def gen_rays(cam, samples: np.ndarray):
 class OracleScene:
     """Holds the FP32 arrays of a scene and (optionally) the oracle's own BVH."""
 
-    def __init__(self, positions, indices, tri_material, materials, use_bvh: bool = True, watertight: bool = False):
+    def __init__(self, positions, indices, tri_material, materials, use_bvh: bool = True, watertight: bool = False,
+                 normals=None):
         self.pos = np.ascontiguousarray(positions, dtype=np.float32)
         self.idx = np.ascontiguousarray(indices, dtype=np.uint32)
         self.tri_mat = np.ascontiguousarray(tri_material, dtype=np.uint32)
         self.mats = np.ascontiguousarray(materials, dtype=np.float32)
         self.s = OrScene(_p(self.pos).value, self.pos.shape[0], _p(self.idx).value, self.idx.shape[0],
                          _p(self.tri_mat).value, _p(self.mats).value, self.mats.shape[0], None,
-                         1 if watertight else 0)
+                         1 if watertight else 0, None)
+        self.nrm = None if normals is None else np.ascontiguousarray(normals, dtype=np.float32)
+        if self.nrm is not None:
+            self.s.nrm = _p(self.nrm).value
         self.watertight = watertight
         self.bvh = lib().or_bvh_build(C.byref(self.s)) if use_bvh else None
         self.inst = None
 
     @classmethod
     def from_scene(cls, scene, use_bvh: bool = True, watertight: bool = False):
-        """watertight: the FP32 side tests triangles with the watertight test (its band model)."""
-        return cls(scene.positions, scene.indices, scene.tri_material, scene.materials, use_bvh, watertight)
+        """watertight: the FP32 side tests triangles with the watertight test (its band model).  The scene's
+        vertex normals, if any, give the shading normal."""
+        return cls(scene.positions, scene.indices, scene.tri_material, scene.materials, use_bvh, watertight,
+                   getattr(scene, "normals", None))
 
     @classmethod
     def two_level(cls, world_positions, rest_positions, indices, tri_material, materials, tri_range, o2w,
-                  use_bvh: bool = True, watertight: bool = False):
+                  use_bvh: bool = True, watertight: bool = False, world_normals=None):
         """A scene whose hit queries go through instances: instance i is triangles tri_range[i] =
         (first, count) of the rest-frame positions, placed by the rigid map [R | t] = o2w[i] (3x4, FP32)
         and tested in its own frame through the world-to-object map w2o_f32(o2w).  Surfaces and
         materials come from the world positions (the FP32 transform of the rest positions)."""
-        self = cls(world_positions, indices, tri_material, materials, use_bvh=False, watertight=watertight)
+        self = cls(world_positions, indices, tri_material, materials, use_bvh=False, watertight=watertight,
+                   normals=world_normals)
         self.rest = cls(rest_positions, indices, tri_material, materials, use_bvh=False, watertight=watertight)
         self.tri_range = np.ascontiguousarray(tri_range, np.uint32).reshape(-1, 2)
         self.w2o = w2o_f32(o2w)
@@ -168,7 +177,7 @@ class OracleScene:
 
     def set_positions(self, positions):
         """Replace vertex positions (same topology) and rebuild the oracle BVH."""
-        self.__init__(positions, self.idx, self.tri_mat, self.mats, self.bvh is not None, self.watertight)
+        self.__init__(positions, self.idx, self.tri_mat, self.mats, self.bvh is not None, self.watertight, self.nrm)
 
     def __del__(self):
         if getattr(self, "inst", None):
@@ -319,6 +328,17 @@ def w2o_f32(o2w) -> np.ndarray:
     x = np.ascontiguousarray(o2w, np.float32).reshape(-1, 12)
     out = np.zeros_like(x)
     lib().or_w2o_f32(_p(x), x.shape[0], _p(out))
+    return out
+
+
+def rotate_f32(rest_normals, body_vrange, body_ids, xforms) -> np.ndarray:
+    """Vertex normals of moved bodies: the FP32 rotation of the rest normals (no translation)."""
+    rest = np.ascontiguousarray(rest_normals, np.float32)
+    out = rest.copy()
+    vr = np.ascontiguousarray(body_vrange, np.uint32)
+    ids = np.ascontiguousarray(body_ids, np.uint32)
+    xf = np.ascontiguousarray(xforms, np.float32)
+    lib().or_rotate_f32(_p(rest), _p(vr), _p(ids), _p(xf), len(ids), _p(out))
     return out
 
 

@@ -33,7 +33,8 @@ F3 = C.c_float * 3
 class RcSceneDesc(C.Structure):
     _fields_ = [("positions", C.c_void_p), ("n_vertices", C.c_uint32), ("indices", C.c_void_p),
                 ("n_tris", C.c_uint32), ("tri_material", C.c_void_p), ("materials", C.c_void_p),
-                ("n_materials", C.c_uint32), ("body_vertex_range", C.c_void_p), ("n_bodies", C.c_uint32)]
+                ("n_materials", C.c_uint32), ("body_vertex_range", C.c_void_p), ("n_bodies", C.c_uint32),
+                ("normals", C.c_void_p)]
 
 
 class RcBuildOpts(C.Structure):
@@ -236,11 +237,12 @@ class Context:
     def last_error(self) -> int:
         return int(lib().rc_get_last_error(self.h))
 
-    def scene(self, positions, indices, tri_material, materials, body_vertex_range=None) -> "Scene":
-        return Scene(self, positions, indices, tri_material, materials, body_vertex_range)
+    def scene(self, positions, indices, tri_material, materials, body_vertex_range=None, normals=None) -> "Scene":
+        return Scene(self, positions, indices, tri_material, materials, body_vertex_range, normals)
 
     def scene_from(self, sc) -> "Scene":
-        return Scene(self, sc.positions, sc.indices, sc.tri_material, sc.materials, sc.body_vertex_range)
+        return Scene(self, sc.positions, sc.indices, sc.tri_material, sc.materials, sc.body_vertex_range,
+                     getattr(sc, "normals", None))
 
     def render(self, scene: "Scene", cam, lights=(), rect=None, area_samples: int = 0, area_stream: int = 0,
                timing: bool = False, sample_rgba: bool = False, out: Optional[dict] = None,
@@ -377,7 +379,8 @@ class Context:
 
 
 class Scene:
-    def __init__(self, ctx: Context, positions, indices, tri_material, materials, body_vertex_range=None):
+    def __init__(self, ctx: Context, positions, indices, tri_material, materials, body_vertex_range=None,
+                 normals=None):
         self.ctx = ctx
         self.pos = np.ascontiguousarray(positions, np.float32)
         self.idx = np.ascontiguousarray(indices, np.uint32)
@@ -385,8 +388,10 @@ class Scene:
         self.mats = np.ascontiguousarray(materials, np.float32)
         self.bvr = None if body_vertex_range is None else np.ascontiguousarray(body_vertex_range, np.uint32)
         nb = 0 if self.bvr is None else self.bvr.shape[0]
+        self.nrm = None if normals is None else np.ascontiguousarray(normals, np.float32)
         d = RcSceneDesc(_ptr(self.pos), self.pos.shape[0], _ptr(self.idx), self.idx.shape[0], _ptr(self.tm),
-                        _ptr(self.mats), self.mats.shape[0], None if nb == 0 else _ptr(self.bvr), nb)
+                        _ptr(self.mats), self.mats.shape[0], None if nb == 0 else _ptr(self.bvr), nb,
+                        None if self.nrm is None else _ptr(self.nrm))
         ctx._sync_stream()
         h = C.c_void_p()
         check(lib().rc_scene_create(ctx.h, C.byref(d), C.byref(h)), "rc_scene_create")

@@ -67,8 +67,10 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, uint32_t n)
 }
 
 // x' = ((R00 x + R01 y) + R02 z) + t0 per row, from the rest positions of body body_ids[blockIdx.y]
-__global__ __launch_bounds__(256) void k_transform(const float* rest, float* pos, const uint32_t* body_vrange,
-                                                   const float* xf, const uint32_t* body_ids)
+// vertex normals (when present) are rotated the same way, without the translation
+__global__ __launch_bounds__(256) void k_transform(const float* rest, float* pos, const float* nrm_rest, float* nrm,
+                                                   const uint32_t* body_vrange, const float* xf,
+                                                   const uint32_t* body_ids)
 {
     uint32_t b = blockIdx.y;
     uint32_t body = body_ids[b];
@@ -83,6 +85,17 @@ __global__ __launch_bounds__(256) void k_transform(const float* rest, float* pos
             float bb = M[4 * r + 1] * y;
             float cc = M[4 * r + 2] * z;
             pos[3 * (size_t)(first + i) + r] = ((a + bb) + cc) + M[4 * r + 3];
+        }
+        if (nrm) {
+            const float* q = nrm_rest + 3 * (size_t)(first + i);
+            float nx = q[0], ny = q[1], nz = q[2];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                float a = M[4 * r + 0] * nx;
+                float bb = M[4 * r + 1] * ny;
+                float cc = M[4 * r + 2] * nz;
+                nrm[3 * (size_t)(first + i) + r] = (a + bb) + cc;
+            }
         }
     }
 }
@@ -211,12 +224,14 @@ void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st)
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks(n, 256)), dim3(256), 0, st, p, value, n);
 }
 
-void rc_launch_transform(const float* rest, float* pos, const uint32_t* body_vrange, const float* xf,
-                         const uint32_t* body_ids, uint32_t n_bodies, uint32_t max_count, hipStream_t st)
+void rc_launch_transform(const float* rest, float* pos, const float* nrm_rest, float* nrm,
+                         const uint32_t* body_vrange, const float* xf, const uint32_t* body_ids, uint32_t n_bodies,
+                         uint32_t max_count, hipStream_t st)
 {
     if (n_bodies == 0 || max_count == 0) return;
     unsigned gx = std::min(blocks(max_count, 256), 64u);
-    hipLaunchKernelGGL(k_transform, dim3(gx, n_bodies), dim3(256), 0, st, rest, pos, body_vrange, xf, body_ids);
+    hipLaunchKernelGGL(k_transform, dim3(gx, n_bodies), dim3(256), 0, st, rest, pos, nrm_rest, nrm, body_vrange, xf,
+                       body_ids);
 }
 
 void rc_launch_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, float* o2w, hipStream_t st)

@@ -110,6 +110,7 @@ DevScene dev_scene(const rc_scene* s)
     d.inst = s->two_level ? s->d_inst : nullptr;
     d.tlas_root = s->blas_nodes;
     d.watertight = s->watertight ? 1u : 0u;
+    d.nrm = s->d_nrm;
     return d;
 }
 
@@ -229,6 +230,11 @@ int rc_scene_create(rc_ctx* c, const rc_scene_desc* d, rc_scene** out)
     if (d->n_bodies > 0 && !d->body_vertex_range) return RC_ERR_INVALID_ARG;
     for (uint32_t i = 0; i < d->n_vertices; ++i)
         if (!finite3(d->positions + 3 * (size_t)i)) return RC_ERR_INVALID_VALUE;
+    if (d->normals)
+        for (uint32_t i = 0; i < d->n_vertices; ++i) {
+            const float* q = d->normals + 3 * (size_t)i;
+            if (!finite3(q) || (q[0] == 0.0f && q[1] == 0.0f && q[2] == 0.0f)) return RC_ERR_INVALID_VALUE;
+        }
     for (size_t i = 0; i < 3 * (size_t)d->n_tris; ++i)
         if (d->indices[i] >= d->n_vertices) return RC_ERR_INVALID_VALUE;
     for (uint32_t t = 0; t < d->n_tris; ++t)
@@ -255,6 +261,7 @@ int rc_scene_create(rc_ctx* c, const rc_scene_desc* d, rc_scene** out)
     s->tri_mat.assign(d->tri_material, d->tri_material + s->nt);
     s->mats.assign(d->materials, d->materials + 5 * (size_t)s->nm);
     if (s->nb) s->body_vr.assign(d->body_vertex_range, d->body_vertex_range + 2 * (size_t)s->nb);
+    if (d->normals) s->nrm.assign(d->normals, d->normals + 3 * (size_t)s->nv);
     float scale = 1.0f;
     for (float x : s->pos) scale = std::max(scale, fabsf(x));
     s->scale = scale;
@@ -265,6 +272,8 @@ int rc_scene_create(rc_ctx* c, const rc_scene_desc* d, rc_scene** out)
     if (st == RC_OK && s->nb) st = dev_alloc(&s->d_rest, s->pos.size());
     if (st == RC_OK && s->nb) st = dev_alloc(&s->d_body_vr, s->body_vr.size());
     if (st == RC_OK && s->nb) st = dev_alloc(&s->d_o2w, 12 * (size_t)s->nb);
+    if (st == RC_OK && !s->nrm.empty()) st = dev_alloc(&s->d_nrm, s->nrm.size());
+    if (st == RC_OK && !s->nrm.empty() && s->nb) st = dev_alloc(&s->d_nrm_rest, s->nrm.size());
     std::vector<float> ident;
     if (s->nb) {
         ident.assign(12 * (size_t)s->nb, 0.0f);
@@ -281,6 +290,10 @@ int rc_scene_create(rc_ctx* c, const rc_scene_desc* d, rc_scene** out)
         up(s->d_rest, s->pos.data(), s->pos.size() * 4);
         up(s->d_body_vr, s->body_vr.data(), s->body_vr.size() * 4);
         up(s->d_o2w, ident.data(), ident.size() * 4);
+    }
+    if (!s->nrm.empty()) {
+        up(s->d_nrm, s->nrm.data(), s->nrm.size() * 4);
+        if (s->nb) up(s->d_nrm_rest, s->nrm.data(), s->nrm.size() * 4);
     }
     if (st == RC_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = RC_ERR_HIP;
     if (st != RC_OK) { rc_scene_destroy(c, s); return st; }
@@ -301,6 +314,8 @@ int rc_scene_destroy(rc_ctx* c, rc_scene* s)
     dev_free(s->d_mats);
     dev_free(s->d_body_vr);
     dev_free(s->d_o2w);
+    dev_free(s->d_nrm);
+    dev_free(s->d_nrm_rest);
     delete s;
     return RC_OK;
 }
@@ -484,7 +499,8 @@ int rc_scene_set_transforms(rc_ctx* c, rc_scene* s, const float* d_xforms, const
     if (n == 0) return RC_OK;
     if (!d_xforms || !d_body_ids || n > s->nb || s->nb == 0) return RC_ERR_INVALID_ARG;
     RC_HIP(hipSetDevice(c->device));
-    rc_launch_transform(s->d_rest, s->d_pos, s->d_body_vr, d_xforms, d_body_ids, n, s->max_body_verts, c->stream);
+    rc_launch_transform(s->d_rest, s->d_pos, s->d_nrm_rest, s->d_nrm, s->d_body_vr, d_xforms, d_body_ids, n,
+                        s->max_body_verts, c->stream);
     rc_launch_record_o2w(d_xforms, d_body_ids, n, s->d_o2w, c->stream);
     RC_HIP(hipGetLastError());
     s->host_pos_stale = true;

@@ -68,6 +68,7 @@ struct Surface {
     D3 p;   // hit point
     D3 n;   // unit geometric normal facing the viewer
     D3 wo;  // unit direction towards the viewer
+    D3 ns;  // unit shading normal: interpolated vertex normal on the viewer's side, or n
 };
 
 // FP64 reconstruction of a camera hit from the FP32 ray and the FP32 triangle: barycentric
@@ -96,6 +97,17 @@ __device__ inline Surface rc_surface(const DevScene& sc, const DevCamera& cam, u
     if (d3dot(ng, d) > 0.0) ng = d3scl(ng, -1.0);
     S.n = ng;
     S.wo = d3nrm(d3scl(d, -1.0));
+    S.ns = ng;
+    if (sc.nrm) {
+        const float* na = sc.nrm + 3 * (size_t)ix[0];
+        const float* nb = sc.nrm + 3 * (size_t)ix[1];
+        const float* nc = sc.nrm + 3 * (size_t)ix[2];
+        D3 ns = d3add(d3add(d3scl(d3(na[0], na[1], na[2]), 1.0 - u - v), d3scl(d3(nb[0], nb[1], nb[2]), u)),
+                      d3scl(d3(nc[0], nc[1], nc[2]), v));
+        ns = d3nrm(ns);
+        if (d3dot(ns, ng) < 0.0) ns = d3scl(ns, -1.0);
+        S.ns = ns;
+    }
     return S;
 }
 

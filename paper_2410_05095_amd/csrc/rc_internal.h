@@ -53,6 +53,7 @@ struct DevScene {
     const DevInst* inst;      // two-level structures: instances (NULL for a flat BVH)
     uint32_t tlas_root;       // two-level structures: root node of the top level
     uint32_t watertight;      // triangles packed as (v0, v1, v2) and tested watertight (else (v0, e1, e2), MT)
+    const float* nrm;         // n_vertices x 3 vertex normals (current pose), or NULL
 };
 
 struct DevCamera {
@@ -179,7 +180,8 @@ void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order
                     float4* tris, bool raw, hipStream_t st);
 void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st);
 void rc_launch_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, float* o2w, hipStream_t st);
-void rc_launch_transform(const float* rest, float* pos, const uint32_t* body_vrange, const float* xf,
+void rc_launch_transform(const float* rest, float* pos, const float* nrm_rest, float* nrm,
+                         const uint32_t* body_vrange, const float* xf,
                          const uint32_t* body_ids, uint32_t n_bodies, uint32_t max_count, hipStream_t st);
 void rc_launch_refit_level(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order,
                            uint32_t first, uint32_t count, hipStream_t st);

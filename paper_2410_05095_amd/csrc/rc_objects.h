@@ -40,6 +40,9 @@ struct rc_scene {
     uint32_t nv = 0, nt = 0, nm = 0, nb = 0, max_body_verts = 0;
     float* d_pos = nullptr;
     float* d_rest = nullptr;
+    std::vector<float> nrm;            // vertex normals as given (empty: none)
+    float* d_nrm = nullptr;            // current vertex normals
+    float* d_nrm_rest = nullptr;       // vertex normals at creation (when bodies can move)
     uint32_t* d_idx = nullptr;
     uint32_t* d_tri_mat = nullptr;
     float* d_mats = nullptr;

@@ -416,8 +416,8 @@ __device__ inline float4 rc_shade_sample(const DevScene& sc, const DevCamera& ca
         double d2 = d3dot(tl, tl);
         D3 wi = d3nrm(tl);
         double f[3];
-        rc_brdf(S.n, S.wo, wi, mat, f);
-        double cosi = fmax(d3dot(S.n, wi), 0.0);
+        rc_brdf(S.ns, S.wo, wi, mat, f);
+        double cosi = fmax(d3dot(S.ns, wi), 0.0);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) rgb[ch] += f[ch] * (double)L[3 + ch] * cosi / d2;
     }
@@ -431,9 +431,9 @@ __device__ inline float4 rc_shade_sample(const DevScene& sc, const DevCamera& ca
         double d2 = d3dot(tl, tl);
         D3 wi = d3nrm(tl);
         double cosl = fmax(-d3dot(nL, wi), 0.0);
-        double cosi = fmax(d3dot(S.n, wi), 0.0);
+        double cosi = fmax(d3dot(S.ns, wi), 0.0);
         double f[3];
-        rc_brdf(S.n, S.wo, wi, mat, f);
+        rc_brdf(S.ns, S.wo, wi, mat, f);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) rgb[ch] += f[ch] * (double)rect[9 + ch] * area * cosl * cosi / d2 * vis;
     }

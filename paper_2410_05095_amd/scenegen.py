@@ -254,6 +254,7 @@ class Scene:
     rect_light: Optional[RectLight]
     cameras: List[Camera]
     name: str = ""
+    normals: Optional[np.ndarray] = None   # (Nv, 3) float32 vertex normals, or None (flat shading)
 
     @property
     def n_tris(self) -> int:
@@ -299,6 +300,26 @@ class _Builder:
             cameras=cams,
             name=name,
         )
+
+
+def vertex_normals(positions: np.ndarray, indices: np.ndarray) -> np.ndarray:
+    """Area-weighted average of the faces' normals at each vertex (FP64, unit, stored FP32): smooth on
+    meshes that share vertices (spheres, tori), the face normal where faces own their vertices (boxes)."""
+    p = positions.astype(np.float64)
+    f = indices.astype(np.int64)
+    fn = np.cross(p[f[:, 1]] - p[f[:, 0]], p[f[:, 2]] - p[f[:, 0]])
+    acc = np.zeros_like(p)
+    for k in range(3):
+        np.add.at(acc, f[:, k], fn)
+    ln = np.linalg.norm(acc, axis=1, keepdims=True)
+    acc = np.where(ln > 0, acc / np.where(ln > 0, ln, 1.0), np.array([0.0, 1.0, 0.0]))
+    return np.ascontiguousarray(acc.astype(F32))
+
+
+def with_vertex_normals(scene: "Scene") -> "Scene":
+    """The scene with vertex normals computed from its current positions (smooth shading)."""
+    return dataclasses.replace(scene, normals=vertex_normals(scene.positions, scene.indices),
+                               name=scene.name + "_smooth")
 
 
 def tiny_box_scene(seed: int = 0, width: int = 128, height: int = 128) -> Scene:
