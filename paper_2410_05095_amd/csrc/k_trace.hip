@@ -294,7 +294,7 @@ typedef const __attribute__((address_space(4))) rc_v4f rc_const_v4f;
 template <bool UNIFORM_OCTANT>
 __device__ inline void wave_node_keys(const rc_v4f& lx, const rc_v4f& hx, const rc_v4f& ly, const rc_v4f& hy,
                                       const rc_v4f& lz, const rc_v4f& hz, const TravRay& ray, uint32_t oct,
-                                      bool live, uint32_t key[4])
+                                      float bound, uint32_t key[4])
 {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -312,7 +312,8 @@ __device__ inline void wave_node_keys(const rc_v4f& lx, const rc_v4f& hx, const 
                          fmaxf((nz - ray.o[2]) * ray.inv[2], 0.0f));
         float t1 = fminf(fminf((fx - ray.o[0]) * ray.inv[0], (fy - ray.o[1]) * ray.inv[1]),
                          (fz - ray.o[2]) * ray.inv[2]);
-        bool hit = live && t0 <= fminf(t1 * RC_FAR_GROW, 1.0f);
+        // bound: 1 (the segment's end) for live rays, -1 for finished ones, which then never hit (t0 >= 0)
+        bool hit = t0 <= fminf(t1 * RC_FAR_GROW, bound);
         uint64_t m = __ballot(hit);
         uint32_t k = 0x7F800000u;   // +inf: no live ray hits this child
         if (m != 0) {
@@ -414,8 +415,9 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
                 const rc_v4f lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
                 const rc_v4f chf = np[6];
                 uint32_t key[4], cw[4];
-                if (uniform_oct) wave_node_keys<true>(lx, hx, ly, hy, lz, hz, ray, oct, live, key);
-                else wave_node_keys<false>(lx, hx, ly, hy, lz, hz, ray, oct, live, key);
+                const float bound = live ? 1.0f : -1.0f;
+                if (uniform_oct) wave_node_keys<true>(lx, hx, ly, hy, lz, hz, ray, oct, bound, key);
+                else wave_node_keys<false>(lx, hx, ly, hy, lz, hz, ray, oct, bound, key);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) cw[c] = __float_as_uint(chf[c]);
                 if (live) ++node_visits;
