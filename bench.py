@@ -33,7 +33,7 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # the copy-kernel calibration), keyed by (workload, spp, hash of the traversal kernel sources); the
 # value only applies while those sources are unchanged (summaries under profiles/).
 MEASURED_TRAFFIC = {
-    ("big_7M", 64, "0a586d4eb4e3d6ca:96fd43948bc92d3c:ed4254a5d1e3e117"): 425_663_000,
+    ("big_7M", 64, "83f0ab1dea680da5:5ce1cb11be5fdbcb:9f5f62c0a697ac34"): 426_638_000,
 }
 
 
