@@ -284,43 +284,51 @@ __global__ __launch_bounds__(256) void k_shadow_setup(DevScene sc, DevCamera cam
 // tests its own ray against every box and triangle the wave visits, with the same FP32 arithmetic as
 // the per-lane traversal; a triangle that a lane's own boxes would not have led to can only report a
 // true crossing, so the occlusion result of every ray is the one the per-lane traversal finds.
-// Children are visited nearest first by the entry distance of the lowest lane that hits them; the
-// distances are non-negative, so their bit patterns order like the values and the sort runs on the
-// scalar unit.  When all live rays share a direction octant (the usual case for a small light), the
-// near/far planes are picked once per wave, also on the scalar unit.
+// Children are visited nearest first by the entry distance of the lowest lane that hits them.  The
+// distances are non-negative, so their bit patterns order like the values; the two lowest bits carry the
+// child's slot instead (children whose keys differ only there are ordered by slot), so the keys sort with
+// plain minima and maxima on the scalar unit and the child word is then taken by slot.  When all live
+// rays share a direction octant (the usual case for a small light), the near and far plane blocks of the
+// node are loaded at byte offsets picked by the octant; otherwise each lane picks its own planes.
 typedef float rc_v4f __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) rc_v4f rc_const_v4f;
+typedef const __attribute__((address_space(4))) uint32_t rc_const_u32;
 
-template <bool UNIFORM_OCTANT>
-__device__ inline void wave_node_keys(const rc_v4f& lx, const rc_v4f& hx, const rc_v4f& ly, const rc_v4f& hy,
-                                      const rc_v4f& lz, const rc_v4f& hz, const TravRay& ray, uint32_t oct,
-                                      float bound, uint32_t key[4])
+#define RC_KEY_MISS 0x7F800000u   // keys >= this: no live ray enters the child
+
+__device__ inline uint32_t wave_key(bool hit, float t0, uint32_t slot)
+{
+    const uint64_t m = __ballot(hit);
+    if (m == 0) return RC_KEY_MISS | slot;
+    const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(t0), __builtin_ctzll(m));
+    return (t & 0x7FFFFFFCu) | slot;
+}
+
+// bound: 1 (the segment's end) for live rays, -1 for finished ones, which then never hit (t0 >= 0)
+__device__ inline void wave_keys_uniform(const rc_v4f& nx, const rc_v4f& fx, const rc_v4f& ny, const rc_v4f& fy,
+                                         const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray, float bound,
+                                         uint32_t key[4])
 {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        float nx, fx, ny, fy, nz, fz;
-        if (UNIFORM_OCTANT) {
-            nx = (oct & 1u) ? hx[c] : lx[c]; fx = (oct & 1u) ? lx[c] : hx[c];
-            ny = (oct & 2u) ? hy[c] : ly[c]; fy = (oct & 2u) ? ly[c] : hy[c];
-            nz = (oct & 4u) ? hz[c] : lz[c]; fz = (oct & 4u) ? lz[c] : hz[c];
-        } else {
-            nx = ray.inv[0] >= 0.0f ? lx[c] : hx[c]; fx = ray.inv[0] >= 0.0f ? hx[c] : lx[c];
-            ny = ray.inv[1] >= 0.0f ? ly[c] : hy[c]; fy = ray.inv[1] >= 0.0f ? hy[c] : ly[c];
-            nz = ray.inv[2] >= 0.0f ? lz[c] : hz[c]; fz = ray.inv[2] >= 0.0f ? hz[c] : lz[c];
-        }
-        float t0 = fmaxf(fmaxf((nx - ray.o[0]) * ray.inv[0], (ny - ray.o[1]) * ray.inv[1]),
-                         fmaxf((nz - ray.o[2]) * ray.inv[2], 0.0f));
-        float t1 = fminf(fminf((fx - ray.o[0]) * ray.inv[0], (fy - ray.o[1]) * ray.inv[1]),
-                         (fz - ray.o[2]) * ray.inv[2]);
-        // bound: 1 (the segment's end) for live rays, -1 for finished ones, which then never hit (t0 >= 0)
-        bool hit = t0 <= fminf(t1 * RC_FAR_GROW, bound);
-        uint64_t m = __ballot(hit);
-        uint32_t k = 0x7F800000u;   // +inf: no live ray hits this child
-        if (m != 0) {
-            int first = __builtin_ctzll(m);
-            k = (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(t0), first) & 0x7FFFFFFFu;
-        }
-        key[c] = k;
+        float t0;
+        const bool hit = rc_slab(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], bound, t0);
+        key[c] = wave_key(hit, t0, (uint32_t)c);
+    }
+}
+
+__device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const rc_v4f& ly, const rc_v4f& hy,
+                                       const rc_v4f& lz, const rc_v4f& hz, const TravRay& ray, float bound,
+                                       uint32_t key[4])
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float nx = ray.inv[0] >= 0.0f ? lx[c] : hx[c], fx = ray.inv[0] >= 0.0f ? hx[c] : lx[c];
+        const float ny = ray.inv[1] >= 0.0f ? ly[c] : hy[c], fy = ray.inv[1] >= 0.0f ? hy[c] : ly[c];
+        const float nz = ray.inv[2] >= 0.0f ? lz[c] : hz[c], fz = ray.inv[2] >= 0.0f ? hz[c] : lz[c];
+        float t0;
+        const bool hit = rc_slab(ray, nx, ny, nz, fx, fy, fz, bound, t0);
+        key[c] = wave_key(hit, t0, (uint32_t)c);
     }
 }
 
@@ -335,8 +343,8 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
     const uint64_t N = (uint64_t)P.L.area_samples;
     const uint64_t total = (uint64_t)P.n_items * N;
     const uint64_t n_blocks = (total + 63) / 64;
-    const uint32_t KEY_MISS = 0x7F800000u;
     uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
+    const char* nodes_b = (const char*)(const void*)sc.nodes;
     const XcdQueue<RECT_CHUNK> queue(P.w.counters, P.slot, n_blocks);
     uint32_t pos = 0, pos_end = 0;   // wave-uniform range of claimed positions
     for (;;) {
@@ -367,7 +375,7 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
             }
         }
         const uint64_t busy_mask = __ballot(busy);
-        uint32_t oct = 0;
+        uint32_t oct = 0, on0 = 0, on1 = 32, on2 = 64, of0 = 16, of1 = 48, of2 = 80;
         bool uniform_oct = false;
         auto set_octant = [&]() {
             const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
@@ -375,6 +383,15 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
             oct = 0;
             if (busy_mask != 0) oct = (uint32_t)__builtin_amdgcn_readlane((int)my_oct, __builtin_ctzll(busy_mask));
             uniform_oct = __ballot(busy && my_oct != oct) == 0;
+            // byte offsets of the near- and far-plane blocks (axis a: lo at 32 a, hi at 32 a + 16)
+            on0 = (oct & 1u) ? 16u : 0u;
+            on1 = (oct & 2u) ? 48u : 32u;
+            on2 = (oct & 4u) ? 80u : 64u;
+            of0 = on0 ^ 16u;
+            of1 = on1 ^ 16u;
+            of2 = on2 ^ 16u;
+            // opaque to the compiler (no instruction): keeps node + offset in the scalar-offset form of the loads
+            asm volatile("" : "+s"(on0), "+s"(on1), "+s"(on2), "+s"(of0), "+s"(of1), "+s"(of2));
         };
         set_octant();
         float wo[3] = {ray.o[0], ray.o[1], ray.o[2]}, wd[3] = {ray.d[0], ray.d[1], ray.d[2]};   // world ray
@@ -411,29 +428,31 @@ __global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts
         while (cur != RC_STACK_EMPTY) {
             const bool live = busy && !occ;
             if (!rc_is_leaf(cur)) {
-                rc_const_v4f* np = (rc_const_v4f*)(const void*)(sc.nodes + cur);
-                const rc_v4f lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-                const rc_v4f chf = np[6];
-                uint32_t key[4], cw[4];
+                // 32-bit byte offsets into the node array (the host keeps it below 4 GiB for this kernel), so
+                // that each block load takes its offset in a scalar register
+                const uint32_t nofs = cur << 7;
+                auto blk = [&](uint32_t off) { return *(rc_const_v4f*)(const void*)(nodes_b + (uint32_t)(nofs + off)); };
+                uint32_t key[4];
                 const float bound = live ? 1.0f : -1.0f;
-                if (uniform_oct) wave_node_keys<true>(lx, hx, ly, hy, lz, hz, ray, oct, bound, key);
-                else wave_node_keys<false>(lx, hx, ly, hy, lz, hz, ray, oct, bound, key);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) cw[c] = __float_as_uint(chf[c]);
+                if (uniform_oct)
+                    wave_keys_uniform(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, bound, key);
+                else
+                    wave_keys_mixed(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, bound, key);
                 if (live) ++node_visits;
 #define RC_CS(a, b)                                                                   \
     {                                                                                 \
-        bool sw = key[b] < key[a];                                                    \
-        uint32_t ka = sw ? key[b] : key[a], kb = sw ? key[a] : key[b];                \
-        uint32_t ca = sw ? cw[b] : cw[a], cb = sw ? cw[a] : cw[b];                    \
-        key[a] = ka; key[b] = kb; cw[a] = ca; cw[b] = cb;                             \
+        const uint32_t lo = min(key[a], key[b]), hi = max(key[a], key[b]);            \
+        key[a] = lo; key[b] = hi;                                                     \
     }
                 RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
 #undef RC_CS
+                auto child = [&](uint32_t k) {
+                    return *(rc_const_u32*)(const void*)(nodes_b + (uint32_t)(nofs + 96u + ((k & 3u) << 2)));
+                };
 #pragma unroll
                 for (int c = 3; c >= 1; --c)
-                    if (key[c] < KEY_MISS) push_entry(cw[c]);
-                cur = key[0] < KEY_MISS ? cw[0] : pop_next();
+                    if (key[c] < RC_KEY_MISS) push_entry(child(key[c]));
+                cur = key[0] < RC_KEY_MISS ? child(key[0]) : pop_next();
             } else if (TWO && in_blas == 0u) {
                 // top-level leaf: map every ray into the instance and descend into its tree
                 rc_const_v4f* ip = (rc_const_v4f*)(const void*)(sc.inst + rc_leaf_first(cur));
@@ -551,11 +570,8 @@ __global__ __launch_bounds__(BLOCK) void k_primary_wave(KParams P)
                     float nx = ray.inv[0] >= 0.0f ? lx[c] : hx[c], fx = ray.inv[0] >= 0.0f ? hx[c] : lx[c];
                     float ny = ray.inv[1] >= 0.0f ? ly[c] : hy[c], fy = ray.inv[1] >= 0.0f ? hy[c] : ly[c];
                     float nz = ray.inv[2] >= 0.0f ? lz[c] : hz[c], fz = ray.inv[2] >= 0.0f ? hz[c] : lz[c];
-                    float t0 = fmaxf(fmaxf((nx - ray.o[0]) * ray.inv[0], (ny - ray.o[1]) * ray.inv[1]),
-                                     fmaxf((nz - ray.o[2]) * ray.inv[2], 0.0f));
-                    float t1 = fminf(fminf((fx - ray.o[0]) * ray.inv[0], (fy - ray.o[1]) * ray.inv[1]),
-                                     (fz - ray.o[2]) * ray.inv[2]);
-                    bool hit = t0 <= fminf(t1 * RC_FAR_GROW, best_t);
+                    float t0;
+                    const bool hit = rc_slab(ray, nx, ny, nz, fx, fy, fz, best_t, t0);
                     uint64_t m = __ballot(hit);
                     uint32_t k = KEY_MISS;
                     if (m != 0) {
@@ -749,8 +765,9 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         P.claim = claim_size(n_packets, grid, 64, 1, 4);
         uint32_t n_pix = (uint32_t)(cam.width * cam.height);
         rc_launch_fill_u32(counts, 0u, n_pix, st);
-        // the wave-uniform traversal pays off when a wave holds the samples of one pixel (common origin)
-        if (sc.max_stack <= 128 && !per_lane_rect && L.area_samples >= 64) {
+        // the wave-uniform traversal pays off when a wave holds the samples of one pixel (common origin);
+        // it addresses nodes by 32-bit byte offsets
+        if (sc.max_stack <= 128 && !per_lane_rect && L.area_samples >= 64 && sc.n_nodes < (1u << 25)) {
             hipLaunchKernelGGL(k_shadow_setup, dim3((n_pix + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_pix,
                                setup);
             RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), 0, st, P, counts, (const float4*)setup);

@@ -104,7 +104,8 @@ DevScene dev_scene(const rc_scene* s)
     d.nodes = s->d_nodes;
     d.tris = s->d_tris;
     d.n_tris = s->nt;
-    d.n_nodes = (uint32_t)s->hb.nodes.size();
+    // allocated node count (a two-level scene's array has room for its largest top level)
+    d.n_nodes = s->two_level ? s->blas_nodes + s->tlas.cap : (uint32_t)s->hb.nodes.size();
     d.max_stack = s->hb.max_stack;
     d.scale = s->scale;
     d.inst = s->two_level ? s->d_inst : nullptr;

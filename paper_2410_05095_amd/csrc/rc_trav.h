@@ -8,11 +8,12 @@
 // stack entry that ends a bottom-level traversal (two-level structures): the ray returns to world space
 #define RC_INST_RETURN 0xFFFFFFFDu
 
-// conservative growth of the far slab distance (covers FP32 rounding of the slab tests)
+// growth of the far-plane reciprocals (1 + 2^-20): the far slab distances round outward
 #define RC_FAR_GROW 1.000001f
 
 struct TravRay {
     float o[3], d[3], inv[3];
+    float invf[3], cn[3], cf[3];   // slab test constants (set with inv by rc_ray_inv)
     float sx, sy, sz;         // watertight test: shear constants (set with inv by rc_ray_inv)
     uint32_t kx, ky, kz;      // watertight test: axes
 };
@@ -34,16 +35,30 @@ struct TravWorld {
     uint32_t in_blas;
 };
 
-// Per-ray constants of the traversal: the clamped reciprocals of the slab tests and, for the watertight
-// triangle test, the axis kz of the largest |d| (first on ties), kx and ky the next axes cyclically (swapped
-// when d[kz] < 0), Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1 / d[kz] (correctly rounded).  Kernels that
-// test triangles with Moller-Trumbore never read the shear constants, so their computation is dropped.
+// Per-ray constants of the traversal.
+// Slab tests: with dd the direction clamped away from zero (|dd| >= 1e-20), a plane at coordinate p lies at
+// distance (p - o) / dd along the ray, which the tests evaluate as one FMA, p * inv + c:
+//   near planes  inv  = 1 / dd (correctly rounded),      cn = -o * inv  moved down by 2^-21 |.| + 2^-120,
+//   far planes   invf = inv * (1 + 2^-20),               cf = -o * invf moved up   by 2^-21 |.| + 2^-120.
+// The margins exceed the rounding of the products -o * inv (and of the margin additions), so cn <= -o * inv
+// and cf >= -o * invf hold in exact arithmetic.  A computed near distance is then at most (1 + 2u) times the
+// exact one and a computed far distance, where the exact one is >= 0, at least (1 + 12u) times it
+// (u = 2^-24), so a box that the exact segment enters always passes max(near, 0) <= min(far, bound).
+// Watertight triangle test: the axis kz of the largest |d| (first on ties), kx and ky the next axes
+// cyclically (swapped when d[kz] < 0), Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1 / d[kz] (correctly
+// rounded).  Kernels that test triangles with Moller-Trumbore never read the shear constants, so their
+// computation is dropped.
 __device__ inline void rc_ray_inv(TravRay& r)
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float dd = fabsf(r.d[a]) < 1e-20f ? copysignf(1e-20f, r.d[a]) : r.d[a];
         r.inv[a] = 1.0f / dd;
+        r.invf[a] = r.inv[a] * RC_FAR_GROW;
+        const float c = -(r.o[a] * r.inv[a]);
+        r.cn[a] = c - (fabsf(c) * 0x1p-21f + 0x1p-120f);
+        const float e = -(r.o[a] * r.invf[a]);
+        r.cf[a] = e + (fabsf(e) * 0x1p-21f + 0x1p-120f);
     }
     uint32_t kz = 0u;
     if (fabsf(r.d[1]) > fabsf(r.d[0])) kz = 1u;
@@ -56,6 +71,18 @@ __device__ inline void rc_ray_inv(TravRay& r)
     r.sx = rc_axis(r.d, kx) / dz;
     r.sy = rc_axis(r.d, ky) / dz;
     r.sz = 1.0f / dz;
+}
+
+// Slab test of one box, its near (nx, ny, nz) and far (fx, fy, fz) plane coordinates picked by the signs
+// of the ray's direction: whether the segment [0, bound] enters the box, and the entry distance t0 >= 0.
+__device__ inline bool rc_slab(const TravRay& r, float nx, float ny, float nz, float fx, float fy, float fz,
+                               float bound, float& t0)
+{
+    t0 = fmaxf(fmaxf(fmaf(nx, r.inv[0], r.cn[0]), fmaf(ny, r.inv[1], r.cn[1])),
+               fmaxf(fmaf(nz, r.inv[2], r.cn[2]), 0.0f));
+    const float t1 = fminf(fminf(fmaf(fx, r.invf[0], r.cf[0]), fmaf(fy, r.invf[1], r.cf[1])),
+                           fminf(fmaf(fz, r.invf[2], r.cf[2]), bound));
+    return t0 <= t1;
 }
 
 // The world ray (o, d) mapped into an instance by its world-to-object map W = [M | m] (row-major 3x4):
@@ -205,10 +232,8 @@ __device__ inline void trav_visit_node(const DevScene& sc, TravRay& r, TravState
         float nx = r.inv[0] >= 0.0f ? lxs[c] : hxs[c], fx = r.inv[0] >= 0.0f ? hxs[c] : lxs[c];
         float ny = r.inv[1] >= 0.0f ? lys[c] : hys[c], fy = r.inv[1] >= 0.0f ? hys[c] : lys[c];
         float nz = r.inv[2] >= 0.0f ? lzs[c] : hzs[c], fz = r.inv[2] >= 0.0f ? hzs[c] : lzs[c];
-        float t0 = fmaxf(fmaxf((nx - r.o[0]) * r.inv[0], (ny - r.o[1]) * r.inv[1]),
-                         fmaxf((nz - r.o[2]) * r.inv[2], 0.0f));
-        float t1 = fminf(fminf((fx - r.o[0]) * r.inv[0], (fy - r.o[1]) * r.inv[1]), (fz - r.o[2]) * r.inv[2]);
-        bool hit = t0 <= fminf(t1 * RC_FAR_GROW, bound);
+        float t0;
+        const bool hit = rc_slab(r, nx, ny, nz, fx, fy, fz, bound, t0);
         tn[c] = hit ? t0 : INFINITY;
     }
     // sort (distance, child) ascending with five comparators: misses (inf) sink to the end
