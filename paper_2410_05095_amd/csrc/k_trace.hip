@@ -336,7 +336,7 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
 // wave pushes an end marker and descends into the instance's tree; popping the marker restores the world
 // rays (and the wave's octant).
 template <bool TWO, bool WT>
-__global__ __launch_bounds__(BLOCK) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 : 8))) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
 {
     const uint32_t lane = __lane_id();
     const DevScene sc = P.sc;
