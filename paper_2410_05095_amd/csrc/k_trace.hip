@@ -279,8 +279,8 @@ __global__ __launch_bounds__(256) void k_shadow_setup(DevScene sc, DevCamera cam
 // Rect-light visibility, wave-uniform traversal.  The 64 ray slots of a wave (the samples of one
 // pixel, or the single samples of an 8x8 pixel tile) walk the BVH together: the wave visits a node
 // when any of its live rays hits one of its boxes, so node and triangle records are read once per wave
-// through the scalar cache, and the traversal stack is wave-uniform, held one entry per lane in two
-// registers (128 entries; the host uses this kernel when 3 x depth + 1 entries fit).  Each lane still
+// through the scalar cache, and the traversal stack is wave-uniform, held one entry per lane in one
+// register (64 entries) or two (128; the host picks the smallest that holds 3 x depth + 1 entries).  Each lane still
 // tests its own ray against every box and triangle the wave visits, with the same FP32 arithmetic as
 // the per-lane traversal; a triangle that a lane's own boxes would not have led to can only report a
 // true crossing, so the occlusion result of every ray is the one the per-lane traversal finds.
@@ -292,7 +292,8 @@ __global__ __launch_bounds__(256) void k_shadow_setup(DevScene sc, DevCamera cam
 // node are loaded at byte offsets picked by the octant; otherwise each lane picks its own planes.
 typedef float rc_v4f __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) rc_v4f rc_const_v4f;
-typedef const __attribute__((address_space(4))) uint32_t rc_const_u32;
+typedef uint32_t rc_v4u __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) rc_v4u rc_const_v4u;
 
 #define RC_KEY_MISS 0x7F800000u   // keys >= this: no live ray enters the child
 
@@ -335,7 +336,8 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
 // Two-level structures: at a top-level leaf every lane maps its ray into the instance (rc_map_ray), the
 // wave pushes an end marker and descends into the instance's tree; popping the marker restores the world
 // rays (and the wave's octant).
-template <bool TWO, bool WT>
+// BIG: the stack spans two registers (128 entries); otherwise one (64 entries, when 3 x depth + 1 <= 64).
+template <bool TWO, bool WT, bool BIG>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 : 8))) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
 {
     const uint32_t lane = __lane_id();
@@ -405,7 +407,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 :
             for (;;) {
                 if (sp == 0) return RC_STACK_EMPTY;
                 --sp;
-                const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63);
+                const uint32_t c = BIG ? (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63)
+                                       : (uint32_t)__builtin_amdgcn_readlane((int)stk0, sp);
                 if (!TWO || c != RC_INST_RETURN) return c;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) { ray.o[a] = wo[a]; ray.d[a] = wd[a]; }
@@ -418,7 +421,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 :
             if (sp < 64) {
                 stk0 = (int)lane == sp ? w : stk0;
                 ++sp;
-            } else if (sp < 128) {
+            } else if (BIG && sp < 128) {
                 stk1 = (int)lane == sp - 64 ? w : stk1;
                 ++sp;
             } else if (lane == 0) {
@@ -446,8 +449,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 :
     }
                 RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
 #undef RC_CS
+                const rc_v4u chw = *(rc_const_v4u*)(const void*)(nodes_b + (uint32_t)(nofs + 96u));
+                const uint64_t c01 = ((uint64_t)chw[1] << 32) | chw[0], c23 = ((uint64_t)chw[3] << 32) | chw[2];
                 auto child = [&](uint32_t k) {
-                    return *(rc_const_u32*)(const void*)(nodes_b + (uint32_t)(nofs + 96u + ((k & 3u) << 2)));
+                    const uint64_t pr = (k & 2u) ? c23 : c01;
+                    return (k & 1u) ? (uint32_t)(pr >> 32) : (uint32_t)pr;
                 };
 #pragma unroll
                 for (int c = 3; c >= 1; --c)
@@ -703,7 +709,7 @@ int rc_trace_grid(int device)
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, reinterpret_cast<const void*>(&k_rect_packets<false, false>), BLOCK,
                                                  TravStack<SL, BLOCK, false>::lds_bytes());
     int e = 0, f = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave<false, false>), BLOCK, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave<false, false, false>), BLOCK, 0);
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, reinterpret_cast<const void*>(&k_primary_wave<false>), BLOCK, 0);
     e = std::max(e, f);
     return std::max(std::max(std::max(a, d * n_cu), std::max(b, c)), e * n_cu);
@@ -770,7 +776,12 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         if (sc.max_stack <= 128 && !per_lane_rect && L.area_samples >= 64 && sc.n_nodes < (1u << 25)) {
             hipLaunchKernelGGL(k_shadow_setup, dim3((n_pix + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_pix,
                                setup);
-            RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), 0, st, P, counts, (const float4*)setup);
+            if (sc.max_stack <= 64)
+                RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, false>), dim3(grid), dim3(BLOCK), 0, st, P, counts,
+                             (const float4*)setup);
+            else
+                RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, true>), dim3(grid), dim3(BLOCK), 0, st, P, counts,
+                             (const float4*)setup);
         } else {
             const size_t lds = TravStack<SL, BLOCK, false>::lds_bytes();
             RC_LAUNCH_TW((k_rect_packets<RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), lds, st, P, counts);

@@ -225,6 +225,40 @@ def test_rect_light_small(ctx, oracle_mod, seed, w, h, N, stream):
     assert 0.0 < st["mean_V"] < 1.0
 
 
+def deep_scene(n=300, ratio=0.8):
+    """A ground square and n triangles shrinking geometrically (factor `ratio`) towards a point above it:
+    binned SAH gives a tree of depth 31, so the wave kernel's traversal stack needs its second register
+    (3 x depth + 1 > 64 entries)."""
+    tris = [[(-4, 0, -4), (4, 0, -4), (4, 0, 4)], [(-4, 0, -4), (4, 0, 4), (-4, 0, 4)]]
+    for k in range(n):
+        s = ratio ** k
+        c = np.array([0.6 * s, 0.3 + 0.4 * s, 0.05 * s])
+        tris.append([c + (-0.4 * s, 0, -0.4 * s), c + (0.4 * s, 0, -0.3 * s), c + (0.0, 0.0, 0.45 * s)])
+    pos = np.asarray(tris, np.float32).reshape(-1, 3)
+    nt = len(pos) // 3
+    cam = sg.Camera(eye=(0.9, 1.4, -1.6), target=(0.1, 0.1, 0.1), up=(0.0, 1.0, 0.0), vfov_deg=50.0,
+                    width=40, height=30, ssaa=1)
+    rect = sg.RectLight(center=(0.1, 2.5, 0.1), edge_u=(1.0, 0.0, 0.0), edge_v=(0.0, 0.0, 1.0),
+                        radiance=(40.0, 40.0, 40.0))
+    return sg.Scene(positions=pos, indices=np.arange(3 * nt, dtype=np.uint32).reshape(nt, 3),
+                    tri_material=np.zeros(nt, np.uint32), materials=np.array([[0.7, 0.6, 0.5, 0.4, 0.0]], np.float32),
+                    body_vertex_range=np.array([[0, len(pos)]], np.uint32),
+                    body_tri_range=np.array([[0, nt]], np.uint32), point_lights=np.zeros((0, 6), np.float32),
+                    rect_light=rect, cameras=[cam], name="deep")
+
+
+def test_rect_light_deep_tree(ctx, oracle_mod):
+    """The wave kernel with its two-register stack (a flat tree deeper than 21 levels)."""
+    scene = deep_scene()
+    gs = ctx.scene_from(scene).build()
+    depth = gs.stats()["depth"]
+    say(f"[rect deep] depth {depth}, stack bound {3 * depth + 1}")
+    assert 3 * depth + 1 > 64
+    out, orc, st = compare_rect(ctx, oracle_mod, scene, scene.cameras[0], 64, 1, gs=gs)
+    assert 0.0 < st["mean_V"] < 1.0
+    gs.close()
+
+
 def test_rect_light_big_scene_sampled(ctx, oracle_mod):
     """7.3M triangles at 1920x1080 with 64 light samples per pixel (the benchmark's plain path):
     4000 pixels checked against the oracle."""
