@@ -297,12 +297,13 @@ typedef const __attribute__((address_space(4))) rc_v4u rc_const_v4u;
 
 #define RC_KEY_MISS 0x7F800000u   // keys >= this: no live ray enters the child
 
+// The key of the first lane that enters the child; when none does, lane 63's, which is then a miss key
+// (the node step runs with all 64 lanes active, so every lane holds its candidate).
 __device__ inline uint32_t wave_key(bool hit, float t0, uint32_t slot)
 {
-    const uint64_t m = __ballot(hit);
-    if (m == 0) return RC_KEY_MISS | slot;
-    const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(t0), __builtin_ctzll(m));
-    return (t & 0x7FFFFFFCu) | slot;
+    const uint32_t kv = hit ? ((__float_as_uint(t0) & 0x7FFFFFFCu) | slot) : (RC_KEY_MISS | slot);
+    const uint64_t m = __ballot(hit) | (1ull << 63);
+    return (uint32_t)__builtin_amdgcn_readlane((int)kv, __builtin_ctzll(m));
 }
 
 // bound: 1 (the segment's end) for live rays, -1 for finished ones, which then never hit (t0 >= 0)
@@ -338,7 +339,7 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
 // rays (and the wave's octant).
 // BIG: the stack spans two registers (128 entries); otherwise one (64 entries, when 3 x depth + 1 <= 64).
 template <bool TWO, bool WT, bool BIG>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 : 8))) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT ? 1 : 8))) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
 {
     const uint32_t lane = __lane_id();
     const DevScene sc = P.sc;
@@ -347,6 +348,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 :
     const uint64_t n_blocks = (total + 63) / 64;
     uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
     const char* nodes_b = (const char*)(const void*)sc.nodes;
+    const char* tris_b = (const char*)(const void*)sc.tris;
     const XcdQueue<RECT_CHUNK> queue(P.w.counters, P.slot, n_blocks);
     uint32_t pos = 0, pos_end = 0;   // wave-uniform range of claimed positions
     for (;;) {
@@ -398,7 +400,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 :
         set_octant();
         float wo[3] = {ray.o[0], ray.o[1], ray.o[2]}, wd[3] = {ray.d[0], ray.d[1], ray.d[2]};   // world ray
         uint32_t in_blas = 0u;
-        bool occ = false;
+        // per-lane state as 32-bit words: occ (an occluder found), live (busy and not occluded) and the
+        // slab bound, 1 (the segment's end) for live rays and -1 otherwise, so that finished rays enter
+        // no box (t0 >= 0)
+        uint32_t occ = 0u, live = busy ? 1u : 0u;
+        float bound = busy ? 1.0f : -1.0f;
         uint32_t cur = busy_mask != 0 ? (TWO ? sc.tlas_root : 0u) : RC_STACK_EMPTY;
         int sp = 0;
         uint32_t stk0 = 0, stk1 = 0;   // entry e of the wave's stack lives in lane e % 64 of stk{e / 64}
@@ -429,19 +435,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 :
             }
         };
         while (cur != RC_STACK_EMPTY) {
-            const bool live = busy && !occ;
             if (!rc_is_leaf(cur)) {
                 // 32-bit byte offsets into the node array (the host keeps it below 4 GiB for this kernel), so
                 // that each block load takes its offset in a scalar register
                 const uint32_t nofs = cur << 7;
                 auto blk = [&](uint32_t off) { return *(rc_const_v4f*)(const void*)(nodes_b + (uint32_t)(nofs + off)); };
                 uint32_t key[4];
-                const float bound = live ? 1.0f : -1.0f;
                 if (uniform_oct)
                     wave_keys_uniform(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, bound, key);
                 else
                     wave_keys_mixed(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, bound, key);
-                if (live) ++node_visits;
+                node_visits += live;
 #define RC_CS(a, b)                                                                   \
     {                                                                                 \
         const uint32_t lo = min(key[a], key[b]), hi = max(key[a], key[b]);            \
@@ -471,23 +475,33 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO ? 1 :
                 in_blas = 1u;
                 cur = __float_as_uint(q3[0]);
             } else {
+                // every lane tests every triangle of the leaf, without lane branches: a finished lane only
+                // repeats work (its flag stays set; idle lanes' flags are never read), and the counter
+                // takes the tests of live lanes
                 const uint32_t first = rc_leaf_first(cur), cnt = rc_leaf_count(cur);
+                const uint32_t tofs = first * 48u;   // 32-bit byte offset (the host keeps the array below 4 GiB)
+                uint32_t o = occ;
                 for (uint32_t i = 0; i < cnt; ++i) {
-                    rc_const_v4f* tp = (rc_const_v4f*)(const void*)(sc.tris + 3 * (size_t)(first + i));
+                    rc_const_v4f* tp = (rc_const_v4f*)(const void*)(tris_b + (uint32_t)(tofs + 48u * i));
                     const rc_v4f A = tp[0], B = tp[1], C = tp[2];
-                    if (busy && !occ) {
-                        ++tri_tests;
+                    tri_tests += live & (o ^ 1u);
+                    bool hit;
+                    if (WT) {
                         float t, u, v;
-                        bool hit = WT ? rc_wt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v)
-                                      : rc_mt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v);
-                        occ = hit && t < 1.0f;
+                        hit = rc_wt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v) && t < 1.0f;
+                    } else {
+                        hit = rc_mt_segment(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z);
                     }
+                    o |= hit ? 1u : 0u;
                 }
-                cur = __ballot(busy && !occ) == 0 ? RC_STACK_EMPTY : pop_next();
+                occ = o;
+                live &= o ^ 1u;
+                bound = live != 0u ? bound : -1.0f;
+                cur = __ballot(live != 0u) == 0 ? RC_STACK_EMPTY : pop_next();
             }
             cur = __builtin_amdgcn_readfirstlane(cur);
         }
-        const uint64_t vis = __ballot(busy && !occ);
+        const uint64_t vis = __ballot(busy && occ == 0u);
         if (in_image && (lane == 0 || k == 0)) {
             uint32_t end = (uint32_t)min<uint64_t>(64, lane + (N - k));
             uint64_t seg = (end >= 64 ? ~0ull : ((1ull << end) - 1)) & ~((1ull << lane) - 1);
@@ -772,8 +786,9 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         uint32_t n_pix = (uint32_t)(cam.width * cam.height);
         rc_launch_fill_u32(counts, 0u, n_pix, st);
         // the wave-uniform traversal pays off when a wave holds the samples of one pixel (common origin);
-        // it addresses nodes by 32-bit byte offsets
-        if (sc.max_stack <= 128 && !per_lane_rect && L.area_samples >= 64 && sc.n_nodes < (1u << 25)) {
+        // it addresses nodes and triangles by 32-bit byte offsets
+        if (sc.max_stack <= 128 && !per_lane_rect && L.area_samples >= 64 && sc.n_nodes < (1u << 25) &&
+            (uint64_t)sc.n_tris * 48u < (1ull << 32)) {
             hipLaunchKernelGGL(k_shadow_setup, dim3((n_pix + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_pix,
                                setup);
             if (sc.max_stack <= 64)

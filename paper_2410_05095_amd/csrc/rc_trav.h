@@ -267,16 +267,55 @@ __device__ inline bool rc_mt(const TravRay& r, float ax, float ay, float az, flo
     float su = sx * px_ + sy * py_;
     su = su + sz * pz_;
     u = su * idet;
+    t = 0.0f;
+    v = 0.0f;
+    // staged so that a wave skips the rest once no lane can still hit; u > 1 fails as u + v <= 1 would
+    // (v >= 0 makes the rounded u + v at least u), so every decision is the unstaged test's
+    if (!(u >= 0.0f && u <= 1.0f)) return false;
     float qx = sy * bz - sz * by;
     float qy = sz * bx - sx * bz;
     float qz = sx * by - sy * bx;
     float sv = r.d[0] * qx + r.d[1] * qy;
     sv = sv + r.d[2] * qz;
     v = sv * idet;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return false;
     float stq = cx * qx + cy * qy;
     stq = stq + cz * qz;
     t = stq * idet;
-    return u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f;
+    return t > 0.0f;
+}
+
+// rc_mt's arithmetic with its conditions decided without branches, for a segment: whether the ray crosses
+// the triangle at 0 < t < 1.  min(u, v, 1 - (u + v)) >= 0 holds exactly when u >= 0, v >= 0 and u + v <= 1
+// (1 - s, for an FP32 s > 1, is at most -2^-23, so its sign is exact) as long as rcp(det) is finite (m is
+// then never NaN); when it is not, t is infinite or NaN and fails the range test, as it fails rc_mt.
+// 0 < t < 1 is one unsigned compare of t's bit pattern minus one against that of the largest float below 1.
+__device__ inline bool rc_mt_segment(const TravRay& r, float ax, float ay, float az, float bx, float by, float bz,
+                                     float cx, float cy, float cz)
+{
+    float px_ = r.d[1] * cz - r.d[2] * cy;
+    float py_ = r.d[2] * cx - r.d[0] * cz;
+    float pz_ = r.d[0] * cy - r.d[1] * cx;
+    float det = bx * px_ + by * py_;
+    det = det + bz * pz_;
+    float idet = __builtin_amdgcn_rcpf(det);
+    float sx = r.o[0] - ax, sy = r.o[1] - ay, sz = r.o[2] - az;
+    float su = sx * px_ + sy * py_;
+    su = su + sz * pz_;
+    const float u = su * idet;
+    float qx = sy * bz - sz * by;
+    float qy = sz * bx - sx * bz;
+    float qz = sx * by - sy * bx;
+    float sv = r.d[0] * qx + r.d[1] * qy;
+    sv = sv + r.d[2] * qz;
+    const float v = sv * idet;
+    float stq = cx * qx + cy * qy;
+    stq = stq + cz * qz;
+    const float t = stq * idet;
+    const float m = fminf(fminf(u, v), 1.0f - (u + v));
+    // all ones when m < 0 (m + 0 turns -0 into +0, which passes like u >= 0 does for u = -0)
+    const uint32_t neg = (uint32_t)((int32_t)__float_as_uint(m + 0.0f) >> 31);
+    return ((__float_as_uint(t) - 1u) | neg) < 0x3F7FFFFFu;
 }
 
 // Watertight ray/triangle test (Woop, Benthin and Wald, JCGT 2013) in FP32 on a triangle given by its three
