@@ -290,6 +290,8 @@ __device__ inline bool rc_mt(const TravRay& r, float ax, float ay, float az, flo
 // (1 - s, for an FP32 s > 1, is at most -2^-23, so its sign is exact) as long as rcp(det) is finite (m is
 // then never NaN); when it is not, t is infinite or NaN and fails the range test, as it fails rc_mt.
 // 0 < t < 1 is one unsigned compare of t's bit pattern minus one against that of the largest float below 1.
+// Called by whole waves (uniform control flow): once u is known, the wave skips the rest when no lane has
+// 0 <= u <= 1 (u > 1 fails as u + v <= 1 would, since v >= 0 makes the rounded u + v at least u).
 __device__ inline bool rc_mt_segment(const TravRay& r, float ax, float ay, float az, float bx, float by, float bz,
                                      float cx, float cy, float cz)
 {
@@ -303,6 +305,7 @@ __device__ inline bool rc_mt_segment(const TravRay& r, float ax, float ay, float
     float su = sx * px_ + sy * py_;
     su = su + sz * pz_;
     const float u = su * idet;
+    if (__ballot(u >= 0.0f && u <= 1.0f) == 0) return false;
     float qx = sy * bz - sz * by;
     float qy = sz * bx - sx * bz;
     float qz = sx * by - sy * bx;
