@@ -295,6 +295,8 @@ typedef const __attribute__((address_space(4))) rc_v4f rc_const_v4f;
 typedef uint32_t rc_v4u __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) rc_v4u rc_const_v4u;
 
+extern "C" __device__ uint32_t __ockl_wfred_max_u32(uint32_t);   // ROCm device library: wavefront maximum
+
 #define RC_KEY_MISS 0x7F800000u   // keys >= this: no live ray enters the child
 
 // The key of the first lane that enters the child; when none does, lane 63's, which is then a miss key
@@ -651,9 +653,9 @@ __global__ __launch_bounds__(BLOCK) void k_primary_wave(KParams P)
                         }
                     }
                 }
-                float m = best_t;
-                for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-                wmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m)));   // equal in every lane
+                // largest closest-hit distance over the wave's valid lanes (non-negative floats order like
+                // their bit patterns; invalid lanes, at -inf, count as 0), reduced in registers
+                wmax = __uint_as_float(__ockl_wfred_max_u32(__float_as_uint(fmaxf(best_t, 0.0f))));
                 cur = pop();
             }
             cur = __builtin_amdgcn_readfirstlane(cur);
