@@ -236,8 +236,9 @@ enum {
     RC_FLAG_TIMING = 1u,     /* record per-stage device times (rc_get_stage_times) */
     RC_FLAG_PER_LANE = 4u      /* trace camera rays and rect-light samples one ray per lane with per-lane
                                   stacks even where the wave-uniform traversal would be used (camera rays
-                                  with ssaa = 2, rect light from 64 samples per pixel; BVH depth <= 42); same
-                                  results outside the FP32 band, for comparison */
+                                  with ssaa = 2, rect-light samples at any count; BVH depth <= 42, under
+                                  2^25 nodes and 2^32 bytes of packed triangles); same results outside the
+                                  FP32 band, for comparison */
 };
 
 typedef struct rc_render_opts {

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256) void k_shadow_setup(DevScene sc, DevCamera cam
 }
 
 // Rect-light visibility, wave-uniform traversal.  The 64 ray slots of a wave (the samples of one
-// pixel, or the single samples of an 8x8 pixel tile) walk the BVH together: the wave visits a node
+// pixel, or the N samples of each of 64 / N neighbouring pixels) walk the BVH together: the wave visits a node
 // when any of its live rays hits one of its boxes, so node and triangle records are read once per wave
 // through the scalar cache, and the traversal stack is wave-uniform, held one entry per lane in one
 // register (64 entries) or two (128; the host picks the smallest that holds 3 x depth + 1 entries).  Each lane still
@@ -787,9 +787,10 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         P.claim = claim_size(n_packets, grid, 64, 1, 4);
         uint32_t n_pix = (uint32_t)(cam.width * cam.height);
         rc_launch_fill_u32(counts, 0u, n_pix, st);
-        // the wave-uniform traversal pays off when a wave holds the samples of one pixel (common origin);
-        // it addresses nodes and triangles by 32-bit byte offsets
-        if (sc.max_stack <= 128 && !per_lane_rect && L.area_samples >= 64 && sc.n_nodes < (1u << 25) &&
+        // the wave-uniform traversal, at every sample count: a wave holds the samples of one pixel, or of
+        // 64 / N neighbouring pixels, whose rays start close together (measured faster than the per-lane
+        // kernel from one sample per pixel on); it addresses nodes and triangles by 32-bit byte offsets
+        if (sc.max_stack <= 128 && !per_lane_rect && sc.n_nodes < (1u << 25) &&
             (uint64_t)sc.n_tris * 48u < (1ull << 32)) {
             hipLaunchKernelGGL(k_shadow_setup, dim3((n_pix + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_pix,
                                setup);

@@ -166,7 +166,7 @@ def test_render_error_paths(ctx):
 
 
 def compare_rect(ctx, O, scene, cam, N, stream, pixels=None, device_build=False, gs=None, osc=None):
-    """Both rect-light kernels (wave-uniform traversal, used from 64 samples per pixel; per-lane stacks)
+    """Both rect-light kernels (wave-uniform traversal, the default; per-lane stacks)
     against one oracle run: hit ids and visible-sample counts exact outside the FP32 band, radiance within
     1e-4.  gs / osc: an already built GPU scene / oracle scene to use instead."""
     import torch
