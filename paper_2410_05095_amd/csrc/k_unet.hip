@@ -131,18 +131,37 @@ __device__ inline int xcd_tile(int b, int n)
 
 // ---------------------------------------------------------------- 3x3 convolution, LDS-tiled
 // Workgroup of 4 waves; output tile = 4 rows x TW = 16 MT columns of one image, wave w computes row w:
-// MT 16-pixel M-tiles x NT 16-channel N-tiles.  The input halo (6 rows x TW + 2 columns) of a chunk of
-// CC channels is staged in LDS, zero outside the image, and the 9 taps read their shifted pixels from
-// there (each input value is fetched from memory once per tile instead of once per tap).  With a second
-// source the halo loader reads channels [0, Ca) from the 2x nearest-upsampled low-resolution tensor and
-// the rest from the skip tensor, so the decoder's upsample + concat is never materialised.
-template <int MT, int NT, int CC>
+// MT 16-pixel M-tiles x NT 16-channel N-tiles.  For each chunk of CC input channels the input halo (6 rows
+// x TW + 2 columns) is staged in LDS, zero outside the image, and the 9 taps read their shifted pixels
+// from there (each input value is fetched from memory once per tile instead of once per tap).  With SW the
+// chunk's weights are staged in LDS too, in MFMA fragment order, and read back with one conflict-free
+// 16-byte LDS read per lane and N-tile: the 4 waves then fetch them from memory once per workgroup instead
+// of once each per K-step, which pays from 4 N-tiles on; otherwise each wave streams its weight fragments
+// through L1 one K-step ahead.  With a second source the halo loader reads channels [0, Ca) from the 2x
+// nearest-upsampled low-resolution tensor and the rest from the skip tensor, so the decoder's upsample +
+// concat is never materialised.
+template <int MT, int NT, int CC, bool SW>
+struct ConvLds {
+    static constexpr int TW = 16 * MT, HW = TW + 2, HR = 6;
+    static constexpr int PST = CC + 8;                         // LDS pixel stride in bf16 (bank padding)
+    static constexpr int KS = (9 * CC + 31) / 32;              // K-steps of one chunk (zero-padded)
+    static constexpr int HALO_U4 = (HR * HW * PST * 2 + 15) / 16;
+    static constexpr int W_U4 = SW ? KS * NT * 64 : 0;         // weight fragments of one chunk
+    static constexpr size_t bytes()
+    {
+        const size_t in = (size_t)(HALO_U4 + W_U4) * 16, out = (size_t)4 * TW * 16 * NT * 2;
+        return in > out ? in : out;
+    }
+};
+
+template <int MT, int NT, int CC, bool SW>
 __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
 {
     extern __shared__ uint4 conv_lds[];
-    constexpr int TW = 16 * MT, HW = TW + 2, HR = 6;
-    constexpr int PST = CC + 8;   // LDS pixel stride in bf16 elements (padding against bank conflicts)
+    using L = ConvLds<MT, NT, CC, SW>;
+    constexpr int TW = L::TW, HW = L::HW, HR = L::HR, PST = L::PST, KS = L::KS;
     uint16_t* lds = reinterpret_cast<uint16_t*>(conv_lds);
+    uint4* wfrag = conv_lds + L::HALO_U4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + 3) / 4;
     int tt = xcd_tile(blockIdx.x, gridDim.x);
@@ -179,24 +198,43 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
             }
             *reinterpret_cast<uint4*>(lds + pix * PST + 8 * gg) = v;
         }
+        // weight fragment (ks, nt) of lane l: output channel 16 nt + (l & 15), the 8 K values from
+        // 32 ks + 8 (l >> 4) on (tap = K / CC, input channel c0 + K % CC), zero from 9 CC on
+        if constexpr (SW) {
+            for (int f = threadIdx.x; f < L::W_U4; f += 256) {
+                const int l = f & 63, q = f >> 6, nt = q % NT, ks = q / NT;
+                const int co = 16 * nt + (l & 15), kk = 32 * ks + 8 * (l >> 4);
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (kk < 9 * CC && co < a.Cout) {
+                    const int tap = kk / CC, cl = kk - tap * CC;
+                    v = *reinterpret_cast<const uint4*>(a.wt + (size_t)co * K + tap * a.Cin + c0 + cl);
+                }
+                wfrag[f] = v;
+            }
+        }
         __syncthreads();
-        // weight fragments of step k0 + 32 are loaded while the MFMAs of step k0 run
-        auto load_b = [&](int k0, bf16x8* B) {
-            const int kk = k0 + 8 * g;
+        // streamed weights: fragments of K-step ks loaded while the MFMAs of the step before run
+        auto load_b = [&](int ks, bf16x8* Bd) {
+            const int kk = 32 * ks + 8 * g;
             const bool kv = kk < 9 * CC;
             const int tap = kv ? kk / CC : 0;
             const int cl = kk - tap * CC;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = 16 * nt + r;
-                B[nt] = (kv && co < a.Cout) ? load8(a.wt + (size_t)co * K + tap * a.Cin + c0 + cl) : zero;
+                Bd[nt] = (kv && co < a.Cout) ? load8(a.wt + (size_t)co * K + tap * a.Cin + c0 + cl) : zero;
             }
         };
         bf16x8 B[NT], Bn[NT];
-        load_b(0, B);
-        for (int k0 = 0; k0 < 9 * CC; k0 += 32) {
-            if (k0 + 32 < 9 * CC) load_b(k0 + 32, Bn);
-            const int kk = k0 + 8 * g;
+        if constexpr (!SW) load_b(0, B);
+        for (int ks = 0; ks < KS; ++ks) {
+            if constexpr (SW) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) B[nt] = __builtin_bit_cast(bf16x8, wfrag[(ks * NT + nt) * 64 + lane]);
+            } else if (ks + 1 < KS) {
+                load_b(ks + 1, Bn);
+            }
+            const int kk = 32 * ks + 8 * g;
             const bool kv = kk < 9 * CC;
             const int tap = kv ? kk / CC : 0;
             const int cl = kk - tap * CC;
@@ -212,8 +250,10 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+            if constexpr (!SW) {
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) B[nt] = Bn[nt];
+                for (int nt = 0; nt < NT; ++nt) B[nt] = Bn[nt];
+            }
         }
     }
     // Epilogue through LDS: each wave writes its 16 MT pixels x 16 NT channels (bias, ReLU applied) as
@@ -834,29 +874,38 @@ inline unsigned nb(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-template <int MT, int NT, int CC>
+template <int MT, int NT, int CC, bool SW>
 void launch_conv_lds(const ConvArgs& a, hipStream_t st)
 {
     constexpr int TW = 16 * MT;
     const size_t tiles = (size_t)a.N * ((a.H + 3) / 4) * ((a.W + TW - 1) / TW);
-    const size_t halo = (size_t)6 * (TW + 2) * (CC + 8) * 2, out_tile = (size_t)4 * TW * 16 * NT * 2;
-    const size_t lds = halo > out_tile ? halo : out_tile;
-    hipLaunchKernelGGL((k_conv_lds<MT, NT, CC>), dim3((unsigned)tiles), dim3(256), lds, st, a);
+    const size_t lds = ConvLds<MT, NT, CC, SW>::bytes();
+    hipLaunchKernelGGL((k_conv_lds<MT, NT, CC, SW>), dim3((unsigned)tiles), dim3(256), lds, st, a);
 }
 
 void unet_conv3x3(const ConvArgs& a, hipStream_t st)
 {
     const int nt = (a.Cout + 15) / 16;
-    const int cc = a.Cin % 64 == 0 ? 64 : (a.Cin % 32 == 0 ? 32 : 8);
-    switch (nt * 100 + cc) {
-    case 208: launch_conv_lds<4, 2, 8>(a, st); return;
-    case 232: launch_conv_lds<4, 2, 32>(a, st); return;
-    case 264: launch_conv_lds<4, 2, 64>(a, st); return;
-    case 432: launch_conv_lds<4, 4, 32>(a, st); return;
-    case 464: launch_conv_lds<4, 4, 64>(a, st); return;
-    case 632: launch_conv_lds<2, 6, 32>(a, st); return;
-    case 864: launch_conv_lds<2, 8, 64>(a, st); return;
-    case 1264: launch_conv_lds<2, 12, 64>(a, st); return;
+    // up to 2 N-tiles: 32- or 64-channel chunks, weights streamed through L1; from 4 N-tiles on: weights
+    // staged in LDS, with chunks small enough that halo and weights fit in 64 KB (16 channels up to 8
+    // N-tiles, padding a chunk's 144 K values to 160; 8 channels beyond)
+    int cfg = 0;
+    if (nt <= 2)
+        cfg = a.Cin % 64 == 0 ? 264 : (a.Cin % 32 == 0 ? 232 : 208);
+    else if (a.Cin % 16 == 0)
+        cfg = nt * 100 + (nt <= 8 ? 16 : 8);
+    static_assert(ConvLds<4, 2, 64, false>::bytes() <= 65536 && ConvLds<4, 4, 16, true>::bytes() <= 65536 &&
+                      ConvLds<2, 6, 16, true>::bytes() <= 65536 && ConvLds<2, 8, 16, true>::bytes() <= 65536 &&
+                      ConvLds<2, 12, 8, true>::bytes() <= 65536,
+                  "convolution LDS beyond 64 KB");
+    switch (cfg) {
+    case 208: launch_conv_lds<4, 2, 8, false>(a, st); return;
+    case 232: launch_conv_lds<4, 2, 32, false>(a, st); return;
+    case 264: launch_conv_lds<4, 2, 64, false>(a, st); return;
+    case 416: launch_conv_lds<4, 4, 16, true>(a, st); return;
+    case 616: launch_conv_lds<2, 6, 16, true>(a, st); return;
+    case 816: launch_conv_lds<2, 8, 16, true>(a, st); return;
+    case 1208: launch_conv_lds<2, 12, 8, true>(a, st); return;
     default: break;
     }
     unet_conv3x3_direct(a, st);
