@@ -259,15 +259,16 @@ __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* cou
 // Per-pixel shadow-ray setup of the rect-light pass: (origin, 1) and (unit normal, 0) in FP32 from the
 // FP64 surface reconstruction, or (0, 0, 0, 0) for pixels without a primary hit.  Keeps the FP64 code
 // (and its registers) out of the traversal kernel.
-__global__ __launch_bounds__(256) void k_shadow_setup(DevScene sc, DevCamera cam, const uint4* gbuf, uint32_t n_pix,
+__global__ __launch_bounds__(256) void k_shadow_setup(DevScene sc, DevCamera cam, const uint4* gbuf, uint32_t n_samples,
                                                       float4* setup)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pix) return;
+    if (i >= n_samples) return;
+    const uint32_t spp = (uint32_t)(cam.ssaa * cam.ssaa);
     const uint4 h = gbuf[i];
     float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
     if (h.x != RC_NO_HIT) {
-        Surface S = rc_surface(sc, cam, i, 0, h.x);
+        Surface S = rc_surface(sc, cam, i / spp, i % spp, h.x);
         D3 O = rc_shadow_origin(S);
         a = make_float4((float)O.x, (float)O.y, (float)O.z, 1.0f);
         b = make_float4((float)S.n.x, (float)S.n.y, (float)S.n.z, 0.0f);
@@ -339,7 +340,143 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
 // Two-level structures: at a top-level leaf every lane maps its ray into the instance (rc_map_ray), the
 // wave pushes an end marker and descends into the instance's tree; popping the marker restores the world
 // rays (and the wave's octant).
-// BIG: the stack spans two registers (128 entries); otherwise one (64 entries, when 3 x depth + 1 <= 64).
+// Any-hit traversal of the segments o + t d, 0 <= t <= 1, of a wave's rays (called by all 64 lanes; busy
+// lanes hold a ray whose traversal constants rc_ray_inv set): returns 1 in the lanes whose segment is
+// occluded.  BIG: the stack spans two registers (128 entries); otherwise one (64 entries, when
+// 3 x depth + 1 <= 64).
+template <bool TWO, bool WT, bool BIG>
+__device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const DevScene& sc, const char* nodes_b,
+                                                                      const char* tris_b, TravRay& ray, bool busy,
+                                                                      uint32_t& node_visits, uint32_t& tri_tests,
+                                                                      uint32_t* error_flag)
+{
+    const uint32_t lane = __lane_id();
+    const uint64_t busy_mask = __ballot(busy);
+    uint32_t oct = 0, on0 = 0, on1 = 32, on2 = 64, of0 = 16, of1 = 48, of2 = 80;
+    bool uniform_oct = false;
+    auto set_octant = [&]() {
+        const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
+                                (ray.inv[2] < 0.0f ? 4u : 0u);
+        oct = 0;
+        if (busy_mask != 0) oct = (uint32_t)__builtin_amdgcn_readlane((int)my_oct, __builtin_ctzll(busy_mask));
+        uniform_oct = __ballot(busy && my_oct != oct) == 0;
+        // byte offsets of the near- and far-plane blocks (axis a: lo at 32 a, hi at 32 a + 16)
+        on0 = (oct & 1u) ? 16u : 0u;
+        on1 = (oct & 2u) ? 48u : 32u;
+        on2 = (oct & 4u) ? 80u : 64u;
+        of0 = on0 ^ 16u;
+        of1 = on1 ^ 16u;
+        of2 = on2 ^ 16u;
+        // opaque to the compiler (no instruction): keeps node + offset in the scalar-offset form of the loads
+        asm volatile("" : "+s"(on0), "+s"(on1), "+s"(on2), "+s"(of0), "+s"(of1), "+s"(of2));
+    };
+    set_octant();
+    float wo[3] = {ray.o[0], ray.o[1], ray.o[2]}, wd[3] = {ray.d[0], ray.d[1], ray.d[2]};   // world ray
+    uint32_t in_blas = 0u;
+    // per-lane state as 32-bit words: occ (an occluder found), live (busy and not occluded) and the
+    // slab bound, 1 (the segment's end) for live rays and -1 otherwise, so that finished rays enter
+    // no box (t0 >= 0)
+    uint32_t occ = 0u, live = busy ? 1u : 0u;
+    float bound = busy ? 1.0f : -1.0f;
+    uint32_t cur = busy_mask != 0 ? (TWO ? sc.tlas_root : 0u) : RC_STACK_EMPTY;
+    int sp = 0;
+    uint32_t stk0 = 0, stk1 = 0;   // entry e of the wave's stack lives in lane e % 64 of stk{e / 64}
+    // next entry of the wave's stack (an instance's end marker returns the rays to world space)
+    auto pop_next = [&]() -> uint32_t {
+        for (;;) {
+            if (sp == 0) return RC_STACK_EMPTY;
+            --sp;
+            const uint32_t c = BIG ? (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63)
+                                   : (uint32_t)__builtin_amdgcn_readlane((int)stk0, sp);
+            if (!TWO || c != RC_INST_RETURN) return c;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { ray.o[a] = wo[a]; ray.d[a] = wd[a]; }
+            rc_ray_inv(ray);
+            set_octant();
+            in_blas = 0u;
+        }
+    };
+    auto push_entry = [&](uint32_t w) {
+        if (sp < 64) {
+            stk0 = (int)lane == sp ? w : stk0;
+            ++sp;
+        } else if (BIG && sp < 128) {
+            stk1 = (int)lane == sp - 64 ? w : stk1;
+            ++sp;
+        } else if (lane == 0) {
+            *error_flag = 1u;   // beyond the bound the host checked: entry dropped, reported
+        }
+    };
+    while (cur != RC_STACK_EMPTY) {
+        if (!rc_is_leaf(cur)) {
+            // 32-bit byte offsets into the node array (the host keeps it below 4 GiB for this kernel), so
+            // that each block load takes its offset in a scalar register
+            const uint32_t nofs = cur << 7;
+            auto blk = [&](uint32_t off) { return *(rc_const_v4f*)(const void*)(nodes_b + (uint32_t)(nofs + off)); };
+            uint32_t key[4];
+            if (uniform_oct)
+                wave_keys_uniform(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, bound, key);
+            else
+                wave_keys_mixed(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, bound, key);
+            node_visits += live;
+#define RC_CS(a, b)                                                                   \
+{                                                                                 \
+    const uint32_t lo = min(key[a], key[b]), hi = max(key[a], key[b]);            \
+    key[a] = lo; key[b] = hi;                                                     \
+}
+            RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
+#undef RC_CS
+            const rc_v4u chw = *(rc_const_v4u*)(const void*)(nodes_b + (uint32_t)(nofs + 96u));
+            const uint64_t c01 = ((uint64_t)chw[1] << 32) | chw[0], c23 = ((uint64_t)chw[3] << 32) | chw[2];
+            auto child = [&](uint32_t k) {
+                const uint64_t pr = (k & 2u) ? c23 : c01;
+                return (k & 1u) ? (uint32_t)(pr >> 32) : (uint32_t)pr;
+            };
+#pragma unroll
+            for (int c = 3; c >= 1; --c)
+                if (key[c] < RC_KEY_MISS) push_entry(child(key[c]));
+            cur = key[0] < RC_KEY_MISS ? child(key[0]) : pop_next();
+        } else if (TWO && in_blas == 0u) {
+            // top-level leaf: map every ray into the instance and descend into its tree
+            rc_const_v4f* ip = (rc_const_v4f*)(const void*)(sc.inst + rc_leaf_first(cur));
+            const rc_v4f q0 = ip[0], q1 = ip[1], q2 = ip[2], q3 = ip[3];
+            const float W[12] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3],
+                                 q2[0], q2[1], q2[2], q2[3]};
+            rc_map_ray(W, wo, wd, ray);
+            set_octant();
+            push_entry(RC_INST_RETURN);
+            in_blas = 1u;
+            cur = __float_as_uint(q3[0]);
+        } else {
+            // every lane tests every triangle of the leaf, without lane branches: a finished lane only
+            // repeats work (its flag stays set; idle lanes' flags are never read), and the counter
+            // takes the tests of live lanes
+            const uint32_t first = rc_leaf_first(cur), cnt = rc_leaf_count(cur);
+            const uint32_t tofs = first * 48u;   // 32-bit byte offset (the host keeps the array below 4 GiB)
+            uint32_t o = occ;
+            for (uint32_t i = 0; i < cnt; ++i) {
+                rc_const_v4f* tp = (rc_const_v4f*)(const void*)(tris_b + (uint32_t)(tofs + 48u * i));
+                const rc_v4f A = tp[0], B = tp[1], C = tp[2];
+                tri_tests += live & (o ^ 1u);
+                bool hit;
+                if (WT) {
+                    float t, u, v;
+                    hit = rc_wt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v) && t < 1.0f;
+                } else {
+                    hit = rc_mt_segment(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z);
+                }
+                o |= hit ? 1u : 0u;
+            }
+            occ = o;
+            live &= o ^ 1u;
+            bound = live != 0u ? bound : -1.0f;
+            cur = __ballot(live != 0u) == 0 ? RC_STACK_EMPTY : pop_next();
+        }
+        cur = __builtin_amdgcn_readfirstlane(cur);
+    }
+    return occ;
+}
+
 template <bool TWO, bool WT, bool BIG>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT ? 1 : 8))) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
 {
@@ -380,129 +517,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT
                 }
             }
         }
-        const uint64_t busy_mask = __ballot(busy);
-        uint32_t oct = 0, on0 = 0, on1 = 32, on2 = 64, of0 = 16, of1 = 48, of2 = 80;
-        bool uniform_oct = false;
-        auto set_octant = [&]() {
-            const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
-                                    (ray.inv[2] < 0.0f ? 4u : 0u);
-            oct = 0;
-            if (busy_mask != 0) oct = (uint32_t)__builtin_amdgcn_readlane((int)my_oct, __builtin_ctzll(busy_mask));
-            uniform_oct = __ballot(busy && my_oct != oct) == 0;
-            // byte offsets of the near- and far-plane blocks (axis a: lo at 32 a, hi at 32 a + 16)
-            on0 = (oct & 1u) ? 16u : 0u;
-            on1 = (oct & 2u) ? 48u : 32u;
-            on2 = (oct & 4u) ? 80u : 64u;
-            of0 = on0 ^ 16u;
-            of1 = on1 ^ 16u;
-            of2 = on2 ^ 16u;
-            // opaque to the compiler (no instruction): keeps node + offset in the scalar-offset form of the loads
-            asm volatile("" : "+s"(on0), "+s"(on1), "+s"(on2), "+s"(of0), "+s"(of1), "+s"(of2));
-        };
-        set_octant();
-        float wo[3] = {ray.o[0], ray.o[1], ray.o[2]}, wd[3] = {ray.d[0], ray.d[1], ray.d[2]};   // world ray
-        uint32_t in_blas = 0u;
-        // per-lane state as 32-bit words: occ (an occluder found), live (busy and not occluded) and the
-        // slab bound, 1 (the segment's end) for live rays and -1 otherwise, so that finished rays enter
-        // no box (t0 >= 0)
-        uint32_t occ = 0u, live = busy ? 1u : 0u;
-        float bound = busy ? 1.0f : -1.0f;
-        uint32_t cur = busy_mask != 0 ? (TWO ? sc.tlas_root : 0u) : RC_STACK_EMPTY;
-        int sp = 0;
-        uint32_t stk0 = 0, stk1 = 0;   // entry e of the wave's stack lives in lane e % 64 of stk{e / 64}
-        // next entry of the wave's stack (an instance's end marker returns the rays to world space)
-        auto pop_next = [&]() -> uint32_t {
-            for (;;) {
-                if (sp == 0) return RC_STACK_EMPTY;
-                --sp;
-                const uint32_t c = BIG ? (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63)
-                                       : (uint32_t)__builtin_amdgcn_readlane((int)stk0, sp);
-                if (!TWO || c != RC_INST_RETURN) return c;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) { ray.o[a] = wo[a]; ray.d[a] = wd[a]; }
-                rc_ray_inv(ray);
-                set_octant();
-                in_blas = 0u;
-            }
-        };
-        auto push_entry = [&](uint32_t w) {
-            if (sp < 64) {
-                stk0 = (int)lane == sp ? w : stk0;
-                ++sp;
-            } else if (BIG && sp < 128) {
-                stk1 = (int)lane == sp - 64 ? w : stk1;
-                ++sp;
-            } else if (lane == 0) {
-                *P.w.error_flag = 1u;   // beyond the bound the host checked: entry dropped, reported
-            }
-        };
-        while (cur != RC_STACK_EMPTY) {
-            if (!rc_is_leaf(cur)) {
-                // 32-bit byte offsets into the node array (the host keeps it below 4 GiB for this kernel), so
-                // that each block load takes its offset in a scalar register
-                const uint32_t nofs = cur << 7;
-                auto blk = [&](uint32_t off) { return *(rc_const_v4f*)(const void*)(nodes_b + (uint32_t)(nofs + off)); };
-                uint32_t key[4];
-                if (uniform_oct)
-                    wave_keys_uniform(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, bound, key);
-                else
-                    wave_keys_mixed(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, bound, key);
-                node_visits += live;
-#define RC_CS(a, b)                                                                   \
-    {                                                                                 \
-        const uint32_t lo = min(key[a], key[b]), hi = max(key[a], key[b]);            \
-        key[a] = lo; key[b] = hi;                                                     \
-    }
-                RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
-#undef RC_CS
-                const rc_v4u chw = *(rc_const_v4u*)(const void*)(nodes_b + (uint32_t)(nofs + 96u));
-                const uint64_t c01 = ((uint64_t)chw[1] << 32) | chw[0], c23 = ((uint64_t)chw[3] << 32) | chw[2];
-                auto child = [&](uint32_t k) {
-                    const uint64_t pr = (k & 2u) ? c23 : c01;
-                    return (k & 1u) ? (uint32_t)(pr >> 32) : (uint32_t)pr;
-                };
-#pragma unroll
-                for (int c = 3; c >= 1; --c)
-                    if (key[c] < RC_KEY_MISS) push_entry(child(key[c]));
-                cur = key[0] < RC_KEY_MISS ? child(key[0]) : pop_next();
-            } else if (TWO && in_blas == 0u) {
-                // top-level leaf: map every ray into the instance and descend into its tree
-                rc_const_v4f* ip = (rc_const_v4f*)(const void*)(sc.inst + rc_leaf_first(cur));
-                const rc_v4f q0 = ip[0], q1 = ip[1], q2 = ip[2], q3 = ip[3];
-                const float W[12] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3],
-                                     q2[0], q2[1], q2[2], q2[3]};
-                rc_map_ray(W, wo, wd, ray);
-                set_octant();
-                push_entry(RC_INST_RETURN);
-                in_blas = 1u;
-                cur = __float_as_uint(q3[0]);
-            } else {
-                // every lane tests every triangle of the leaf, without lane branches: a finished lane only
-                // repeats work (its flag stays set; idle lanes' flags are never read), and the counter
-                // takes the tests of live lanes
-                const uint32_t first = rc_leaf_first(cur), cnt = rc_leaf_count(cur);
-                const uint32_t tofs = first * 48u;   // 32-bit byte offset (the host keeps the array below 4 GiB)
-                uint32_t o = occ;
-                for (uint32_t i = 0; i < cnt; ++i) {
-                    rc_const_v4f* tp = (rc_const_v4f*)(const void*)(tris_b + (uint32_t)(tofs + 48u * i));
-                    const rc_v4f A = tp[0], B = tp[1], C = tp[2];
-                    tri_tests += live & (o ^ 1u);
-                    bool hit;
-                    if (WT) {
-                        float t, u, v;
-                        hit = rc_wt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v) && t < 1.0f;
-                    } else {
-                        hit = rc_mt_segment(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z);
-                    }
-                    o |= hit ? 1u : 0u;
-                }
-                occ = o;
-                live &= o ^ 1u;
-                bound = live != 0u ? bound : -1.0f;
-                cur = __ballot(live != 0u) == 0 ? RC_STACK_EMPTY : pop_next();
-            }
-            cur = __builtin_amdgcn_readfirstlane(cur);
-        }
+        const uint32_t occ = wave_occluded<TWO, WT, BIG>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests,
+                                                         P.w.error_flag);
         const uint64_t vis = __ballot(busy && occ == 0u);
         if (in_image && (lane == 0 || k == 0)) {
             uint32_t end = (uint32_t)min<uint64_t>(64, lane + (N - k));
@@ -510,6 +526,70 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT
             uint32_t c = (uint32_t)__popcll(vis & seg);
             if (c) atomicAdd(counts + px, c);
         }
+    }
+    if (P.w.ray_count) {
+        unsigned long long cnt[3] = {rays_cast, node_visits, tri_tests};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            unsigned long long v = cnt[q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) atomicAdd(P.w.ray_count + 2 * q, v);
+        }
+    }
+}
+
+// Point-light shadow rays, wave-uniform traversal.  The 64 lanes of a wave hold 64 consecutive samples
+// (neighbouring pixels); the wave walks the tree once per light, each lane casting its sample's segment to
+// that light where the light lies above the surface, with the same tests and results as the per-lane kernel.
+// Mask bit l of a sample: the ray to light l is cast and not occluded.
+template <bool TWO, bool WT, bool BIG>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT ? 1 : 8))) void k_point_wave(KParams P, const float4* setup)
+{
+    const uint32_t lane = __lane_id();
+    const DevScene sc = P.sc;
+    const uint32_t spp = (uint32_t)(P.cam.ssaa * P.cam.ssaa);
+    const uint64_t n_blocks = ((uint64_t)P.n_items + 63) / 64;
+    uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
+    const char* nodes_b = (const char*)(const void*)sc.nodes;
+    const char* tris_b = (const char*)(const void*)sc.tris;
+    const XcdQueue<RECT_CHUNK> queue(P.w.counters, P.slot, n_blocks);
+    uint32_t pos = 0, pos_end = 0;   // wave-uniform range of claimed positions
+    for (;;) {
+        if (pos == pos_end) {
+            pos = queue.claim(P.claim);
+            pos_end = pos + P.claim;
+        }
+        const uint32_t j = pos++;
+        if (queue.exhausted(j)) break;
+        const uint64_t blk = queue.at(j);
+        if (blk >= n_blocks) continue;
+        const uint64_t item = blk * 64 + lane;
+        uint32_t px = 0, pk = 0;
+        const bool in_image = item < P.n_items && rc_item_to_sample(P.cam, (uint32_t)item, px, pk);
+        const size_t smp = (size_t)px * spp + pk;
+        float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+        if (in_image) {
+            a = setup[2 * smp];
+            b = setup[2 * smp + 1];
+        }
+        float os[3] = {a.x, a.y, a.z}, nf[3] = {b.x, b.y, b.z};
+        uint32_t mask = 0;
+        for (int l = 0; l < P.L.n_point; ++l) {
+            TravRay ray;
+            bool busy = false;
+            if (a.w != 0.0f) {
+                busy = rc_shadow_ray(P.L.point[l], P.L.rect, P.nL, false, px, (uint32_t)l, P.L.area_stream,
+                                     P.cam.seed, P.cam.frame, os, nf, ray);
+                if (busy) {
+                    rc_ray_inv(ray);
+                    ++rays_cast;
+                }
+            }
+            const uint32_t occ = wave_occluded<TWO, WT, BIG>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests,
+                                                             P.w.error_flag);
+            if (busy && occ == 0u) mask |= 1u << l;
+        }
+        if (in_image) P.mask[smp] = mask;
     }
     if (P.w.ray_count) {
         unsigned long long cnt[3] = {rays_cast, node_visits, tri_tests};
@@ -724,10 +804,11 @@ int rc_trace_grid(int device)
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, reinterpret_cast<const void*>(&k_rect_packets<false, false>), BLOCK,
                                                  TravStack<SL, BLOCK, false>::lds_bytes());
-    int e = 0, f = 0;
+    int e = 0, f = 0, g = 0;
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave<false, false, false>), BLOCK, 0);
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, reinterpret_cast<const void*>(&k_primary_wave<false>), BLOCK, 0);
-    e = std::max(e, f);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&g, reinterpret_cast<const void*>(&k_point_wave<false, false, false>), BLOCK, 0);
+    e = std::max(std::max(e, f), g);
     return std::max(std::max(std::max(a, d * n_cu), std::max(b, c)), e * n_cu);
 }
 
@@ -759,7 +840,7 @@ void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, co
 
 void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
                       uint32_t* mask, float* visibility, uint32_t* counts, float4* setup, const TraceWork& w,
-                      int grid, bool per_lane_rect, hipStream_t st)
+                      int grid, bool per_lane, hipStream_t st)
 {
     KParams P = {};
     P.sc = sc;
@@ -771,10 +852,32 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     P.w = w;
     P.n_items = rc_n_items(cam.width, cam.height, cam.ssaa);
     const bool two = sc.inst != nullptr, wt = sc.watertight != 0u;
+    // the wave-uniform kernels (the default) address nodes and triangles by 32-bit byte offsets and hold
+    // at most 128 stack entries; they read each sample's shadow-ray origin and normal from `setup`
+    const bool wave = sc.max_stack <= 128 && !per_lane && sc.n_nodes < (1u << 25) &&
+                      (uint64_t)sc.n_tris * 48u < (1ull << 32);
+    if (wave && ((L.n_point > 0 && !wt) || L.has_rect)) {
+        // one setup entry per sample of the image (the item count is padded to whole tiles)
+        const uint32_t n_samples = (uint32_t)(cam.width * cam.height * cam.ssaa * cam.ssaa);
+        hipLaunchKernelGGL(k_shadow_setup, dim3((n_samples + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_samples,
+                           setup);
+    }
     if (L.n_point > 0) {
         P.slot = 1;
-        P.claim = claim_size(P.n_items, grid, 16, 32, 128);
-        RC_LAUNCH_TW((k_trace<MODE_POINT, RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
+        // with the watertight test (its FP64 fallback branches per lane) the per-lane kernel measured faster
+        // for one ray per sample and light
+        if (wave && !wt) {
+            P.claim = claim_size((P.n_items + 63) / 64, grid, 64, 1, 4);
+            if (sc.max_stack <= 64)
+                RC_LAUNCH_TW((k_point_wave<RC_TWO, RC_WT, false>), dim3(grid), dim3(BLOCK), 0, st, P,
+                             (const float4*)setup);
+            else
+                RC_LAUNCH_TW((k_point_wave<RC_TWO, RC_WT, true>), dim3(grid), dim3(BLOCK), 0, st, P,
+                             (const float4*)setup);
+        } else {
+            P.claim = claim_size(P.n_items, grid, 16, 32, 128);
+            RC_LAUNCH_TW((k_trace<MODE_POINT, RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
+        }
     }
     if (L.has_rect) {
         // unit normal of the emitting side, from FP64 and rounded once
@@ -789,11 +892,8 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         rc_launch_fill_u32(counts, 0u, n_pix, st);
         // the wave-uniform traversal, at every sample count: a wave holds the samples of one pixel, or of
         // 64 / N neighbouring pixels, whose rays start close together (measured faster than the per-lane
-        // kernel from one sample per pixel on); it addresses nodes and triangles by 32-bit byte offsets
-        if (sc.max_stack <= 128 && !per_lane_rect && sc.n_nodes < (1u << 25) &&
-            (uint64_t)sc.n_tris * 48u < (1ull << 32)) {
-            hipLaunchKernelGGL(k_shadow_setup, dim3((n_pix + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_pix,
-                               setup);
+        // kernel from one sample per pixel on)
+        if (wave) {
             if (sc.max_stack <= 64)
                 RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, false>), dim3(grid), dim3(BLOCK), 0, st, P, counts,
                              (const float4*)setup);

@@ -666,20 +666,21 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     rc_launch_primary(ds, dc, gbuf, w, c->grid, opts && (opts->flags & RC_FLAG_PER_LANE), q);
     if (timing) RC_HIP(hipEventRecord(c->ev[1], q));
     if (n_lights > 0 || rect) {
-        size_t n_pix = (size_t)cam->width * cam->height;
-        // per pixel: one visible-sample counter, then (16-byte aligned) two float4 of shadow-ray setup
-        const size_t setup_off = (n_pix + 3) & ~(size_t)3;
-        if (rect && n_pix > c->counts_cap) {
+        const size_t n_pix = (size_t)cam->width * cam->height, n_samples = n_pix * cam->ssaa * cam->ssaa;
+        // per pixel one visible-sample counter of the rect light, then (16-byte aligned) per sample two float4
+        // of shadow-ray setup (origin, normal) for the wave-uniform shadow kernels
+        const size_t setup_off = (n_pix + 3) & ~(size_t)3, words = setup_off + 8 * n_samples;
+        if (words > c->counts_cap) {
             RC_HIP(hipStreamSynchronize(q));
             dev_free(c->d_counts);
             c->counts_cap = 0;
-            st = dev_alloc(&c->d_counts, setup_off + 8 * n_pix);
+            st = dev_alloc(&c->d_counts, words);
             if (st != RC_OK) return st;
-            c->counts_cap = n_pix;
+            c->counts_cap = words;
         }
         w.ray_count = c->d_rays + 1;
         bool per_lane = opts && (opts->flags & RC_FLAG_PER_LANE);
-        float4* setup = rect ? reinterpret_cast<float4*>(c->d_counts + setup_off) : nullptr;
+        float4* setup = reinterpret_cast<float4*>(c->d_counts + setup_off);
         rc_launch_shadow(ds, dc, L, gbuf, out->d_shadow, out->d_visibility, c->d_counts, setup, w, c->grid, per_lane,
                          q);
     }

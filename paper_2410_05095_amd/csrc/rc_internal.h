@@ -129,7 +129,7 @@ void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, co
                        int grid, bool per_lane, hipStream_t st);
 void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
                       uint32_t* mask, float* visibility, uint32_t* counts, float4* setup, const TraceWork& w,
-                      int grid, bool per_lane_rect, hipStream_t st);
+                      int grid, bool per_lane, hipStream_t st);
 int rc_trace_grid(int device);
 // Display post pass (k_post.hip): tone map + sRGB8 into `out`, or into `scratch` followed by FXAA into `out`
 void rc_launch_postprocess(const float* rgba, uint32_t w, uint32_t h, bool fxaa, uint8_t* scratch, uint8_t* out,

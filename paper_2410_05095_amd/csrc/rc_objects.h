@@ -13,8 +13,8 @@ struct rc_ctx {
     unsigned long long* d_rays = nullptr; // [0] primary, [1] shadow rays cast
     uint32_t* d_overflow = nullptr;
     size_t overflow_words = 0;
-    uint32_t* d_counts = nullptr;         // per-pixel visible-sample counters of the rect light
-    size_t counts_cap = 0;
+    uint32_t* d_counts = nullptr;         // rect-light counters per pixel, then shadow-ray setup per sample
+    size_t counts_cap = 0;                // in 32-bit words
     uint8_t* d_post = nullptr;            // tone-mapped image between the two post-pass kernels
     size_t post_cap = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
