@@ -236,8 +236,7 @@ enum {
     RC_FLAG_TIMING = 1u,     /* record per-stage device times (rc_get_stage_times) */
     RC_FLAG_PER_LANE = 4u      /* trace camera rays and shadow rays one ray per lane with per-lane stacks
                                   even where the wave-uniform traversal would be used (camera rays with
-                                  ssaa = 2; point-light shadow rays without the watertight test and rect-
-                                  light shadow rays always; BVH depth <= 42,
+                                  ssaa = 2; point- and rect-light shadow rays always; BVH depth <= 42,
                                   under 2^25 nodes and 2^32 bytes of packed triangles); same results
                                   outside the FP32 band, for comparison */
 };

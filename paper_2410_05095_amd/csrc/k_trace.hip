@@ -458,13 +458,8 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const De
                 rc_const_v4f* tp = (rc_const_v4f*)(const void*)(tris_b + (uint32_t)(tofs + 48u * i));
                 const rc_v4f A = tp[0], B = tp[1], C = tp[2];
                 tri_tests += live & (o ^ 1u);
-                bool hit;
-                if (WT) {
-                    float t, u, v;
-                    hit = rc_wt(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z, t, u, v) && t < 1.0f;
-                } else {
-                    hit = rc_mt_segment(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z);
-                }
+                const bool hit = WT ? rc_wt_segment(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z)
+                                    : rc_mt_segment(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z);
                 o |= hit ? 1u : 0u;
             }
             occ = o;
@@ -856,7 +851,7 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     // at most 128 stack entries; they read each sample's shadow-ray origin and normal from `setup`
     const bool wave = sc.max_stack <= 128 && !per_lane && sc.n_nodes < (1u << 25) &&
                       (uint64_t)sc.n_tris * 48u < (1ull << 32);
-    if (wave && ((L.n_point > 0 && !wt) || L.has_rect)) {
+    if (wave && (L.n_point > 0 || L.has_rect)) {
         // one setup entry per sample of the image (the item count is padded to whole tiles)
         const uint32_t n_samples = (uint32_t)(cam.width * cam.height * cam.ssaa * cam.ssaa);
         hipLaunchKernelGGL(k_shadow_setup, dim3((n_samples + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_samples,
@@ -864,9 +859,7 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     }
     if (L.n_point > 0) {
         P.slot = 1;
-        // with the watertight test (its FP64 fallback branches per lane) the per-lane kernel measured faster
-        // for one ray per sample and light
-        if (wave && !wt) {
+        if (wave) {
             P.claim = claim_size((P.n_items + 63) / 64, grid, 64, 1, 4);
             if (sc.max_stack <= 64)
                 RC_LAUNCH_TW((k_point_wave<RC_TWO, RC_WT, false>), dim3(grid), dim3(BLOCK), 0, st, P,

@@ -20,6 +20,14 @@ struct TravRay {
 
 __device__ inline float rc_axis(const float v[3], uint32_t k) { return k == 0u ? v[0] : (k == 1u ? v[1] : v[2]); }
 
+// a, b or c for k = 0, 1, 2, as two selects (a nested conditional or an indexed array compiled into per-lane
+// branches or scratch memory in the triangle tests)
+__device__ inline float rc_pick(float a, float b, float c, uint32_t k)
+{
+    const float ab = k == 0u ? a : b;
+    return k == 2u ? c : ab;
+}
+
 struct TravState {
     uint32_t cur;       // child word being processed (node index or leaf), or RC_STACK_EMPTY
     int sp;
@@ -329,17 +337,17 @@ __device__ inline bool rc_mt_segment(const TravRay& r, float ax, float ay, float
 __device__ inline bool rc_wt(const TravRay& r, float ax, float ay, float az, float bx, float by, float bz, float cx,
                              float cy, float cz, float& t, float& u, float& v)
 {
-    const float A[3] = {ax - r.o[0], ay - r.o[1], az - r.o[2]};
-    const float B[3] = {bx - r.o[0], by - r.o[1], bz - r.o[2]};
-    const float C[3] = {cx - r.o[0], cy - r.o[1], cz - r.o[2]};
-    const float Akz = rc_axis(A, r.kz), Bkz = rc_axis(B, r.kz), Ckz = rc_axis(C, r.kz);
+    const float A0 = ax - r.o[0], A1 = ay - r.o[1], A2 = az - r.o[2];
+    const float B0 = bx - r.o[0], B1 = by - r.o[1], B2 = bz - r.o[2];
+    const float C0 = cx - r.o[0], C1 = cy - r.o[1], C2 = cz - r.o[2];
+    const float Akz = rc_pick(A0, A1, A2, r.kz), Bkz = rc_pick(B0, B1, B2, r.kz), Ckz = rc_pick(C0, C1, C2, r.kz);
     float p, q;
-    p = r.sx * Akz; const float Ax = rc_axis(A, r.kx) - p;
-    p = r.sy * Akz; const float Ay = rc_axis(A, r.ky) - p;
-    p = r.sx * Bkz; const float Bx = rc_axis(B, r.kx) - p;
-    p = r.sy * Bkz; const float By = rc_axis(B, r.ky) - p;
-    p = r.sx * Ckz; const float Cx = rc_axis(C, r.kx) - p;
-    p = r.sy * Ckz; const float Cy = rc_axis(C, r.ky) - p;
+    p = r.sx * Akz; const float Ax = rc_pick(A0, A1, A2, r.kx) - p;
+    p = r.sy * Akz; const float Ay = rc_pick(A0, A1, A2, r.ky) - p;
+    p = r.sx * Bkz; const float Bx = rc_pick(B0, B1, B2, r.kx) - p;
+    p = r.sy * Bkz; const float By = rc_pick(B0, B1, B2, r.ky) - p;
+    p = r.sx * Ckz; const float Cx = rc_pick(C0, C1, C2, r.kx) - p;
+    p = r.sy * Ckz; const float Cy = rc_pick(C0, C1, C2, r.ky) - p;
     p = Cx * By; q = Cy * Bx; float U = p - q;
     p = Ax * Cy; q = Ay * Cx; float V = p - q;
     p = Bx * Ay; q = By * Ax; float W = p - q;
@@ -363,6 +371,55 @@ __device__ inline bool rc_wt(const TravRay& r, float ax, float ay, float az, flo
     u = V * rcp;
     v = W * rcp;
     return t > 0.0f;
+}
+
+// rc_wt's arithmetic for the wave kernels (called by whole waves), for a segment: whether the ray crosses the
+// triangle at 0 < t < 1.  The FP64 recomputation of the edge functions runs when some lane of the wave has one
+// exactly zero, and applies to those lanes; the sign test is min(U, V, W) < 0 < max(U, V, W) on the sign
+// bits (-0 and +0 count as zero, as in rc_wt; U, V, W are finite for finite scenes); det = 0 makes t
+// infinite or NaN, which fails the range test as rc_wt's det test does; the wave skips the depth once no
+// lane is inside all three edges.
+__device__ inline bool rc_wt_segment(const TravRay& r, float ax, float ay, float az, float bx, float by, float bz,
+                                     float cx, float cy, float cz)
+{
+    const float A0 = ax - r.o[0], A1 = ay - r.o[1], A2 = az - r.o[2];
+    const float B0 = bx - r.o[0], B1 = by - r.o[1], B2 = bz - r.o[2];
+    const float C0 = cx - r.o[0], C1 = cy - r.o[1], C2 = cz - r.o[2];
+    const float Akz = rc_pick(A0, A1, A2, r.kz), Bkz = rc_pick(B0, B1, B2, r.kz), Ckz = rc_pick(C0, C1, C2, r.kz);
+    float p, q;
+    p = r.sx * Akz; const float Ax = rc_pick(A0, A1, A2, r.kx) - p;
+    p = r.sy * Akz; const float Ay = rc_pick(A0, A1, A2, r.ky) - p;
+    p = r.sx * Bkz; const float Bx = rc_pick(B0, B1, B2, r.kx) - p;
+    p = r.sy * Bkz; const float By = rc_pick(B0, B1, B2, r.ky) - p;
+    p = r.sx * Ckz; const float Cx = rc_pick(C0, C1, C2, r.kx) - p;
+    p = r.sy * Ckz; const float Cy = rc_pick(C0, C1, C2, r.ky) - p;
+    p = Cx * By; q = Cy * Bx; float U = p - q;
+    p = Ax * Cy; q = Ay * Cx; float V = p - q;
+    p = Bx * Ay; q = By * Ax; float W = p - q;
+    const bool z = U == 0.0f || V == 0.0f || W == 0.0f;
+    if (__ballot(z) != 0) {
+        const float U2 = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        const float V2 = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        const float W2 = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+        U = z ? U2 : U;
+        V = z ? V2 : V;
+        W = z ? W2 : W;
+    }
+    // all ones when one edge function is negative and another positive (x + 0 and 0 - x turn -0 into +0)
+    const float mn = fminf(fminf(U, V), W), mx = fmaxf(fmaxf(U, V), W);
+    const uint32_t mixed = (uint32_t)((int32_t)__float_as_uint(mn + 0.0f) >> 31) &
+                           (uint32_t)((int32_t)__float_as_uint(0.0f - mx) >> 31);
+    if (__ballot(mixed == 0u) == 0) return false;
+    float det = U + V;
+    det = det + W;
+    const float Az = r.sz * Akz, Bz = r.sz * Bkz, Cz = r.sz * Ckz;
+    p = U * Az;
+    q = V * Bz;
+    float T = p + q;
+    p = W * Cz;
+    T = T + p;
+    const float t = T * __builtin_amdgcn_rcpf(det);
+    return ((__float_as_uint(t) - 1u) | mixed) < 0x3F7FFFFFu;
 }
 
 // The triangle test of the scene: Moller-Trumbore on (v0, e1, e2) records, or the watertight test on
