@@ -22,10 +22,10 @@ HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES = 128, 48
 # FP32 lane-operations of the traversal as written (selects not counted; an FMA is one operation, as it
 # issues as one): per 4-wide node visit 4 x (6 FMA for the plane distances, 3 max with 0, 3 min with the
-# bound, 1 compare) + 5 sorting compares = 57; per Moller-Trumbore test 2 cross products (12 mul, 6 sub),
-# 3 dot products (9 mul, 6 add), 3 sub, 1 reciprocal, 3 mul by it, 1 add and 5 compares for the hit
-# conditions = 51.
-NODE_OPS, TRI_OPS = 57, 51
+# bound, 1 compare) + 5 sorting compares = 57; per Moller-Trumbore test 2 cross products (6 mul, 6 FMA),
+# 4 dot products (4 mul, 8 FMA), 3 sub, 1 reciprocal, 3 mul by it, 1 add and 5 compares for the hit
+# conditions = 37.
+NODE_OPS, TRI_OPS = 57, 37
 # Issue peak of non-packed FP32 vector ops: 256 CUs x 64 lanes per clock x 2.4 GHz (the 157.3 TFLOP/s
 # datasheet figure counts packed FMAs, i.e. 4 FLOP per lane and clock).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12

@@ -297,6 +297,9 @@ typedef uint32_t rc_v4u __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) rc_v4u rc_const_v4u;
 
 extern "C" __device__ uint32_t __ockl_wfred_max_u32(uint32_t);   // ROCm device library: wavefront maximum
+// the compiler intrinsic behind v_writelane_b32 (no clang builtin in this toolchain): returns `old` with lane
+// `lane` (wave-uniform) replaced by the wave-uniform `value`
+extern "C" __device__ int rc_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
 #define RC_KEY_MISS 0x7F800000u   // keys >= this: no live ray enters the child
 
@@ -398,10 +401,10 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const De
     };
     auto push_entry = [&](uint32_t w) {
         if (sp < 64) {
-            stk0 = (int)lane == sp ? w : stk0;
+            stk0 = (uint32_t)rc_writelane((int)w, sp, (int)stk0);
             ++sp;
         } else if (BIG && sp < 128) {
-            stk1 = (int)lane == sp - 64 ? w : stk1;
+            stk1 = (uint32_t)rc_writelane((int)w, sp - 64, (int)stk1);
             ++sp;
         } else if (lane == 0) {
             *error_flag = 1u;   // beyond the bound the host checked: entry dropped, reported
@@ -432,9 +435,19 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const De
                 const uint64_t pr = (k & 2u) ? c23 : c01;
                 return (k & 1u) ? (uint32_t)(pr >> 32) : (uint32_t)pr;
             };
+            if (sp <= 61) {
+                // room for the (at most 3) pushes of this node in the first stack register
 #pragma unroll
-            for (int c = 3; c >= 1; --c)
-                if (key[c] < RC_KEY_MISS) push_entry(child(key[c]));
+                for (int c = 3; c >= 1; --c)
+                    if (key[c] < RC_KEY_MISS) {
+                        stk0 = (uint32_t)rc_writelane((int)child(key[c]), sp, (int)stk0);
+                        ++sp;
+                    }
+            } else {
+#pragma unroll
+                for (int c = 3; c >= 1; --c)
+                    if (key[c] < RC_KEY_MISS) push_entry(child(key[c]));
+            }
             cur = key[0] < RC_KEY_MISS ? child(key[0]) : pop_next();
         } else if (TWO && in_blas == 0u) {
             // top-level leaf: map every ray into the instance and descend into its tree

@@ -261,34 +261,33 @@ __device__ inline void trav_visit_node(const DevScene& sc, TravRay& r, TravState
 }
 
 // Moller-Trumbore in FP32 on a packed triangle (v0, e1, e2): the fixed operation order every traversal
-// kernel uses.  Returns whether the ray's line crosses the triangle at t > 0 (edges inclusive).
+// kernel uses.  Each cross-product component is fma(a, b, -(c d)) and each dot product
+// fma(z, z', fma(y, y', x x')): one rounding per FMA, so every result stays within the running forward-error
+// bound of the unfused evaluation (product roundings and sum roundings counted separately).  Returns whether
+// the ray's line crosses the triangle at t > 0 (edges inclusive).
 __device__ inline bool rc_mt(const TravRay& r, float ax, float ay, float az, float bx, float by, float bz, float cx,
                              float cy, float cz, float& t, float& u, float& v)
 {
-    float px_ = r.d[1] * cz - r.d[2] * cy;
-    float py_ = r.d[2] * cx - r.d[0] * cz;
-    float pz_ = r.d[0] * cy - r.d[1] * cx;
-    float det = bx * px_ + by * py_;
-    det = det + bz * pz_;
-    float idet = __builtin_amdgcn_rcpf(det);
-    float sx = r.o[0] - ax, sy = r.o[1] - ay, sz = r.o[2] - az;
-    float su = sx * px_ + sy * py_;
-    su = su + sz * pz_;
+    const float px_ = fmaf(r.d[1], cz, -(r.d[2] * cy));
+    const float py_ = fmaf(r.d[2], cx, -(r.d[0] * cz));
+    const float pz_ = fmaf(r.d[0], cy, -(r.d[1] * cx));
+    const float det = fmaf(bz, pz_, fmaf(by, py_, bx * px_));
+    const float idet = __builtin_amdgcn_rcpf(det);
+    const float sx = r.o[0] - ax, sy = r.o[1] - ay, sz = r.o[2] - az;
+    const float su = fmaf(sz, pz_, fmaf(sy, py_, sx * px_));
     u = su * idet;
     t = 0.0f;
     v = 0.0f;
     // staged so that a wave skips the rest once no lane can still hit; u > 1 fails as u + v <= 1 would
     // (v >= 0 makes the rounded u + v at least u), so every decision is the unstaged test's
     if (!(u >= 0.0f && u <= 1.0f)) return false;
-    float qx = sy * bz - sz * by;
-    float qy = sz * bx - sx * bz;
-    float qz = sx * by - sy * bx;
-    float sv = r.d[0] * qx + r.d[1] * qy;
-    sv = sv + r.d[2] * qz;
+    const float qx = fmaf(sy, bz, -(sz * by));
+    const float qy = fmaf(sz, bx, -(sx * bz));
+    const float qz = fmaf(sx, by, -(sy * bx));
+    const float sv = fmaf(r.d[2], qz, fmaf(r.d[1], qy, r.d[0] * qx));
     v = sv * idet;
     if (!(v >= 0.0f && u + v <= 1.0f)) return false;
-    float stq = cx * qx + cy * qy;
-    stq = stq + cz * qz;
+    const float stq = fmaf(cz, qz, fmaf(cy, qy, cx * qx));
     t = stq * idet;
     return t > 0.0f;
 }
@@ -303,25 +302,21 @@ __device__ inline bool rc_mt(const TravRay& r, float ax, float ay, float az, flo
 __device__ inline bool rc_mt_segment(const TravRay& r, float ax, float ay, float az, float bx, float by, float bz,
                                      float cx, float cy, float cz)
 {
-    float px_ = r.d[1] * cz - r.d[2] * cy;
-    float py_ = r.d[2] * cx - r.d[0] * cz;
-    float pz_ = r.d[0] * cy - r.d[1] * cx;
-    float det = bx * px_ + by * py_;
-    det = det + bz * pz_;
-    float idet = __builtin_amdgcn_rcpf(det);
-    float sx = r.o[0] - ax, sy = r.o[1] - ay, sz = r.o[2] - az;
-    float su = sx * px_ + sy * py_;
-    su = su + sz * pz_;
+    const float px_ = fmaf(r.d[1], cz, -(r.d[2] * cy));
+    const float py_ = fmaf(r.d[2], cx, -(r.d[0] * cz));
+    const float pz_ = fmaf(r.d[0], cy, -(r.d[1] * cx));
+    const float det = fmaf(bz, pz_, fmaf(by, py_, bx * px_));
+    const float idet = __builtin_amdgcn_rcpf(det);
+    const float sx = r.o[0] - ax, sy = r.o[1] - ay, sz = r.o[2] - az;
+    const float su = fmaf(sz, pz_, fmaf(sy, py_, sx * px_));
     const float u = su * idet;
     if (__ballot(u >= 0.0f && u <= 1.0f) == 0) return false;
-    float qx = sy * bz - sz * by;
-    float qy = sz * bx - sx * bz;
-    float qz = sx * by - sy * bx;
-    float sv = r.d[0] * qx + r.d[1] * qy;
-    sv = sv + r.d[2] * qz;
+    const float qx = fmaf(sy, bz, -(sz * by));
+    const float qy = fmaf(sz, bx, -(sx * bz));
+    const float qz = fmaf(sx, by, -(sy * bx));
+    const float sv = fmaf(r.d[2], qz, fmaf(r.d[1], qy, r.d[0] * qx));
     const float v = sv * idet;
-    float stq = cx * qx + cy * qy;
-    stq = stq + cz * qz;
+    const float stq = fmaf(cz, qz, fmaf(cy, qy, cx * qx));
     const float t = stq * idet;
     const float m = fminf(fminf(u, v), 1.0f - (u + v));
     // all ones when m < 0 (m + 0 turns -0 into +0, which passes like u >= 0 does for u = -0)
