@@ -293,6 +293,8 @@ __global__ __launch_bounds__(256) void k_shadow_setup(DevScene sc, DevCamera cam
 // node are loaded at byte offsets picked by the octant; otherwise each lane picks its own planes.
 typedef float rc_v4f __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) rc_v4f rc_const_v4f;
+typedef float rc_v8f __attribute__((ext_vector_type(8)));
+typedef const __attribute__((address_space(4))) rc_v8f rc_const_v8f;
 typedef uint32_t rc_v4u __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) rc_v4u rc_const_v4u;
 
@@ -343,15 +345,17 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
 // Two-level structures: at a top-level leaf every lane maps its ray into the instance (rc_map_ray), the
 // wave pushes an end marker and descends into the instance's tree; popping the marker restores the world
 // rays (and the wave's octant).
-// Any-hit traversal of the segments o + t d, 0 <= t <= 1, of a wave's rays (called by all 64 lanes; busy
-// lanes hold a ray whose traversal constants rc_ray_inv set): returns 1 in the lanes whose segment is
-// occluded.  BIG: the stack spans two registers (128 entries); otherwise one (64 entries, when
-// 3 x depth + 1 <= 64).
-template <bool TWO, bool WT, bool BIG>
-__device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const DevScene& sc, const char* nodes_b,
-                                                                      const char* tris_b, TravRay& ray, bool busy,
-                                                                      uint32_t& node_visits, uint32_t& tri_tests,
-                                                                      uint32_t* error_flag)
+// The walk of wave_occluded.  BIG: the stack spans two registers (128 entries); otherwise one (64 entries,
+// when 3 x depth + 1 <= 64).
+// OCT: 0..7, every busy ray in that direction octant (fixed for the whole walk, as in flat trees): the node's
+// plane blocks come with three 32-byte loads at constant offsets and the near/far choice is made when
+// compiling; 8: mixed octants (each lane picks its planes); -1: decided at run time, per instance for
+// two-level structures (the mapped rays' octant changes at each instance).
+template <bool TWO, bool WT, bool BIG, int OCT>
+__device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevScene& sc, const char* nodes_b,
+                                                                  const char* tris_b, TravRay& ray, bool busy,
+                                                                  uint32_t& node_visits, uint32_t& tri_tests,
+                                                                  uint32_t* error_flag)
 {
     const uint32_t lane = __lane_id();
     const uint64_t busy_mask = __ballot(busy);
@@ -373,7 +377,7 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const De
         // opaque to the compiler (no instruction): keeps node + offset in the scalar-offset form of the loads
         asm volatile("" : "+s"(on0), "+s"(on1), "+s"(on2), "+s"(of0), "+s"(of1), "+s"(of2));
     };
-    set_octant();
+    if constexpr (OCT < 0) set_octant();
     float wo[3] = {ray.o[0], ray.o[1], ray.o[2]}, wd[3] = {ray.d[0], ray.d[1], ray.d[2]};   // world ray
     uint32_t in_blas = 0u;
     // per-lane state as 32-bit words: occ (an occluder found), live (busy and not occluded) and the
@@ -417,10 +421,22 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const De
             const uint32_t nofs = cur << 7;
             auto blk = [&](uint32_t off) { return *(rc_const_v4f*)(const void*)(nodes_b + (uint32_t)(nofs + off)); };
             uint32_t key[4];
-            if (uniform_oct)
+            if constexpr (OCT >= 0) {
+                // axis a: lo[4] then hi[4] in one 32-byte block at 32 a
+                const char* np = nodes_b + nofs;
+                const rc_v8f X = *(rc_const_v8f*)(const void*)np, Y = *(rc_const_v8f*)(const void*)(np + 32),
+                             Z = *(rc_const_v8f*)(const void*)(np + 64);
+                const rc_v4f lx = X.lo, hx = X.hi, ly = Y.lo, hy = Y.hi, lz = Z.lo, hz = Z.hi;
+                if constexpr (OCT < 8)
+                    wave_keys_uniform((OCT & 1) ? hx : lx, (OCT & 1) ? lx : hx, (OCT & 2) ? hy : ly,
+                                      (OCT & 2) ? ly : hy, (OCT & 4) ? hz : lz, (OCT & 4) ? lz : hz, ray, bound, key);
+                else
+                    wave_keys_mixed(lx, hx, ly, hy, lz, hz, ray, bound, key);
+            } else if (uniform_oct) {
                 wave_keys_uniform(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, bound, key);
-            else
+            } else {
                 wave_keys_mixed(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, bound, key);
+            }
             node_visits += live;
 #define RC_CS(a, b)                                                                   \
 {                                                                                 \
@@ -429,7 +445,8 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const De
 }
             RC_CS(0, 1) RC_CS(2, 3) RC_CS(0, 2) RC_CS(1, 3) RC_CS(1, 2)
 #undef RC_CS
-            const rc_v4u chw = *(rc_const_v4u*)(const void*)(nodes_b + (uint32_t)(nofs + 96u));
+            const rc_v4u chw = OCT >= 0 ? *(rc_const_v4u*)(const void*)(nodes_b + nofs + 96u)
+                                        : *(rc_const_v4u*)(const void*)(nodes_b + (uint32_t)(nofs + 96u));
             const uint64_t c01 = ((uint64_t)chw[1] << 32) | chw[0], c23 = ((uint64_t)chw[3] << 32) | chw[2];
             auto child = [&](uint32_t k) {
                 const uint64_t pr = (k & 2u) ? c23 : c01;
@@ -483,6 +500,40 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const De
         cur = __builtin_amdgcn_readfirstlane(cur);
     }
     return occ;
+}
+
+// Any-hit traversal of the segments o + t d, 0 <= t <= 1, of a wave's rays (called by all 64 lanes; busy
+// lanes hold a ray whose traversal constants rc_ray_inv set): returns 1 in the lanes whose segment is
+// occluded.  Flat trees: one walk specialised for the wave's octant, or for mixed octants.
+template <bool TWO, bool WT, bool BIG>
+__device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const DevScene& sc, const char* nodes_b,
+                                                                      const char* tris_b, TravRay& ray, bool busy,
+                                                                      uint32_t& node_visits, uint32_t& tri_tests,
+                                                                      uint32_t* error_flag)
+{
+#define RC_WALK(o) wave_walk<TWO, WT, BIG, o>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag)
+    if constexpr (TWO) {
+        return RC_WALK(-1);
+    } else {
+        const uint64_t busy_mask = __ballot(busy);
+        const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
+                                (ray.inv[2] < 0.0f ? 4u : 0u);
+        const uint32_t oct = busy_mask != 0
+                                 ? (uint32_t)__builtin_amdgcn_readlane((int)my_oct, __builtin_ctzll(busy_mask))
+                                 : 0u;
+        if (__ballot(busy && my_oct != oct) != 0) return RC_WALK(8);
+        switch (oct) {
+        case 0: return RC_WALK(0);
+        case 1: return RC_WALK(1);
+        case 2: return RC_WALK(2);
+        case 3: return RC_WALK(3);
+        case 4: return RC_WALK(4);
+        case 5: return RC_WALK(5);
+        case 6: return RC_WALK(6);
+        default: return RC_WALK(7);
+        }
+    }
+#undef RC_WALK
 }
 
 template <bool TWO, bool WT, bool BIG>
