@@ -14,6 +14,10 @@
 
 #include "rc_unet.h"
 
+#ifndef RC_CONV_ROWS
+#define RC_CONV_ROWS 8   // output rows per wave of the row-blocked convolution
+#endif
+
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
@@ -295,6 +299,135 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
             v = pack8(f);
         }
         *reinterpret_cast<uint4*>(a.out + o) = v;
+    }
+}
+
+// ---------------------------------------------------------------- 3x3 convolution, row-blocked
+// For up to 32 output channels (NT <= 2) and Cin a multiple of 32.  With one row per wave (k_conv_lds) an
+// A fragment read from LDS feeds only NT MFMAs, so these layers wait on LDS reads.  Here each wave owns R
+// output rows x 16 pixels and walks the R + 2 halo rows: the fragment of halo row h and horizontal tap dx is
+// read once and serves the vertical taps dy = 0, 1, 2 of output rows h - dy (up to 3 NT MFMAs per read).
+// Workgroup: 4 waves side by side (tile R rows x 64 columns); per chunk of 32 input channels the halo is
+// staged in LDS (zero outside the image, the same two-source loader as k_conv_lds) and the chunk's
+// weights, 9 taps x NT fragments, stay in registers.  Each output row still sums its taps in the order
+// tap = 3 dy + dx within a chunk, as k_conv_lds does with 32-channel chunks.
+template <int R, int NT>
+struct ConvRows {
+    static constexpr int TW = 64, HW = TW + 2, HR = R + 2, CC = 32, PST = CC + 8;
+    static constexpr int HALO_U4 = (HR * HW * PST * 2 + 15) / 16;
+    static constexpr size_t bytes()
+    {
+        const size_t in = (size_t)HALO_U4 * 16, out = (size_t)4 * R * 16 * 16 * NT * 2;
+        return in > out ? in : out;
+    }
+};
+
+template <int R, int NT>
+__global__ __launch_bounds__(256) void k_conv_rows(ConvArgs a)
+{
+    extern __shared__ uint4 conv_lds[];
+    using L = ConvRows<R, NT>;
+    constexpr int TW = L::TW, HW = L::HW, HR = L::HR, PST = L::PST, CC = L::CC;
+    uint16_t* lds = reinterpret_cast<uint16_t*>(conv_lds);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + R - 1) / R;
+    int tt = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tt % tiles_x;
+    tt /= tiles_x;
+    const int ty = tt % tiles_y, n = tt / tiles_y;
+    const int x0 = tx * TW, y0 = ty * R;
+    const int r = lane & 15, g = lane >> 4;
+    const int K = 9 * a.Cin;
+    const int Cs = a.Cin - a.Ca;
+    f32x4 acc[R][NT];
+#pragma unroll
+    for (int o = 0; o < R; ++o)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[o][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    for (int c0 = 0; c0 < a.Cin; c0 += CC) {
+        // weight fragment (tap, nt) of lane l: output channel 16 nt + (l & 15), input channels
+        // c0 + 8 (l >> 4) .. + 8 of that tap
+        bf16x8 B[9][NT];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = 16 * nt + r;
+                B[tap][nt] = co < a.Cout ? load8(a.wt + (size_t)co * K + tap * a.Cin + c0 + 8 * g) : zero;
+            }
+        __syncthreads();
+        constexpr int GROUPS = CC / 8;
+        for (int i = threadIdx.x; i < HR * HW * GROUPS; i += 256) {
+            const int gg = i % GROUPS, pix = i / GROUPS;
+            const int hx = pix % HW, hy = pix / HW;
+            const int y = y0 - 1 + hy, x = x0 - 1 + hx;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
+                const int ci = c0 + 8 * gg;
+                if (a.in2 == nullptr)
+                    v = *reinterpret_cast<const uint4*>(a.in + ((size_t)(n * a.H + y) * a.W + x) * a.Cin + ci);
+                else if (ci < a.Ca)
+                    v = *reinterpret_cast<const uint4*>(
+                        a.in + ((size_t)(n * (a.H / 2) + y / 2) * (a.W / 2) + x / 2) * a.Ca + ci);
+                else
+                    v = *reinterpret_cast<const uint4*>(a.in2 + ((size_t)(n * a.H + y) * a.W + x) * Cs + (ci - a.Ca));
+            }
+            *reinterpret_cast<uint4*>(lds + pix * PST + 8 * gg) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < HR; ++h)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const bf16x8 A = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4*>(lds + (h * HW + 16 * wave + r + dx) * PST + 8 * g));
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const int o = h - dy;
+                    if (o >= 0 && o < R) {
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[o][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[3 * dy + dx][nt], acc[o][nt],
+                                                                                  0, 0, 0);
+                    }
+                }
+            }
+    }
+    // epilogue through LDS, as in k_conv_lds: per wave R rows of 16 pixels x 16 NT channels
+    constexpr int TC = 16 * NT;
+    __syncthreads();
+    uint16_t* tile = lds + (size_t)wave * R * 16 * TC;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int co = 16 * nt + r;
+        const float b = (a.bias && co < a.Cout) ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int o = 0; o < R; ++o)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[o][nt][i] + b;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                tile[(o * 16 + 4 * g + i) * TC + co] = f2bf(v);
+            }
+    }
+    __syncthreads();
+    const int c8n = a.Cout / 8;
+    for (int q = lane; q < R * 16 * c8n; q += 64) {
+        const int px = q / c8n, c8 = q - px * c8n;
+        const int o = px / 16, x = x0 + 16 * wave + (px % 16), y = y0 + o;
+        if (x >= a.W || y >= a.H) continue;
+        uint4 v = *reinterpret_cast<const uint4*>(tile + px * TC + 8 * c8);
+        const size_t off = ((size_t)(n * a.H + y) * a.W + x) * a.Cout + 8 * c8;
+        if (a.mask) {
+            float f[8], mk[8];
+            unpack8(v, f);
+            unpack8(*reinterpret_cast<const uint4*>(a.mask + off), mk);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) f[e] = mk[e] > 0.0f ? f[e] : 0.0f;
+            v = pack8(f);
+        }
+        *reinterpret_cast<uint4*>(a.out + off) = v;
     }
 }
 
@@ -883,10 +1016,19 @@ void launch_conv_lds(const ConvArgs& a, hipStream_t st)
     hipLaunchKernelGGL((k_conv_lds<MT, NT, CC, SW>), dim3((unsigned)tiles), dim3(256), lds, st, a);
 }
 
+template <int R, int NT>
+void launch_conv_rows(const ConvArgs& a, hipStream_t st)
+{
+    const size_t tiles = (size_t)a.N * ((a.H + R - 1) / R) * ((a.W + 63) / 64);
+    const size_t lds = ConvRows<R, NT>::bytes();
+    hipLaunchKernelGGL((k_conv_rows<R, NT>), dim3((unsigned)tiles), dim3(256), lds, st, a);
+}
+
 void unet_conv3x3(const ConvArgs& a, hipStream_t st)
 {
     const int nt = (a.Cout + 15) / 16;
-    // up to 2 N-tiles: 32- or 64-channel chunks, weights streamed through L1; from 4 N-tiles on: weights
+    // up to 2 N-tiles: row-blocked waves over 32-channel chunks with the weights in registers (8-channel
+    // inputs: the one-row kernel with 8-channel chunks, weights streamed through L1); from 4 N-tiles on: weights
     // staged in LDS, with chunks small enough that halo and weights fit in 64 KB (16 channels up to 8
     // N-tiles, padding a chunk's 144 K values to 160; 8 channels beyond)
     int cfg = 0;
@@ -894,14 +1036,17 @@ void unet_conv3x3(const ConvArgs& a, hipStream_t st)
         cfg = a.Cin % 64 == 0 ? 264 : (a.Cin % 32 == 0 ? 232 : 208);
     else if (a.Cin % 16 == 0)
         cfg = nt * 100 + (nt <= 8 ? 16 : 8);
-    static_assert(ConvLds<4, 2, 64, false>::bytes() <= 65536 && ConvLds<4, 4, 16, true>::bytes() <= 65536 &&
+    static_assert(ConvRows<RC_CONV_ROWS, 2>::bytes() <= 65536 && ConvLds<4, 4, 16, true>::bytes() <= 65536 &&
                       ConvLds<2, 6, 16, true>::bytes() <= 65536 && ConvLds<2, 8, 16, true>::bytes() <= 65536 &&
                       ConvLds<2, 12, 8, true>::bytes() <= 65536,
                   "convolution LDS beyond 64 KB");
     switch (cfg) {
     case 208: launch_conv_lds<4, 2, 8, false>(a, st); return;
-    case 232: launch_conv_lds<4, 2, 32, false>(a, st); return;
-    case 264: launch_conv_lds<4, 2, 64, false>(a, st); return;
+    case 232:
+    case 264:
+        if (nt == 1) launch_conv_rows<RC_CONV_ROWS, 1>(a, st);
+        else launch_conv_rows<RC_CONV_ROWS, 2>(a, st);
+        return;
     case 416: launch_conv_lds<4, 4, 16, true>(a, st); return;
     case 616: launch_conv_lds<2, 6, 16, true>(a, st); return;
     case 816: launch_conv_lds<2, 8, 16, true>(a, st); return;
