@@ -388,7 +388,8 @@ int rc_denoiser_destroy(rc_ctx* ctx, rc_denoiser* den);
 int rc_denoiser_get_params(rc_ctx* ctx, const rc_denoiser* den, float* out);
 int rc_denoiser_set_params(rc_ctx* ctx, rc_denoiser* den, const float* in);
 int rc_denoiser_get_grads(rc_ctx* ctx, const rc_denoiser* den, float* out);
-/* d_out: N*H*W float visibility in (0, 1). */
+/* d_out: N*H*W float visibility in (0, 1), device memory, 4-byte aligned (else RC_ERR_INVALID_ARG), written
+ * directly by the last layer's kernel (it must not overlap the features). */
 int rc_denoiser_infer(rc_ctx* ctx, rc_denoiser* den, const uint16_t* d_features, uint32_t n, uint32_t h, uint32_t w,
                       float* d_out);
 /* The same network evaluated in FP32 from the FP32 master weights (FP32 activations and accumulation,

@@ -50,6 +50,28 @@ __device__ inline uint4 pack8(const float f[8])
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// 2x2 average pool of four 8-channel groups: a = (2y, 2x), b = (2y, 2x + 1), c = (2y + 1, 2x),
+// d = (2y + 1, 2x + 1), as ((a + b) + (c + d)) / 4 rounded to BF16
+__device__ inline uint4 pool4(uint4 a, uint4 b, uint4 c, uint4 d)
+{
+    float fa[8], fb[8], fc[8], fd[8], r[8];
+    unpack8(a, fa); unpack8(b, fb); unpack8(c, fc); unpack8(d, fd);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = ((fa[e] + fb[e]) + (fc[e] + fd[e])) * 0.25f;
+    return pack8(r);
+}
+
+// the 1x1 head on one pixel's 32 BF16 channels (FP32, channels in order, weights rounded to BF16), then the
+// sigmoid
+__device__ inline float head_value(const float f[32], const float* wh, const float* bh)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) s = fmaf(f[c], bf2f(f2bf(wh[c])), s);
+    s += bh[0];
+    return 1.0f / (1.0f + expf(-s));
+}
+
 // ---------------------------------------------------------------- 3x3 convolution
 // Each wave computes 32 pixels (two 16-row MFMA tiles) x 16*NT output channels; a block has 4 waves.
 template <int NT>
@@ -281,6 +303,21 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
             }
     }
     __syncthreads();
+    if (a.pool_out) {
+        // 2x2 average pool of the tile (rows 0-1 and 2-3 of the 4 waves; tile origin and H, W even)
+        const int Hp = a.H / 2, Wp = a.W / 2, c8p = a.Cout / 8;
+        for (int q = threadIdx.x; q < 2 * (TPX / 2) * c8p; q += 256) {
+            const int pp = q / c8p, c8 = q - pp * c8p;
+            const int po = pp / (TPX / 2), px2 = pp % (TPX / 2);
+            const int y = y0 + 2 * po, x = x0 + 2 * px2;
+            if (x >= a.W || y >= a.H) continue;
+            const uint16_t* t0 = lds + (size_t)(2 * po) * TPX * TC + (2 * px2) * TC + 8 * c8;
+            const uint4 v = pool4(*reinterpret_cast<const uint4*>(t0), *reinterpret_cast<const uint4*>(t0 + TC),
+                                  *reinterpret_cast<const uint4*>(t0 + TPX * TC),
+                                  *reinterpret_cast<const uint4*>(t0 + TPX * TC + TC));
+            *reinterpret_cast<uint4*>(a.pool_out + ((size_t)(n * Hp + y / 2) * Wp + x / 2) * a.Cout + 8 * c8) = v;
+        }
+    }
     const int y = y0 + wave;
     if (y >= a.H) return;
     const int c8n = a.Cout / 8;
@@ -413,21 +450,48 @@ __global__ __launch_bounds__(256) void k_conv_rows(ConvArgs a)
     }
     __syncthreads();
     const int c8n = a.Cout / 8;
-    for (int q = lane; q < R * 16 * c8n; q += 64) {
-        const int px = q / c8n, c8 = q - px * c8n;
-        const int o = px / 16, x = x0 + 16 * wave + (px % 16), y = y0 + o;
-        if (x >= a.W || y >= a.H) continue;
-        uint4 v = *reinterpret_cast<const uint4*>(tile + px * TC + 8 * c8);
-        const size_t off = ((size_t)(n * a.H + y) * a.W + x) * a.Cout + 8 * c8;
-        if (a.mask) {
-            float f[8], mk[8];
-            unpack8(v, f);
-            unpack8(*reinterpret_cast<const uint4*>(a.mask + off), mk);
+    if (a.head_out) {
+        // the network's head on each pixel of the tile, from the BF16 values the layer would have stored
+        for (int px = lane; px < R * 16; px += 64) {
+            const int o = px / 16, x = x0 + 16 * wave + (px % 16), y = y0 + o;
+            if (x >= a.W || y >= a.H) continue;
+            float f[32];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) f[e] = mk[e] > 0.0f ? f[e] : 0.0f;
-            v = pack8(f);
+            for (int q = 0; q < 4; ++q) unpack8(*reinterpret_cast<const uint4*>(tile + px * TC + 8 * q), f + 8 * q);
+            a.head_out[(size_t)(n * a.H + y) * a.W + x] = head_value(f, a.head_w, a.head_b);
         }
-        *reinterpret_cast<uint4*>(a.out + off) = v;
+    } else {
+        for (int q = lane; q < R * 16 * c8n; q += 64) {
+            const int px = q / c8n, c8 = q - px * c8n;
+            const int o = px / 16, x = x0 + 16 * wave + (px % 16), y = y0 + o;
+            if (x >= a.W || y >= a.H) continue;
+            uint4 v = *reinterpret_cast<const uint4*>(tile + px * TC + 8 * c8);
+            const size_t off = ((size_t)(n * a.H + y) * a.W + x) * a.Cout + 8 * c8;
+            if (a.mask) {
+                float f[8], mk[8];
+                unpack8(v, f);
+                unpack8(*reinterpret_cast<const uint4*>(a.mask + off), mk);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) f[e] = mk[e] > 0.0f ? f[e] : 0.0f;
+                v = pack8(f);
+            }
+            *reinterpret_cast<uint4*>(a.out + off) = v;
+        }
+    }
+    if (a.pool_out) {
+        // 2x2 average pool of the wave's R rows x 16 pixels (tile origin and H, W even)
+        const int Hp = a.H / 2, Wp = a.W / 2;
+        for (int q = lane; q < (R / 2) * 8 * c8n; q += 64) {
+            const int pp = q / c8n, c8 = q - pp * c8n;
+            const int po = pp / 8, px2 = pp % 8;
+            const int y = y0 + 2 * po, x = x0 + 16 * wave + 2 * px2;
+            if (x >= a.W || y >= a.H) continue;
+            const uint16_t* t0 = tile + (2 * po * 16 + 2 * px2) * TC + 8 * c8;
+            const uint4 v = pool4(*reinterpret_cast<const uint4*>(t0), *reinterpret_cast<const uint4*>(t0 + TC),
+                                  *reinterpret_cast<const uint4*>(t0 + 16 * TC),
+                                  *reinterpret_cast<const uint4*>(t0 + 17 * TC));
+            *reinterpret_cast<uint4*>(a.pool_out + ((size_t)(n * Hp + y / 2) * Wp + x / 2) * a.Cout + 8 * c8) = v;
+        }
     }
 }
 
@@ -802,12 +866,7 @@ __global__ __launch_bounds__(256) void k_pool2(const uint16_t* in, int N, int H,
     size_t q = i / C8;
     int x = (int)(q % w), t = (int)(q / w), y = t % h, n = t / h;
     const uint16_t* b = in + (((size_t)n * H + 2 * y) * W + 2 * x) * C + c;
-    float a[8], bb[8], cc[8], d[8], r[8];
-    unpack8(ld8(b), a); unpack8(ld8(b + C), bb);
-    unpack8(ld8(b + (size_t)W * C), cc); unpack8(ld8(b + (size_t)W * C + C), d);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = ((a[e] + bb[e]) + (cc[e] + d[e])) * 0.25f;
-    st8(out + q * C + c, pack8(r));
+    st8(out + q * C + c, pool4(ld8(b), ld8(b + C), ld8(b + (size_t)W * C), ld8(b + (size_t)W * C + C)));
 }
 
 // out[N,2h,2w,Ca+Cs] = [nearest-upsampled a (Ca channels), skip (Cs channels)]
@@ -881,11 +940,11 @@ __global__ __launch_bounds__(256) void k_head(const uint16_t* d1, const float* w
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    float s = 0.0f;
     const uint16_t* row = d1 + (size_t)p * 32;
-    for (int c = 0; c < 32; ++c) s += bf2f(row[c]) * bf2f(f2bf(wh[c]));
-    s += bh[0];
-    y[p] = 1.0f / (1.0f + expf(-s));
+    float f[32];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) unpack8(ld8(row + 8 * q), f + 8 * q);
+    y[p] = head_value(f, wh, bh);
 }
 
 // per-chunk sums of mask and mask * (y - t)^2

@@ -164,8 +164,10 @@ int chunk_for(size_t P)
 }
 
 // layer l; with `skip`, the input is [2x nearest-upsampled `in` (Ca channels), skip] read directly
+// pool_out: also write the 2x2 average pool of the output; head_out: write the network's head of the output
+// (layer D1B) instead of the output
 void conv(rc_denoiser* d, const uint16_t* in, int n, int h, int w, int l, uint16_t* out, hipStream_t st,
-          const uint16_t* skip = nullptr, int Ca = 0)
+          const uint16_t* skip = nullptr, int Ca = 0, uint16_t* pool_out = nullptr, float* head_out = nullptr)
 {
     ConvArgs a = {};
     a.in = in; a.in2 = skip; a.Ca = Ca;
@@ -176,6 +178,13 @@ void conv(rc_denoiser* d, const uint16_t* in, int n, int h, int w, int l, uint16
     a.out = out;
     a.Cout = LAYERS[l].cout;
     a.relu = 1;
+    a.pool_out = pool_out;
+    if (head_out) {
+        a.head_w = d->d_w + d->off_w[N_LAYERS];
+        a.head_b = d->d_w + d->off_b[N_LAYERS];
+        a.head_out = head_out;
+        a.out = nullptr;
+    }
     unet_conv3x3(a, st);
 }
 
@@ -214,19 +223,20 @@ void conv_back_weights(rc_denoiser* d, const uint16_t* x, const uint16_t* g, int
     unet_reduce_blocks(d->d_partial, unet_colsum_blocks((int)P), LAYERS[l].cout, d->d_g + d->off_b[l], 0, st);
 }
 
-// keep_concat: also materialise the decoder's concatenated inputs (the weight gradients read them)
-int forward(rc_denoiser* d, const uint16_t* x, int n, int h, int w, hipStream_t st, bool keep_concat)
+// keep_concat: also materialise the decoder's concatenated inputs (the weight gradients read them).
+// y_out (inference): the head is computed in the last convolution's epilogue and written there, and the
+// last layer's activations are not stored; otherwise they are, and the head writes d_y.
+int forward(rc_denoiser* d, const uint16_t* x, int n, int h, int w, hipStream_t st, bool keep_concat,
+            float* y_out = nullptr)
 {
     int st_ = ensure_workspace(d, n, h, w);
     if (st_ != RC_OK) return st_;
     uint16_t* A = d->act;
     int h2 = h / 2, w2 = w / 2, h4 = h / 4, w4 = w / 4;
     conv(d, x, n, h, w, E1A, A + d->a_e1a, st);
-    conv(d, A + d->a_e1a, n, h, w, E1B, A + d->a_e1b, st);
-    unet_pool2(A + d->a_e1b, n, h, w, 32, A + d->a_p1, st);
+    conv(d, A + d->a_e1a, n, h, w, E1B, A + d->a_e1b, st, nullptr, 0, A + d->a_p1);
     conv(d, A + d->a_p1, n, h2, w2, E2A, A + d->a_e2a, st);
-    conv(d, A + d->a_e2a, n, h2, w2, E2B, A + d->a_e2b, st);
-    unet_pool2(A + d->a_e2b, n, h2, w2, 64, A + d->a_p2, st);
+    conv(d, A + d->a_e2a, n, h2, w2, E2B, A + d->a_e2b, st, nullptr, 0, A + d->a_p2);
     conv(d, A + d->a_p2, n, h4, w4, BNA, A + d->a_bna, st);
     conv(d, A + d->a_bna, n, h4, w4, BNB, A + d->a_bnb, st);
     if (keep_concat) unet_up2_concat(A + d->a_bnb, A + d->a_e2b, n, h2, w2, 128, 64, A + d->a_u2, st);
@@ -234,8 +244,12 @@ int forward(rc_denoiser* d, const uint16_t* x, int n, int h, int w, hipStream_t 
     conv(d, A + d->a_d2a, n, h2, w2, D2B, A + d->a_d2b, st);
     if (keep_concat) unet_up2_concat(A + d->a_d2b, A + d->a_e1b, n, h, w, 64, 32, A + d->a_u1, st);
     conv(d, A + d->a_d2b, n, h, w, D1A, A + d->a_d1a, st, A + d->a_e1b, 64);
-    conv(d, A + d->a_d1a, n, h, w, D1B, A + d->a_d1b, st);
-    unet_head(A + d->a_d1b, d->d_w + d->off_w[N_LAYERS], d->d_w + d->off_b[N_LAYERS], n * h * w, d->d_y, st);
+    if (y_out) {
+        conv(d, A + d->a_d1a, n, h, w, D1B, nullptr, st, nullptr, 0, nullptr, y_out);
+    } else {
+        conv(d, A + d->a_d1a, n, h, w, D1B, A + d->a_d1b, st);
+        unet_head(A + d->a_d1b, d->d_w + d->off_w[N_LAYERS], d->d_w + d->off_b[N_LAYERS], n * h * w, d->d_y, st);
+    }
     DN_HIP(hipGetLastError());
     return RC_OK;
 }
@@ -463,10 +477,8 @@ int rc_denoiser_infer(rc_ctx* c, rc_denoiser* d, const uint16_t* d_feat, uint32_
     if (reinterpret_cast<uintptr_t>(d_feat) & 15u) return RC_ERR_INVALID_ARG;
     DN_HIP(hipSetDevice(d->device));
     hipStream_t s = ctx_stream(c);
-    int st = forward(d, d_feat, (int)n, (int)h, (int)w, s, false);
-    if (st != RC_OK) return st;
-    DN_HIP(hipMemcpyAsync(d_out, d->d_y, (size_t)n * h * w * 4, hipMemcpyDeviceToDevice, s));
-    return RC_OK;
+    if (reinterpret_cast<uintptr_t>(d_out) & 3u) return RC_ERR_INVALID_ARG;
+    return forward(d, d_feat, (int)n, (int)h, (int)w, s, false, d_out);
 }
 
 int rc_denoiser_infer_fp32(rc_ctx* c, rc_denoiser* d, const uint16_t* d_feat, uint32_t n, uint32_t h, uint32_t w,

@@ -16,6 +16,11 @@ struct ConvArgs {
     uint16_t* out;          // NHWC bf16, Cout channels
     int Cout;
     int relu;
+    uint16_t* pool_out;     // optional: also the 2x2 average pool of the output, N x H/2 x W/2 x Cout (H, W even;
+                            // the LDS-tiled kernels)
+    const float* head_w;    // optional 1x1 head for Cout = 32 (the row-blocked kernel): with head_out the
+    const float* head_b;    // epilogue writes sigmoid(head_b + sum_c out[c] head_w[c]) per pixel (FP32) and
+    float* head_out;        // not `out`
 };
 
 struct ConvArgsF32 {
