@@ -351,11 +351,17 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
 // plane blocks come with three 32-byte loads at constant offsets and the near/far choice is made when
 // compiling; 8: mixed octants (each lane picks its planes); -1: decided at run time, per instance for
 // two-level structures (the mapped rays' octant changes at each instance).
+template <bool WT, bool BIG>
+__device__ __attribute__((always_inline)) inline uint32_t wave_walk_flat(const DevScene& sc, const char* nodes_b,
+                                                                       const char* tris_b, TravRay& ray, bool busy,
+                                                                       uint32_t& node_visits, uint32_t& tri_tests,
+                                                                       uint32_t* error_flag, uint32_t root);
+
 template <bool TWO, bool WT, bool BIG, int OCT>
 __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevScene& sc, const char* nodes_b,
                                                                   const char* tris_b, TravRay& ray, bool busy,
                                                                   uint32_t& node_visits, uint32_t& tri_tests,
-                                                                  uint32_t* error_flag)
+                                                                  uint32_t* error_flag, uint32_t root)
 {
     const uint32_t lane = __lane_id();
     const uint64_t busy_mask = __ballot(busy);
@@ -379,29 +385,20 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
     };
     if constexpr (OCT < 0) set_octant();
     float wo[3] = {ray.o[0], ray.o[1], ray.o[2]}, wd[3] = {ray.d[0], ray.d[1], ray.d[2]};   // world ray
-    uint32_t in_blas = 0u;
     // per-lane state as 32-bit words: occ (an occluder found), live (busy and not occluded) and the
     // slab bound, 1 (the segment's end) for live rays and -1 otherwise, so that finished rays enter
     // no box (t0 >= 0)
     uint32_t occ = 0u, live = busy ? 1u : 0u;
     float bound = busy ? 1.0f : -1.0f;
-    uint32_t cur = busy_mask != 0 ? (TWO ? sc.tlas_root : 0u) : RC_STACK_EMPTY;
+    uint32_t cur = busy_mask != 0 ? (TWO ? sc.tlas_root : root) : RC_STACK_EMPTY;
     int sp = 0;
     uint32_t stk0 = 0, stk1 = 0;   // entry e of the wave's stack lives in lane e % 64 of stk{e / 64}
-    // next entry of the wave's stack (an instance's end marker returns the rays to world space)
+    // next entry of the wave's stack
     auto pop_next = [&]() -> uint32_t {
-        for (;;) {
-            if (sp == 0) return RC_STACK_EMPTY;
-            --sp;
-            const uint32_t c = BIG ? (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63)
-                                   : (uint32_t)__builtin_amdgcn_readlane((int)stk0, sp);
-            if (!TWO || c != RC_INST_RETURN) return c;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) { ray.o[a] = wo[a]; ray.d[a] = wd[a]; }
-            rc_ray_inv(ray);
-            set_octant();
-            in_blas = 0u;
-        }
+        if (sp == 0) return RC_STACK_EMPTY;
+        --sp;
+        return BIG ? (uint32_t)__builtin_amdgcn_readlane((int)(sp < 64 ? stk0 : stk1), sp & 63)
+                   : (uint32_t)__builtin_amdgcn_readlane((int)stk0, sp);
     };
     auto push_entry = [&](uint32_t w) {
         if (sp < 64) {
@@ -466,17 +463,24 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
                     if (key[c] < RC_KEY_MISS) push_entry(child(key[c]));
             }
             cur = key[0] < RC_KEY_MISS ? child(key[0]) : pop_next();
-        } else if (TWO && in_blas == 0u) {
-            // top-level leaf: map every ray into the instance and descend into its tree
+        } else if (TWO) {
+            // top-level leaf: every ray mapped into the instance, whose tree the flat walk takes (compiled for
+            // the mapped rays' octant, with a stack of its own) for the rays still live; then back to world
+            // space
             rc_const_v4f* ip = (rc_const_v4f*)(const void*)(sc.inst + rc_leaf_first(cur));
             const rc_v4f q0 = ip[0], q1 = ip[1], q2 = ip[2], q3 = ip[3];
             const float W[12] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3],
                                  q2[0], q2[1], q2[2], q2[3]};
             rc_map_ray(W, wo, wd, ray);
-            set_octant();
-            push_entry(RC_INST_RETURN);
-            in_blas = 1u;
-            cur = __float_as_uint(q3[0]);
+            const uint32_t ob = wave_walk_flat<WT, false>(sc, nodes_b, tris_b, ray, live != 0u, node_visits,
+                                                          tri_tests, error_flag, __float_as_uint(q3[0]));
+            occ |= ob;
+            live &= ob ^ 1u;
+            bound = live != 0u ? bound : -1.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { ray.o[a] = wo[a]; ray.d[a] = wd[a]; }
+            rc_ray_inv(ray);
+            cur = __ballot(live != 0u) == 0 ? RC_STACK_EMPTY : pop_next();
         } else {
             // every lane tests every triangle of the leaf, without lane branches: a finished lane only
             // repeats work (its flag stays set; idle lanes' flags are never read), and the counter
@@ -511,27 +515,40 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const De
                                                                       uint32_t& node_visits, uint32_t& tri_tests,
                                                                       uint32_t* error_flag)
 {
-#define RC_WALK(o) wave_walk<TWO, WT, BIG, o>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag)
-    if constexpr (TWO) {
-        return RC_WALK(-1);
-    } else {
-        const uint64_t busy_mask = __ballot(busy);
-        const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
-                                (ray.inv[2] < 0.0f ? 4u : 0u);
-        const uint32_t oct = busy_mask != 0
-                                 ? (uint32_t)__builtin_amdgcn_readlane((int)my_oct, __builtin_ctzll(busy_mask))
-                                 : 0u;
-        if (__ballot(busy && my_oct != oct) != 0) return RC_WALK(8);
-        switch (oct) {
-        case 0: return RC_WALK(0);
-        case 1: return RC_WALK(1);
-        case 2: return RC_WALK(2);
-        case 3: return RC_WALK(3);
-        case 4: return RC_WALK(4);
-        case 5: return RC_WALK(5);
-        case 6: return RC_WALK(6);
-        default: return RC_WALK(7);
-        }
+    if constexpr (TWO)
+        return wave_walk<TWO, WT, BIG, -1>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, 0u);
+    else
+        return wave_walk_flat<WT, BIG>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, 0u);
+}
+
+// The flat walk from node `root`, compiled once per direction octant of the busy rays and once for mixed
+// octants.  For two-level structures it walks an instance's tree with a one-register stack: the host takes
+// the wave kernels only when 3 x (deepest instance tree + 24) + 2 <= 128, so an instance tree is at most 18
+// levels deep and its walk needs at most 55 stack entries.
+template <bool WT, bool BIG>
+__device__ __attribute__((always_inline)) inline uint32_t wave_walk_flat(const DevScene& sc, const char* nodes_b,
+                                                                       const char* tris_b, TravRay& ray, bool busy,
+                                                                       uint32_t& node_visits, uint32_t& tri_tests,
+                                                                       uint32_t* error_flag, uint32_t root)
+{
+#define RC_WALK(o) \
+    wave_walk<false, WT, BIG, o>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, root)
+    const uint64_t busy_mask = __ballot(busy);
+    const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
+                            (ray.inv[2] < 0.0f ? 4u : 0u);
+    const uint32_t oct = busy_mask != 0
+                             ? (uint32_t)__builtin_amdgcn_readlane((int)my_oct, __builtin_ctzll(busy_mask))
+                             : 0u;
+    if (__ballot(busy && my_oct != oct) != 0) return RC_WALK(8);
+    switch (oct) {
+    case 0: return RC_WALK(0);
+    case 1: return RC_WALK(1);
+    case 2: return RC_WALK(2);
+    case 3: return RC_WALK(3);
+    case 4: return RC_WALK(4);
+    case 5: return RC_WALK(5);
+    case 6: return RC_WALK(6);
+    default: return RC_WALK(7);
     }
 #undef RC_WALK
 }
