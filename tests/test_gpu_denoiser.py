@@ -96,6 +96,25 @@ def test_forward_matches_oracle(ctx):
         assert err.max() < 2e-3 and err.mean() < 1e-4
 
 
+def test_fused_inference_equals_training_forward(ctx):
+    """Inference computes the 2x2 pools and the head inside the convolution epilogues and writes the head
+    straight into the output; the training step's forward stores every activation and runs the separate
+    head kernel.  Both must give the same values bit for bit: a training step at lr = 0, with the inference
+    output as its target and a full mask, reports a loss of exactly 0."""
+    import torch
+    from paper_2410_05095_amd import _native as N
+    den = N.Denoiser(ctx, seed=1)
+    den.set_params(U.flat(oracle_params(5)).astype(np.float32))
+    for seed, (n, h, w) in enumerate([(2, 32, 48), (1, 36, 20), (1, 68, 132)]):
+        x, t, m = random_batch(seed, n, h, w)
+        xd, _, _ = to_dev(ctx, x, t, m)
+        y = den.infer(xd).clone()
+        ones = torch.ones_like(y)
+        loss = den.train_step(xd, y, ones, lr=0.0)
+        say(f"[fused vs stored {n}x{h}x{w}] loss {loss!r}")
+        assert loss == 0.0, (n, h, w, loss)
+
+
 def test_fp32_copy_matches_oracle(ctx):
     """The FP32 copy of the network (FP32 master weights, FP32 activations) against the FP64 oracle without
     BF16 emulation; the BF16 inference differs from it by BF16 rounding only."""
