@@ -34,7 +34,7 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # the copy-kernel calibration), keyed by (workload, spp, hash of the traversal kernel sources); the
 # value only applies while those sources are unchanged (summaries under profiles/).
 MEASURED_TRAFFIC = {
-    ("big_7M", 64, "b5f30da9c8f13f5d:5ce1cb11be5fdbcb:70040863f1edf569"): 446_528_000,
+    ("big_7M", 64, "ff787ee5bc0f2761:5ce1cb11be5fdbcb:70040863f1edf569"): 446_670_000,
 }
 
 

@@ -197,8 +197,9 @@ int rc_batch_max_blocks_per_cu(int device)
 {
     int blocks = 0;
     (void)device;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_batch), BLOCK,
-                                                 TravStack<SL, BLOCK, true>::lds_bytes());
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_batch), BLOCK,
+                                                     TravStack<SL, BLOCK, true>::lds_bytes()) != hipSuccess)
+        blocks = 1;
     return blocks < 1 ? 1 : blocks;
 }
 

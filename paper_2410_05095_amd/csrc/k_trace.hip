@@ -840,15 +840,19 @@ __global__ void k_rect_finish(const uint32_t* counts, uint32_t n_pix, uint32_t N
 template <int MODE>
 constexpr size_t lds_bytes() { return TravStack<SL, BLOCK, MODE == MODE_PRIMARY>::lds_bytes(); }
 
-template <int MODE>
-int occupancy_grid(int device)
+// compute units of the device and resident blocks of a kernel per compute unit (1 if a query fails)
+int cu_count(int device)
 {
-    int n_cu = 0, blocks = 0;
-    hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_trace<MODE, false, false>), BLOCK,
-                                                 lds_bytes<MODE>());
-    if (blocks < 1) blocks = 1;
-    return n_cu * blocks;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+int blocks_per_cu(const void* kernel, size_t lds)
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, BLOCK, lds) != hipSuccess || b < 1) b = 1;
+    return b;
 }
 
 }  // namespace
@@ -871,21 +875,20 @@ int occupancy_grid(int device)
         }                                                                          \
     } while (0)
 
+// persistent grid of the traversal kernels: compute units x the largest resident block count among them
 int rc_trace_grid(int device)
 {
-    int a = occupancy_grid<MODE_PRIMARY>(device);
-    int b = occupancy_grid<MODE_POINT>(device);
-    int c = occupancy_grid<MODE_RECT>(device);
-    int d = 0, n_cu = 0;
-    hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, reinterpret_cast<const void*>(&k_rect_packets<false, false>), BLOCK,
-                                                 TravStack<SL, BLOCK, false>::lds_bytes());
-    int e = 0, f = 0, g = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, reinterpret_cast<const void*>(&k_rect_wave<false, false, false>), BLOCK, 0);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, reinterpret_cast<const void*>(&k_primary_wave<false>), BLOCK, 0);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&g, reinterpret_cast<const void*>(&k_point_wave<false, false, false>), BLOCK, 0);
-    e = std::max(std::max(e, f), g);
-    return std::max(std::max(std::max(a, d * n_cu), std::max(b, c)), e * n_cu);
+    const int blocks[] = {
+        blocks_per_cu(reinterpret_cast<const void*>(&k_trace<MODE_PRIMARY, false, false>), lds_bytes<MODE_PRIMARY>()),
+        blocks_per_cu(reinterpret_cast<const void*>(&k_trace<MODE_POINT, false, false>), lds_bytes<MODE_POINT>()),
+        blocks_per_cu(reinterpret_cast<const void*>(&k_trace<MODE_RECT, false, false>), lds_bytes<MODE_RECT>()),
+        blocks_per_cu(reinterpret_cast<const void*>(&k_rect_packets<false, false>), TravStack<SL, BLOCK, false>::lds_bytes()),
+        blocks_per_cu(reinterpret_cast<const void*>(&k_rect_wave<false, false, false>), 0),
+        blocks_per_cu(reinterpret_cast<const void*>(&k_primary_wave<false>), 0),
+        blocks_per_cu(reinterpret_cast<const void*>(&k_point_wave<false, false, false>), 0)};
+    int b = 1;
+    for (int x : blocks) b = std::max(b, x);
+    return cu_count(device) * b;
 }
 
 void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, const TraceWork& w, int grid,
