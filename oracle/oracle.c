@@ -1204,6 +1204,126 @@ OR_API void or_render_rect(const or_scene* s, const or_bvh* B, const or_camera* 
 }
 
 /* ------------------------------------------------------------------------- */
+/* Instrumented any-hit traversal of a 4-wide BVH given in the library's      */
+/* exported layout (per node 32 words: lo_x[4] hi_x[4] lo_y[4] hi_y[4]        */
+/* lo_z[4] hi_z[4] child[4] meta[4]; child word: 0xFFFFFFFF empty, bit 31 =   */
+/* leaf with count - 1 in bits 28..30 and first slot in bits 0..27, else an   */
+/* internal node; `order` maps a leaf slot to the original triangle id).      */
+/* The work a ray's own traversal does (Sec. IV-B: an acceleration structure  */
+/* answers a ray query by visiting few nodes): from the root, visit a node =  */
+/* test its four child boxes against the segment 0 <= t <= 1; continue with  */
+/* the nearest entered child and stack the others (farthest first); at a leaf */
+/* test its triangles in slot order and stop at the first crossing with       */
+/* 0 < t < 1.  Everything in FP64.  Counts node visits and triangle tests.    */
+/* ------------------------------------------------------------------------- */
+static float word_f(uint32_t w) { float f; memcpy(&f, &w, 4); return f; }
+
+static int count_any_bvh4(const or_scene* s, const uint32_t* nodes, const uint32_t* order, v3 o, v3 d,
+                          int64_t* n_nodes, int64_t* n_tris)
+{
+    uint32_t stack[256];
+    int sp = 0;
+    uint32_t cur = 0;
+    const double O[3] = {o.x, o.y, o.z}, D[3] = {d.x, d.y, d.z};
+    for (;;) {
+        if (cur == 0xFFFFFFFFu) {
+            if (sp == 0) return 0;
+            cur = stack[--sp];
+            continue;
+        }
+        if (!(cur & 0x80000000u)) {
+            const uint32_t* nd = nodes + 32 * (int64_t)cur;
+            (*n_nodes)++;
+            double tn[4];
+            uint32_t cw[4];
+            int nh = 0;
+            for (int c = 0; c < 4; ++c) {
+                uint32_t w = nd[24 + c];
+                if (w == 0xFFFFFFFFu) continue;
+                double t0 = 0.0, t1 = 1.0;
+                int hit = 1;
+                for (int a = 0; a < 3 && hit; ++a) {
+                    double lo = word_f(nd[8 * a + c]), hi = word_f(nd[8 * a + 4 + c]);
+                    if (D[a] == 0.0) {
+                        if (O[a] < lo || O[a] > hi) hit = 0;
+                        continue;
+                    }
+                    double ta = (lo - O[a]) / D[a], tb = (hi - O[a]) / D[a];
+                    if (ta > tb) { double x = ta; ta = tb; tb = x; }
+                    t0 = fmax(t0, ta);
+                    t1 = fmin(t1, tb);
+                    if (t0 > t1) hit = 0;
+                }
+                if (!hit) continue;
+                /* insertion by entry distance, earlier slots first on ties */
+                int k = nh++;
+                while (k > 0 && tn[k - 1] > t0) { tn[k] = tn[k - 1]; cw[k] = cw[k - 1]; --k; }
+                tn[k] = t0; cw[k] = w;
+            }
+            for (int k = nh - 1; k >= 1; --k) stack[sp++] = cw[k];
+            cur = nh > 0 ? cw[0] : 0xFFFFFFFFu;
+            continue;
+        }
+        uint32_t first = cur & 0x0FFFFFFFu, cnt = ((cur >> 28) & 7u) + 1u;
+        for (uint32_t i = 0; i < cnt; ++i) {
+            v3 a, b, c;
+            tri_verts(s, order[first + i], &a, &b, &c);
+            (*n_tris)++;
+            v3 e1 = sub(b, a), e2 = sub(c, a), pv = cross(d, e2);
+            double det = dot(e1, pv);
+            if (det == 0.0) continue;
+            v3 sv = sub(o, a), qv = cross(sv, e1);
+            double u = dot(sv, pv) / det, v = dot(d, qv) / det, t = dot(e2, qv) / det;
+            if (u >= 0.0 && v >= 0.0 && u + v <= 1.0 && t > 0.0 && t < 1.0) return 1;
+        }
+        cur = 0xFFFFFFFFu;
+    }
+}
+
+/* Explicit segments o + t d, 0 < t < 1 (n x 3 doubles each): occluded flag per segment and, added to out[0] and
+ * out[1], the node visits and triangle tests of the instrumented traversal. */
+OR_API void or_count_any(const or_scene* s, const uint32_t* nodes, const uint32_t* order, const double* o,
+                         const double* d, int64_t n, uint8_t* occluded, int64_t out[2])
+{
+    for (int64_t q = 0; q < n; ++q)
+        occluded[q] = (uint8_t)count_any_bvh4(s, nodes, order, mk(o[3 * q], o[3 * q + 1], o[3 * q + 2]),
+                                              mk(d[3 * q], d[3 * q + 1], d[3 * q + 2]), &out[0], &out[1]);
+}
+
+/* Rect-light shadow rays of the given pixels (1 camera sample each, as or_render_rect), traced through the
+ * exported BVH by the instrumented traversal: adds to out[0] the rays cast (n . d > 0 and the light's
+ * emitting side faces the point), out[1] node visits, out[2] triangle tests. */
+OR_API void or_count_rect(const or_scene* s, const or_bvh* B, const uint32_t* nodes, const uint32_t* order,
+                          const or_camera* cam, const float* rect, int n_light_samples, uint32_t stream,
+                          const int64_t* pixels, int64_t n, int64_t out[3])
+{
+    cam_basis cb;
+    camera_basis(cam, &cb);
+    rect_geo R;
+    rect_setup(rect, &R);
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t pix = pixels[q];
+        float of[3], df[3];
+        gen_ray(cam, &cb, pix, of, df);
+        ray_ev r = exact_ray(from_f(of), from_f(df));
+        hit_rec h;
+        closest_q(s, B, &r, 0.0, INFINITY, 4.0, &h);
+        if (h.id == NO_HIT) continue;
+        surface S;
+        make_surface(s, h.id, h.u, h.v, r.d, &S);
+        for (int k = 0; k < n_light_samples; ++k) {
+            uint32_t ctr[4] = {(uint32_t)pix, (uint32_t)k, 1u + stream, 0u}, key[2] = {cam->seed, cam->frame}, rr[4];
+            or_philox4x32_10(ctr, key, rr);
+            v3 y = add(add(R.C, scl(R.EU, unit24(rr[0]) - 0.5)), scl(R.EV, unit24(rr[1]) - 0.5));
+            v3 d = sub(y, S.os);
+            if (!(dot(S.n, d) > 0.0) || !(dot(R.nL, d) < 0.0)) continue;
+            out[0]++;
+            count_any_bvh4(s, nodes, order, S.os, d, &out[1], &out[2]);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* FP32 mirrors: supersampling resolve and rigid vertex transforms.          */
 /* ------------------------------------------------------------------------- */
 /* out[p] = ((s0 + s1) + (s2 + s3)) * 0.25 per channel; n_per = 4; or copy when n_per = 1 */

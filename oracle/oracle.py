@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import threading
 import os
 from concurrent.futures import ThreadPoolExecutor
 from typing import Optional
@@ -72,6 +73,8 @@ def _declare(L):
                                   P, P, P, P, P, P, P]
     L.or_render_rect.argtypes = [P, P, P, P, C.c_int, C.c_uint32, C.c_double, P, C.c_int64,
                                  P, P, P, P, P, P]
+    L.or_count_rect.argtypes = [P, P, P, P, P, P, C.c_int, C.c_uint32, P, C.c_int64, P]
+    L.or_count_any.argtypes = [P, P, P, P, P, C.c_int64, P, P]
     L.or_resolve_f32.argtypes = [P, C.c_int64, C.c_int, P]
     L.or_transform_f32.argtypes = [P, P, P, P, C.c_int64, P]
     L.or_ggx_D.argtypes = [P, P, C.c_double]
@@ -274,6 +277,48 @@ class OracleScene:
 
         _parallel(run, n, threads)
         return out
+
+
+    def count_rect(self, cam, rect, n_light_samples: int, stream: int, pixels: np.ndarray, nodes: np.ndarray,
+                   order: np.ndarray, threads: Optional[int] = None) -> dict:
+        """Own-path work of the rect-light shadow rays of `pixels` through a BVH in the library's exported layout
+        (nodes: n x 32 uint32, order: slot -> triangle id): rays cast, node visits and triangle tests of each
+        ray's own near-first any-hit traversal (FP64)."""
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        nodes = np.ascontiguousarray(nodes, dtype=np.uint32)
+        order = np.ascontiguousarray(order, dtype=np.uint32)
+        R = rect_array(rect)
+        cs = camera_struct(cam)
+        bvh = self._query_bvh(False)
+        n = len(pixels)
+        parts = []
+        lock = threading.Lock()
+
+        def run(a, b):
+            if b <= a:
+                return
+            acc = np.zeros(3, np.int64)
+            lib().or_count_rect(C.byref(self.s), bvh, _p(nodes), _p(order), C.byref(cs), _p(R), int(n_light_samples),
+                                int(stream), _p(pixels[a:b]), b - a, _p(acc))
+            with lock:
+                parts.append(acc)
+
+        _parallel(run, n, threads)
+        tot = np.sum(parts, axis=0) if parts else np.zeros(3, np.int64)
+        return {"rays": int(tot[0]), "nodes": int(tot[1]), "tris": int(tot[2])}
+
+
+    def count_any(self, o, d, nodes: np.ndarray, order: np.ndarray):
+        """Instrumented any-hit traversal of segments o + t d (0 < t < 1) through an exported BVH:
+        (occluded per segment, node visits, triangle tests)."""
+        o = np.ascontiguousarray(np.asarray(o, np.float64).reshape(-1, 3))
+        d = np.ascontiguousarray(np.asarray(d, np.float64).reshape(-1, 3))
+        nodes = np.ascontiguousarray(nodes, dtype=np.uint32)
+        order = np.ascontiguousarray(order, dtype=np.uint32)
+        occ = np.zeros(len(o), np.uint8)
+        acc = np.zeros(2, np.int64)
+        lib().or_count_any(C.byref(self.s), _p(nodes), _p(order), _p(o), _p(d), len(o), _p(occ), _p(acc))
+        return occ.astype(bool), int(acc[0]), int(acc[1])
 
 
 def rect_array(rect) -> np.ndarray:

@@ -92,15 +92,18 @@ def up2_backward(g):
     return g.reshape(N, H // 2, 2, W // 2, 2, C).sum(axis=(2, 4))
 
 
-def forward(params: dict, x: np.ndarray, bf16: bool = False):
-    """Returns (y (N,H,W), cache of every stored tensor)."""
+def forward(params: dict, x: np.ndarray, bf16: bool = False, conv=None):
+    """Returns (y (N,H,W), cache of every stored tensor).  `conv` replaces conv3x3 (same signature),
+    e.g. by a variant that sums in another precision, to measure how much BF16 rounding of the
+    stored activations alone moves the result."""
+    conv = conv3x3 if conv is None else conv
     rd = bf16_round if bf16 else (lambda a: a)
     P = {k: (rd(v) if k.endswith(".w") else v) for k, v in params.items()}
     c = {"x": rd(x)}
 
     def block(name_a, name_b, inp, tag):
-        a = rd(np.maximum(conv3x3(inp, P[name_a + ".w"], P[name_a + ".b"]), 0.0))
-        b = rd(np.maximum(conv3x3(a, P[name_b + ".w"], P[name_b + ".b"]), 0.0))
+        a = rd(np.maximum(conv(inp, P[name_a + ".w"], P[name_a + ".b"]), 0.0))
+        b = rd(np.maximum(conv(a, P[name_b + ".w"], P[name_b + ".b"]), 0.0))
         c[tag + "_in"], c[tag + "_a"], c[tag + "_b"] = inp, a, b
         return b
 

@@ -428,6 +428,70 @@ def test_plane_radiance_closed_form(oracle_mod):
     assert np.allclose(res["rgb"][0], fwant * inten / hgt ** 2, rtol=1e-12)
 
 
+def _rect_centre_radiance(O, mats, cam, rect, size=20.0):
+    """Unshadowed centre-point rect-light radiance of the centre pixel of `cam` on the plane y = 0."""
+    v, f = quad(0.0, size)
+    sc = tri_scene(O, v, f, mats=mats)
+    centre = (cam.height // 2) * cam.width + cam.width // 2
+    res = sc.render_rect(cam, rect, 16, 0, np.array([centre]))
+    assert res["hit_id"][0] != NO_HIT
+    return res["rgb_unshadowed"][0], res["vis_count"][0]
+
+
+def test_rect_light_radiance_closed_form(oracle_mod):
+    """Rect light of area A seen from a plane point p: the unshadowed centre-point term is
+    f(wo, wi) L_e A cos_L cos_i / d^2 (the light as a point source of intensity L_e A cos_L).
+
+    Poses with dyadic coordinates, so every input is exact in FP32 and the closed form holds to rounding:
+     - light straight above p facing it (cos_L = cos_i = 1; camera on the same axis, so wo = wi = n and
+       f is the normal-incidence special case (1 - F0)(1 - m) a / pi + F0 / (4 pi alpha^2));
+     - the same light tilted about x so its normal makes a 3-4-5 angle with the axis (cos_L = 0.8);
+     - the edges swapped, so the emitting side faces away (term and visibility both 0);
+     - an oblique light (cos_i = 0.8) with the camera on the line from p to the light, so wo = wi = h
+       and f = (1 - F0)(1 - m) a / pi + D(n.h) F0 / (4 (x (1 - k) + k)^2) with the textbook GGX
+       D = alpha^2 / (pi (alpha^2 x^2 + 1 - x^2)^2), x = n.h, k = (r + 1)^2 / 8; the camera ray's FP32
+       rounding moves p by ~1e-7, hence the looser bound there."""
+    O = oracle_mod
+    alb, r, Le = np.array([0.75, 0.5, 0.25]), 0.375, 3.0
+    mats = [[*alb, r, 0.0]]
+    F0 = 0.04
+    alpha = r * r
+    f_normal = (1 - F0) * alb / math.pi + F0 / (4 * math.pi * alpha ** 2)
+    top = sg.Camera(eye=(0.0, 3.0, 0.0), target=(0.0, 0.0, 0.0), up=(0, 0, 1), vfov_deg=30.0, width=3, height=3)
+    H = 5.0
+
+    # 1. facing straight down, A = 0.75 x 0.625
+    A = 0.75 * 0.625
+    flat = sg.RectLight(center=(0.0, H, 0.0), edge_u=(0.75, 0.0, 0.0), edge_v=(0.0, 0.0, 0.625), radiance=(Le,) * 3)
+    rgb, vis = _rect_centre_radiance(O, mats, top, flat)
+    assert vis == 16
+    assert np.allclose(rgb, f_normal * Le * A / H ** 2, rtol=1e-12, atol=0)
+
+    # 2. tilted: edge_v = 0.625 (0, 0.6, 0.8), normal (0, -0.8, 0.6): cos_L = 0.8, same area
+    tilt = sg.RectLight(center=(0.0, H, 0.0), edge_u=(0.75, 0.0, 0.0), edge_v=(0.0, 0.375, 0.5), radiance=(Le,) * 3)
+    rgb_t, _ = _rect_centre_radiance(O, mats, top, tilt)
+    assert np.allclose(rgb_t, f_normal * Le * A * 0.8 / H ** 2, rtol=1e-12, atol=0)
+
+    # 3. emitting side away from the plane
+    away = sg.RectLight(center=(0.0, H, 0.0), edge_u=(0.0, 0.0, 0.625), edge_v=(0.75, 0.0, 0.0), radiance=(Le,) * 3)
+    rgb_a, vis_a = _rect_centre_radiance(O, mats, top, away)
+    assert np.all(rgb_a == 0.0) and vis_a == 0
+
+    # 4. oblique: light centre at distance 5 along wi = (0.6, 0.8, 0) from p = 0, facing down (cos_L = 0.8)
+    cam = sg.Camera(eye=(1.5, 2.0, 0.0), target=(0.0, 0.0, 0.0), up=(0, 0, 1), vfov_deg=30.0, width=3, height=3)
+    obl = sg.RectLight(center=(3.0, 4.0, 0.0), edge_u=(0.75, 0.0, 0.0), edge_v=(0.0, 0.0, 0.625), radiance=(Le,) * 3)
+    x = 0.8
+    k = (r + 1) ** 2 / 8
+    D = alpha ** 2 / (math.pi * (alpha ** 2 * x ** 2 + 1 - x ** 2) ** 2)
+    f_obl = (1 - F0) * alb / math.pi + D * F0 / (4 * (x * (1 - k) + k) ** 2)
+    rgb_o, _ = _rect_centre_radiance(O, mats, cam, obl)
+    assert np.allclose(rgb_o, f_obl * Le * A * 0.8 * 0.8 / 25.0, rtol=1e-6, atol=0)
+    # the same light turned to face p (normal -wi: edges (0, 0, 0.5) and (-0.5, 0.375, 0)): cos_L = 1
+    face = sg.RectLight(center=(3.0, 4.0, 0.0), edge_u=(0.0, 0.0, 0.5), edge_v=(-0.5, 0.375, 0.0), radiance=(Le,) * 3)
+    rgb_f, _ = _rect_centre_radiance(O, mats, cam, face)
+    assert np.allclose(rgb_f, f_obl * Le * (0.5 * 0.625) * 0.8 / 25.0, rtol=1e-6, atol=0)
+
+
 # ----------------------------------------------------------------------------- FP32 mirrors
 def test_resolve_f32(oracle_mod):
     O = oracle_mod
@@ -455,3 +519,56 @@ def test_transform_f32(oracle_mod):
     want = np.stack([rest[:50, 2] + np.float32(0.5), rest[:50, 1] - np.float32(2.0), -rest[:50, 0] + np.float32(0.25)], 1)
     assert np.array_equal(out[:50], want)
     assert np.array_equal(out[50:], rest[50:])
+
+
+# ----------------------------------------------------------------------------- instrumented traversal
+def _bvh4_words(boxes, children):
+    """One node in the exported layout: boxes = 4 x (lo3, hi3) (None = empty), children = 4 child words."""
+    w = np.zeros(32, np.uint32)
+    f = w.view(np.float32)
+    for c in range(4):
+        if boxes[c] is None:
+            lo, hi = (np.inf,) * 3, (-np.inf,) * 3
+        else:
+            lo, hi = boxes[c]
+        for a in range(3):
+            f[8 * a + c], f[8 * a + 4 + c] = lo[a], hi[a]
+        w[24 + c] = children[c]
+    return w
+
+
+def test_instrumented_traversal_counts(oracle_mod):
+    """Hand-built 4-wide tree: root with two leaves (one triangle each, at z = 2 and z = 6) and an inner node
+    holding a leaf of two triangles at z = 4 (x < 0 and x > 0).  Rays along +z over the segment count
+    exactly the node visits and triangle tests of a near-first any-hit walk; a ray that misses every box
+    visits the root only; occlusion equals brute force."""
+    O = oracle_mod
+    L = lambda first, cnt: np.uint32(0x80000000 | ((cnt - 1) << 28) | first)
+    EMPTY = np.uint32(0xFFFFFFFF)
+    # triangles: 0 at z=2, 1 at z=6 (both cover |x|,|y| < 1), 2 and 3 at z=4 covering x<0 and x>0
+    verts = [(-1, -1, 2), (3, -1, 2), (-1, 3, 2), (-1, -1, 6), (3, -1, 6), (-1, 3, 6),
+             (-1.5, -1, 4), (0, -1, 4), (-1.5, 3, 4), (0, -1, 4), (1.5, -1, 4), (0, 3, 4)]
+    tris = [(0, 1, 2), (3, 4, 5), (6, 7, 8), (9, 10, 11)]
+    sc = tri_scene(O, verts, tris)
+    box = lambda z0, z1, x0=-1.5, x1=3.0: ((x0, -1.0, z0), (x1, 3.0, z1))
+    root = _bvh4_words([box(5.9, 6.1), box(1.9, 2.1), box(3.9, 4.1), None], [L(1, 1), L(0, 1), 1, EMPTY])
+    inner = _bvh4_words([box(3.9, 4.1, -1.5, 1.5), None, None, None], [L(2, 2), EMPTY, EMPTY, EMPTY])
+    nodes = np.stack([root, inner])
+    order = np.array([0, 1, 2, 3], np.uint32)      # slot -> triangle id
+    cases = [
+        # o, d (segment o + t d, 0 < t < 1), occluded, node visits, triangle tests
+        ((0.5, 0.5, 0.0), (0, 0, 10.0), True, 1, 1),     # near leaf (z=2) hits at once
+        ((0.5, 0.5, 3.0), (0, 0, 10.0), True, 2, 2),     # inner node (z=4) first: slot 2 (x<0) misses, slot 3 hits
+        ((-0.5, 0.5, 5.0), (0, 0, 10.0), True, 1, 1),    # only the z=6 leaf lies ahead
+        ((0.5, 0.5, 6.5), (0, 0, 10.0), False, 1, 0),    # every box behind the origin
+        ((0.5, 0.5, 3.0), (0, 0, -10.0), True, 1, 1),    # backwards: z=2 leaf
+        ((2.5, 2.5, 3.0), (0, 0, 10.0), False, 2, 1),    # inner node entered, its leaf box not; z=6 triangle missed
+        ((-1.2, 0.0, 3.0), (0, 0, 10.0), True, 2, 1),    # inner leaf: slot 2 (x<0) hits first
+        ((-0.2, 0.5, 3.0), (0, 0, 10.0), True, 2, 3),    # inner leaf: both miss (right of slot 2 hypotenuse), z=6 hits
+        ((10.0, 0.5, 0.0), (0, 0, 10.0), False, 1, 0),   # misses every box
+    ]
+    for o, d, occ_want, nn_want, nt_want in cases:
+        occ, nn, nt = sc.count_any([o], [d], nodes, order)
+        brute = sc.any_hit(np.array(o), np.array(d), 0.0, 1.0, brute=True)
+        assert bool(occ[0]) == occ_want == bool(brute[0] if isinstance(brute, tuple) else brute), (o, d)
+        assert (nn, nt) == (nn_want, nt_want), (o, d, nn, nt)

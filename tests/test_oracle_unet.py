@@ -112,3 +112,18 @@ def test_forward_bf16_close_to_fp64():
     y16, _ = U.forward(p, x, bf16=True)
     assert np.abs(y64 - y16).max() < 0.05
     assert np.abs(y64 - y16).max() > 0
+
+
+def test_bf16_rounding_flips_set_the_gradient_tolerance():
+    """BF16 rounding flips alone (the oracle with FP32 instead of FP64 convolution sums, same storage
+    points) move the parameter gradients of the 2x16x24 test batch by more than 5e-3 for several tensors,
+    and those of the 2x64x96 batch by less than 2e-3: a fixed 5e-3 bound fits the larger batch only, and
+    the GPU gradient test bounds each tensor by max(5e-3, 2 x this oracle-internal difference)."""
+    from tests import unet_flips as F
+    from tests.test_gpu_denoiser import oracle_params, random_batch
+    p = oracle_params(5)
+    small, flips_s = F.flip_scale(p, *random_batch(7, 2, 16, 24))
+    large, flips_l = F.flip_scale(p, *random_batch(7, 2, 64, 96))
+    assert flips_s > 0 and flips_l > 0
+    assert sum(v > 5e-3 for v in small.values()) >= 4, small
+    assert max(large.values()) < 2e-3, large
