@@ -59,7 +59,10 @@ int rc_version(void);
 int rc_create(rc_ctx** out, int device, void* hip_stream);
 int rc_destroy(rc_ctx* ctx);
 int rc_set_stream(rc_ctx* ctx, void* hip_stream);
-/* Report and clear the sticky device error (synchronises the stream). */
+/* Report and clear the sticky device errors (synchronises the stream): RC_ERR_QUEUE_OVERFLOW when a
+ * kernel exceeded a work-queue or stack bound, else RC_ERR_INVALID_VALUE when a kernel met an input it
+ * cannot use (a hit id beyond the scene's triangles in rc_shade / rc_pack_features), else any error of
+ * an asynchronous call, else RC_OK. */
 int rc_get_last_error(rc_ctx* ctx);
 
 /* ---------------------------------------------------------------- scene ---- */
@@ -282,7 +285,10 @@ int rc_render(rc_ctx* ctx, rc_scene* scene, const rc_camera* cam,
               const rc_rect_light* rect, const rc_render_opts* opts, const rc_outputs* out);
 
 /* The shading + resolve stage of rc_render alone, from given G-buffer, shadow masks and
- * visibility (for example a denoised visibility).  Same layouts and rules as rc_render. */
+ * visibility (for example a denoised visibility).  Same layouts, rules and argument checks as rc_render
+ * (RC_ERR_NOT_BUILT before rc_bvh_build; RC_ERR_INVALID_VALUE for a non-finite camera or light).  A sample
+ * whose hit id is neither 0xFFFFFFFF nor below the scene's triangle count (a G-buffer of another scene) is
+ * shaded as a miss and sets the sticky RC_ERR_INVALID_VALUE reported by rc_get_last_error. */
 int rc_shade(rc_ctx* ctx, rc_scene* scene, const rc_camera* cam, const rc_point_light* lights, uint32_t n_lights,
              const rc_rect_light* rect, const uint32_t* d_hit, const uint32_t* d_shadow, const float* d_visibility,
              float* d_rgba, float* d_sample_rgba);
@@ -409,7 +415,9 @@ int rc_denoiser_save(rc_ctx* ctx, const rc_denoiser* den, const char* path);
 int rc_denoiser_load(rc_ctx* ctx, rc_denoiser* den, const char* path);
 
 /* Denoiser input features of a 1-sample-per-pixel render (d_hit and d_visibility as written by
- * rc_render with a rect light) into d_features (W*H*8 bfloat16). */
+ * rc_render with a rect light) into d_features (W*H*8 bfloat16).  A hit id beyond the scene's triangles is
+ * packed as background and sets the sticky RC_ERR_INVALID_VALUE (rc_get_last_error).  RC_ERR_NOT_BUILT
+ * before rc_bvh_build. */
 int rc_pack_features(rc_ctx* ctx, rc_scene* scene, const rc_camera* cam, const uint32_t* d_hit,
                      const float* d_visibility, float depth_norm, uint16_t* d_features);
 

@@ -6,9 +6,11 @@ namespace {
 // One thread per pixel: every sample is shaded in FP64 from the FP32 hit (the hit point is
 // reconstructed from the camera ray and the triangle), rounded to FP32, and the samples are
 // box-averaged in the fixed order ((s0 + s1) + (s2 + s3)) * 0.25.
+// A hit id at or beyond the scene's triangle count (a G-buffer from another scene) is shaded as a miss and
+// sets the context's invalid-value flag.
 __global__ __launch_bounds__(256) void k_shade(DevScene sc, DevCamera cam, DevLights L, const uint4* gbuf,
                                                const uint32_t* mask, const float* vis, float* rgba,
-                                               float* sample_rgba)
+                                               float* sample_rgba, uint32_t* bad_value)
 {
     const uint32_t n_pix = (uint32_t)cam.width * (uint32_t)cam.height;
     const uint32_t pixel = blockIdx.x * blockDim.x + threadIdx.x;
@@ -19,9 +21,12 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, DevCamera cam, DevLi
         size_t s = (size_t)pixel * spp + k;
         uint4 h = gbuf[s];
         float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (h.x != RC_NO_HIT)
+        if (h.x != RC_NO_HIT && h.x >= sc.n_tris) {
+            *bad_value = 1u;
+        } else if (h.x != RC_NO_HIT) {
             out = rc_shade_sample(sc, cam, &L.point[0][0], L.n_point, L.has_rect ? L.rect : nullptr,
                                   L.has_rect ? (double)vis[pixel] : 0.0, pixel, k, h.x, mask ? mask[s] : 0u);
+        }
         smp[k] = out;
         if (sample_rgba) reinterpret_cast<float4*>(sample_rgba)[s] = out;
     }
@@ -161,15 +166,18 @@ __device__ inline uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
-// denoiser features per pixel: 1-spp visibility, log depth, normal, albedo (background: 1, 1, 0...)
+// denoiser features per pixel: 1-spp visibility, log depth, normal, albedo (background: 1, 1, 0...); a hit id
+// beyond the scene's triangles is packed as background and sets the invalid-value flag
 __global__ __launch_bounds__(256) void k_pack_features(DevScene sc, DevCamera cam, const uint4* gbuf, const float* vis,
-                                                       float inv_log_norm, uint16_t* feat)
+                                                       float inv_log_norm, uint16_t* feat, uint32_t* bad_value)
 {
     uint32_t pixel = blockIdx.x * blockDim.x + threadIdx.x;
     if (pixel >= (uint32_t)(cam.width * cam.height)) return;
     uint4 h = gbuf[pixel];
     float f[8] = {1.0f, 1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (h.x != RC_NO_HIT) {
+    if (h.x != RC_NO_HIT && h.x >= sc.n_tris) {
+        *bad_value = 1u;
+    } else if (h.x != RC_NO_HIT) {
         Surface S = rc_surface(sc, cam, pixel, 0, h.x);
         const float* mat = sc.mats + 5 * (size_t)sc.tri_mat[h.x];
         f[0] = vis[pixel];
@@ -191,11 +199,11 @@ inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b
 
 void rc_launch_shade(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
                      const uint32_t* mask, const float* visibility, float* rgba, float* sample_rgba,
-                     hipStream_t st)
+                     uint32_t* bad_value, hipStream_t st)
 {
     size_t n = (size_t)cam.width * cam.height;
     hipLaunchKernelGGL(k_shade, dim3(blocks(n, 256)), dim3(256), 0, st, sc, cam, L, gbuf, mask, visibility, rgba,
-                       sample_rgba);
+                       sample_rgba, bad_value);
 }
 
 void rc_launch_camera_rays(const DevCamera& cam, float* o, float* d, uint32_t n, hipStream_t st)
@@ -205,10 +213,11 @@ void rc_launch_camera_rays(const DevCamera& cam, float* o, float* d, uint32_t n,
 }
 
 void rc_launch_pack_features(const DevScene& sc, const DevCamera& cam, const uint4* gbuf, const float* vis,
-                             float inv_log_norm, uint16_t* feat, hipStream_t st)
+                             float inv_log_norm, uint16_t* feat, uint32_t* bad_value, hipStream_t st)
 {
     size_t n = (size_t)cam.width * cam.height;
-    hipLaunchKernelGGL(k_pack_features, dim3(blocks(n, 256)), dim3(256), 0, st, sc, cam, gbuf, vis, inv_log_norm, feat);
+    hipLaunchKernelGGL(k_pack_features, dim3(blocks(n, 256)), dim3(256), 0, st, sc, cam, gbuf, vis, inv_log_norm, feat,
+                       bad_value);
 }
 
 void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris, float4* tris,

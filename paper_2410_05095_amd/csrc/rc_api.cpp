@@ -211,12 +211,12 @@ int rc_get_last_error(rc_ctx* c)
     int st = c->sticky;
     c->sticky = RC_OK;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return RC_ERR_HIP;
-    uint32_t flag = 0;
-    if (hipMemcpy(&flag, c->d_counters + 8, sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess) return RC_ERR_HIP;
-    if (flag) {
-        uint32_t zero = 0;
-        hipMemcpy(c->d_counters + 8, &zero, sizeof(zero), hipMemcpyHostToDevice);
-        if (st == RC_OK) st = RC_ERR_QUEUE_OVERFLOW;
+    uint32_t flag[2] = {0, 0};   // [0] a queue or stack bound was exceeded, [1] a kernel met an invalid input value
+    if (hipMemcpy(flag, c->d_counters + 8, sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess) return RC_ERR_HIP;
+    if (flag[0] | flag[1]) {
+        const uint32_t zero[2] = {0, 0};
+        hipMemcpy(c->d_counters + 8, zero, sizeof(zero), hipMemcpyHostToDevice);
+        if (st == RC_OK) st = flag[0] ? RC_ERR_QUEUE_OVERFLOW : RC_ERR_INVALID_VALUE;
     }
     return st;
 }
@@ -605,15 +605,45 @@ int rc_bvh_export(rc_ctx* c, const rc_scene* s, uint32_t* nodes_out, uint32_t* o
     return RC_OK;
 }
 
-int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light* lights, uint32_t n_lights,
-              const rc_rect_light* rect, const rc_render_opts* opts, const rc_outputs* out)
+namespace {
+
+// Camera checks shared by the entry points that take a camera: size, sample grid, finite pose, field of view.
+int check_camera(const rc_camera* cam)
 {
-    if (!c || !s || !cam || !out) return RC_ERR_INVALID_ARG;
     if (cam->width <= 0 || cam->height <= 0 || (int64_t)cam->width * cam->height > (1ll << 28)) return RC_ERR_INVALID_ARG;
     if (cam->ssaa != 1 && cam->ssaa != 2) return RC_ERR_UNSUPPORTED;
     if (!(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f) || !finite3(cam->eye) || !finite3(cam->target) ||
         !finite3(cam->up))
         return RC_ERR_INVALID_VALUE;
+    return RC_OK;
+}
+
+// Light table of a render or shade call: finite positions, intensities and rect-light geometry.
+int fill_lights(DevLights& L, const rc_point_light* lights, uint32_t n_lights, const rc_rect_light* rect)
+{
+    memset(&L, 0, sizeof(L));
+    L.n_point = (int)n_lights;
+    for (uint32_t l = 0; l < n_lights; ++l) {
+        if (!finite3(lights[l].position) || !finite3(lights[l].intensity)) return RC_ERR_INVALID_VALUE;
+        for (int k = 0; k < 3; ++k) { L.point[l][k] = lights[l].position[k]; L.point[l][3 + k] = lights[l].intensity[k]; }
+    }
+    if (rect) {
+        L.has_rect = 1;
+        memcpy(L.rect, rect, sizeof(float) * 12);
+        for (int k = 0; k < 12; ++k)
+            if (!isfinite(L.rect[k])) return RC_ERR_INVALID_VALUE;
+    }
+    return RC_OK;
+}
+
+}  // namespace
+
+int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light* lights, uint32_t n_lights,
+              const rc_rect_light* rect, const rc_render_opts* opts, const rc_outputs* out)
+{
+    if (!c || !s || !cam || !out) return RC_ERR_INVALID_ARG;
+    int st = check_camera(cam);
+    if (st != RC_OK) return st;
     if (n_lights > 16 || (n_lights > 0 && !lights)) return RC_ERR_INVALID_ARG;
     if (!out->d_rgba || !out->d_hit) return RC_ERR_INVALID_ARG;
     if (n_lights > 0 && !out->d_shadow) return RC_ERR_INVALID_ARG;
@@ -630,17 +660,9 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     DevCamera dc = make_camera(cam);
     DevScene ds = dev_scene(s);
     DevLights L;
-    memset(&L, 0, sizeof(L));
-    L.n_point = (int)n_lights;
-    for (uint32_t l = 0; l < n_lights; ++l) {
-        if (!finite3(lights[l].position) || !finite3(lights[l].intensity)) return RC_ERR_INVALID_VALUE;
-        for (int k = 0; k < 3; ++k) { L.point[l][k] = lights[l].position[k]; L.point[l][3 + k] = lights[l].intensity[k]; }
-    }
+    st = fill_lights(L, lights, n_lights, rect);
+    if (st != RC_OK) return st;
     if (rect) {
-        L.has_rect = 1;
-        memcpy(L.rect, rect, sizeof(float) * 12);
-        for (int k = 0; k < 12; ++k)
-            if (!isfinite(L.rect[k])) return RC_ERR_INVALID_VALUE;
         L.area_samples = (int)opts->area_samples;
         L.area_stream = opts->area_stream;
     }
@@ -652,7 +674,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     w.overflow_depth = s->hb.max_stack > RC_STACK_LDS ? s->hb.max_stack - RC_STACK_LDS : 0;
     w.n_lanes = (uint32_t)c->grid * RC_TRACE_BLOCK;
     w.error_flag = c->d_counters + 8;
-    int st = ensure_overflow(c, s->hb.max_stack);
+    st = ensure_overflow(c, s->hb.max_stack);
     if (st != RC_OK) return st;
     w.overflow = c->d_overflow;
 
@@ -686,7 +708,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     }
     if (timing) RC_HIP(hipEventRecord(c->ev[2], q));
     rc_launch_shade(ds, dc, L, gbuf, n_lights ? out->d_shadow : nullptr, out->d_visibility, out->d_rgba,
-                    out->d_sample_rgba, q);
+                    out->d_sample_rgba, c->d_counters + 9, q);
     if (timing) RC_HIP(hipEventRecord(c->ev[3], q));
     c->timed = timing;
     c->timed_batch = false;
@@ -699,27 +721,22 @@ int rc_shade(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light*
              float* d_rgba, float* d_sample_rgba)
 {
     if (!c || !s || !cam || !d_hit || !d_rgba) return RC_ERR_INVALID_ARG;
-    if (cam->width <= 0 || cam->height <= 0 || (int64_t)cam->width * cam->height > (1ll << 28)) return RC_ERR_INVALID_ARG;
-    if (cam->ssaa != 1 && cam->ssaa != 2) return RC_ERR_UNSUPPORTED;
+    int st = check_camera(cam);
+    if (st != RC_OK) return st;
     if (n_lights > 16 || (n_lights > 0 && (!lights || !d_shadow))) return RC_ERR_INVALID_ARG;
     if (rect && (!d_vis || cam->ssaa != 1)) return RC_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(d_rgba) | reinterpret_cast<uintptr_t>(d_hit) |
          reinterpret_cast<uintptr_t>(d_sample_rgba)) & 15u)
         return RC_ERR_INVALID_ARG;
+    if (!s->built) return RC_ERR_NOT_BUILT;
+    DevLights L;
+    st = fill_lights(L, lights, n_lights, rect);
+    if (st != RC_OK) return st;
     RC_HIP(hipSetDevice(c->device));
     DevCamera dc = make_camera(cam);
     DevScene ds = dev_scene(s);
-    DevLights L;
-    memset(&L, 0, sizeof(L));
-    L.n_point = (int)n_lights;
-    for (uint32_t l = 0; l < n_lights; ++l)
-        for (int k = 0; k < 3; ++k) { L.point[l][k] = lights[l].position[k]; L.point[l][3 + k] = lights[l].intensity[k]; }
-    if (rect) {
-        L.has_rect = 1;
-        memcpy(L.rect, rect, sizeof(float) * 12);
-    }
     rc_launch_shade(ds, dc, L, reinterpret_cast<const uint4*>(d_hit), n_lights ? d_shadow : nullptr, d_vis, d_rgba,
-                    d_sample_rgba, c->stream);
+                    d_sample_rgba, c->d_counters + 9, c->stream);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }
@@ -762,15 +779,17 @@ int rc_pack_features(rc_ctx* c, rc_scene* s, const rc_camera* cam, const uint32_
                      float depth_norm, uint16_t* d_feat)
 {
     if (!c || !s || !cam || !d_hit || !d_vis || !d_feat) return RC_ERR_INVALID_ARG;
-    if (cam->width <= 0 || cam->height <= 0 || (int64_t)cam->width * cam->height > (1ll << 28)) return RC_ERR_INVALID_ARG;
+    int st = check_camera(cam);
+    if (st != RC_OK) return st;
     if (cam->ssaa != 1) return RC_ERR_UNSUPPORTED;
     if (!(depth_norm > 0.0f) || !isfinite(depth_norm)) return RC_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(d_hit) | reinterpret_cast<uintptr_t>(d_feat)) & 15u) return RC_ERR_INVALID_ARG;
+    if (!s->built) return RC_ERR_NOT_BUILT;
     RC_HIP(hipSetDevice(c->device));
     DevCamera dc = make_camera(cam);
     DevScene ds = dev_scene(s);
     rc_launch_pack_features(ds, dc, reinterpret_cast<const uint4*>(d_hit), d_vis, (float)(1.0 / log1p((double)depth_norm)),
-                            d_feat, c->stream);
+                            d_feat, c->d_counters + 9, c->stream);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

@@ -107,7 +107,8 @@ hipError_t rc_tlas_build(TlasWork& w, const float* o2w, Node4* nodes, uint32_t t
 
 // Traversal launch geometry
 #define RC_TRACE_BLOCK 128
-// Work-queue counters: words [0, 8) single queues, [8] error flag; from word RC_QUEUE_BASE, per queue slot
+// Work-queue counters: words [0, 8) single queues, [8] sticky bound-exceeded flag, [9] sticky invalid-value flag
+// (an input a kernel cannot use, e.g. a hit id beyond the scene); from word RC_QUEUE_BASE, per queue slot
 // one counter per XCD, each on its own 256-byte line.
 #define RC_XCDS 8
 #define RC_QUEUE_SLOTS 4
@@ -172,10 +173,10 @@ int rc_batch_max_blocks_per_cu(int device);
 // Launchers (k_shade.hip)
 void rc_launch_shade(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
                      const uint32_t* mask, const float* visibility, float* rgba, float* sample_rgba,
-                     hipStream_t st);
+                     uint32_t* bad_value, hipStream_t st);
 void rc_launch_camera_rays(const DevCamera& cam, float* o, float* d, uint32_t n, hipStream_t st);
 void rc_launch_pack_features(const DevScene& sc, const DevCamera& cam, const uint4* gbuf, const float* vis,
-                             float inv_log_norm, uint16_t* feat, hipStream_t st);
+                             float inv_log_norm, uint16_t* feat, uint32_t* bad_value, hipStream_t st);
 void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris,
                     float4* tris, bool raw, hipStream_t st);
 void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st);

@@ -96,6 +96,35 @@ def test_forward_matches_oracle(ctx):
         assert err.max() < 2e-3 and err.mean() < 1e-4
 
 
+@pytest.mark.parametrize("n,h,w", [(1, 128, 256), (1, 256, 512), (2, 68, 132)])
+def test_forward_full_tiling_matches_oracle(ctx, n, h, w):
+    """The fused BF16 inference (pools and head in the convolution epilogues, decoder concat in the halo
+    loads) and the FP32 copy, element by element against the oracle, at sizes with several 64-column
+    tiles and row blocks per level and ragged tile edges (68x132).  BF16 bound: max(2e-3, 2 x) for the
+    maximum and max(1e-4, 2 x) for the mean of the oracle's own difference between FP32 and FP64
+    convolution sums (the BF16 rounding-flip scale of this input)."""
+    from paper_2410_05095_amd import _native as N
+    from tests import unet_flips as F
+    den = N.Denoiser(ctx, seed=1)
+    p = oracle_params(3)
+    den.set_params(U.flat(p).astype(np.float32))
+    x, t, m = random_batch(40 + h, n, h, w)
+    xd, _, _ = to_dev(ctx, x, t, m)
+    y = den.infer(xd).cpu().numpy().astype(np.float64)
+    y32 = den.infer(xd, fp32=True).cpu().numpy().astype(np.float64)
+    yo, _ = U.forward(p, x, bf16=True)
+    yo32, _ = U.forward(p, x, bf16=True, conv=F.conv3x3_f32)
+    y64, _ = U.forward(p, x, bf16=False)
+    flip = np.abs(yo32 - yo)
+    err = np.abs(y - yo)
+    err32 = np.abs(y32 - y64)
+    say(f"[unet fwd tiled {n}x{h}x{w}] bf16: max {err.max():.2e} mean {err.mean():.2e} (oracle flip scale max "
+        f"{flip.max():.2e} mean {flip.mean():.2e}); fp32 copy vs fp64: max {err32.max():.2e}")
+    assert err.max() <= max(2e-3, 2 * flip.max())
+    assert err.mean() <= max(1e-4, 2 * flip.mean())
+    assert err32.max() < 2e-5
+
+
 def test_fused_inference_equals_training_forward(ctx):
     """Inference computes the 2x2 pools and the head inside the convolution epilogues and writes the head
     straight into the output; the training step's forward stores every activation and runs the separate
@@ -135,14 +164,15 @@ def test_fp32_copy_matches_oracle(ctx):
         assert np.abs(y16 - y32).max() < 2e-2
 
 
-@pytest.mark.parametrize("n,h,w,frob", [(2, 16, 24, False), (2, 64, 96, True)])
-def test_gradients_match_oracle(ctx, n, h, w, frob):
-    """Training-step gradients against the oracle with BF16 emulation.  The per-tensor relative Frobenius
-    bound (5e-3) is checked on the 2x64x96 batch.  On 2x16x24 the GPU/oracle difference is decided by a
-    handful of activations whose FP32 and FP64 sums round to different BF16 values (one image of that
-    batch matches to 7e-8, the other differs by 1e-3 or not at all depending on the summation order of the
-    convolution), so there only the loss and the cosine of every gradient are bounded."""
+@pytest.mark.parametrize("n,h,w", [(2, 16, 24), (2, 64, 96)])
+def test_gradients_match_oracle(ctx, n, h, w):
+    """Training-step gradients against the oracle with BF16 emulation.  Each parameter tensor's relative
+    Frobenius error is bounded by max(5e-3, 2 x the oracle's own BF16-flip scale on the same batch): the
+    difference between the oracle's gradients with FP32 and with FP64 convolution sums (tests/unet_flips.py).
+    On 2x64x96 that scale is below 2e-3, so the bound is 5e-3; on 2x16x24 a handful of activations whose
+    sums round to different BF16 values decide several tensors' errors, and the scale reaches 1.7e-2."""
     from paper_2410_05095_amd import _native as N
+    from tests import unet_flips as F
     den = N.Denoiser(ctx, seed=2)
     p = oracle_params(5)
     den.set_params(U.flat(p).astype(np.float32))
@@ -153,17 +183,18 @@ def test_gradients_match_oracle(ctx, n, h, w, frob):
     yo, cache = U.forward(p, x, bf16=True)
     go, _ = U.backward(p, cache, t, m, bf16_grads=True)
     lo = U.masked_mse(yo, t, m)
-    say(f"[unet loss {n}x{h}x{w}] gpu {loss:.6e} oracle {lo:.6e}")
+    scale, flips = F.flip_scale(p, x, t, m)
+    say(f"[unet loss {n}x{h}x{w}] gpu {loss:.6e} oracle {lo:.6e}; oracle FP32/FP64-sum flips {flips}")
     assert abs(loss - lo) <= 1e-4 * lo
     worst = 0.0
     for k in U.param_names():
         rf, cs = rel_frob(g[k], go[k]), cosine(g[k], go[k])
-        worst = max(worst, rf)
-        say(f"  {k:8s} rel_frob {rf:.2e} cos {cs:.8f}")
+        bound = max(5e-3, 2.0 * scale[k])
+        worst = max(worst, rf / bound)
+        say(f"  {k:8s} rel_frob {rf:.2e} (bound {bound:.2e}, oracle flip scale {scale[k]:.2e}) cos {cs:.8f}")
         assert cs >= 0.9999, k
-        if frob:
-            assert rf <= 5e-3, k
-    say(f"[unet grads {n}x{h}x{w}] worst relative Frobenius error {worst:.2e}")
+        assert rf <= bound, k
+    say(f"[unet grads {n}x{h}x{w}] worst error / bound {worst:.3f}")
     # the lr = 0 step left the weights unchanged
     assert np.array_equal(den.params(), U.flat(p).astype(np.float32))
 

@@ -165,6 +165,45 @@ def test_render_error_paths(ctx):
     assert ctx.last_error() == 0
 
 
+def test_shade_rejects_foreign_hit_ids(ctx):
+    """rc_shade and rc_pack_features take a caller's G-buffer: an id at or beyond the scene's triangle count
+    (a buffer from a larger scene) is shaded and packed as a miss, and the context reports
+    RC_ERR_INVALID_VALUE; the other pixels are unchanged.  rc_shade validates lights like rc_render."""
+    import torch
+    from paper_2410_05095_amd import _native as N
+    scene = sg.small_random_scene(4, n_instances=4, width=16, height=12, ssaa=1)
+    cam = scene.cameras[0]
+    gs = ctx.scene_from(scene).build()
+    out = ctx.render(gs, cam, scene.point_lights, rect=scene.rect_light, area_samples=4, area_stream=0)
+    torch.cuda.synchronize()
+    assert ctx.last_error() == 0
+    ref = out["rgba"].clone()
+    hit = out["hit"].view(torch.int32).view(-1, 4)
+    ids = hit[:, 0].cpu().numpy().view(np.uint32)
+    victim = int(np.nonzero(ids != 0xFFFFFFFF)[0][0])
+    for bad_id in (scene.n_tris, 0x7FFFFFF0):
+        hit[victim, 0] = int(np.array(bad_id, np.uint32).view(np.int32))
+        ctx.shade(gs, cam, out, lights=scene.point_lights, rect=scene.rect_light)
+        torch.cuda.synchronize()
+        assert ctx.last_error() == -2, bad_id
+        got = out["rgba"].cpu().numpy().reshape(-1, 4)
+        want = ref.cpu().numpy().reshape(-1, 4)
+        assert np.all(got[victim] == 0.0)
+        others = np.arange(len(got)) != victim
+        assert np.array_equal(got[others], want[others])
+        feat = N.pack_features(ctx, gs, cam, out, depth_norm=60.0)
+        torch.cuda.synchronize()
+        assert ctx.last_error() == -2
+        f = feat.float().cpu().numpy().reshape(-1, 8)
+        assert np.array_equal(f[victim], np.array([1, 1, 0, 0, 0, 0, 0, 0], np.float32))
+    assert ctx.last_error() == 0      # the flag was cleared when read
+    lights = np.array(scene.point_lights, np.float32).copy()
+    lights[0, 0] = np.nan
+    with pytest.raises(N.RcError) as e:
+        ctx.shade(gs, cam, out, lights=lights)
+    assert e.value.status == -2
+
+
 def compare_rect(ctx, O, scene, cam, N, stream, pixels=None, device_build=False, gs=None, osc=None):
     """Both rect-light kernels (wave-uniform traversal, the default; per-lane stacks)
     against one oracle run: hit ids and visible-sample counts exact outside the FP32 band, radiance within
