@@ -316,6 +316,18 @@ enum { RC_POST_FXAA = 1u };
 int rc_postprocess(rc_ctx* ctx, const float* d_rgba, uint32_t width, uint32_t height, uint32_t flags,
                    uint8_t* d_out);
 
+/* rc_postprocess without any allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid allocation after set-up).  Same arguments, definition
+ * and output as rc_postprocess; the tone-mapped intermediate image of the FXAA pass lives in a fixed per-GPU
+ * scratch array of RC_POST_NOALLOC_MAX_PIXELS (2^22) pixels x 4 bytes = 16 MiB, set up by rc_create and held
+ * until the process ends.  width x height above 2^22 gives RC_ERR_INVALID_ARG.  Every call on one GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (two streams, two contexts or two threads) race and must
+ * be ordered by the caller.  Enqueues kernels only: no hipMalloc, hipFree or synchronisation.  RC_ERR_HIP if
+ * rc_create could not obtain the scratch's device address. */
+enum { RC_POST_NOALLOC_MAX_PIXELS = 1 << 22 };
+int rc_postprocess_noalloc(rc_ctx* ctx, const float* d_rgba, uint32_t width, uint32_t height, uint32_t flags,
+                           uint8_t* d_out);
+
 /* Camera rays of every sample, exactly as the traversal generates them: d_origins and
  * d_dirs receive W*H*S x 3 float each (sample s = pixel * S + k).  For verification of the
  * FP32 ray definition. */

@@ -121,6 +121,7 @@ SIGNATURES = {
     "rc_denoiser_set_params": (C.c_int, [P, P, P]),
     "rc_denoiser_get_grads": (C.c_int, [P, P, P]),
     "rc_postprocess": (C.c_int, [P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
+    "rc_postprocess_noalloc": (C.c_int, [P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
     "rc_denoiser_infer": (C.c_int, [P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
     "rc_denoiser_infer_fp32": (C.c_int, [P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
     "rc_denoiser_train_step": (C.c_int, [P, P, P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_float,
@@ -367,6 +368,17 @@ class Context:
         self._sync_stream()
         check(lib().rc_postprocess(self.h, C.c_void_p(rgba.data_ptr()), W, H, 1 if fxaa else 0,
                                    C.c_void_p(out.data_ptr())), "rc_postprocess")
+        return out
+
+    def postprocess_noalloc(self, rgba, out, fxaa: bool = True):
+        """rc_postprocess_noalloc: the display post pass into the caller's (H, W, 4) uint8 `out`, with the FXAA
+        intermediate in the library's fixed per-GPU scratch (no allocation)."""
+        assert rgba.dtype == self.torch.float32 and rgba.is_contiguous() and rgba.shape[-1] == 4
+        assert out.dtype == self.torch.uint8 and out.is_contiguous() and out.shape == rgba.shape
+        H, W = int(rgba.shape[0]), int(rgba.shape[1])
+        self._sync_stream()
+        check(lib().rc_postprocess_noalloc(self.h, C.c_void_p(rgba.data_ptr()), W, H, 1 if fxaa else 0,
+                                           C.c_void_p(out.data_ptr())), "rc_postprocess_noalloc")
         return out
 
     def stage_times(self) -> dict:

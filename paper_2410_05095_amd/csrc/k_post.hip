@@ -4,6 +4,8 @@
 // rc_postprocess in include/raycast.h; both kernels are HBM-bound image passes.
 #include "rc_internal.h"
 
+#include <mutex>
+
 namespace {
 
 constexpr int EDGE_MIN = 2048;   // minimum local luma range (luma scale 0..65280)
@@ -121,4 +123,41 @@ void rc_launch_postprocess(const float* rgba, uint32_t w, uint32_t h, bool fxaa,
     if (fxaa)
         hipLaunchKernelGGL(k_fxaa, dim3((w + 15) / 16, (h + 15) / 16), dim3(256), 0, st, tm, (int)w, (int)h,
                            reinterpret_cast<uchar4*>(out));
+}
+
+// Fixed scratch of rc_postprocess_noalloc: the tone-mapped 8-bit image that FXAA reads, for images of at most
+// RC_POST_SCRATCH_PIXELS pixels (16 MiB).  Each GPU the library runs on holds its own copy until the
+// process ends.  In host code this name is only a stand-in for the symbol: kernels receive the device address
+// that rc_post_scratch_init obtained for the current device.
+static __device__ __align__(256) uchar4 scratch[RC_POST_SCRATCH_PIXELS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+uint8_t* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t rc_post_scratch_init(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && ptr) g_scratch_ptr[device] = static_cast<uint8_t*>(ptr);
+    else if (e == hipSuccess) e = hipErrorInvalidSymbol;
+    hipError_t e2 = hipSetDevice(prev);
+    return e != hipSuccess ? e : e2;
+}
+
+uint8_t* rc_post_scratch(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_ptr[device];
 }

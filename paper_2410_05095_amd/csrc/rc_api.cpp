@@ -170,6 +170,9 @@ int rc_create(rc_ctx** out, int device, void* hip_stream)
     if (st == RC_OK && hipMemset(c->d_counters, 0, RC_COUNTER_WORDS * sizeof(uint32_t)) != hipSuccess) st = RC_ERR_HIP;
     if (st == RC_OK && hipMemset(c->d_rays, 0, 8 * sizeof(unsigned long long)) != hipSuccess) st = RC_ERR_HIP;
     if (st != RC_OK) { rc_destroy(c); return st; }
+    // the fixed scratch of rc_postprocess_noalloc on this device; should its address be unavailable, that entry
+    // point reports RC_ERR_HIP and everything else works
+    if (rc_post_scratch_init(device) != hipSuccess) (void)hipGetLastError();
     *out = c;
     return RC_OK;
 }
@@ -759,6 +762,23 @@ int rc_postprocess(rc_ctx* c, const float* d_rgba, uint32_t width, uint32_t heig
         c->post_cap = bytes;
     }
     rc_launch_postprocess(d_rgba, width, height, fxaa, c->d_post, d_out, c->stream);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+static_assert(RC_POST_SCRATCH_PIXELS == (uint32_t)RC_POST_NOALLOC_MAX_PIXELS, "scratch size of the ABI");
+
+int rc_postprocess_noalloc(rc_ctx* c, const float* d_rgba, uint32_t width, uint32_t height, uint32_t flags,
+                           uint8_t* d_out)
+{
+    if (!c || !d_rgba || !d_out || width == 0 || height == 0) return RC_ERR_INVALID_ARG;
+    if ((flags & ~(uint32_t)RC_POST_FXAA) != 0) return RC_ERR_INVALID_ARG;
+    if ((uint64_t)width * height > RC_POST_NOALLOC_MAX_PIXELS) return RC_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(d_rgba) & 15u || reinterpret_cast<uintptr_t>(d_out) & 3u) return RC_ERR_INVALID_ARG;
+    uint8_t* scratch = rc_post_scratch(c->device);
+    if (!scratch) return RC_ERR_HIP;
+    RC_HIP(hipSetDevice(c->device));
+    rc_launch_postprocess(d_rgba, width, height, (flags & RC_POST_FXAA) != 0, scratch, d_out, c->stream);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

@@ -135,6 +135,11 @@ int rc_trace_grid(int device);
 // Display post pass (k_post.hip): tone map + sRGB8 into `out`, or into `scratch` followed by FXAA into `out`
 void rc_launch_postprocess(const float* rgba, uint32_t w, uint32_t h, bool fxaa, uint8_t* scratch, uint8_t* out,
                            hipStream_t st);
+// Fixed per-device scratch of rc_postprocess_noalloc (k_post.hip): rc_post_scratch_init obtains its device
+// address on `device` (once; called by rc_create), rc_post_scratch returns it (NULL before init).
+constexpr uint32_t RC_POST_SCRATCH_PIXELS = 1u << 22;   // = RC_POST_NOALLOC_MAX_PIXELS of the C ABI
+hipError_t rc_post_scratch_init(int device);
+uint8_t* rc_post_scratch(int device);
 
 // Batched rendering: one persistent launch over many views of several scenes.
 struct DevView {
