@@ -124,7 +124,14 @@ int rc_scene_destroy(rc_ctx* ctx, rc_scene* scene);
  * RC_ERR_INVALID_ARG).  All methods give exact child boxes (FP32 min/max of what the child
  * holds) and leaves of at most `max_leaf` (1..4, default 4) triangles.  Replaces any previous
  * BVH.  Synchronous with respect to the host (works on the context stream and waits for it). */
-enum { RC_BUILD_HOST_SAH = 0u, RC_BUILD_DEVICE_LBVH = 1u, RC_BUILD_TWO_LEVEL = 2u };
+enum { RC_BUILD_HOST_SAH = 0u, RC_BUILD_DEVICE_LBVH = 1u, RC_BUILD_TWO_LEVEL = 2u, RC_BUILD_DEVICE_SAH = 3u };
+/* RC_BUILD_DEVICE_SAH (3): the binned SAH of RC_BUILD_HOST_SAH built on the GPU from the positions already there,
+ * with the same arithmetic (bins per axis from the centroid bounds, bin = (int)(((double)c - lo) * (bins /
+ * (double)(hi - lo))), split costs area(left) n_left + area(right) n_right in FP64 from exact FP32 boxes, the first
+ * minimum over axis then bin, the same leaf rule, coinciding centroids halved), so that it chooses the host build's
+ * splits; ranges are partitioned stably (the leaf order within a range may differ from the host build's), and the
+ * binary tree is collapsed to 4-wide by the same rule (open the child of largest surface until four children).
+ * bins <= 64 (else RC_ERR_UNSUPPORTED). */
 /* flags: RC_BUILD_WATERTIGHT makes every ray/triangle test of the scene the watertight test
  * of Woop, Benthin and Wald (JCGT 2013) instead of Moller-Trumbore: vertices relative to the
  * ray origin, sheared with kz = axis of the largest |d| (first on ties), kx and ky the next

@@ -422,13 +422,14 @@ class Scene:
             pass
 
     def build(self, bins: int = 32, max_leaf: int = 4, node_cost: float = 4.0, device: bool = False,
-              two_level: bool = False, watertight: bool = False):
-        """Host binned-SAH build; device=True: the GPU LBVH build (RC_BUILD_DEVICE_LBVH); two_level=True: one
-        GPU-built tree per body under a top level over the bodies (RC_BUILD_TWO_LEVEL); watertight=True: the
-        scene's ray/triangle tests use the watertight test (RC_BUILD_WATERTIGHT)."""
+              two_level: bool = False, watertight: bool = False, device_sah: bool = False):
+        """Host binned-SAH build; device=True: the GPU LBVH build (RC_BUILD_DEVICE_LBVH); device_sah=True: the
+        binned SAH built on the GPU (RC_BUILD_DEVICE_SAH); two_level=True: one GPU-built tree per body under a top
+        level over the bodies (RC_BUILD_TWO_LEVEL); watertight=True: the scene's ray/triangle tests use the
+        watertight test (RC_BUILD_WATERTIGHT)."""
         self.ctx._sync_stream()
-        opts = RcBuildOpts(bins, max_leaf, node_cost, 2 if two_level else (1 if device else 0),
-                           1 if watertight else 0)
+        method = 2 if two_level else (3 if device_sah else (1 if device else 0))
+        opts = RcBuildOpts(bins, max_leaf, node_cost, method, 1 if watertight else 0)
         check(lib().rc_bvh_build(self.ctx.h, self.h, C.byref(opts)), "rc_bvh_build")
         return self
 

@@ -323,19 +323,30 @@ __global__ __launch_bounds__(256) void k_bottom_up(const Box6* prim_box, const u
     }
 }
 
+// A binary tree to collapse.  Radix trees (explicit = 0): internal nodes 0 .. n-2 with inclusive primitive ranges,
+// leaves n-1 .. 2n-2 of one primitive each; a subtree of at most max_leaf primitives becomes one leaf.  Explicit
+// trees (explicit = 1, the binned-SAH build): node b is a leaf when child[b].x < 0, with range[b] = (first slot,
+// count); every other node is opened.
 struct TreeView {
     int n, max_leaf;
     const int2* child;
     const int2* range;
     const Box6* box;
     const uint32_t* leaf_id;   // when set (leaves of one primitive): leaf word holds leaf_id[position]
+    int explicit_leaves = 0;
 };
 
 __device__ inline int node_size(const TreeView& T, int b) { return b >= T.n - 1 ? 1 : T.range[b].y - T.range[b].x + 1; }
-__device__ inline bool openable(const TreeView& T, int b) { return b < T.n - 1 && node_size(T, b) > T.max_leaf; }
-__device__ inline float box_area(const Box6& b)
+__device__ inline bool openable(const TreeView& T, int b)
 {
-    const float dx = b.hi[0] - b.lo[0], dy = b.hi[1] - b.lo[1], dz = b.hi[2] - b.lo[2];
+    if (T.explicit_leaves) return T.child[b].x >= 0;
+    return b < T.n - 1 && node_size(T, b) > T.max_leaf;
+}
+// half the surface area, in FP64 from the FP32 box (as the host builder's collapse compares it)
+__device__ inline double box_area(const Box6& b)
+{
+    const double dx = (double)b.hi[0] - b.lo[0], dy = (double)b.hi[1] - b.lo[1], dz = (double)b.hi[2] - b.lo[2];
+    if (!(dx >= 0.0) || !(dy >= 0.0) || !(dz >= 0.0)) return 0.0;
     return dx * dy + dy * dz + dz * dx;
 }
 
@@ -352,10 +363,10 @@ __device__ inline int gather_kids(const TreeView& T, int b, int kids[4])
     kids[1] = T.child[b].y;
     while (cnt < 4) {
         int pick = -1;
-        float best = -1.0f;
+        double best = -1.0;
         for (int k = 0; k < cnt; ++k) {
             if (!openable(T, kids[k])) continue;
-            const float a = box_area(T.box[kids[k]]);
+            const double a = box_area(T.box[kids[k]]);
             if (a > best) { best = a; pick = k; }
         }
         if (pick < 0) break;
@@ -370,6 +381,7 @@ __device__ inline int gather_kids(const TreeView& T, int b, int kids[4])
 
 __device__ inline uint32_t leaf_word(const TreeView& T, int b)
 {
+    if (T.explicit_leaves) return rc_make_leaf((uint32_t)T.range[b].x, (uint32_t)T.range[b].y);
     const int first = b >= T.n - 1 ? b - (T.n - 1) : T.range[b].x;
     if (T.leaf_id) return rc_make_leaf(T.leaf_id[first], 1u);
     return rc_make_leaf((uint32_t)first, (uint32_t)node_size(T, b));
@@ -529,6 +541,52 @@ __global__ __launch_bounds__(CB_THREADS) void k_collapse_block(TreeView T, int r
             nodes[base] = nd;
         }
     }
+}
+
+// Sort of up to SORT_BLOCK_MAX (key, value) pairs in one workgroup, bitonic in LDS, by (key, value): with
+// distinct values given in increasing order (instance ids) this is the order a stable sort by key gives.  The
+// per-frame top level sorts its ~1500 instance keys with it in one launch.
+constexpr uint32_t SORT_BLOCK_MAX = 4096;
+constexpr int SORT_THREADS = 1024;
+
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_block(const uint64_t* keys, const uint32_t* vals, uint32_t n,
+                                                             uint64_t* keys_out, uint32_t* vals_out)
+{
+    __shared__ uint64_t K[SORT_BLOCK_MAX];
+    __shared__ uint32_t V[SORT_BLOCK_MAX];
+    uint32_t m = 1;
+    while (m < n) m <<= 1;
+    for (uint32_t i = threadIdx.x; i < m; i += SORT_THREADS) {
+        K[i] = i < n ? keys[i] : ~0ull;
+        V[i] = i < n ? vals[i] : ~0u;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= m; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < m; i += SORT_THREADS) {
+                const uint32_t l = i ^ j;
+                if (l <= i) continue;
+                const uint64_t ka = K[i], kb = K[l];
+                const uint32_t va = V[i], vb = V[l];
+                const bool greater = ka > kb || (ka == kb && va > vb);
+                if (greater == ((i & k) == 0)) {   // ascending runs where bit k of i is clear
+                    K[i] = kb; K[l] = ka;
+                    V[i] = vb; V[l] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += SORT_THREADS) {
+        keys_out[i] = K[i];
+        vals_out[i] = V[i];
+    }
+}
+
+__global__ void k_iota(uint32_t* p, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
 }
 
 __global__ void k_fill_i32(int* p, int v, uint32_t n)
@@ -701,6 +759,670 @@ hipError_t rc_build_bvh_device(const float* d_pos, const uint32_t* d_idx, uint32
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------- binned SAH on the GPU --------
+// The host builder's algorithm (binned SAH over triangle centroids, `bins` bins per axis, node cost relative to
+// a triangle test, leaves of at most max_leaf triangles) with the same arithmetic, so that it chooses the same
+// splits: bin k = (int)(((double)c - lo) * (bins / (double)(hi - lo))) clamped to [0, bins - 1] per axis with a
+// positive centroid extent; cost of a split before bin k = area(left) n_left + area(right) n_right in FP64 from
+// the exact FP32 union boxes, the first minimum over (axis, k) in order; a range of n <= max_leaf triangles
+// stays a leaf when no split exists or n <= node_cost + best / area(node); a range whose centroids coincide is
+// halved.  Ranges above SAH_SMALL triangles are split level by level, every workgroup binning a chunk of one
+// range; each smaller range is then built to the leaves by one wave.  Partitions are stable, so the build is
+// deterministic.  The binary tree is collapsed to 4-wide like the radix trees (explicit leaves).
+namespace {
+
+constexpr int SAH_NB_MAX = 64;
+constexpr uint32_t SAH_SMALL = 4096;
+constexpr uint32_t SAH_CHUNK = 8192;
+constexpr int SAH_BIN_WORDS = 8;   // ordered lo[3], hi[3], count, pad
+
+__device__ inline uint32_t f2o(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float o2f(uint32_t o) { return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o); }
+constexpr uint32_t O_POS_INF = 0xFF800000u;   // f2o(+inf)
+constexpr uint32_t O_NEG_INF = 0x007FFFFFu;   // f2o(-inf)
+
+// surface area 2 (dx dy + dy dz + dz dx) in FP64, 0 for an empty or inverted box (the host builder's)
+__device__ inline double sah_area(const float lo[3], const float hi[3])
+{
+    const double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+    if (!(dx >= 0.0) || !(dy >= 0.0) || !(dz >= 0.0)) return 0.0;
+    return 2.0 * (dx * dy + dy * dz + dz * dx);
+}
+
+__device__ inline int sah_bin(float c, float lo, double scale, int NB)
+{
+    int k = (int)(((double)c - (double)lo) * scale);
+    return min(max(k, 0), NB - 1);
+}
+
+struct SahTask {
+    uint32_t node, first, count, pad;
+};
+
+struct SahTree {
+    int2* child;     // (left, right), or (-1, -1) for a leaf
+    int2* range;     // (first slot, count)
+    Box6* box;
+    uint32_t* node_ctr;
+};
+
+// The split decision of one range, by one wave: from the bins of the three axes (box as ordered words, count)
+// and the node box; returns best axis (-1: none), the first bin of the right side, and the left count.  Lanes
+// k < NB hold bin k of the axis being swept.
+__device__ inline void sah_decide(const uint32_t* bins /* [3][NB][SAH_BIN_WORDS] */, int NB, const float clo[3],
+                                  const float chi[3], int& best_axis, int& best_split, uint32_t& best_nl,
+                                  double& best_cost)
+{
+    const int lane = (int)__lane_id();
+    double bc = INFINITY;
+    int bidx = 0x7FFFFFFF;
+    uint32_t bnl = 0;
+    for (int axis = 0; axis < 3; ++axis) {
+        const float ext = chi[axis] - clo[axis];
+        if (!(ext > 0.0f)) continue;
+        float lo[3], hi[3];
+        uint32_t cnt = 0;
+        if (lane < NB) {
+            const uint32_t* b = bins + ((size_t)axis * NB + lane) * SAH_BIN_WORDS;
+            for (int k = 0; k < 3; ++k) { lo[k] = o2f(b[k]); hi[k] = o2f(b[3 + k]); }
+            cnt = b[6];
+        } else {
+            for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+        }
+        // inclusive prefix (lanes 0..k) and suffix (lanes k..NB-1) unions and counts
+        float plo[3], phi[3], slo[3], shi[3];
+        uint32_t pc = cnt, sc = cnt;
+        for (int k = 0; k < 3; ++k) { plo[k] = slo[k] = lo[k]; phi[k] = shi[k] = hi[k]; }
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t pcu = __shfl_up(pc, off), scd = __shfl_down(sc, off);
+            float u[6], d[6];
+            for (int k = 0; k < 3; ++k) {
+                u[k] = __shfl_up(plo[k], off); u[3 + k] = __shfl_up(phi[k], off);
+                d[k] = __shfl_down(slo[k], off); d[3 + k] = __shfl_down(shi[k], off);
+            }
+            if (lane >= off) {
+                pc += pcu;
+                for (int k = 0; k < 3; ++k) { plo[k] = fminf(plo[k], u[k]); phi[k] = fmaxf(phi[k], u[3 + k]); }
+            }
+            if (lane + off < 64) {
+                sc += scd;
+                for (int k = 0; k < 3; ++k) { slo[k] = fminf(slo[k], d[k]); shi[k] = fmaxf(shi[k], d[3 + k]); }
+            }
+        }
+        // split before bin lane + 1: left = prefix of lane, right = suffix of lane + 1
+        float rlo[3], rhi[3];
+        for (int k = 0; k < 3; ++k) { rlo[k] = __shfl_down(slo[k], 1); rhi[k] = __shfl_down(shi[k], 1); }
+        const uint32_t rc = __shfl_down(sc, 1);
+        if (lane < NB - 1 && pc > 0 && rc > 0) {
+            const double cost = sah_area(plo, phi) * (double)pc + sah_area(rlo, rhi) * (double)rc;
+            const int idx = axis * NB + lane + 1;
+            if (cost < bc) { bc = cost; bidx = idx; bnl = pc; }
+        }
+    }
+    // first minimum over (axis, split) in order
+    for (int off = 32; off > 0; off >>= 1) {
+        const double oc = __shfl_xor(bc, off);
+        const int oi = __shfl_xor(bidx, off);
+        const uint32_t on = __shfl_xor(bnl, off);
+        if (oc < bc || (oc == bc && oi < bidx)) { bc = oc; bidx = oi; bnl = on; }
+    }
+    best_cost = bc;
+    if (bidx == 0x7FFFFFFF) {
+        best_axis = -1;
+        best_split = 0;
+        best_nl = 0;
+    } else {
+        best_axis = bidx / NB;
+        best_split = bidx % NB;
+        best_nl = bnl;
+    }
+}
+
+__device__ inline void write_sah_node(const SahTree& T, uint32_t node, const float lo[3], const float hi[3], int left,
+                                      int right, uint32_t first, uint32_t count)
+{
+    Box6 b;
+    for (int k = 0; k < 3; ++k) { b.lo[k] = lo[k]; b.hi[k] = hi[k]; }
+    T.box[node] = b;
+    T.child[node] = make_int2(left, right);
+    T.range[node] = make_int2((int)first, (int)count);
+}
+
+// ---- large ranges, level by level (chunk c of the level: elements chunk_begin[c] .. chunk_end[c] - 1 of task
+// chunk_task[c]) ----
+__global__ __launch_bounds__(256) void k_sah_reset(uint32_t* acc, uint32_t* bins, uint32_t n_tasks, int NB)
+{
+    const size_t per_task = 12 + (size_t)3 * NB * SAH_BIN_WORDS;
+    const size_t total = per_task * n_tasks;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const size_t t = i / per_task, w = i % per_task;
+        uint32_t v;
+        if (w < 12) {
+            v = (w % 6) < 3 ? O_POS_INF : O_NEG_INF;   // box lo, box hi, centroid lo, centroid hi
+            acc[t * 12 + w] = v;
+        } else {
+            const size_t q = w - 12, word = q % SAH_BIN_WORDS;
+            v = word < 3 ? O_POS_INF : (word < 6 ? O_NEG_INF : 0u);
+            bins[t * (per_task - 12) + q] = v;
+        }
+    }
+}
+
+__device__ inline void block_reduce_minmax(float v[12], float* sm /* [12][4] */)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1)
+        for (int k = 0; k < 12; ++k) {
+            const float o = __shfl_xor(v[k], off);
+            v[k] = (k % 6) < 3 ? fminf(v[k], o) : fmaxf(v[k], o);
+        }
+    if (lane == 0)
+        for (int k = 0; k < 12; ++k) sm[k * 4 + wave] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 12; ++k)
+            for (int w = 1; w < 4; ++w) v[k] = (k % 6) < 3 ? fminf(v[k], sm[k * 4 + w]) : fmaxf(v[k], sm[k * 4 + w]);
+}
+
+__global__ __launch_bounds__(256) void k_sah_bounds(const uint32_t* ids, const Box6* tri_box, const float4* cen,
+                                                    const uint32_t* chunk_task, const uint32_t* chunk_begin,
+                                                    const uint32_t* chunk_end, uint32_t* acc)
+{
+    __shared__ float sm[48];
+    const uint32_t c = blockIdx.x;
+    float v[12];
+    for (int k = 0; k < 12; ++k) v[k] = (k % 6) < 3 ? INFINITY : -INFINITY;
+    for (uint32_t i = chunk_begin[c] + threadIdx.x; i < chunk_end[c]; i += 256) {
+        const uint32_t t = ids[i];
+        const Box6 b = tri_box[t];
+        const float4 q = cen[t];
+        const float cc[3] = {q.x, q.y, q.z};
+        for (int k = 0; k < 3; ++k) {
+            v[k] = fminf(v[k], b.lo[k]); v[3 + k] = fmaxf(v[3 + k], b.hi[k]);
+            v[6 + k] = fminf(v[6 + k], cc[k]); v[9 + k] = fmaxf(v[9 + k], cc[k]);
+        }
+    }
+    block_reduce_minmax(v, sm);
+    if (threadIdx.x == 0) {
+        uint32_t* a = acc + 12 * (size_t)chunk_task[c];
+        for (int k = 0; k < 12; ++k) {
+            if ((k % 6) < 3) atomicMin(a + k, f2o(v[k]));
+            else atomicMax(a + k, f2o(v[k]));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sah_bins(const uint32_t* ids, const Box6* tri_box, const float4* cen,
+                                                  const uint32_t* chunk_task, const uint32_t* chunk_begin,
+                                                  const uint32_t* chunk_end, const uint32_t* acc, uint32_t* bins,
+                                                  int NB)
+{
+    __shared__ uint32_t lb[3 * SAH_NB_MAX * SAH_BIN_WORDS];
+    const uint32_t c = blockIdx.x, task = chunk_task[c];
+    const int words = 3 * NB * SAH_BIN_WORDS;
+    for (int i = threadIdx.x; i < words; i += 256) {
+        const int w = i % SAH_BIN_WORDS;
+        lb[i] = w < 3 ? O_POS_INF : (w < 6 ? O_NEG_INF : 0u);
+    }
+    const uint32_t* a = acc + 12 * (size_t)task;
+    float clo[3], chi[3];
+    for (int k = 0; k < 3; ++k) { clo[k] = o2f(a[6 + k]); chi[k] = o2f(a[9 + k]); }
+    __syncthreads();
+    for (uint32_t i = chunk_begin[c] + threadIdx.x; i < chunk_end[c]; i += 256) {
+        const uint32_t t = ids[i];
+        const Box6 b = tri_box[t];
+        const float4 q = cen[t];
+        const float cc[3] = {q.x, q.y, q.z};
+        for (int axis = 0; axis < 3; ++axis) {
+            const float ext = chi[axis] - clo[axis];
+            if (!(ext > 0.0f)) continue;
+            const int k = sah_bin(cc[axis], clo[axis], (double)NB / (double)ext, NB);
+            uint32_t* w = lb + ((size_t)axis * NB + k) * SAH_BIN_WORDS;
+            for (int j = 0; j < 3; ++j) { atomicMin(w + j, f2o(b.lo[j])); atomicMax(w + 3 + j, f2o(b.hi[j])); }
+            atomicAdd(w + 6, 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t* g = bins + (size_t)task * 3 * NB * SAH_BIN_WORDS;
+    for (int i = threadIdx.x; i < words; i += 256) {
+        const int w = i % SAH_BIN_WORDS;
+        if (lb[i - w + 6] == 0u || w == 7) continue;   // empty bin
+        if (w < 3) atomicMin(g + i, lb[i]);
+        else if (w < 6) atomicMax(g + i, lb[i]);
+        else atomicAdd(g + i, lb[i]);
+    }
+}
+
+// One wave per large range: split it (it holds more than SAH_SMALL >= max_leaf triangles, so it is never a
+// leaf), write its node, and queue its halves as large or small ranges.  decision[t] = (axis or -1, split bin,
+// left count).
+__global__ __launch_bounds__(64) void k_sah_split(const SahTask* tasks, const uint32_t* acc, const uint32_t* bins,
+                                                  int NB, SahTree T, SahTask* big_next, uint32_t* big_next_n,
+                                                  SahTask* small, uint32_t* small_n, int4* decision)
+{
+    const uint32_t t = blockIdx.x;
+    const SahTask task = tasks[t];
+    const uint32_t* a = acc + 12 * (size_t)t;
+    float blo[3], bhi[3], clo[3], chi[3];
+    for (int k = 0; k < 3; ++k) {
+        blo[k] = o2f(a[k]); bhi[k] = o2f(a[3 + k]); clo[k] = o2f(a[6 + k]); chi[k] = o2f(a[9 + k]);
+    }
+    int axis, split;
+    uint32_t nl;
+    double cost;
+    sah_decide(bins + (size_t)t * 3 * NB * SAH_BIN_WORDS, NB, clo, chi, axis, split, nl, cost);
+    if (axis < 0) nl = task.count / 2;
+    if (__lane_id() == 0) {
+        const uint32_t l = atomicAdd(T.node_ctr, 2u), r = l + 1;
+        write_sah_node(T, task.node, blo, bhi, (int)l, (int)r, task.first, task.count);
+        const SahTask kids[2] = {{l, task.first, nl, 0u}, {r, task.first + nl, task.count - nl, 0u}};
+        for (int s = 0; s < 2; ++s) {
+            if (kids[s].count > SAH_SMALL) big_next[atomicAdd(big_next_n, 1u)] = kids[s];
+            else small[atomicAdd(small_n, 1u)] = kids[s];
+        }
+        decision[t] = make_int4(axis, split, (int)nl, 0);
+    }
+}
+
+// stable partition of the large ranges: per chunk the left count, per task the chunks' offsets, then the scatter
+__device__ inline bool sah_goes_left(const float4* cen, uint32_t tri, int axis, int split, const uint32_t* a, int NB)
+{
+    const float lo = o2f(a[6 + axis]), hi = o2f(a[9 + axis]);
+    const float4 q = cen[tri];
+    const float c = axis == 0 ? q.x : (axis == 1 ? q.y : q.z);
+    return sah_bin(c, lo, (double)NB / (double)(hi - lo), NB) < split;
+}
+
+__global__ __launch_bounds__(256) void k_sah_count(const uint32_t* ids, const float4* cen, const SahTask* tasks,
+                                                   const uint32_t* chunk_task,
+                                                   const uint32_t* chunk_begin, const uint32_t* chunk_end,
+                                                   const uint32_t* acc, const int4* decision, int NB,
+                                                   uint32_t* chunk_left)
+{
+    __shared__ uint32_t s;
+    const uint32_t c = blockIdx.x, task = chunk_task[c];
+    const int4 d = decision[task];
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    uint32_t mine = 0;
+    for (uint32_t i = chunk_begin[c] + threadIdx.x; i < chunk_end[c]; i += 256) {
+        const bool left = d.x >= 0 ? sah_goes_left(cen, ids[i], d.x, d.y, acc + 12 * (size_t)task, NB)
+                                   : (i - tasks[task].first) < (uint32_t)d.z;   // halved range: order kept
+        mine += left ? 1u : 0u;
+    }
+    atomicAdd(&s, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) chunk_left[c] = s;
+}
+
+// one thread per large range: exclusive offsets of its chunks' left counts (its chunks are consecutive)
+__global__ __launch_bounds__(256) void k_sah_offsets(const uint32_t* task_chunk0, const uint32_t* task_nchunks,
+                                                     uint32_t n_tasks, const uint32_t* chunk_left, uint32_t* chunk_off)
+{
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tasks) return;
+    uint32_t acc = 0;
+    for (uint32_t c = task_chunk0[t]; c < task_chunk0[t] + task_nchunks[t]; ++c) {
+        chunk_off[c] = acc;
+        acc += chunk_left[c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sah_scatter(const uint32_t* ids, const float4* cen, const SahTask* tasks,
+                                                     const uint32_t* chunk_task, const uint32_t* chunk_begin,
+                                                     const uint32_t* chunk_end, const uint32_t* acc,
+                                                     const int4* decision, int NB, const uint32_t* chunk_off,
+                                                     uint32_t* ids_out)
+{
+    __shared__ uint32_t s_wave[4];
+    const uint32_t c = blockIdx.x, task = chunk_task[c];
+    const int4 d = decision[task];
+    const SahTask tk = tasks[task];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // left slots: first + chunk_off + rank; right slots: first + nl + (elements before this chunk that go right)
+    uint32_t left_base = tk.first + chunk_off[c];
+    uint32_t right_base = tk.first + (uint32_t)d.z + (chunk_begin[c] - tk.first - chunk_off[c]);
+    for (uint32_t i0 = chunk_begin[c]; i0 < chunk_end[c]; i0 += 256) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool valid = i < chunk_end[c];
+        const uint32_t tri = valid ? ids[i] : 0u;
+        bool left;
+        if (d.x >= 0) left = valid && sah_goes_left(cen, tri, d.x, d.y, acc + 12 * (size_t)task, NB);
+        else left = valid && (i - tk.first) < (uint32_t)d.z;   // halved range: order kept
+        const uint64_t m = __ballot(left);
+        const uint32_t below = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (uint32_t w = 0; w < 4; ++w) {
+            if (w < wave) before += s_wave[w];
+            total += s_wave[w];
+        }
+        const uint32_t rank_l = before + below;
+        const uint32_t n_valid = min(256u, chunk_end[c] - i0);
+        const uint32_t dst = left ? left_base + rank_l : right_base + (threadIdx.x - rank_l);
+        if (valid && dst < tk.first + tk.count) ids_out[dst] = tri;   // always in range (same decisions as the bins)
+        left_base += total;
+        right_base += n_valid - total;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sah_copy(const uint32_t* src, const uint32_t* chunk_begin,
+                                                  const uint32_t* chunk_end, uint32_t* dst)
+{
+    const uint32_t c = blockIdx.x;
+    for (uint32_t i = chunk_begin[c] + threadIdx.x; i < chunk_end[c]; i += 256) dst[i] = src[i];
+}
+
+// ---- small ranges: one wave builds the whole subtree (depth first, its pending ranges in stack[first ..]) ----
+__global__ __launch_bounds__(256) void k_sah_small(const SahTask* small, uint32_t n_small, uint32_t* ids,
+                                                   uint32_t* tmp, const Box6* tri_box, const float4* cen, int NB,
+                                                   uint32_t max_leaf, double node_cost, SahTree T, uint4* stack)
+{
+    __shared__ uint32_t lbins[4][3 * SAH_NB_MAX * SAH_BIN_WORDS];
+    const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t ti = blockIdx.x * 4 + wave;
+    if (ti >= n_small) return;   // whole waves only: no workgroup barrier below
+    uint32_t* lb = lbins[wave];
+    const SahTask root = small[ti];
+    uint4* stk = stack + root.first;
+    uint32_t sp = 0;
+    uint32_t node = root.node, f = root.first, n = root.count;
+    const int words = 3 * NB * SAH_BIN_WORDS;
+    for (;;) {
+        // bounds of the range
+        float v[12];
+        for (int k = 0; k < 12; ++k) v[k] = (k % 6) < 3 ? INFINITY : -INFINITY;
+        for (uint32_t i = f + lane; i < f + n; i += 64) {
+            const uint32_t t = ids[i];
+            const Box6 b = tri_box[t];
+            const float4 q = cen[t];
+            const float cc[3] = {q.x, q.y, q.z};
+            for (int k = 0; k < 3; ++k) {
+                v[k] = fminf(v[k], b.lo[k]); v[3 + k] = fmaxf(v[3 + k], b.hi[k]);
+                v[6 + k] = fminf(v[6 + k], cc[k]); v[9 + k] = fmaxf(v[9 + k], cc[k]);
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1)
+            for (int k = 0; k < 12; ++k) {
+                const float o = __shfl_xor(v[k], off);
+                v[k] = (k % 6) < 3 ? fminf(v[k], o) : fmaxf(v[k], o);
+            }
+        const float blo[3] = {v[0], v[1], v[2]}, bhi[3] = {v[3], v[4], v[5]};
+        const float clo[3] = {v[6], v[7], v[8]}, chi[3] = {v[9], v[10], v[11]};
+        bool leaf = n == 1;
+        int axis = -1, split = 0;
+        uint32_t nl = 0;
+        if (!leaf) {
+            for (int i = lane; i < words; i += 64) {
+                const int w = i % SAH_BIN_WORDS;
+                lb[i] = w < 3 ? O_POS_INF : (w < 6 ? O_NEG_INF : 0u);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (uint32_t i = f + lane; i < f + n; i += 64) {
+                const uint32_t t = ids[i];
+                const Box6 b = tri_box[t];
+                const float4 q = cen[t];
+                const float cc[3] = {q.x, q.y, q.z};
+                for (int ax = 0; ax < 3; ++ax) {
+                    const float ext = chi[ax] - clo[ax];
+                    if (!(ext > 0.0f)) continue;
+                    const int k = sah_bin(cc[ax], clo[ax], (double)NB / (double)ext, NB);
+                    uint32_t* w = lb + ((size_t)ax * NB + k) * SAH_BIN_WORDS;
+                    for (int j = 0; j < 3; ++j) { atomicMin(w + j, f2o(b.lo[j])); atomicMax(w + 3 + j, f2o(b.hi[j])); }
+                    atomicAdd(w + 6, 1u);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            double best;
+            sah_decide(lb, NB, clo, chi, axis, split, nl, best);
+            const double parea = sah_area(blo, bhi);
+            const double split_cost = parea > 0.0 ? node_cost + best / parea : (double)n;
+            leaf = n <= max_leaf && (axis < 0 || (double)n <= split_cost);
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (leaf) {
+            if (lane == 0) write_sah_node(T, node, blo, bhi, -1, -1, f, n);
+            if (sp == 0) break;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const uint4 e = stk[--sp];
+            node = e.x; f = e.y; n = e.z;
+            continue;
+        }
+        if (axis < 0) {
+            nl = n / 2;   // coinciding centroids: halve the range, order kept
+        } else {
+            // stable partition into tmp, then back
+            const float lo = clo[axis];
+            const double scale = (double)NB / (double)(chi[axis] - clo[axis]);
+            uint32_t lpos = f, rpos = f + nl;
+            for (uint32_t i0 = f; i0 < f + n; i0 += 64) {
+                const uint32_t i = i0 + lane;
+                const bool valid = i < f + n;
+                const uint32_t t = valid ? ids[i] : 0u;
+                float c = 0.0f;
+                if (valid) {
+                    const float4 q = cen[t];
+                    c = axis == 0 ? q.x : (axis == 1 ? q.y : q.z);
+                }
+                const bool left = valid && sah_bin(c, lo, scale, NB) < split;
+                const uint64_t m = __ballot(left), mv = __ballot(valid);
+                const uint64_t below = (1ull << lane) - 1ull;
+                const uint32_t rl = (uint32_t)__popcll(m & below), rr = (uint32_t)__popcll(mv & ~m & below);
+                const uint32_t dst = left ? lpos + rl : rpos + rr;
+                if (valid && dst < f + n) tmp[dst] = t;   // always in range: the bins counted the same decisions
+                lpos += (uint32_t)__popcll(m);
+                rpos += (uint32_t)__popcll(mv & ~m);
+            }
+            // the lanes exchange ids through global memory: order the stores before the other lanes' loads
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            for (uint32_t i = f + lane; i < f + n; i += 64) ids[i] = tmp[i];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        uint32_t l = 0;
+        if (lane == 0) l = atomicAdd(T.node_ctr, 2u);
+        l = (uint32_t)__builtin_amdgcn_readfirstlane((int)l);
+        if (lane == 0) write_sah_node(T, node, blo, bhi, (int)l, (int)(l + 1), f, n);
+        stk[sp] = make_uint4(l + 1, f + nl, n - nl, 0u);   // every lane writes (and later reads) the same entry
+        ++sp;
+        node = l;
+        n = nl;
+    }
+}
+
+}  // namespace
+
+// Binned-SAH build of n triangles on the device (see above); outputs as rc_build_bvh_device.
+hipError_t rc_build_bvh_device_sah(const float* d_pos, const uint32_t* d_idx, uint32_t n, uint32_t bins,
+                                   uint32_t max_leaf, float node_cost, Node4** d_nodes_out, uint32_t* n_nodes_out,
+                                   uint32_t* d_order, std::vector<uint32_t>& level_start, hipStream_t st)
+{
+    *d_nodes_out = nullptr;
+    *n_nodes_out = 0;
+    level_start.clear();
+    if (n == 0 || n > (1u << 28) || max_leaf < 1 || max_leaf > 4 || bins < 2 || bins > (uint32_t)SAH_NB_MAX)
+        return hipErrorInvalidValue;
+    const int NB = (int)bins;
+    const size_t n2 = 2 * (size_t)n;                 // binary nodes
+    const uint32_t max_big = n / SAH_SMALL + 2;      // large ranges of one level are disjoint
+    const uint32_t max_chunks = n / SAH_CHUNK + max_big + 2;
+    const size_t cap = (size_t)n + 2;                 // 4-wide nodes: at most one per internal binary node, plus root
+    DevBuf<Box6> tri_box, box;
+    DevBuf<float4> cen;
+    DevBuf<int2> child, range;
+    DevBuf<uint32_t> tmp, ctr, acc, binbuf, chunk_task, chunk_begin, chunk_end, chunk_left, chunk_off, task_chunk0,
+        task_nchunks, par_a, par_b, overflow;
+    DevBuf<SahTask> big_a, big_b, small;
+    DevBuf<int4> decision;
+    DevBuf<uint4> stack;
+    DevBuf<int> lvl_a, lvl_b, nint, offs;
+    DevBuf<Node4> nodes;
+    DevBuf<uint8_t> temp;
+    BH(tri_box.alloc(n));
+    BH(cen.alloc(n));
+    BH(box.alloc(n2));
+    BH(child.alloc(n2));
+    BH(range.alloc(n2));
+    BH(tmp.alloc(n));
+    BH(ctr.alloc(4));
+    BH(acc.alloc((size_t)max_big * 12));
+    BH(binbuf.alloc((size_t)max_big * 3 * NB * SAH_BIN_WORDS));
+    BH(chunk_task.alloc(max_chunks));
+    BH(chunk_begin.alloc(max_chunks));
+    BH(chunk_end.alloc(max_chunks));
+    BH(chunk_left.alloc(max_chunks));
+    BH(chunk_off.alloc(max_chunks));
+    BH(task_chunk0.alloc(max_big));
+    BH(task_nchunks.alloc(max_big));
+    BH(big_a.alloc(max_big));
+    BH(big_b.alloc(max_big));
+    BH(small.alloc(n));
+    BH(decision.alloc(max_big));
+    BH(stack.alloc(n));
+    BH(nodes.alloc(cap));
+    BH(lvl_a.alloc(cap));
+    BH(lvl_b.alloc(cap));
+    BH(par_a.alloc(cap));
+    BH(par_b.alloc(cap));
+    BH(nint.alloc(cap));
+    BH(offs.alloc(cap));
+    BH(overflow.alloc(1));
+    size_t scan_bytes = 0;
+    BH(rocprim::exclusive_scan(nullptr, scan_bytes, nint.p, offs.p, 0, cap, rocprim::plus<int>(), st));
+    BH(temp.alloc(scan_bytes));
+
+    hipLaunchKernelGGL(k_tri_boxes, dim3(nb(n, 256)), dim3(256), 0, st, d_pos, d_idx, n, tri_box.p, cen.p);
+    hipLaunchKernelGGL(k_iota, dim3(nb(n, 256)), dim3(256), 0, st, d_order, n);
+    // counters: [0] binary nodes allocated (the root is node 0), [1] large ranges of the next level, [2] small ranges
+    const uint32_t ctr0[4] = {1u, 0u, 0u, 0u};
+    BH(hipMemcpyAsync(ctr.p, ctr0, sizeof(ctr0), hipMemcpyHostToDevice, st));
+    const SahTree T{child.p, range.p, box.p, ctr.p};
+    std::vector<SahTask> big_h;
+    if (n > SAH_SMALL) {
+        big_h.push_back({0u, 0u, n, 0u});
+    } else {
+        const SahTask root{0u, 0u, n, 0u};
+        BH(hipMemcpyAsync(small.p, &root, sizeof(root), hipMemcpyHostToDevice, st));
+        const uint32_t one = 1u;
+        BH(hipMemcpyAsync(ctr.p + 2, &one, sizeof(one), hipMemcpyHostToDevice, st));
+    }
+    if (!big_h.empty()) BH(hipMemcpyAsync(big_a.p, big_h.data(), sizeof(SahTask), hipMemcpyHostToDevice, st));
+    std::vector<uint32_t> ct, cb, ce, t0, tn;
+    while (!big_h.empty()) {
+        const uint32_t nt = (uint32_t)big_h.size();
+        ct.clear(); cb.clear(); ce.clear(); t0.clear(); tn.clear();
+        for (uint32_t t = 0; t < nt; ++t) {
+            t0.push_back((uint32_t)ct.size());
+            for (uint32_t b = big_h[t].first; b < big_h[t].first + big_h[t].count; b += SAH_CHUNK) {
+                ct.push_back(t);
+                cb.push_back(b);
+                ce.push_back(std::min(b + SAH_CHUNK, big_h[t].first + big_h[t].count));
+            }
+            tn.push_back((uint32_t)ct.size() - t0.back());
+        }
+        const uint32_t nc = (uint32_t)ct.size();
+        if (nc > max_chunks || nt > max_big) return hipErrorUnknown;
+        BH(hipMemcpyAsync(chunk_task.p, ct.data(), nc * 4, hipMemcpyHostToDevice, st));
+        BH(hipMemcpyAsync(chunk_begin.p, cb.data(), nc * 4, hipMemcpyHostToDevice, st));
+        BH(hipMemcpyAsync(chunk_end.p, ce.data(), nc * 4, hipMemcpyHostToDevice, st));
+        BH(hipMemcpyAsync(task_chunk0.p, t0.data(), nt * 4, hipMemcpyHostToDevice, st));
+        BH(hipMemcpyAsync(task_nchunks.p, tn.data(), nt * 4, hipMemcpyHostToDevice, st));
+        const uint32_t zero = 0u;
+        BH(hipMemcpyAsync(ctr.p + 1, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_sah_reset, dim3(std::min<unsigned>(1024, nb((size_t)nt * (12 + 3 * NB * SAH_BIN_WORDS), 256))),
+                           dim3(256), 0, st, acc.p, binbuf.p, nt, NB);
+        hipLaunchKernelGGL(k_sah_bounds, dim3(nc), dim3(256), 0, st, d_order, tri_box.p, cen.p, chunk_task.p,
+                           chunk_begin.p, chunk_end.p, acc.p);
+        hipLaunchKernelGGL(k_sah_bins, dim3(nc), dim3(256), 0, st, d_order, tri_box.p, cen.p, chunk_task.p,
+                           chunk_begin.p, chunk_end.p, acc.p, binbuf.p, NB);
+        hipLaunchKernelGGL(k_sah_split, dim3(nt), dim3(64), 0, st, big_a.p, acc.p, binbuf.p, NB, T, big_b.p, ctr.p + 1,
+                           small.p, ctr.p + 2, decision.p);
+        hipLaunchKernelGGL(k_sah_count, dim3(nc), dim3(256), 0, st, d_order, cen.p, big_a.p, chunk_task.p,
+                           chunk_begin.p, chunk_end.p, acc.p, decision.p, NB, chunk_left.p);
+        hipLaunchKernelGGL(k_sah_offsets, dim3(nb(nt, 256)), dim3(256), 0, st, task_chunk0.p, task_nchunks.p, nt,
+                           chunk_left.p, chunk_off.p);
+        hipLaunchKernelGGL(k_sah_scatter, dim3(nc), dim3(256), 0, st, d_order, cen.p, big_a.p, chunk_task.p,
+                           chunk_begin.p, chunk_end.p, acc.p, decision.p, NB, chunk_off.p, tmp.p);
+        hipLaunchKernelGGL(k_sah_copy, dim3(nc), dim3(256), 0, st, tmp.p, chunk_begin.p, chunk_end.p, d_order);
+        BH(hipGetLastError());
+        uint32_t next = 0;
+        BH(hipMemcpyAsync(&next, ctr.p + 1, sizeof(next), hipMemcpyDeviceToHost, st));
+        BH(hipStreamSynchronize(st));
+        if (next > max_big) return hipErrorUnknown;
+        big_h.resize(next);
+        if (next) BH(hipMemcpyAsync(big_h.data(), big_b.p, next * sizeof(SahTask), hipMemcpyDeviceToHost, st));
+        BH(hipStreamSynchronize(st));
+        std::swap(big_a.p, big_b.p);
+        if (next) BH(hipMemcpyAsync(big_a.p, big_h.data(), next * sizeof(SahTask), hipMemcpyHostToDevice, st));
+    }
+    uint32_t n_small = 0;
+    BH(hipMemcpyAsync(&n_small, ctr.p + 2, sizeof(n_small), hipMemcpyDeviceToHost, st));
+    BH(hipStreamSynchronize(st));
+    if (n_small > n) return hipErrorUnknown;
+    if (n_small)
+        hipLaunchKernelGGL(k_sah_small, dim3(nb(n_small, 4)), dim3(256), 0, st, small.p, n_small, d_order, tmp.p,
+                           tri_box.p, cen.p, NB, max_leaf, (double)node_cost, T, stack.p);
+    BH(hipGetLastError());
+
+    // 4-wide collapse from the root (binary node 0), level by level
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, lvl_a.p, 0, 1u);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int*>(par_a.p), -1, 1u);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int*>(overflow.p), 0, 1u);
+    TreeView TV{(int)n, (int)max_leaf, child.p, range.p, box.p, nullptr};
+    TV.explicit_leaves = 1;
+    uint32_t m = 1, base = 0, depth = 0;
+    while (m > 0) {
+        if ((size_t)base + m > cap) return hipErrorUnknown;
+        hipLaunchKernelGGL(k_collapse_count, dim3(nb(m, 256)), dim3(256), 0, st, TV, lvl_a.p, (int)m, nint.p);
+        size_t sb = scan_bytes;
+        BH(rocprim::exclusive_scan(temp.p, sb, nint.p, offs.p, 0, (size_t)m, rocprim::plus<int>(), st));
+        hipLaunchKernelGGL(k_collapse_write, dim3(nb(m, 256)), dim3(256), 0, st, TV, lvl_a.p, par_a.p, (int)m, offs.p,
+                           base, base + m, depth, (uint32_t)cap, nodes.p, lvl_b.p, par_b.p, overflow.p);
+        BH(hipGetLastError());
+        int tail[2] = {0, 0};
+        uint32_t ovf = 0;
+        BH(hipMemcpyAsync(&tail[0], offs.p + (m - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+        BH(hipMemcpyAsync(&tail[1], nint.p + (m - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+        BH(hipMemcpyAsync(&ovf, overflow.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        BH(hipStreamSynchronize(st));
+        if (ovf) return hipErrorUnknown;
+        level_start.push_back(base);
+        base += m;
+        ++depth;
+        m = (uint32_t)(tail[0] + tail[1]);
+        std::swap(lvl_a.p, lvl_b.p);
+        std::swap(par_a.p, par_b.p);
+    }
+    level_start.push_back(base);
+    const uint32_t total = level_start.back();
+    Node4* out = nullptr;
+    BH(hipMalloc(reinterpret_cast<void**>(&out), (size_t)total * sizeof(Node4)));
+    hipError_t e = hipMemcpyAsync(out, nodes.p, (size_t)total * sizeof(Node4), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(out);
+        return e;
+    }
+    *d_nodes_out = out;
+    *n_nodes_out = total;
+    return hipSuccess;
+}
+
 // ---------------------------------------------------------------- top level --------
 hipError_t rc_tlas_alloc(TlasWork& w, uint32_t n)
 {
@@ -763,9 +1485,14 @@ hipError_t rc_tlas_build(TlasWork& w, const float* o2w, Node4* nodes, uint32_t t
                        (float*)w.bounds);
     hipLaunchKernelGGL(k_morton, dim3(nb(n, 256)), dim3(256), 0, st, cen, n, (const float*)w.bounds,
                        (uint64_t*)w.keys, (uint32_t*)w.vals);
-    size_t bytes = w.temp_bytes;
-    BH(rocprim::radix_sort_pairs(w.temp, bytes, (uint64_t*)w.keys, (uint64_t*)w.keys_s, (uint32_t*)w.vals,
-                                 (uint32_t*)w.order, n, 0, 63, st));
+    if (n <= SORT_BLOCK_MAX) {
+        hipLaunchKernelGGL(k_sort_block, dim3(1), dim3(SORT_THREADS), 0, st, (const uint64_t*)w.keys,
+                           (const uint32_t*)w.vals, n, (uint64_t*)w.keys_s, (uint32_t*)w.order);
+    } else {
+        size_t bytes = w.temp_bytes;
+        BH(rocprim::radix_sort_pairs(w.temp, bytes, (uint64_t*)w.keys, (uint64_t*)w.keys_s, (uint32_t*)w.vals,
+                                     (uint32_t*)w.order, n, 0, 63, st));
+    }
     hipLaunchKernelGGL(k_fill_i32, dim3(nb(2 * (size_t)n, 256)), dim3(256), 0, st, (int*)w.parent, -1, 2 * n);
     hipLaunchKernelGGL(k_fill_i32, dim3(nb(n, 256)), dim3(256), 0, st, (int*)w.flags, 0, n);
     const int N = (int)n;

@@ -75,10 +75,14 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, uint32_t n)
 // vertex normals (when present) are rotated the same way, without the translation
 __global__ __launch_bounds__(256) void k_transform(const float* rest, float* pos, const float* nrm_rest, float* nrm,
                                                    const uint32_t* body_vrange, const float* xf,
-                                                   const uint32_t* body_ids)
+                                                   const uint32_t* body_ids, uint32_t n_bodies, uint32_t* bad_value)
 {
     uint32_t b = blockIdx.y;
     uint32_t body = body_ids[b];
+    if (body >= n_bodies) {   // not a body of the scene: nothing moves, the invalid-value flag is set
+        if (blockIdx.x == 0 && threadIdx.x == 0) *bad_value = 1u;
+        return;
+    }
     uint32_t first = body_vrange[2 * (size_t)body], count = body_vrange[2 * (size_t)body + 1];
     const float* M = xf + 12 * (size_t)b;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
@@ -106,11 +110,123 @@ __global__ __launch_bounds__(256) void k_transform(const float* rest, float* pos
 }
 
 // The current rigid map of each moved body (read by the top level of two-level structures).
-__global__ __launch_bounds__(256) void k_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, float* o2w)
+__global__ __launch_bounds__(256) void k_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n,
+                                                    uint32_t scene_bodies, float* o2w)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= 12 * n) return;
-    o2w[12 * (size_t)body_ids[q / 12] + q % 12] = xf[q];
+    const uint32_t body = body_ids[q / 12];
+    if (body < scene_bodies) o2w[12 * (size_t)body + q % 12] = xf[q];
+}
+
+// Dirty-node refit of a flat BVH under rigid motion.  tri_node[t] = the node whose leaf child holds
+// triangle t; rc_scene_set_transforms marks (dirty = 1) the nodes holding triangles of the moved bodies; the
+// refit then recomputes, level by level from the deepest, only the dirty nodes (exact FP32 min/max, and the
+// packed records of their leaf triangles), each marking its parent.  Untouched nodes keep boxes that are
+// already exact for their unmoved triangles, so the result equals a full refit bit for bit.
+__global__ __launch_bounds__(256) void k_tri_nodes(const Node4* nodes, uint32_t n_nodes, const uint32_t* order,
+                                                   uint32_t* tri_node)
+{
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t w = nodes[n].child[c];
+        if (!rc_is_leaf(w)) continue;
+        for (uint32_t i = 0; i < rc_leaf_count(w); ++i) tri_node[order[rc_leaf_first(w) + i]] = n;
+    }
+}
+
+// One block per moved body: its triangles (body_tris[tri_off[b] .. tri_off[b + 1])) mark their nodes.
+__global__ __launch_bounds__(256) void k_mark_dirty(const uint32_t* body_ids, uint32_t n_bodies, const uint32_t* tri_off,
+                                                    const uint32_t* body_tris, const uint32_t* tri_node,
+                                                    uint32_t* dirty, uint32_t n_nodes)
+{
+    const uint32_t b = body_ids[blockIdx.x];
+    if (b >= n_bodies) return;   // reported by k_transform
+    for (uint32_t i = tri_off[b] + threadIdx.x; i < tri_off[b + 1]; i += blockDim.x) {
+        const uint32_t n = tri_node[body_tris[i]];
+        if (n < n_nodes) dirty[n] = 1u;
+    }
+}
+
+// Recompute node n's four child boxes (leaf children from their triangles' current vertices, whose packed
+// records are rewritten on the way; internal children from their own, already refit, boxes), clear its flag
+// and mark its parent.
+__device__ inline void refit_node(Node4* nodes, uint32_t n, const float* pos, const uint32_t* idx,
+                                  const uint32_t* order, float4* tris, uint32_t raw, uint32_t* dirty, uint32_t n_nodes)
+{
+    Node4* nd = nodes + n;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t w = nd->child[c];
+        if (w == RC_EMPTY_CHILD) continue;
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (rc_is_leaf(w)) {
+            const uint32_t f = rc_leaf_first(w), cnt = rc_leaf_count(w);
+            for (uint32_t i = 0; i < cnt; ++i) {
+                const uint32_t t = order[f + i];
+                const uint32_t* ix = idx + 3 * (size_t)t;
+                const float* a = pos + 3 * (size_t)ix[0];
+                const float* b = pos + 3 * (size_t)ix[1];
+                const float* cc = pos + 3 * (size_t)ix[2];
+                for (int k = 0; k < 3; ++k) {
+                    lo[k] = fminf(fminf(fminf(lo[k], a[k]), b[k]), cc[k]);
+                    hi[k] = fmaxf(fmaxf(fmaxf(hi[k], a[k]), b[k]), cc[k]);
+                }
+                float4* tp = tris + 3 * (size_t)(f + i);
+                tp[0] = make_float4(a[0], a[1], a[2], __uint_as_float(t));
+                if (raw) {
+                    tp[1] = make_float4(b[0], b[1], b[2], 0.0f);
+                    tp[2] = make_float4(cc[0], cc[1], cc[2], 0.0f);
+                } else {
+                    tp[1] = make_float4(b[0] - a[0], b[1] - a[1], b[2] - a[2], 0.0f);
+                    tp[2] = make_float4(cc[0] - a[0], cc[1] - a[1], cc[2] - a[2], 0.0f);
+                }
+            }
+        } else {
+            const Node4* ch = nodes + w;
+            for (int k = 0; k < 4; ++k) {
+                lo[0] = fminf(lo[0], ch->lo_x[k]); hi[0] = fmaxf(hi[0], ch->hi_x[k]);
+                lo[1] = fminf(lo[1], ch->lo_y[k]); hi[1] = fmaxf(hi[1], ch->hi_y[k]);
+                lo[2] = fminf(lo[2], ch->lo_z[k]); hi[2] = fmaxf(hi[2], ch->hi_z[k]);
+            }
+        }
+        nd->lo_x[c] = lo[0]; nd->hi_x[c] = hi[0];
+        nd->lo_y[c] = lo[1]; nd->hi_y[c] = hi[1];
+        nd->lo_z[c] = lo[2]; nd->hi_z[c] = hi[2];
+    }
+    dirty[n] = 0u;
+    const uint32_t p = nd->parent;
+    if (p < n_nodes) dirty[p] = 1u;   // the root's parent is 0xFFFFFFFF
+}
+
+// The dirty nodes of one level (nodes first .. first + count - 1), one thread per node.
+__global__ __launch_bounds__(256) void k_refit_dirty(Node4* nodes, const float* pos, const uint32_t* idx,
+                                                     const uint32_t* order, float4* tris, uint32_t raw,
+                                                     uint32_t* dirty, uint32_t first, uint32_t count, uint32_t n_nodes)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count || dirty[first + q] == 0u) return;
+    refit_node(nodes, first + q, pos, idx, order, tris, raw, dirty, n_nodes);
+}
+
+// The top levels (nodes 0 .. start[levels] - 1, a few thousand) in one workgroup, deepest level first, a
+// barrier between levels.
+struct TopLevels {
+    uint32_t start[RC_REFIT_TOP_MAX + 1];
+    int levels;
+};
+
+__global__ __launch_bounds__(1024) void k_refit_top(Node4* nodes, const float* pos, const uint32_t* idx,
+                                                    const uint32_t* order, float4* tris, uint32_t raw,
+                                                    uint32_t* dirty, TopLevels L, uint32_t n_nodes)
+{
+    for (int lv = L.levels - 1; lv >= 0; --lv) {
+        for (uint32_t n = L.start[lv] + threadIdx.x; n < L.start[lv + 1]; n += blockDim.x)
+            if (dirty[n] != 0u) refit_node(nodes, n, pos, idx, order, tris, raw, dirty, n_nodes);
+        __syncthreads();
+    }
 }
 
 // One thread per node of one BVH level: child boxes from the triangles of leaf children and
@@ -235,18 +351,19 @@ void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st)
 
 void rc_launch_transform(const float* rest, float* pos, const float* nrm_rest, float* nrm,
                          const uint32_t* body_vrange, const float* xf, const uint32_t* body_ids, uint32_t n_bodies,
-                         uint32_t max_count, hipStream_t st)
+                         uint32_t max_count, uint32_t scene_bodies, uint32_t* bad_value, hipStream_t st)
 {
     if (n_bodies == 0 || max_count == 0) return;
     unsigned gx = std::min(blocks(max_count, 256), 64u);
     hipLaunchKernelGGL(k_transform, dim3(gx, n_bodies), dim3(256), 0, st, rest, pos, nrm_rest, nrm, body_vrange, xf,
-                       body_ids);
+                       body_ids, scene_bodies, bad_value);
 }
 
-void rc_launch_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, float* o2w, hipStream_t st)
+void rc_launch_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, uint32_t scene_bodies, float* o2w,
+                          hipStream_t st)
 {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_record_o2w, dim3(blocks(12 * n, 256)), dim3(256), 0, st, xf, body_ids, n, o2w);
+    hipLaunchKernelGGL(k_record_o2w, dim3(blocks(12 * n, 256)), dim3(256), 0, st, xf, body_ids, n, scene_bodies, o2w);
 }
 
 void rc_launch_refit_level(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order,
@@ -254,4 +371,43 @@ void rc_launch_refit_level(Node4* nodes, const float* pos, const uint32_t* idx, 
 {
     if (count == 0) return;
     hipLaunchKernelGGL(k_refit, dim3(blocks(count, 256)), dim3(256), 0, st, nodes, pos, idx, order, first, count);
+}
+
+void rc_launch_tri_nodes(const Node4* nodes, uint32_t n_nodes, const uint32_t* order, uint32_t* tri_node,
+                         hipStream_t st)
+{
+    if (n_nodes == 0) return;
+    hipLaunchKernelGGL(k_tri_nodes, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, nodes, n_nodes, order, tri_node);
+}
+
+void rc_launch_mark_dirty(const uint32_t* body_ids, uint32_t n, uint32_t n_bodies, const uint32_t* tri_off,
+                          const uint32_t* body_tris, const uint32_t* tri_node, uint32_t* dirty, uint32_t n_nodes,
+                          hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_mark_dirty, dim3(n), dim3(256), 0, st, body_ids, n_bodies, tri_off, body_tris, tri_node, dirty,
+                       n_nodes);
+}
+
+void rc_launch_refit_dirty(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order, float4* tris,
+                           bool raw, uint32_t* dirty, const std::vector<uint32_t>& level_start, hipStream_t st)
+{
+    const int depth = (int)level_start.size() - 1;
+    const uint32_t n_nodes = level_start[depth];
+    // top levels: as many of the shallowest levels as hold at most RC_REFIT_TOP_NODES nodes together
+    int top = 0;
+    while (top < depth && top < RC_REFIT_TOP_MAX && level_start[top + 1] <= RC_REFIT_TOP_NODES) ++top;
+    for (int lv = depth - 1; lv >= top; --lv) {
+        const uint32_t first = level_start[lv], count = level_start[lv + 1] - level_start[lv];
+        if (count == 0) continue;
+        hipLaunchKernelGGL(k_refit_dirty, dim3(blocks(count, 256)), dim3(256), 0, st, nodes, pos, idx, order, tris,
+                           raw ? 1u : 0u, dirty, first, count, n_nodes);
+    }
+    if (top > 0) {
+        TopLevels L;
+        for (int i = 0; i <= top; ++i) L.start[i] = level_start[i];
+        L.levels = top;
+        hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(1024), 0, st, nodes, pos, idx, order, tris, raw ? 1u : 0u,
+                           dirty, L, n_nodes);
+    }
 }

@@ -48,6 +48,8 @@ void free_bvh(rc_scene* s)
     dev_free(s->d_order);
     dev_free(s->d_tris);
     dev_free(s->d_inst);
+    dev_free(s->d_tri_node);
+    dev_free(s->d_dirty);
     rc_tlas_free(s->tlas);
     s->two_level = false;
     s->blas_nodes = s->blas_depth = 0;
@@ -224,6 +226,63 @@ int rc_get_last_error(rc_ctx* c)
     return st;
 }
 
+// Per body, the triangles with a vertex in the body's vertex range (CSR), for the dirty-node refit.  Left
+// empty (full refits) when vertex ranges overlap, so that every moved vertex maps to one body.
+static int upload_body_tris(rc_ctx* c, rc_scene* s)
+{
+    const uint32_t NONE = 0xFFFFFFFFu;
+    std::vector<uint32_t> vb(s->nv, NONE);
+    for (uint32_t b = 0; b < s->nb; ++b) {
+        const uint32_t f = s->body_vr[2 * (size_t)b], n = s->body_vr[2 * (size_t)b + 1];
+        for (uint32_t v = f; v < f + n; ++v) {
+            if (vb[v] != NONE) return RC_OK;
+            vb[v] = b;
+        }
+    }
+    std::vector<uint32_t> off(s->nb + 1, 0);
+    auto bodies_of = [&](uint32_t t, uint32_t out[3]) {
+        int k = 0;
+        for (int j = 0; j < 3; ++j) {
+            const uint32_t b = vb[s->idx[3 * (size_t)t + j]];
+            bool seen = b == NONE;
+            for (int q = 0; q < k; ++q) seen = seen || out[q] == b;
+            if (!seen) out[k++] = b;
+        }
+        return k;
+    };
+    uint32_t bs[3];
+    for (uint32_t t = 0; t < s->nt; ++t)
+        for (int q = 0, k = bodies_of(t, bs); q < k; ++q) ++off[bs[q] + 1];
+    for (uint32_t b = 0; b < s->nb; ++b) off[b + 1] += off[b];
+    std::vector<uint32_t> tris(off[s->nb]), fill(off.begin(), off.end() - 1);
+    for (uint32_t t = 0; t < s->nt; ++t)
+        for (int q = 0, k = bodies_of(t, bs); q < k; ++q) tris[fill[bs[q]]++] = t;
+    int st = dev_alloc(&s->d_body_tri_off, off.size());
+    if (st == RC_OK) st = dev_alloc(&s->d_body_tris, tris.size());
+    if (st == RC_OK && (hipMemcpy(s->d_body_tri_off, off.data(), off.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                        (!tris.empty() && hipMemcpy(s->d_body_tris, tris.data(), tris.size() * 4,
+                                                    hipMemcpyHostToDevice) != hipSuccess)))
+        st = RC_ERR_HIP;
+    if (st != RC_OK) {
+        dev_free(s->d_body_tri_off);
+        dev_free(s->d_body_tris);
+    }
+    return st;
+}
+
+// After a flat build of a scene with bodies: the node of each triangle's leaf, and clear dirty flags.
+static int prepare_dirty_refit(rc_ctx* c, rc_scene* s, uint32_t n_nodes)
+{
+    if (!s->d_body_tri_off) return RC_OK;
+    int st = dev_alloc(&s->d_tri_node, s->nt);
+    if (st == RC_OK) st = dev_alloc(&s->d_dirty, n_nodes);
+    if (st != RC_OK) return st;
+    rc_launch_fill_u32(s->d_tri_node, 0xFFFFFFFFu, s->nt, c->stream);
+    rc_launch_tri_nodes(s->d_nodes, n_nodes, s->d_order, s->d_tri_node, c->stream);
+    rc_launch_fill_u32(s->d_dirty, 0u, n_nodes, c->stream);
+    return hipGetLastError() == hipSuccess ? RC_OK : RC_ERR_HIP;
+}
+
 int rc_scene_create(rc_ctx* c, const rc_scene_desc* d, rc_scene** out)
 {
     if (!c || !d || !out) return RC_ERR_INVALID_ARG;
@@ -299,6 +358,7 @@ int rc_scene_create(rc_ctx* c, const rc_scene_desc* d, rc_scene** out)
         up(s->d_nrm, s->nrm.data(), s->nrm.size() * 4);
         if (s->nb) up(s->d_nrm_rest, s->nrm.data(), s->nrm.size() * 4);
     }
+    if (st == RC_OK && s->nb) st = upload_body_tris(c, s);
     if (st == RC_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = RC_ERR_HIP;
     if (st != RC_OK) { rc_scene_destroy(c, s); return st; }
     *out = s;
@@ -320,13 +380,16 @@ int rc_scene_destroy(rc_ctx* c, rc_scene* s)
     dev_free(s->d_o2w);
     dev_free(s->d_nrm);
     dev_free(s->d_nrm_rest);
+    dev_free(s->d_body_tri_off);
+    dev_free(s->d_body_tris);
     delete s;
     return RC_OK;
 }
 
 // Device build (k_build.hip): the tree and leaf order stay on the GPU; the nodes are read back once for the
 // host-side statistics (leaf count, SAH cost), after the build time is taken.
-static int build_device(rc_ctx* c, rc_scene* s, uint32_t max_leaf)
+static int build_device(rc_ctx* c, rc_scene* s, uint32_t max_leaf, bool sah = false, uint32_t bins = 32,
+                        float node_cost = 4.0f)
 {
     free_bvh(s);
     RC_HIP(hipStreamSynchronize(c->stream));
@@ -337,13 +400,17 @@ static int build_device(rc_ctx* c, rc_scene* s, uint32_t max_leaf)
     if (st != RC_OK) { free_bvh(s); return st; }
     Node4* d_nodes = nullptr;
     uint32_t n_nodes = 0;
-    hipError_t e = rc_build_bvh_device(s->d_pos, s->d_idx, s->nt, max_leaf, nullptr, {}, {}, &d_nodes, &n_nodes,
-                                       s->d_order, hb.level_start, c->stream);
+    hipError_t e = sah ? rc_build_bvh_device_sah(s->d_pos, s->d_idx, s->nt, bins, max_leaf, node_cost, &d_nodes,
+                                                 &n_nodes, s->d_order, hb.level_start, c->stream)
+                       : rc_build_bvh_device(s->d_pos, s->d_idx, s->nt, max_leaf, nullptr, {}, {}, &d_nodes, &n_nodes,
+                                             s->d_order, hb.level_start, c->stream);
     if (e != hipSuccess) { free_bvh(s); return hip_status(e); }
     s->d_nodes = d_nodes;
     rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, s->watertight, c->stream);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) { free_bvh(s); return RC_ERR_HIP; }
     s->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st = prepare_dirty_refit(c, s, n_nodes);
+    if (st != RC_OK) { free_bvh(s); return st; }
     hb.nodes.resize(n_nodes);
     if (hipMemcpy(hb.nodes.data(), d_nodes, (size_t)n_nodes * sizeof(Node4), hipMemcpyDeviceToHost) != hipSuccess) {
         free_bvh(s);
@@ -465,11 +532,15 @@ int rc_bvh_build(rc_ctx* c, rc_scene* s, const rc_build_opts* o)
     float node_cost = o && o->node_cost != 0.0f ? o->node_cost : 4.0f;
     const uint32_t method = o ? o->method : RC_BUILD_HOST_SAH;
     if (bins < 2 || bins > 256 || max_leaf < 1 || max_leaf > 4 || !(node_cost > 0.0f && node_cost <= 64.0f) ||
-        method > RC_BUILD_TWO_LEVEL || (o && (o->flags & ~(uint32_t)RC_BUILD_WATERTIGHT)))
+        method > RC_BUILD_DEVICE_SAH || (o && (o->flags & ~(uint32_t)RC_BUILD_WATERTIGHT)))
         return RC_ERR_INVALID_ARG;
     RC_HIP(hipSetDevice(c->device));
     s->watertight = o && (o->flags & RC_BUILD_WATERTIGHT);
     if (method == RC_BUILD_DEVICE_LBVH) return build_device(c, s, max_leaf);
+    if (method == RC_BUILD_DEVICE_SAH) {
+        if (bins > 64) return RC_ERR_UNSUPPORTED;
+        return build_device(c, s, max_leaf, true, bins, node_cost);
+    }
     if (method == RC_BUILD_TWO_LEVEL) return build_two_level(c, s, max_leaf);
     if (s->host_pos_stale) {
         RC_HIP(hipMemcpyAsync(s->pos.data(), s->d_pos, s->pos.size() * 4, hipMemcpyDeviceToHost, c->stream));
@@ -491,6 +562,8 @@ int rc_bvh_build(rc_ctx* c, rc_scene* s, const rc_build_opts* o)
                                       hipMemcpyHostToDevice, c->stream) != hipSuccess) st = RC_ERR_HIP;
     if (st != RC_OK) { free_bvh(s); return st; }
     rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, s->watertight, c->stream);
+    st = prepare_dirty_refit(c, s, (uint32_t)hb.nodes.size());
+    if (st != RC_OK) { free_bvh(s); return st; }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) { free_bvh(s); return RC_ERR_HIP; }
     s->hb = std::move(hb);
     s->built = true;
@@ -504,8 +577,11 @@ int rc_scene_set_transforms(rc_ctx* c, rc_scene* s, const float* d_xforms, const
     if (!d_xforms || !d_body_ids || n > s->nb || s->nb == 0) return RC_ERR_INVALID_ARG;
     RC_HIP(hipSetDevice(c->device));
     rc_launch_transform(s->d_rest, s->d_pos, s->d_nrm_rest, s->d_nrm, s->d_body_vr, d_xforms, d_body_ids, n,
-                        s->max_body_verts, c->stream);
-    rc_launch_record_o2w(d_xforms, d_body_ids, n, s->d_o2w, c->stream);
+                        s->max_body_verts, s->nb, c->d_counters + 9, c->stream);
+    rc_launch_record_o2w(d_xforms, d_body_ids, n, s->nb, s->d_o2w, c->stream);
+    if (s->built && !s->two_level && s->d_dirty)
+        rc_launch_mark_dirty(d_body_ids, n, s->nb, s->d_body_tri_off, s->d_body_tris, s->d_tri_node, s->d_dirty,
+                             s->hb.level_start.back(), c->stream);
     RC_HIP(hipGetLastError());
     s->host_pos_stale = true;
     return RC_OK;
@@ -517,10 +593,16 @@ int rc_bvh_refit(rc_ctx* c, rc_scene* s)
     if (!s->built) return RC_ERR_NOT_BUILT;
     RC_HIP(hipSetDevice(c->device));
     if (s->two_level) return rc_tlas_rebuild(c, s, nullptr);
-    rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, s->watertight, c->stream);
     const auto& ls = s->hb.level_start;
-    for (int lv = (int)s->hb.depth - 1; lv >= 0; --lv)
-        rc_launch_refit_level(s->d_nodes, s->d_pos, s->d_idx, s->d_order, ls[lv], ls[lv + 1] - ls[lv], c->stream);
+    if (s->d_dirty) {
+        // only the nodes holding moved triangles and their ancestors
+        rc_launch_refit_dirty(s->d_nodes, s->d_pos, s->d_idx, s->d_order, s->d_tris, s->watertight, s->d_dirty, ls,
+                              c->stream);
+    } else {
+        rc_launch_pack(s->d_pos, s->d_idx, s->d_order, s->nt, s->d_tris, s->watertight, c->stream);
+        for (int lv = (int)s->hb.depth - 1; lv >= 0; --lv)
+            rc_launch_refit_level(s->d_nodes, s->d_pos, s->d_idx, s->d_order, ls[lv], ls[lv + 1] - ls[lv], c->stream);
+    }
     RC_HIP(hipGetLastError());
     s->sah_stale = true;
     return RC_OK;

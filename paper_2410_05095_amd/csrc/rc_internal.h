@@ -91,6 +91,11 @@ hipError_t rc_build_bvh_device(const float* d_pos, const uint32_t* d_idx, uint32
                                const uint32_t* d_seg, const std::vector<uint32_t>& seg_first,
                                const std::vector<uint32_t>& seg_count, Node4** d_nodes_out, uint32_t* n_nodes_out,
                                uint32_t* d_order, std::vector<uint32_t>& level_start, hipStream_t st);
+// Device binned-SAH build (k_build.hip): the host builder's algorithm on the GPU (bins <= 64); outputs as
+// rc_build_bvh_device.
+hipError_t rc_build_bvh_device_sah(const float* d_pos, const uint32_t* d_idx, uint32_t n, uint32_t bins,
+                                   uint32_t max_leaf, float node_cost, Node4** d_nodes_out, uint32_t* n_nodes_out,
+                                   uint32_t* d_order, std::vector<uint32_t>& level_start, hipStream_t st);
 // Top-level workspace (all device memory, sized for n instances at allocation).
 struct TlasWork {
     uint32_t n = 0, cap = 0;
@@ -185,9 +190,22 @@ void rc_launch_pack_features(const DevScene& sc, const DevCamera& cam, const uin
 void rc_launch_pack(const float* pos, const uint32_t* idx, const uint32_t* order, uint32_t n_tris,
                     float4* tris, bool raw, hipStream_t st);
 void rc_launch_fill_u32(uint32_t* p, uint32_t value, uint32_t n, hipStream_t st);
-void rc_launch_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, float* o2w, hipStream_t st);
+void rc_launch_record_o2w(const float* xf, const uint32_t* body_ids, uint32_t n, uint32_t scene_bodies, float* o2w,
+                          hipStream_t st);
 void rc_launch_transform(const float* rest, float* pos, const float* nrm_rest, float* nrm,
-                         const uint32_t* body_vrange, const float* xf,
-                         const uint32_t* body_ids, uint32_t n_bodies, uint32_t max_count, hipStream_t st);
+                         const uint32_t* body_vrange, const float* xf, const uint32_t* body_ids, uint32_t n_bodies,
+                         uint32_t max_count, uint32_t scene_bodies, uint32_t* bad_value, hipStream_t st);
 void rc_launch_refit_level(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order,
                            uint32_t first, uint32_t count, hipStream_t st);
+// Dirty-node refit (k_shade.hip): tri_node[t] = node holding triangle t in a leaf; moved bodies mark those
+// nodes; the refit recomputes the marked nodes and their ancestors only.  The shallowest levels with at most
+// RC_REFIT_TOP_NODES nodes together are done by one workgroup.
+#define RC_REFIT_TOP_MAX 16
+#define RC_REFIT_TOP_NODES 8192u
+void rc_launch_tri_nodes(const Node4* nodes, uint32_t n_nodes, const uint32_t* order, uint32_t* tri_node,
+                         hipStream_t st);
+void rc_launch_mark_dirty(const uint32_t* body_ids, uint32_t n, uint32_t n_bodies, const uint32_t* tri_off,
+                          const uint32_t* body_tris, const uint32_t* tri_node, uint32_t* dirty, uint32_t n_nodes,
+                          hipStream_t st);
+void rc_launch_refit_dirty(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order, float4* tris,
+                           bool raw, uint32_t* dirty, const std::vector<uint32_t>& level_start, hipStream_t st);

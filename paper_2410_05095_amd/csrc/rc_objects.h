@@ -65,4 +65,11 @@ struct rc_scene {
     DevInst* d_inst = nullptr;
     uint32_t blas_nodes = 0, blas_depth = 0;
     TlasWork tlas;
+    // dirty-node refit of a flat BVH: per body the triangles with a vertex in it (CSR over bodies, built at
+    // creation when the bodies' vertex ranges do not overlap), per triangle the node holding it in a leaf, per
+    // node a flag marked by moved bodies (both allocated with a flat BVH of a scene with bodies)
+    uint32_t* d_body_tri_off = nullptr;
+    uint32_t* d_body_tris = nullptr;
+    uint32_t* d_tri_node = nullptr;
+    uint32_t* d_dirty = nullptr;
 };

@@ -95,3 +95,55 @@ def test_refit_big_scene_300_bodies(ctx, oracle_mod):
     assert (hit[ok] != orc["hit_id"][ok]).sum() == 0
     assert (np.abs(cnt - orc["vis_count"])[ok] <= orc["band_count"][ok]).all()
     say(f"[big refit] sah built {sah0:.3f} after 3 frames {gs.stats()['sah_cost']:.3f}; leaf sizes {hist.tolist()}")
+
+
+@pytest.mark.parametrize("build", ["device", "watertight"])
+def test_refit_after_several_moves(ctx, oracle_mod, build):
+    """The refit recomputes only the nodes that hold moved triangles (and their ancestors): two transform calls
+    on different bodies before one refit, on a GPU-built tree and on a watertight (raw-vertex) tree, leave
+    every box exact and the renders at parity."""
+    import torch
+    O = oracle_mod
+    scene = sg.small_random_scene(8, n_instances=40, width=48, height=40, ssaa=1, n_lights=2)
+    gs = ctx.scene_from(scene)
+    gs.build(device=(build == "device"), watertight=(build == "watertight"))
+    anim = sg.RigidAnimation(scene, n_bodies=20, seed=4, max_disp=0.4, max_rot_deg=15.0)
+    xf = anim.transforms(3)
+    ids = anim.body_ids.astype(np.int32)
+    half = len(ids) // 2
+    for sel in (slice(0, half), slice(half, None)):
+        gs.set_transforms(torch.from_numpy(xf[sel].copy()).cuda(), torch.from_numpy(ids[sel].copy()).cuda())
+    gs.refit()
+    torch.cuda.synchronize()
+    assert ctx.last_error() == 0
+    want = O.transform_f32(scene.positions, scene.body_vertex_range, anim.body_ids, xf)
+    assert np.array_equal(gs.positions().view(np.uint32), want.view(np.uint32))
+    nodes, order = gs.export()
+    assert bvh_bound_errors(nodes, order, want, scene.indices)[0] == 0
+    # a second refit without motion changes nothing
+    gs.refit()
+    nodes2, _ = gs.export()
+    assert np.array_equal(nodes, nodes2)
+    moved = sg.Scene(**{**scene.__dict__, "positions": want})
+    cam = scene.cameras[0]
+    out = ctx.render(gs, cam, scene.point_lights, sample_rgba=True)
+    orc = O.OracleScene.from_scene(moved, watertight=(build == "watertight")).render_point(
+        cam, scene.point_lights, np.arange(cam.n_samples))
+    st = compare_point(to_np(out["hit"]), to_np(out["shadow"]), to_np(out["sample_rgba"]), orc,
+                       len(scene.point_lights))
+    say(f"[refit {build}]", st)
+    assert_clean(st)
+
+
+def test_transform_rejects_unknown_body(ctx):
+    """A body id beyond the scene's bodies moves nothing and sets the sticky RC_ERR_INVALID_VALUE."""
+    import torch
+    scene = sg.small_random_scene(9, n_instances=6, width=16, height=16)
+    gs = ctx.scene_from(scene).build()
+    before = gs.positions()
+    xf = torch.from_numpy(np.tile(np.array([1, 0, 0, 5, 0, 1, 0, 0, 0, 0, 1, 0], np.float32), (1, 1))).cuda()
+    gs.set_transforms(xf, torch.tensor([scene.body_vertex_range.shape[0] + 3], dtype=torch.int32).cuda())
+    gs.refit()
+    torch.cuda.synchronize()
+    assert ctx.last_error() == -2
+    assert np.array_equal(gs.positions(), before)
