@@ -26,6 +26,9 @@ NODE_BYTES, TRI_BYTES = 128, 48
 # 4 dot products (4 mul, 8 FMA), 3 sub, 1 reciprocal, 3 mul by it, 1 add and 5 compares for the hit
 # conditions = 37.
 NODE_OPS, TRI_OPS = 57, 37
+# Per-lane (vector) part of a node visit: the 5 sorting compares run on wave-uniform keys in scalar
+# instructions in the wave kernel, so the algorithmic vector work of a node visit is 4 x 13 = 52.
+NODE_VOPS = 52
 # Issue peak of non-packed FP32 vector ops: 256 CUs x 64 lanes per clock x 2.4 GHz (the 157.3 TFLOP/s
 # datasheet figure counts packed FMAs, i.e. 4 FLOP per lane and clock).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
@@ -51,42 +54,119 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene, cam, args, budget_s=12.0):
-    """The FP64 oracle as it stands, on a bounded random sample of the same frame's pixels."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(scene, cam, args):
+    """The FP64 oracle as it stands, on the host cores (one thread per core), median of 3 runs per workload:
+    bounded random pixel samples of the benchmark frame at 1, args.spp and 256 rect-light samples per pixel,
+    the 12+1280-triangle box frame whole, a sample of the 1.1M-triangle 4-light 2x2-supersampled frame, and a
+    sample of the 64 batched views.  Rays counted: camera rays plus the shadow rays the oracle casts (point
+    lights: those it casts, i.e. with the light above the surface).  Scene generation and the oracle's BVH
+    builds are timed separately."""
     import numpy as np
 
     from oracle import oracle as O
+    from paper_2410_05095_amd import scenegen as sg
+    threads = O.n_threads()
+    rng = np.random.default_rng(123)
+
+    def rect_run(osc, sc, c, spp, n):
+        pix = np.sort(rng.choice(c.width * c.height, n, replace=False))
+        t = time.perf_counter()
+        r = osc.render_rect(c, sc.rect_light, spp, 0, pix, threads=threads)
+        return n + int(r["cast_count"].sum()), time.perf_counter() - t
+
+    def point_run(osc, sc, c, n):
+        npix = c.width * c.height
+        pix = np.sort(rng.choice(npix, min(n, npix), replace=False))
+        spp = c.ssaa ** 2
+        smp = (pix[:, None] * spp + np.arange(spp)[None, :]).ravel()
+        t = time.perf_counter()
+        r = osc.render_point(c, sc.point_lights, smp, threads=threads)
+        dt = time.perf_counter() - t
+        cast = int(np.unpackbits(r["cast"].view(np.uint8)).sum())
+        return len(smp) + cast, dt
+
+    def median3(fn, calib, target_s):
+        rays, dt = fn(calib)
+        n = int(max(calib, calib * target_s / max(dt, 1e-3)))
+        runs = [fn(n) for _ in range(3)]
+        rates = sorted(r / t / 1e6 for r, t in runs)
+        return {"mrays_per_s": round(rates[1], 3), "runs_mrays_per_s": [round(x, 3) for x in rates],
+                "pixels_per_run": n, "rays_per_run": int(np.median([r for r, _ in runs])),
+                "s_per_run": round(float(np.median([t for _, t in runs])), 2)}
+
+    res = {}
     t0 = time.perf_counter()
     osc = O.OracleScene.from_scene(scene)
-    build_s = time.perf_counter() - t0
-    rng = np.random.default_rng(123)
-    npix = cam.width * cam.height
-    threads = O.n_threads()
+    build7 = time.perf_counter() - t0
+    head = median3(lambda n: rect_run(osc, scene, cam, args.spp, n), 400, 4.0)
+    res[f"big_7M_{args.spp}spp"] = head
+    res["big_7M_1spp"] = median3(lambda n: rect_run(osc, scene, cam, 1, n), 4000, 1.0)
+    res["big_7M_256spp"] = median3(lambda n: rect_run(osc, scene, cam, 256, n), 100, 3.0)
+    del osc
+    tiny = sg.tiny_box_scene(0)
+    tosc = O.OracleScene.from_scene(tiny)
+    tc = tiny.cameras[0]
+    res["tiny_box_full_frame"] = median3(lambda n: point_run(tosc, tiny, tc, n), tc.width * tc.height, 0.0)
+    t1 = time.perf_counter()
+    city = sg.city_scene(args.seed)
+    cosc = O.OracleScene.from_scene(city)
+    city_build = time.perf_counter() - t1
+    res["city_1M_4spp_4lights"] = median3(lambda n: point_run(cosc, city, city.cameras[0], n), 2000, 2.0)
+    del cosc, city
+    t2 = time.perf_counter()
+    bscenes, bcams = sg.batch_scenes(args.seed)
+    boscs = [O.OracleScene.from_scene(b) for b in bscenes]
+    batch_build = time.perf_counter() - t2
 
-    def run(n):
-        pix = np.sort(rng.choice(npix, n, replace=False))
+    def batch_run(n):
+        # n pixels spread evenly over the 64 views; the views run concurrently, one host thread each
+        from concurrent.futures import ThreadPoolExecutor
+        per = max(1, n // len(bcams))
+        jobs = []
+        for i, c in enumerate(bcams):
+            pix = np.sort(rng.choice(c.width * c.height, min(per, c.width * c.height), replace=False))
+            jobs.append((boscs[i % 4], bscenes[i % 4], c, pix))
+
+        def one(j):
+            osc_, sc_, c_, pix = j
+            r = osc_.render_point(c_, sc_.point_lights, pix, threads=1)
+            return len(pix) + int(np.unpackbits(r["cast"].view(np.uint8)).sum())
+
         t = time.perf_counter()
-        if args.workload == "big_7M":
-            r = osc.render_rect(cam, scene.rect_light, args.spp, 0, pix, threads=threads)
-            rays = n + int(r["cast_count"].sum())
-        else:
-            spp = cam.ssaa ** 2
-            smp = (pix[:, None] * spp + np.arange(spp)[None, :]).ravel()
-            r = osc.render_point(cam, scene.point_lights, smp, threads=threads)
-            rays = len(smp) + int(sum(bin(int(m)).count("1") for m in r["mask"]))  # lit shadow rays only: a lower bound
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            rays = sum(ex.map(one, jobs))
         return rays, time.perf_counter() - t
 
-    rays, dt = run(500)
-    n = int(min(npix, max(500, 500 * budget_s / max(dt, 1e-3))))
-    rays, dt = run(n)
-    return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} random pixels of the same frame ({rays} rays, {dt:.1f} s); oracle BVH build "
-                      f"{build_s:.1f} s not included"}
+    res["batch_64_views"] = median3(batch_run, 64 * 500, 2.0)
+    return {"value": head["mrays_per_s"], "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "model": cpu_model(), "runs": 3, "statistic": "median of 3 runs",
+            "sample": (f"{head['pixels_per_run']} random pixels of the benchmark frame per run "
+                       f"({head['rays_per_run']} rays, {head['s_per_run']} s); oracle BVH builds not included "
+                       f"(7.3M: {build7:.1f} s, city: {city_build:.1f} s with scene generation, batch scenes: "
+                       f"{batch_build:.1f} s with generation)"),
+            "configs": res}
 
 
 def learned_path(ctx, gs, scene, cam, args):
-    """Train the denoiser on the method's own 1/256-sample renders of other scene seeds, then compare
-    on this frame: shadow MSE against 256 samples and device frame time, learned 1 spp vs plain."""
+    """Train the denoiser on the method's own 1/256-sample renders of other scene seeds (2000 crops of 512x512
+    from 200 1080p views by default: 50 views of each of 4 seeds, 10 crops each), then compare on the
+    evaluation scene: shadow MSE against 256 samples on the benchmark view and on 8 held-out views, and
+    device frame times of the learned 1-spp path and of the plain path (64 spp, and the sample count of
+    equal MSE).  `target_met`: denoised 1 spp at or below the plain 64-spp MSE on the held-out views with a
+    faster frame."""
+    import numpy as np
     import torch
 
     from paper_2410_05095_amd import _native as N
@@ -98,25 +178,60 @@ def learned_path(ctx, gs, scene, cam, args):
         sc = sg.big_scene(seed)
         train_scenes.append((sc, ctx.scene_from(sc).build()))
     log(f"[bench] training scenes ready ({time.perf_counter() - t0:.1f} s)")
-    data = D.make_training_set(ctx, train_scenes, n_views=args.denoiser_views, crops_per_view=12, crop=256,
-                               seed=args.seed, log=log)
+    data = D.make_training_set(ctx, train_scenes, n_views=args.denoiser_views, crops_per_view=args.denoiser_cpv,
+                               crop=args.denoiser_crop, seed=args.seed, log=log)
     n_crops = len(data)
     for _, h in train_scenes:
         h.close()
     den = N.Denoiser(ctx, seed=args.seed)
     t1 = time.perf_counter()
-    losses = D.train(den, data, steps=args.denoiser_steps, batch=8, lr=2e-3, seed=args.seed, log=log, log_every=300)
+    losses = D.train(den, data, steps=args.denoiser_steps, batch=8, lr=args.denoiser_lr, seed=args.seed, log=log,
+                     log_every=500, warmup=args.denoiser_warmup)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     del data
+    torch.cuda.empty_cache()
     ev = D.evaluate(ctx, den, gs, scene, cam, plain_spp=args.spp, ref_spp=256, reps=5)
+    held = D.orbit_views(np.random.default_rng(args.seed + 4242), 8, cam.width, cam.height, seed0=90000)
+    ev["held_out"] = D.evaluate_views(ctx, den, gs, scene, held, plain_spp=args.spp)
+    ho = ev["held_out"]
+    ev["target_met"] = bool(ho["mse_denoised_1spp"] <= ho[f"mse_plain_{args.spp}spp"]
+                            and ev["frame_ms_learned"] < ev[f"frame_ms_plain_{args.spp}spp"])
+    ev["frame_faster_than_plain"] = bool(ev["frame_ms_learned"] < ev[f"frame_ms_plain_{args.spp}spp"])
+    ev["held_out_plain_spp_equivalent"] = ho["mse_raw_1spp"] / max(ho["mse_denoised_1spp"], 1e-12)
     if args.anim_frames > 0:
         ev["animated"] = animated(ctx, gs, scene, den, args)
     ev.update({"train_steps": args.denoiser_steps, "train_s": round(train_s, 1), "train_crops": n_crops,
-               "crop": 256, "final_loss": [x for x in losses if x == x][-1],
+               "lr": args.denoiser_lr, "warmup_steps": args.denoiser_warmup,
+               "crop": args.denoiser_crop, "train_views": args.denoiser_views,
+               "train_scene_seeds": list(range(args.seed + 1, args.seed + 1 + args.denoiser_scenes)),
+               "final_loss": [x for x in losses if x == x][-1],
                "weights": "bf16 (FP32 master)", "parity": "unpinned (statistical)"})
-    rnd = lambda v: round(v, 6) if isinstance(v, float) else v
+    den.close()
+    rnd = lambda v: round(v, 7) if isinstance(v, float) else v
     return {k: ({a: rnd(b) for a, b in v.items()} if isinstance(v, dict) else rnd(v)) for k, v in ev.items()}
+
+
+def timed_frames(ctx, gs, cam, kw, steps, warmup, out=None):
+    """`steps` frames back to back after `warmup` untimed ones, a HIP event pair around each frame on the
+    stream the library enqueues on (torch's current stream), the host synchronised only before and after.
+    Returns (outputs, wall ms per frame, median event ms, event ms of each frame)."""
+    import numpy as np
+    import torch
+    out = {} if out is None else out
+    for _ in range(warmup):
+        ctx.render(gs, cam, out=out, **kw)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        ctx.render(gs, cam, out=out, **kw)
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [a.elapsed_time(b) for a, b in ev]
+    return out, wall * 1000.0 / steps, float(np.median(ms)), ms
 
 
 def post_pass(ctx, out, args):
@@ -319,11 +434,65 @@ def dynamic_structures(ctx, gs_flat, scene, cam, args):
     return res
 
 
+def batch_views(ctx, args):
+    """Batched views: 64 cameras (square, 256..1024 pixels a side) over four scenes of 0.1M, 0.5M, 1M and 2M
+    triangles with 1-4 point lights each, all rendered by one persistent launch fed by the device work queue.
+    The autotuner times every candidate of its built-in grid (tile, queue depth, rays per wave, waves per
+    SIMD) on this batch and picks the fastest; the batch is then captured as a hipGraph and replayed:
+    device time per replay (HIP events, median), rays per batch, and Mrays/s."""
+    import numpy as np
+    import torch
+
+    from paper_2410_05095_amd import scenegen as sg
+    t0 = time.perf_counter()
+    scenes, _ = sg.batch_scenes(args.seed)
+    handles, views, lights = [], [], []
+    for si, sc in enumerate(scenes):
+        handles.append(ctx.scene_from(sc).build())
+        lf = len(lights)
+        lights.extend(sc.point_lights.tolist())
+        for cam in sc.cameras:
+            views.append((si, cam, lf, len(sc.point_lights)))
+    lights = np.asarray(lights, np.float32).reshape(-1, 6)
+    log(f"[bench] batch: {len(views)} views over {[s.n_tris for s in scenes]} triangles "
+        f"({time.perf_counter() - t0:.1f} s)")
+    t1 = time.perf_counter()
+    best, tune_ms = ctx.autotune(handles, views, lights, reps=3)
+    tune_s = time.perf_counter() - t1
+    outs = ctx.render_batch(handles, views, lights, tune=best, timing=True)
+    st = ctx.stage_times()
+    for _ in range(3):
+        outs = ctx.render_batch(handles, views, lights, tune=best, graph=True, outs=outs)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        ctx.render_batch(handles, views, lights, tune=best, graph=True, outs=outs)
+        b.record()
+    torch.cuda.synchronize()
+    assert ctx.last_error() == 0
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    default_outs = ctx.render_batch(handles, views, lights, timing=True)
+    default_ms = ctx.stage_times()["total_ms"]
+    for h in handles:
+        h.close()
+    del outs, default_outs
+    rays = int(st["primary_rays"])
+    pixels = int(sum(c.width * c.height for _, c, _, _ in views))
+    log(f"[bench] batch: tuning {best} ({tune_s:.1f} s), replay {ms:.3f} ms")
+    return {"views": len(views), "scenes_tris": [int(s.n_tris) for s in scenes], "pixels": pixels,
+            "rays_per_batch": rays, "camera_rays": pixels, "shadow_rays": rays - pixels,
+            "graph_replay_ms": round(ms, 4), "mrays_per_s": round(rays / ms / 1e3, 1),
+            "default_tuning_ms": round(default_ms, 4), "tuning": best,
+            "autotune": {"grid": "built-in (tile 8x8/16x8/16x16, queue 64/256/1024, min rays 16/32/48, "
+                                 "2 occupancies)", "best_candidate_ms": round(tune_ms, 4), "search_s": round(tune_s, 1)}}
+
+
 def animated(ctx, gs, scene, den, args):
     """The same scene with 300 rigid bodies moving (<= 5 cm, <= 2 degrees per frame), BVH refit every frame,
     args.anim_views 1080p views per frame on the learned 1-spp path; per-frame shadow MSE of the BF16
-    denoiser and of its FP32 copy against 256 samples, for view f mod V of frame f and for every view of the
-    first and last frame."""
+    denoiser and of its FP32 copy against 256 samples, for every view of frames 0, 30, 60, 90 and the last,
+    and for view f mod V of every other frame f."""
     import numpy as np
 
     from paper_2410_05095_amd import animate as A
@@ -332,8 +501,12 @@ def animated(ctx, gs, scene, den, args):
     anim = sg.RigidAnimation(scene, n_bodies=300, seed=args.seed)
     views = D.orbit_views(np.random.default_rng(args.seed + 77), args.anim_views, 1920, 1080, seed0=5000)
     F, V = args.anim_frames, args.anim_views
-    plan = lambda f: list(range(V)) if f in (0, F - 1) else [f % V]
+    full = {0, F - 1} | {f for f in (30, 60, 90) if f < F}
+    plan = lambda f: list(range(V)) if f in full else [f % V]
     res = A.run(ctx, scene, gs, den, anim, views, F, plan, log=log)
+    res.pop("per_frame")
+    res["reference_plan"] = (f"256-sample references for all {V} views of frames {sorted(full)} and for view "
+                             f"f mod {V} of every other frame f")
     rnd = lambda v: round(v, 6) if isinstance(v, float) else v
     return {k: rnd(v) for k, v in res.items()}
 
@@ -341,23 +514,28 @@ def animated(ctx, gs, scene, den, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="big_7M", choices=["big_7M", "city_1M"])
     ap.add_argument("--spp", type=int, default=64, help="rect-light samples per pixel (big_7M)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--denoiser-steps", type=int, default=12000,
-                    help="training steps of the learned 1-spp path (0 = skip the learned-path comparison)")
+    ap.add_argument("--denoiser-steps", type=int, default=6000,
+                    help="training steps (batches of 8 crops) of the learned 1-spp path (0 = skip the learned path)")
     ap.add_argument("--denoiser-scenes", type=int, default=4,
                     help="training scenes (seeds after the evaluation seed) of the denoiser's training set")
-    ap.add_argument("--denoiser-views", type=int, default=400,
-                    help="1080p views of the training scenes rendered for the denoiser's training set (12 crops each)")
-    ap.add_argument("--anim-frames", type=int, default=12,
+    ap.add_argument("--denoiser-views", type=int, default=200,
+                    help="1080p views of the training scenes rendered for the denoiser's training set")
+    ap.add_argument("--denoiser-cpv", type=int, default=10, help="training crops cut from each view")
+    ap.add_argument("--denoiser-crop", type=int, default=512, help="training crop side in pixels")
+    ap.add_argument("--denoiser-lr", type=float, default=1e-3, help="peak Adam learning rate (cosine decay)")
+    ap.add_argument("--denoiser-warmup", type=int, default=300, help="steps of linear learning-rate ramp")
+    ap.add_argument("--anim-frames", type=int, default=120,
                     help="animated frames (moving bodies, refit) rendered after the learned-path comparison")
     ap.add_argument("--anim-views", type=int, default=16, help="1080p views per animated frame")
     ap.add_argument("--dyn-frames", type=int, default=24,
                     help="frames of the moving-body comparison of flat refit and two-level rebuild (0 = skip)")
+    ap.add_argument("--batch", type=int, default=1, help="run the 64-view / 4-scene batched leg (autotuned, graph replay)")
     ap.add_argument("--profile-denoiser", type=int, default=0,
                     help="instead of rendering, run this many BF16 denoiser inferences of one 1080p view (twice: "
                          "warm-up, timed) and one FP32-copy inference")
@@ -430,33 +608,42 @@ def main():
         kw = dict(lights=scene.point_lights)
     out = {}
     for i in range(args.warmup):
-        ctx.render(gs, cam, out=out, timing=True, **kw)
+        ctx.render(gs, cam, out=out, **kw)
     torch.cuda.synchronize()
     assert ctx.last_error() == 0
     log(f"[bench] warmup done")
 
-    stages = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ctx.render(gs, cam, out=out, timing=True, **kw)
-        stages.append(ctx.stage_times())   # synchronises the stream after each frame
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # timed region: K frames back to back on the library's stream, HIP events around each frame, one host
+    # synchronisation at each end
+    out, ms_step, frame_med, _ = timed_frames(ctx, gs, cam, kw, args.steps, 0, out)
     assert ctx.last_error() == 0
-    ms_step = wall * 1000.0 / args.steps
-    st = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    # per-stage device times (RC_FLAG_TIMING adds events between the stages): median of 10 frames
+    stages = []
+    for _ in range(10):
+        ctx.render(gs, cam, out=out, timing=True, **kw)
+        stages.append(ctx.stage_times())
+    st = {k: float(np.median([s[k] for s in stages])) for k in stages[0]}
+    # own-path work: the same frame through the per-lane kernels, whose counters count each ray's own node
+    # visits and triangle tests (near-first order, any hit), as the oracle's instrumented traversal does
+    ctx.render(gs, cam, out={}, per_lane=True, **kw)
+    own = ctx.stage_times()
+    torch.cuda.synchronize()
+    assert ctx.last_error() == 0
     rays = st["primary_rays"] + st["shadow_rays"]
     value = rays / (ms_step / 1000.0) / 1e6
     # roofline of the dominant kernel (shadow traversal).  Its lanes mostly fetch the same nodes (the
     # light samples of one pixel share a wave), so the caches serve nearly all node and triangle bytes and
-    # the measured fabric traffic is far below HBM bandwidth: the bound is instruction issue, reported as
-    # FP32 arithmetic per launch (counted node visits and triangle tests) against the FP32 issue peak.
+    # the measured fabric traffic is far below HBM bandwidth: the bound is vector instruction issue.
+    # achieved = the algorithmic vector work of the launch (each ray's own node visits x 52 + own triangle
+    # tests x 37 FP32 lane-operations) / the kernel's device time.
     npix = cam.width * cam.height * cam.ssaa ** 2
     dom_ms = st["shadow_ms"]
-    dom_ops = st["shadow_nodes"] * NODE_OPS + st["shadow_tris"] * TRI_OPS
+    sh_rays = max(st["shadow_rays"], 1)
+    own_nodes, own_tris = own["shadow_nodes"] / max(own["shadow_rays"], 1), own["shadow_tris"] / max(own["shadow_rays"], 1)
+    dom_ops = st["shadow_rays"] * (own_nodes * NODE_VOPS + own_tris * TRI_OPS)
+    exec_ops = st["shadow_nodes"] * NODE_VOPS + st["shadow_tris"] * TRI_OPS
     achieved = dom_ops / (dom_ms / 1000.0) / 1e12
-    logical_bytes = st["shadow_nodes"] * NODE_BYTES + st["shadow_tris"] * TRI_BYTES + npix * 20
+    logical_bytes = st["shadow_rays"] * (own_nodes * NODE_BYTES + own_tris * TRI_BYTES) + npix * 20
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -467,26 +654,31 @@ def main():
                                    f"{cam.ssaa ** 2} samples/pixel, {len(scene.point_lights)} point lights")),
                    "tris": scene.n_tris, "width": cam.width, "height": cam.height},
         "frame_ms": round(ms_step, 4),
+        "frame_ms_median_events": round(frame_med, 4),
         "stages_ms": {"primary": round(st["primary_ms"], 4), "shadow": round(st["shadow_ms"], 4),
                       "shade_resolve": round(st["shade_ms"], 4), "render_device": round(st["total_ms"], 4)},
         "rays_per_frame": {"primary": int(st["primary_rays"]), "shadow": int(st["shadow_rays"])},
         "mrays_per_s_kernel": {"primary": round(st["primary_rays"] / st["primary_ms"] / 1e3, 1),
                                "shadow": round(st["shadow_rays"] / st["shadow_ms"] / 1e3, 1)},
-        "per_ray": {"primary_nodes": round(st["primary_nodes"] / max(st["primary_rays"], 1), 2),
-                    "primary_tris": round(st["primary_tris"] / max(st["primary_rays"], 1), 2),
-                    "shadow_nodes": round(st["shadow_nodes"] / max(st["shadow_rays"], 1), 2),
-                    "shadow_tris": round(st["shadow_tris"] / max(st["shadow_rays"], 1), 2)},
+        "mrays_per_s_frame": {"primary": round(st["primary_rays"] / ms_step / 1e3, 1),
+                              "shadow": round(st["shadow_rays"] / ms_step / 1e3, 1)},
+        "per_ray": {"primary_nodes": round(own["primary_nodes"] / max(own["primary_rays"], 1), 2),
+                    "primary_tris": round(own["primary_tris"] / max(own["primary_rays"], 1), 2),
+                    "shadow_nodes": round(own_nodes, 2), "shadow_tris": round(own_tris, 2),
+                    "counted_by": "own path (per-lane traversal counters)",
+                    "wave_union_shadow_nodes": round(st["shadow_nodes"] / sh_rays, 2),
+                    "wave_union_shadow_tris": round(st["shadow_tris"] / sh_rays, 2)},
         "bvh": {"build_ms": round(bst["build_ms"], 1), "nodes": int(bst["n_nodes"]), "depth": int(bst["depth"]),
                 "sah": round(bst["sah_cost"], 2)},
-        "roofline": ({"kernel": "k_rect_wave", "bound": "alu", "achieved": round(achieved, 3),
-                      "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
-                      "traffic": MEASURED_TRAFFIC.get((args.workload, args.spp, kernel_hash())),
-                      "logical_node_tri_GBps": round(logical_bytes / (dom_ms / 1000.0) / 1e9, 1)}
-                     if args.workload == "big_7M" else
-                     {"kernel": "k_trace<point>", "bound": "alu", "achieved": round(achieved, 3),
-                      "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
-                      "traffic": None,
-                      "logical_node_tri_GBps": round(logical_bytes / (dom_ms / 1000.0) / 1e9, 1)}),
+        "roofline": {"kernel": "k_rect_wave" if args.workload == "big_7M" else "k_point_wave", "bound": "alu",
+                     "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
+                     "frac": round(achieved / ALU_PEAK_TOPS, 4),
+                     "traffic": (MEASURED_TRAFFIC.get((args.workload, args.spp, kernel_hash()))
+                                 if args.workload == "big_7M" else None),
+                     "work": f"own path: {own_nodes:.2f} node visits x {NODE_VOPS} + {own_tris:.2f} triangle tests "
+                             f"x {TRI_OPS} FP32 lane-ops per ray",
+                     "executed_union_over_own": round(exec_ops / max(dom_ops, 1.0), 3),
+                     "logical_node_tri_GBps": round(logical_bytes / (dom_ms / 1000.0) / 1e9, 1)},
     }
     res["post"] = post_pass(ctx, out, args)
     res["device_bvh"] = device_build(ctx, scene, cam, kw, args)
@@ -496,6 +688,8 @@ def main():
         res["dynamic_structures"] = dynamic_structures(ctx, gs, scene, cam, args)
     if args.workload == "big_7M":
         res["hard_shadows"] = hard_shadows(ctx, gs, scene, cam, args)
+    if args.batch:
+        res["batch"] = batch_views(ctx, args)
     if args.workload == "big_7M" and args.denoiser_steps > 0:
         res["denoiser"] = learned_path(ctx, gs, scene, cam, args)
     if not args.no_cpu_baseline:

@@ -1057,7 +1057,7 @@ OR_API void or_render_point(const or_scene* s, const or_bvh* B, const or_camera*
                             const float* lights, int n_lights, double c,
                             const int64_t* samples, int64_t n,
                             uint32_t* hit_id, double* tuv, double* tuv_err, uint8_t* band_primary,
-                            uint32_t* mask, uint32_t* band_shadow, double* rgb)
+                            uint32_t* mask, uint32_t* band_shadow, double* rgb, uint32_t* cast_mask)
 {
     cam_basis cb;
     camera_basis(cam, &cb);
@@ -1071,7 +1071,7 @@ OR_API void or_render_point(const or_scene* s, const or_bvh* B, const or_camera*
         tuv[3 * q + 0] = h.t; tuv[3 * q + 1] = h.u; tuv[3 * q + 2] = h.v;
         tuv_err[3 * q + 0] = h.et; tuv_err[3 * q + 1] = h.eu; tuv_err[3 * q + 2] = h.ev;
         band_primary[q] = (uint8_t)h.band;
-        mask[q] = 0; band_shadow[q] = 0;
+        mask[q] = 0; band_shadow[q] = 0; cast_mask[q] = 0;
         rgb[3 * q + 0] = rgb[3 * q + 1] = rgb[3 * q + 2] = 0.0;
         if (h.id == NO_HIT) continue;
         surface S;
@@ -1083,6 +1083,7 @@ OR_API void or_render_point(const or_scene* s, const or_bvh* B, const or_camera*
             int cast, band;
             int occ = shadow_test(s, B, &S, lp, 0.0, c, &cast, &band);
             if (band) band_shadow[q] |= 1u << l;
+            if (cast) cast_mask[q] |= 1u << l;
             if (!cast || occ) continue;
             mask[q] |= 1u << l;
             v3 tl = sub(lp, S.p);

@@ -70,7 +70,7 @@ def _declare(L):
     L.or_brdf.argtypes = [P, P, P, P, C.c_double, C.c_double, P]
     L.or_brdf_k.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, P]
     L.or_render_point.argtypes = [P, P, P, P, C.c_int, C.c_double, P, C.c_int64,
-                                  P, P, P, P, P, P, P]
+                                  P, P, P, P, P, P, P, P]
     L.or_render_rect.argtypes = [P, P, P, P, C.c_int, C.c_uint32, C.c_double, P, C.c_int64,
                                  P, P, P, P, P, P]
     L.or_count_rect.argtypes = [P, P, P, P, P, P, C.c_int, C.c_uint32, P, C.c_int64, P]
@@ -232,13 +232,14 @@ class OracleScene:
     # -- rendering ------------------------------------------------------------
     def render_point(self, cam, lights: np.ndarray, samples: np.ndarray, c: float = 4.0,
                      brute: bool = False, threads: Optional[int] = None):
-        """Per-sample primary hit, shadow mask and FP64 radiance for point lights."""
+        """Per-sample primary hit, shadow mask, FP64 radiance and the mask of cast shadow rays (light above the
+        surface) for point lights."""
         samples = np.ascontiguousarray(samples, dtype=np.int64)
         n = len(samples)
         L = np.ascontiguousarray(lights, dtype=np.float32).reshape(-1, 6)
         out = dict(hit_id=np.zeros(n, np.uint32), tuv=np.zeros((n, 3)), tuv_err=np.zeros((n, 3)),
                    band_primary=np.zeros(n, np.uint8), mask=np.zeros(n, np.uint32),
-                   band_shadow=np.zeros(n, np.uint32), rgb=np.zeros((n, 3)))
+                   band_shadow=np.zeros(n, np.uint32), rgb=np.zeros((n, 3)), cast=np.zeros(n, np.uint32))
         cs = camera_struct(cam)
         bvh = self._query_bvh(brute)
 
@@ -249,7 +250,7 @@ class OracleScene:
                                   _p(samples[a:b]), b - a,
                                   _p(out["hit_id"][a:b]), _p(out["tuv"][a:b]), _p(out["tuv_err"][a:b]),
                                   _p(out["band_primary"][a:b]), _p(out["mask"][a:b]),
-                                  _p(out["band_shadow"][a:b]), _p(out["rgb"][a:b]))
+                                  _p(out["band_shadow"][a:b]), _p(out["rgb"][a:b]), _p(out["cast"][a:b]))
 
         _parallel(run, n, threads)
         return out

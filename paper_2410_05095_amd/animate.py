@@ -84,6 +84,9 @@ def run(ctx: N.Context, scene: sg.Scene, gs: N.Scene, den: N.Denoiser, anim: sg.
         "mse_raw_1spp_mean": float(np.mean([x["mse_raw_1spp"] for x in allv])) if allv else None,
         "max_abs_bf16_fp32": float(max(x["max_abs_bf16_fp32"] for x in allv)) if allv else None,
         "reference_views": len(allv),
+        "per_frame_mse_bf16": [round(float(np.mean([x["mse_bf16"] for x in r["views"]])), 6) for r in records],
+        "per_frame_mse_fp32": [round(float(np.mean([x["mse_fp32"] for x in r["views"]])), 6) for r in records],
+        "per_frame_refit_ms": [round(r["refit_ms"], 4) for r in records],
         "per_frame": [{"frame": r["frame"], "refit_ms": round(r["refit_ms"], 4), "views_ms": round(r["views_ms"], 3),
                        "mse_bf16": [round(x["mse_bf16"], 6) for x in r["views"]],
                        "mse_fp32": [round(x["mse_fp32"], 6) for x in r["views"]]} for r in records],

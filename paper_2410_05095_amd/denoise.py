@@ -84,8 +84,9 @@ def make_training_set(ctx: N.Context, scenes, n_views: int, crops_per_view: int,
 
 
 def train(den: N.Denoiser, data: TrainingSet, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 0,
-          log=None, log_every: int = 50) -> List[float]:
-    """Adam with a cosine learning-rate schedule from lr to lr / 20; returns the loss of every step."""
+          log=None, log_every: int = 50, warmup: int = 0) -> List[float]:
+    """Adam with a cosine learning-rate schedule from lr to lr / 20, after a linear ramp from lr / warmup over
+    the first `warmup` steps; returns the loss of every step."""
     rng = np.random.default_rng(seed)
     losses = []
     n = len(data)
@@ -96,6 +97,8 @@ def train(den: N.Denoiser, data: TrainingSet, steps: int, batch: int = 8, lr: fl
         t = data.targets.index_select(0, idx).contiguous()
         m = data.masks.index_select(0, idx).contiguous()
         cur = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * s / max(steps, 1))))
+        if s < warmup:
+            cur *= (s + 1) / warmup
         want = log is not None and (s % log_every == 0 or s == steps - 1)
         losses.append(den.train_step(f, t, m, cur, want_loss=want))
         if want:
@@ -124,6 +127,33 @@ def plain_frame(ctx: N.Context, gs: N.Scene, scene: sg.Scene, cam, spp: int, ref
 def masked_mse(a, b, mask) -> float:
     m = mask.double()
     return float(((a.double() - b.double()) ** 2 * m).sum() / m.sum().clamp(min=1.0))
+
+
+def evaluate_views(ctx: N.Context, den: N.Denoiser, gs: N.Scene, scene: sg.Scene, cams, plain_spp: int = 64,
+                   ref_spp: int = 256) -> dict:
+    """Shadow MSE against the ref_spp reference on each of `cams` (held-out views of an evaluation scene):
+    denoised 1 spp (BF16 network and its FP32 copy), raw 1 spp and plain plain_spp; per-view values and means."""
+    torch = ctx.torch
+    rect = scene.rect_light
+    diag = scene_diagonal(scene)
+    rows = []
+    for cam in cams:
+        H, W = cam.height, cam.width
+        ref = render_visibility(ctx, gs, cam, rect, ref_spp, STREAM_REF)["visibility"].clone()
+        o1 = render_visibility(ctx, gs, cam, rect, 1, STREAM_1SPP)
+        mask = (o1["hit"][:, 0] != -1).reshape(H, W)
+        feat = N.pack_features(ctx, gs, cam, o1, diag).unsqueeze(0)
+        vden = den.infer(feat)[0]
+        v32 = den.infer(feat, fp32=True)[0]
+        vp = render_visibility(ctx, gs, cam, rect, plain_spp, STREAM_PLAIN)["visibility"]
+        rows.append({"den": masked_mse(vden, ref, mask), "den_fp32": masked_mse(v32, ref, mask),
+                     "raw": masked_mse(o1["visibility"], ref, mask), "plain": masked_mse(vp, ref, mask)})
+    torch.cuda.synchronize()
+    mean = {k: float(np.mean([r[k] for r in rows])) for k in rows[0]}
+    return {"views": len(cams), "mse_denoised_1spp": mean["den"], "mse_denoised_1spp_fp32": mean["den_fp32"],
+            "mse_raw_1spp": mean["raw"], f"mse_plain_{plain_spp}spp": mean["plain"],
+            "per_view_denoised": [round(r["den"], 7) for r in rows],
+            f"per_view_plain_{plain_spp}spp": [round(r["plain"], 7) for r in rows]}
 
 
 def evaluate(ctx: N.Context, den: N.Denoiser, gs: N.Scene, scene: sg.Scene, cam, plain_spp: int = 64,
