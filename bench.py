@@ -176,7 +176,7 @@ def learned_path(ctx, gs, scene, cam, args):
     train_scenes = []
     for seed in range(args.seed + 1, args.seed + 1 + args.denoiser_scenes):
         sc = sg.big_scene(seed)
-        train_scenes.append((sc, ctx.scene_from(sc).build()))
+        train_scenes.append((sc, ctx.scene_from(sc).build(device_sah=True)))
     log(f"[bench] training scenes ready ({time.perf_counter() - t0:.1f} s)")
     data = D.make_training_set(ctx, train_scenes, n_views=args.denoiser_views, crops_per_view=args.denoiser_cpv,
                                crop=args.denoiser_crop, seed=args.seed, log=log)
@@ -287,36 +287,41 @@ def hard_shadows(ctx, gs, scene, cam, args):
 
 
 def device_build(ctx, scene, cam, kw, args):
-    """The GPU LBVH build of the same scene (positions already in HBM): build time (median of 3, from the
-    first kernel to the finished tree, allocation included), tree size and SAH cost, and the frame's
-    device time rendered through that tree (median of args.steps frames)."""
+    """The GPU builds of the same scene (positions already in HBM): the binned SAH (the host build's algorithm,
+    giving its tree) and the linear BVH.  Build time (median of 3, from the first kernel to the finished tree,
+    allocation included), tree size and SAH cost, and the frame's device time rendered through each tree
+    (median of args.steps frames)."""
     import numpy as np
-    gs = ctx.scene_from(scene)
-    ms = []
-    for _ in range(3):
-        gs.build(device=True)
-        ms.append(gs.stats()["build_ms"])
-    st = gs.stats()
-    out = {}
-    for _ in range(args.warmup):
-        ctx.render(gs, cam, out=out, timing=True, **kw)
-    frames = []
-    for _ in range(args.steps):
-        ctx.render(gs, cam, out=out, timing=True, **kw)
-        frames.append(ctx.stage_times())
-    assert ctx.last_error() == 0
-    gs.close()
-    med = lambda k: round(float(np.median([f[k] for f in frames])), 4)
-    return {"build_ms": round(float(np.median(ms)), 2), "nodes": int(st["n_nodes"]), "depth": int(st["depth"]),
-            "sah": round(st["sah_cost"], 2), "frame_device_ms": med("total_ms"), "shadow_ms": med("shadow_ms"),
-            "primary_ms": med("primary_ms")}
+    res = {}
+    for name, opt in (("binned_sah", dict(device_sah=True)), ("lbvh", dict(device=True))):
+        gs = ctx.scene_from(scene)
+        ms = []
+        for _ in range(3):
+            gs.build(**opt)
+            ms.append(gs.stats()["build_ms"])
+        st = gs.stats()
+        out = {}
+        for _ in range(args.warmup):
+            ctx.render(gs, cam, out=out, timing=True, **kw)
+        frames = []
+        for _ in range(args.steps):
+            ctx.render(gs, cam, out=out, timing=True, **kw)
+            frames.append(ctx.stage_times())
+        assert ctx.last_error() == 0
+        gs.close()
+        med = lambda k: round(float(np.median([f[k] for f in frames])), 4)
+        res[name] = {"build_ms": round(float(np.median(ms)), 2), "nodes": int(st["n_nodes"]), "depth": int(st["depth"]),
+                     "sah": round(st["sah_cost"], 4), "frame_device_ms": med("total_ms"), "shadow_ms": med("shadow_ms"),
+                     "primary_ms": med("primary_ms")}
+        log(f"[bench] device build {name}: {res[name]}")
+    return res
 
 
 def watertight_frames(ctx, scene, cam, kw, args):
-    """The same frames with every ray/triangle test watertight (RC_BUILD_WATERTIGHT, host binned-SAH tree of
+    """The same frames with every ray/triangle test watertight (RC_BUILD_WATERTIGHT, binned-SAH tree of
     the same scene): device time of the 64-sample frame and of the hard-shadow frame, medians of args.steps."""
     import numpy as np
-    gs = ctx.scene_from(scene).build(watertight=True)
+    gs = ctx.scene_from(scene).build(watertight=True, device_sah=True)
     c = scene.rect_light.center
     hard = dict(lights=np.array([[c[0], c[1], c[2], 400.0, 400.0, 400.0]], np.float32))
     res = {}
@@ -448,7 +453,7 @@ def batch_views(ctx, args):
     scenes, _ = sg.batch_scenes(args.seed)
     handles, views, lights = [], [], []
     for si, sc in enumerate(scenes):
-        handles.append(ctx.scene_from(sc).build())
+        handles.append(ctx.scene_from(sc).build(device_sah=True))
         lf = len(lights)
         lights.extend(sc.point_lights.tolist())
         for cam in sc.cameras:
@@ -598,7 +603,7 @@ def main():
             ms.append(gs.stats()["build_ms"])
         print(json.dumps({"device_build_ms": ms, "tris": scene.n_tris, **gs.stats()}), flush=True)
         return
-    gs = ctx.scene_from(scene).build()
+    gs = ctx.scene_from(scene).build(device_sah=True)   # the binned-SAH tree of the host builder, built on the GPU
     bst = gs.stats()
     log(f"[bench] BVH: {bst}")
 
@@ -668,8 +673,9 @@ def main():
                     "counted_by": "own path (per-lane traversal counters)",
                     "wave_union_shadow_nodes": round(st["shadow_nodes"] / sh_rays, 2),
                     "wave_union_shadow_tris": round(st["shadow_tris"] / sh_rays, 2)},
-        "bvh": {"build_ms": round(bst["build_ms"], 1), "nodes": int(bst["n_nodes"]), "depth": int(bst["depth"]),
-                "sah": round(bst["sah_cost"], 2)},
+        "bvh": {"method": "binned SAH (32 bins, leaves <= 4, node cost 4) built on the GPU",
+                "build_ms": round(bst["build_ms"], 1), "nodes": int(bst["n_nodes"]), "depth": int(bst["depth"]),
+                "sah": round(bst["sah_cost"], 4)},
         "roofline": {"kernel": "k_rect_wave" if args.workload == "big_7M" else "k_point_wave", "bound": "alu",
                      "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
                      "frac": round(achieved / ALU_PEAK_TOPS, 4),

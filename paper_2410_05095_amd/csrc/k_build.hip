@@ -554,18 +554,22 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_block(const uint64_t* key
 {
     __shared__ uint64_t K[SORT_BLOCK_MAX];
     __shared__ uint32_t V[SORT_BLOCK_MAX];
-    uint32_t m = 1;
+    uint32_t m = 64;
     while (m < n) m <<= 1;
     for (uint32_t i = threadIdx.x; i < m; i += SORT_THREADS) {
         K[i] = i < n ? keys[i] : ~0ull;
         V[i] = i < n ? vals[i] : ~0u;
     }
     __syncthreads();
+    // Each step compares the m / 2 pairs (i, i + j), i with bit j clear, one pair per thread and iteration: pair
+    // t has i = t with a zero bit inserted at j's position.  For j < 64 the 64 pairs of a wave lie in one block
+    // of 128 elements that no other wave touches, so such steps need no workgroup barrier between them: the
+    // wave's own LDS accesses complete in order.
     for (uint32_t k = 2; k <= m; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < m; i += SORT_THREADS) {
-                const uint32_t l = i ^ j;
-                if (l <= i) continue;
+            for (uint32_t t = threadIdx.x; t < m / 2; t += SORT_THREADS) {
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const uint32_t l = i | j;
                 const uint64_t ka = K[i], kb = K[l];
                 const uint32_t va = V[i], vb = V[l];
                 const bool greater = ka > kb || (ka == kb && va > vb);
@@ -574,7 +578,14 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_block(const uint64_t* key
                     V[i] = vb; V[l] = va;
                 }
             }
-            __syncthreads();
+            const bool next_in_wave = (j >> 1) > 0 ? (j >> 1) < 64 : (k << 1) <= 64;
+            if (next_in_wave && j < 64) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else {
+                __syncthreads();
+            }
         }
     }
     for (uint32_t i = threadIdx.x; i < n; i += SORT_THREADS) {
@@ -772,7 +783,7 @@ hipError_t rc_build_bvh_device(const float* d_pos, const uint32_t* d_idx, uint32
 namespace {
 
 constexpr int SAH_NB_MAX = 64;
-constexpr uint32_t SAH_SMALL = 4096;
+constexpr uint32_t SAH_SMALL = 1024;
 constexpr uint32_t SAH_CHUNK = 8192;
 constexpr int SAH_BIN_WORDS = 8;   // ordered lo[3], hi[3], count, pad
 

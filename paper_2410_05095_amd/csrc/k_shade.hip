@@ -119,11 +119,12 @@ __global__ __launch_bounds__(256) void k_record_o2w(const float* xf, const uint3
     if (body < scene_bodies) o2w[12 * (size_t)body + q % 12] = xf[q];
 }
 
-// Dirty-node refit of a flat BVH under rigid motion.  tri_node[t] = the node whose leaf child holds
-// triangle t; rc_scene_set_transforms marks (dirty = 1) the nodes holding triangles of the moved bodies; the
-// refit then recomputes, level by level from the deepest, only the dirty nodes (exact FP32 min/max, and the
-// packed records of their leaf triangles), each marking its parent.  Untouched nodes keep boxes that are
-// already exact for their unmoved triangles, so the result equals a full refit bit for bit.
+// Refit of a flat BVH touching only moved bodies.  tri_node[t] = the node whose leaf child holds triangle t;
+// rc_scene_set_transforms marks (dirty = 1) the nodes holding triangles of the moved bodies; the refit then
+// goes through the levels from the deepest, recomputing only marked nodes (exact FP32 min/max of their leaf
+// triangles' current vertices, whose packed records are rewritten on the way, and of their already refit child
+// nodes), each marking its parent.  Untouched nodes keep boxes that are exact for their unmoved triangles, so
+// the result equals a full refit bit for bit.
 __global__ __launch_bounds__(256) void k_tri_nodes(const Node4* nodes, uint32_t n_nodes, const uint32_t* order,
                                                    uint32_t* tri_node)
 {
@@ -137,95 +138,84 @@ __global__ __launch_bounds__(256) void k_tri_nodes(const Node4* nodes, uint32_t 
     }
 }
 
-// One block per moved body: its triangles (body_tris[tri_off[b] .. tri_off[b + 1])) mark their nodes.
+// grid (x: triangle blocks of the largest body, y: moved bodies): mark the nodes holding moved triangles
 __global__ __launch_bounds__(256) void k_mark_dirty(const uint32_t* body_ids, uint32_t n_bodies, const uint32_t* tri_off,
                                                     const uint32_t* body_tris, const uint32_t* tri_node,
                                                     uint32_t* dirty, uint32_t n_nodes)
 {
-    const uint32_t b = body_ids[blockIdx.x];
+    const uint32_t b = body_ids[blockIdx.y];
     if (b >= n_bodies) return;   // reported by k_transform
-    for (uint32_t i = tri_off[b] + threadIdx.x; i < tri_off[b + 1]; i += blockDim.x) {
-        const uint32_t n = tri_node[body_tris[i]];
-        if (n < n_nodes) dirty[n] = 1u;
-    }
+    const uint32_t i = tri_off[b] + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tri_off[b + 1]) return;
+    const uint32_t n = tri_node[body_tris[i]];
+    if (n < n_nodes) dirty[n] = 1u;
 }
 
-// Recompute node n's four child boxes (leaf children from their triangles' current vertices, whose packed
-// records are rewritten on the way; internal children from their own, already refit, boxes), clear its flag
-// and mark its parent.
-__device__ inline void refit_node(Node4* nodes, uint32_t n, const float* pos, const uint32_t* idx,
-                                  const uint32_t* order, float4* tris, uint32_t raw, uint32_t* dirty, uint32_t n_nodes)
+// The marked nodes of one level (first .. first + count - 1), four threads per node: thread c recomputes child
+// slot c; thread 0 then clears the node's mark and marks its parent (read by the next launch).
+__global__ __launch_bounds__(256) void k_refit_level_dirty(Node4* nodes, const float* pos, const uint32_t* idx,
+                                                           const uint32_t* order, float4* tris, uint32_t raw,
+                                                           uint32_t* dirty, uint32_t first, uint32_t count,
+                                                           uint32_t n_nodes)
 {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q / 4 >= count) return;
+    const uint32_t n = first + q / 4, c = q & 3u;
+    if (dirty[n] == 0u) return;
     Node4* nd = nodes + n;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const uint32_t w = nd->child[c];
-        if (w == RC_EMPTY_CHILD) continue;
+    const uint32_t w = nd->child[c];
+    if (w != RC_EMPTY_CHILD) {
         float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         if (rc_is_leaf(w)) {
+            // independent loads first (slots, then vertex indices, then vertices), then the packed records
             const uint32_t f = rc_leaf_first(w), cnt = rc_leaf_count(w);
-            for (uint32_t i = 0; i < cnt; ++i) {
-                const uint32_t t = order[f + i];
-                const uint32_t* ix = idx + 3 * (size_t)t;
-                const float* a = pos + 3 * (size_t)ix[0];
-                const float* b = pos + 3 * (size_t)ix[1];
-                const float* cc = pos + 3 * (size_t)ix[2];
+            uint32_t t[4], ix[4][3];
+            float v[4][9];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) t[i] = (uint32_t)i < cnt ? order[f + i] : 0u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) ix[i][k] = (uint32_t)i < cnt ? idx[3 * (size_t)t[i] + k] : 0u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int k = 0; k < 9; ++k) v[i][k] = (uint32_t)i < cnt ? pos[3 * (size_t)ix[i][k / 3] + k % 3] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if ((uint32_t)i >= cnt) continue;
+#pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    lo[k] = fminf(fminf(fminf(lo[k], a[k]), b[k]), cc[k]);
-                    hi[k] = fmaxf(fmaxf(fmaxf(hi[k], a[k]), b[k]), cc[k]);
+                    lo[k] = fminf(fminf(fminf(lo[k], v[i][k]), v[i][3 + k]), v[i][6 + k]);
+                    hi[k] = fmaxf(fmaxf(fmaxf(hi[k], v[i][k]), v[i][3 + k]), v[i][6 + k]);
                 }
                 float4* tp = tris + 3 * (size_t)(f + i);
-                tp[0] = make_float4(a[0], a[1], a[2], __uint_as_float(t));
+                tp[0] = make_float4(v[i][0], v[i][1], v[i][2], __uint_as_float(t[i]));
                 if (raw) {
-                    tp[1] = make_float4(b[0], b[1], b[2], 0.0f);
-                    tp[2] = make_float4(cc[0], cc[1], cc[2], 0.0f);
+                    tp[1] = make_float4(v[i][3], v[i][4], v[i][5], 0.0f);
+                    tp[2] = make_float4(v[i][6], v[i][7], v[i][8], 0.0f);
                 } else {
-                    tp[1] = make_float4(b[0] - a[0], b[1] - a[1], b[2] - a[2], 0.0f);
-                    tp[2] = make_float4(cc[0] - a[0], cc[1] - a[1], cc[2] - a[2], 0.0f);
+                    tp[1] = make_float4(v[i][3] - v[i][0], v[i][4] - v[i][1], v[i][5] - v[i][2], 0.0f);
+                    tp[2] = make_float4(v[i][6] - v[i][0], v[i][7] - v[i][1], v[i][8] - v[i][2], 0.0f);
                 }
             }
         } else {
             const Node4* ch = nodes + w;
-            for (int k = 0; k < 4; ++k) {
-                lo[0] = fminf(lo[0], ch->lo_x[k]); hi[0] = fmaxf(hi[0], ch->hi_x[k]);
-                lo[1] = fminf(lo[1], ch->lo_y[k]); hi[1] = fmaxf(hi[1], ch->hi_y[k]);
-                lo[2] = fminf(lo[2], ch->lo_z[k]); hi[2] = fmaxf(hi[2], ch->hi_z[k]);
-            }
+            const float4 lx = *reinterpret_cast<const float4*>(ch->lo_x), hx = *reinterpret_cast<const float4*>(ch->hi_x);
+            const float4 ly = *reinterpret_cast<const float4*>(ch->lo_y), hy = *reinterpret_cast<const float4*>(ch->hi_y);
+            const float4 lz = *reinterpret_cast<const float4*>(ch->lo_z), hz = *reinterpret_cast<const float4*>(ch->hi_z);
+            lo[0] = fminf(fminf(lx.x, lx.y), fminf(lx.z, lx.w)); hi[0] = fmaxf(fmaxf(hx.x, hx.y), fmaxf(hx.z, hx.w));
+            lo[1] = fminf(fminf(ly.x, ly.y), fminf(ly.z, ly.w)); hi[1] = fmaxf(fmaxf(hy.x, hy.y), fmaxf(hy.z, hy.w));
+            lo[2] = fminf(fminf(lz.x, lz.y), fminf(lz.z, lz.w)); hi[2] = fmaxf(fmaxf(hz.x, hz.y), fmaxf(hz.z, hz.w));
         }
         nd->lo_x[c] = lo[0]; nd->hi_x[c] = hi[0];
         nd->lo_y[c] = lo[1]; nd->hi_y[c] = hi[1];
         nd->lo_z[c] = lo[2]; nd->hi_z[c] = hi[2];
     }
-    dirty[n] = 0u;
-    const uint32_t p = nd->parent;
-    if (p < n_nodes) dirty[p] = 1u;   // the root's parent is 0xFFFFFFFF
-}
-
-// The dirty nodes of one level (nodes first .. first + count - 1), one thread per node.
-__global__ __launch_bounds__(256) void k_refit_dirty(Node4* nodes, const float* pos, const uint32_t* idx,
-                                                     const uint32_t* order, float4* tris, uint32_t raw,
-                                                     uint32_t* dirty, uint32_t first, uint32_t count, uint32_t n_nodes)
-{
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= count || dirty[first + q] == 0u) return;
-    refit_node(nodes, first + q, pos, idx, order, tris, raw, dirty, n_nodes);
-}
-
-// The top levels (nodes 0 .. start[levels] - 1, a few thousand) in one workgroup, deepest level first, a
-// barrier between levels.
-struct TopLevels {
-    uint32_t start[RC_REFIT_TOP_MAX + 1];
-    int levels;
-};
-
-__global__ __launch_bounds__(1024) void k_refit_top(Node4* nodes, const float* pos, const uint32_t* idx,
-                                                    const uint32_t* order, float4* tris, uint32_t raw,
-                                                    uint32_t* dirty, TopLevels L, uint32_t n_nodes)
-{
-    for (int lv = L.levels - 1; lv >= 0; --lv) {
-        for (uint32_t n = L.start[lv] + threadIdx.x; n < L.start[lv + 1]; n += blockDim.x)
-            if (dirty[n] != 0u) refit_node(nodes, n, pos, idx, order, tris, raw, dirty, n_nodes);
-        __syncthreads();
+    if (c == 0u) {   // every lane of the node read the mark above, in the same instruction
+        dirty[n] = 0u;
+        const uint32_t p = nd->parent;
+        if (p < n_nodes) dirty[p] = 1u;   // the root's parent is 0xFFFFFFFF
     }
 }
 
@@ -380,13 +370,13 @@ void rc_launch_tri_nodes(const Node4* nodes, uint32_t n_nodes, const uint32_t* o
     hipLaunchKernelGGL(k_tri_nodes, dim3(blocks(n_nodes, 256)), dim3(256), 0, st, nodes, n_nodes, order, tri_node);
 }
 
-void rc_launch_mark_dirty(const uint32_t* body_ids, uint32_t n, uint32_t n_bodies, const uint32_t* tri_off,
-                          const uint32_t* body_tris, const uint32_t* tri_node, uint32_t* dirty, uint32_t n_nodes,
-                          hipStream_t st)
+void rc_launch_mark_dirty(const uint32_t* body_ids, uint32_t n, uint32_t n_bodies, uint32_t max_body_tris,
+                          const uint32_t* tri_off, const uint32_t* body_tris, const uint32_t* tri_node, uint32_t* dirty,
+                          uint32_t n_nodes, hipStream_t st)
 {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_mark_dirty, dim3(n), dim3(256), 0, st, body_ids, n_bodies, tri_off, body_tris, tri_node, dirty,
-                       n_nodes);
+    if (n == 0 || max_body_tris == 0) return;
+    hipLaunchKernelGGL(k_mark_dirty, dim3(blocks(max_body_tris, 256), n), dim3(256), 0, st, body_ids, n_bodies, tri_off,
+                       body_tris, tri_node, dirty, n_nodes);
 }
 
 void rc_launch_refit_dirty(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order, float4* tris,
@@ -394,20 +384,11 @@ void rc_launch_refit_dirty(Node4* nodes, const float* pos, const uint32_t* idx, 
 {
     const int depth = (int)level_start.size() - 1;
     const uint32_t n_nodes = level_start[depth];
-    // top levels: as many of the shallowest levels as hold at most RC_REFIT_TOP_NODES nodes together
-    int top = 0;
-    while (top < depth && top < RC_REFIT_TOP_MAX && level_start[top + 1] <= RC_REFIT_TOP_NODES) ++top;
-    for (int lv = depth - 1; lv >= top; --lv) {
+    for (int lv = depth - 1; lv >= 0; --lv) {
         const uint32_t first = level_start[lv], count = level_start[lv + 1] - level_start[lv];
         if (count == 0) continue;
-        hipLaunchKernelGGL(k_refit_dirty, dim3(blocks(count, 256)), dim3(256), 0, st, nodes, pos, idx, order, tris,
-                           raw ? 1u : 0u, dirty, first, count, n_nodes);
-    }
-    if (top > 0) {
-        TopLevels L;
-        for (int i = 0; i <= top; ++i) L.start[i] = level_start[i];
-        L.levels = top;
-        hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(1024), 0, st, nodes, pos, idx, order, tris, raw ? 1u : 0u,
-                           dirty, L, n_nodes);
+        hipLaunchKernelGGL(k_refit_level_dirty, dim3(blocks(4 * (size_t)count, 256)), dim3(256), 0, st, nodes, pos, idx,
+                           order, tris, raw ? 1u : 0u, dirty, first, count, n_nodes);
     }
 }
+

@@ -52,6 +52,7 @@ void free_bvh(rc_scene* s)
     dev_free(s->d_dirty);
     rc_tlas_free(s->tlas);
     s->two_level = false;
+    s->refit_nodes = 0;
     s->blas_nodes = s->blas_depth = 0;
     s->built = false;
     s->hb = HostBvh();
@@ -253,6 +254,7 @@ static int upload_body_tris(rc_ctx* c, rc_scene* s)
     uint32_t bs[3];
     for (uint32_t t = 0; t < s->nt; ++t)
         for (int q = 0, k = bodies_of(t, bs); q < k; ++q) ++off[bs[q] + 1];
+    for (uint32_t b = 0; b < s->nb; ++b) s->max_body_tris = std::max(s->max_body_tris, off[b + 1]);
     for (uint32_t b = 0; b < s->nb; ++b) off[b + 1] += off[b];
     std::vector<uint32_t> tris(off[s->nb]), fill(off.begin(), off.end() - 1);
     for (uint32_t t = 0; t < s->nt; ++t)
@@ -275,11 +277,13 @@ static int prepare_dirty_refit(rc_ctx* c, rc_scene* s, uint32_t n_nodes)
 {
     if (!s->d_body_tri_off) return RC_OK;
     int st = dev_alloc(&s->d_tri_node, s->nt);
-    if (st == RC_OK) st = dev_alloc(&s->d_dirty, n_nodes);
+    const size_t words = n_nodes;   // one mark per node
+    if (st == RC_OK) st = dev_alloc(&s->d_dirty, words);
     if (st != RC_OK) return st;
+    s->refit_nodes = n_nodes;
     rc_launch_fill_u32(s->d_tri_node, 0xFFFFFFFFu, s->nt, c->stream);
     rc_launch_tri_nodes(s->d_nodes, n_nodes, s->d_order, s->d_tri_node, c->stream);
-    rc_launch_fill_u32(s->d_dirty, 0u, n_nodes, c->stream);
+    rc_launch_fill_u32(s->d_dirty, 0u, (uint32_t)words, c->stream);
     return hipGetLastError() == hipSuccess ? RC_OK : RC_ERR_HIP;
 }
 
@@ -580,8 +584,8 @@ int rc_scene_set_transforms(rc_ctx* c, rc_scene* s, const float* d_xforms, const
                         s->max_body_verts, s->nb, c->d_counters + 9, c->stream);
     rc_launch_record_o2w(d_xforms, d_body_ids, n, s->nb, s->d_o2w, c->stream);
     if (s->built && !s->two_level && s->d_dirty)
-        rc_launch_mark_dirty(d_body_ids, n, s->nb, s->d_body_tri_off, s->d_body_tris, s->d_tri_node, s->d_dirty,
-                             s->hb.level_start.back(), c->stream);
+        rc_launch_mark_dirty(d_body_ids, n, s->nb, s->max_body_tris, s->d_body_tri_off, s->d_body_tris, s->d_tri_node,
+                             s->d_dirty, s->refit_nodes, c->stream);
     RC_HIP(hipGetLastError());
     s->host_pos_stale = true;
     return RC_OK;

@@ -197,15 +197,13 @@ void rc_launch_transform(const float* rest, float* pos, const float* nrm_rest, f
                          uint32_t max_count, uint32_t scene_bodies, uint32_t* bad_value, hipStream_t st);
 void rc_launch_refit_level(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order,
                            uint32_t first, uint32_t count, hipStream_t st);
-// Dirty-node refit (k_shade.hip): tri_node[t] = node holding triangle t in a leaf; moved bodies mark those
-// nodes; the refit recomputes the marked nodes and their ancestors only.  The shallowest levels with at most
-// RC_REFIT_TOP_NODES nodes together are done by one workgroup.
-#define RC_REFIT_TOP_MAX 16
-#define RC_REFIT_TOP_NODES 8192u
+// Refit touching only moved bodies (k_shade.hip): tri_node[t] = node holding triangle t in a leaf; moved
+// bodies mark the nodes holding their triangles; the refit recomputes, level by level from the deepest, the
+// marked nodes, which mark their parents.
 void rc_launch_tri_nodes(const Node4* nodes, uint32_t n_nodes, const uint32_t* order, uint32_t* tri_node,
                          hipStream_t st);
-void rc_launch_mark_dirty(const uint32_t* body_ids, uint32_t n, uint32_t n_bodies, const uint32_t* tri_off,
-                          const uint32_t* body_tris, const uint32_t* tri_node, uint32_t* dirty, uint32_t n_nodes,
-                          hipStream_t st);
+void rc_launch_mark_dirty(const uint32_t* body_ids, uint32_t n, uint32_t n_bodies, uint32_t max_body_tris,
+                          const uint32_t* tri_off, const uint32_t* body_tris, const uint32_t* tri_node, uint32_t* dirty,
+                          uint32_t n_nodes, hipStream_t st);
 void rc_launch_refit_dirty(Node4* nodes, const float* pos, const uint32_t* idx, const uint32_t* order, float4* tris,
                            bool raw, uint32_t* dirty, const std::vector<uint32_t>& level_start, hipStream_t st);

@@ -70,6 +70,8 @@ struct rc_scene {
     // node a flag marked by moved bodies (both allocated with a flat BVH of a scene with bodies)
     uint32_t* d_body_tri_off = nullptr;
     uint32_t* d_body_tris = nullptr;
+    uint32_t max_body_tris = 0;
     uint32_t* d_tri_node = nullptr;
-    uint32_t* d_dirty = nullptr;
+    uint32_t* d_dirty = nullptr;      // one mark per node
+    uint32_t refit_nodes = 0;         // nodes covered by d_dirty
 };

@@ -71,7 +71,7 @@ def test_device_sah_equals_host_build(ctx, seed, n_inst, max_leaf, bins):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 9, 17, 5000])
 def test_device_sah_few_and_many_triangles(ctx, n):
-    """Sizes around the leaf size, and above the size (4096) where ranges switch from level-wise splitting to
+    """Sizes around the leaf size, and above the size (1024) where ranges switch from level-wise splitting to
     one wave per range."""
     rng = np.random.default_rng(n)
     pos = rng.normal(size=(3 * n, 3)) * np.array([3.0, 1.0, 2.0])
