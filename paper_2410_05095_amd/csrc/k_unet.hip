@@ -17,6 +17,19 @@
 #ifndef RC_CONV_ROWS
 #define RC_CONV_ROWS 8   // output rows per wave of the row-blocked convolution
 #endif
+// minimum waves per SIMD the compiler keeps the convolution kernels to (their register budget)
+#ifndef RC_OCC_E1A
+#define RC_OCC_E1A 4
+#endif
+#ifndef RC_OCC_ROWS
+#define RC_OCC_ROWS 2
+#endif
+#ifndef RC_OCC_416
+#define RC_OCC_416 3
+#endif
+#ifndef RC_OCC_816
+#define RC_OCC_816 2
+#endif
 
 namespace {
 
@@ -155,6 +168,30 @@ __device__ inline int xcd_tile(int b, int n)
     return g * q + min(g, r) + k;
 }
 
+// One 16-byte group of a convolution's input halo: pixel (y, x) of image n, channels [ci, ci + 8), zero
+// outside the image.  The address is formed from the clamped position, so the load is always in bounds and
+// needs no branch, and the value is replaced by zero afterwards; a tile's loads can then all be in flight at
+// once.  With a second source, channels below Ca come from the 2x nearest-upsampled `in`, the rest from in2.
+__device__ inline const uint16_t* group_ptr(const ConvArgs& a, int n, int y, int x, int ci)
+{
+    if (a.in2 == nullptr) return a.in + ((size_t)(n * a.H + y) * a.W + x) * a.Cin + ci;
+    const bool up = ci < a.Ca;
+    const size_t ou = ((size_t)(n * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1)) * a.Ca + ci;
+    const size_t os = ((size_t)(n * a.H + y) * a.W + x) * (a.Cin - a.Ca) + (ci - a.Ca);
+    return (up ? a.in : a.in2) + (up ? ou : os);
+}
+__device__ inline uint4 halo_group(const ConvArgs& a, int n, int y, int x, int ci)
+{
+    const bool inb = (unsigned)y < (unsigned)a.H && (unsigned)x < (unsigned)a.W;
+    const int yc = min(max(y, 0), a.H - 1), xc = min(max(x, 0), a.W - 1);
+    const uint4 v = *reinterpret_cast<const uint4*>(group_ptr(a, n, yc, xc, ci));
+    return inb ? v : make_uint4(0u, 0u, 0u, 0u);
+}
+
+// 16 zero bytes in device memory: the source of halo groups outside the image for loads that write LDS
+// directly
+__device__ __align__(16) const uint4 g_zero_group = {0u, 0u, 0u, 0u};
+
 // ---------------------------------------------------------------- 3x3 convolution, LDS-tiled
 // Workgroup of 4 waves; output tile = 4 rows x TW = 16 MT columns of one image, wave w computes row w:
 // MT 16-pixel M-tiles x NT 16-channel N-tiles.  For each chunk of CC input channels the input halo (6 rows
@@ -180,8 +217,8 @@ struct ConvLds {
     }
 };
 
-template <int MT, int NT, int CC, bool SW>
-__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
+template <int MT, int NT, int CC, bool SW, int OCC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void k_conv_lds(ConvArgs a)
 {
     extern __shared__ uint4 conv_lds[];
     using L = ConvLds<MT, NT, CC, SW>;
@@ -197,46 +234,62 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
     const int x0 = tx * TW, y0 = ty * 4;
     const int r = lane & 15, g = lane >> 4;
     const int K = 9 * a.Cin;
-    const int Cs = a.Cin - a.Ca;
     f32x4 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero = {};
-    for (int c0 = 0; c0 < a.Cin; c0 += CC) {
-        __syncthreads();
-        constexpr int GROUPS = CC / 8;
-        for (int i = threadIdx.x; i < HR * HW * GROUPS; i += 256) {
-            const int gg = i % GROUPS, pix = i / GROUPS;
-            const int hx = pix % HW, hy = pix / HW;
-            const int y = y0 - 1 + hy, x = x0 - 1 + hx;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
-                const int ci = c0 + 8 * gg;
-                if (a.in2 == nullptr)
-                    v = *reinterpret_cast<const uint4*>(a.in + ((size_t)(n * a.H + y) * a.W + x) * a.Cin + ci);
-                else if (ci < a.Ca)
-                    v = *reinterpret_cast<const uint4*>(
-                        a.in + ((size_t)(n * (a.H / 2) + y / 2) * (a.W / 2) + x / 2) * a.Ca + ci);
-                else
-                    v = *reinterpret_cast<const uint4*>(a.in2 + ((size_t)(n * a.H + y) * a.W + x) * Cs + (ci - a.Ca));
-            }
-            *reinterpret_cast<uint4*>(lds + pix * PST + 8 * gg) = v;
+    constexpr int GROUPS = CC / 8;
+    constexpr int HALO_ITEMS = HR * HW * GROUPS;
+    // item i of a chunk's halo: pixel i / GROUPS of the (HR x HW) halo, channel group i % GROUPS; item f of its
+    // staged weights: lane f % 64 of fragment (K-step, N-tile) f / 64 (output channel 16 nt + (l & 15), the
+    // 8 K values from 32 ks + 8 (l >> 4) on, tap = K / CC, input channel c0 + K % CC, zero from 9 CC on).
+    // Every thread holds PF halo items and WPF weight items in registers: all of its loads are issued before
+    // the first is waited for (loaded one by one, each load's latency would be paid in turn).
+    constexpr int PF = (HALO_ITEMS + 255) / 256;
+    constexpr int WPF = SW ? (L::W_U4 + 255) / 256 : 0;
+    auto halo_item = [&](int c0, int i) -> uint4 {
+        const int pix = i / GROUPS;
+        return halo_group(a, n, y0 - 1 + pix / HW, x0 - 1 + pix % HW, c0 + 8 * (i % GROUPS));
+    };
+    auto w_item = [&](int c0, int f) -> uint4 {
+        const int l = f & 63, q = f >> 6, nt = q % NT, ks = q / NT;
+        const int co = 16 * nt + (l & 15), kk = 32 * ks + 8 * (l >> 4);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (kk < 9 * CC && co < a.Cout) {
+            const int tap = kk / CC, cl = kk - tap * CC;
+            v = *reinterpret_cast<const uint4*>(a.wt + (size_t)co * K + tap * a.Cin + c0 + cl);
         }
-        // weight fragment (ks, nt) of lane l: output channel 16 nt + (l & 15), the 8 K values from
-        // 32 ks + 8 (l >> 4) on (tap = K / CC, input channel c0 + K % CC), zero from 9 CC on
-        if constexpr (SW) {
-            for (int f = threadIdx.x; f < L::W_U4; f += 256) {
-                const int l = f & 63, q = f >> 6, nt = q % NT, ks = q / NT;
-                const int co = 16 * nt + (l & 15), kk = 32 * ks + 8 * (l >> 4);
-                uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                if (kk < 9 * CC && co < a.Cout) {
-                    const int tap = kk / CC, cl = kk - tap * CC;
-                    v = *reinterpret_cast<const uint4*>(a.wt + (size_t)co * K + tap * a.Cin + c0 + cl);
-                }
-                wfrag[f] = v;
-            }
+        return v;
+    };
+    uint4 pf[PF];
+    uint4 wpf[WPF > 0 ? WPF : 1];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            pf[k] = (HALO_ITEMS % 256 == 0 || i < HALO_ITEMS) ? halo_item(c0, i) : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < WPF; ++k) {
+            const int f = (int)threadIdx.x + 256 * k;
+            wpf[k] = (L::W_U4 % 256 == 0 || f < L::W_U4) ? w_item(c0, f) : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    for (int c0 = 0; c0 < a.Cin; c0 += CC) {
+        fetch(c0);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            if (HALO_ITEMS % 256 == 0 || i < HALO_ITEMS)
+                *reinterpret_cast<uint4*>(lds + (i / GROUPS) * PST + 8 * (i % GROUPS)) = pf[k];
+        }
+#pragma unroll
+        for (int k = 0; k < WPF; ++k) {
+            const int f = (int)threadIdx.x + 256 * k;
+            if (L::W_U4 % 256 == 0 || f < L::W_U4) wfrag[f] = wpf[k];
         }
         __syncthreads();
         // streamed weights: fragments of K-step ks loaded while the MFMAs of the step before run
@@ -344,28 +397,38 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
 // A fragment read from LDS feeds only NT MFMAs, so these layers wait on LDS reads.  Here each wave owns R
 // output rows x 16 pixels and walks the R + 2 halo rows: the fragment of halo row h and horizontal tap dx is
 // read once and serves the vertical taps dy = 0, 1, 2 of output rows h - dy (up to 3 NT MFMAs per read).
-// Workgroup: 4 waves side by side (tile R rows x 64 columns); per chunk of 32 input channels the halo is
-// staged in LDS (zero outside the image, the same two-source loader as k_conv_lds) and the chunk's
-// weights, 9 taps x NT fragments, stay in registers.  Each output row still sums its taps in the order
-// tap = 3 dy + dx within a chunk, as k_conv_lds does with 32-channel chunks.
+// Workgroup: 4 waves side by side (tile R rows x 64 columns); the chunk's weights, 9 taps x NT fragments,
+// stay in registers.  Each output row still sums its taps in the order tap = 3 dy + dx within a chunk, as
+// k_conv_lds does with 32-channel chunks.
+//
+// Per chunk of 32 input channels the (R + 2) x 66-pixel halo is staged in LDS, 64 bytes per pixel with no
+// padding: the four 16-byte channel groups of halo pixel hx sit in the slots g ^ ((hx >> 1) & 3), so that
+// the A-fragment reads (16 consecutive pixels x 4 groups) hit distinct banks in every group of 8 lanes.
+// The 64 interior pixels of a halo row are read from memory straight into LDS (global_load_lds_dwordx4: one
+// instruction per wave and row, lane l landing at the wave's base + 16 l, so lane l fetches the channel
+// group that the swizzle puts in its slot; pixels outside the image read g_zero_group); the two edge
+// pixels of each row pass through registers.  No halo data occupies vector registers.
 template <int R, int NT>
 struct ConvRows {
-    static constexpr int TW = 64, HW = TW + 2, HR = R + 2, CC = 32, PST = CC + 8;
-    static constexpr int HALO_U4 = (HR * HW * PST * 2 + 15) / 16;
+    static constexpr int TW = 64, HW = TW + 2, HR = R + 2, CC = 32, PIX_BYTES = CC * 2;
     static constexpr size_t bytes()
     {
-        const size_t in = (size_t)HALO_U4 * 16, out = (size_t)4 * R * 16 * 16 * NT * 2;
+        const size_t in = (size_t)HR * HW * PIX_BYTES, out = (size_t)4 * R * 16 * 16 * NT * 2;
         return in > out ? in : out;
     }
 };
 
-template <int R, int NT>
-__global__ __launch_bounds__(256) void k_conv_rows(ConvArgs a)
+__device__ inline int rows_slot_offset(int hx, int g) { return (g ^ ((hx >> 1) & 3)) << 4; }
+
+template <int R, int NT, int OCC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void k_conv_rows(ConvArgs a)
 {
     extern __shared__ uint4 conv_lds[];
     using L = ConvRows<R, NT>;
-    constexpr int TW = L::TW, HW = L::HW, HR = L::HR, PST = L::PST, CC = L::CC;
+    constexpr int TW = L::TW, HW = L::HW, HR = L::HR, CC = L::CC, PB = L::PIX_BYTES;
+    static_assert(8 * HR <= 256, "edge items beyond one per thread");
     uint16_t* lds = reinterpret_cast<uint16_t*>(conv_lds);
+    char* ldsb = reinterpret_cast<char*>(conv_lds);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + R - 1) / R;
     int tt = xcd_tile(blockIdx.x, gridDim.x);
@@ -375,7 +438,21 @@ __global__ __launch_bounds__(256) void k_conv_rows(ConvArgs a)
     const int x0 = tx * TW, y0 = ty * R;
     const int r = lane & 15, g = lane >> 4;
     const int K = 9 * a.Cin;
-    const int Cs = a.Cin - a.Ca;
+    // this lane's interior halo group: pixel hx = 1 + 16 wave + (lane >> 2) of every halo row, LDS slot lane & 3
+    const int d_hx = 1 + 16 * wave + (lane >> 2);
+    const int d_x = x0 - 1 + d_hx;
+    const int d_g = (lane & 3) ^ ((d_hx >> 1) & 3);
+    // this thread's edge group (threads below 8 HR): halo row t >> 3, pixel 0 or HW - 1, group t & 3
+    const int t = threadIdx.x;
+    const int e_hy = t >> 3, e_hx = ((t >> 2) & 1) ? HW - 1 : 0, e_g = t & 3;
+    const int e_off = (e_hy * HW + e_hx) * PB + rows_slot_offset(e_hx, e_g);
+    // byte offsets of this lane's A fragment (pixel 16 wave + r + dx, group g) within a halo row
+    int a_off[3];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+        const int hx = 16 * wave + r + dx;
+        a_off[dx] = hx * PB + rows_slot_offset(hx, g);
+    }
     f32x4 acc[R][NT];
 #pragma unroll
     for (int o = 0; o < R; ++o)
@@ -393,32 +470,24 @@ __global__ __launch_bounds__(256) void k_conv_rows(ConvArgs a)
                 const int co = 16 * nt + r;
                 B[tap][nt] = co < a.Cout ? load8(a.wt + (size_t)co * K + tap * a.Cin + c0 + 8 * g) : zero;
             }
-        __syncthreads();
-        constexpr int GROUPS = CC / 8;
-        for (int i = threadIdx.x; i < HR * HW * GROUPS; i += 256) {
-            const int gg = i % GROUPS, pix = i / GROUPS;
-            const int hx = pix % HW, hy = pix / HW;
-            const int y = y0 - 1 + hy, x = x0 - 1 + hx;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
-                const int ci = c0 + 8 * gg;
-                if (a.in2 == nullptr)
-                    v = *reinterpret_cast<const uint4*>(a.in + ((size_t)(n * a.H + y) * a.W + x) * a.Cin + ci);
-                else if (ci < a.Ca)
-                    v = *reinterpret_cast<const uint4*>(
-                        a.in + ((size_t)(n * (a.H / 2) + y / 2) * (a.W / 2) + x / 2) * a.Ca + ci);
-                else
-                    v = *reinterpret_cast<const uint4*>(a.in2 + ((size_t)(n * a.H + y) * a.W + x) * Cs + (ci - a.Ca));
-            }
-            *reinterpret_cast<uint4*>(lds + pix * PST + 8 * gg) = v;
+        __syncthreads();   // every wave is done with the previous chunk's halo
+#pragma unroll
+        for (int hy = 0; hy < HR; ++hy) {
+            const int y = y0 - 1 + hy;
+            const bool ok = (unsigned)y < (unsigned)a.H && d_x < a.W;
+            const void* src = ok ? (const void*)group_ptr(a, n, y, d_x, c0 + 8 * d_g) : (const void*)&g_zero_group;
+            __builtin_amdgcn_global_load_lds(src, ldsb + (hy * HW + 1 + 16 * wave) * PB, 16, 0, 0);
         }
+        uint4 ev = make_uint4(0u, 0u, 0u, 0u);
+        if (t < 8 * HR) ev = halo_group(a, n, y0 - 1 + e_hy, x0 - 1 + e_hx, c0 + 8 * e_g);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the direct-to-LDS loads have landed
+        if (t < 8 * HR) *reinterpret_cast<uint4*>(ldsb + e_off) = ev;
         __syncthreads();
 #pragma unroll
         for (int h = 0; h < HR; ++h)
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
-                const bf16x8 A = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const uint4*>(lds + (h * HW + 16 * wave + r + dx) * PST + 8 * g));
+                const bf16x8 A = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(ldsb + h * HW * PB + a_off[dx]));
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
                     const int o = h - dy;
@@ -1066,21 +1135,21 @@ inline unsigned nb(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-template <int MT, int NT, int CC, bool SW>
+template <int MT, int NT, int CC, bool SW, int OCC>
 void launch_conv_lds(const ConvArgs& a, hipStream_t st)
 {
     constexpr int TW = 16 * MT;
     const size_t tiles = (size_t)a.N * ((a.H + 3) / 4) * ((a.W + TW - 1) / TW);
     const size_t lds = ConvLds<MT, NT, CC, SW>::bytes();
-    hipLaunchKernelGGL((k_conv_lds<MT, NT, CC, SW>), dim3((unsigned)tiles), dim3(256), lds, st, a);
+    hipLaunchKernelGGL((k_conv_lds<MT, NT, CC, SW, OCC>), dim3((unsigned)tiles), dim3(256), lds, st, a);
 }
 
-template <int R, int NT>
+template <int R, int NT, int OCC>
 void launch_conv_rows(const ConvArgs& a, hipStream_t st)
 {
     const size_t tiles = (size_t)a.N * ((a.H + R - 1) / R) * ((a.W + 63) / 64);
     const size_t lds = ConvRows<R, NT>::bytes();
-    hipLaunchKernelGGL((k_conv_rows<R, NT>), dim3((unsigned)tiles), dim3(256), lds, st, a);
+    hipLaunchKernelGGL((k_conv_rows<R, NT, OCC>), dim3((unsigned)tiles), dim3(256), lds, st, a);
 }
 
 void unet_conv3x3(const ConvArgs& a, hipStream_t st)
@@ -1100,16 +1169,16 @@ void unet_conv3x3(const ConvArgs& a, hipStream_t st)
                       ConvLds<2, 12, 8, true>::bytes() <= 65536,
                   "convolution LDS beyond 64 KB");
     switch (cfg) {
-    case 208: launch_conv_lds<4, 2, 8, false>(a, st); return;
+    case 208: launch_conv_lds<4, 2, 8, false, RC_OCC_E1A>(a, st); return;
     case 232:
     case 264:
-        if (nt == 1) launch_conv_rows<RC_CONV_ROWS, 1>(a, st);
-        else launch_conv_rows<RC_CONV_ROWS, 2>(a, st);
+        if (nt == 1) launch_conv_rows<RC_CONV_ROWS, 1, RC_OCC_ROWS + 1>(a, st);
+        else launch_conv_rows<RC_CONV_ROWS, 2, RC_OCC_ROWS>(a, st);
         return;
-    case 416: launch_conv_lds<4, 4, 16, true>(a, st); return;
-    case 616: launch_conv_lds<2, 6, 16, true>(a, st); return;
-    case 816: launch_conv_lds<2, 8, 16, true>(a, st); return;
-    case 1208: launch_conv_lds<2, 12, 8, true>(a, st); return;
+    case 416: launch_conv_lds<4, 4, 16, true, RC_OCC_416>(a, st); return;
+    case 616: launch_conv_lds<2, 6, 16, true, RC_OCC_816>(a, st); return;
+    case 816: launch_conv_lds<2, 8, 16, true, RC_OCC_816>(a, st); return;
+    case 1208: launch_conv_lds<2, 12, 8, true, 1>(a, st); return;
     default: break;
     }
     unet_conv3x3_direct(a, st);
