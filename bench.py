@@ -671,6 +671,8 @@ def main():
                     "primary_tris": round(own["primary_tris"] / max(own["primary_rays"], 1), 2),
                     "shadow_nodes": round(own_nodes, 2), "shadow_tris": round(own_tris, 2),
                     "counted_by": "own path (per-lane traversal counters)",
+                    "wave_union_primary_nodes": round(st["primary_nodes"] / max(st["primary_rays"], 1), 2),
+                    "wave_union_primary_tris": round(st["primary_tris"] / max(st["primary_rays"], 1), 2),
                     "wave_union_shadow_nodes": round(st["shadow_nodes"] / sh_rays, 2),
                     "wave_union_shadow_tris": round(st["shadow_tris"] / sh_rays, 2)},
         "bvh": {"method": "binned SAH (32 bins, leaves <= 4, node cost 4) built on the GPU",
