@@ -541,6 +541,8 @@ def main():
     ap.add_argument("--dyn-frames", type=int, default=24,
                     help="frames of the moving-body comparison of flat refit and two-level rebuild (0 = skip)")
     ap.add_argument("--batch", type=int, default=1, help="run the 64-view / 4-scene batched leg (autotuned, graph replay)")
+    ap.add_argument("--profile-denoiser-train", type=int, default=0,
+                    help="time N training steps of the denoiser alone (batch 8 x crop^2) and exit")
     ap.add_argument("--profile-denoiser", type=int, default=0,
                     help="instead of rendering, run this many BF16 denoiser inferences of one 1080p view (twice: "
                          "warm-up, timed) and one FP32-copy inference")
@@ -569,6 +571,28 @@ def main():
 
     from paper_2410_05095_amd import _native as N
     from paper_2410_05095_amd import scenegen as sg
+
+    if args.profile_denoiser_train:
+        # the denoiser's training step alone (for profilers): batch 8 of crops of --denoiser-crop pixels, random
+        # features, targets and an all-ones mask
+        ctx = N.Context(0)
+        den = N.Denoiser(ctx, seed=args.seed)
+        g = torch.Generator(device="cuda").manual_seed(args.seed)
+        S = args.denoiser_crop
+        feat = torch.rand((8, S, S, 8), device="cuda", generator=g).to(torch.bfloat16).contiguous()
+        tgt = torch.rand((8, S, S), device="cuda", generator=g).contiguous()
+        msk = torch.ones((8, S, S), device="cuda")
+        for _ in range(2):
+            den.train_step(feat, tgt, msk, 1e-4, want_loss=False)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(args.profile_denoiser_train):
+            den.train_step(feat, tgt, msk, 1e-4, want_loss=False)
+        ev[1].record()
+        torch.cuda.synchronize()
+        print(json.dumps({"denoiser_train_step_ms": ev[0].elapsed_time(ev[1]) / args.profile_denoiser_train,
+                          "batch": 8, "crop": S}), flush=True)
+        return
 
     if args.profile_denoiser:
         # the denoiser alone (for profilers): BF16 inference of a 1920x1080 view, then the FP32 copy

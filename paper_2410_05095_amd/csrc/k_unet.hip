@@ -772,38 +772,71 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(WgradArgs a, int tiles_per_ch
     for (int t = t_begin; t < t_end; ++t) {
         const int tx = t % tiles_x, rest = t / tiles_x, ty = rest % tiles_y, n = rest / tiles_y;
         const int x0 = tx * TW, y0 = ty * R;
-        __syncthreads();
-        for (int i = threadIdx.x; i < R * TW * c8_out; i += 192) {
-            const int c8 = i % c8_out, px = i / c8_out;
-            const int y = y0 + px / TW, x = x0 + px % TW;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (y < a.H && x < a.W) v = *reinterpret_cast<const uint4*>(a.g + ((size_t)(n * a.H + y) * a.W + x) * a.Cout + 8 * c8);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        // Staging, transposed to [channel][pixel] in registers: a thread holds the 8-channel groups of 8 (10)
+        // consecutive pixels and writes, for each of the 8 channels, the 8 pixels as one 16-byte LDS store
+        // (two pixels per 32-bit word); the input's dx-shifted copies come from the same 10 registers.  All
+        // loads of an item are in flight together (clamped addresses, zeros substituted afterwards).
+        constexpr int X_ITEMS = HRW * (TW / 8) * (CIN_T / 8), G_ITEMS = R * (TW / 8) * (COUT / 8);
+        static_assert(X_ITEMS <= 192, "one input item per thread");
+        auto pack_ch = [](const uint4& lo, const uint4& hi, int e) -> uint32_t {
+            const uint32_t wl = e < 2 ? lo.x : e < 4 ? lo.y : e < 6 ? lo.z : lo.w;
+            const uint32_t wh = e < 2 ? hi.x : e < 4 ? hi.y : e < 6 ? hi.z : hi.w;
+            return (e & 1) ? ((wl >> 16) | (wh & 0xFFFF0000u)) : ((wl & 0xFFFFu) | (wh << 16));
+        };
+        uint4 xv[10];
+        int x_c8 = 0, x_q = 0, x_row = 0;
+        const bool x_item = (int)threadIdx.x < X_ITEMS;
+        if (x_item) {
+            x_c8 = threadIdx.x % (CIN_T / 8);
+            const int rest = threadIdx.x / (CIN_T / 8);
+            x_q = rest % (TW / 8);
+            x_row = rest / (TW / 8);
+            const int y = y0 - 1 + x_row, ci = ci0 + 8 * x_c8;
+            const bool rowok = y >= 0 && y < a.H && ci < a.Cin;
+            const int yc = min(max(y, 0), a.H - 1), cic = ci < a.Cin ? ci : 0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                gs[(8 * c8 + 2 * e) * GS_CO + px] = (uint16_t)(w[e] & 0xFFFFu);
-                gs[(8 * c8 + 2 * e + 1) * GS_CO + px] = (uint16_t)(w[e] >> 16);
+            for (int k = 0; k < 10; ++k) {
+                const int x = x0 - 1 + 8 * x_q + k;
+                const int xc = min(max(x, 0), a.W - 1);
+                const uint4 v = *reinterpret_cast<const uint4*>(a.x + ((size_t)(n * a.H + yc) * a.W + xc) * a.Cin + cic);
+                xv[k] = (rowok && x >= 0 && x < a.W) ? v : make_uint4(0u, 0u, 0u, 0u);
             }
         }
-        for (int i = threadIdx.x; i < HRW * HC * (CIN_T / 8); i += 192) {
-            const int c8 = i % (CIN_T / 8), hp = i / (CIN_T / 8);
-            const int hc = hp % HC, hrow = hp / HC;
-            const int y = y0 - 1 + hrow, x = x0 - 1 + hc, ci = ci0 + 8 * c8;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (y >= 0 && y < a.H && x >= 0 && x < a.W && ci < a.Cin)
-                v = *reinterpret_cast<const uint4*>(a.x + ((size_t)(n * a.H + y) * a.W + x) * a.Cin + ci);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        auto g_load = [&](int it, uint4* gv) {
+            const int c8 = it % c8_out, rest = it / c8_out, q = rest % (TW / 8), row = rest / (TW / 8);
+            const int y = y0 + row, yc = min(y, a.H - 1);
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const int c = hc - dx;
-                if (c < 0 || c >= TW) continue;
-                uint16_t* dst = xs + dx * XS_DX + (8 * c8) * XS_CI + hrow * TW + c;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    dst[(2 * e) * XS_CI] = (uint16_t)(w[e] & 0xFFFFu);
-                    dst[(2 * e + 1) * XS_CI] = (uint16_t)(w[e] >> 16);
-                }
+            for (int k = 0; k < 8; ++k) {
+                const int x = x0 + 8 * q + k, xc = min(x, a.W - 1);
+                const uint4 v = *reinterpret_cast<const uint4*>(a.g + ((size_t)(n * a.H + yc) * a.W + xc) * a.Cout + 8 * c8);
+                gv[k] = (y < a.H && x < a.W) ? v : make_uint4(0u, 0u, 0u, 0u);
             }
+        };
+        auto g_store = [&](int it, const uint4* gv) {
+            const int c8 = it % c8_out, rest = it / c8_out, q = rest % (TW / 8), row = rest / (TW / 8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                *reinterpret_cast<uint4*>(gs + (8 * c8 + e) * GS_CO + row * TW + 8 * q) =
+                    make_uint4(pack_ch(gv[0], gv[1], e), pack_ch(gv[2], gv[3], e), pack_ch(gv[4], gv[5], e),
+                               pack_ch(gv[6], gv[7], e));
+        };
+        uint4 gv[8];
+        const bool g_first = (int)threadIdx.x < G_ITEMS;
+        if (g_first) g_load(threadIdx.x, gv);
+        __syncthreads();   // every wave is done with the previous tile's operands
+        if (x_item) {
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    *reinterpret_cast<uint4*>(xs + dx * XS_DX + (8 * x_c8 + e) * XS_CI + x_row * TW + 8 * x_q) =
+                        make_uint4(pack_ch(xv[dx], xv[dx + 1], e), pack_ch(xv[dx + 2], xv[dx + 3], e),
+                                   pack_ch(xv[dx + 4], xv[dx + 5], e), pack_ch(xv[dx + 6], xv[dx + 7], e));
+        }
+        if (g_first) g_store(threadIdx.x, gv);
+        for (int it = threadIdx.x + 192; it < G_ITEMS; it += 192) {
+            g_load(it, gv);
+            g_store(it, gv);
         }
         __syncthreads();
 #pragma unroll
