@@ -411,14 +411,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
 template <int R, int NT>
 struct ConvRows {
     static constexpr int TW = 64, HW = TW + 2, HR = R + 2, CC = 32, PIX_BYTES = CC * 2;
+    static constexpr int W_OFF = HR * HW * PIX_BYTES;   // then the chunk's 9 NT weight fragments, 1 KB each
     static constexpr size_t bytes()
     {
-        const size_t in = (size_t)HR * HW * PIX_BYTES, out = (size_t)4 * R * 16 * 16 * NT * 2;
+        const size_t in = (size_t)W_OFF + 9 * NT * 1024, out = (size_t)4 * R * 16 * 16 * NT * 2;
         return in > out ? in : out;
     }
 };
 
 __device__ inline int rows_slot_offset(int hx, int g) { return (g ^ ((hx >> 1) & 3)) << 4; }
+
+// the 9 NT weight fragments of chunk c0 straight into LDS at `dst` (fragment f = NT tap + nt, 1 KB each; wave w
+// issues every 4th); lane (r, g) of fragment (tap, nt) holds output channel 16 nt + r, input channels
+// c0 + 8 g .. + 8 of that tap, zero beyond Cout
+template <int NT>
+__device__ __attribute__((always_inline)) inline void rows_weights_to_lds(const ConvArgs& a, int c0, char* dst, int wave,
+                                                                          int r, int g)
+{
+    const int K = 9 * a.Cin;
+    for (int f = wave; f < 9 * NT; f += 4) {
+        const int tap = f / NT, co = 16 * (f % NT) + r;
+        const void* src = co < a.Cout ? (const void*)(a.wt + (size_t)co * K + tap * a.Cin + c0 + 8 * g)
+                                      : (const void*)&g_zero_group;
+        __builtin_amdgcn_global_load_lds(src, dst + f * 1024, 16, 0, 0);
+    }
+}
 
 template <int R, int NT, int OCC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void k_conv_rows(ConvArgs a)
@@ -460,17 +477,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
         for (int nt = 0; nt < NT; ++nt) acc[o][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero = {};
     for (int c0 = 0; c0 < a.Cin; c0 += CC) {
-        // weight fragment (tap, nt) of lane l: output channel 16 nt + (l & 15), input channels
-        // c0 + 8 (l >> 4) .. + 8 of that tap
-        bf16x8 B[9][NT];
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = 16 * nt + r;
-                B[tap][nt] = co < a.Cout ? load8(a.wt + (size_t)co * K + tap * a.Cin + c0 + 8 * g) : zero;
-            }
-        __syncthreads();   // every wave is done with the previous chunk's halo
+        __syncthreads();   // every wave is done with the previous chunk's halo and weights
+        // weight fragment f = NT tap + nt, read once per workgroup straight into LDS: lane l holds output
+        // channel 16 nt + (l & 15), input channels c0 + 8 (l >> 4) .. + 8 of that tap
+        rows_weights_to_lds<NT>(a, c0, ldsb + L::W_OFF, wave, r, g);
 #pragma unroll
         for (int hy = 0; hy < HR; ++hy) {
             const int y = y0 - 1 + hy;
@@ -483,6 +493,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the direct-to-LDS loads have landed
         if (t < 8 * HR) *reinterpret_cast<uint4*>(ldsb + e_off) = ev;
         __syncthreads();
+        bf16x8 B[9][NT];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                B[tap][nt] = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4*>(ldsb + L::W_OFF + (tap * NT + nt) * 1024 + lane * 16));
 #pragma unroll
         for (int h = 0; h < HR; ++h)
 #pragma unroll
