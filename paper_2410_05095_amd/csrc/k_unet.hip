@@ -212,7 +212,7 @@ struct ConvLds {
     static constexpr int W_U4 = SW ? KS * NT * 64 : 0;         // weight fragments of one chunk
     static constexpr size_t bytes()
     {
-        const size_t in = (size_t)(HALO_U4 + W_U4) * 16, out = (size_t)4 * TW * 16 * NT * 2;
+        const size_t in = (size_t)(HALO_U4 + W_U4) * 16, out = (size_t)4 * TW * (16 * NT + 8) * 2;
         return in > out ? in : out;
     }
 };
@@ -339,9 +339,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
     // bf16 rows of a [pixel][channel] tile, then the tile leaves in 16-byte chunks, consecutive pixels of
     // one image row being contiguous in NHWC.
     constexpr int TC = 16 * NT;                 // channels of the tile
+    constexpr int TS = TC + 8;                  // tile row stride (padding spreads the 4 row groups over the banks)
     constexpr int TPX = 16 * MT;                // pixels per wave
     __syncthreads();                            // every wave is done with the halo
-    uint16_t* tile = lds + (size_t)wave * TPX * TC;
+    uint16_t* tile = lds + (size_t)wave * TPX * TS;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int co = 16 * nt + r;
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
             for (int i = 0; i < 4; ++i) {
                 float v = acc[mt][nt][i] + b;
                 if (a.relu) v = fmaxf(v, 0.0f);
-                tile[(16 * mt + 4 * g + i) * TC + co] = f2bf(v);
+                tile[(16 * mt + 4 * g + i) * TS + co] = f2bf(v);
             }
     }
     __syncthreads();
@@ -364,10 +365,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
             const int po = pp / (TPX / 2), px2 = pp % (TPX / 2);
             const int y = y0 + 2 * po, x = x0 + 2 * px2;
             if (x >= a.W || y >= a.H) continue;
-            const uint16_t* t0 = lds + (size_t)(2 * po) * TPX * TC + (2 * px2) * TC + 8 * c8;
-            const uint4 v = pool4(*reinterpret_cast<const uint4*>(t0), *reinterpret_cast<const uint4*>(t0 + TC),
-                                  *reinterpret_cast<const uint4*>(t0 + TPX * TC),
-                                  *reinterpret_cast<const uint4*>(t0 + TPX * TC + TC));
+            const uint16_t* t0 = lds + (size_t)(2 * po) * TPX * TS + (2 * px2) * TS + 8 * c8;
+            const uint4 v = pool4(*reinterpret_cast<const uint4*>(t0), *reinterpret_cast<const uint4*>(t0 + TS),
+                                  *reinterpret_cast<const uint4*>(t0 + TPX * TS),
+                                  *reinterpret_cast<const uint4*>(t0 + TPX * TS + TS));
             *reinterpret_cast<uint4*>(a.pool_out + ((size_t)(n * Hp + y / 2) * Wp + x / 2) * a.Cout + 8 * c8) = v;
         }
     }
@@ -378,7 +379,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
         const int px = q / c8n, c8 = q - px * c8n;
         const int x = x0 + px;
         if (x >= a.W) continue;
-        uint4 v = *reinterpret_cast<const uint4*>(tile + px * TC + 8 * c8);
+        uint4 v = *reinterpret_cast<const uint4*>(tile + px * TS + 8 * c8);
         const size_t o = ((size_t)(n * a.H + y) * a.W + x) * a.Cout + 8 * c8;
         if (a.mask) {
             float f[8], mk[8];
@@ -414,7 +415,7 @@ struct ConvRows {
     static constexpr int W_OFF = HR * HW * PIX_BYTES;   // then the chunk's 9 NT weight fragments, 1 KB each
     static constexpr size_t bytes()
     {
-        const size_t in = (size_t)W_OFF + 9 * NT * 1024, out = (size_t)4 * R * 16 * 16 * NT * 2;
+        const size_t in = (size_t)W_OFF + 9 * NT * 1024, out = (size_t)4 * R * 16 * (16 * NT + 8) * 2;
         return in > out ? in : out;
     }
 };
@@ -519,8 +520,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
     }
     // epilogue through LDS, as in k_conv_lds: per wave R rows of 16 pixels x 16 NT channels
     constexpr int TC = 16 * NT;
+    constexpr int TS = TC + 8;                  // tile row stride (padding spreads the 4 row groups over the banks)
     __syncthreads();
-    uint16_t* tile = lds + (size_t)wave * R * 16 * TC;
+    uint16_t* tile = lds + (size_t)wave * R * 16 * TS;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int co = 16 * nt + r;
@@ -531,7 +533,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
             for (int i = 0; i < 4; ++i) {
                 float v = acc[o][nt][i] + b;
                 if (a.relu) v = fmaxf(v, 0.0f);
-                tile[(o * 16 + 4 * g + i) * TC + co] = f2bf(v);
+                tile[(o * 16 + 4 * g + i) * TS + co] = f2bf(v);
             }
     }
     __syncthreads();
@@ -543,7 +545,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
             if (x >= a.W || y >= a.H) continue;
             float f[32];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) unpack8(*reinterpret_cast<const uint4*>(tile + px * TC + 8 * q), f + 8 * q);
+            for (int q = 0; q < 4; ++q) unpack8(*reinterpret_cast<const uint4*>(tile + px * TS + 8 * q), f + 8 * q);
             a.head_out[(size_t)(n * a.H + y) * a.W + x] = head_value(f, a.head_w, a.head_b);
         }
     } else {
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
             const int px = q / c8n, c8 = q - px * c8n;
             const int o = px / 16, x = x0 + 16 * wave + (px % 16), y = y0 + o;
             if (x >= a.W || y >= a.H) continue;
-            uint4 v = *reinterpret_cast<const uint4*>(tile + px * TC + 8 * c8);
+            uint4 v = *reinterpret_cast<const uint4*>(tile + px * TS + 8 * c8);
             const size_t off = ((size_t)(n * a.H + y) * a.W + x) * a.Cout + 8 * c8;
             if (a.mask) {
                 float f[8], mk[8];
@@ -572,10 +574,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) void
             const int po = pp / 8, px2 = pp % 8;
             const int y = y0 + 2 * po, x = x0 + 16 * wave + 2 * px2;
             if (x >= a.W || y >= a.H) continue;
-            const uint16_t* t0 = tile + (2 * po * 16 + 2 * px2) * TC + 8 * c8;
-            const uint4 v = pool4(*reinterpret_cast<const uint4*>(t0), *reinterpret_cast<const uint4*>(t0 + TC),
-                                  *reinterpret_cast<const uint4*>(t0 + 16 * TC),
-                                  *reinterpret_cast<const uint4*>(t0 + 17 * TC));
+            const uint16_t* t0 = tile + (2 * po * 16 + 2 * px2) * TS + 8 * c8;
+            const uint4 v = pool4(*reinterpret_cast<const uint4*>(t0), *reinterpret_cast<const uint4*>(t0 + TS),
+                                  *reinterpret_cast<const uint4*>(t0 + 16 * TS),
+                                  *reinterpret_cast<const uint4*>(t0 + 17 * TS));
             *reinterpret_cast<uint4*>(a.pool_out + ((size_t)(n * Hp + y / 2) * Wp + x / 2) * a.Cout + 8 * c8) = v;
         }
     }
@@ -803,11 +805,13 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(WgradArgs a, int tiles_per_ch
         uint4 xv[10];
         int x_c8 = 0, x_q = 0, x_row = 0;
         const bool x_item = (int)threadIdx.x < X_ITEMS;
+        // consecutive threads take consecutive 8-pixel groups q, so that the 16-byte stores of 8 neighbouring
+        // lanes (one channel row, q = 0..7) cover all LDS banks
         if (x_item) {
-            x_c8 = threadIdx.x % (CIN_T / 8);
-            const int rest = threadIdx.x / (CIN_T / 8);
-            x_q = rest % (TW / 8);
-            x_row = rest / (TW / 8);
+            x_q = threadIdx.x % (TW / 8);
+            const int rest = threadIdx.x / (TW / 8);
+            x_c8 = rest % (CIN_T / 8);
+            x_row = rest / (CIN_T / 8);
             const int y = y0 - 1 + x_row, ci = ci0 + 8 * x_c8;
             const bool rowok = y >= 0 && y < a.H && ci < a.Cin;
             const int yc = min(max(y, 0), a.H - 1), cic = ci < a.Cin ? ci : 0;
@@ -820,7 +824,7 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(WgradArgs a, int tiles_per_ch
             }
         }
         auto g_load = [&](int it, uint4* gv) {
-            const int c8 = it % c8_out, rest = it / c8_out, q = rest % (TW / 8), row = rest / (TW / 8);
+            const int q = it % (TW / 8), rest = it / (TW / 8), c8 = rest % c8_out, row = rest / c8_out;
             const int y = y0 + row, yc = min(y, a.H - 1);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -830,7 +834,7 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(WgradArgs a, int tiles_per_ch
             }
         };
         auto g_store = [&](int it, const uint4* gv) {
-            const int c8 = it % c8_out, rest = it / c8_out, q = rest % (TW / 8), row = rest / (TW / 8);
+            const int q = it % (TW / 8), rest = it / (TW / 8), c8 = rest % c8_out, row = rest / c8_out;
 #pragma unroll
             for (int e = 0; e < 8; ++e)
                 *reinterpret_cast<uint4*>(gs + (8 * c8 + e) * GS_CO + row * TW + 8 * q) =
