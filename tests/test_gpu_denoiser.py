@@ -125,6 +125,39 @@ def test_forward_full_tiling_matches_oracle(ctx, n, h, w):
     assert err32.max() < 2e-5
 
 
+def test_forward_1080p_sampled(ctx):
+    """The benchmark's launch: BF16 inference of a whole 1x1080x1920 view, checked at sampled pixels (corners,
+    edge midpoints, centre, two random points).  Around each, the oracle evaluates a 96x96 crop whose origin is
+    a multiple of 4 (so the pooling and upsampling grids line up) and lies at the image edge or at least 44
+    pixels from the sample; the network's receptive field reaches about 26 pixels, so the crop's output at the
+    8x8 block around the sample is the full image's.  Same bound as the tiled test."""
+    from paper_2410_05095_amd import _native as N
+    from tests import unet_flips as F
+    den = N.Denoiser(ctx, seed=1)
+    p = oracle_params(3)
+    den.set_params(U.flat(p).astype(np.float32))
+    H, W, C = 1080, 1920, 96
+    x, t, m = random_batch(1080, 1, H, W)
+    xd, _, _ = to_dev(ctx, x, t, m)
+    y = den.infer(xd).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(5)
+    pts = [(0, 0), (H - 1, W - 1), (0, W // 2), (H // 2, 0), (H // 2, W // 2)]
+    pts += [(int(rng.integers(0, H)), int(rng.integers(0, W))) for _ in range(2)]
+    for py, px in pts:
+        oy = min(max((py - C // 2) // 4 * 4, 0), H - C)
+        ox = min(max((px - C // 2) // 4 * 4, 0), W - C)
+        crop = x[:, oy:oy + C, ox:ox + C]
+        yo, _ = U.forward(p, crop, bf16=True)
+        yo32, _ = U.forward(p, crop, bf16=True, conv=F.conv3x3_f32)
+        by, bx = min(max(py - 4, 0), H - 8), min(max(px - 4, 0), W - 8)
+        g = y[:, by:by + 8, bx:bx + 8]
+        o = yo[:, by - oy:by - oy + 8, bx - ox:bx - ox + 8]
+        flip = np.abs(yo32 - yo)[:, by - oy:by - oy + 8, bx - ox:bx - ox + 8]
+        err = np.abs(g - o)
+        say(f"[unet fwd 1080p at ({py},{px}), crop at ({oy},{ox})] max {err.max():.2e} (flip scale {flip.max():.2e})")
+        assert err.max() <= max(2e-3, 2 * flip.max())
+
+
 def test_fused_inference_equals_training_forward(ctx):
     """Inference computes the 2x2 pools and the head inside the convolution epilogues and writes the head
     straight into the output; the training step's forward stores every activation and runs the separate
