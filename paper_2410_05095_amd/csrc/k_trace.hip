@@ -18,6 +18,9 @@
 namespace {
 
 constexpr int BLOCK = RC_TRACE_BLOCK;
+#ifndef RC_SKIP_EMPTY
+#define RC_SKIP_EMPTY 1   // the wave walk skips the slab tests of empty child slots 2 and 3
+#endif
 constexpr int SL = RC_STACK_LDS;
 constexpr int REFILL_AT = 40;    // refill once a wave has at most this many busy lanes
 constexpr uint32_t ITEM_CHUNK = 256;
@@ -327,6 +330,24 @@ __device__ inline void wave_keys_uniform(const rc_v4f& nx, const rc_v4f& fx, con
     }
 }
 
+// As wave_keys_uniform, for a node whose child words `chw` (wave-uniform) are known: slots 2 and 3 that hold no
+// child get a miss key without their slab tests (a uniform branch), since an empty slot's box never hits.
+__device__ inline void wave_keys_uniform_skip(const rc_v4f& nx, const rc_v4f& fx, const rc_v4f& ny, const rc_v4f& fy,
+                                              const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray, float bound,
+                                              const uint32_t chw[4], uint32_t key[4])
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (RC_SKIP_EMPTY && c >= 2 && chw[c] == RC_EMPTY_CHILD) {
+            key[c] = RC_KEY_MISS | (uint32_t)c;
+            continue;
+        }
+        float t0;
+        const bool hit = rc_slab(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], bound, t0);
+        key[c] = wave_key(hit, t0, (uint32_t)c);
+    }
+}
+
 __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const rc_v4f& ly, const rc_v4f& hy,
                                        const rc_v4f& lz, const rc_v4f& hz, const TravRay& ray, float bound,
                                        uint32_t key[4])
@@ -424,10 +445,13 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
                 const rc_v8f X = *(rc_const_v8f*)(const void*)np, Y = *(rc_const_v8f*)(const void*)(np + 32),
                              Z = *(rc_const_v8f*)(const void*)(np + 64);
                 const rc_v4f lx = X.lo, hx = X.hi, ly = Y.lo, hy = Y.hi, lz = Z.lo, hz = Z.hi;
-                if constexpr (OCT < 8)
-                    wave_keys_uniform((OCT & 1) ? hx : lx, (OCT & 1) ? lx : hx, (OCT & 2) ? hy : ly,
-                                      (OCT & 2) ? ly : hy, (OCT & 4) ? hz : lz, (OCT & 4) ? lz : hz, ray, bound, key);
-                else
+                if constexpr (OCT < 8) {
+                    const rc_v4u cw = *(rc_const_v4u*)(const void*)(np + 96);
+                    const uint32_t cws[4] = {cw[0], cw[1], cw[2], cw[3]};
+                    wave_keys_uniform_skip((OCT & 1) ? hx : lx, (OCT & 1) ? lx : hx, (OCT & 2) ? hy : ly,
+                                           (OCT & 2) ? ly : hy, (OCT & 4) ? hz : lz, (OCT & 4) ? lz : hz, ray, bound,
+                                           cws, key);
+                } else
                     wave_keys_mixed(lx, hx, ly, hy, lz, hz, ray, bound, key);
             } else if (uniform_oct) {
                 wave_keys_uniform(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, bound, key);
