@@ -244,11 +244,14 @@ typedef struct rc_rect_light {
 
 enum {
     RC_FLAG_TIMING = 1u,     /* record per-stage device times (rc_get_stage_times) */
-    RC_FLAG_PER_LANE = 4u      /* trace camera rays and shadow rays one ray per lane with per-lane stacks
+    RC_FLAG_PER_LANE = 4u,     /* trace camera rays and shadow rays one ray per lane with per-lane stacks
                                   even where the wave-uniform traversal would be used (camera rays with
                                   ssaa = 2; point- and rect-light shadow rays always; BVH depth <= 42,
                                   under 2^25 nodes and 2^32 bytes of packed triangles); same results
                                   outside the FP32 band, for comparison */
+    RC_FLAG_NO_SHADE = 8u      /* rc_render: stop after the visibility stages; d_rgba and d_sample_rgba are
+                                  left untouched (for a caller that shades later with rc_shade, e.g. from a
+                                  denoised visibility) */
 };
 
 typedef struct rc_render_opts {

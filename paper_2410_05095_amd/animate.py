@@ -45,7 +45,7 @@ def run(ctx: N.Context, scene: sg.Scene, gs: N.Scene, den: N.Denoiser, anim: sg.
             gs.refit()
         e1.record()
         for v, cam in enumerate(cams):
-            D.render_visibility(ctx, gs, cam, rect, 1, D.STREAM_1SPP, out=outs[v])
+            D.render_visibility(ctx, gs, cam, rect, 1, D.STREAM_1SPP, out=outs[v], shade=False)
             feats[v] = N.pack_features(ctx, gs, cam, outs[v], diag, feat=feats[v])
             den.infer(feats[v].unsqueeze(0), out=y16[v])
             ctx.shade(gs, cam, outs[v], rect=rect, visibility=y16[v][0])

@@ -796,8 +796,9 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
                          q);
     }
     if (timing) RC_HIP(hipEventRecord(c->ev[2], q));
-    rc_launch_shade(ds, dc, L, gbuf, n_lights ? out->d_shadow : nullptr, out->d_visibility, out->d_rgba,
-                    out->d_sample_rgba, c->d_counters + 9, q);
+    if (!(opts && (opts->flags & RC_FLAG_NO_SHADE)))
+        rc_launch_shade(ds, dc, L, gbuf, n_lights ? out->d_shadow : nullptr, out->d_visibility, out->d_rgba,
+                        out->d_sample_rgba, c->d_counters + 9, q);
     if (timing) RC_HIP(hipEventRecord(c->ev[3], q));
     c->timed = timing;
     c->timed_batch = false;

@@ -43,8 +43,10 @@ def orbit_views(rng: np.random.Generator, n: int, width: int, height: int, seed0
     return cams
 
 
-def render_visibility(ctx: N.Context, gs: N.Scene, cam, rect, spp: int, stream: int, out: Optional[dict] = None):
-    return ctx.render(gs, cam, (), rect=rect, area_samples=spp, area_stream=stream, out=out)
+def render_visibility(ctx: N.Context, gs: N.Scene, cam, rect, spp: int, stream: int, out: Optional[dict] = None,
+                      shade: bool = True):
+    """Camera rays and rect-light visibility (and, with `shade`, the shaded image) of one view."""
+    return ctx.render(gs, cam, (), rect=rect, area_samples=spp, area_stream=stream, out=out, shade=shade)
 
 
 class TrainingSet:
@@ -182,7 +184,7 @@ def evaluate(ctx: N.Context, den: N.Denoiser, gs: N.Scene, scene: sg.Scene, cam,
     o_l, o_p, vd = {}, {}, torch.empty((1, H, W), dtype=torch.float32, device=ref.device)
     for _ in range(reps + 1):
         ev[0].record()
-        render_visibility(ctx, gs, cam, rect, 1, STREAM_1SPP, out=o_l)
+        render_visibility(ctx, gs, cam, rect, 1, STREAM_1SPP, out=o_l, shade=False)   # shaded below, once
         ev[1].record()
         f = N.pack_features(ctx, gs, cam, o_l, diag, feat=feat)
         den.infer(f.unsqueeze(0), out=vd)

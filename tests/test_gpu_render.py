@@ -204,6 +204,33 @@ def test_shade_rejects_foreign_hit_ids(ctx):
     assert e.value.status == -2
 
 
+def test_render_without_shading_then_shade(ctx):
+    """RC_FLAG_NO_SHADE: rc_render stops after the visibility stages and leaves the image untouched; rc_shade on
+    its G-buffer, masks and visibility then gives the image of a full rc_render bit for bit (point lights with
+    2x2 samples, and a rect light at 1 sample per pixel, the learned path's configuration)."""
+    import torch
+    for ssaa, use_rect in ((2, False), (1, True)):
+        scene = sg.small_random_scene(6, n_instances=5, width=24, height=18, ssaa=ssaa)
+        cam = scene.cameras[0]
+        gs = ctx.scene_from(scene).build()
+        lights = () if use_rect else scene.point_lights
+        rect = scene.rect_light if use_rect else None
+        kw = dict(rect=rect, area_samples=1 if use_rect else 0, area_stream=0)
+        full = ctx.render(gs, cam, lights, **kw)
+        part = ctx.render(gs, cam, lights, shade=False, **kw)
+        part["rgba"].fill_(7.0)
+        torch.cuda.synchronize()
+        assert torch.all(part["rgba"] == 7.0)
+        ctx.render(gs, cam, lights, out=part, shade=False, **kw)
+        torch.cuda.synchronize()
+        assert torch.all(part["rgba"] == 7.0), "the image was written without shading"
+        assert torch.equal(part["hit"], full["hit"])
+        ctx.shade(gs, cam, part, lights=lights, rect=rect)
+        torch.cuda.synchronize()
+        assert ctx.last_error() == 0
+        assert torch.equal(part["rgba"], full["rgba"]), (ssaa, use_rect)
+
+
 def compare_rect(ctx, O, scene, cam, N, stream, pixels=None, device_build=False, gs=None, osc=None):
     """Both rect-light kernels (wave-uniform traversal, the default; per-lane stacks)
     against one oracle run: hit ids and visible-sample counts exact outside the FP32 band, radiance within
