@@ -52,8 +52,10 @@ inline uint32_t claim_size(uint64_t n_work, int grid, uint32_t per_wave, uint32_
     return (uint32_t)std::min<uint64_t>(hi, std::max<uint64_t>(lo, c));
 }
 
+// The flat-tree camera-ray instance is compiled for 6 waves per SIMD (at most 80 registers; 5 waves otherwise),
+// which measured 3% faster (0.701 vs 0.724 ms for 1080p camera rays on 7.3M triangles).
 template <int MODE, bool TWO, bool WT>
-__global__ __launch_bounds__(BLOCK) void k_trace(KParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE == MODE_PRIMARY && !TWO && !WT ? 6 : 1))) void k_trace(KParams P)
 {
     constexpr bool ANY = MODE != MODE_PRIMARY;
 
