@@ -165,7 +165,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE == M
         // ---- traversal: node phase then leaf phase for all busy lanes, until enough lanes are idle
         for (;;) {
             uint32_t occluded = 0u;
-            trav_advance<TWO, WT>(sc, ray, ts, st, state == 1, ANY, occluded, node_visits, tri_tests, twp);
+            trav_advance<TWO, WT, 3, 1>(sc, ray, ts, st, state == 1, ANY, occluded, node_visits, tri_tests, twp);
             if (state == 1 && ts.cur == RC_STACK_EMPTY) {
                 if (!end_ray(occluded != 0u)) state = 0;
             }
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* cou
         }
         uint32_t occluded = 0u;
         while (__ballot(busy && ts.cur != RC_STACK_EMPTY) != 0)
-            trav_advance<TWO, WT>(sc, ray, ts, st, busy, true, occluded, node_visits, tri_tests, twp);
+            trav_advance<TWO, WT, 3, 1>(sc, ray, ts, st, busy, true, occluded, node_visits, tri_tests, twp);
         const uint64_t vis = __ballot(busy && occluded == 0u);
         if (in_image && (lane == 0 || k == 0)) {
             uint32_t end = (uint32_t)min<uint64_t>(64, lane + (N - k));

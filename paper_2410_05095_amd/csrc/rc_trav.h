@@ -461,26 +461,30 @@ __device__ inline void trav_test_leaf(const DevScene& sc, TravRay& r, TravState&
     s.cur = occluded != 0u ? RC_STACK_EMPTY : trav_pop<TWO>(r, s, st, any, w);
 }
 
-// Advance every busy lane of the wave: first all lanes standing at an internal node visit nodes until
-// none does, then all lanes standing at a leaf test leaves until none does.  A lane's own sequence of
-// visits is the same as visiting one node or leaf at a time, whatever the other lanes do; only the
-// grouping of the work into SIMD steps changes (fewer steps that execute both code paths).
-template <bool TWO = false, bool WT = false, class Stack>
+// Advance every busy lane of the wave: first the lanes standing at an internal node visit nodes, then the
+// lanes standing at a leaf test leaves.  NODE_STEPS / LEAF_STEPS bound the rounds of each phase per call (0:
+// until no lane stands at a node / leaf).  Unbounded phases run fewer SIMD steps that execute both code paths,
+// but a lane that reaches a leaf early then idles until the last lane of the wave has reached one; with the
+// traversal latency-bound (each step waits on its node or triangle loads), short phases keep more lanes moving:
+// 3 node rounds and 1 leaf round per call took 1080p camera rays on 7.3M triangles from 0.70 to 0.57 ms.  A
+// lane's own sequence of visits is the same whatever the other lanes do; only the grouping of the work into
+// SIMD steps changes.
+template <bool TWO = false, bool WT = false, int NODE_STEPS = 0, int LEAF_STEPS = 0, class Stack>
 __device__ inline void trav_advance(const DevScene& sc, TravRay& r, TravState& s, Stack& st, bool busy,
                                     bool any, uint32_t& occluded, uint32_t& node_visits, uint32_t& tri_tests,
                                     TravWorld* w = nullptr)
 {
-    for (;;) {
+    for (int it = 0;; ++it) {
         bool inner = busy && !rc_is_leaf(s.cur);
-        if (__ballot(inner) == 0) break;
+        if (__ballot(inner) == 0 || (NODE_STEPS > 0 && it >= NODE_STEPS)) break;
         if (inner) {
             ++node_visits;
             trav_visit_node<TWO>(sc, r, s, st, any, w);
         }
     }
-    for (;;) {
+    for (int it = 0;; ++it) {
         bool leaf = busy && s.cur != RC_STACK_EMPTY && rc_is_leaf(s.cur);
-        if (__ballot(leaf) == 0) break;
+        if (__ballot(leaf) == 0 || (LEAF_STEPS > 0 && it >= LEAF_STEPS)) break;
         if (leaf) trav_test_leaf<TWO, WT>(sc, r, s, st, any, occluded, tri_tests, w);
     }
 }
