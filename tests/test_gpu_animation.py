@@ -43,5 +43,12 @@ def test_animated_frames_bf16_vs_fp32():
     assert res["max_abs_bf16_fp32"] < 0.05
     # the denoised estimate beats the raw 1-sample estimate it starts from, on every frame
     assert res["mse_bf16_mean"] < 0.6 * res["mse_raw_1spp_mean"]
+    # the views dealt over three streams (the default) give the results of one stream, bit for bit: the same
+    # per-view errors on a fresh copy of the scene
+    gs1 = ctx.scene_from(scene).build()
+    anim1 = sg.RigidAnimation(scene, n_bodies=60, seed=0)
+    res1 = A.run(ctx, scene, gs1, den, anim1, views, n_frames=3, ref_views=lambda f: list(range(4)), lanes=1)
+    for r2, r1 in zip(res["per_frame"][:3], res1["per_frame"]):
+        assert r2["mse_bf16"] == r1["mse_bf16"] and r2["mse_fp32"] == r1["mse_fp32"], (r2, r1)
     torch.cuda.synchronize()
     assert ctx.last_error() == 0
