@@ -322,15 +322,43 @@ __device__ inline uint32_t wave_key(bool hit, float t0, uint32_t slot)
     return m != 0 ? (k0 | slot) : (RC_KEY_MISS | slot);
 }
 
-// bound: 1 (the segment's end) for live rays, -1 for finished ones, which then never hit (t0 >= 0)
+// Slab test of the wave kernels for a segment 0 <= t <= 1: the entry distance, clamped to [0, 1] in one
+// median, against the exit distance.  Against max(entry, 0) <= min(exit, 1) it also accepts boxes that the
+// line meets only beyond t = 1 (beyond the light): extra visits, no change in any result, and one vector
+// operation less per child.  Finished and idle lanes carry far-plane addends of -inf (wave_mute), so their
+// exit distance is -inf (or NaN) and no box accepts them.
+__device__ inline bool rc_slab_seg(const TravRay& r, float nx, float ny, float nz, float fx, float fy, float fz,
+                                   float& t0)
+{
+    const float u = fmaxf(fmaxf(fmaf(nx, r.inv[0], r.cn[0]), fmaf(ny, r.inv[1], r.cn[1])), fmaf(nz, r.inv[2], r.cn[2]));
+    t0 = __builtin_amdgcn_fmed3f(u, 0.0f, 1.0f);
+    const float v = fminf(fminf(fmaf(fx, r.invf[0], r.cf[0]), fmaf(fy, r.invf[1], r.cf[1])), fmaf(fz, r.invf[2], r.cf[2]));
+    return t0 <= v;
+}
+
+// A lane whose ray is finished (live == 0) takes part in no slab test: its far-plane addends become -inf.  An
+// idle lane's traversal constants were never set (set == false): they become 0 first, so that every far
+// distance is -inf (or NaN for an infinite plane) and the entry distance finite (or NaN).
+__device__ inline void wave_mute(TravRay& r, uint32_t live, bool set)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!set) {
+            r.inv[a] = 0.0f;
+            r.cn[a] = 0.0f;
+            r.invf[a] = 0.0f;
+        }
+        r.cf[a] = live != 0u ? r.cf[a] : -INFINITY;
+    }
+}
+
 __device__ inline void wave_keys_uniform(const rc_v4f& nx, const rc_v4f& fx, const rc_v4f& ny, const rc_v4f& fy,
-                                         const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray, float bound,
-                                         uint32_t key[4])
+                                         const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray, uint32_t key[4])
 {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         float t0;
-        const bool hit = rc_slab(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], bound, t0);
+        const bool hit = rc_slab_seg(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], t0);
         key[c] = wave_key(hit, t0, (uint32_t)c);
     }
 }
@@ -338,7 +366,7 @@ __device__ inline void wave_keys_uniform(const rc_v4f& nx, const rc_v4f& fx, con
 // As wave_keys_uniform, for a node whose child words `chw` (wave-uniform) are known: slots 2 and 3 that hold no
 // child get a miss key without their slab tests (a uniform branch), since an empty slot's box never hits.
 __device__ inline void wave_keys_uniform_skip(const rc_v4f& nx, const rc_v4f& fx, const rc_v4f& ny, const rc_v4f& fy,
-                                              const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray, float bound,
+                                              const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray,
                                               const uint32_t chw[4], uint32_t key[4])
 {
 #pragma unroll
@@ -348,14 +376,13 @@ __device__ inline void wave_keys_uniform_skip(const rc_v4f& nx, const rc_v4f& fx
             continue;
         }
         float t0;
-        const bool hit = rc_slab(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], bound, t0);
+        const bool hit = rc_slab_seg(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], t0);
         key[c] = wave_key(hit, t0, (uint32_t)c);
     }
 }
 
 __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const rc_v4f& ly, const rc_v4f& hy,
-                                       const rc_v4f& lz, const rc_v4f& hz, const TravRay& ray, float bound,
-                                       uint32_t key[4])
+                                       const rc_v4f& lz, const rc_v4f& hz, const TravRay& ray, uint32_t key[4])
 {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -363,7 +390,7 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
         const float ny = ray.inv[1] >= 0.0f ? ly[c] : hy[c], fy = ray.inv[1] >= 0.0f ? hy[c] : ly[c];
         const float nz = ray.inv[2] >= 0.0f ? lz[c] : hz[c], fz = ray.inv[2] >= 0.0f ? hz[c] : lz[c];
         float t0;
-        const bool hit = rc_slab(ray, nx, ny, nz, fx, fy, fz, bound, t0);
+        const bool hit = rc_slab_seg(ray, nx, ny, nz, fx, fy, fz, t0);
         key[c] = wave_key(hit, t0, (uint32_t)c);
     }
 }
@@ -411,11 +438,10 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
     };
     if constexpr (OCT < 0) set_octant();
     float wo[3] = {ray.o[0], ray.o[1], ray.o[2]}, wd[3] = {ray.d[0], ray.d[1], ray.d[2]};   // world ray
-    // per-lane state as 32-bit words: occ (an occluder found), live (busy and not occluded) and the
-    // slab bound, 1 (the segment's end) for live rays and -1 otherwise, so that finished rays enter
-    // no box (t0 >= 0)
+    // per-lane state as 32-bit words: occ (an occluder found) and live (busy and not occluded); lanes that
+    // are not live take part in no slab test
     uint32_t occ = 0u, live = busy ? 1u : 0u;
-    float bound = busy ? 1.0f : -1.0f;
+    wave_mute(ray, live, busy);
     uint32_t cur = busy_mask != 0 ? (TWO ? sc.tlas_root : root) : RC_STACK_EMPTY;
     int sp = 0;
     uint32_t stk0 = 0, stk1 = 0;   // entry e of the wave's stack lives in lane e % 64 of stk{e / 64}
@@ -454,14 +480,14 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
                     const rc_v4u cw = *(rc_const_v4u*)(const void*)(np + 96);
                     const uint32_t cws[4] = {cw[0], cw[1], cw[2], cw[3]};
                     wave_keys_uniform_skip((OCT & 1) ? hx : lx, (OCT & 1) ? lx : hx, (OCT & 2) ? hy : ly,
-                                           (OCT & 2) ? ly : hy, (OCT & 4) ? hz : lz, (OCT & 4) ? lz : hz, ray, bound,
+                                           (OCT & 2) ? ly : hy, (OCT & 4) ? hz : lz, (OCT & 4) ? lz : hz, ray,
                                            cws, key);
                 } else
-                    wave_keys_mixed(lx, hx, ly, hy, lz, hz, ray, bound, key);
+                    wave_keys_mixed(lx, hx, ly, hy, lz, hz, ray, key);
             } else if (uniform_oct) {
-                wave_keys_uniform(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, bound, key);
+                wave_keys_uniform(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, key);
             } else {
-                wave_keys_mixed(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, bound, key);
+                wave_keys_mixed(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, key);
             }
             node_visits += live;
 #define RC_CS(a, b)                                                                   \
@@ -505,10 +531,10 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
                                                           tri_tests, error_flag, __float_as_uint(q3[0]));
             occ |= ob;
             live &= ob ^ 1u;
-            bound = live != 0u ? bound : -1.0f;
 #pragma unroll
             for (int a = 0; a < 3; ++a) { ray.o[a] = wo[a]; ray.d[a] = wd[a]; }
             rc_ray_inv(ray);
+            wave_mute(ray, live, true);
             cur = __ballot(live != 0u) == 0 ? RC_STACK_EMPTY : pop_next();
         } else {
             // every lane tests every triangle of the leaf, without lane branches: a finished lane only
@@ -527,7 +553,7 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
             }
             occ = o;
             live &= o ^ 1u;
-            bound = live != 0u ? bound : -1.0f;
+            wave_mute(ray, live, true);
             cur = __ballot(live != 0u) == 0 ? RC_STACK_EMPTY : pop_next();
         }
         cur = __builtin_amdgcn_readfirstlane(cur);
