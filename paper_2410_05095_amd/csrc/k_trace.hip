@@ -352,21 +352,27 @@ __device__ inline void wave_mute(TravRay& r, uint32_t live, bool set)
     }
 }
 
+// CLAMP: rc_slab_seg (finished lanes muted); otherwise rc_slab with bound, 1 for live rays and -1 for finished
+// ones, which then never hit (t0 >= 0)
+template <bool CLAMP>
 __device__ inline void wave_keys_uniform(const rc_v4f& nx, const rc_v4f& fx, const rc_v4f& ny, const rc_v4f& fy,
-                                         const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray, uint32_t key[4])
+                                         const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray, float bound,
+                                         uint32_t key[4])
 {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         float t0;
-        const bool hit = rc_slab_seg(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], t0);
+        const bool hit = CLAMP ? rc_slab_seg(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], t0)
+                                 : rc_slab(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], bound, t0);
         key[c] = wave_key(hit, t0, (uint32_t)c);
     }
 }
 
 // As wave_keys_uniform, for a node whose child words `chw` (wave-uniform) are known: slots 2 and 3 that hold no
 // child get a miss key without their slab tests (a uniform branch), since an empty slot's box never hits.
+template <bool CLAMP>
 __device__ inline void wave_keys_uniform_skip(const rc_v4f& nx, const rc_v4f& fx, const rc_v4f& ny, const rc_v4f& fy,
-                                              const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray,
+                                              const rc_v4f& nz, const rc_v4f& fz, const TravRay& ray, float bound,
                                               const uint32_t chw[4], uint32_t key[4])
 {
 #pragma unroll
@@ -376,13 +382,16 @@ __device__ inline void wave_keys_uniform_skip(const rc_v4f& nx, const rc_v4f& fx
             continue;
         }
         float t0;
-        const bool hit = rc_slab_seg(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], t0);
+        const bool hit = CLAMP ? rc_slab_seg(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], t0)
+                                 : rc_slab(ray, nx[c], ny[c], nz[c], fx[c], fy[c], fz[c], bound, t0);
         key[c] = wave_key(hit, t0, (uint32_t)c);
     }
 }
 
+template <bool CLAMP>
 __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const rc_v4f& ly, const rc_v4f& hy,
-                                       const rc_v4f& lz, const rc_v4f& hz, const TravRay& ray, uint32_t key[4])
+                                       const rc_v4f& lz, const rc_v4f& hz, const TravRay& ray, float bound,
+                                       uint32_t key[4])
 {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -390,7 +399,7 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
         const float ny = ray.inv[1] >= 0.0f ? ly[c] : hy[c], fy = ray.inv[1] >= 0.0f ? hy[c] : ly[c];
         const float nz = ray.inv[2] >= 0.0f ? lz[c] : hz[c], fz = ray.inv[2] >= 0.0f ? hz[c] : lz[c];
         float t0;
-        const bool hit = rc_slab_seg(ray, nx, ny, nz, fx, fy, fz, t0);
+        const bool hit = CLAMP ? rc_slab_seg(ray, nx, ny, nz, fx, fy, fz, t0) : rc_slab(ray, nx, ny, nz, fx, fy, fz, bound, t0);
         key[c] = wave_key(hit, t0, (uint32_t)c);
     }
 }
@@ -404,13 +413,16 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
 // plane blocks come with three 32-byte loads at constant offsets and the near/far choice is made when
 // compiling; 8: mixed octants (each lane picks its planes); -1: decided at run time, per instance for
 // two-level structures (the mapped rays' octant changes at each instance).
-template <bool WT, bool BIG>
+template <bool WT, bool BIG, bool CLAMP>
 __device__ __attribute__((always_inline)) inline uint32_t wave_walk_flat(const DevScene& sc, const char* nodes_b,
                                                                        const char* tris_b, TravRay& ray, bool busy,
                                                                        uint32_t& node_visits, uint32_t& tri_tests,
                                                                        uint32_t* error_flag, uint32_t root);
 
-template <bool TWO, bool WT, bool BIG, int OCT>
+// CLAMP: the slab test rc_slab_seg with muted lanes (flat trees, Moller-Trumbore: 10 vector operations per child
+// instead of 12); otherwise rc_slab with a bound per lane (two-level structures and the watertight test, whose
+// walks hold more registers and measured slower with the muting)
+template <bool TWO, bool WT, bool BIG, int OCT, bool CLAMP>
 __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevScene& sc, const char* nodes_b,
                                                                   const char* tris_b, TravRay& ray, bool busy,
                                                                   uint32_t& node_visits, uint32_t& tri_tests,
@@ -439,9 +451,10 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
     if constexpr (OCT < 0) set_octant();
     float wo[3] = {ray.o[0], ray.o[1], ray.o[2]}, wd[3] = {ray.d[0], ray.d[1], ray.d[2]};   // world ray
     // per-lane state as 32-bit words: occ (an occluder found) and live (busy and not occluded); lanes that
-    // are not live take part in no slab test
+    // are not live take part in no slab test (muted, or bound = -1)
     uint32_t occ = 0u, live = busy ? 1u : 0u;
-    wave_mute(ray, live, busy);
+    float bound = busy ? 1.0f : -1.0f;
+    if constexpr (CLAMP) wave_mute(ray, live, busy);
     uint32_t cur = busy_mask != 0 ? (TWO ? sc.tlas_root : root) : RC_STACK_EMPTY;
     int sp = 0;
     uint32_t stk0 = 0, stk1 = 0;   // entry e of the wave's stack lives in lane e % 64 of stk{e / 64}
@@ -479,15 +492,15 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
                 if constexpr (OCT < 8) {
                     const rc_v4u cw = *(rc_const_v4u*)(const void*)(np + 96);
                     const uint32_t cws[4] = {cw[0], cw[1], cw[2], cw[3]};
-                    wave_keys_uniform_skip((OCT & 1) ? hx : lx, (OCT & 1) ? lx : hx, (OCT & 2) ? hy : ly,
-                                           (OCT & 2) ? ly : hy, (OCT & 4) ? hz : lz, (OCT & 4) ? lz : hz, ray,
+                    wave_keys_uniform_skip<CLAMP>((OCT & 1) ? hx : lx, (OCT & 1) ? lx : hx, (OCT & 2) ? hy : ly,
+                                           (OCT & 2) ? ly : hy, (OCT & 4) ? hz : lz, (OCT & 4) ? lz : hz, ray, bound,
                                            cws, key);
                 } else
-                    wave_keys_mixed(lx, hx, ly, hy, lz, hz, ray, key);
+                    wave_keys_mixed<CLAMP>(lx, hx, ly, hy, lz, hz, ray, bound, key);
             } else if (uniform_oct) {
-                wave_keys_uniform(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, key);
+                wave_keys_uniform<CLAMP>(blk(on0), blk(of0), blk(on1), blk(of1), blk(on2), blk(of2), ray, bound, key);
             } else {
-                wave_keys_mixed(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, key);
+                wave_keys_mixed<CLAMP>(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, bound, key);
             }
             node_visits += live;
 #define RC_CS(a, b)                                                                   \
@@ -527,14 +540,14 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
             const float W[12] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3],
                                  q2[0], q2[1], q2[2], q2[3]};
             rc_map_ray(W, wo, wd, ray);
-            const uint32_t ob = wave_walk_flat<WT, false>(sc, nodes_b, tris_b, ray, live != 0u, node_visits,
+            const uint32_t ob = wave_walk_flat<WT, false, false>(sc, nodes_b, tris_b, ray, live != 0u, node_visits,
                                                           tri_tests, error_flag, __float_as_uint(q3[0]));
             occ |= ob;
             live &= ob ^ 1u;
 #pragma unroll
             for (int a = 0; a < 3; ++a) { ray.o[a] = wo[a]; ray.d[a] = wd[a]; }
             rc_ray_inv(ray);
-            wave_mute(ray, live, true);
+            bound = live != 0u ? bound : -1.0f;
             cur = __ballot(live != 0u) == 0 ? RC_STACK_EMPTY : pop_next();
         } else {
             // every lane tests every triangle of the leaf, without lane branches: a finished lane only
@@ -553,7 +566,8 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
             }
             occ = o;
             live &= o ^ 1u;
-            wave_mute(ray, live, true);
+            if constexpr (CLAMP) wave_mute(ray, live, true);
+            else bound = live != 0u ? bound : -1.0f;
             cur = __ballot(live != 0u) == 0 ? RC_STACK_EMPTY : pop_next();
         }
         cur = __builtin_amdgcn_readfirstlane(cur);
@@ -571,23 +585,23 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const De
                                                                       uint32_t* error_flag)
 {
     if constexpr (TWO)
-        return wave_walk<TWO, WT, BIG, -1>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, 0u);
+        return wave_walk<TWO, WT, BIG, -1, false>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, 0u);
     else
-        return wave_walk_flat<WT, BIG>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, 0u);
+        return wave_walk_flat<WT, BIG, !WT>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, 0u);
 }
 
 // The flat walk from node `root`, compiled once per direction octant of the busy rays and once for mixed
 // octants.  For two-level structures it walks an instance's tree with a one-register stack: the host takes
 // the wave kernels only when 3 x (deepest instance tree + 24) + 2 <= 128, so an instance tree is at most 18
 // levels deep and its walk needs at most 55 stack entries.
-template <bool WT, bool BIG>
+template <bool WT, bool BIG, bool CLAMP>
 __device__ __attribute__((always_inline)) inline uint32_t wave_walk_flat(const DevScene& sc, const char* nodes_b,
                                                                        const char* tris_b, TravRay& ray, bool busy,
                                                                        uint32_t& node_visits, uint32_t& tri_tests,
                                                                        uint32_t* error_flag, uint32_t root)
 {
 #define RC_WALK(o) \
-    wave_walk<false, WT, BIG, o>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, root)
+    wave_walk<false, WT, BIG, o, CLAMP>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, root)
     const uint64_t busy_mask = __ballot(busy);
     const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
                             (ray.inv[2] < 0.0f ? 4u : 0u);
