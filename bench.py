@@ -234,6 +234,23 @@ def timed_frames(ctx, gs, cam, kw, steps, warmup, out=None):
     return out, wall * 1000.0 / steps, float(np.median(ms)), ms
 
 
+def frame_and_stages(ctx, gs, cam, kw, steps, warmup):
+    """Device time of a frame (HIP events around plain renders, median of `steps`), its stage split (renders
+    timed by stage, medians of `steps`) and the ray, node and triangle counts (one counting render)."""
+    import numpy as np
+    out, _, frame_ms, _ = timed_frames(ctx, gs, cam, kw, steps, warmup)
+    frames = []
+    for _ in range(steps):
+        ctx.render(gs, cam, out=out, timing=True, **kw)
+        frames.append(ctx.stage_times())
+    st = {k: float(np.median([f[k] for f in frames])) for k in ("primary_ms", "shadow_ms", "shade_ms", "total_ms")}
+    ctx.render(gs, cam, out=out, count=True, **kw)
+    c = ctx.stage_times()
+    assert ctx.last_error() == 0
+    st.update({k: c[k] for k in c if not k.endswith("_ms")})
+    return out, frame_ms, st
+
+
 def post_pass(ctx, out, args):
     """The display post pass (tone map + sRGB8, FXAA) on the benchmark frame: device time per frame, and the
     bytes each kernel moves at minimum (tone map: 16 B in + 4 B out per pixel; FXAA: 4 B in + 4 B out)."""
@@ -264,24 +281,18 @@ def post_pass(ctx, out, args):
 def hard_shadows(ctx, gs, scene, cam, args):
     """The configuration the paper times (Sec. V): one camera ray and one hard-shadow ray per pixel, one point
     light (placed at the rect light's centre, intensity 400), 1920x1080, the 7.3M-triangle scene.  Device
-    time of the whole frame (camera rays, shadow rays, shading), median of args.steps frames."""
+    time of the whole frame (camera rays, shadow rays, shading), median of args.steps frames, and its stage
+    split."""
     import numpy as np
     import torch
     c = scene.rect_light.center
     light = np.array([[c[0], c[1], c[2], 400.0, 400.0, 400.0]], np.float32)
-    out = {}
-    for _ in range(args.warmup):
-        ctx.render(gs, cam, light, out=out, timing=True)
-    frames = []
-    for _ in range(args.steps):
-        ctx.render(gs, cam, light, out=out, timing=True)
-        frames.append(ctx.stage_times())
+    _, frame_ms, st = frame_and_stages(ctx, gs, cam, dict(lights=light), args.steps, args.warmup)
     torch.cuda.synchronize()
-    assert ctx.last_error() == 0
-    med = lambda k: round(float(np.median([f[k] for f in frames])), 4)
-    rays = frames[-1]["primary_rays"] + frames[-1]["shadow_rays"]
-    return {"frame_ms": med("total_ms"), "primary_ms": med("primary_ms"), "shadow_ms": med("shadow_ms"),
-            "rays_per_frame": int(rays), "mrays_per_s": round(rays / med("total_ms") / 1e3, 1),
+    rays = st["primary_rays"] + st["shadow_rays"]
+    return {"frame_ms": round(frame_ms, 4), "primary_ms": round(st["primary_ms"], 4),
+            "shadow_ms": round(st["shadow_ms"], 4), "rays_per_frame": int(rays),
+            "mrays_per_s": round(rays / frame_ms / 1e3, 1),
             "paper_context": "paper: >7M triangles within 2 ms of GPU time per frame on an RTX 4090 "
                              "(raster + hardware ray queries; resolution not stated)"}
 
@@ -300,19 +311,11 @@ def device_build(ctx, scene, cam, kw, args):
             gs.build(**opt)
             ms.append(gs.stats()["build_ms"])
         st = gs.stats()
-        out = {}
-        for _ in range(args.warmup):
-            ctx.render(gs, cam, out=out, timing=True, **kw)
-        frames = []
-        for _ in range(args.steps):
-            ctx.render(gs, cam, out=out, timing=True, **kw)
-            frames.append(ctx.stage_times())
-        assert ctx.last_error() == 0
+        _, frame_ms, sg_ = frame_and_stages(ctx, gs, cam, kw, args.steps, args.warmup)
         gs.close()
-        med = lambda k: round(float(np.median([f[k] for f in frames])), 4)
         res[name] = {"build_ms": round(float(np.median(ms)), 2), "nodes": int(st["n_nodes"]), "depth": int(st["depth"]),
-                     "sah": round(st["sah_cost"], 4), "frame_device_ms": med("total_ms"), "shadow_ms": med("shadow_ms"),
-                     "primary_ms": med("primary_ms")}
+                     "sah": round(st["sah_cost"], 4), "frame_device_ms": round(frame_ms, 4),
+                     "shadow_ms": round(sg_["shadow_ms"], 4), "primary_ms": round(sg_["primary_ms"], 4)}
         log(f"[bench] device build {name}: {res[name]}")
     return res
 
@@ -326,15 +329,9 @@ def watertight_frames(ctx, scene, cam, kw, args):
     hard = dict(lights=np.array([[c[0], c[1], c[2], 400.0, 400.0, 400.0]], np.float32))
     res = {}
     for name, k in (("soft", kw), ("hard", hard)):
-        out = {}
-        for _ in range(args.warmup):
-            ctx.render(gs, cam, out=out, timing=True, **k)
-        frames = []
-        for _ in range(args.steps):
-            ctx.render(gs, cam, out=out, timing=True, **k)
-            frames.append(ctx.stage_times())
-        med = lambda key: round(float(np.median([f[key] for f in frames])), 4)
-        res[name] = {"frame_device_ms": med("total_ms"), "shadow_ms": med("shadow_ms"), "primary_ms": med("primary_ms")}
+        _, frame_ms, st = frame_and_stages(ctx, gs, cam, k, args.steps, args.warmup)
+        res[name] = {"frame_device_ms": round(frame_ms, 4), "shadow_ms": round(st["shadow_ms"], 4),
+                     "primary_ms": round(st["primary_ms"], 4)}
     assert ctx.last_error() == 0
     gs.close()
     return res
@@ -386,7 +383,7 @@ def dynamic_structures(ctx, gs_flat, scene, cam, args):
             if f > 0:
                 upd.append(ev[0].elapsed_time(ev[1]))
                 tot.append(ev[0].elapsed_time(ev[2]))
-        ctx.render(g, cam, out=out, timing=True, **kw)
+        ctx.render(g, cam, out=out, count=True, **kw)
         st = ctx.stage_times()
         assert ctx.last_error() == 0
         return {"update_ms": round(float(np.mean(upd)), 4), "frame_ms": round(float(np.mean(tot)), 4), **per_ray(st)}
@@ -652,9 +649,13 @@ def main():
         ctx.render(gs, cam, out=out, timing=True, **kw)
         stages.append(ctx.stage_times())
     st = {k: float(np.median([s[k] for s in stages])) for k in stages[0]}
+    # rays cast and the wave kernels' node visits and triangle tests: one counting render (RC_FLAG_COUNT)
+    ctx.render(gs, cam, out=out, count=True, **kw)
+    cnt = ctx.stage_times()
+    st.update({k: float(cnt[k]) for k in cnt if not k.endswith("_ms")})
     # own-path work: the same frame through the per-lane kernels, whose counters count each ray's own node
     # visits and triangle tests (near-first order, any hit), as the oracle's instrumented traversal does
-    ctx.render(gs, cam, out={}, per_lane=True, **kw)
+    ctx.render(gs, cam, out={}, per_lane=True, count=True, **kw)
     own = ctx.stage_times()
     torch.cuda.synchronize()
     assert ctx.last_error() == 0

@@ -249,9 +249,12 @@ enum {
                                   ssaa = 2; point- and rect-light shadow rays always; BVH depth <= 42,
                                   under 2^25 nodes and 2^32 bytes of packed triangles); same results
                                   outside the FP32 band, for comparison */
-    RC_FLAG_NO_SHADE = 8u      /* rc_render: stop after the visibility stages; d_rgba and d_sample_rgba are
+    RC_FLAG_NO_SHADE = 8u,     /* rc_render: stop after the visibility stages; d_rgba and d_sample_rgba are
                                   left untouched (for a caller that shades later with rc_shade, e.g. from a
                                   denoised visibility) */
+    RC_FLAG_COUNT = 16u        /* rc_render: count rays cast, nodes visited and triangles tested
+                                  (rc_get_stage_times); without it the wave-uniform shadow kernels run
+                                  without their counters */
 };
 
 typedef struct rc_render_opts {
@@ -345,7 +348,7 @@ int rc_camera_rays(rc_ctx* ctx, const rc_camera* cam, float* d_origins, float* d
 
 /* Device milliseconds of the stages of the last rc_render made with RC_FLAG_TIMING:
  * ms[0] primary traversal, ms[1] shadow traversal, ms[2] shade + resolve, ms[3] whole
- * render.  Counts of the last rc_render (with or without timing), [0] primary and [1] shadow
+ * render.  Counts of the last rc_render made with RC_FLAG_COUNT, [0] primary and [1] shadow
  * traversal: rays cast, 4-wide nodes visited, triangles tested.  Synchronises the stream. */
 typedef struct rc_stage_times {
     float ms[8];

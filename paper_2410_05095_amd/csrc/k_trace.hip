@@ -413,7 +413,7 @@ __device__ inline void wave_keys_mixed(const rc_v4f& lx, const rc_v4f& hx, const
 // plane blocks come with three 32-byte loads at constant offsets and the near/far choice is made when
 // compiling; 8: mixed octants (each lane picks its planes); -1: decided at run time, per instance for
 // two-level structures (the mapped rays' octant changes at each instance).
-template <bool WT, bool BIG, bool CLAMP>
+template <bool WT, bool BIG, bool CLAMP, bool COUNT>
 __device__ __attribute__((always_inline)) inline uint32_t wave_walk_flat(const DevScene& sc, const char* nodes_b,
                                                                        const char* tris_b, TravRay& ray, bool busy,
                                                                        uint32_t& node_visits, uint32_t& tri_tests,
@@ -422,7 +422,8 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk_flat(const D
 // CLAMP: the slab test rc_slab_seg with muted lanes (flat trees, Moller-Trumbore: 10 vector operations per child
 // instead of 12); otherwise rc_slab with a bound per lane (two-level structures and the watertight test, whose
 // walks hold more registers and measured slower with the muting)
-template <bool TWO, bool WT, bool BIG, int OCT, bool CLAMP>
+// COUNT: the walk counts node visits and triangle tests of live lanes (frames timed by stage report them)
+template <bool TWO, bool WT, bool BIG, int OCT, bool CLAMP, bool COUNT>
 __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevScene& sc, const char* nodes_b,
                                                                   const char* tris_b, TravRay& ray, bool busy,
                                                                   uint32_t& node_visits, uint32_t& tri_tests,
@@ -502,7 +503,7 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
             } else {
                 wave_keys_mixed<CLAMP>(blk(0), blk(16), blk(32), blk(48), blk(64), blk(80), ray, bound, key);
             }
-            node_visits += live;
+            if constexpr (COUNT) node_visits += live;
 #define RC_CS(a, b)                                                                   \
 {                                                                                 \
     const uint32_t lo = min(key[a], key[b]), hi = max(key[a], key[b]);            \
@@ -540,7 +541,7 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
             const float W[12] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3],
                                  q2[0], q2[1], q2[2], q2[3]};
             rc_map_ray(W, wo, wd, ray);
-            const uint32_t ob = wave_walk_flat<WT, false, false>(sc, nodes_b, tris_b, ray, live != 0u, node_visits,
+            const uint32_t ob = wave_walk_flat<WT, false, false, COUNT>(sc, nodes_b, tris_b, ray, live != 0u, node_visits,
                                                           tri_tests, error_flag, __float_as_uint(q3[0]));
             occ |= ob;
             live &= ob ^ 1u;
@@ -559,7 +560,7 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
             for (uint32_t i = 0; i < cnt; ++i) {
                 rc_const_v4f* tp = (rc_const_v4f*)(const void*)(tris_b + (uint32_t)(tofs + 48u * i));
                 const rc_v4f A = tp[0], B = tp[1], C = tp[2];
-                tri_tests += live & (o ^ 1u);
+                if constexpr (COUNT) tri_tests += live & (o ^ 1u);
                 const bool hit = WT ? rc_wt_segment(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z)
                                     : rc_mt_segment(ray, A.x, A.y, A.z, B.x, B.y, B.z, C.x, C.y, C.z);
                 o |= hit ? 1u : 0u;
@@ -578,30 +579,31 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk(const DevSce
 // Any-hit traversal of the segments o + t d, 0 <= t <= 1, of a wave's rays (called by all 64 lanes; busy
 // lanes hold a ray whose traversal constants rc_ray_inv set): returns 1 in the lanes whose segment is
 // occluded.  Flat trees: one walk specialised for the wave's octant, or for mixed octants.
-template <bool TWO, bool WT, bool BIG>
+template <bool TWO, bool WT, bool BIG, bool COUNT>
 __device__ __attribute__((always_inline)) inline uint32_t wave_occluded(const DevScene& sc, const char* nodes_b,
                                                                       const char* tris_b, TravRay& ray, bool busy,
                                                                       uint32_t& node_visits, uint32_t& tri_tests,
                                                                       uint32_t* error_flag)
 {
     if constexpr (TWO)
-        return wave_walk<TWO, WT, BIG, -1, false>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, 0u);
+        return wave_walk<TWO, WT, BIG, -1, false, COUNT>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag,
+                                                        0u);
     else
-        return wave_walk_flat<WT, BIG, !WT>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, 0u);
+        return wave_walk_flat<WT, BIG, !WT, COUNT>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, 0u);
 }
 
 // The flat walk from node `root`, compiled once per direction octant of the busy rays and once for mixed
 // octants.  For two-level structures it walks an instance's tree with a one-register stack: the host takes
 // the wave kernels only when 3 x (deepest instance tree + 24) + 2 <= 128, so an instance tree is at most 18
 // levels deep and its walk needs at most 55 stack entries.
-template <bool WT, bool BIG, bool CLAMP>
+template <bool WT, bool BIG, bool CLAMP, bool COUNT>
 __device__ __attribute__((always_inline)) inline uint32_t wave_walk_flat(const DevScene& sc, const char* nodes_b,
                                                                        const char* tris_b, TravRay& ray, bool busy,
                                                                        uint32_t& node_visits, uint32_t& tri_tests,
                                                                        uint32_t* error_flag, uint32_t root)
 {
 #define RC_WALK(o) \
-    wave_walk<false, WT, BIG, o, CLAMP>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, root)
+    wave_walk<false, WT, BIG, o, CLAMP, COUNT>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests, error_flag, root)
     const uint64_t busy_mask = __ballot(busy);
     const uint32_t my_oct = (ray.inv[0] < 0.0f ? 1u : 0u) | (ray.inv[1] < 0.0f ? 2u : 0u) |
                             (ray.inv[2] < 0.0f ? 4u : 0u);
@@ -622,7 +624,7 @@ __device__ __attribute__((always_inline)) inline uint32_t wave_walk_flat(const D
 #undef RC_WALK
 }
 
-template <bool TWO, bool WT, bool BIG>
+template <bool TWO, bool WT, bool BIG, bool COUNT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT ? 1 : 8))) void k_rect_wave(KParams P, uint32_t* counts, const float4* setup)
 {
     const uint32_t lane = __lane_id();
@@ -662,7 +664,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT
                 }
             }
         }
-        const uint32_t occ = wave_occluded<TWO, WT, BIG>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests,
+        const uint32_t occ = wave_occluded<TWO, WT, BIG, COUNT>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests,
                                                          P.w.error_flag);
         const uint64_t vis = __ballot(busy && occ == 0u);
         if (in_image && (lane == 0 || k == 0)) {
@@ -687,7 +689,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT
 // (neighbouring pixels); the wave walks the tree once per light, each lane casting its sample's segment to
 // that light where the light lies above the surface, with the same tests and results as the per-lane kernel.
 // Mask bit l of a sample: the ray to light l is cast and not occluded.
-template <bool TWO, bool WT, bool BIG>
+template <bool TWO, bool WT, bool BIG, bool COUNT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT ? 1 : 8))) void k_point_wave(KParams P, const float4* setup)
 {
     const uint32_t lane = __lane_id();
@@ -730,7 +732,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TWO || WT
                     ++rays_cast;
                 }
             }
-            const uint32_t occ = wave_occluded<TWO, WT, BIG>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests,
+            const uint32_t occ = wave_occluded<TWO, WT, BIG, COUNT>(sc, nodes_b, tris_b, ray, busy, node_visits, tri_tests,
                                                              P.w.error_flag);
             if (busy && occ == 0u) mask |= 1u << l;
         }
@@ -952,9 +954,9 @@ int rc_trace_grid(int device)
         blocks_per_cu(reinterpret_cast<const void*>(&k_trace<MODE_POINT, false, false>), lds_bytes<MODE_POINT>()),
         blocks_per_cu(reinterpret_cast<const void*>(&k_trace<MODE_RECT, false, false>), lds_bytes<MODE_RECT>()),
         blocks_per_cu(reinterpret_cast<const void*>(&k_rect_packets<false, false>), TravStack<SL, BLOCK, false>::lds_bytes()),
-        blocks_per_cu(reinterpret_cast<const void*>(&k_rect_wave<false, false, false>), 0),
+        blocks_per_cu(reinterpret_cast<const void*>(&k_rect_wave<false, false, false, false>), 0),
         blocks_per_cu(reinterpret_cast<const void*>(&k_primary_wave<false>), 0),
-        blocks_per_cu(reinterpret_cast<const void*>(&k_point_wave<false, false, false>), 0)};
+        blocks_per_cu(reinterpret_cast<const void*>(&k_point_wave<false, false, false, false>), 0)};
     int b = 1;
     for (int x : blocks) b = std::max(b, x);
     return cu_count(device) * b;
@@ -1000,6 +1002,7 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     P.w = w;
     P.n_items = rc_n_items(cam.width, cam.height, cam.ssaa);
     const bool two = sc.inst != nullptr, wt = sc.watertight != 0u;
+    const bool count = w.ray_count != nullptr;   // the wave kernels count visits only when asked
     // the wave-uniform kernels (the default) address nodes and triangles by 32-bit byte offsets and hold
     // at most 128 stack entries; they read each sample's shadow-ray origin and normal from `setup`
     const bool wave = sc.max_stack <= 128 && !per_lane && sc.n_nodes < (1u << 25) &&
@@ -1014,12 +1017,21 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         P.slot = 1;
         if (wave) {
             P.claim = claim_size((P.n_items + 63) / 64, grid, 64, 1, 4);
-            if (sc.max_stack <= 64)
-                RC_LAUNCH_TW((k_point_wave<RC_TWO, RC_WT, false>), dim3(grid), dim3(BLOCK), 0, st, P,
-                             (const float4*)setup);
-            else
-                RC_LAUNCH_TW((k_point_wave<RC_TWO, RC_WT, true>), dim3(grid), dim3(BLOCK), 0, st, P,
-                             (const float4*)setup);
+            if (sc.max_stack <= 64) {
+                if (count)
+                    RC_LAUNCH_TW((k_point_wave<RC_TWO, RC_WT, false, true>), dim3(grid), dim3(BLOCK), 0, st, P,
+                                 (const float4*)setup);
+                else
+                    RC_LAUNCH_TW((k_point_wave<RC_TWO, RC_WT, false, false>), dim3(grid), dim3(BLOCK), 0, st, P,
+                                 (const float4*)setup);
+            } else {
+                if (count)
+                    RC_LAUNCH_TW((k_point_wave<RC_TWO, RC_WT, true, true>), dim3(grid), dim3(BLOCK), 0, st, P,
+                                 (const float4*)setup);
+                else
+                    RC_LAUNCH_TW((k_point_wave<RC_TWO, RC_WT, true, false>), dim3(grid), dim3(BLOCK), 0, st, P,
+                                 (const float4*)setup);
+            }
         } else {
             P.claim = claim_size(P.n_items, grid, 16, 32, 128);
             RC_LAUNCH_TW((k_trace<MODE_POINT, RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), lds_bytes<MODE_POINT>(), st, P);
@@ -1040,12 +1052,21 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         // 64 / N neighbouring pixels, whose rays start close together (measured faster than the per-lane
         // kernel from one sample per pixel on)
         if (wave) {
-            if (sc.max_stack <= 64)
-                RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, false>), dim3(grid), dim3(BLOCK), 0, st, P, counts,
-                             (const float4*)setup);
-            else
-                RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, true>), dim3(grid), dim3(BLOCK), 0, st, P, counts,
-                             (const float4*)setup);
+            if (sc.max_stack <= 64) {
+                if (count)
+                    RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, false, true>), dim3(grid), dim3(BLOCK), 0, st, P, counts,
+                                 (const float4*)setup);
+                else
+                    RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, false, false>), dim3(grid), dim3(BLOCK), 0, st, P, counts,
+                                 (const float4*)setup);
+            } else {
+                if (count)
+                    RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, true, true>), dim3(grid), dim3(BLOCK), 0, st, P, counts,
+                                 (const float4*)setup);
+                else
+                    RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, true, false>), dim3(grid), dim3(BLOCK), 0, st, P, counts,
+                                 (const float4*)setup);
+            }
         } else {
             const size_t lds = TravStack<SL, BLOCK, false>::lds_bytes();
             RC_LAUNCH_TW((k_rect_packets<RC_TWO, RC_WT>), dim3(grid), dim3(BLOCK), lds, st, P, counts);

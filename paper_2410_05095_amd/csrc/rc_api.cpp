@@ -770,10 +770,13 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     hipStream_t q = c->stream;
     rc_launch_fill_u32(c->d_counters, 0u, 8, q);
     rc_launch_fill_u32(c->d_counters + RC_QUEUE_BASE, 0u, RC_COUNTER_WORDS - RC_QUEUE_BASE, q);
-    rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, q);
+    // ray, node and triangle counts are gathered on request only (RC_FLAG_COUNT: the wave kernels are compiled
+    // without their counters otherwise)
+    const bool counting = opts && (opts->flags & RC_FLAG_COUNT);
+    if (counting) rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, q);
     uint4* gbuf = reinterpret_cast<uint4*>(out->d_hit);
     if (timing) RC_HIP(hipEventRecord(c->ev[0], q));
-    w.ray_count = c->d_rays + 0;
+    w.ray_count = counting ? c->d_rays + 0 : nullptr;
     rc_launch_primary(ds, dc, gbuf, w, c->grid, opts && (opts->flags & RC_FLAG_PER_LANE), q);
     if (timing) RC_HIP(hipEventRecord(c->ev[1], q));
     if (n_lights > 0 || rect) {
@@ -789,7 +792,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
             if (st != RC_OK) return st;
             c->counts_cap = words;
         }
-        w.ray_count = c->d_rays + 1;
+        w.ray_count = counting ? c->d_rays + 1 : nullptr;
         bool per_lane = opts && (opts->flags & RC_FLAG_PER_LANE);
         float4* setup = reinterpret_cast<float4*>(c->d_counts + setup_off);
         rc_launch_shadow(ds, dc, L, gbuf, out->d_shadow, out->d_visibility, c->d_counts, setup, w, c->grid, per_lane,
