@@ -461,7 +461,7 @@ def batch_views(ctx, args):
     t1 = time.perf_counter()
     best, tune_ms = ctx.autotune(handles, views, lights, reps=3)
     tune_s = time.perf_counter() - t1
-    outs = ctx.render_batch(handles, views, lights, tune=best, timing=True)
+    outs = ctx.render_batch(handles, views, lights, tune=best, timing=True, count=True)
     st = ctx.stage_times()
     for _ in range(3):
         outs = ctx.render_batch(handles, views, lights, tune=best, graph=True, outs=outs)

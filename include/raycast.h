@@ -386,7 +386,7 @@ enum {
 
 /* Render all views in one persistent kernel launch fed by a device work queue (point lights and
  * 2x2 or 1 sample per pixel).  Every view's outputs are bit-identical to rc_render of that view
- * alone with RC_FLAG_PER_LANE (the same per-lane traversal), for any tuning.  flags: RC_FLAG_TIMING (rc_get_stage_times ms[3]), RC_FLAG_GRAPH.  All
+ * alone with RC_FLAG_PER_LANE (the same per-lane traversal), for any tuning.  flags: RC_FLAG_TIMING (rc_get_stage_times ms[3]), RC_FLAG_COUNT (its counts), RC_FLAG_GRAPH.  All
  * scenes must be built (flat BVHs: two-level structures give RC_ERR_UNSUPPORTED).  Errors:
  * RC_ERR_INVALID_ARG, RC_ERR_NOT_BUILT, RC_ERR_UNSUPPORTED, RC_ERR_HIP. */
 int rc_render_batch(rc_ctx* ctx, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,

@@ -328,7 +328,7 @@ class Context:
         return sarr, varr
 
     def render_batch(self, scenes, views, lights, tune: Optional[dict] = None, graph: bool = False,
-                     timing: bool = False, outs: Optional[list] = None) -> list:
+                     timing: bool = False, outs: Optional[list] = None, count: bool = False) -> list:
         self._sync_stream()
         if outs is None:
             outs = [{} for _ in views]
@@ -336,7 +336,7 @@ class Context:
         Larr = light_array(lights)
         nl = 0 if Larr is None else len(Larr)
         t = RcTune(**tune) if tune else None
-        flags = (RC_FLAG_GRAPH if graph else 0) | (RC_FLAG_TIMING if timing else 0)
+        flags = (RC_FLAG_GRAPH if graph else 0) | (RC_FLAG_TIMING if timing else 0) | (RC_FLAG_COUNT if count else 0)
         check(lib().rc_render_batch(self.h, sarr, len(scenes), varr, len(views), Larr, nl,
                                     C.byref(t) if t is not None else None, flags), "rc_render_batch")
         return outs

@@ -1082,7 +1082,7 @@ int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc
     P.w.overflow_depth = depth;
     P.w.n_lanes = (uint32_t)grid * RC_TRACE_BLOCK;
     P.w.error_flag = c->d_counters + 8;
-    P.w.ray_count = c->d_rays;
+    P.w.ray_count = (flags & RC_FLAG_COUNT) ? c->d_rays : nullptr;   // counts on request only
 
     bool timing = (flags & RC_FLAG_TIMING) != 0;
     if (timing) RC_HIP(hipEventRecord(c->ev[0], c->stream));

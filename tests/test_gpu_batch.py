@@ -146,7 +146,7 @@ def test_batch_64_views_4_scenes(ctx, oracle_mod):
         f"tris {[s.n_tris for s in scenes]}")
     best, best_ms = ctx.autotune(handles, views, lights, reps=1)
     say(f"[batch64] autotuned: {best} ({best_ms:.2f} ms)")
-    outs = ctx.render_batch(handles, views, lights, tune=best, timing=True)
+    outs = ctx.render_batch(handles, views, lights, tune=best, timing=True, count=True)
     st = ctx.stage_times()
     say(f"[batch64] {st['total_ms']:.2f} ms, {st['primary_rays']} rays")
     for o in outs:
