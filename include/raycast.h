@@ -246,15 +246,21 @@ enum {
     RC_FLAG_TIMING = 1u,     /* record per-stage device times (rc_get_stage_times) */
     RC_FLAG_PER_LANE = 4u,     /* trace camera rays and shadow rays one ray per lane with per-lane stacks
                                   even where the wave-uniform traversal would be used (camera rays with
-                                  ssaa = 2; point- and rect-light shadow rays always; BVH depth <= 42,
-                                  under 2^25 nodes and 2^32 bytes of packed triangles); same results
-                                  outside the FP32 band, for comparison */
+                                  ssaa = 2; point-light shadow rays from 1.5M samples per light and
+                                  rect-light shadow rays from 3M rays per frame; BVH depth <= 42, under 2^25
+                                  nodes and 2^32 bytes of packed triangles); same results outside the FP32
+                                  band, for comparison */
     RC_FLAG_NO_SHADE = 8u,     /* rc_render: stop after the visibility stages; d_rgba and d_sample_rgba are
                                   left untouched (for a caller that shades later with rc_shade, e.g. from a
                                   denoised visibility) */
-    RC_FLAG_COUNT = 16u        /* rc_render: count rays cast, nodes visited and triangles tested
+    RC_FLAG_COUNT = 16u,       /* rc_render: count rays cast, nodes visited and triangles tested
                                   (rc_get_stage_times); without it the wave-uniform shadow kernels run
                                   without their counters */
+    RC_FLAG_WAVE = 32u         /* rc_render: shadow rays through the wave-uniform kernels (where the BVH
+                                  allows them) also for passes below the sizes above, which by default go
+                                  one ray per lane: a small pass lasts as long as its most divergent wave's
+                                  walk.  Same results outside the FP32 band.  With RC_FLAG_PER_LANE:
+                                  RC_ERR_INVALID_ARG */
 };
 
 typedef struct rc_render_opts {

@@ -20,6 +20,7 @@ RC_FLAG_PER_LANE = 4
 RC_FLAG_GRAPH = 2
 RC_FLAG_NO_SHADE = 8
 RC_FLAG_COUNT = 16
+RC_FLAG_WAVE = 32
 NO_HIT = 0xFFFFFFFF
 
 
@@ -249,7 +250,7 @@ class Context:
 
     def render(self, scene: "Scene", cam, lights=(), rect=None, area_samples: int = 0, area_stream: int = 0,
                timing: bool = False, sample_rgba: bool = False, out: Optional[dict] = None,
-               per_lane: bool = False, shade: bool = True, count: bool = False) -> dict:
+               per_lane: bool = False, shade: bool = True, count: bool = False, wave: bool = False) -> dict:
         torch = self.torch
         self._sync_stream()
         W, H, S = int(cam.width), int(cam.height), int(cam.ssaa) ** 2
@@ -271,7 +272,7 @@ class Context:
         srgba = get("sample_rgba", (H * W * S, 4), torch.float32) if sample_rgba else None
         o = RcOutputs(_dptr(rgba), _dptr(hit), _dptr(shadow), _dptr(vis), _dptr(srgba))
         flags = (RC_FLAG_TIMING if timing else 0) | (RC_FLAG_PER_LANE if per_lane else 0) | \
-            (0 if shade else RC_FLAG_NO_SHADE) | (RC_FLAG_COUNT if count else 0)
+            (0 if shade else RC_FLAG_NO_SHADE) | (RC_FLAG_COUNT if count else 0) | (RC_FLAG_WAVE if wave else 0)
         opts = RcRenderOpts(int(area_samples), int(area_stream), flags)
         camc = camera_struct(cam)
         rc = rect_struct(rect) if rect is not None else None

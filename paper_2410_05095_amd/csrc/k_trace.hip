@@ -990,7 +990,7 @@ void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, co
 
 void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
                       uint32_t* mask, float* visibility, uint32_t* counts, float4* setup, const TraceWork& w,
-                      int grid, bool per_lane, hipStream_t st)
+                      int grid, RcKernels kernels, hipStream_t st)
 {
     KParams P = {};
     P.sc = sc;
@@ -1003,11 +1003,23 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     P.n_items = rc_n_items(cam.width, cam.height, cam.ssaa);
     const bool two = sc.inst != nullptr, wt = sc.watertight != 0u;
     const bool count = w.ray_count != nullptr;   // the wave kernels count visits only when asked
-    // the wave-uniform kernels (the default) address nodes and triangles by 32-bit byte offsets and hold
-    // at most 128 stack entries; they read each sample's shadow-ray origin and normal from `setup`
-    const bool wave = sc.max_stack <= 128 && !per_lane && sc.n_nodes < (1u << 25) &&
-                      (uint64_t)sc.n_tris * 48u < (1ull << 32);
-    if (wave && (L.n_point > 0 || L.has_rect)) {
+    // the wave-uniform kernels address nodes and triangles by 32-bit byte offsets and hold at most 128 stack
+    // entries; they read each sample's shadow-ray origin and normal from `setup`
+    const bool wave_ok = sc.max_stack <= 128 && kernels != RC_KERNELS_LANE && sc.n_nodes < (1u << 25) &&
+                         (uint64_t)sc.n_tris * 48u < (1ull << 32);
+    // By default they serve the passes with many rays.  A wave-uniform pass cannot end before its slowest
+    // wave, whose 64 rays (an 8x8-pixel tile at one sample per pixel) may diverge over detailed geometry and
+    // walk the union of their paths, some hundreds of dependent node steps.  With few rays that walk sets the
+    // pass's duration and the per-lane kernels finish first; with many, the wave kernels' shared node loads
+    // win.  Measured on the 7.3M-triangle scene: one point light, per-lane / wave 0.24 / 0.46 ms at 960x540,
+    // 0.44 / 0.41 ms at 1920x1080, 1.23 / 0.79 ms at 3840x2160; rect light, 1 sample per pixel at 1080p
+    // 0.41 / 0.54 ms, 2 samples 0.62 / 0.53 ms, 1 sample at 2160p 1.10 / 0.89 ms.
+    const uint64_t n_samples_img = (uint64_t)cam.width * cam.height * cam.ssaa * cam.ssaa;
+    const bool big_point = n_samples_img >= 1500000u;
+    const bool big_rect = n_samples_img * (uint64_t)(L.has_rect ? L.area_samples : 0) >= 3000000u;
+    const bool wave_point = wave_ok && (kernels == RC_KERNELS_WAVE || big_point);
+    const bool wave_rect = wave_ok && (kernels == RC_KERNELS_WAVE || big_rect);
+    if ((wave_point && L.n_point > 0) || (wave_rect && L.has_rect)) {
         // one setup entry per sample of the image (the item count is padded to whole tiles)
         const uint32_t n_samples = (uint32_t)(cam.width * cam.height * cam.ssaa * cam.ssaa);
         hipLaunchKernelGGL(k_shadow_setup, dim3((n_samples + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_samples,
@@ -1015,7 +1027,7 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     }
     if (L.n_point > 0) {
         P.slot = 1;
-        if (wave) {
+        if (wave_point) {
             P.claim = claim_size((P.n_items + 63) / 64, grid, 64, 1, 4);
             if (sc.max_stack <= 64) {
                 if (count)
@@ -1048,10 +1060,9 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
         P.claim = claim_size(n_packets, grid, 64, 1, 4);
         uint32_t n_pix = (uint32_t)(cam.width * cam.height);
         rc_launch_fill_u32(counts, 0u, n_pix, st);
-        // the wave-uniform traversal, at every sample count: a wave holds the samples of one pixel, or of
-        // 64 / N neighbouring pixels, whose rays start close together (measured faster than the per-lane
-        // kernel from one sample per pixel on)
-        if (wave) {
+        // the wave-uniform traversal: a wave holds the samples of one pixel, or of 64 / N neighbouring
+        // pixels, whose rays start close together
+        if (wave_rect) {
             if (sc.max_stack <= 64) {
                 if (count)
                     RC_LAUNCH_TW((k_rect_wave<RC_TWO, RC_WT, false, true>), dim3(grid), dim3(BLOCK), 0, st, P, counts,

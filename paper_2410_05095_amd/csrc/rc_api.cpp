@@ -743,6 +743,7 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
     if ((reinterpret_cast<uintptr_t>(out->d_rgba) | reinterpret_cast<uintptr_t>(out->d_hit) |
          reinterpret_cast<uintptr_t>(out->d_sample_rgba)) & 15u)
         return RC_ERR_INVALID_ARG;
+    if (opts && (opts->flags & RC_FLAG_PER_LANE) && (opts->flags & RC_FLAG_WAVE)) return RC_ERR_INVALID_ARG;
     if (!s->built) return RC_ERR_NOT_BUILT;
     RC_HIP(hipSetDevice(c->device));
 
@@ -793,10 +794,12 @@ int rc_render(rc_ctx* c, rc_scene* s, const rc_camera* cam, const rc_point_light
             c->counts_cap = words;
         }
         w.ray_count = counting ? c->d_rays + 1 : nullptr;
-        bool per_lane = opts && (opts->flags & RC_FLAG_PER_LANE);
+        const RcKernels kern = !opts ? RC_KERNELS_AUTO
+                               : (opts->flags & RC_FLAG_PER_LANE) ? RC_KERNELS_LANE
+                               : (opts->flags & RC_FLAG_WAVE)     ? RC_KERNELS_WAVE
+                                                                  : RC_KERNELS_AUTO;
         float4* setup = reinterpret_cast<float4*>(c->d_counts + setup_off);
-        rc_launch_shadow(ds, dc, L, gbuf, out->d_shadow, out->d_visibility, c->d_counts, setup, w, c->grid, per_lane,
-                         q);
+        rc_launch_shadow(ds, dc, L, gbuf, out->d_shadow, out->d_visibility, c->d_counts, setup, w, c->grid, kern, q);
     }
     if (timing) RC_HIP(hipEventRecord(c->ev[2], q));
     if (!(opts && (opts->flags & RC_FLAG_NO_SHADE)))

@@ -133,9 +133,11 @@ struct TraceWork {
 // Launchers (k_trace.hip)
 void rc_launch_primary(const DevScene& sc, const DevCamera& cam, uint4* gbuf, const TraceWork& w,
                        int grid, bool per_lane, hipStream_t st);
+// shadow-ray kernels: chosen by pass size (AUTO), or forced one ray per lane or wave-uniform
+enum RcKernels { RC_KERNELS_AUTO = 0, RC_KERNELS_LANE = 1, RC_KERNELS_WAVE = 2 };
 void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,
                       uint32_t* mask, float* visibility, uint32_t* counts, float4* setup, const TraceWork& w,
-                      int grid, bool per_lane, hipStream_t st);
+                      int grid, RcKernels kernels, hipStream_t st);
 int rc_trace_grid(int device);
 // Display post pass (k_post.hip): tone map + sRGB8 into `out`, or into `scratch` followed by FXAA into `out`
 void rc_launch_postprocess(const float* rgba, uint32_t w, uint32_t h, bool fxaa, uint8_t* scratch, uint8_t* out,

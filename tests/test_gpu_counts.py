@@ -35,7 +35,7 @@ def test_per_lane_counts_match_instrumented_oracle(ctx, oracle_mod, seed, n_inst
     gs = ctx.scene_from(scene).build()
     got = {}
     for per_lane in (True, False):
-        ctx.render(gs, cam, (), rect=scene.rect_light, area_samples=N, area_stream=0, per_lane=per_lane, count=True)
+        ctx.render(gs, cam, (), rect=scene.rect_light, area_samples=N, area_stream=0, per_lane=per_lane, wave=not per_lane, count=True)
         torch.cuda.synchronize()
         assert ctx.last_error() == 0
         st = ctx.stage_times()

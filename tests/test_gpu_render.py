@@ -25,8 +25,9 @@ def ctx():
 
 def render_and_compare(ctx, O, scene, cam, rtol=1e-4, sample_idx=None, brute=False, device_build=False, gs=None,
                        osc=None):
-    """Render with the default kernels (wave-uniform camera rays) and with per-lane traversal, and check both
-    against one oracle run.  gs / osc: an already built GPU scene / oracle scene to use instead."""
+    """Render with per-lane traversal, with the wave-uniform kernels forced, and with the library's own
+    choice, and check each against one oracle run.  gs / osc: an already built GPU scene / oracle scene to use
+    instead."""
     import torch
     say(f"[render] {scene.name} {cam.width}x{cam.height} ssaa={cam.ssaa} tris={scene.n_tris} "
         f"build={'given' if gs is not None else ('device' if device_build else 'host')}")
@@ -37,15 +38,15 @@ def render_and_compare(ctx, O, scene, cam, rtol=1e-4, sample_idx=None, brute=Fal
     if osc is None:
         osc = O.OracleScene.from_scene(scene, use_bvh=not brute)
     orc = osc.render_point(cam, scene.point_lights, smp, brute=brute)
-    for per_lane in (True, False):
-        out = ctx.render(gs, cam, scene.point_lights, sample_rgba=True, per_lane=per_lane)
+    for mode, kw in (("per-lane", dict(per_lane=True)), ("wave", dict(wave=True)), ("auto", {})):
+        out = ctx.render(gs, cam, scene.point_lights, sample_rgba=True, **kw)
         torch.cuda.synchronize()
         assert ctx.last_error() == 0
         hit = to_np(out["hit"])[smp]
         mask = to_np(out["shadow"])[smp] if len(scene.point_lights) else None
         srgba = to_np(out["sample_rgba"])[smp]
         st = compare_point(hit, mask, srgba, orc, len(scene.point_lights), rtol=rtol)
-        say("[parity]", "per-lane" if per_lane else "wave", st)
+        say("[parity]", mode, st)
         assert_clean(st)
     # resolve: bit-exact against the fixed FP32 order applied to the GPU's own samples
     spp = cam.ssaa ** 2
@@ -162,6 +163,35 @@ def test_render_error_paths(ctx):
     with pytest.raises(N.RcError) as e:
         ctx.scene(scene.positions * np.nan, scene.indices, scene.tri_material, scene.materials)
     assert e.value.status == -2
+    with pytest.raises(N.RcError) as e:   # per-lane and wave-uniform kernels both forced
+        ctx.render(gs, scene.cameras[0], scene.point_lights, per_lane=True, wave=True)
+    assert e.value.status == -1
+    assert ctx.last_error() == 0
+
+
+def test_default_kernels_small_and_large_passes(ctx):
+    """The library traces small shadow passes one ray per lane and large ones wave-uniformly: a small frame
+    in the default mode equals the per-lane render bit for bit; rect-light frames above the ray threshold
+    equal the forced wave-uniform render."""
+    import dataclasses
+    import torch
+    scene = sg.small_random_scene(6, n_instances=40, width=96, height=64, n_lights=2)
+    gs = ctx.scene_from(scene).build()
+    cam = scene.cameras[0]
+    rect = scene.rect_light
+    cases = [(cam, dict(lights=scene.point_lights)), (cam, dict(rect=rect, area_samples=4, area_stream=0))]
+    big = dataclasses.replace(cam, width=512, height=384)
+    cases.append((big, dict(rect=rect, area_samples=16, area_stream=1)))   # 3.1M rays: the wave kernels
+    for i, (c, kw) in enumerate(cases):
+        res = {}
+        for mode, extra in (("auto", {}), ("lane", dict(per_lane=True)), ("wave", dict(wave=True))):
+            o = ctx.render(gs, c, shade=False, **kw, **extra)
+            torch.cuda.synchronize()
+            res[mode] = {k: v.clone() for k, v in o.items() if k in ("hit", "shadow", "visibility") and v is not None}
+        want = "wave" if i == 2 else "lane"
+        say(f"[kernels] case {i} {c.width}x{c.height}: default = {want}")
+        for k in res["auto"]:
+            assert torch.equal(res["auto"][k], res[want][k]), (i, k)
     assert ctx.last_error() == 0
 
 
@@ -243,7 +273,7 @@ def compare_rect(ctx, O, scene, cam, N, stream, pixels=None, device_build=False,
     outs = {}
     for per_lane in (False, True):
         outs[per_lane] = ctx.render(gs, cam, (), rect=scene.rect_light, area_samples=N, area_stream=stream,
-                                    sample_rgba=True, per_lane=per_lane)
+                                    sample_rgba=True, per_lane=per_lane, wave=not per_lane)
         torch.cuda.synchronize()
         assert ctx.last_error() == 0
     npix = cam.width * cam.height
