@@ -378,21 +378,25 @@ typedef struct rc_view {
     uint32_t* d_shadow;
 } rc_view;
 
-/* Tuning of the persistent batched kernel.  Zero fields take defaults (8, 8, 256, 40, max). */
+/* Tuning of the persistent batched kernels.  Zero fields take defaults (8, 8, 256, 40, max, 3). */
 typedef struct rc_tune {
     uint32_t tile_w, tile_h;   /* work-item tile in pixels; tile_w * tile_h in 16..1024 */
     uint32_t queue_depth;      /* pixels a wave claims per atomic on the device queue (64..4096, multiple of 64) */
     uint32_t min_rays;         /* rays per wave kept in flight: a wave refills its idle lanes when fewer are busy (1..64) */
-    uint32_t waves_per_simd;   /* resident waves per SIMD of the persistent grid (1..occupancy limit) */
+    uint32_t waves_per_simd;   /* resident waves per SIMD of the persistent grids (1..occupancy limit of the form's
+                                  largest kernel; each launch is capped at its own kernel's limit) */
+    uint32_t passes;           /* 1: one kernel traces, shades and resolves each pixel; 3: three kernels over all
+                                  views (camera rays, shadow rays, shading + resolve), each with its own work queue */
 } rc_tune;
 
 enum {
     RC_FLAG_GRAPH = 2u         /* rc_render_batch: capture the launch as a hipGraph once per batch shape, then replay */
 };
 
-/* Render all views in one persistent kernel launch fed by a device work queue (point lights and
- * 2x2 or 1 sample per pixel).  Every view's outputs are bit-identical to rc_render of that view
- * alone with RC_FLAG_PER_LANE (the same per-lane traversal), for any tuning.  flags: RC_FLAG_TIMING (rc_get_stage_times ms[3]), RC_FLAG_COUNT (its counts), RC_FLAG_GRAPH.  All
+/* Render all views in persistent launches fed by device work queues (point lights and 2x2 or 1
+ * sample per pixel): one launch, or one per stage (rc_tune.passes); with RC_FLAG_GRAPH one graph launch
+ * either way.  Every view's outputs are bit-identical to rc_render of that view
+ * alone with RC_FLAG_PER_LANE (the same per-lane traversal), for any tuning.  flags: RC_FLAG_TIMING (rc_get_stage_times ms[3]; with three passes and no graph also ms[0..2] per pass), RC_FLAG_COUNT (its counts: all rays in [0] for one pass, camera and shadow rays in [0] and [1] for three), RC_FLAG_GRAPH.  All
  * scenes must be built (flat BVHs: two-level structures give RC_ERR_UNSUPPORTED).  Errors:
  * RC_ERR_INVALID_ARG, RC_ERR_NOT_BUILT, RC_ERR_UNSUPPORTED, RC_ERR_HIP. */
 int rc_render_batch(rc_ctx* ctx, rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views, uint32_t n_views,

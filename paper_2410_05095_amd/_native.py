@@ -81,7 +81,7 @@ class RcView(C.Structure):
 
 class RcTune(C.Structure):
     _fields_ = [("tile_w", C.c_uint32), ("tile_h", C.c_uint32), ("queue_depth", C.c_uint32),
-                ("min_rays", C.c_uint32), ("waves_per_simd", C.c_uint32)]
+                ("min_rays", C.c_uint32), ("waves_per_simd", C.c_uint32), ("passes", C.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -1,11 +1,15 @@
-// Batched rendering megakernel: every view of every scene in one persistent launch.
+// Batched rendering: every view of every scene in persistent launches fed by device work queues.
 //
 // Work items are pixels of all views, numbered view by view in tiles of tile_w x tile_h pixels; a
 // wave claims `queue_depth` items per atomicAdd on its XCD's counter (XcdQueue) and hands them to its idle
-// lanes.  A lane renders its pixel completely: for each sample the camera ray (closest hit), the
-// shadow rays towards the view's point lights (any hit), FP64 shading, and finally the fixed-order
-// resolve.  The traversal, shading and resolve use the same device code as the single-view kernels,
-// so every view is bit-identical to its single-view render whatever the tuning.
+// lanes.  In the one-kernel form (PASS 0) a lane renders its pixel completely: for each sample the camera
+// ray (closest hit), the shadow rays towards the view's point lights (any hit), FP64 shading, and finally
+// the fixed-order resolve.  In the three-kernel form the same stages run as three launches over all views:
+// camera rays into the views' hit buffers (PASS 1), shadow rays into their masks (PASS 2), shading and
+// resolve (PASS 3).  Each launch then holds only its own stage's code: the camera-ray kernel needs no FP64
+// registers, and no kernel keeps a lane's FP64 shading state across a traversal.  The traversal, shading
+// and resolve use the same device code as the single-view kernels, so every view is bit-identical to its
+// single-view render whatever the form and tuning.
 #include "rc_trav.h"
 
 namespace {
@@ -23,8 +27,10 @@ __device__ inline uint32_t find_view(const DevView* views, uint32_t n, uint32_t 
     return lo;
 }
 
+template <int PASS>
 __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
 {
+    static_assert(PASS >= 0 && PASS <= 3, "pass");
     const int tid = threadIdx.x;
     const uint32_t lane = __lane_id();
     const uint32_t glane = blockIdx.x * BLOCK + tid;
@@ -42,20 +48,25 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
     sc.tris = nullptr;
     TravRay ray;
     TravState ts;
-    const XcdQueue<256> queue(P.w.counters, 3, P.n_items);
+    const XcdQueue<256> queue(P.w.counters, PASS <= 1 ? 3u : (uint32_t)PASS + 2u, P.n_items);
     uint32_t q_next = 0, q_end = 0;   // wave-local range of claimed positions of the XCD's share (wave-uniform)
     bool queue_empty = false;
     uint32_t rays_cast = 0, node_visits = 0, tri_tests = 0;
 
-    auto start_sample = [&]() {
-        const DevView& V = P.views[v];
-        rc_camera_ray(V.cam, px, k, ray.o, ray.d);
+    // camera ray of sample k of pixel px (a closure without captures: the camera kernel keeps every lane's
+    // ray and traversal state in registers only if no closure object holds their addresses)
+    const auto start_camera = [](const DevCamera& cam, uint32_t px, uint32_t k, TravRay& ray, TravState& ts,
+                                 uint32_t& rays_cast, int& state) __attribute__((always_inline)) {
+        rc_camera_ray(cam, px, k, ray.o, ray.d);
         trav_begin(ray, ts);
         ++rays_cast;
         state = 1;
     };
+    auto start_sample = [&]() __attribute__((always_inline)) {
+        start_camera(P.views[v].cam, px, k, ray, ts, rays_cast, state);
+    };
 
-    auto next_shadow = [&]() -> bool {
+    auto next_shadow = [&]() __attribute__((always_inline)) -> bool {
         const DevView& V = P.views[v];
         while (j < n_l) {
             if (rc_shadow_ray(P.lights + 6 * (size_t)(V.light_first + j), nullptr, nullptr, false, px, j, 0u,
@@ -70,8 +81,57 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
         return false;
     };
 
-    // sample k is done: write its mask, shade it, fold it into the resolve; next sample or pixel
-    auto finish_sample = [&]() {
+    // shadow pass: from sample k on, the first sample whose camera ray hit starts its shadow rays; samples
+    // before it get their (empty) masks; the pixel is done when none is left
+    auto shadow_sample = [&]() __attribute__((always_inline)) {
+        const DevView& V = P.views[v];
+        for (; k < spp; ++k) {
+            const size_t s = (size_t)px * spp + k;
+            hid = V.hit[s].x;
+            mask = 0;
+            j = 0;
+            if (hid != RC_NO_HIT) {
+                DevScene full = P.scenes[V.scene];
+                Surface Sf = rc_surface(full, V.cam, px, k, hid);
+                D3 O = rc_shadow_origin(Sf);
+                os[0] = (float)O.x; os[1] = (float)O.y; os[2] = (float)O.z;
+                nf[0] = (float)Sf.n.x; nf[1] = (float)Sf.n.y; nf[2] = (float)Sf.n.z;
+                if (next_shadow()) return;
+            }
+            V.shadow[s] = mask;
+        }
+        state = 0;
+    };
+
+    // shading pass: every sample of the pixel from its hit and mask, folded in the resolve's order
+    auto shade_pixel = [&]() __attribute__((always_inline)) {
+        const DevView& V = P.views[v];
+        const DevScene full = P.scenes[V.scene];
+        float4 c4[4];
+        for (uint32_t q = 0; q < spp; ++q) {
+            const size_t s = (size_t)px * spp + q;
+            const uint32_t h = V.hit[s].x;
+            c4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (h != RC_NO_HIT)
+                c4[q] = rc_shade_sample(full, V.cam, P.lights + 6 * (size_t)V.light_first, (int)V.n_lights, nullptr,
+                                        0.0, px, q, h, V.shadow ? V.shadow[s] : 0u);
+        }
+        if (spp == 1) {
+            reinterpret_cast<float4*>(V.rgba)[px] = c4[0];
+            return;
+        }
+        float4 pr, b, r;
+        pr.x = c4[0].x + c4[1].x; pr.y = c4[0].y + c4[1].y; pr.z = c4[0].z + c4[1].z; pr.w = c4[0].w + c4[1].w;
+        b.x = c4[2].x + c4[3].x; b.y = c4[2].y + c4[3].y; b.z = c4[2].z + c4[3].z; b.w = c4[2].w + c4[3].w;
+        r.x = (pr.x + b.x) * 0.25f; r.y = (pr.y + b.y) * 0.25f;
+        r.z = (pr.z + b.z) * 0.25f; r.w = (pr.w + b.w) * 0.25f;
+        reinterpret_cast<float4*>(V.rgba)[px] = r;
+    };
+
+    // sample k is done: write its mask, shade it, fold it into the resolve; next sample or pixel (one-kernel
+    // form only: elsewhere the body is discarded, so that no closure holds the others' state in memory)
+    auto finish_sample = [&]() __attribute__((always_inline)) {
+      if constexpr (PASS == 0) {
         const DevView& V = P.views[v];
         size_t s = (size_t)px * spp + k;
         if (V.shadow) V.shadow[s] = mask;
@@ -101,9 +161,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
         }
         ++k;
         start_sample();
+      }
     };
 
-    auto start_item = [&](uint32_t item) -> bool {
+    auto start_item = [&](uint32_t item) __attribute__((always_inline)) -> bool {
         v = find_view(P.views, P.n_views, item);
         const DevView& V = P.views[v];
         uint32_t local = item - V.item_first;
@@ -118,12 +179,35 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
         sc.nodes = S.nodes;
         sc.tris = S.tris;
         k = 0;
-        start_sample();
-        return true;
+        if constexpr (PASS == 3) {
+            shade_pixel();
+            return false;
+        } else if constexpr (PASS == 2) {
+            if (n_l == 0) return false;
+            shadow_sample();
+            return state != 0;
+        } else {
+            start_camera(V.cam, px, k, ray, ts, rays_cast, state);
+            return true;
+        }
     };
 
-    auto end_ray = [&](bool occluded) {
-        if (state == 1) {
+    auto end_ray = [&](bool occluded) __attribute__((always_inline)) {
+        if constexpr (PASS == 1) {   // camera ray done: its hit; next sample or pixel
+            (void)occluded;
+            const DevView& V = P.views[v];
+            V.hit[(size_t)px * spp + k] =
+                make_uint4(ts.best_id, __float_as_uint(ts.best_t), __float_as_uint(ts.best_u), __float_as_uint(ts.best_v));
+            if (++k < spp) start_camera(V.cam, px, k, ray, ts, rays_cast, state);
+            else state = 0;
+        } else if constexpr (PASS == 2) {   // shadow ray done: next light, else the sample's mask and the next one
+            if (!occluded) mask |= 1u << j;
+            ++j;
+            if (next_shadow()) return;
+            P.views[v].shadow[(size_t)px * spp + k] = mask;
+            ++k;
+            shadow_sample();
+        } else if (state == 1) {
             const DevView& V = P.views[v];
             V.hit[(size_t)px * spp + k] =
                 make_uint4(ts.best_id, __float_as_uint(ts.best_t), __float_as_uint(ts.best_u), __float_as_uint(ts.best_v));
@@ -169,13 +253,16 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
             q_next += min(avail, (uint32_t)__popcll(need));
         }
         if (__ballot(state != 0) == 0) break;
+        if constexpr (PASS == 3) continue;   // no traversal: lanes stay idle and refill until the queue is done
 
         for (;;) {
             uint32_t occluded = 0u;
-            // at most 16 node rounds and 4 leaf rounds per step: 64 views in 28.4 instead of 29.6 ms (3 and 1,
-            // the camera kernel's bounds, took 38 ms here, where camera and shadow rays share a wave)
-            trav_advance<false, false, 16, 4>(sc, ray, ts, st, state != 0, state == 2, occluded, node_visits,
-                                              tri_tests);
+            // bounded traversal phases per step.  Where camera and shadow rays share a wave (one kernel), 16 node
+            // rounds and 4 leaf rounds: 64 views in 28.4 instead of 29.6 ms unbounded (3 and 1 took 38 ms);
+            // the one-stage kernels take the single-view kernels' 3 and 1
+            constexpr int NODE_STEPS = PASS == 0 ? 16 : 3, LEAF_STEPS = PASS == 0 ? 4 : 1;
+            trav_advance<false, false, NODE_STEPS, LEAF_STEPS>(sc, ray, ts, st, state != 0, state == 2, occluded,
+                                                               node_visits, tri_tests);
             if (state != 0 && ts.cur == RC_STACK_EMPTY) end_ray(occluded != 0u);
             uint32_t n_act = (uint32_t)__popcll(__ballot(state != 0));
             if (n_act == 0) break;
@@ -189,26 +276,43 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
         for (int q = 0; q < 3; ++q) {
             unsigned long long vv = cnt[q];
             for (int off = 32; off > 0; off >>= 1) vv += __shfl_xor(vv, off);
-            if (lane == 0) atomicAdd(P.w.ray_count + 2 * q, vv);
+            // the shadow pass counts into the second slot of each pair (the one-kernel form counts all rays in
+            // the first)
+            if (lane == 0) atomicAdd(P.w.ray_count + 2 * q + (PASS == 2 ? 1 : 0), vv);
         }
     }
 }
 
 }  // namespace
 
-int rc_batch_max_blocks_per_cu(int device)
+static const void* batch_kernel(int pass)
+{
+    switch (pass) {
+    case 1: return reinterpret_cast<const void*>(&k_batch<1>);
+    case 2: return reinterpret_cast<const void*>(&k_batch<2>);
+    case 3: return reinterpret_cast<const void*>(&k_batch<3>);
+    default: return reinterpret_cast<const void*>(&k_batch<0>);
+    }
+}
+
+int rc_batch_max_blocks_per_cu(int device, int pass)
 {
     int blocks = 0;
     (void)device;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(&k_batch), BLOCK,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel(pass), BLOCK,
                                                      TravStack<SL, BLOCK, true>::lds_bytes()) != hipSuccess)
         blocks = 1;
     return blocks < 1 ? 1 : blocks;
 }
 
-void rc_launch_batch(const BatchParams& P, int grid, hipStream_t st)
+void rc_launch_batch(const BatchParams& P, int pass, int grid, hipStream_t st)
 {
-    const size_t lds = TravStack<SL, BLOCK, true>::lds_bytes();
+    const size_t lds = pass == 3 ? 0 : TravStack<SL, BLOCK, true>::lds_bytes();
     if (grid < (int)RC_XCDS) grid = RC_XCDS;   // every XCD share of the queue needs workgroups
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), lds, st, P);
+    switch (pass) {
+    case 1: hipLaunchKernelGGL(k_batch<1>, dim3(grid), dim3(BLOCK), lds, st, P); break;
+    case 2: hipLaunchKernelGGL(k_batch<2>, dim3(grid), dim3(BLOCK), lds, st, P); break;
+    case 3: hipLaunchKernelGGL(k_batch<3>, dim3(grid), dim3(BLOCK), lds, st, P); break;
+    default: hipLaunchKernelGGL(k_batch<0>, dim3(grid), dim3(BLOCK), lds, st, P); break;
+    }
 }

@@ -950,12 +950,27 @@ int check_tune(rc_tune* t, int max_wps)
     if (t->tile_h == 0) t->tile_h = 8;
     if (t->queue_depth == 0) t->queue_depth = 256;
     if (t->min_rays == 0) t->min_rays = 40;
+    if (t->passes == 0) t->passes = 3;
+    if (t->passes != 1 && t->passes != 3) return RC_ERR_INVALID_ARG;
     if (t->waves_per_simd == 0 || t->waves_per_simd > (uint32_t)max_wps) t->waves_per_simd = (uint32_t)max_wps;
     uint32_t tp = t->tile_w * t->tile_h;
     if (tp < 16 || tp > 1024 || t->queue_depth < 64 || t->queue_depth > 4096 || t->queue_depth % 64 ||
         t->min_rays > 64)
         return RC_ERR_INVALID_ARG;
     return RC_OK;
+}
+
+// resident waves per SIMD allowed by the occupancy of a batch kernel (pass 0: the one-kernel form)
+int batch_wps_limit(int device, int pass)
+{
+    return std::max(1, rc_batch_max_blocks_per_cu(device, pass) * (RC_TRACE_BLOCK / 64) / 4);
+}
+
+// largest limit among the kernels of a form (1 pass: the one kernel; 3: camera, shadow and shading kernels)
+int batch_form_wps(int device, uint32_t passes)
+{
+    if (passes == 1) return batch_wps_limit(device, 0);
+    return std::max(batch_wps_limit(device, 1), std::max(batch_wps_limit(device, 2), batch_wps_limit(device, 3)));
 }
 
 struct BatchPlan {
@@ -1023,17 +1038,21 @@ int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc
     RC_HIP(hipSetDevice(c->device));
     int n_cu = 0;
     RC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
-    int max_blocks = rc_batch_max_blocks_per_cu(c->device);
-    int max_wps = std::max(1, max_blocks * (RC_TRACE_BLOCK / 64) / 4);
-    rc_tune t = tune_in ? *tune_in : rc_tune{0, 0, 0, 0, 0};
-    int st = check_tune(&t, max_wps);
+    rc_tune t = tune_in ? *tune_in : rc_tune{0, 0, 0, 0, 0, 0};
+    const uint32_t passes_in = t.passes == 0 ? 3u : t.passes;
+    if (passes_in != 1 && passes_in != 3) return RC_ERR_INVALID_ARG;
+    int st = check_tune(&t, batch_form_wps(c->device, passes_in));
     if (st != RC_OK) return st;
     BatchPlan bp;
     st = plan_batch(scenes, n_scenes, views, n_views, lights, n_lights_total, t, bp);
     if (st != RC_OK) return st;
-    int blocks_per_cu = std::max(1, (int)(t.waves_per_simd * 4) / (RC_TRACE_BLOCK / 64));
-    blocks_per_cu = std::min(blocks_per_cu, max_blocks);
-    int grid = n_cu * blocks_per_cu;
+    // persistent grid of each launch: the requested waves per SIMD, capped at that kernel's own occupancy
+    const int blocks_req = std::max(1, (int)(t.waves_per_simd * 4) / (RC_TRACE_BLOCK / 64));
+    int grids[4] = {0, 0, 0, 0};
+    for (int p = 0; p < 4; ++p)
+        if ((p == 0) == (t.passes == 1))
+            grids[p] = n_cu * std::min(blocks_req, rc_batch_max_blocks_per_cu(c->device, p));
+    const int grid = std::max(std::max(grids[0], grids[1]), std::max(grids[2], grids[3]));
 
     // overflow stack area for this grid
     uint32_t depth = bp.max_stack > RC_STACK_LDS ? bp.max_stack - RC_STACK_LDS : 0;
@@ -1079,7 +1098,7 @@ int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc
     P.lights = reinterpret_cast<const float*>(c->d_table + bp.off_lights);
     P.n_views = n_views;
     P.n_items = bp.n_items;
-    P.tune = BatchTune{t.tile_w, t.tile_h, t.queue_depth, t.min_rays, t.waves_per_simd};
+    P.tune = BatchTune{t.tile_w, t.tile_h, t.queue_depth, t.min_rays, t.waves_per_simd, t.passes};
     P.w.counters = c->d_counters;
     P.w.overflow = c->d_overflow;
     P.w.overflow_depth = depth;
@@ -1091,7 +1110,7 @@ int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc
     if (timing) RC_HIP(hipEventRecord(c->ev[0], c->stream));
     if (flags & RC_FLAG_GRAPH) {
         uint64_t key = fnv1a(1469598103934665603ull, &P, sizeof(P));
-        key = fnv1a(key, &grid, sizeof(grid));
+        key = fnv1a(key, grids, sizeof(grids));
         if (key != c->graph_key || !c->graph_exec) {
             if (c->graph_exec) { hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
             if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
@@ -1100,7 +1119,8 @@ int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc
             rc_launch_fill_u32(c->d_counters, 0u, 8, c->capture_stream);   // not word 8: the sticky error flag
             rc_launch_fill_u32(c->d_counters + RC_QUEUE_BASE, 0u, RC_COUNTER_WORDS - RC_QUEUE_BASE, c->capture_stream);
             rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, c->capture_stream);
-            rc_launch_batch(P, grid, c->capture_stream);
+            for (int p = 0; p < 4; ++p)
+                if (grids[p]) rc_launch_batch(P, p, grids[p], c->capture_stream);
             hipError_t e = hipStreamEndCapture(c->capture_stream, &c->graph);
             if (e != hipSuccess) return RC_ERR_HIP;
             RC_HIP(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
@@ -1111,11 +1131,20 @@ int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc
         rc_launch_fill_u32(c->d_counters, 0u, 8, c->stream);   // not word 8: the sticky error flag
         rc_launch_fill_u32(c->d_counters + RC_QUEUE_BASE, 0u, RC_COUNTER_WORDS - RC_QUEUE_BASE, c->stream);
         rc_launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_rays), 0u, 16, c->stream);
-        rc_launch_batch(P, grid, c->stream);
+        if (t.passes == 1) {
+            rc_launch_batch(P, 0, grids[0], c->stream);
+        } else {
+            // events between the stages: per-pass times in rc_get_stage_times ms[0..2]
+            rc_launch_batch(P, 1, grids[1], c->stream);
+            if (timing) RC_HIP(hipEventRecord(c->ev[1], c->stream));
+            rc_launch_batch(P, 2, grids[2], c->stream);
+            if (timing) RC_HIP(hipEventRecord(c->ev[2], c->stream));
+            rc_launch_batch(P, 3, grids[3], c->stream);
+        }
     }
     if (timing) RC_HIP(hipEventRecord(c->ev[3], c->stream));
     c->timed = timing;
-    c->timed_batch = true;
+    c->timed_batch = !(t.passes == 3 && !(flags & RC_FLAG_GRAPH));
     RC_HIP(hipGetLastError());
     return RC_OK;
 }
@@ -1168,7 +1197,9 @@ bool cache_lookup(const char* path, const std::string& key, rc_tune* t, float* m
         if (read_field(line, "tile_w", &a) && read_field(line, "tile_h", &b) && read_field(line, "queue_depth", &q) &&
             read_field(line, "min_rays", &m) && read_field(line, "waves_per_simd", &w)) {
             read_field(line, "ms", &x);
-            *t = rc_tune{(uint32_t)a, (uint32_t)b, (uint32_t)q, (uint32_t)m, (uint32_t)w};
+            double ps = 1;   // entries written before the three-kernel form existed were one-kernel tunings
+            read_field(line, "passes", &ps);
+            *t = rc_tune{(uint32_t)a, (uint32_t)b, (uint32_t)q, (uint32_t)m, (uint32_t)w, (uint32_t)ps};
             *ms = (float)x;
             found = true;
         }
@@ -1197,7 +1228,7 @@ int rc_autotune(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc_
     std::string key;
     if (cache_path) {
         BatchPlan probe;
-        rc_tune d = {8, 8, 256, 40, 1};
+        rc_tune d = {8, 8, 256, 40, 1, 3};
         int st = plan_batch(scenes, n_scenes, views, n_views, lights, n_lights_total, d, probe);
         if (st != RC_OK) return st;
         key = tune_key(c, scenes, n_scenes, views, n_views);
@@ -1211,15 +1242,17 @@ int rc_autotune(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc_
     if (candidates && n_candidates) {
         cand.assign(candidates, candidates + n_candidates);
     } else {
-        int max_blocks = rc_batch_max_blocks_per_cu(c->device);
-        uint32_t max_wps = (uint32_t)std::max(1, max_blocks * (RC_TRACE_BLOCK / 64) / 4);
         const uint32_t tiles[3][2] = {{8, 8}, {16, 8}, {16, 16}};
         const uint32_t depths[3] = {64, 256, 1024};
         const uint32_t mins[3] = {16, 32, 48};
-        for (auto& tl : tiles)
-            for (uint32_t q : depths)
-                for (uint32_t m : mins)
-                    for (uint32_t w = max_wps; w + 1 >= max_wps && w >= 1; --w) cand.push_back(rc_tune{tl[0], tl[1], q, m, w});
+        for (uint32_t passes : {1u, 3u}) {
+            const uint32_t max_wps = (uint32_t)batch_form_wps(c->device, passes);
+            for (auto& tl : tiles)
+                for (uint32_t q : depths)
+                    for (uint32_t m : mins)
+                        for (uint32_t w = max_wps; w + 1 >= max_wps && w >= 1; --w)
+                            cand.push_back(rc_tune{tl[0], tl[1], q, m, w, passes});
+        }
     }
     hipEvent_t e0, e1;
     RC_HIP(hipEventCreate(&e0));
@@ -1250,9 +1283,9 @@ int rc_autotune(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc_
         FILE* f = fopen(cache_path, "a");
         if (f) {
             fprintf(f, "{\"key\":\"%s\",\"tile_w\":%u,\"tile_h\":%u,\"queue_depth\":%u,\"min_rays\":%u,"
-                       "\"waves_per_simd\":%u,\"ms\":%.4f}\n",
+                       "\"waves_per_simd\":%u,\"passes\":%u,\"ms\":%.4f}\n",
                     key.c_str(), best->tile_w, best->tile_h, best->queue_depth, best->min_rays, best->waves_per_simd,
-                    best_t);
+                    best->passes, best_t);
             fclose(f);
         }
     }

@@ -116,7 +116,7 @@ hipError_t rc_tlas_build(TlasWork& w, const float* o2w, Node4* nodes, uint32_t t
 // (an input a kernel cannot use, e.g. a hit id beyond the scene); from word RC_QUEUE_BASE, per queue slot
 // one counter per XCD, each on its own 256-byte line.
 #define RC_XCDS 8
-#define RC_QUEUE_SLOTS 4
+#define RC_QUEUE_SLOTS 6
 #define RC_QUEUE_BASE 64
 #define RC_COUNTER_WORDS (RC_QUEUE_BASE + RC_QUEUE_SLOTS * RC_XCDS * 64)
 #define RC_STACK_LDS 12
@@ -167,6 +167,7 @@ struct BatchTune {
     uint32_t queue_depth;         // items a wave claims per atomic (multiple of 64)
     uint32_t min_rays;            // a wave refills its idle lanes once fewer rays are in flight
     uint32_t waves_per_simd;      // resident waves per SIMD of the persistent grid
+    uint32_t passes;              // 1: one kernel per pixel's whole render; 3: one kernel per stage
 };
 
 struct BatchParams {
@@ -179,8 +180,9 @@ struct BatchParams {
     TraceWork w;
 };
 
-void rc_launch_batch(const BatchParams& P, int grid, hipStream_t st);
-int rc_batch_max_blocks_per_cu(int device);
+// pass 0: the one-kernel form; 1, 2, 3: camera rays, shadow rays, shading + resolve (work-queue slots 3, 4, 5)
+void rc_launch_batch(const BatchParams& P, int pass, int grid, hipStream_t st);
+int rc_batch_max_blocks_per_cu(int device, int pass);
 
 // Launchers (k_shade.hip)
 void rc_launch_shade(const DevScene& sc, const DevCamera& cam, const DevLights& L, const uint4* gbuf,

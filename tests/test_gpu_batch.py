@@ -70,9 +70,12 @@ def small_batch():
 
 
 TUNES = [None,
-         dict(tile_w=4, tile_h=4, queue_depth=64, min_rays=1, waves_per_simd=1),
-         dict(tile_w=32, tile_h=32, queue_depth=4096, min_rays=64, waves_per_simd=0),
-         dict(tile_w=16, tile_h=4, queue_depth=128, min_rays=24, waves_per_simd=2)]
+         dict(tile_w=4, tile_h=4, queue_depth=64, min_rays=1, waves_per_simd=1, passes=1),
+         dict(tile_w=32, tile_h=32, queue_depth=4096, min_rays=64, waves_per_simd=0, passes=1),
+         dict(tile_w=16, tile_h=4, queue_depth=128, min_rays=24, waves_per_simd=2, passes=1),
+         dict(tile_w=4, tile_h=4, queue_depth=64, min_rays=1, waves_per_simd=1, passes=3),
+         dict(tile_w=32, tile_h=32, queue_depth=4096, min_rays=64, waves_per_simd=0, passes=3),
+         dict(tile_w=16, tile_h=4, queue_depth=128, min_rays=24, waves_per_simd=2, passes=3)]
 
 
 def test_batch_bit_identical_to_single_views(ctx):
@@ -89,14 +92,16 @@ def test_batch_bit_identical_to_single_views(ctx):
         say(f"[batch] tune {tune}: {len(views)} views identical")
 
 
-def test_batch_graph_replays(ctx):
+@pytest.mark.parametrize("passes", [3, 1])
+def test_batch_graph_replays(ctx, passes):
     import torch
     scenes, cams = small_batch()
     handles, views, lights = build_batch(ctx, scenes, cams)
     ref = single_renders(ctx, scenes, handles, views)
+    tune = dict(tile_w=8, tile_h=8, queue_depth=256, min_rays=40, waves_per_simd=0, passes=passes)
     outs = None
     for rep in range(4):
-        outs = ctx.render_batch(handles, views, lights, graph=True, outs=outs)
+        outs = ctx.render_batch(handles, views, lights, tune=tune, graph=True, outs=outs)
         torch.cuda.synchronize()
         # eager work between replays
         x = torch.randn(1 << 16, device="cuda").sum().item()
@@ -110,7 +115,7 @@ def test_batch_graph_replays(ctx):
     moved = [(si, sg.Camera(**{**cam.__dict__, "eye": (cam.eye[0] + 1.0, cam.eye[1], cam.eye[2])}), lf, nl)
              for si, cam, lf, nl in views]
     ref2 = single_renders(ctx, scenes, handles, moved)
-    outs = ctx.render_batch(handles, moved, lights, graph=True, outs=outs)
+    outs = ctx.render_batch(handles, moved, lights, tune=tune, graph=True, outs=outs)
     torch.cuda.synchronize()
     for i in range(len(views)):
         assert same(outs[i], ref2[i]) is None
@@ -120,8 +125,8 @@ def test_batch_graph_replays(ctx):
 def test_autotune_and_cache(ctx):
     scenes, cams = small_batch()
     handles, views, lights = build_batch(ctx, scenes, cams)
-    cands = [dict(tile_w=8, tile_h=8, queue_depth=256, min_rays=40, waves_per_simd=0),
-             dict(tile_w=16, tile_h=16, queue_depth=64, min_rays=16, waves_per_simd=1)]
+    cands = [dict(tile_w=8, tile_h=8, queue_depth=256, min_rays=40, waves_per_simd=0, passes=3),
+             dict(tile_w=16, tile_h=16, queue_depth=64, min_rays=16, waves_per_simd=1, passes=1)]
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tune.jsonl")
         best, ms = ctx.autotune(handles, views, lights, candidates=cands, reps=2, cache_path=path)
@@ -148,7 +153,7 @@ def test_batch_64_views_4_scenes(ctx, oracle_mod):
     say(f"[batch64] autotuned: {best} ({best_ms:.2f} ms)")
     outs = ctx.render_batch(handles, views, lights, tune=best, timing=True, count=True)
     st = ctx.stage_times()
-    say(f"[batch64] {st['total_ms']:.2f} ms, {st['primary_rays']} rays")
+    say(f"[batch64] {st['total_ms']:.2f} ms, {st['primary_rays'] + st['shadow_rays']} rays")
     for o in outs:
         for k in o:
             if o[k] is not None:
