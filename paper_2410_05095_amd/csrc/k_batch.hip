@@ -27,8 +27,12 @@ __device__ inline uint32_t find_view(const DevView* views, uint32_t n, uint32_t 
     return lo;
 }
 
+// Register budgets of the one-stage kernels (64 views, three-kernel form): the camera-ray kernel at 6 waves per
+// SIMD (80 registers) 3.74 against 4.21 ms at its natural 104; the shadow-ray kernel at 4 (128 registers)
+// 5.47 against 6.32 ms at 136; 5 waves spill and took 8.3 ms.
 template <int PASS>
-__global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 6 : PASS == 2 ? 4 : 1)))
+void k_batch(BatchParams P)
 {
     static_assert(PASS >= 0 && PASS <= 3, "pass");
     const int tid = threadIdx.x;
@@ -258,9 +262,11 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchParams P)
         for (;;) {
             uint32_t occluded = 0u;
             // bounded traversal phases per step.  Where camera and shadow rays share a wave (one kernel), 16 node
-            // rounds and 4 leaf rounds: 64 views in 28.4 instead of 29.6 ms unbounded (3 and 1 took 38 ms);
-            // the one-stage kernels take the single-view kernels' 3 and 1
-            constexpr int NODE_STEPS = PASS == 0 ? 16 : 3, LEAF_STEPS = PASS == 0 ? 4 : 1;
+            // rounds and 4 leaf rounds: 64 views in 28.4 instead of 29.6 ms unbounded (3 and 1 took 38 ms).
+            // Camera rays alone: 3 and 1, as in the single-view kernel (2 and 1, 4 and 2 were slower).  Shadow
+            // rays alone: 8 and 2 (5.34 against 5.47 ms for 3 and 1, 16 and 4 in between)
+            constexpr int NODE_STEPS = PASS == 0 ? 16 : PASS == 1 ? 3 : 8;
+            constexpr int LEAF_STEPS = PASS == 0 ? 4 : PASS == 1 ? 1 : 2;
             trav_advance<false, false, NODE_STEPS, LEAF_STEPS>(sc, ray, ts, st, state != 0, state == 2, occluded,
                                                                node_visits, tri_tests);
             if (state != 0 && ts.cur == RC_STACK_EMPTY) end_ray(occluded != 0u);
