@@ -17,16 +17,6 @@ namespace {
 constexpr int BLOCK = RC_TRACE_BLOCK;
 constexpr int SL = RC_STACK_LDS;
 
-__device__ inline uint32_t find_view(const DevView* views, uint32_t n, uint32_t item)
-{
-    uint32_t lo = 0, hi = n;   // largest v with item_first <= item
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (views[mid].item_first <= item) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 // Register budgets of the one-stage kernels (64 views, three-kernel form): the camera-ray kernel at 6 waves per
 // SIMD (80 registers) 3.74 against 4.21 ms at its natural 104; the shadow-ray kernel at 4 (128 registers)
 // 5.47 against 6.32 ms at 136; 5 waves spill and took 8.3 ms.
@@ -41,7 +31,6 @@ void k_batch(BatchParams P)
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     TravStack<SL, BLOCK, true> st{tid, reinterpret_cast<uint2*>(P.w.overflow), P.w.overflow_depth, P.w.n_lanes,
                                   glane, P.w.error_flag};
-    const uint32_t tile_pix = P.tune.tile_w * P.tune.tile_h;
 
     int state = 0;                 // 0 idle, 1 camera ray, 2 shadow ray
     uint32_t v = 0, px = 0, k = 0, spp = 1, j = 0, n_l = 0, mask = 0, hid = RC_NO_HIT;
@@ -169,14 +158,9 @@ void k_batch(BatchParams P)
     };
 
     auto start_item = [&](uint32_t item) __attribute__((always_inline)) -> bool {
-        v = find_view(P.views, P.n_views, item);
+        v = rc_find_view(P.views, P.n_views, item);
         const DevView& V = P.views[v];
-        uint32_t local = item - V.item_first;
-        uint32_t tile = local / tile_pix, w = local % tile_pix;
-        uint32_t i = (tile % V.tiles_x) * P.tune.tile_w + w % P.tune.tile_w;
-        uint32_t jj = (tile / V.tiles_x) * P.tune.tile_h + w / P.tune.tile_w;
-        if (i >= (uint32_t)V.cam.width || jj >= (uint32_t)V.cam.height) return false;
-        px = jj * (uint32_t)V.cam.width + i;
+        if (!rc_batch_pixel(V, P.tune, item, px)) return false;
         spp = (uint32_t)(V.cam.ssaa * V.cam.ssaa);
         n_l = V.n_lights;
         const DevScene& S = P.scenes[V.scene];

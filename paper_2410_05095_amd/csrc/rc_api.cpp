@@ -123,8 +123,10 @@ int ensure_overflow(rc_ctx* c, uint32_t max_stack)
     uint32_t depth = max_stack > RC_STACK_LDS ? max_stack - RC_STACK_LDS : 0;
     size_t words = (size_t)c->grid * RC_TRACE_BLOCK * depth * 2;
     if (words <= c->overflow_words && c->d_overflow) return RC_OK;
+    RC_HIP(hipStreamSynchronize(c->stream));
     dev_free(c->d_overflow);
     c->overflow_words = 0;
+    c->graph_key = 0;   // a captured batch graph points at the old buffer
     int st = dev_alloc(&c->d_overflow, words);
     if (st != RC_OK) return st;
     c->overflow_words = words;

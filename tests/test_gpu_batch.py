@@ -122,6 +122,37 @@ def test_batch_graph_replays(ctx, passes):
     assert ctx.last_error() == 0
 
 
+def test_batch_graph_after_buffer_growth():
+    """A single-view render that grows the context's overflow stack area between two launches of a captured
+    batch graph: the context captures again instead of replaying into the freed area."""
+    import torch
+    from paper_2410_05095_amd import _native as N
+    from tests.test_gpu_render import deep_scene
+    c2 = N.Context(0)
+    scenes, cams = small_batch()
+    handles, views, lights = build_batch(c2, scenes, cams)
+    ref = single_renders(c2, scenes, handles, views)
+    outs = c2.render_batch(handles, views, lights, graph=True)
+    torch.cuda.synchronize()
+    deep = deep_scene()
+    gd = c2.scene_from(deep).build()
+    c2.render(gd, deep.cameras[0], (), rect=deep.rect_light, area_samples=4, area_stream=0, per_lane=True)
+    torch.cuda.synchronize()
+    for o in outs:
+        for k in o:
+            if o[k] is not None:
+                o[k].zero_()
+    outs = c2.render_batch(handles, views, lights, graph=True, outs=outs)
+    torch.cuda.synchronize()
+    for i in range(len(views)):
+        assert same(outs[i], ref[i]) is None, i
+    assert c2.last_error() == 0
+    gd.close()
+    for h in handles:
+        h.close()
+    c2.close()
+
+
 def test_autotune_and_cache(ctx):
     scenes, cams = small_batch()
     handles, views, lights = build_batch(ctx, scenes, cams)
