@@ -17,6 +17,30 @@ namespace {
 constexpr int BLOCK = RC_TRACE_BLOCK;
 constexpr int SL = RC_STACK_LDS;
 
+// The view holding work item `item` (the largest v with item_first <= item), and the
+// pixel of the item inside that view's tiles of tile_w x tile_h pixels (false for tile padding).
+__device__ inline uint32_t rc_find_view(const DevView* views, uint32_t n, uint32_t item)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (views[mid].item_first <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline bool rc_batch_pixel(const DevView& V, const BatchTune& t, uint32_t item, uint32_t& px)
+{
+    const uint32_t tile_pix = t.tile_w * t.tile_h;
+    const uint32_t local = item - V.item_first;
+    const uint32_t tile = local / tile_pix, w = local % tile_pix;
+    const uint32_t i = (tile % V.tiles_x) * t.tile_w + w % t.tile_w;
+    const uint32_t jj = (tile / V.tiles_x) * t.tile_h + w / t.tile_w;
+    if (i >= (uint32_t)V.cam.width || jj >= (uint32_t)V.cam.height) return false;
+    px = jj * (uint32_t)V.cam.width + i;
+    return true;
+}
+
 // Register budgets of the one-stage kernels (64 views, three-kernel form): the camera-ray kernel at 6 waves per
 // SIMD (80 registers) 3.74 against 4.21 ms at its natural 104; the shadow-ray kernel at 4 (128 registers)
 // 5.47 against 6.32 ms at 136; 5 waves spill and took 8.3 ms.

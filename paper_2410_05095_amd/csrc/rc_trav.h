@@ -562,27 +562,3 @@ __device__ inline float4 rc_shade_sample(const DevScene& sc, const DevCamera& ca
     }
     return make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], 1.0f);
 }
-
-// Batched rendering: the view holding work item `item` (the largest v with item_first <= item), and the
-// pixel of the item inside that view's tiles of tile_w x tile_h pixels (false for tile padding).
-__device__ inline uint32_t rc_find_view(const DevView* views, uint32_t n, uint32_t item)
-{
-    uint32_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (views[mid].item_first <= item) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ inline bool rc_batch_pixel(const DevView& V, const BatchTune& t, uint32_t item, uint32_t& px)
-{
-    const uint32_t tile_pix = t.tile_w * t.tile_h;
-    const uint32_t local = item - V.item_first;
-    const uint32_t tile = local / tile_pix, w = local % tile_pix;
-    const uint32_t i = (tile % V.tiles_x) * t.tile_w + w % t.tile_w;
-    const uint32_t jj = (tile / V.tiles_x) * t.tile_h + w / t.tile_w;
-    if (i >= (uint32_t)V.cam.width || jj >= (uint32_t)V.cam.height) return false;
-    px = jj * (uint32_t)V.cam.width + i;
-    return true;
-}
