@@ -42,10 +42,11 @@ __device__ inline bool rc_batch_pixel(const DevView& V, const BatchTune& t, uint
 }
 
 // Register budgets of the one-stage kernels (64 views, three-kernel form): the camera-ray kernel at 6 waves per
-// SIMD (80 registers) 3.74 against 4.21 ms at its natural 104; the shadow-ray kernel at 4 (128 registers)
-// 5.47 against 6.32 ms at 136; 5 waves spill and took 8.3 ms.
+// SIMD (80 registers) 3.74 against 4.21 ms at its natural 104; the shadow-ray kernel, whose FP64 surface
+// reconstruction moved to k_batch_setup, at 5 (96 registers) 4.91 ms with the setup, against 5.46 at 4 and
+// 5.47 at 6 waves.
 template <int PASS>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 6 : PASS == 2 ? 4 : 1)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 6 : PASS == 2 ? 5 : 1)))
 void k_batch(BatchParams P)
 {
     static_assert(PASS >= 0 && PASS <= 3, "pass");
@@ -83,11 +84,13 @@ void k_batch(BatchParams P)
         start_camera(P.views[v].cam, px, k, ray, ts, rays_cast, state);
     };
 
-    auto next_shadow = [&]() __attribute__((always_inline)) -> bool {
-        const DevView& V = P.views[v];
+    // the next shadow ray of the sample from light j on (lights below the surface are skipped); false when
+    // none is left.  Without captures, like start_camera.
+    const auto start_shadow = [](const float* lights, uint32_t& j, uint32_t n_l, uint32_t px, const float* os,
+                                 const float* nf, TravRay& ray, TravState& ts, uint32_t& rays_cast,
+                                 int& state) __attribute__((always_inline)) -> bool {
         while (j < n_l) {
-            if (rc_shadow_ray(P.lights + 6 * (size_t)(V.light_first + j), nullptr, nullptr, false, px, j, 0u,
-                              0u, 0u, os, nf, ray)) {
+            if (rc_shadow_ray(lights + 6 * (size_t)j, nullptr, nullptr, false, px, j, 0u, 0u, 0u, os, nf, ray)) {
                 trav_begin(ray, ts);
                 ++rays_cast;
                 state = 2;
@@ -97,23 +100,24 @@ void k_batch(BatchParams P)
         }
         return false;
     };
+#define RC_NEXT_SHADOW() \
+    start_shadow(P.lights + 6 * (size_t)P.views[v].light_first, j, n_l, px, os, nf, ray, ts, rays_cast, state)
 
     // shadow pass: from sample k on, the first sample whose camera ray hit starts its shadow rays; samples
     // before it get their (empty) masks; the pixel is done when none is left
+    // (origin and normal from the setup entries that k_batch_setup wrote, so that this kernel holds no FP64 code)
     auto shadow_sample = [&]() __attribute__((always_inline)) {
         const DevView& V = P.views[v];
         for (; k < spp; ++k) {
             const size_t s = (size_t)px * spp + k;
-            hid = V.hit[s].x;
+            const float4 a = P.setup[2 * ((size_t)V.setup_first + s)];
             mask = 0;
             j = 0;
-            if (hid != RC_NO_HIT) {
-                DevScene full = P.scenes[V.scene];
-                Surface Sf = rc_surface(full, V.cam, px, k, hid);
-                D3 O = rc_shadow_origin(Sf);
-                os[0] = (float)O.x; os[1] = (float)O.y; os[2] = (float)O.z;
-                nf[0] = (float)Sf.n.x; nf[1] = (float)Sf.n.y; nf[2] = (float)Sf.n.z;
-                if (next_shadow()) return;
+            if (a.w != 0.0f) {
+                const float4 b = P.setup[2 * ((size_t)V.setup_first + s) + 1];
+                os[0] = a.x; os[1] = a.y; os[2] = a.z;
+                nf[0] = b.x; nf[1] = b.y; nf[2] = b.z;
+                if (RC_NEXT_SHADOW()) return;
             }
             V.shadow[s] = mask;
         }
@@ -215,7 +219,7 @@ void k_batch(BatchParams P)
         } else if constexpr (PASS == 2) {   // shadow ray done: next light, else the sample's mask and the next one
             if (!occluded) mask |= 1u << j;
             ++j;
-            if (next_shadow()) return;
+            if (RC_NEXT_SHADOW()) return;
             P.views[v].shadow[(size_t)px * spp + k] = mask;
             ++k;
             shadow_sample();
@@ -232,13 +236,13 @@ void k_batch(BatchParams P)
                 D3 O = rc_shadow_origin(Sf);
                 os[0] = (float)O.x; os[1] = (float)O.y; os[2] = (float)O.z;
                 nf[0] = (float)Sf.n.x; nf[1] = (float)Sf.n.y; nf[2] = (float)Sf.n.z;
-                if (next_shadow()) return;
+                if (RC_NEXT_SHADOW()) return;
             }
             finish_sample();
         } else {
             if (!occluded) mask |= 1u << j;
             ++j;
-            if (next_shadow()) return;
+            if (RC_NEXT_SHADOW()) return;
             finish_sample();
         }
     };
@@ -295,9 +299,37 @@ void k_batch(BatchParams P)
             if (lane == 0) atomicAdd(P.w.ray_count + 2 * q + (PASS == 2 ? 1 : 0), vv);
         }
     }
+#undef RC_NEXT_SHADOW
 }
 
 }  // namespace
+
+// Shadow-ray setup of the three-kernel form: for every sample of every view with point lights, the origin
+// (offset along the normal, in FP64 from the hit, as in the one-kernel form) and the normal, rounded to FP32,
+// at the view's place in P.setup; (0, 0, 0, 0) for samples without a hit.
+__global__ __launch_bounds__(256) void k_batch_setup(BatchParams P)
+{
+    const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= P.n_items) return;
+    const DevView& V = P.views[rc_find_view(P.views, P.n_views, item)];
+    uint32_t px = 0;
+    if (V.n_lights == 0 || !rc_batch_pixel(V, P.tune, item, px)) return;
+    const uint32_t spp = (uint32_t)(V.cam.ssaa * V.cam.ssaa);
+    const DevScene sc = P.scenes[V.scene];
+    for (uint32_t k = 0; k < spp; ++k) {
+        const size_t s = (size_t)px * spp + k;
+        const uint32_t h = V.hit[s].x;
+        float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+        if (h != RC_NO_HIT) {
+            Surface Sf = rc_surface(sc, V.cam, px, k, h);
+            D3 O = rc_shadow_origin(Sf);
+            a = make_float4((float)O.x, (float)O.y, (float)O.z, 1.0f);
+            b = make_float4((float)Sf.n.x, (float)Sf.n.y, (float)Sf.n.z, 0.0f);
+        }
+        P.setup[2 * ((size_t)V.setup_first + s)] = a;
+        P.setup[2 * ((size_t)V.setup_first + s) + 1] = b;
+    }
+}
 
 static const void* batch_kernel(int pass)
 {
@@ -325,7 +357,10 @@ void rc_launch_batch(const BatchParams& P, int pass, int grid, hipStream_t st)
     if (grid < (int)RC_XCDS) grid = RC_XCDS;   // every XCD share of the queue needs workgroups
     switch (pass) {
     case 1: hipLaunchKernelGGL(k_batch<1>, dim3(grid), dim3(BLOCK), lds, st, P); break;
-    case 2: hipLaunchKernelGGL(k_batch<2>, dim3(grid), dim3(BLOCK), lds, st, P); break;
+    case 2:
+        hipLaunchKernelGGL(k_batch_setup, dim3((P.n_items + 255) / 256), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(k_batch<2>, dim3(grid), dim3(BLOCK), lds, st, P);
+        break;
     case 3: hipLaunchKernelGGL(k_batch<3>, dim3(grid), dim3(BLOCK), lds, st, P); break;
     default: hipLaunchKernelGGL(k_batch<0>, dim3(grid), dim3(BLOCK), lds, st, P); break;
     }

@@ -199,6 +199,7 @@ int rc_destroy(rc_ctx* c)
     dev_free(c->d_overflow);
     dev_free(c->d_post);
     dev_free(c->d_counts);
+    dev_free(c->d_bsetup);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
     delete c;
@@ -980,6 +981,7 @@ struct BatchPlan {
     std::vector<DevView> views;
     uint32_t n_items = 0;
     uint32_t max_stack = 0;
+    uint64_t n_samples = 0;    // samples of all views: entries of the three-kernel form's shadow-ray setup
     size_t bytes = 0, off_views = 0, off_lights = 0;
 };
 
@@ -1018,6 +1020,9 @@ int plan_batch(rc_scene* const* scenes, uint32_t n_scenes, const rc_view* views,
         uint32_t tiles_y = ((uint32_t)cam->height + t.tile_h - 1) / t.tile_h;
         d.item_first = (uint32_t)items;
         items += (uint64_t)d.tiles_x * tiles_y * t.tile_w * t.tile_h;
+        d.setup_first = (uint32_t)bp.n_samples;
+        bp.n_samples += (uint64_t)cam->width * cam->height * cam->ssaa * cam->ssaa;
+        if (bp.n_samples >= (1ull << 32)) return RC_ERR_UNSUPPORTED;
         d.rgba = V.d_rgba;
         d.hit = reinterpret_cast<uint4*>(V.d_hit);
         d.shadow = V.n_lights > 0 ? V.d_shadow : nullptr;
@@ -1093,8 +1098,20 @@ int batch_launch(rc_ctx* c, rc_scene* const* scenes, uint32_t n_scenes, const rc
     RC_HIP(hipEventRecord(c->ev_staging, c->stream));
     c->staging_pending = true;
 
+    // shadow-ray setup entries of the three-kernel form (2 float4 per sample)
+    if (t.passes == 3 && 2 * bp.n_samples > c->bsetup_cap) {
+        RC_HIP(hipStreamSynchronize(c->stream));
+        dev_free(c->d_bsetup);
+        c->bsetup_cap = 0;
+        st = dev_alloc(&c->d_bsetup, 2 * bp.n_samples);
+        if (st != RC_OK) return st;
+        c->bsetup_cap = 2 * bp.n_samples;
+        c->graph_key = 0;   // the captured graph points at the old buffer
+    }
+
     BatchParams P;
     memset(&P, 0, sizeof(P));
+    P.setup = t.passes == 3 ? c->d_bsetup : nullptr;
     P.scenes = reinterpret_cast<const DevScene*>(c->d_table);
     P.views = reinterpret_cast<const DevView*>(c->d_table + bp.off_views);
     P.lights = reinterpret_cast<const float*>(c->d_table + bp.off_lights);

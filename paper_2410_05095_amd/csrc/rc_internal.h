@@ -156,7 +156,7 @@ struct DevView {
     uint32_t n_lights;
     uint32_t item_first;      // first work item of this view (exclusive prefix over views)
     uint32_t tiles_x;         // tiles per image row
-    uint32_t pad;
+    uint32_t setup_first;     // first sample of this view in the shadow-ray setup buffer (three-kernel form)
     float* rgba;
     uint4* hit;
     uint32_t* shadow;
@@ -174,13 +174,15 @@ struct BatchParams {
     const DevScene* scenes;
     const DevView* views;
     const float* lights;
+    float4* setup;            // three-kernel form: per sample (shadow-ray origin, 1 | 0) and (normal, 0)
     uint32_t n_views;
     uint32_t n_items;
     BatchTune tune;
     TraceWork w;
 };
 
-// pass 0: the one-kernel form; 1, 2, 3: camera rays, shadow rays, shading + resolve (work-queue slots 3, 4, 5)
+// pass 0: the one-kernel form; 1, 2, 3: camera rays, shadow rays, shading + resolve (work-queue slots 3, 4, 5);
+// the shadow pass first fills P.setup from the camera hits
 void rc_launch_batch(const BatchParams& P, int pass, int grid, hipStream_t st);
 int rc_batch_max_blocks_per_cu(int device, int pass);
 

@@ -31,6 +31,8 @@ struct rc_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     uint64_t graph_key = 0;
+    float4* d_bsetup = nullptr;           // shadow-ray setup of the batch's three-kernel form, per sample
+    size_t bsetup_cap = 0;                // in float4
 };
 
 struct rc_scene {
