@@ -37,6 +37,7 @@ struct KParams {
     const uint4* gbuf_in;
     uint32_t* mask;
     float* vis;
+    const float4* setup;      // shadow rays: per sample (origin, 1 | 0 without a hit) and (normal, 0), k_shadow_setup
     TraceWork w;
     uint32_t n_items;
     uint32_t slot;
@@ -109,16 +110,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MODE == M
             ++rays_cast;
             return true;
         } else {
+            // origin and normal from the setup pass (the FP64 reconstruction stays out of this kernel)
             size_t s = (size_t)px * (P.cam.ssaa * P.cam.ssaa) + pk;
-            uint4 h = P.gbuf_in[s];
+            const float4 a = P.setup[2 * s];
             acc = 0;
             j = 0;
             n_rays = MODE == MODE_POINT ? (uint32_t)P.L.n_point : (uint32_t)P.L.area_samples;
-            if (h.x == RC_NO_HIT) { finish_item(); return false; }
-            Surface S = rc_surface(sc, P.cam, px, pk, h.x);
-            D3 O = rc_shadow_origin(S);
-            os[0] = (float)O.x; os[1] = (float)O.y; os[2] = (float)O.z;
-            nf[0] = (float)S.n.x; nf[1] = (float)S.n.y; nf[2] = (float)S.n.z;
+            if (a.w == 0.0f) { finish_item(); return false; }
+            const float4 b = P.setup[2 * s + 1];
+            os[0] = a.x; os[1] = a.y; os[2] = a.z;
+            nf[0] = b.x; nf[1] = b.y; nf[2] = b.z;
             if (next_shadow_ray()) return true;
             finish_item();
             return false;
@@ -225,12 +226,11 @@ __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* cou
         const bool in_image = r < total && rc_item_to_sample(P.cam, item, px, pk);
         bool busy = false;
         if (in_image) {
-            uint4 h = P.gbuf_in[px];
-            if (h.x != RC_NO_HIT) {
-                Surface S = rc_surface(sc, P.cam, px, 0, h.x);
-                D3 O = rc_shadow_origin(S);
-                float os[3] = {(float)O.x, (float)O.y, (float)O.z};
-                float nf[3] = {(float)S.n.x, (float)S.n.y, (float)S.n.z};
+            const float4 a = P.setup[2 * (size_t)px];   // one sample per pixel: setup entry px
+            if (a.w != 0.0f) {
+                const float4 b = P.setup[2 * (size_t)px + 1];
+                float os[3] = {a.x, a.y, a.z};
+                float nf[3] = {b.x, b.y, b.z};
                 busy = rc_shadow_ray(P.L.point[0], P.L.rect, P.nL, true, px, k, P.L.area_stream, P.cam.seed,
                                      P.cam.frame, os, nf, ray);
                 if (busy) {
@@ -261,9 +261,9 @@ __global__ __launch_bounds__(BLOCK) void k_rect_packets(KParams P, uint32_t* cou
     }
 }
 
-// Per-pixel shadow-ray setup of the rect-light pass: (origin, 1) and (unit normal, 0) in FP32 from the
-// FP64 surface reconstruction, or (0, 0, 0, 0) for pixels without a primary hit.  Keeps the FP64 code
-// (and its registers) out of the traversal kernel.
+// Per-sample shadow-ray setup of the shadow passes: (origin, 1) and (unit normal, 0) in FP32 from the
+// FP64 surface reconstruction, or (0, 0, 0, 0) for samples without a primary hit.  Keeps the FP64 code
+// (and its registers) out of the traversal kernels, wave-uniform and per-lane alike.
 __global__ __launch_bounds__(256) void k_shadow_setup(DevScene sc, DevCamera cam, const uint4* gbuf, uint32_t n_samples,
                                                       float4* setup)
 {
@@ -1019,8 +1019,10 @@ void rc_launch_shadow(const DevScene& sc, const DevCamera& cam, const DevLights&
     const bool big_rect = n_samples_img * (uint64_t)(L.has_rect ? L.area_samples : 0) >= 3000000u;
     const bool wave_point = wave_ok && (kernels == RC_KERNELS_WAVE || big_point);
     const bool wave_rect = wave_ok && (kernels == RC_KERNELS_WAVE || big_rect);
-    if ((wave_point && L.n_point > 0) || (wave_rect && L.has_rect)) {
-        // one setup entry per sample of the image (the item count is padded to whole tiles)
+    P.setup = setup;
+    if (L.n_point > 0 || L.has_rect) {
+        // one setup entry per sample of the image (the item count is padded to whole tiles); every shadow kernel
+        // reads its rays' origins and normals from there
         const uint32_t n_samples = (uint32_t)(cam.width * cam.height * cam.ssaa * cam.ssaa);
         hipLaunchKernelGGL(k_shadow_setup, dim3((n_samples + 255) / 256), dim3(256), 0, st, sc, cam, gbuf, n_samples,
                            setup);
