@@ -37,7 +37,7 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # the copy-kernel calibration), keyed by (workload, spp, hash of the traversal kernel sources); the
 # value only applies while those sources are unchanged (summaries under profiles/).
 MEASURED_TRAFFIC = {
-    ("big_7M", 64, "1f06b1fb420f7dd7:5ce1cb11be5fdbcb:619146c7bd55091c"): 443_100_000,
+    ("big_7M", 64, "7d238b039053ec4a:5ce1cb11be5fdbcb:619146c7bd55091c"): 442_900_000,
 }
 
 
