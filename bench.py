@@ -549,8 +549,8 @@ def main():
                     help="instead of rendering, copy a buffer of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (views or tiles would be split "
-              "across GPUs with a final image gather; see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (views or tiles would be split "
+              "across GPUs with a final image gather).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
