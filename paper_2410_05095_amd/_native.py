@@ -251,6 +251,11 @@ class Context:
     def render(self, scene: "Scene", cam, lights=(), rect=None, area_samples: int = 0, area_stream: int = 0,
                timing: bool = False, sample_rgba: bool = False, out: Optional[dict] = None,
                per_lane: bool = False, shade: bool = True, count: bool = False, wave: bool = False) -> dict:
+        """One view through rc_render: camera rays, shadow rays (point lights, and the rect light with
+        `area_samples` samples per pixel), shading and resolve into `out` (allocated when missing).
+        per_lane / wave force the per-lane or the wave-uniform shadow kernels (by default the library picks by
+        pass size); count gathers ray, node and triangle counts for stage_times(); shade=False stops after the
+        visibility stages."""
         torch = self.torch
         self._sync_stream()
         W, H, S = int(cam.width), int(cam.height), int(cam.ssaa) ** 2
