@@ -19,12 +19,30 @@ constexpr int SL = RC_STACK_LDS;
 
 // The view holding work item `item` (the largest v with item_first <= item), and the
 // pixel of the item inside that view's tiles of tile_w x tile_h pixels (false for tile padding).
-__device__ inline uint32_t rc_find_view(const DevView* views, uint32_t n, uint32_t item)
+// Batches of up to VIEW_LDS views search a copy of the views' first items in LDS (rc_views_to_lds), others
+// the view table in device memory.
+constexpr uint32_t VIEW_LDS = 256;
+
+__device__ inline void rc_views_to_lds(const BatchParams& P, uint32_t* first)
+{
+    if (P.n_views <= VIEW_LDS)
+        for (uint32_t i = threadIdx.x; i < P.n_views; i += blockDim.x) first[i] = P.views[i].item_first;
+    __syncthreads();
+}
+
+__device__ inline uint32_t rc_find_view(const DevView* views, const uint32_t* first, uint32_t n, uint32_t item)
 {
     uint32_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (views[mid].item_first <= item) lo = mid; else hi = mid;
+    if (n <= VIEW_LDS) {
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (first[mid] <= item) lo = mid; else hi = mid;
+        }
+    } else {
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (views[mid].item_first <= item) lo = mid; else hi = mid;
+        }
     }
     return lo;
 }
@@ -50,6 +68,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PASS == 1
 void k_batch(BatchParams P)
 {
     static_assert(PASS >= 0 && PASS <= 3, "pass");
+    __shared__ uint32_t view_first[VIEW_LDS];
+    rc_views_to_lds(P, view_first);
     const int tid = threadIdx.x;
     const uint32_t lane = __lane_id();
     const uint32_t glane = blockIdx.x * BLOCK + tid;
@@ -186,7 +206,7 @@ void k_batch(BatchParams P)
     };
 
     auto start_item = [&](uint32_t item) __attribute__((always_inline)) -> bool {
-        v = rc_find_view(P.views, P.n_views, item);
+        v = rc_find_view(P.views, view_first, P.n_views, item);
         const DevView& V = P.views[v];
         if (!rc_batch_pixel(V, P.tune, item, px)) return false;
         spp = (uint32_t)(V.cam.ssaa * V.cam.ssaa);
@@ -309,9 +329,11 @@ void k_batch(BatchParams P)
 // at the view's place in P.setup; (0, 0, 0, 0) for samples without a hit.
 __global__ __launch_bounds__(256) void k_batch_setup(BatchParams P)
 {
+    __shared__ uint32_t view_first[VIEW_LDS];
+    rc_views_to_lds(P, view_first);
     const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
     if (item >= P.n_items) return;
-    const DevView& V = P.views[rc_find_view(P.views, P.n_views, item)];
+    const DevView& V = P.views[rc_find_view(P.views, view_first, P.n_views, item)];
     uint32_t px = 0;
     if (V.n_lights == 0 || !rc_batch_pixel(V, P.tune, item, px)) return;
     const uint32_t spp = (uint32_t)(V.cam.ssaa * V.cam.ssaa);
