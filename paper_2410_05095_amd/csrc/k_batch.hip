@@ -62,7 +62,8 @@ __device__ inline bool rc_batch_pixel(const DevView& V, const BatchTune& t, uint
 // Register budgets of the one-stage kernels (64 views, three-kernel form): the camera-ray kernel at 6 waves per
 // SIMD (80 registers) 3.74 against 4.21 ms at its natural 104; the shadow-ray kernel, whose FP64 surface
 // reconstruction moved to k_batch_setup, at 5 (96 registers) 4.91 ms with the setup, against 5.46 at 4 and
-// 5.47 at 6 waves.
+// 5.47 at 6 waves.  The camera kernel at 5 waves (3.79 ms) and the shading kernel held to 5 or 6 waves (1.05,
+// 1.42 against 0.66 ms at its natural 128 registers) were slower.
 template <int PASS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 6 : PASS == 2 ? 5 : 1)))
 void k_batch(BatchParams P)
