@@ -122,6 +122,32 @@ def test_batch_graph_replays(ctx, passes):
     assert ctx.last_error() == 0
 
 
+@pytest.mark.parametrize("passes", [3, 1])
+def test_batch_more_views_than_the_lds_table(ctx, passes):
+    """300 small views (the kernels keep the views' first items in LDS only up to 256 views and search the
+    device table beyond): every view bit-identical to its single-view render."""
+    import torch
+    scenes = [sg.small_random_scene(30 + i, n_instances=8, width=8, height=8, n_lights=1 + i) for i in range(2)]
+    rng = np.random.default_rng(5)
+    cams = [[], []]
+    for n in range(300):
+        eye = tuple(float(x) for x in rng.uniform([-20, 5, -30], [20, 25, -20]))
+        cams[n % 2].append(sg.Camera(eye=eye, target=(0.0, 6.0, 0.0), up=(0, 1, 0), vfov_deg=40.0 + n % 30,
+                                     width=12 + n % 9, height=8 + n % 7, ssaa=1 + n % 2, seed=n, frame=n % 3))
+    handles, views, lights = build_batch(ctx, scenes, cams)
+    assert len(views) > 256
+    ref = single_renders(ctx, scenes, handles, views)
+    tune = dict(tile_w=8, tile_h=8, queue_depth=256, min_rays=40, waves_per_simd=0, passes=passes)
+    outs = ctx.render_batch(handles, views, lights, tune=tune)
+    torch.cuda.synchronize()
+    assert ctx.last_error() == 0
+    bad = [i for i in range(len(views)) if same(outs[i], ref[i]) is not None]
+    say(f"[batch300] passes {passes}: {len(views)} views, {len(bad)} differ")
+    assert not bad
+    for h in handles:
+        h.close()
+
+
 def test_batch_graph_after_buffer_growth():
     """A single-view render that grows the context's overflow stack area between two launches of a captured
     batch graph: the context captures again instead of replaying into the freed area."""
